@@ -1,0 +1,665 @@
+"""Pins of the FP64 oracle against what the paper and mathematics fix.
+
+Every test here checks the oracle (oracle/tpf_oracle.c) against something
+other than itself: closed forms derived from Eq. 2 and the tanh profile of its
+footnote, the continuum identities Eqs. 9-12, exact discrete identities
+(summation by parts, product rule), exact amplification factors of RK4 on
+Fourier modes, symmetry and conservation.  No GPU is needed.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.integrate import cumulative_simpson, quad
+
+import workloads
+
+# ----------------------------------------------------------------- helpers
+
+
+def circle_params(ora, n, eps, dim=2, **kw):
+    base = dict(n=(n,) * dim, eps=eps, rho1=1.0, rho2=1.0, visc1=0.1, visc2=0.1, sigma=1.0)
+    base.update(kw)
+    return ora.Params(**base)
+
+
+def radius(P, center=0.5):
+    ax = [(np.arange(m) + 0.5) * P.h - center for m in P.shape]
+    g = np.meshgrid(*ax, indexing="ij")
+    return np.sqrt(sum(x * x for x in g))
+
+
+def tanh_phi(r, R, eps):
+    return 0.5 * (1.0 + np.tanh((R - r) / (2.0 * eps)))
+
+
+def orders(errs):
+    return [math.log2(errs[q] / errs[q + 1]) for q in range(len(errs) - 1)]
+
+
+def face_positions_r(P, a, center=0.5):
+    """Distance from the centre of the lower a-faces of every cell."""
+    ax = []
+    for d, m in enumerate(P.shape):         # d indexes C-order axes (z, y, x) or (y, x)
+        axis = P.dim - 1 - d                 # physical axis
+        off = 0.0 if axis == a else 0.5
+        ax.append((np.arange(m) + off) * P.h - center)
+    g = np.meshgrid(*ax, indexing="ij")
+    return np.sqrt(sum(x * x for x in g))
+
+
+def roll(q, a, s, dim):
+    """q[c + s e_a] for physical axis a (x = 0) on C-order arrays."""
+    return np.roll(q, -s, axis=dim - 1 - a)
+
+
+# ----------------------------------------------------------------- initial state
+
+
+def test_paper_parameters_golden():
+    """The static-drop parameters printed in Sec. 3.1 are self-consistent:
+    La = sigma rho D / mu^2 = 12000 (tests/golden/static_drop_params.txt)."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "static_drop_params.txt")
+    vals = {}
+    for line in open(path):
+        line = line.split("#")[0].strip()
+        if line:
+            k, v = line.split("=")
+            vals[k.strip()] = float(v)
+    La = vals["sigma"] * vals["rho"] * vals["D"] / vals["mu"] ** 2
+    assert La == pytest.approx(vals["La"], rel=1e-12)
+    # the 64^2 workload keeps visc and La and uses D = 0.5, so rho = La visc^2 / (sigma D)
+    c = workloads.static_drop_64()
+    assert c.rho1 * c.sigma * 2 * c.semi_axes[0] / c.visc1 ** 2 == pytest.approx(vals["La"])
+    assert c.dt() == pytest.approx(1.5625e-3, rel=1e-12)
+
+
+def test_init_is_tanh_of_signed_distance(ora):
+    """Footnote of Eq. 2: phi = [1 + tanh(s / 2 eps)] / 2 with s = R - r."""
+    P = circle_params(ora, 48, 0.03)
+    phi = ora.init_droplet(P, (0.5, 0.5), (0.25, 0.25))
+    np.testing.assert_allclose(phi, tanh_phi(radius(P), 0.25, 0.03), rtol=0, atol=1e-15)
+    P3 = circle_params(ora, 16, 0.05, dim=3)
+    phi3 = ora.init_droplet(P3, (0.5, 0.5, 0.5), (0.3, 0.3, 0.3))
+    np.testing.assert_allclose(phi3, tanh_phi(radius(P3), 0.3, 0.05), rtol=0, atol=1e-15)
+
+
+def test_init_ellipse_zero_level_set(ora):
+    """The first-order distance keeps the exact ellipse as the phi = 1/2 set
+    and its gradient there equals the exact signed-distance gradient."""
+    P = circle_params(ora, 64, 0.02)
+    phi = ora.init_droplet(P, (0.5, 0.5), (0.3, 0.22))
+    x = (np.arange(64) + 0.5) / 64 - 0.5
+    X = x[None, :]
+    Y = x[:, None]
+    q = np.sqrt((X / 0.3) ** 2 + (Y / 0.22) ** 2)
+    assert np.all((phi > 0.5) == (q < 1.0))
+    assert phi.max() < 1.0 and phi.min() > 0.0
+
+
+# ----------------------------------------------------------------- Eq. 2: chemical potential
+
+
+def test_chem_potential_tanh_circle_order2(ora):
+    """P1: on the tanh circle, Eq. 2 gives mu = sigma_hat (d-1) phi(1-phi)/r
+    exactly (from phi'' = (1-2phi) phi(1-phi)/eps^2); the discrete mu converges
+    to it at second order with eps fixed."""
+    eps, R, errs = 0.02, 0.25, []
+    for n in (128, 256, 512):
+        P = circle_params(ora, n, eps)
+        r = radius(P)
+        phi = tanh_phi(r, R, eps)
+        mu = ora.chem_potential(P, phi)
+        exact = 6.0 * phi * (1 - phi) / r
+        m = r < 0.45
+        errs.append(np.abs(mu - exact)[m].max())
+    o = orders(errs)
+    assert min(o) > 1.9 and max(o) < 2.2, (errs, o)
+
+
+def test_chem_potential_planar_front_zero(ora):
+    """A planar tanh front is an exact equilibrium: continuum mu = 0."""
+    errs, eps = [], 0.01
+    for n in (256, 512, 1024):
+        P = ora.Params(n=(n, 4), eps=eps)
+        x = (np.arange(n) + 0.5) / n
+        # a periodic pair of fronts at x = 0.25 and x = 0.75 (s > 0 between them)
+        s = 0.25 - np.abs(x - 0.5)
+        phi = np.tile(0.5 * (1 + np.tanh(s / (2 * eps))), (4, 1))
+        mu = ora.chem_potential(P, phi)
+        errs.append(np.abs(mu).max())
+    assert min(orders(errs)) > 1.9, errs
+
+
+# ----------------------------------------------------------------- Table 1: regularisation
+
+
+@pytest.mark.parametrize("model", ["CDI", "SB", "ISODI"])
+def test_regularization_tanh_circle_steady_order2(ora, model):
+    """P2: the tanh circle is an exact continuum steady state of all three
+    models of Table 1 at u = 0 (CDI: the face flux vanishes pointwise; SB and
+    ISODI: the terms cancel by Eqs. 9-10); the discrete g -> 0 at order 2."""
+    eps, R, errs = 0.02, 0.25, []
+    for n in (128, 256, 512):
+        P = circle_params(ora, n, eps, model=ora.MODELS[model])
+        r = radius(P)
+        g = ora.regularization(P, tanh_phi(r, R, eps))
+        errs.append(np.abs(g)[r < 0.45].max())
+    o = orders(errs)
+    assert min(o) > 1.8, (errs, o)
+
+
+def test_curvature_circle_order2(ora):
+    """Eq. 3 on the tanh circle: kappa = (d - 1)/r (positive for a drop)."""
+    for dim, ns, eps in ((2, (64, 128, 256), 0.03), (3, (48, 96, 192), 0.03)):
+        errs = []
+        for n in ns:
+            P = circle_params(ora, n, eps, dim=dim)
+            r = radius(P)
+            phi = tanh_phi(r, 0.25, eps)
+            k = ora.curvature(P, phi)
+            band = (phi > 0.05) & (phi < 0.95)
+            errs.append(np.abs(k - (dim - 1) / r)[band].max())
+        o = orders(errs)
+        assert min(o) > 1.8, (dim, errs, o)
+
+
+def test_normals_regularised(ora):
+    """n = grad phi / |grad phi| (Table 1 caption) with the delta
+    regularisation: unit length where |g| >> delta, zero where phi is flat."""
+    P = circle_params(ora, 32, 0.05)
+    phi = tanh_phi(radius(P), 0.25, 0.05)
+    n, gmag = ora.normals(P, phi)
+    nn = np.sqrt(n[0] ** 2 + n[1] ** 2)
+    m = gmag > 1e-6
+    np.testing.assert_allclose(nn[m], 1.0, rtol=0, atol=1e-12)
+    n0, g0 = ora.normals(P, np.full(P.shape, 0.3))
+    assert np.abs(n0[0]).max() == 0.0 and np.abs(g0).max() == 0.0
+
+
+# ----------------------------------------------------------------- Eqs. 5, 12: forces
+
+
+def test_eb_equals_lcsf_at_equilibrium_order2(ora):
+    """P3 (Eq. 12): on the tanh circle the energy-based and localized CSF
+    forces coincide in the continuum; discretely F_EB - F_LCSF -> 0 at order 2."""
+    eps, R, errs = 0.02, 0.25, []
+    for n in (128, 256, 512):
+        P = circle_params(ora, n, eps)
+        phi = tanh_phi(radius(P), R, eps)
+        Fe = ora.surface_force(ora.Params(**{**P.__dict__, "force": ora.EB}), phi)
+        Fl = ora.surface_force(ora.Params(**{**P.__dict__, "force": ora.LCSF}), phi)
+        errs.append(max(np.abs(Fe[a] - Fl[a]).max() for a in range(2)))
+    assert min(orders(errs)) > 1.8, errs
+
+
+def test_force_magnitudes_continuum(ora):
+    """EB force -> sigma_hat (d-1) phi(1-phi)/r grad phi and CSF force ->
+    sigma (d-1)/r grad phi at face centres, both at order 2."""
+    eps, R = 0.02, 0.25
+    for force in ("EB", "CSF"):
+        errs = []
+        for n in (128, 256, 512):
+            P = circle_params(ora, n, eps, force=ora.FORCES[force])
+            phi = tanh_phi(radius(P), R, eps)
+            F = ora.surface_force(P, phi)
+            e = 0.0
+            for a in range(2):
+                rf = face_positions_r(P, a)
+                pf = tanh_phi(rf, R, eps)
+                # d phi / d x_a = -phi(1-phi)/eps * x_a / r
+                ax = []
+                for d, m in enumerate(P.shape):
+                    axis = P.dim - 1 - d
+                    off = 0.0 if axis == a else 0.5
+                    ax.append((np.arange(m) + off) * P.h - 0.5)
+                xa = np.meshgrid(*ax, indexing="ij")[P.dim - 1 - a]
+                grad = -pf * (1 - pf) / eps * xa / rf
+                coef = 6.0 * pf * (1 - pf) / rf if force == "EB" else 1.0 / rf
+                m = rf < 0.45
+                e = max(e, np.abs(F[a] - coef * grad)[m].max())
+            errs.append(e)
+        assert min(orders(errs)) > 1.8, (force, errs)
+
+
+def test_eb_gauge_identity(ora):
+    """P4 (Eq. 8): mu grad phi differs from -phi grad mu by the gradient of
+    mu phi, which the pressure absorbs.  With uniform density the discrete
+    product rule A(mu)G(phi) = G(mu phi) - A(phi)G(mu) is exact, so both forms
+    give the same du/dt and pressures that differ by mu phi - mean."""
+    P = circle_params(ora, 32, 1 / 32, rho1=3.0, rho2=3.0, visc1=0.05, visc2=0.05)
+    phi = ora.init_droplet(P, (0.5, 0.5), (0.3, 0.22))
+    u = workloads.random_velocity(P.shape, 7, amplitude=0.05)
+    d1, du1, p1 = ora.stage(P, phi, u)
+    Pg = ora.Params(**{**P.__dict__, "force": ora.EB_GAUGE})
+    d2, du2, p2 = ora.stage(Pg, phi, u)
+    np.testing.assert_array_equal(d1, d2)
+    scale = max(np.abs(du1[0]).max(), 1e-30)
+    for a in range(2):
+        np.testing.assert_allclose(du1[a], du2[a], rtol=0, atol=1e-11 * scale)
+    mu = ora.chem_potential(P, phi)
+    shift = mu * phi - (mu * phi).mean()
+    np.testing.assert_allclose(p1 - p2, shift, rtol=0, atol=1e-10 * np.abs(shift).max())
+
+
+# ----------------------------------------------------------------- pressure
+
+
+def laplace_jump_exact(eps, R, dim, masks_r=None):
+    """Continuum pressure of the tanh drop: dp/dr = mu phi_r, so
+    p(r) - p(inf) = (sigma_hat (d-1)/eps) int_r^inf [phi(1-phi)]^2 / r' dr'."""
+    rr = np.linspace(1e-9, 1.5, 1_500_001)
+    ph = tanh_phi(rr, R, eps)
+    f = 6.0 * (dim - 1) / eps * (ph * (1 - ph)) ** 2 / rr
+    F = cumulative_simpson(f, x=rr, initial=0.0)
+    prof = F[-1] - F                    # int_r^inf
+    return rr, prof
+
+
+def test_laplace_jump_limit():
+    """As eps -> 0 the integral tends to Laplace's law (d-1) sigma / R."""
+    for dim, R in ((2, 0.25), (3, 0.25)):
+        vals = []
+        for eps in (0.02, 0.01, 0.005):
+            val = quad(lambda r: 6.0 * (dim - 1) / eps * (tanh_phi(r, R, eps) * (1 - tanh_phi(r, R, eps))) ** 2 / r,
+                       1e-9, 1.0, points=[R], limit=400, epsabs=1e-14, epsrel=1e-13)[0]
+            vals.append(abs(val - (dim - 1) / R))
+        assert vals[-1] < 0.01 * (dim - 1) / R
+        assert min(orders(vals)) > 1.8, vals
+
+
+def test_laplace_jump_discrete_order2(ora):
+    """P5: at u = 0 the projection pressure of the energy-based force tends to
+    the continuum pressure of the tanh drop; the phi-masked jump
+    mean(p | phi > 0.99) - mean(p | phi < 0.01) converges at order 2."""
+    eps, R, errs = 0.04, 0.25, []
+    rr, prof = laplace_jump_exact(eps, R, 2)
+    for n in (64, 128, 256):
+        P = circle_params(ora, n, eps, rho1=2.0, rho2=2.0, poisson_rtol=1e-13)
+        r = radius(P)
+        phi = tanh_phi(r, R, eps)
+        zero = [np.zeros(P.shape)] * 2
+        _, _, p = ora.stage(P, phi, zero)
+        dp = ora.diagnostics(P, phi, zero, p)["dp"]
+        pe = np.interp(r, rr, prof)
+        dpe = pe[phi > 0.99].mean() - pe[phi < 0.01].mean()
+        errs.append(abs(dp - dpe))
+    assert min(orders(errs)) > 1.8, errs
+
+
+def dense_operator(ora, P, phi):
+    N = int(np.prod(P.n))
+    M = np.zeros((N, N))
+    for q in range(N):
+        e = np.zeros(N)
+        e[q] = 1.0
+        M[:, q] = ora.poisson_apply(P, phi, e.reshape(P.shape)).ravel()
+    return M
+
+
+@pytest.mark.parametrize("dim,n", [(2, 16), (3, 8)])
+def test_poisson_dense(ora, dim, n):
+    """P6: the variable-density operator D(beta G .) is symmetric, negative
+    semidefinite with exactly the constants as null space, and the oracle's
+    solution equals the dense least-squares solution (zero mean)."""
+    P = circle_params(ora, n, 1.0 / n, dim=dim, rho1=1000.0, rho2=1.0)
+    phi = ora.init_droplet(P, (0.5,) * dim, (0.3,) * dim)
+    M = dense_operator(ora, P, phi)
+    scale = np.abs(M).max()
+    np.testing.assert_allclose(M, M.T, rtol=0, atol=1e-13 * scale)
+    np.testing.assert_allclose(M.sum(axis=1), 0.0, atol=1e-12 * scale)
+    w = np.linalg.eigvalsh(M)
+    assert w[-1] < 1e-10 * scale and w[-2] < -1e-8 * scale
+    b = workloads.noise_field(P.shape, 3)
+    x, it, rr = ora.poisson_solve(P, phi, b)
+    assert rr <= 1e-13
+    xd = np.linalg.lstsq(M, (b - b.mean()).ravel(), rcond=None)[0]
+    xd -= xd.mean()
+    np.testing.assert_allclose(x.ravel(), xd, rtol=0, atol=1e-11 * np.abs(xd).max())
+
+
+def test_poisson_energy_identity(ora):
+    """Summation by parts: <x, D(beta G x)> = - sum over faces of beta_a (G_a x)^2,
+    with beta_a = 2 / (rho[c-e_a] + rho[c]) from the linear density law."""
+    for dim, n in ((2, 12), (3, 6)):
+        P = circle_params(ora, n, 1.0 / n, dim=dim, rho1=50.0, rho2=2.0)
+        phi = workloads.noise_field(P.shape, 11, 0.7) + 0.5
+        x = workloads.noise_field(P.shape, 12)
+        y = ora.poisson_apply(P, phi, x)
+        rho = 2.0 + 48.0 * np.clip(phi, 0, 1)
+        rhs = 0.0
+        for a in range(dim):
+            beta = 2.0 / (roll(rho, a, -1, dim) + rho)
+            gx = (x - roll(x, a, -1, dim)) / P.h
+            rhs -= (beta * gx * gx).sum()
+        assert np.sum(x * y) == pytest.approx(rhs, rel=1e-12)
+
+
+def test_poisson_fourier_eigenvalues(ora):
+    """Constant density: the operator is diagonal in Fourier space with
+    eigenvalue -(1/rho) sum_a (4/h^2) sin^2(pi k_a / n)."""
+    for dim, n, k in ((2, 16, (3, 1)), (3, 8, (1, 2, 3))):
+        P = circle_params(ora, n, 1.0 / n, dim=dim, rho1=4.0, rho2=4.0)
+        ax = [(np.arange(n) + 0.5) / n for _ in range(dim)]
+        g = np.meshgrid(*ax, indexing="ij")[::-1]        # g[a] = x_a on C-order array
+        mode = np.cos(2 * np.pi * sum(k[a] * g[a] for a in range(dim)) + 0.3)
+        lam = -0.25 * sum(4 * n * n * math.sin(math.pi * k[a] / n) ** 2 for a in range(dim))
+        y = ora.poisson_apply(P, np.zeros(P.shape), mode)
+        np.testing.assert_allclose(y, lam * mode, rtol=0, atol=1e-12 * abs(lam))
+        x, _, _ = ora.poisson_solve(P, np.zeros(P.shape), mode)
+        np.testing.assert_allclose(x, mode / lam, rtol=0, atol=1e-12 / abs(lam))
+
+
+# ----------------------------------------------------------------- momentum operators
+
+
+@pytest.mark.parametrize("dim,shape", [(2, (10, 12)), (3, (4, 5, 6))])
+def test_advection_kinetic_energy_identity(ora, dim, shape):
+    """Exact discrete identity of the velocity-form advection with arithmetic
+    mean fluxes: sum_a sum_c u_a N_a = -1/2 sum_a sum_c u_a^2 A_a(D m), i.e.
+    advection moves no kinetic energy when d rho/dt = -D m."""
+    n = tuple(reversed(shape))
+    P = ora.Params(n=n)
+    m = [workloads.noise_field(shape, 20 + a) for a in range(dim)]
+    u = [workloads.noise_field(shape, 40 + a) for a in range(dim)]
+    N = ora.advection(P, m, u)
+    Dm = sum((roll(m[a], a, 1, dim) - m[a]) / P.h for a in range(dim))
+    lhs = sum(np.sum(u[a] * N[a]) for a in range(dim))
+    rhs = -0.5 * sum(np.sum(u[a] ** 2 * 0.5 * (roll(Dm, a, -1, dim) + Dm)) for a in range(dim))
+    assert lhs == pytest.approx(rhs, rel=1e-12, abs=1e-12 * np.abs(rhs))
+
+
+@pytest.mark.parametrize("dim,shape", [(2, (10, 12)), (3, (4, 5, 6))])
+def test_advection_uniform_velocity_is_zero(ora, dim, shape):
+    """For a uniform velocity, N = U.div(m) - U A(D m) vanishes for any mass flux."""
+    P = ora.Params(n=tuple(reversed(shape)))
+    m = [workloads.noise_field(shape, 60 + a) for a in range(dim)]
+    u = [np.full(shape, 0.3 + 0.2 * a) for a in range(dim)]
+    N = ora.advection(P, m, u)
+    for a in range(dim):
+        assert np.abs(N[a]).max() < 1e-12 * np.abs(m[0]).max() / P.h
+
+
+@pytest.mark.parametrize("dim,shape", [(2, (10, 12)), (3, (4, 5, 6))])
+def test_viscous_self_adjoint_dissipative(ora, dim, shape):
+    """The full-stress viscous operator is self-adjoint and negative
+    semidefinite for any positive viscosity field."""
+    P = ora.Params(n=tuple(reversed(shape)))
+    eta = 0.1 + np.abs(workloads.noise_field(shape, 80))
+    u = [workloads.noise_field(shape, 81 + a) for a in range(dim)]
+    w = [workloads.noise_field(shape, 91 + a) for a in range(dim)]
+    Vu = ora.viscous(P, eta, u)
+    Vw = ora.viscous(P, eta, w)
+    a1 = sum(np.sum(Vu[a] * w[a]) for a in range(dim))
+    a2 = sum(np.sum(u[a] * Vw[a]) for a in range(dim))
+    assert a1 == pytest.approx(a2, rel=1e-12)
+    assert sum(np.sum(Vu[a] * u[a]) for a in range(dim)) < 0
+
+
+@pytest.mark.parametrize("dim,shape", [(2, (10, 12)), (3, (4, 5, 6))])
+def test_viscous_constant_viscosity(ora, dim, shape):
+    """Constant viscosity: div(eta (grad u + grad u^T)) = eta (lap u + grad div u)."""
+    P = ora.Params(n=tuple(reversed(shape)))
+    eta = np.full(shape, 0.37)
+    u = [workloads.noise_field(shape, 101 + a) for a in range(dim)]
+    V = ora.viscous(P, eta, u)
+    divu = sum((roll(u[a], a, 1, dim) - u[a]) / P.h for a in range(dim))
+    for a in range(dim):
+        lap = sum((roll(u[a], b, 1, dim) - 2 * u[a] + roll(u[a], b, -1, dim)) / P.h ** 2
+                  for b in range(dim))
+        graddiv = (divu - roll(divu, a, -1, dim)) / P.h
+        np.testing.assert_allclose(V[a], 0.37 * (lap + graddiv), rtol=0,
+                                   atol=1e-12 * np.abs(lap).max())
+
+
+# ----------------------------------------------------------------- RK4 and projection
+
+
+def rk4_amp(z):
+    return 1 + z + z * z / 2 + z ** 3 / 6 + z ** 4 / 24
+
+
+def test_rk4_fourier_advection_exact(ora):
+    """P7: gamma = 0, sigma = 0, constant u: a Fourier mode is amplified by
+    exactly R(z)^n with z = -i U dt sin(kh)/h and R the RK4 polynomial;
+    the velocity stays uniform."""
+    n, U, k, dt, steps = 32, 0.7, 2, 0.004, 25
+    P = ora.Params(n=(n, 8), gamma=0.0, sigma=0.0, rho1=2.0, rho2=2.0, visc1=0.01, visc2=0.01)
+    x = (np.arange(n) + 0.5) / n
+    phi0 = np.tile(0.5 + 0.1 * np.cos(2 * np.pi * k * x), (8, 1))
+    u = [np.full(P.shape, U), np.zeros(P.shape)]
+    phi, uu, _ = ora.step(P, dt, steps, phi0, u)
+    z = -1j * U * dt * math.sin(2 * math.pi * k * P.h) / P.h
+    exact = 0.5 + 0.1 * np.real(rk4_amp(z) ** steps * np.exp(2j * np.pi * k * x))
+    np.testing.assert_allclose(phi, np.tile(exact, (8, 1)), rtol=0, atol=1e-13)
+    np.testing.assert_allclose(uu[0], U, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(uu[1], 0.0, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_rk4_shear_wave_exact(ora, dim):
+    """P8: a shear wave u_a = U sin(2 pi x_b) in a single fluid decays by
+    exactly R(-nu dt lam)^n with lam = (4/h^2) sin^2(pi h); advection and
+    pressure vanish identically."""
+    n, U, dt, steps = 16, 0.2, 2e-3, 12
+    nu_rho, visc = 2.0, 0.5
+    P = ora.Params(n=(n,) * dim, rho1=nu_rho, rho2=nu_rho, visc1=visc, visc2=visc, sigma=1.0)
+    yc = (np.arange(n) + 0.5) / n
+    shape = P.shape
+    # 2D: u_x(y) and u_y(x) (their advection is the gradient of u_x u_y, which
+    # the projection removes); 3D: u_x(y) and u_z(y) (advection vanishes)
+    u0 = [np.zeros(shape) for _ in range(dim)]
+    prof_y = U * np.sin(2 * np.pi * yc)
+    u0[0] += prof_y.reshape([-1 if d == dim - 2 else 1 for d in range(dim)])
+    axis2 = dim - 1 if dim == 2 else dim - 2
+    u0[dim - 1] += 0.5 * prof_y.reshape([-1 if d == axis2 else 1 for d in range(dim)])
+    phi0 = np.zeros(shape)
+    phi, uu, _ = ora.step(P, dt, steps, phi0, u0)
+    lam = 4 * n * n * math.sin(math.pi / n) ** 2
+    amp = rk4_amp(-visc / nu_rho * dt * lam) ** steps
+    for a in range(dim):
+        np.testing.assert_allclose(uu[a], amp * u0[a], rtol=0, atol=1e-14)
+    assert np.abs(phi).max() == 0.0
+
+
+def test_cdi_conserves_mass(ora):
+    """P9: the CDI model is in divergence form, so sum(phi) is conserved to
+    round-off whatever the velocity."""
+    P = ora.Params(n=(32, 32), eps=1 / 32, rho1=10.0, rho2=1.0, visc1=0.01, visc2=0.001)
+    phi = ora.init_droplet(P, (0.5, 0.5), (0.3, 0.22))
+    u = workloads.random_velocity(P.shape, 5, amplitude=0.2)
+    m0 = phi.sum()
+    phi1, u1, _ = ora.step(P, 2e-4, 5, phi, u)
+    assert abs(phi1.sum() - m0) / m0 < 1e-13
+    assert np.abs(phi1 - phi).max() > 1e-6        # something actually moved
+
+
+@pytest.mark.parametrize("dim,n", [(2, 24), (3, 10)])
+def test_mass_flux_consistent_with_phase_flux(ora, dim, n):
+    """The momentum mass flux carries exactly the density change the phase
+    field makes: with the linear density law and D u = 0,
+    D m = -(rho1 - rho2) dphi/dt (CDI includes the regularisation flux)."""
+    P = ora.Params(n=(n,) * dim, eps=1.0 / n, rho1=7.0, rho2=0.5, clamp=0)
+    phi = ora.init_droplet(P, (0.5,) * dim, (0.3,) * dim)
+    u = workloads.divergence_free_velocity(P.shape, 4, 0.3)
+    assert np.abs(ora.divergence(P, u)).max() < 1e-12
+    m = ora.mass_flux(P, phi, u)
+    lhs = ora.divergence(P, m)
+    rhs = -(7.0 - 0.5) * ora.phase_rhs(P, phi, u)
+    np.testing.assert_allclose(lhs, rhs, rtol=0, atol=1e-11 * np.abs(rhs).max())
+
+
+def test_kinetic_energy_conserved_inviscid(ora):
+    """Semi-discrete energy conservation (CDI, whose mass flux is consistent
+    with the phase-field flux): without viscosity or surface tension the
+    advection, the face-density kinetic energy and the projection give
+    dKE/dt = 0 exactly, so one RK4 step changes KE by O(dt^5).  (SB and ISODI
+    change the density outside divergence form, so they do not conserve it.)"""
+    P = ora.Params(n=(24, 24), eps=1 / 24, rho1=10.0, rho2=1.0, visc1=0.0, visc2=0.0,
+                   sigma=0.0, gamma=0.5, clamp=0)
+    phi = ora.init_droplet(P, (0.5, 0.5), (0.3, 0.22))
+    u = workloads.divergence_free_velocity(P.shape, 8, 0.3)
+    ke0 = ora.diagnostics(P, phi, u)["ke"]
+    dke = []
+    for dt in (4e-3, 2e-3, 1e-3):
+        f1, u1, _ = ora.step(P, dt, 1, phi, u)
+        dke.append(abs(ora.diagnostics(P, f1, u1)["ke"] - ke0) / ke0)
+    assert dke[0] < 1e-6 and min(orders(dke)) > 4.5, dke
+
+
+def test_kinetic_energy_viscous_budget(ora):
+    """With viscosity the semi-discrete budget is dKE/dt = <u, V(u)> h^d
+    (variable density and viscosity, CDI, no surface tension)."""
+    P = ora.Params(n=(24, 24), eps=1 / 24, rho1=10.0, rho2=1.0, visc1=0.02, visc2=0.004,
+                   sigma=0.0, gamma=0.5, clamp=0)
+    phi = ora.init_droplet(P, (0.5, 0.5), (0.3, 0.22))
+    u = workloads.divergence_free_velocity(P.shape, 8, 0.3)
+    ke0 = ora.diagnostics(P, phi, u)["ke"]
+    V = ora.viscous(P, ora.viscosity_field(P, phi), u)
+    rate = sum(np.sum(u[a] * V[a]) for a in range(2)) * P.h ** 2
+    errs = []
+    for dt in (2e-3, 1e-3, 5e-4):
+        f1, u1, _ = ora.step(P, dt, 1, phi, u)
+        errs.append(abs((ora.diagnostics(P, f1, u1)["ke"] - ke0) / dt - rate))
+    assert errs[-1] < 0.05 * abs(rate)
+    assert min(orders(errs)) > 0.9, errs
+
+
+def test_uniform_velocity_stays_uniform(ora):
+    """Galilean check: sigma = 0, any phi and density ratio -- a uniform
+    velocity stays exactly uniform (advection, viscous and pressure terms vanish)."""
+    for model in ("CDI", "SB", "ISODI"):
+        P = ora.Params(n=(24, 20), eps=1 / 24, sigma=0.0, rho1=1000.0, rho2=1.0, visc1=0.1,
+                       visc2=0.001, model=ora.MODELS[model])
+        phi = ora.init_droplet(P, (0.4, 0.6), (0.2, 0.25))
+        u = [np.full(P.shape, 0.3), np.full(P.shape, -0.2)]
+        _, uu, _ = ora.step(P, 5e-4, 3, phi, u)
+        np.testing.assert_allclose(uu[0], 0.3, rtol=0, atol=1e-13)
+        np.testing.assert_allclose(uu[1], -0.2, rtol=0, atol=1e-13)
+
+
+def test_projection_divergence_free(ora):
+    """P11: every stage derivative is discretely divergence free, so D u stays
+    at its initial (zero) value up to the solver tolerance."""
+    P = ora.Params(n=(32, 32), eps=1 / 32, rho1=100.0, rho2=1.0, visc1=0.01, visc2=0.001,
+                   force=ora.CSF)
+    phi = ora.init_droplet(P, (0.5, 0.5), (0.3, 0.22))
+    zero = [np.zeros(P.shape)] * 2
+    phi1, u1, _ = ora.step(P, 5e-5, 4, phi, zero)
+    umax = max(np.abs(x).max() for x in u1)
+    assert umax > 0
+    assert ora.diagnostics(P, phi1, u1)["div_max"] * P.h < 1e-10 * umax
+
+
+# ----------------------------------------------------------------- symmetry / translation
+
+
+@pytest.mark.parametrize("model,force", [("CDI", "EB"), ("SB", "LCSF"), ("ISODI", "CSF")])
+def test_mirror_symmetry(ora, model, force):
+    """P10: an ellipse centred in the box keeps both mirror symmetries
+    (cell i <-> n-1-i, face velocity u_x[i] <-> -u_x[n-i])."""
+    n = 32
+    P = ora.Params(n=(n, n), eps=1 / 32, rho1=10.0, rho2=1.0, visc1=0.01, visc2=0.002,
+                   model=ora.MODELS[model], force=ora.FORCES[force])
+    phi0 = ora.init_droplet(P, (0.5, 0.5), (0.3, 0.22))
+    zero = [np.zeros(P.shape)] * 2
+    phi, u, _ = ora.step(P, 1e-4, 3, phi0, zero)
+    us = max(np.abs(u[0]).max(), np.abs(u[1]).max())
+    assert us > 0
+    np.testing.assert_allclose(phi, phi[:, ::-1], rtol=0, atol=1e-14)
+    np.testing.assert_allclose(phi, phi[::-1, :], rtol=0, atol=1e-14)
+    ux_m = -np.roll(u[0][:, ::-1], 1, axis=1)         # u_x[i] -> -u_x[n - i]
+    np.testing.assert_allclose(u[0], ux_m, rtol=0, atol=1e-11 * us)
+    np.testing.assert_allclose(u[1], u[1][:, ::-1], rtol=0, atol=1e-11 * us)
+    uy_m = -np.roll(u[1][::-1, :], 1, axis=0)
+    np.testing.assert_allclose(u[1], uy_m, rtol=0, atol=1e-11 * us)
+
+
+def test_swap_symmetry_and_translation(ora):
+    """A circle is invariant under x <-> y (u_x <-> u_y); an integer-cell
+    shift of the initial state shifts the result."""
+    n = 24
+    P = ora.Params(n=(n, n), eps=1 / 24, rho1=5.0, rho2=1.0, visc1=0.02, visc2=0.01)
+    phi0 = ora.init_droplet(P, (0.5, 0.5), (0.27, 0.27))
+    u0 = workloads.random_velocity(P.shape, 9, 0.05)
+    u0 = [u0[0], u0[0].T.copy()]
+    phi, u, _ = ora.step(P, 2e-4, 2, phi0, u0)
+    us = np.abs(u[0]).max()
+    np.testing.assert_allclose(phi, phi.T, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(u[0], u[1].T, rtol=0, atol=1e-11 * us)
+    sh = (5, -3)
+    phis, us_, _ = ora.step(P, 2e-4, 2, np.roll(phi0, sh, (0, 1)),
+                            [np.roll(x, sh, (0, 1)) for x in u0])
+    np.testing.assert_allclose(phis, np.roll(phi, sh, (0, 1)), rtol=0, atol=1e-13)
+    for a in range(2):
+        np.testing.assert_allclose(us_[a], np.roll(u[a], sh, (0, 1)), rtol=0, atol=1e-11 * us)
+
+
+def test_3d_reduces_to_2d(ora):
+    """A 3D state that is uniform along one axis evolves exactly like the 2D
+    state in the other two axes (both the z-uniform and y-uniform cases)."""
+    n, nz = 16, 4
+    kw = dict(eps=1 / 16, rho1=10.0, rho2=1.0, visc1=0.02, visc2=0.005, force=ora.CSF)
+    P2 = ora.Params(n=(n, n), **kw)
+    phi2 = ora.init_droplet(P2, (0.5, 0.5), (0.3, 0.22))
+    zero2 = [np.zeros(P2.shape)] * 2
+    ref, uref, _ = ora.step(P2, 2e-4, 2, phi2, zero2)
+    us = max(np.abs(x).max() for x in uref)
+    # uniform along z: (nz, ny, nx) with the 2D field in (y, x)
+    P3 = ora.Params(n=(n, n, nz), **kw)
+    phi3 = np.repeat(phi2[None, :, :], nz, axis=0)
+    z3 = [np.zeros(P3.shape)] * 3
+    f3, u3, _ = ora.step(P3, 2e-4, 2, phi3, z3)
+    for k in range(nz):
+        np.testing.assert_allclose(f3[k], ref, rtol=0, atol=1e-13)
+        np.testing.assert_allclose(u3[0][k], uref[0], rtol=0, atol=1e-10 * us)
+        np.testing.assert_allclose(u3[1][k], uref[1], rtol=0, atol=1e-10 * us)
+    assert np.abs(u3[2]).max() < 1e-10 * us
+    # uniform along y: 2D axes (x, y) become 3D axes (x, z)
+    P3b = ora.Params(n=(n, nz, n), **kw)
+    phi3b = np.repeat(phi2[:, None, :], nz, axis=1)
+    f3b, u3b, _ = ora.step(P3b, 2e-4, 2, phi3b, [np.zeros(P3b.shape)] * 3)
+    for j in range(nz):
+        np.testing.assert_allclose(f3b[:, j, :], ref, rtol=0, atol=1e-13)
+        np.testing.assert_allclose(u3b[0][:, j, :], uref[0], rtol=0, atol=1e-10 * us)
+        np.testing.assert_allclose(u3b[2][:, j, :], uref[1], rtol=0, atol=1e-10 * us)
+    assert np.abs(u3b[1]).max() < 1e-10 * us
+
+
+# ----------------------------------------------------------------- diagnostics
+
+
+def test_diagnostics_mass_and_surface_energy(ora):
+    """Mass -> int phi dA (midpoint rule, spectrally accurate on this smooth
+    periodic field) and the free energy -> the continuum value of the tanh
+    drop at order 2; SE -> sigma * perimeter as eps -> 0 (Z16 reading)."""
+    eps, R = 0.02, 0.25
+    se_exact = quad(lambda r: 2 * np.pi * r * 6.0 / eps * (tanh_phi(r, R, eps) * (1 - tanh_phi(r, R, eps))) ** 2,
+                    0, 0.5, points=[R], epsabs=1e-14, limit=200)[0]
+    assert se_exact == pytest.approx(2 * np.pi * R, rel=5e-3)
+    errs = []
+    for n in (128, 256, 512):
+        P = circle_params(ora, n, eps)
+        phi = tanh_phi(radius(P), R, eps)
+        d = ora.diagnostics(P, phi, [np.zeros(P.shape)] * 2)
+        errs.append(abs(d["se"] - se_exact))
+    # mass: thin interface so the box corners (r > 1/2) hold < 1e-11 of phi
+    e2 = 0.01
+    m_exact = quad(lambda r: 2 * np.pi * r * tanh_phi(r, R, e2), 0, 0.5, points=[R],
+                   epsabs=1e-15, limit=200)[0]
+    P = circle_params(ora, 256, e2)
+    d = ora.diagnostics(P, tanh_phi(radius(P), R, e2), [np.zeros(P.shape)] * 2)
+    assert d["mass"] == pytest.approx(m_exact, rel=1e-11)
+    assert min(orders(errs)) > 1.8, errs
+
+
+def test_diagnostics_velocity(ora):
+    """Uniform flow: Ca = |U| visc1/sigma, KE = rho U^2 |box| / 2, div = 0."""
+    P = ora.Params(n=(16, 16), rho1=3.0, rho2=3.0, visc1=0.2, sigma=2.0)
+    u = [np.full(P.shape, 0.3), np.full(P.shape, 0.4)]
+    d = ora.diagnostics(P, np.full(P.shape, 0.5), u)
+    assert d["umax"] == pytest.approx(0.5)
+    assert d["ca_inf"] == pytest.approx(0.5 * 0.2 / 2.0)
+    assert d["ke"] == pytest.approx(0.5 * 3.0 * 0.25)
+    assert d["div_max"] == 0.0
