@@ -1,0 +1,179 @@
+/*
+ * tpf.h -- C ABI of the MI355X (gfx950) two-phase phase-field step library.
+ *
+ * Method: Mirjalili, Khanwale & Mani, "Assessment of an energy-based surface
+ * tension model for simulation of two-phase flows using second-order phase
+ * field methods" (arXiv 2205.05835).  One time step advances the phase field
+ * phi (Eq. 1 with a regularisation g of Table 1: CDI, SB or ISODI) and the
+ * incompressible velocity u with a surface tension force on cell faces
+ * (energy-based F = mu grad phi of Eq. 5 with mu of Eq. 2, or CSF, or the
+ * localized CSF of Eq. 12), momentum advection and viscous diffusion, and a
+ * variable-density pressure projection D(beta G p) = D f*, integrated with
+ * classical RK4 on a uniform periodic staggered grid (Sec. 3, opening).
+ *
+ * Grid and layout (every array handed across this ABI):
+ *   cells (nx, ny, nz), nz = 1 in 2D, equal spacing h = length / nx on all
+ *   axes; cell c = (k*ny + j)*nx + i, x fastest (C order [z][y][x]).
+ *   phi, p live at cell centres; velocity component u_a[c] lives on the LOWER
+ *   a-face of cell c (between c - e_a and c).  Phase 1 is phi = 1.
+ *
+ * Memory and streams:
+ *   The caller owns all device memory.  tpf_workspace_bytes() sizes one
+ *   device buffer that the caller allocates and passes to tpf_create(); the
+ *   library carves every field, multigrid level and reduction scratch out of
+ *   it and never allocates device memory itself.  All work is issued on the
+ *   hip_stream given at creation (NULL = the legacy default stream).
+ *   Host-side arrays passed to set/get functions are read or written before
+ *   the call returns and are never retained.  Arrays exchanged across the ABI
+ *   are always FP64, whatever the internal precision.
+ *
+ * Errors: every call returns a tpf_status; nothing throws, nothing aborts.
+ * tpf_last_error() returns a thread-local message for the last failure.
+ * One context must not be used from two host threads at once.
+ */
+#ifndef TPF_H
+#define TPF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TPF_OK = 0,
+    TPF_EINVAL = -1,     /* invalid argument or parameter set                   */
+    TPF_ENOMEM = -2,     /* workspace smaller than tpf_workspace_bytes()        */
+    TPF_EDEVICE = -3,    /* a HIP runtime call failed                           */
+    TPF_ENOCONV = -4,    /* pressure solve hit poisson_maxit; state rolled back */
+    TPF_ENONFINITE = -5, /* NaN/Inf produced by a step; state rolled back       */
+    TPF_ESTATE = -6      /* call not valid in the current context state         */
+} tpf_status;
+
+typedef enum { TPF_CDI = 0, TPF_SB = 1, TPF_ISODI = 2 } tpf_model;  /* Table 1 */
+typedef enum { TPF_EB = 0, TPF_CSF = 1, TPF_LCSF = 2 } tpf_force;   /* Eq. 5, CSF, Eq. 12 */
+typedef enum {
+    TPF_FP64 = 0,        /* everything in FP64                                   */
+    TPF_FP32_MIXED = 1   /* FP32 state, stencils and smoothers; FP64 pressure,
+                            Poisson right-hand side, outer residual (defect
+                            correction) and all diagnostics                     */
+} tpf_precision;
+
+/* Parameters of one case.  Non-dimensional throughout. */
+typedef struct {
+    int32_t dim;              /* 2 or 3                                           */
+    int32_t n[3];             /* cells per axis; n[2] = 1 when dim = 2            */
+    double length;            /* box edge along x; h = length / n[0]              */
+    int32_t model;            /* tpf_model                                        */
+    int32_t force;            /* tpf_force                                        */
+    int32_t precision;        /* tpf_precision                                    */
+    int32_t clamp_properties; /* 1: clamp phi to [0,1] in the density/viscosity laws */
+    double sigma;             /* surface tension coefficient (sigma_hat = 6 sigma, Eq. 2) */
+    double eps;               /* interface thickness epsilon                      */
+    double gamma;             /* regularisation velocity scale gamma (Table 1)    */
+    double rho1, rho2;        /* densities of phase phi=1 and phi=0               */
+    double visc1, visc2;      /* dynamic viscosities of phase phi=1 and phi=0     */
+    double normal_delta;      /* n = g / sqrt(g.g + delta^2); 0 -> 1e-12          */
+    double poisson_rtol;      /* stop at ||r|| <= rtol ||rhs||; 0 -> 1e-13 (FP64) or 1e-9 (mixed) */
+    double poisson_rtol_inner;/* FP32 inner PCG tolerance (mixed); 0 -> 1e-4      */
+    int32_t poisson_maxit;    /* PCG iteration cap per solve; 0 -> 400            */
+    int32_t mg_levels;        /* multigrid levels; 0 -> as deep as the grid allows */
+} tpf_params;
+
+/* Scalar diagnostics of the current state (FP64; t and step count included). */
+typedef struct {
+    double t;
+    int64_t step;
+    double mass;          /* h^d sum phi                                          */
+    double mass0;         /* mass when the state was last set                     */
+    double phi_min, phi_max;
+    double umax;          /* max over cells of |cell-averaged u|                  */
+    double ca_inf;        /* umax * visc1 / sigma (Sec. 3.1)                      */
+    double ke;            /* 1/2 h^d sum_a sum_c rho_a u_a^2 (face densities)     */
+    double se;            /* h^d sum [sigma_hat/eps psi + 1/2 sigma_hat eps |G phi|^2] */
+    double dp;            /* mean(p | phi > 0.99) - mean(p | phi < 0.01)          */
+    double div_max;       /* max |D u|                                            */
+    double poisson_relres;/* relative residual of the last pressure solve         */
+    int32_t poisson_outer;/* outer (defect-correction) iterations, last solve     */
+    int32_t poisson_inner;/* PCG iterations, last solve (summed over outer)       */
+} tpf_diag;
+
+typedef struct tpf_ctx tpf_ctx;
+
+/* Size in bytes of the device workspace for params (validated first). */
+tpf_status tpf_workspace_bytes(const tpf_params* params, size_t* bytes);
+
+/* Create a context on the current HIP device.  workspace: device pointer,
+ * 256-byte aligned, at least tpf_workspace_bytes(); owned by the caller and
+ * not freed by tpf_destroy().  hip_stream: a hipStream_t (may be NULL). */
+tpf_status tpf_create(const tpf_params* params, void* workspace, size_t ws_bytes,
+                      void* hip_stream, tpf_ctx** out);
+tpf_status tpf_destroy(tpf_ctx* ctx);
+
+/* Set the state.  phi: N = nx*ny*nz values; u: dim arrays of N values (u[2]
+ * ignored in 2D).  on_device = 1: device pointers read on the context's stream;
+ * 0: host pointers, copied before return.  Resets t, step and the pressure
+ * warm start, and records mass0. */
+tpf_status tpf_set_state(tpf_ctx* ctx, const double* phi, const double* u0,
+                         const double* u1, const double* u2, int32_t on_device);
+
+/* phi = [1 + tanh(s / 2 eps)] / 2 (Eq. 2 footnote) for an ellipse/ellipsoid
+ * with the given centre and semi-axes (s = first-order signed distance,
+ * minimum image in the periodic box); u = 0, p = 0. */
+tpf_status tpf_init_droplet(tpf_ctx* ctx, const double center[3], const double semi_axes[3]);
+
+/* Advance nsteps classical RK4 steps of size dt (> 0).  Each step is
+ * transactional: on TPF_ENOCONV / TPF_ENONFINITE the state stays at the last
+ * completed step. */
+tpf_status tpf_step(tpf_ctx* ctx, double dt, int32_t nsteps);
+
+/* Copy the state out (any pointer may be NULL to skip it).  p is the
+ * projection pressure of the current state (computed on demand by one stage
+ * evaluation, zero mean). */
+tpf_status tpf_get_state(tpf_ctx* ctx, double* phi, double* u0, double* u1, double* u2,
+                         double* p, int32_t on_device);
+
+/* Diagnostics of the current state; synchronises the stream.  dp uses the
+ * projection pressure of the current state (one stage evaluation). */
+tpf_status tpf_diagnostics(tpf_ctx* ctx, tpf_diag* out);
+
+/* Fields of one stage evaluation at the current state, for verification of
+ * each operator.  out: N doubles (host if on_device = 0). */
+typedef enum {
+    TPF_FIELD_NORMAL0 = 0, TPF_FIELD_NORMAL1, TPF_FIELD_NORMAL2,   /* n_a at cells      */
+    TPF_FIELD_MU,                                                  /* mu (Eq. 2)        */
+    TPF_FIELD_KAPPA,                                               /* kappa (Eq. 3)     */
+    TPF_FIELD_CDIFLUX0, TPF_FIELD_CDIFLUX1, TPF_FIELD_CDIFLUX2,    /* CDI face flux r_a */
+    TPF_FIELD_MASSFLUX0, TPF_FIELD_MASSFLUX1, TPF_FIELD_MASSFLUX2, /* m_a              */
+    TPF_FIELD_DPHI,                                                /* dphi/dt (Eq. 1)   */
+    TPF_FIELD_FORCE0, TPF_FIELD_FORCE1, TPF_FIELD_FORCE2,          /* surface force F_a */
+    TPF_FIELD_FSTAR0, TPF_FIELD_FSTAR1, TPF_FIELD_FSTAR2,          /* f*_a              */
+    TPF_FIELD_DIVFSTAR,                                            /* D f*              */
+    TPF_FIELD_PRESSURE,                                            /* p                 */
+    TPF_FIELD_DU0, TPF_FIELD_DU1, TPF_FIELD_DU2,                   /* du_a/dt           */
+    TPF_FIELD_COUNT
+} tpf_field;
+tpf_status tpf_eval_field(tpf_ctx* ctx, int32_t field, double* out, int32_t on_device);
+
+/* Solve D(beta G x) = b - mean(b), mean(x) = 0, with beta from the current
+ * phi, by the library's multigrid-preconditioned CG.  b, x: N doubles; x is
+ * the initial guess on entry.  iters/relres may be NULL. */
+tpf_status tpf_poisson_solve(tpf_ctx* ctx, const double* b, double* x, int32_t on_device,
+                             int32_t* iters, double* relres);
+
+/* Per-kernel-class device timing (HIP events on the context stream around
+ * each launch).  enable = 1 clears and starts recording; names/ms/launches
+ * report accumulated totals per class. */
+tpf_status tpf_profile_enable(tpf_ctx* ctx, int32_t enable);
+tpf_status tpf_profile_read(tpf_ctx* ctx, int32_t kernel_class, const char** name,
+                            double* total_ms, int64_t* launches, double* bytes_per_launch);
+int32_t tpf_profile_classes(void);
+
+const char* tpf_last_error(void);
+const char* tpf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,162 @@
+// Device-side helpers shared by the stage and pressure kernels: periodic
+// indexing on the [z][y][x] cell grid, the pointwise laws of the method and
+// the deterministic block reductions.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace tpf {
+
+// 256-thread blocks laid out as 64 consecutive x cells (one wave64 = one
+// coalesced row segment) by 4 rows in y; grid z walks the z planes.
+constexpr int BX = 64;
+constexpr int BY = 4;
+constexpr int BLOCK = BX * BY;
+
+struct Dims {
+    int nx, ny, nz;
+};
+
+// Physical parameters as the kernels consume them.
+struct Phys {
+    int model, force, clamp;
+    double h, inv_h, sigma, sigma_hat, eps, gamma, rho1, rho2, visc1, visc2, delta2;
+};
+
+enum { MODEL_CDI = 0, MODEL_SB = 1, MODEL_ISODI = 2 };
+enum { FORCE_EB = 0, FORCE_CSF = 1, FORCE_LCSF = 2 };
+
+// wrap an index that is at most one period out of range
+__device__ __forceinline__ int wrapc(int v, int n) {
+    v = v < 0 ? v + n : v;
+    return v >= n ? v - n : v;
+}
+
+// A cell and its periodic neighbours; a, b are physical axes (0 = x).
+struct Cell {
+    int i, j, k;
+    int nx, ny, nz;
+    __device__ __forceinline__ long id() const { return ((long)k * ny + j) * nx + i; }
+    __device__ __forceinline__ long at(int di, int dj, int dk) const {
+        return ((long)wrapc(k + dk, nz) * ny + wrapc(j + dj, ny)) * nx + wrapc(i + di, nx);
+    }
+    // c + s e_a + t e_b
+    __device__ __forceinline__ long off2(int a, int s, int b, int t) const {
+        int d[3] = {0, 0, 0};
+        d[a] += s;
+        d[b] += t;
+        return at(d[0], d[1], d[2]);
+    }
+    __device__ __forceinline__ long off(int a, int s) const { return off2(a, s, a, 0); }
+};
+
+__device__ __forceinline__ bool cell_of_thread(const Dims& d, Cell& C) {
+    C.i = blockIdx.x * BX + threadIdx.x;
+    C.j = blockIdx.y * BY + threadIdx.y;
+    C.k = blockIdx.z;
+    C.nx = d.nx;
+    C.ny = d.ny;
+    C.nz = d.nz;
+    return C.i < d.nx && C.j < d.ny;
+}
+
+__device__ __forceinline__ int block_linear() {
+    return (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+}
+__device__ __forceinline__ int nblocks_linear() { return gridDim.x * gridDim.y * gridDim.z; }
+__device__ __forceinline__ int thread_linear() {
+    return (threadIdx.z * blockDim.y + threadIdx.y) * blockDim.x + threadIdx.x;
+}
+
+// ---------------------------------------------------------------- pointwise laws
+
+// psi'(phi) = phi (1 - phi)(1 - 2 phi)   (Eq. 2)
+template <typename T>
+__device__ __forceinline__ T dpsi(T f) {
+    return f * (T(1) - f) * (T(1) - T(2) * f);
+}
+template <typename T>
+__device__ __forceinline__ T psi(T f) {
+    T w = f * (T(1) - f);
+    return T(0.5) * w * w;
+}
+template <typename T>
+__device__ __forceinline__ T clamp01(const Phys& P, T f) {
+    if (!P.clamp) return f;
+    return f < T(0) ? T(0) : (f > T(1) ? T(1) : f);
+}
+// linear mixture laws, phase 1 = phi 1
+template <typename T>
+__device__ __forceinline__ T rho_of(const Phys& P, T f) {
+    return T(P.rho2) + T(P.rho1 - P.rho2) * clamp01(P, f);
+}
+template <typename T>
+__device__ __forceinline__ T visc_of(const Phys& P, T f) {
+    return T(P.visc2) + T(P.visc1 - P.visc2) * clamp01(P, f);
+}
+
+// ---------------------------------------------------------------- reductions
+
+// Sum NV values over a 256-thread block (wave64 shuffles, then LDS across the
+// four waves).  Result valid in thread 0.  Fixed order: deterministic.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV]) {
+    __shared__ double red[NV][BLOCK / 64];
+    const int t = thread_linear();
+    const int lane = t & 63, wave = t >> 6;
+#pragma unroll
+    for (int q = 0; q < NV; ++q)
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_down(v[q], o, 64);
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < NV; ++q) red[q][wave] = v[q];
+    __syncthreads();
+    if (t == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            double s = 0.0;
+            for (int w = 0; w < BLOCK / 64; ++w) s += red[q][w];
+            v[q] = s;
+        }
+    }
+}
+
+template <int NV>
+__device__ __forceinline__ void block_max(double (&v)[NV]) {
+    __shared__ double red[NV][BLOCK / 64];
+    const int t = thread_linear();
+    const int lane = t & 63, wave = t >> 6;
+#pragma unroll
+    for (int q = 0; q < NV; ++q)
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v[q] = fmax(v[q], __shfl_down(v[q], o, 64));
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < NV; ++q) red[q][wave] = v[q];
+    __syncthreads();
+    if (t == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            double s = red[q][0];
+            for (int w = 1; w < BLOCK / 64; ++w) s = fmax(s, red[q][w]);
+            v[q] = s;
+        }
+    }
+}
+
+// Write the block sums of NV values to partials[q * nblocks + block].
+template <int NV>
+__device__ __forceinline__ void block_partials(double (&v)[NV], double* partials) {
+    block_sum<NV>(v);
+    if (thread_linear() == 0) {
+        const int nb = nblocks_linear(), b = block_linear();
+#pragma unroll
+        for (int q = 0; q < NV; ++q) partials[(long)q * nb + b] = v[q];
+    }
+}
+
+}  // namespace tpf

@@ -1,0 +1,577 @@
+// Host runtime behind the C ABI of include/tpf.h: parameter validation,
+// workspace carving, the RK4 driver with a projection at every stage,
+// state transfer, diagnostics and per-kernel timing.
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "tpf_internal.hpp"
+
+namespace tpf {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+tpf_status hip_fail(hipError_t e, const char* what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return TPF_EDEVICE;
+}
+
+Phys phys_of(const tpf_ctx* c) {
+    Phys P;
+    P.model = c->P.model;
+    P.force = c->P.force;
+    P.clamp = c->P.clamp_properties;
+    P.h = c->h;
+    P.inv_h = 1.0 / c->h;
+    P.sigma = c->P.sigma;
+    P.sigma_hat = 6.0 * c->P.sigma;
+    P.eps = c->P.eps;
+    P.gamma = c->P.gamma;
+    P.rho1 = c->P.rho1;
+    P.rho2 = c->P.rho2;
+    P.visc1 = c->P.visc1;
+    P.visc2 = c->P.visc2;
+    P.delta2 = c->P.normal_delta * c->P.normal_delta;
+    return P;
+}
+
+// ---------------------------------------------------------------- profiling
+static const char* kProfNames[NPROF] = {
+    "stage_cell", "stage_kappa", "stage_face", "stage_phase", "stage_momentum", "stage_div",
+    "stage_project", "pcg_apply_fine", "mg_jacobi_fine", "mg_restrict_fine", "mg_prolong_fine",
+    "pcg_vector_fine", "mg_coarse_levels", "outer_residual64", "reduce_finalize", "other"};
+
+static void prof_flush(tpf_ctx* c) {
+    if (c->ev_count == 0) return;
+    (void)hipStreamSynchronize(c->stream);
+    for (int q = 0; q < c->ev_count; ++q) {
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, c->ev_a[q], c->ev_b[q]);
+        c->prof_ms[c->ev_class[q]] += ms;
+        c->prof_launches[c->ev_class[q]] += 1;
+        c->prof_bytes[c->ev_class[q]] += c->ev_bytes[q];
+    }
+    c->ev_count = 0;
+}
+
+void prof_begin(tpf_ctx* c, int cls, double bytes) {
+    if (!c->prof_on) return;
+    if (c->ev_count == 64) prof_flush(c);
+    const int q = c->ev_count;
+    c->ev_class[q] = cls;
+    c->ev_bytes[q] = bytes;
+    (void)hipEventRecord(c->ev_a[q], c->stream);
+}
+
+void prof_end(tpf_ctx* c) {
+    if (!c->prof_on) return;
+    (void)hipEventRecord(c->ev_b[c->ev_count], c->stream);
+    c->ev_count += 1;
+}
+
+// ---------------------------------------------------------------- workspace
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Carver {
+    char* base;
+    size_t off = 0;
+    void* take(size_t bytes) {
+        void* p = base ? base + off : nullptr;
+        off = align256(off + bytes);
+        return p;
+    }
+};
+
+static int plan_levels(tpf_ctx* c) {
+    int n[3] = {c->n[0], c->n[1], c->n[2]};
+    int L = 1;
+    const int maxl = c->P.mg_levels > 0 ? c->P.mg_levels : MAX_LEVELS;
+    c->lv[0].n[0] = n[0];
+    c->lv[0].n[1] = n[1];
+    c->lv[0].n[2] = n[2];
+    c->lv[0].h = c->h;
+    while (L < maxl && L < MAX_LEVELS) {
+        bool ok = true;
+        for (int a = 0; a < c->dim; ++a)
+            if (n[a] % 2 != 0 || n[a] < 8) ok = false;
+        if (!ok) break;
+        for (int a = 0; a < c->dim; ++a) n[a] /= 2;
+        Level& Lv = c->lv[L];
+        Lv.n[0] = n[0];
+        Lv.n[1] = n[1];
+        Lv.n[2] = c->dim == 3 ? n[2] : 1;
+        Lv.h = c->lv[L - 1].h * 2.0;
+        ++L;
+    }
+    for (int l = 0; l < L; ++l) c->lv[l].N = (long)c->lv[l].n[0] * c->lv[l].n[1] * c->lv[l].n[2];
+    return L;
+}
+
+static size_t carve(tpf_ctx* c, char* base) {
+    Carver cv{base};
+    const size_t NT = (size_t)c->N * c->tsz;
+    const size_t N8 = (size_t)c->N * 8;
+    const size_t ssz = c->mixed ? 4 : 8;
+    for (int s = 0; s < 4; ++s) {
+        c->phi[s] = cv.take(NT);
+        for (int a = 0; a < 3; ++a) c->u[a][s] = a < c->dim ? cv.take(NT) : nullptr;
+    }
+    for (int a = 0; a < 3; ++a) {
+        const bool on = a < c->dim;
+        c->nrm[a] = on ? cv.take(NT) : nullptr;
+        c->rflux[a] = on ? cv.take(NT) : nullptr;
+        c->mflux[a] = on ? cv.take(NT) : nullptr;
+        c->fs[a] = on ? cv.take(NT) : nullptr;
+        c->force[a] = on ? cv.take(NT) : nullptr;
+    }
+    c->mu = cv.take(NT);
+    c->kappa = cv.take(NT);
+    c->b = (double*)cv.take(N8);
+    c->p = (double*)cv.take(N8);
+    c->r64 = c->mixed ? (double*)cv.take(N8) : nullptr;
+    c->pv = cv.take((size_t)c->N * ssz);
+    c->qv = cv.take((size_t)c->N * ssz);
+    c->ev = c->mixed ? cv.take((size_t)c->N * ssz) : nullptr;
+    for (int l = 0; l < c->nlev; ++l) {
+        Level& L = c->lv[l];
+        for (int a = 0; a < 3; ++a) L.beta[a] = a < c->dim ? cv.take((size_t)L.N * ssz) : nullptr;
+        L.z = cv.take((size_t)L.N * ssz);
+        L.zt = cv.take((size_t)L.N * ssz);
+        L.r = cv.take((size_t)L.N * ssz);
+    }
+    c->max_blocks = std::max(nblocks_of(c->n), (long)((c->N + BLOCK - 1) / BLOCK));
+    c->partials = (double*)cv.take((size_t)c->max_blocks * 2 * 8);
+    c->diag_part = (double*)cv.take((size_t)nblocks_of(c->n) * 11 * 8);
+    c->diag_out = (double*)cv.take(16 * 8);
+    c->scal = (SolverScalars*)cv.take(sizeof(SolverScalars));
+    c->flags = (int*)cv.take(64);
+    return cv.off;
+}
+
+static tpf_status resolve(const tpf_params* in, tpf_params* P) {
+    if (!in) { set_error("params is NULL"); return TPF_EINVAL; }
+    *P = *in;
+    if (P->dim != 2 && P->dim != 3) { set_error("dim must be 2 or 3"); return TPF_EINVAL; }
+    if (P->dim == 2) P->n[2] = 1;
+    for (int a = 0; a < P->dim; ++a)
+        if (P->n[a] < 2) { set_error("each n[a] must be >= 2"); return TPF_EINVAL; }
+    if (P->length <= 0) P->length = 1.0;
+    if (P->model < 0 || P->model > 2) { set_error("unknown model"); return TPF_EINVAL; }
+    if (P->force < 0 || P->force > 2) { set_error("unknown force"); return TPF_EINVAL; }
+    if (P->precision < 0 || P->precision > 1) { set_error("unknown precision"); return TPF_EINVAL; }
+    if (!(P->eps > 0) || !(P->rho1 > 0) || !(P->rho2 > 0) || !(P->sigma >= 0) || !(P->gamma >= 0) ||
+        !(P->visc1 >= 0) || !(P->visc2 >= 0)) {
+        set_error("eps, rho1, rho2 must be > 0; sigma, gamma, visc1, visc2 >= 0");
+        return TPF_EINVAL;
+    }
+    if (P->normal_delta <= 0) P->normal_delta = 1e-12;
+    if (P->poisson_rtol <= 0) P->poisson_rtol = P->precision == TPF_FP64 ? 1e-13 : 1e-9;
+    if (P->poisson_rtol_inner <= 0) P->poisson_rtol_inner = 1e-4;
+    if (P->poisson_maxit <= 0) P->poisson_maxit = 400;
+    if (P->mg_levels < 0) { set_error("mg_levels must be >= 0"); return TPF_EINVAL; }
+    return TPF_OK;
+}
+
+static void init_geometry(tpf_ctx* c, const tpf_params* P) {
+    c->P = *P;
+    c->dim = P->dim;
+    c->n[0] = P->n[0];
+    c->n[1] = P->n[1];
+    c->n[2] = P->dim == 3 ? P->n[2] : 1;
+    c->N = (long)c->n[0] * c->n[1] * c->n[2];
+    c->h = P->length / P->n[0];
+    c->mixed = P->precision == TPF_FP32_MIXED;
+    c->tsz = c->mixed ? 4 : 8;
+    c->nlev = plan_levels(c);
+}
+
+}  // namespace tpf
+
+using namespace tpf;
+
+// ================================================================== C ABI
+extern "C" {
+
+const char* tpf_last_error(void) { return g_err.c_str(); }
+const char* tpf_version(void) { return "tpf 0.1 gfx950"; }
+int32_t tpf_profile_classes(void) { return NPROF; }
+
+tpf_status tpf_workspace_bytes(const tpf_params* params, size_t* bytes) {
+    if (!bytes) { set_error("bytes is NULL"); return TPF_EINVAL; }
+    tpf_params P;
+    tpf_status st = resolve(params, &P);
+    if (st != TPF_OK) return st;
+    tpf_ctx tmp;
+    std::memset(&tmp, 0, sizeof(tmp));
+    init_geometry(&tmp, &P);
+    *bytes = carve(&tmp, nullptr);
+    return TPF_OK;
+}
+
+tpf_status tpf_create(const tpf_params* params, void* workspace, size_t ws_bytes, void* hip_stream,
+                      tpf_ctx** out) {
+    if (!out) { set_error("out is NULL"); return TPF_EINVAL; }
+    *out = nullptr;
+    tpf_params P;
+    tpf_status st = resolve(params, &P);
+    if (st != TPF_OK) return st;
+    if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255)) {
+        set_error("workspace must be a non-NULL 256-byte aligned device pointer");
+        return TPF_EINVAL;
+    }
+    tpf_ctx* c = new (std::nothrow) tpf_ctx;
+    if (!c) { set_error("host allocation failed"); return TPF_ENOMEM; }
+    std::memset(c, 0, sizeof(*c));
+    init_geometry(c, &P);
+    const size_t need = carve(c, nullptr);
+    if (ws_bytes < need) {
+        delete c;
+        set_error("workspace too small: need " + std::to_string(need) + " bytes");
+        return TPF_ENOMEM;
+    }
+    c->ws = static_cast<char*>(workspace);
+    c->ws_bytes = ws_bytes;
+    carve(c, c->ws);
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    (void)hipGetDevice(&c->device);
+    c->s_yn = 0;
+    c->s_acc = 1;
+    c->s_y1 = 2;
+    c->s_y2 = 3;
+    for (int q = 0; q < 64; ++q) {
+        if (hipEventCreate(&c->ev_a[q]) != hipSuccess || hipEventCreate(&c->ev_b[q]) != hipSuccess) {
+            delete c;
+            set_error("hipEventCreate failed");
+            return TPF_EDEVICE;
+        }
+    }
+    hipError_t e = hipMemsetAsync(c->ws, 0, need, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        tpf_status s = hip_fail(e, "workspace clear");
+        delete c;
+        return s;
+    }
+    *out = c;
+    return TPF_OK;
+}
+
+tpf_status tpf_destroy(tpf_ctx* c) {
+    if (!c) return TPF_OK;
+    (void)hipStreamSynchronize(c->stream);
+    for (int q = 0; q < 64; ++q) {
+        (void)hipEventDestroy(c->ev_a[q]);
+        (void)hipEventDestroy(c->ev_b[q]);
+    }
+    delete c;
+    return TPF_OK;
+}
+
+static tpf_status finish_set_state(tpf_ctx* c) {
+    hipError_t e = hipMemsetAsync(c->p, 0, (size_t)c->N * 8, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "pressure reset");
+    c->t = 0.0;
+    c->step = 0;
+    c->p_valid = 0;
+    const void* u[3] = {c->u[0][c->s_yn], c->u[1][c->s_yn], c->dim == 3 ? c->u[2][c->s_yn] : c->u[1][c->s_yn]};
+    e = launch_diagnostics(c, c->phi[c->s_yn], u, nullptr);
+    if (e != hipSuccess) return hip_fail(e, "diagnostics");
+    double out[11];
+    e = hipMemcpyAsync(out, c->diag_out, sizeof(out), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "diagnostics readback");
+    c->mass0 = out[0] * std::pow(c->h, c->dim);
+    return TPF_OK;
+}
+
+tpf_status tpf_set_state(tpf_ctx* c, const double* phi, const double* u0, const double* u1,
+                         const double* u2, int32_t on_device) {
+    if (!c || !phi || !u0 || !u1 || (c->dim == 3 && !u2)) {
+        set_error("tpf_set_state: NULL argument");
+        return TPF_EINVAL;
+    }
+    const double* src[4] = {phi, u0, u1, u2};
+    void* dst[4] = {c->phi[c->s_yn], c->u[0][c->s_yn], c->u[1][c->s_yn], c->u[2][c->s_yn]};
+    for (int v = 0; v <= c->dim; ++v) {
+        const double* s = src[v];
+        hipError_t e;
+        if (!on_device) {
+            e = hipMemcpyAsync(c->b, s, (size_t)c->N * 8, hipMemcpyHostToDevice, c->stream);
+            if (e != hipSuccess) return hip_fail(e, "host to device copy");
+            s = c->b;
+        }
+        e = launch_convert_in(c, s, dst[v]);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return hip_fail(e, "state conversion");
+    }
+    return finish_set_state(c);
+}
+
+tpf_status tpf_init_droplet(tpf_ctx* c, const double center[3], const double semi_axes[3]) {
+    if (!c || !center || !semi_axes) { set_error("tpf_init_droplet: NULL argument"); return TPF_EINVAL; }
+    for (int a = 0; a < c->dim; ++a)
+        if (!(semi_axes[a] > 0)) { set_error("semi axes must be > 0"); return TPF_EINVAL; }
+    double cen[3] = {center[0], center[1], c->dim == 3 ? center[2] : 0.0};
+    double ax[3] = {semi_axes[0], semi_axes[1], c->dim == 3 ? semi_axes[2] : 1.0};
+    hipError_t e = launch_init_droplet(c, cen, ax);
+    for (int a = 0; a < c->dim && e == hipSuccess; ++a) e = launch_zero_state(c, c->u[a][c->s_yn]);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "droplet initialisation");
+    return finish_set_state(c);
+}
+
+// One stage evaluation at (phi_s, u_s): fields, phase RHS (+RK update),
+// momentum RHS, pressure solve, projection (+RK update).
+static tpf_status stage_eval(tpf_ctx* c, const void* phi_s, const void* const u_s[3], const RKArgs& rk,
+                             void* phi_out, void* const u_out[3], int want_force) {
+    hipError_t e = launch_stage_fields(c, phi_s, u_s);
+    if (e == hipSuccess) e = launch_phase_update(c, phi_s, u_s, rk, phi_out);
+    if (e == hipSuccess) e = launch_momentum(c, phi_s, u_s, want_force);
+    if (e == hipSuccess) e = launch_divergence(c);
+    if (e != hipSuccess) return hip_fail(e, "stage kernels");
+    int it = 0, outer = 0;
+    double rr = 0;
+    tpf_status st = poisson_solve(c, phi_s, &it, &rr, &outer);
+    c->last_inner = it;
+    c->last_outer = outer;
+    c->last_relres = rr;
+    if (st != TPF_OK) return st;
+    e = launch_project_update(c, phi_s, rk, u_out);
+    if (e != hipSuccess) return hip_fail(e, "projection");
+    return TPF_OK;
+}
+
+static void state_ptrs(tpf_ctx* c, int slot, void** phi, void* u[3]) {
+    *phi = c->phi[slot];
+    for (int a = 0; a < 3; ++a) u[a] = c->u[a][slot] ? c->u[a][slot] : c->u[0][slot];
+}
+
+tpf_status tpf_step(tpf_ctx* c, double dt, int32_t nsteps) {
+    if (!c) { set_error("ctx is NULL"); return TPF_EINVAL; }
+    if (!(dt > 0) || nsteps < 0) { set_error("dt must be > 0 and nsteps >= 0"); return TPF_EINVAL; }
+    const double wacc[4] = {dt / 6.0, dt / 3.0, dt / 3.0, dt / 6.0};
+    const double wnext[4] = {dt / 2.0, dt / 2.0, dt, 0.0};
+    for (int n = 0; n < nsteps; ++n) {
+        hipError_t e = hipMemsetAsync(c->flags, 0, 64, c->stream);
+        if (e != hipSuccess) return hip_fail(e, "flag reset");
+        // stage inputs: yn, y1, y2, y1 ; stage outputs: y1, y2, y1, (acc)
+        const int in_slot[4] = {c->s_yn, c->s_y1, c->s_y2, c->s_y1};
+        const int out_slot[4] = {c->s_y1, c->s_y2, c->s_y1, c->s_acc};
+        for (int s = 0; s < 4; ++s) {
+            void *phi_s, *phi_o;
+            void *u_s[3], *u_o[3];
+            state_ptrs(c, in_slot[s], &phi_s, u_s);
+            state_ptrs(c, out_slot[s], &phi_o, u_o);
+            RKArgs rk{s, 0, wacc[s], wnext[s]};
+            const void* us[3] = {u_s[0], u_s[1], u_s[2]};
+            tpf_status st = stage_eval(c, phi_s, us, rk, phi_o, u_o, 0);
+            if (st != TPF_OK) {
+                c->p_valid = 0;
+                return st;
+            }
+        }
+        int flag = 0;
+        e = hipMemcpyAsync(&flag, c->flags, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return hip_fail(e, "step completion");
+        if (flag) {
+            c->p_valid = 0;
+            set_error("non-finite value produced; state kept at the last completed step");
+            return TPF_ENONFINITE;
+        }
+        const int t = c->s_yn;
+        c->s_yn = c->s_acc;
+        c->s_acc = t;
+        c->t += dt;
+        c->step += 1;
+        c->p_valid = 0;
+    }
+    return TPF_OK;
+}
+
+// Evaluate one stage at the current state without updating it; the
+// derivatives go to the y1 slot and the pressure to c->p.
+static tpf_status eval_current(tpf_ctx* c, int want_force) {
+    void *phi_s, *phi_o;
+    void *u_s[3], *u_o[3];
+    state_ptrs(c, c->s_yn, &phi_s, u_s);
+    state_ptrs(c, c->s_y1, &phi_o, u_o);
+    RKArgs rk{0, 1, 0.0, 0.0};
+    const void* us[3] = {u_s[0], u_s[1], u_s[2]};
+    tpf_status st = stage_eval(c, phi_s, us, rk, phi_o, u_o, want_force);
+    if (st == TPF_OK) c->p_valid = 1;
+    return st;
+}
+
+static tpf_status copy_out(tpf_ctx* c, const void* src, int is_double, double* dst, int on_device) {
+    hipError_t e;
+    if (is_double) {
+        e = hipMemcpyAsync(dst, src, (size_t)c->N * 8,
+                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream);
+    } else {
+        double* tgt = on_device ? dst : c->b;
+        e = launch_convert_out(c, src, tgt);
+        if (e == hipSuccess && !on_device)
+            e = hipMemcpyAsync(dst, c->b, (size_t)c->N * 8, hipMemcpyDeviceToHost, c->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "copy out");
+    return TPF_OK;
+}
+
+tpf_status tpf_get_state(tpf_ctx* c, double* phi, double* u0, double* u1, double* u2, double* p,
+                         int32_t on_device) {
+    if (!c) { set_error("ctx is NULL"); return TPF_EINVAL; }
+    if (p && !c->p_valid) {
+        tpf_status st = eval_current(c, 0);
+        if (st != TPF_OK) return st;
+    }
+    double* dst[4] = {phi, u0, u1, c->dim == 3 ? u2 : nullptr};
+    const void* src[4] = {c->phi[c->s_yn], c->u[0][c->s_yn], c->u[1][c->s_yn], c->u[2][c->s_yn]};
+    for (int v = 0; v < 4; ++v) {
+        if (!dst[v]) continue;
+        tpf_status st = copy_out(c, src[v], 0, dst[v], on_device);
+        if (st != TPF_OK) return st;
+    }
+    if (p) return copy_out(c, c->p, 1, p, on_device);
+    return TPF_OK;
+}
+
+tpf_status tpf_diagnostics(tpf_ctx* c, tpf_diag* out) {
+    if (!c || !out) { set_error("NULL argument"); return TPF_EINVAL; }
+    if (!c->p_valid) {
+        tpf_status st = eval_current(c, 0);
+        if (st != TPF_OK) return st;
+    }
+    const void* u[3] = {c->u[0][c->s_yn], c->u[1][c->s_yn], c->dim == 3 ? c->u[2][c->s_yn] : c->u[1][c->s_yn]};
+    hipError_t e = launch_diagnostics(c, c->phi[c->s_yn], u, c->p);
+    double v[11];
+    if (e == hipSuccess) e = hipMemcpyAsync(v, c->diag_out, sizeof(v), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "diagnostics");
+    const double hd = std::pow(c->h, c->dim);
+    out->t = c->t;
+    out->step = c->step;
+    out->mass = hd * v[0];
+    out->mass0 = c->mass0;
+    out->ke = hd * v[1];
+    out->se = hd * v[2];
+    out->dp = (v[4] > 0 && v[6] > 0) ? v[3] / v[4] - v[5] / v[6] : NAN;
+    out->umax = v[7];
+    out->ca_inf = c->P.sigma > 0 ? v[7] * c->P.visc1 / c->P.sigma : NAN;
+    out->div_max = v[8];
+    out->phi_min = -v[9];
+    out->phi_max = v[10];
+    out->poisson_relres = c->last_relres;
+    out->poisson_outer = c->last_outer;
+    out->poisson_inner = c->last_inner;
+    return TPF_OK;
+}
+
+tpf_status tpf_eval_field(tpf_ctx* c, int32_t field, double* out, int32_t on_device) {
+    if (!c || !out) { set_error("NULL argument"); return TPF_EINVAL; }
+    if (field < 0 || field >= TPF_FIELD_COUNT) { set_error("unknown field"); return TPF_EINVAL; }
+    auto comp = [&](int base) { return field - base; };
+    int a = 0;
+    if ((field >= TPF_FIELD_NORMAL0 && field <= TPF_FIELD_NORMAL2) ||
+        (field >= TPF_FIELD_CDIFLUX0 && field <= TPF_FIELD_CDIFLUX2) ||
+        (field >= TPF_FIELD_MASSFLUX0 && field <= TPF_FIELD_MASSFLUX2) ||
+        (field >= TPF_FIELD_FORCE0 && field <= TPF_FIELD_FORCE2) ||
+        (field >= TPF_FIELD_FSTAR0 && field <= TPF_FIELD_FSTAR2) ||
+        (field >= TPF_FIELD_DU0 && field <= TPF_FIELD_DU2)) {
+        if (field <= TPF_FIELD_NORMAL2) a = comp(TPF_FIELD_NORMAL0);
+        else if (field <= TPF_FIELD_CDIFLUX2) a = comp(TPF_FIELD_CDIFLUX0);
+        else if (field <= TPF_FIELD_MASSFLUX2) a = comp(TPF_FIELD_MASSFLUX0);
+        else if (field <= TPF_FIELD_FORCE2) a = comp(TPF_FIELD_FORCE0);
+        else if (field <= TPF_FIELD_FSTAR2) a = comp(TPF_FIELD_FSTAR0);
+        else a = comp(TPF_FIELD_DU0);
+        if (a >= c->dim) { set_error("component not present in this dimension"); return TPF_EINVAL; }
+    }
+    if (field == TPF_FIELD_KAPPA && c->P.model == TPF_CDI && c->P.force == TPF_EB) {
+        set_error("kappa is not computed for CDI with the energy-based force");
+        return TPF_EINVAL;
+    }
+    if (field == TPF_FIELD_MU && c->P.force != TPF_EB) {
+        set_error("mu is only computed with the energy-based force");
+        return TPF_EINVAL;
+    }
+    if (field >= TPF_FIELD_CDIFLUX0 && field <= TPF_FIELD_CDIFLUX2 && c->P.model != TPF_CDI) {
+        set_error("CDI flux only exists for the CDI model");
+        return TPF_EINVAL;
+    }
+    tpf_status st = eval_current(c, 1);
+    if (st != TPF_OK) return st;
+    const void* src = nullptr;
+    int dbl = 0;
+    switch (field) {
+    case TPF_FIELD_NORMAL0: case TPF_FIELD_NORMAL1: case TPF_FIELD_NORMAL2: src = c->nrm[a]; break;
+    case TPF_FIELD_MU: src = c->mu; break;
+    case TPF_FIELD_KAPPA: src = c->kappa; break;
+    case TPF_FIELD_CDIFLUX0: case TPF_FIELD_CDIFLUX1: case TPF_FIELD_CDIFLUX2: src = c->rflux[a]; break;
+    case TPF_FIELD_MASSFLUX0: case TPF_FIELD_MASSFLUX1: case TPF_FIELD_MASSFLUX2: src = c->mflux[a]; break;
+    case TPF_FIELD_DPHI: src = c->phi[c->s_y1]; break;
+    case TPF_FIELD_FORCE0: case TPF_FIELD_FORCE1: case TPF_FIELD_FORCE2: src = c->force[a]; break;
+    case TPF_FIELD_FSTAR0: case TPF_FIELD_FSTAR1: case TPF_FIELD_FSTAR2: src = c->fs[a]; break;
+    case TPF_FIELD_DIVFSTAR: src = c->b; dbl = 1; break;
+    case TPF_FIELD_PRESSURE: src = c->p; dbl = 1; break;
+    default: src = c->u[a][c->s_y1]; break;
+    }
+    return copy_out(c, src, dbl, out, on_device);
+}
+
+tpf_status tpf_poisson_solve(tpf_ctx* c, const double* b, double* x, int32_t on_device, int32_t* iters,
+                             double* relres) {
+    if (!c || !b || !x) { set_error("NULL argument"); return TPF_EINVAL; }
+    const hipMemcpyKind kin = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    hipError_t e = hipMemcpyAsync(c->b, b, (size_t)c->N * 8, kin, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->p, x, (size_t)c->N * 8, kin, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "copy in");
+    e = launch_rhs_mean(c);
+    if (e != hipSuccess) return hip_fail(e, "rhs mean");
+    int it = 0, outer = 0;
+    double rr = 0;
+    tpf_status st = poisson_solve(c, c->phi[c->s_yn], &it, &rr, &outer);
+    c->p_valid = 0;
+    if (iters) *iters = it;
+    if (relres) *relres = rr;
+    if (st != TPF_OK) return st;
+    e = hipMemcpyAsync(x, c->p, (size_t)c->N * 8, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                       c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "copy out");
+    return TPF_OK;
+}
+
+tpf_status tpf_profile_enable(tpf_ctx* c, int32_t enable) {
+    if (!c) { set_error("ctx is NULL"); return TPF_EINVAL; }
+    prof_flush(c);
+    c->prof_on = enable ? 1 : 0;
+    if (enable) {
+        for (int q = 0; q < NPROF; ++q) {
+            c->prof_ms[q] = 0;
+            c->prof_launches[q] = 0;
+            c->prof_bytes[q] = 0;
+        }
+    }
+    return TPF_OK;
+}
+
+tpf_status tpf_profile_read(tpf_ctx* c, int32_t cls, const char** name, double* total_ms,
+                            int64_t* launches, double* bytes_per_launch) {
+    if (!c || cls < 0 || cls >= NPROF) { set_error("bad profile class"); return TPF_EINVAL; }
+    prof_flush(c);
+    if (name) *name = kProfNames[cls];
+    if (total_ms) *total_ms = c->prof_ms[cls];
+    if (launches) *launches = c->prof_launches[cls];
+    if (bytes_per_launch)
+        *bytes_per_launch = c->prof_launches[cls] ? c->prof_bytes[cls] / c->prof_launches[cls] : 0.0;
+    return TPF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,170 @@
+// Host-side internals shared by the translation units of the library.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/tpf.h"
+#include "tpf_device.hpp"
+
+namespace tpf {
+
+constexpr int MAX_LEVELS = 16;
+constexpr int NPROF = 16;
+
+// Device-resident scalars of the pressure solver.  Kernels read alpha/beta/
+// mean from here, and every solver kernel returns at once when done != 0, so
+// a batch of iterations can be queued without a host round trip.
+struct SolverScalars {
+    double mean;       // mean of the Poisson right-hand side b
+    double ff;         // ||f||^2 of the system being solved
+    double rr;         // ||r||^2 of the current residual
+    double rz;         // <r, z>
+    double pq;         // <p, A p>
+    double alpha, beta;
+    double tol2;       // stop when rr <= tol2 * ff
+    double sum;        // generic sum (mean removal)
+    int done;          // PCG finished (converged, or no work)
+    int iters;         // PCG iterations performed
+    int pad[2];
+};
+
+// Finalize operations on reduced partial sums (one single-block kernel).
+enum FinOp {
+    FIN_MEAN = 0,   // v0 = sum b           -> mean = v0 / N
+    FIN_INIT = 1,   // v0 = ff, v1 = rr     -> ff, rr, done = rr <= tol2 ff
+    FIN_RZ0 = 2,    // v0 = rz              -> rz (first), keeps done
+    FIN_ALPHA = 3,  // v0 = pq              -> alpha = rz / pq
+    FIN_BETA = 4,   // v0 = rr, v1 = rz_new -> beta, rz, rr, done, iters++
+    FIN_SUM = 5     // v0 = sum x           -> sum
+};
+
+struct Level {
+    int n[3];
+    long N;
+    double h;
+    void* beta[3];  // face coefficients 1/rho_a (solver precision)
+    void* z;        // correction / PCG preconditioned residual at level 0
+    void* zt;       // Jacobi ping-pong partner of z
+    void* r;        // right-hand side (level 0: the PCG residual)
+};
+
+enum ProfClass {
+    PC_CELL = 0, PC_KAPPA, PC_FACE, PC_PHASE, PC_MOM, PC_DIV, PC_PROJ,
+    PC_APPLY_FINE, PC_JACOBI_FINE, PC_RESTRICT_FINE, PC_PROLONG_FINE, PC_VEC_FINE,
+    PC_COARSE_LEVELS, PC_RESID64, PC_FINALIZE, PC_OTHER
+};
+
+}  // namespace tpf
+
+struct tpf_ctx {
+    tpf_params P;
+    int dim;
+    int n[3];
+    long N;
+    double h;
+    int mixed;           // 0: FP64, 1: FP32 state + FP64 pressure
+    size_t tsz;          // bytes per state value
+    hipStream_t stream;
+    char* ws;
+    size_t ws_bytes;
+    int device;
+
+    // state (precision T), four slots per variable; roles below
+    void* phi[4];
+    void* u[3][4];
+    int s_yn, s_acc, s_y1, s_y2;
+
+    // stage intermediates (T)
+    void* nrm[3];
+    void* mu;
+    void* kappa;
+    void* rflux[3];
+    void* mflux[3];
+    void* fs[3];
+    void* force[3];      // only filled when tpf_eval_field asks for it
+
+    // pressure (FP64)
+    double* b;           // D f* (Poisson right-hand side)
+    double* p;           // pressure = solver x (warm start)
+    double* r64;         // mixed: outer residual
+    // PCG vectors at level 0 (solver precision S)
+    void* pv;            // search direction
+    void* qv;            // A p
+    void* ev;            // mixed: inner solution (correction)
+    tpf::Level lv[tpf::MAX_LEVELS];
+    int nlev;
+
+    // reductions
+    double* partials;
+    long max_blocks;
+    tpf::SolverScalars* scal;   // device
+    int* flags;                 // device: [0] non-finite seen
+    double* diag_part;          // per-block diagnostic partials
+    double* diag_out;           // finalized diagnostics
+
+    // bookkeeping
+    double t;
+    long step;
+    double mass0;
+    int p_valid;         // ctx->p holds the projection pressure of the current state
+    double last_relres;
+    int last_outer, last_inner;
+
+    // profiling
+    int prof_on;
+    hipEvent_t ev_a[64], ev_b[64];
+    int ev_class[64];
+    double ev_bytes[64];
+    int ev_count;
+    double prof_ms[tpf::NPROF];
+    long prof_launches[tpf::NPROF];
+    double prof_bytes[tpf::NPROF];
+};
+
+namespace tpf {
+
+void set_error(const std::string& msg);
+tpf_status hip_fail(hipError_t e, const char* what);
+
+// profiling hooks around launches
+void prof_begin(tpf_ctx* c, int cls, double bytes);
+void prof_end(tpf_ctx* c);
+
+// stage kernels (tpf_stage.hip)
+struct RKArgs {
+    int stage;        // 0..3
+    int eval_only;    // 1: write the derivative to out instead of updating
+    double wacc;      // acc (+)= wacc * k
+    double wnext;     // ynext = yn + wnext * k (stages 0-2)
+};
+hipError_t launch_stage_fields(tpf_ctx* c, const void* phi_s, const void* const u_s[3]);
+hipError_t launch_phase_update(tpf_ctx* c, const void* phi_s, const void* const u_s[3],
+                               const RKArgs& rk, void* out);
+hipError_t launch_momentum(tpf_ctx* c, const void* phi_s, const void* const u_s[3], int want_force);
+hipError_t launch_divergence(tpf_ctx* c);
+hipError_t launch_project_update(tpf_ctx* c, const void* phi_s, const RKArgs& rk, void* const out[3]);
+hipError_t launch_init_droplet(tpf_ctx* c, const double center[3], const double axes[3]);
+hipError_t launch_convert_in(tpf_ctx* c, const double* src, void* dst);
+hipError_t launch_convert_out(tpf_ctx* c, const void* src, double* dst);
+hipError_t launch_zero_state(tpf_ctx* c, void* dst);
+hipError_t launch_diagnostics(tpf_ctx* c, const void* phi, const void* const u[3], const double* p);
+
+// pressure solver (tpf_poisson.hip)
+tpf_status poisson_solve(tpf_ctx* c, const void* phi, int* iters, double* relres, int* outer);
+hipError_t launch_finalize(tpf_ctx* c, int nblocks, int nv, int op);
+hipError_t launch_rhs_mean(tpf_ctx* c);
+
+inline dim3 grid_of(const int n[3]) {
+    return dim3((n[0] + BX - 1) / BX, (n[1] + BY - 1) / BY, n[2]);
+}
+inline long nblocks_of(const int n[3]) {
+    dim3 g = grid_of(n);
+    return (long)g.x * g.y * g.z;
+}
+inline Dims dims_of(const int n[3]) { return Dims{n[0], n[1], n[2]}; }
+Phys phys_of(const tpf_ctx* c);
+
+}  // namespace tpf

@@ -1,0 +1,266 @@
+"""ctypes binding of the C ABI in include/tpf.h (argument marshalling only).
+
+Every computation runs in the HIP kernels of libtpf.so; this module only
+converts Python arguments to the C types, raises TpfError on a non-zero
+status and offers a small ``Solver`` convenience class that takes device
+memory (the workspace) and the stream from PyTorch.  There is no CPU path:
+if the library is missing, importing ``lib()`` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtpf.so")
+
+TPF_OK, TPF_EINVAL, TPF_ENOMEM, TPF_EDEVICE, TPF_ENOCONV, TPF_ENONFINITE, TPF_ESTATE = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "TPF_OK", -1: "TPF_EINVAL", -2: "TPF_ENOMEM", -3: "TPF_EDEVICE", -4: "TPF_ENOCONV",
+                -5: "TPF_ENONFINITE", -6: "TPF_ESTATE"}
+TPF_CDI, TPF_SB, TPF_ISODI = 0, 1, 2
+TPF_EB, TPF_CSF, TPF_LCSF = 0, 1, 2
+TPF_FP64, TPF_FP32_MIXED = 0, 1
+MODELS = {"CDI": TPF_CDI, "SB": TPF_SB, "ISODI": TPF_ISODI}
+FORCES = {"EB": TPF_EB, "CSF": TPF_CSF, "LCSF": TPF_LCSF}
+PRECISIONS = {"fp64": TPF_FP64, "fp32_mixed": TPF_FP32_MIXED}
+
+FIELDS = ["NORMAL0", "NORMAL1", "NORMAL2", "MU", "KAPPA", "CDIFLUX0", "CDIFLUX1", "CDIFLUX2",
+          "MASSFLUX0", "MASSFLUX1", "MASSFLUX2", "DPHI", "FORCE0", "FORCE1", "FORCE2",
+          "FSTAR0", "FSTAR1", "FSTAR2", "DIVFSTAR", "PRESSURE", "DU0", "DU1", "DU2"]
+FIELD = {name: q for q, name in enumerate(FIELDS)}
+
+# every entry point the header declares (checked by the CPU test-suite)
+EXPORTS = ["tpf_workspace_bytes", "tpf_create", "tpf_destroy", "tpf_set_state", "tpf_init_droplet",
+           "tpf_step", "tpf_get_state", "tpf_diagnostics", "tpf_eval_field", "tpf_poisson_solve",
+           "tpf_profile_enable", "tpf_profile_read", "tpf_profile_classes", "tpf_last_error",
+           "tpf_version"]
+
+
+class TpfError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class tpf_params(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int32 * 3), ("length", ctypes.c_double),
+                ("model", ctypes.c_int32), ("force", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("clamp_properties", ctypes.c_int32), ("sigma", ctypes.c_double),
+                ("eps", ctypes.c_double), ("gamma", ctypes.c_double), ("rho1", ctypes.c_double),
+                ("rho2", ctypes.c_double), ("visc1", ctypes.c_double), ("visc2", ctypes.c_double),
+                ("normal_delta", ctypes.c_double), ("poisson_rtol", ctypes.c_double),
+                ("poisson_rtol_inner", ctypes.c_double), ("poisson_maxit", ctypes.c_int32),
+                ("mg_levels", ctypes.c_int32)]
+
+
+class tpf_diag(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double), ("step", ctypes.c_int64), ("mass", ctypes.c_double),
+                ("mass0", ctypes.c_double), ("phi_min", ctypes.c_double), ("phi_max", ctypes.c_double),
+                ("umax", ctypes.c_double), ("ca_inf", ctypes.c_double), ("ke", ctypes.c_double),
+                ("se", ctypes.c_double), ("dp", ctypes.c_double), ("div_max", ctypes.c_double),
+                ("poisson_relres", ctypes.c_double), ("poisson_outer", ctypes.c_int32),
+                ("poisson_inner", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load libtpf.so (built by paper_2205_05835_amd.build); raise if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build()")
+    try:
+        import torch  # noqa: F401  -- share torch's HIP runtime instance
+    except ImportError:
+        pass
+    L = ctypes.CDLL(LIB_PATH)
+    vp, dp, i32 = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int32
+    P = ctypes.POINTER(tpf_params)
+    sig = {
+        "tpf_workspace_bytes": ([P, ctypes.POINTER(ctypes.c_size_t)], i32),
+        "tpf_create": ([P, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)], i32),
+        "tpf_destroy": ([vp], i32),
+        "tpf_set_state": ([vp, vp, vp, vp, vp, i32], i32),
+        "tpf_init_droplet": ([vp, dp, dp], i32),
+        "tpf_step": ([vp, ctypes.c_double, i32], i32),
+        "tpf_get_state": ([vp, vp, vp, vp, vp, vp, i32], i32),
+        "tpf_diagnostics": ([vp, ctypes.POINTER(tpf_diag)], i32),
+        "tpf_eval_field": ([vp, i32, vp, i32], i32),
+        "tpf_poisson_solve": ([vp, vp, vp, i32, ctypes.POINTER(i32), dp], i32),
+        "tpf_profile_enable": ([vp, i32], i32),
+        "tpf_profile_read": ([vp, i32, ctypes.POINTER(ctypes.c_char_p), dp, ctypes.POINTER(ctypes.c_int64), dp], i32),
+        "tpf_profile_classes": ([], i32),
+        "tpf_last_error": ([], ctypes.c_char_p),
+        "tpf_version": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def check(status: int, where: str) -> None:
+    if status != TPF_OK:
+        raise TpfError(status, where, lib().tpf_last_error().decode())
+
+
+def make_params(n, length=1.0, model="CDI", force="EB", precision="fp64", clamp_properties=1,
+                sigma=1.0, eps=None, gamma=1.0, rho1=1.0, rho2=1.0, visc1=0.1, visc2=0.1,
+                normal_delta=1e-12, poisson_rtol=0.0, poisson_rtol_inner=0.0, poisson_maxit=0,
+                mg_levels=0) -> tpf_params:
+    n = tuple(int(x) for x in n)
+    dim = len(n)
+    h = length / n[0]
+    p = tpf_params()
+    p.dim = dim
+    p.n = (ctypes.c_int32 * 3)(*(list(n) + [1] * (3 - dim)))
+    p.length = length
+    p.model = MODELS[model] if isinstance(model, str) else int(model)
+    p.force = FORCES[force] if isinstance(force, str) else int(force)
+    p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    p.clamp_properties = clamp_properties
+    p.sigma, p.eps, p.gamma = sigma, (eps if eps else h), gamma
+    p.rho1, p.rho2, p.visc1, p.visc2 = rho1, rho2, visc1, visc2
+    p.normal_delta = normal_delta
+    p.poisson_rtol, p.poisson_rtol_inner = poisson_rtol, poisson_rtol_inner
+    p.poisson_maxit, p.mg_levels = poisson_maxit, mg_levels
+    return p
+
+
+def workspace_bytes(params: tpf_params) -> int:
+    out = ctypes.c_size_t(0)
+    check(lib().tpf_workspace_bytes(ctypes.byref(params), ctypes.byref(out)), "tpf_workspace_bytes")
+    return int(out.value)
+
+
+def _host(a, N):
+    a = np.ascontiguousarray(a, dtype=np.float64).ravel()
+    if a.size != N:
+        raise ValueError(f"array has {a.size} values, expected {N}")
+    return a
+
+
+class Solver:
+    """One case on the current GPU: workspace and stream from PyTorch."""
+
+    def __init__(self, params: tpf_params, stream=None, device=None):
+        import torch
+        self.torch = torch
+        self.params = params
+        self.dim = params.dim
+        self.n = tuple(params.n[a] for a in range(self.dim))
+        self.shape = tuple(reversed(self.n))
+        self.N = int(np.prod(self.n))
+        self.device = torch.device(device or "cuda")
+        nbytes = workspace_bytes(params)
+        # 256-byte alignment: torch's caching allocator returns 512-byte aligned blocks
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        ctx = ctypes.c_void_p()
+        check(lib().tpf_create(ctypes.byref(params), ctypes.c_void_p(self.workspace.data_ptr()),
+                               nbytes, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx)),
+              "tpf_create")
+        self.ctx = ctx
+
+    def close(self):
+        if self.ctx:
+            check(lib().tpf_destroy(self.ctx), "tpf_destroy")
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- state
+    def set_state(self, phi, u):
+        """phi: array of N values; u: list of dim face arrays (host numpy or
+        CUDA float64 tensors)."""
+        torch = self.torch
+        if isinstance(phi, torch.Tensor):
+            arrs = [phi] + list(u)
+            for t in arrs:
+                if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+                    raise ValueError("device arrays must be contiguous float64 CUDA tensors")
+            ptrs = [ctypes.c_void_p(t.data_ptr()) for t in arrs] + [None] * (4 - len(arrs))
+            check(lib().tpf_set_state(self.ctx, *ptrs[:4], 1), "tpf_set_state")
+            return
+        arrs = [_host(phi, self.N)] + [_host(x, self.N) for x in u]
+        ptrs = [a.ctypes.data_as(ctypes.c_void_p) for a in arrs] + [None] * (4 - len(arrs))
+        check(lib().tpf_set_state(self.ctx, *ptrs[:4], 0), "tpf_set_state")
+
+    def init_droplet(self, center, semi_axes):
+        c = (ctypes.c_double * 3)(*(list(center) + [0.0] * (3 - len(center))))
+        s = (ctypes.c_double * 3)(*(list(semi_axes) + [1.0] * (3 - len(semi_axes))))
+        check(lib().tpf_init_droplet(self.ctx, c, s), "tpf_init_droplet")
+
+    def step(self, dt: float, nsteps: int = 1):
+        check(lib().tpf_step(self.ctx, float(dt), int(nsteps)), "tpf_step")
+
+    def get_state(self, with_pressure: bool = False):
+        """Host numpy copies: (phi, [u_a], p or None), C-order grid shape."""
+        phi = np.empty(self.shape)
+        u = [np.empty(self.shape) for _ in range(self.dim)]
+        p = np.empty(self.shape) if with_pressure else None
+        ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+        uu = [ptr(x) for x in u] + [None] * (3 - self.dim)
+        check(lib().tpf_get_state(self.ctx, ptr(phi), *uu, ptr(p), 0), "tpf_get_state")
+        return phi, u, p
+
+    def diagnostics(self) -> dict:
+        d = tpf_diag()
+        check(lib().tpf_diagnostics(self.ctx, ctypes.byref(d)), "tpf_diagnostics")
+        return d.as_dict()
+
+    def eval_field(self, name: str) -> np.ndarray:
+        out = np.empty(self.shape)
+        check(lib().tpf_eval_field(self.ctx, FIELD[name], out.ctypes.data_as(ctypes.c_void_p), 0),
+              "tpf_eval_field")
+        return out
+
+    def poisson_solve(self, b, x0=None):
+        bb = _host(b, self.N)
+        x = _host(x0, self.N).copy() if x0 is not None else np.zeros(self.N)
+        it = ctypes.c_int32(0)
+        rr = ctypes.c_double(0)
+        check(lib().tpf_poisson_solve(self.ctx, bb.ctypes.data_as(ctypes.c_void_p),
+                                      x.ctypes.data_as(ctypes.c_void_p), 0, ctypes.byref(it),
+                                      ctypes.byref(rr)), "tpf_poisson_solve")
+        return x.reshape(self.shape), it.value, rr.value
+
+    # ---------------------------------------------------------------- profiling
+    def profile_enable(self, on: bool = True):
+        check(lib().tpf_profile_enable(self.ctx, 1 if on else 0), "tpf_profile_enable")
+
+    def profile_read(self) -> dict:
+        out = {}
+        for q in range(lib().tpf_profile_classes()):
+            name = ctypes.c_char_p()
+            ms = ctypes.c_double()
+            nl = ctypes.c_int64()
+            bpl = ctypes.c_double()
+            check(lib().tpf_profile_read(self.ctx, q, ctypes.byref(name), ctypes.byref(ms),
+                                         ctypes.byref(nl), ctypes.byref(bpl)), "tpf_profile_read")
+            out[name.value.decode()] = {"ms": ms.value, "launches": nl.value,
+                                        "bytes_per_launch": bpl.value}
+        return out
+
+
+def solver_for_case(case, **overrides) -> Solver:
+    """Solver for a workloads.Case (grid, properties, model, force, precision)."""
+    kw = dict(length=case.length, model=case.model, force=case.force, precision=case.precision,
+              sigma=case.sigma, eps=case.eps, gamma=case.gamma, rho1=case.rho1, rho2=case.rho2,
+              visc1=case.visc1, visc2=case.visc2)
+    kw.update(overrides)
+    return Solver(make_params(case.n, **kw))
