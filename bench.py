@@ -1,0 +1,197 @@
+#!/usr/bin/env python3
+"""Throughput of the two-phase phase-field step on one MI355X.
+
+Workload: the 256^3 periodic oscillating drop (ellipsoid with semi-axes
+0.30, 0.25, 0.25 in the unit box, density and viscosity ratio 10,
+eps = 0.75 h, CDI phase field + energy-based surface tension force, FP32
+state and stencils with an FP64 pressure / defect-correction residual),
+time step from the explicit stability limits (capillary bound, 3.6e-5).
+Inputs are synthetic and built on the GPU (tanh profile, u = 0) before the
+timed region.
+
+Prints ONE JSON line: cell-steps/s over the timed steps, the roofline of the
+dominant kernel class (algorithmic bytes per launch / its mean launch time
+from HIP events recorded on the solver stream during the timed steps),
+the FP32-vs-FP64 error of the same workload over a few steps, and the plain
+CPU oracle timed on a bounded sample of the workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, 8 TB/s
+
+
+def gpu_run(args):
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2205_05835_amd import tpf
+
+    torch.cuda.set_device(0)
+    case = workloads.oscillating_drop_3d(args.n, "fp32_mixed")
+    dt = case.dt()
+    s = tpf.solver_for_case(case)
+    s.init_droplet(case.center, case.semi_axes)
+    s.step(dt, args.warmup)
+    torch.cuda.synchronize()
+
+    # attribution pass (all classes timed; not the measured region)
+    s.profile_enable(-1)
+    s.step(dt, 1)
+    prof_all = s.profile_read()
+    s.profile_enable(0)
+    names = s.profile_classes()
+    dominant = max(prof_all, key=lambda k: prof_all[k]["ms"])
+    dom_bit = names.index(dominant)
+
+    # timed region: K steps, events around the dominant class only
+    s.profile_enable(1 << dom_bit)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    s.step(dt, args.steps)
+    ev1.record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    ev_ms = ev0.elapsed_time(ev1)
+    dom = s.profile_read()[dominant]
+    s.profile_enable(0)
+    diag = s.diagnostics()
+
+    cells = case.cells
+    value = cells * args.steps / wall
+    mean_launch_s = dom["ms"] / max(dom["launches"], 1) * 1e-3
+    achieved = dom["bytes_per_launch"] / mean_launch_s / 1e9 if mean_launch_s > 0 else 0.0
+    out = {
+        "case": case, "dt": dt, "value": value, "wall": wall, "ev_ms": ev_ms, "diag": diag,
+        "dominant": dominant, "dom": dom, "achieved": achieved,
+        "breakdown": {k: round(v["ms"], 4) for k, v in sorted(prof_all.items(), key=lambda kv: -kv[1]["ms"]) if v["launches"]},
+        "breakdown_launches": {k: v["launches"] for k, v in prof_all.items() if v["launches"]},
+    }
+    out["step_ms_attribution"] = sum(v["ms"] for v in prof_all.values())
+
+    if not args.no_fp64_compare:
+        m = args.compare_steps
+        s64 = tpf.solver_for_case(workloads.oscillating_drop_3d(args.n, "fp64"))
+        s64.init_droplet(case.center, case.semi_axes)
+        s64.step(dt, m)
+        d64 = s64.diagnostics()
+        phi64, u64, _ = s64.get_state()
+        del s64
+        s32 = tpf.solver_for_case(case)
+        s32.init_droplet(case.center, case.semi_axes)
+        s32.step(dt, m)
+        d32 = s32.diagnostics()
+        phi32, u32, _ = s32.get_state()
+        del s32
+        umax = max(float(np.abs(x).max()) for x in u64)
+        out["fp32_vs_fp64"] = {
+            "steps": m,
+            "phi_max_abs": float(np.abs(phi32 - phi64).max()),
+            "u_max_rel": float(max(np.abs(u32[a] - u64[a]).max() for a in range(3)) / umax),
+            "dp_rel": abs(d32["dp"] - d64["dp"]) / abs(d64["dp"]),
+            "mass_drift_fp32": abs(d32["mass"] - d32["mass0"]) / d32["mass0"],
+            "mass_drift_fp64": abs(d64["mass"] - d64["mass0"]) / d64["mass0"],
+        }
+        del phi64, u64, phi32, u32
+    del s
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(args):
+    """The oracle as it stands, on the host cores, on a bounded sample: the
+    same oscillating-drop configuration at 64^3 for 2 RK4 steps."""
+    import numpy as np
+
+    import oracle
+    import workloads
+
+    n, steps = args.cpu_n, args.cpu_steps
+    c = workloads.oscillating_drop_3d(n, "fp64")
+    P = oracle.Params(n=c.n, eps=c.eps, rho1=c.rho1, rho2=c.rho2, visc1=c.visc1, visc2=c.visc2,
+                      sigma=c.sigma)
+    phi = oracle.init_droplet(P, c.center, c.semi_axes)
+    zero = [np.zeros(P.shape)] * 3
+    t0 = time.perf_counter()
+    oracle.step(P, c.dt(), steps, phi, zero)
+    t = time.perf_counter() - t0
+    return {"value": c.cells * steps / t, "unit": "cell-steps/s", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"{steps} RK4 steps of the same drop configuration at {n}^3 "
+                      f"(FP64, Jacobi-PCG pressure to 1e-14), {t:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=256, help="cells per axis of the drop workload")
+    ap.add_argument("--compare-steps", type=int, default=3)
+    ap.add_argument("--no-fp64-compare", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-n", type=int, default=64)
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--breakdown-out", default="")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU decomposition is a design, not an implementation)", file=sys.stderr)
+        sys.exit(2)
+
+    g = gpu_run(args)
+    case = g["case"]
+    cpu = None if args.no_cpu_baseline else cpu_baseline(args)
+    dom = g["dom"]
+    line = {
+        "metric": "cell-steps/s at 256^3 + % HBM roofline; adjoint/forward time; FP32 vs FP64 err",
+        "value": round(g["value"], 1),
+        "unit": "cell-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(g["wall"] / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": case.name, "grid": list(case.n), "cells": case.cells,
+                   "phase_field": case.model, "surface_force": case.force,
+                   "precision": "fp32 state/stencils/smoothers, fp64 pressure residual",
+                   "density_ratio": case.rho1 / case.rho2, "eps_over_h": case.eps_over_h,
+                   "dt": g["dt"]},
+        "roofline": {"bound": "hbm", "kernel": g["dominant"],
+                     "achieved": round(g["achieved"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(g["achieved"] / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_launch": dom["bytes_per_launch"],
+                     "mean_launch_us": round(dom["ms"] / max(dom["launches"], 1) * 1e3, 3),
+                     "launches": dom["launches"]},
+        "cpu_baseline": cpu,
+        "poisson_last_solve": {"outer": g["diag"]["poisson_outer"], "inner": g["diag"]["poisson_inner"],
+                               "relres": g["diag"]["poisson_relres"]},
+        "fp32_vs_fp64": g.get("fp32_vs_fp64"),
+        "adjoint_over_forward": None,
+        "event_ms_per_step": round(g["ev_ms"] / args.steps, 4),
+    }
+    if args.breakdown_out:
+        with open(args.breakdown_out, "w") as f:
+            json.dump({"ms_one_step": g["breakdown"], "launches": g["breakdown_launches"]}, f, indent=1)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -162,9 +162,13 @@ tpf_status tpf_eval_field(tpf_ctx* ctx, int32_t field, double* out, int32_t on_d
 tpf_status tpf_poisson_solve(tpf_ctx* ctx, const double* b, double* x, int32_t on_device,
                              int32_t* iters, double* relres);
 
-/* Per-kernel-class device timing (HIP events on the context stream around
- * each launch).  enable = 1 clears and starts recording; names/ms/launches
- * report accumulated totals per class. */
+/* Per-kernel-class device timing: HIP events recorded on the context stream
+ * around every launch of the selected classes (the class list is fixed; see
+ * tpf_profile_read for names).  enable = bit mask of classes (bit q selects
+ * class q; -1 selects all; 0 stops recording); enabling clears the totals.
+ * Events are read back when the pool of 8192 pairs fills or on read.
+ * tpf_profile_read reports, per class, the name, total device time, launch
+ * count and the algorithmic bytes one launch moves (mean over launches). */
 tpf_status tpf_profile_enable(tpf_ctx* ctx, int32_t enable);
 tpf_status tpf_profile_read(tpf_ctx* ctx, int32_t kernel_class, const char** name,
                             double* total_ms, int64_t* launches, double* bytes_per_launch);

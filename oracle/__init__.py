@@ -130,12 +130,19 @@ def lib():
             "ora_init_droplet": [pp, dp, dp, dp],
             "ora_diagnostics": [pp, dp, dp, dp, dp, dp, dp],
         }
+        L.ora_threads.argtypes = []
+        L.ora_threads.restype = ctypes.c_int
         for name, args in sig.items():
             f = getattr(L, name)
             f.argtypes = args
             f.restype = ctypes.c_int if name in ("ora_poisson_solve", "ora_stage", "ora_step") else None
         _lib = L
     return _lib
+
+
+def threads() -> int:
+    """OpenMP threads the oracle uses (OMP_NUM_THREADS or all host cores)."""
+    return int(lib().ora_threads())
 
 
 def _ptr(a):

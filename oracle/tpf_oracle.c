@@ -26,6 +26,7 @@
 #include "tpf_oracle.h"
 
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -715,3 +716,5 @@ void ora_diagnostics(const ora_params* P, const double* phi, const double* u0,
     out[ORA_D_DIVMAX] = dmax;
     free(speed); free(ke); free(se); free(dv); free(pin); free(pout); free(min_); free(mout);
 }
+
+int ora_threads(void) { return omp_get_max_threads(); }

@@ -93,6 +93,9 @@ void ora_diagnostics(const ora_params* P, const double* phi, const double* u0,
                      const double* u1, const double* u2, const double* pres,
                      double* out);
 
+/* number of OpenMP threads the oracle's parallel loops use */
+int ora_threads(void);
+
 #ifdef __cplusplus
 }
 #endif

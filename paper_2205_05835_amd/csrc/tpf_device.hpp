@@ -33,32 +33,52 @@ __device__ __forceinline__ int wrapc(int v, int n) {
     return v >= n ? v - n : v;
 }
 
-// A cell and its periodic neighbours; a, b are physical axes (0 = x).
+// A cell and the offsets of its six periodic neighbours; a, b are physical
+// axes (0 = x).  Indices are 32-bit (grids up to 2^31 cells): neighbour
+// addressing is one integer add, and the loads use a scalar base plus a
+// 32-bit vector offset.
+// Every neighbour index is clamped to [0, N-1] (one v_min_u32): the periodic
+// offsets below always land inside the grid, and the clamp makes an access
+// outside the array impossible even if they did not.
 struct Cell {
     int i, j, k;
-    int nx, ny, nz;
-    __device__ __forceinline__ long id() const { return ((long)k * ny + j) * nx + i; }
-    __device__ __forceinline__ long at(int di, int dj, int dk) const {
-        return ((long)wrapc(k + dk, nz) * ny + wrapc(j + dj, ny)) * nx + wrapc(i + di, nx);
+    unsigned id;
+    unsigned last;  // N - 1
+    int o[3][2];    // o[a][0]: offset to c - e_a, o[a][1]: offset to c + e_a
+    __device__ __forceinline__ unsigned off(int a, int s) const {
+        return min(id + (unsigned)o[a][s > 0], last);
     }
-    // c + s e_a + t e_b
-    __device__ __forceinline__ long off2(int a, int s, int b, int t) const {
-        int d[3] = {0, 0, 0};
-        d[a] += s;
-        d[b] += t;
-        return at(d[0], d[1], d[2]);
+    // c + s e_a + t e_b for a != b only: each offset is the one of cell c, so
+    // two shifts compose only when they move along different axes
+    __device__ __forceinline__ unsigned off2(int a, int s, int b, int t) const {
+        return min(id + (unsigned)o[a][s > 0] + (unsigned)o[b][t > 0], last);
     }
-    __device__ __forceinline__ long off(int a, int s) const { return off2(a, s, a, 0); }
 };
 
+__device__ __forceinline__ Cell make_cell(const Dims& d, int i, int j, int k) {
+    Cell C;
+    C.i = i;
+    C.j = j;
+    C.k = k;
+    const int nx = d.nx, plane = d.nx * d.ny;
+    C.id = (unsigned)((k * d.ny + j) * nx + i);
+    C.last = (unsigned)(plane * d.nz - 1);
+    C.o[0][0] = i == 0 ? nx - 1 : -1;
+    C.o[0][1] = i == nx - 1 ? 1 - nx : 1;
+    C.o[1][0] = j == 0 ? (d.ny - 1) * nx : -nx;
+    C.o[1][1] = j == d.ny - 1 ? (1 - d.ny) * nx : nx;
+    C.o[2][0] = k == 0 ? (d.nz - 1) * plane : -plane;
+    C.o[2][1] = k == d.nz - 1 ? (1 - d.nz) * plane : plane;
+    return C;
+}
+
 __device__ __forceinline__ bool cell_of_thread(const Dims& d, Cell& C) {
-    C.i = blockIdx.x * BX + threadIdx.x;
-    C.j = blockIdx.y * BY + threadIdx.y;
-    C.k = blockIdx.z;
-    C.nx = d.nx;
-    C.ny = d.ny;
-    C.nz = d.nz;
-    return C.i < d.nx && C.j < d.ny;
+    const int i = blockIdx.x * BX + threadIdx.x;
+    const int j = blockIdx.y * BY + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= d.nx || j >= d.ny) return false;
+    C = make_cell(d, i, j, k);
+    return true;
 }
 
 __device__ __forceinline__ int block_linear() {

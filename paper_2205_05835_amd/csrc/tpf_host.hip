@@ -44,8 +44,9 @@ Phys phys_of(const tpf_ctx* c) {
 // ---------------------------------------------------------------- profiling
 static const char* kProfNames[NPROF] = {
     "stage_cell", "stage_kappa", "stage_face", "stage_phase", "stage_momentum", "stage_div",
-    "stage_project", "pcg_apply_fine", "mg_jacobi_fine", "mg_restrict_fine", "mg_prolong_fine",
-    "pcg_vector_fine", "mg_coarse_levels", "outer_residual64", "reduce_finalize", "other"};
+    "stage_project", "fine_apply", "fine_update_sweep1", "fine_sweep1", "fine_sweep2",
+    "fine_restrict", "fine_prolong_sweep3", "fine_sweep4_dot", "mg_coarse_levels",
+    "residual", "reduce_finalize", "vector"};
 
 static void prof_flush(tpf_ctx* c) {
     if (c->ev_count == 0) return;
@@ -61,18 +62,47 @@ static void prof_flush(tpf_ctx* c) {
 }
 
 void prof_begin(tpf_ctx* c, int cls, double bytes) {
-    if (!c->prof_on) return;
-    if (c->ev_count == 64) prof_flush(c);
+    c->ev_open = 0;
+    if (!(c->prof_mask & (1u << cls))) return;
+    if (c->ev_count == c->ev_cap) prof_flush(c);
     const int q = c->ev_count;
     c->ev_class[q] = cls;
     c->ev_bytes[q] = bytes;
     (void)hipEventRecord(c->ev_a[q], c->stream);
+    c->ev_open = 1;
 }
 
 void prof_end(tpf_ctx* c) {
-    if (!c->prof_on) return;
+    if (!c->ev_open) return;
     (void)hipEventRecord(c->ev_b[c->ev_count], c->stream);
     c->ev_count += 1;
+    c->ev_open = 0;
+}
+
+static void prof_free(tpf_ctx* c) {
+    for (int q = 0; q < c->ev_cap; ++q) {
+        (void)hipEventDestroy(c->ev_a[q]);
+        (void)hipEventDestroy(c->ev_b[q]);
+    }
+    delete[] c->ev_a;
+    delete[] c->ev_b;
+    delete[] c->ev_class;
+    delete[] c->ev_bytes;
+    c->ev_cap = 0;
+}
+
+static bool prof_alloc(tpf_ctx* c, int cap) {
+    c->ev_a = new (std::nothrow) hipEvent_t[cap];
+    c->ev_b = new (std::nothrow) hipEvent_t[cap];
+    c->ev_class = new (std::nothrow) int[cap];
+    c->ev_bytes = new (std::nothrow) double[cap];
+    if (!c->ev_a || !c->ev_b || !c->ev_class || !c->ev_bytes) return false;
+    for (int q = 0; q < cap; ++q) {
+        if (hipEventCreate(&c->ev_a[q]) != hipSuccess) return false;
+        if (hipEventCreate(&c->ev_b[q]) != hipSuccess) return false;
+        c->ev_cap = q + 1;
+    }
+    return true;
 }
 
 // ---------------------------------------------------------------- workspace
@@ -136,6 +166,7 @@ static size_t carve(tpf_ctx* c, char* base) {
     c->p = (double*)cv.take(N8);
     c->r64 = c->mixed ? (double*)cv.take(N8) : nullptr;
     c->pv = cv.take((size_t)c->N * ssz);
+    c->pv2 = cv.take((size_t)c->N * ssz);
     c->qv = cv.take((size_t)c->N * ssz);
     c->ev = c->mixed ? cv.take((size_t)c->N * ssz) : nullptr;
     for (int l = 0; l < c->nlev; ++l) {
@@ -244,13 +275,6 @@ tpf_status tpf_create(const tpf_params* params, void* workspace, size_t ws_bytes
     c->s_acc = 1;
     c->s_y1 = 2;
     c->s_y2 = 3;
-    for (int q = 0; q < 64; ++q) {
-        if (hipEventCreate(&c->ev_a[q]) != hipSuccess || hipEventCreate(&c->ev_b[q]) != hipSuccess) {
-            delete c;
-            set_error("hipEventCreate failed");
-            return TPF_EDEVICE;
-        }
-    }
     hipError_t e = hipMemsetAsync(c->ws, 0, need, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
@@ -265,10 +289,7 @@ tpf_status tpf_create(const tpf_params* params, void* workspace, size_t ws_bytes
 tpf_status tpf_destroy(tpf_ctx* c) {
     if (!c) return TPF_OK;
     (void)hipStreamSynchronize(c->stream);
-    for (int q = 0; q < 64; ++q) {
-        (void)hipEventDestroy(c->ev_a[q]);
-        (void)hipEventDestroy(c->ev_b[q]);
-    }
+    prof_free(c);
     delete c;
     return TPF_OK;
 }
@@ -551,7 +572,12 @@ tpf_status tpf_poisson_solve(tpf_ctx* c, const double* b, double* x, int32_t on_
 tpf_status tpf_profile_enable(tpf_ctx* c, int32_t enable) {
     if (!c) { set_error("ctx is NULL"); return TPF_EINVAL; }
     prof_flush(c);
-    c->prof_on = enable ? 1 : 0;
+    if (enable && c->ev_cap == 0 && !prof_alloc(c, 8192)) {
+        prof_free(c);
+        set_error("hipEventCreate failed");
+        return TPF_EDEVICE;
+    }
+    c->prof_mask = (unsigned)enable;
     if (enable) {
         for (int q = 0; q < NPROF; ++q) {
             c->prof_ms[q] = 0;

@@ -12,7 +12,6 @@
 namespace tpf {
 
 constexpr int MAX_LEVELS = 16;
-constexpr int NPROF = 16;
 
 // Device-resident scalars of the pressure solver.  Kernels read alpha/beta/
 // mean from here, and every solver kernel returns at once when done != 0, so
@@ -51,11 +50,15 @@ struct Level {
     void* r;        // right-hand side (level 0: the PCG residual)
 };
 
+// Kernel classes for the optional per-launch timing.  Each fine-level (level
+// 0) solver class is one kernel symbol, so its timing can be compared with a
+// profiler's per-kernel statistics.
 enum ProfClass {
     PC_CELL = 0, PC_KAPPA, PC_FACE, PC_PHASE, PC_MOM, PC_DIV, PC_PROJ,
-    PC_APPLY_FINE, PC_JACOBI_FINE, PC_RESTRICT_FINE, PC_PROLONG_FINE, PC_VEC_FINE,
-    PC_COARSE_LEVELS, PC_RESID64, PC_FINALIZE, PC_OTHER
+    PC_F_APPLY, PC_F_FIRST, PC_F_FIRST0, PC_F_SWEEP, PC_F_RESTRICT, PC_F_PROLONG, PC_F_SWEEPDOT,
+    PC_COARSE_LEVELS, PC_RESID, PC_FINALIZE, PC_VECTOR, PC_COUNT
 };
+constexpr int NPROF = PC_COUNT;
 
 }  // namespace tpf
 
@@ -92,6 +95,7 @@ struct tpf_ctx {
     double* r64;         // mixed: outer residual
     // PCG vectors at level 0 (solver precision S)
     void* pv;            // search direction
+    void* pv2;           // search direction, ping-pong partner
     void* qv;            // A p
     void* ev;            // mixed: inner solution (correction)
     tpf::Level lv[tpf::MAX_LEVELS];
@@ -113,12 +117,15 @@ struct tpf_ctx {
     double last_relres;
     int last_outer, last_inner;
 
-    // profiling
-    int prof_on;
-    hipEvent_t ev_a[64], ev_b[64];
-    int ev_class[64];
-    double ev_bytes[64];
+    // profiling: HIP event pairs around the launches of the selected classes
+    unsigned prof_mask;
+    int ev_cap;
+    hipEvent_t* ev_a;
+    hipEvent_t* ev_b;
+    int* ev_class;
+    double* ev_bytes;
     int ev_count;
+    int ev_open;         // a begin event is recorded and awaits its end
     double prof_ms[tpf::NPROF];
     long prof_launches[tpf::NPROF];
     double prof_bytes[tpf::NPROF];

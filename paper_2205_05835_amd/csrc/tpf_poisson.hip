@@ -1,12 +1,24 @@
 // Variable-density pressure Poisson solve, matrix free:
 //     D(beta G p) = D f* - mean(D f*),   mean(p) = 0,   beta_a = 1 / A_a rho
 // Conjugate gradients on the SPD form  A = -D(beta G .)  (zero-mean subspace),
-// preconditioned by one geometric multigrid V-cycle (cell-centred coarsening
-// by 2, rediscretised coarse operators with face-averaged beta, damped Jacobi
-// smoothing, averaging restriction, piecewise-constant prolongation, fixed
-// Jacobi sweeps on the coarsest grid in one workgroup).  Every piece of the
-// V-cycle is a fixed linear symmetric operator, so it is a valid CG
-// preconditioner.
+// preconditioned by one geometric multigrid V-cycle: cell-centred coarsening
+// by 2, rediscretised coarse operators with face-averaged beta, two damped
+// Jacobi sweeps before and after the coarse correction, averaging
+// restriction, piecewise-constant prolongation, fixed Jacobi sweeps on the
+// coarsest grid in one workgroup.  Every piece is a fixed linear symmetric
+// operator, so the V-cycle is a valid CG preconditioner.
+//
+// Fine level: beta is recomputed from phi inside every kernel (one field read
+// instead of one per axis).  The kernels are fused along the data flow of one
+// PCG iteration:
+//   apply     p = z + beta p_old, q = A p, <p,q>
+//   first     x += alpha p, r -= alpha q, <r,r>, z1 = omega r / d
+//   sweep     z2 = z1 + omega (r - A z1) / d
+//   restrict  r_c = mean over children of (r - A z2)     (coalesced, one
+//             thread per fine cell, 2x2x2 sums in registers and LDS)
+//   prolong   z3 = Z + omega (r - A Z) / d, Z = z2 + P z_c formed on the fly
+//   sweep+dot z4 = z3 + omega (r - A z3) / d, <r, z4>
+// Coarse levels use the same kernels with stored face coefficients.
 //
 // Mixed precision: the outer loop forms the residual in FP64 (FP64 beta from
 // phi, FP64 right-hand side and iterate) and solves for the correction with
@@ -14,7 +26,9 @@
 //
 // Scalars (alpha, beta, norms, the done flag) stay on the device; every
 // solver kernel returns immediately once done is set, so the host queues
-// several iterations between convergence checks.
+// several iterations between convergence checks.  Block partial sums go to
+// two regions (offset 0 and offset max_blocks) summed by one finalize kernel.
+#include <algorithm>
 #include <cmath>
 
 #include "tpf_internal.hpp"
@@ -24,62 +38,110 @@ namespace tpf {
 template <typename T>
 static inline T* tp(void* p) { return static_cast<T*>(p); }
 
-// ---------------------------------------------------------------- operator
-// (A x)[c] = sum_a [beta_a[c](x[c]-x[c-e_a]) - beta_a[c+e_a](x[c+e_a]-x[c])] / h^2
-template <typename S, int DIM>
-__device__ __forceinline__ S apply_at(const Cell& C, const S* const* beta, const S* x, S ih2,
-                                      S& diag) {
-    const long c = C.id();
-    const S xc = x[c];
+// 2 / s and 1 / s: correctly rounded in FP64 (parity path), hardware
+// reciprocal in FP32 (inner solver of the mixed path)
+__device__ __forceinline__ double two_over(double s) { return 2.0 / s; }
+__device__ __forceinline__ float two_over(float s) { return 2.0f * __builtin_amdgcn_rcpf(s); }
+__device__ __forceinline__ double recip(double s) { return 1.0 / s; }
+__device__ __forceinline__ float recip(float s) { return __builtin_amdgcn_rcpf(s); }
+
+// block sums of two values to region 0 and region 1 (stride apart)
+__device__ __forceinline__ void block_partials_2r(double (&v)[2], double* partials, long stride) {
+    block_sum<2>(v);
+    if (thread_linear() == 0) {
+        const int b = block_linear();
+        partials[b] = v[0];
+        partials[stride + b] = v[1];
+    }
+}
+
+// ---------------------------------------------------------------- coefficients
+// Fine level: beta on the faces of a cell from the density law of phi.  A face
+// between cells lo < hi is always 2 / (rho(lo) + rho(hi)) in that operand
+// order, so both cells of a face see bit-identical coefficients (symmetric A).
+template <typename T, typename S>
+struct CoefPhi {
+    const T* __restrict__ phi;
+    S rho2, drho;
+    int clamp;
+    __device__ __forceinline__ S rho(unsigned c) const {
+        S f = S(phi[c]);
+        if (clamp) f = f < S(0) ? S(0) : (f > S(1) ? S(1) : f);
+        return rho2 + drho * f;
+    }
+    template <int DIM>
+    __device__ __forceinline__ void faces(const Cell& C, S* bl, S* bh) const {
+        const S rc = rho(C.id);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            bl[a] = two_over(rho(C.off(a, -1)) + rc);
+            bh[a] = two_over(rc + rho(C.off(a, 1)));
+        }
+    }
+};
+
+template <typename S>
+struct CoefStored {
+    const S* __restrict__ b0;
+    const S* __restrict__ b1;
+    const S* __restrict__ b2;
+    template <int DIM>
+    __device__ __forceinline__ void faces(const Cell& C, S* bl, S* bh) const {
+        const S* b[3] = {b0, b1, b2};
+        const unsigned c = C.id;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            bl[a] = b[a][c];
+            bh[a] = b[a][C.off(a, 1)];
+        }
+    }
+};
+
+// (A x)[c] given the face coefficients; x(a, s) returns x at c + s e_a.  Also
+// the diagonal d[c].
+template <typename S, int DIM, typename Fx>
+__device__ __forceinline__ S apply_at(const S* bl, const S* bh, Fx x, S xc, S ih2, S& diag) {
     S acc = S(0), dg = S(0);
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-        const long cp = C.off(a, 1), cm = C.off(a, -1);
-        const S bl = beta[a][c], bh = beta[a][cp];
-        acc += bl * (xc - x[cm]) - bh * (x[cp] - xc);
-        dg += bl + bh;
+        acc += bl[a] * (xc - x(a, -1)) - bh[a] * (x(a, 1) - xc);
+        dg += bl[a] + bh[a];
     }
     diag = dg * ih2;
     return acc * ih2;
 }
 
-struct Betas {
-    const void* b[3];
-};
-
-template <typename S>
-struct BP {
-    const S* b[3];
-};
-template <typename S>
-__host__ __device__ inline BP<S> bp(const Betas& B) {
-    return BP<S>{{static_cast<const S*>(B.b[0]), static_cast<const S*>(B.b[1]),
-                  static_cast<const S*>(B.b[2])}};
-}
-
-// ---------------------------------------------------------------- coefficients
+// ---------------------------------------------------------------- coefficients setup
+// stored coefficients of level 1: mean of the fine face coefficients (same law
+// as CoefPhi) over the fine faces covering each coarse face
 template <typename T, typename S, int DIM>
-__global__ __launch_bounds__(BLOCK) void k_beta_fine(Dims d, Phys P, const T* __restrict__ phi,
-                                                     S* b0, S* b1, S* b2) {
+__global__ __launch_bounds__(BLOCK) void k_beta_from_phi(Dims fd, Dims cd, CoefPhi<T, S> cf, S* b0,
+                                                         S* b1, S* b2) {
     Cell C;
-    if (!cell_of_thread(d, C)) return;
+    if (!cell_of_thread(cd, C)) return;
     S* b[3] = {b0, b1, b2};
-    const long c = C.id();
-    const double f = (double)phi[c];
+    const int i0 = 2 * C.i, j0 = 2 * C.j, k0 = DIM == 3 ? 2 * C.k : 0;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-        const double fm = (double)phi[C.off(a, -1)];
-        b[a][c] = S(1.0 / (0.5 * (rho_of(P, fm) + rho_of(P, f))));
+        S s = S(0);
+        for (int t = 0; t < (1 << (DIM - 1)); ++t) {
+            int o[3] = {0, 0, 0};
+            int q = 0;
+            for (int e = 0; e < DIM; ++e)
+                if (e != a) o[e] = (t >> q++) & 1;
+            const Cell F = make_cell(fd, i0 + o[0], j0 + o[1], k0 + o[2]);
+            s += two_over(cf.rho(F.off(a, -1)) + cf.rho(F.id));
+        }
+        b[a][C.id] = s * S(1.0 / (1 << (DIM - 1)));
     }
 }
 
-// coarse face coefficient = mean of the fine face coefficients it covers
 template <typename S, int DIM>
-__global__ __launch_bounds__(BLOCK) void k_beta_coarsen(Dims fd, Dims cd, Betas fine, S* b0, S* b1,
-                                                        S* b2) {
+__global__ __launch_bounds__(BLOCK) void k_beta_coarsen(Dims fd, Dims cd, CoefStored<S> f, S* b0,
+                                                        S* b1, S* b2) {
     Cell C;
     if (!cell_of_thread(cd, C)) return;
-    const BP<S> f = bp<S>(fine);
+    const S* fb[3] = {f.b0, f.b1, f.b2};
     S* b[3] = {b0, b1, b2};
     const int i0 = 2 * C.i, j0 = 2 * C.j, k0 = DIM == 3 ? 2 * C.k : 0;
 #pragma unroll
@@ -91,140 +153,167 @@ __global__ __launch_bounds__(BLOCK) void k_beta_coarsen(Dims fd, Dims cd, Betas 
             for (int e = 0; e < DIM; ++e)
                 if (e != a) o[e] = (t >> q++) & 1;
             const long fc = ((long)(k0 + o[2]) * fd.ny + (j0 + o[1])) * fd.nx + (i0 + o[0]);
-            s += f.b[a][fc];
+            const long fmax = (long)fd.nx * fd.ny * fd.nz - 1;
+            s += fb[a][fc < fmax ? fc : fmax];
         }
-        b[a][C.id()] = s * S(1.0 / (1 << (DIM - 1)));
+        b[a][C.id] = s * S(1.0 / (1 << (DIM - 1)));
     }
 }
 
 // ---------------------------------------------------------------- residuals
-// FP64 path: r = -(b - mean) - A x,  partials (|f|^2, |r|^2)
-template <int DIM>
-__global__ __launch_bounds__(BLOCK) void k_resid_init(Dims d, double ih2, Betas B,
-                                                      const double* __restrict__ b,
-                                                      const double* __restrict__ x,
-                                                      double* __restrict__ r,
-                                                      const SolverScalars* __restrict__ sc,
-                                                      double* __restrict__ partials) {
+// r = -(b - mean) - A x in precision S (x and b FP64), stored as R;
+// partials: |f|^2 -> region 0, |r|^2 -> region 1
+template <typename T, typename S, typename R, int DIM>
+__global__ __launch_bounds__(BLOCK) void k_resid(Dims d, S ih2, CoefPhi<T, S> cf,
+                                                 const double* __restrict__ b,
+                                                 const double* __restrict__ x,
+                                                 R* __restrict__ r,
+                                                 const SolverScalars* __restrict__ sc,
+                                                 double* __restrict__ partials, long stride) {
     Cell C;
     double v[2] = {0.0, 0.0};
     if (cell_of_thread(d, C)) {
-        const BP<double> bb = bp<double>(B);
-        double dg;
-        const long c = C.id();
+        S bl[3], bh[3], dg;
+        cf.template faces<DIM>(C, bl, bh);
+        const unsigned c = C.id;
+        auto X = [&](int a, int s) { return S(x[C.off(a, s)]); };
         const double f = -(b[c] - sc->mean);
-        const double rc = f - apply_at<double, DIM>(C, bb.b, x, ih2, dg);
-        r[c] = rc;
+        const double rc = f - (double)apply_at<S, DIM>(bl, bh, X, S(x[c]), ih2, dg);
+        r[c] = R(rc);
         v[0] = f * f;
         v[1] = rc * rc;
     }
-    block_partials<2>(v, partials);
-}
-
-// Mixed path outer residual in FP64 with beta recomputed from phi in FP64;
-// the solver-precision copy goes to rs.
-template <typename T, typename S, int DIM>
-__global__ __launch_bounds__(BLOCK) void k_resid64(Dims d, Phys P, const T* __restrict__ phi,
-                                                   const double* __restrict__ b,
-                                                   const double* __restrict__ x,
-                                                   S* __restrict__ rs,
-                                                   const SolverScalars* __restrict__ sc,
-                                                   double* __restrict__ partials) {
-    Cell C;
-    double v[2] = {0.0, 0.0};
-    if (cell_of_thread(d, C)) {
-        const long c = C.id();
-        const double fc = (double)phi[c];
-        const double xc = x[c];
-        const double rho_c = rho_of(P, fc);
-        double acc = 0.0;
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            const long cp = C.off(a, 1), cm = C.off(a, -1);
-            const double bl = 1.0 / (0.5 * (rho_of(P, (double)phi[cm]) + rho_c));
-            const double bh = 1.0 / (0.5 * (rho_c + rho_of(P, (double)phi[cp])));
-            acc += bl * (xc - x[cm]) - bh * (x[cp] - xc);
-        }
-        const double f = -(b[c] - sc->mean);
-        const double rc = f - acc * (P.inv_h * P.inv_h);
-        rs[c] = S(rc);
-        v[0] = f * f;
-        v[1] = rc * rc;
-    }
-    block_partials<2>(v, partials);
+    block_partials_2r(v, partials, stride);
 }
 
 // ---------------------------------------------------------------- smoothing
-template <typename S, int DIM>
-__global__ __launch_bounds__(BLOCK) void k_jacobi0(Dims d, S ih2, S omega, Betas B,
-                                                   const S* __restrict__ r, S* __restrict__ z,
-                                                   const SolverScalars* __restrict__ sc) {
+// z = omega r / d  (first sweep from a zero guess)
+template <typename Coef, typename S, int DIM>
+__global__ __launch_bounds__(BLOCK) void k_jac_first(Dims d, S ih2, S omega, Coef cf,
+                                                     const S* __restrict__ r, S* __restrict__ z,
+                                                     const SolverScalars* __restrict__ sc) {
     if (sc->done) return;
     Cell C;
     if (!cell_of_thread(d, C)) return;
-    const BP<S> bb = bp<S>(B);
-    const long c = C.id();
-    S dg = S(0);
+    S bl[3], bh[3], dg = S(0);
+    cf.template faces<DIM>(C, bl, bh);
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) dg += bb.b[a][c] + bb.b[a][C.off(a, 1)];
-    z[c] = omega * r[c] / (dg * ih2);
+    for (int a = 0; a < DIM; ++a) dg += bl[a] + bh[a];
+    const unsigned c = C.id;
+    z[c] = omega * r[c] * recip(dg * ih2);
 }
 
-template <typename S, int DIM>
-__global__ __launch_bounds__(BLOCK) void k_jacobi(Dims d, S ih2, S omega, Betas B,
-                                                  const S* __restrict__ r, const S* __restrict__ z,
-                                                  S* __restrict__ zt,
-                                                  const SolverScalars* __restrict__ sc) {
+// PCG update fused with the first smoothing sweep of the V-cycle:
+//   x += alpha p, r -= alpha q, <r,r> (region 0), z = omega r / d
+template <typename Coef, typename S, typename X, int DIM>
+__global__ __launch_bounds__(BLOCK) void k_jac_first_update(Dims d, S ih2, S omega, Coef cf,
+                                                            X* __restrict__ x, S* __restrict__ r,
+                                                            const S* __restrict__ p,
+                                                            const S* __restrict__ q,
+                                                            S* __restrict__ z,
+                                                            const SolverScalars* __restrict__ sc,
+                                                            double* __restrict__ partials) {
     if (sc->done) return;
     Cell C;
-    if (!cell_of_thread(d, C)) return;
-    const BP<S> bb = bp<S>(B);
-    S dg;
-    const S az = apply_at<S, DIM>(C, bb.b, z, ih2, dg);
-    const long c = C.id();
-    zt[c] = z[c] + omega * (r[c] - az) / dg;
+    double v[1] = {0.0};
+    if (cell_of_thread(d, C)) {
+        const unsigned c = C.id;
+        const double alpha = sc->alpha;
+        x[c] = X((double)x[c] + alpha * (double)p[c]);
+        const S rn = S((double)r[c] - alpha * (double)q[c]);
+        r[c] = rn;
+        v[0] = (double)rn * (double)rn;
+        S bl[3], bh[3], dg = S(0);
+        cf.template faces<DIM>(C, bl, bh);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) dg += bl[a] + bh[a];
+        z[c] = omega * rn * recip(dg * ih2);
+    }
+    block_partials<1>(v, partials);
 }
 
-// coarse rhs = mean over the children of (r - A z); one thread per coarse cell
-template <typename S, int DIM>
-__global__ __launch_bounds__(BLOCK) void k_restrict(Dims fd, Dims cd, S ih2, Betas B,
+// zt = Z + omega (r - A Z) / d, with Z = z (PRO = 0) or Z = z + P zc (PRO = 1:
+// piecewise-constant prolongation of the coarse correction formed on the
+// fly); DOT = 1 also emits <r, zt> to region 1.
+template <typename Coef, typename S, int DIM, int PRO, int DOT>
+__global__ __launch_bounds__(BLOCK) void k_jac(Dims d, Dims cd, S ih2, S omega, Coef cf,
+                                               const S* __restrict__ r, const S* __restrict__ z,
+                                               const S* __restrict__ zc, S* __restrict__ zt,
+                                               const SolverScalars* __restrict__ sc,
+                                               double* __restrict__ partials) {
+    if (sc->done) return;
+    Cell C;
+    double v[1] = {0.0};
+    if (cell_of_thread(d, C)) {
+        // parent of c + s e_a on the coarse grid: the parent of c itself when
+        // the shift stays inside the same 2x2x2 family, else its neighbour
+        Cell Pc;
+        if (PRO) Pc = make_cell(cd, C.i >> 1, C.j >> 1, DIM == 3 ? C.k >> 1 : 0);
+        const int par[3] = {C.i & 1, C.j & 1, C.k & 1};
+        auto parent = [&](int a, int s) -> unsigned {
+            const bool leaves = (s < 0) ? (par[a] == 0) : (par[a] == 1);
+            return leaves ? Pc.off(a, s) : Pc.id;
+        };
+        auto Z = [&](int a, int s) -> S {
+            if (!PRO) return z[C.off(a, s)];
+            return z[C.off(a, s)] + zc[parent(a, s)];
+        };
+        S bl[3], bh[3], dg;
+        cf.template faces<DIM>(C, bl, bh);
+        const unsigned c = C.id;
+        const S zcen = PRO ? z[c] + zc[Pc.id] : z[c];
+        const S az = apply_at<S, DIM>(bl, bh, Z, zcen, ih2, dg);
+        const S rc = r[c];
+        const S out = zcen + omega * (rc - az) * recip(dg);
+        zt[c] = out;
+        if (DOT) v[0] = (double)rc * (double)out;
+    }
+    if (DOT) block_partials<1>(v, partials);
+}
+
+// coarse rhs = mean over the 2^DIM children of (r - A z).  One thread per
+// fine cell (coalesced); block 64 x 2 x 2 (3D) or 64 x 4 (2D); x pairs summed
+// with a lane shuffle, y/z pairs through LDS.
+template <typename Coef, typename S, int DIM>
+__global__ __launch_bounds__(BLOCK) void k_restrict(Dims fd, Dims cd, S ih2, Coef cf,
                                                     const S* __restrict__ r,
-                                                    const S* __restrict__ z, S* __restrict__ rc,
+                                                    const S* __restrict__ z,
+                                                    S* __restrict__ rc,
                                                     const SolverScalars* __restrict__ sc) {
     if (sc->done) return;
-    Cell Cc;
-    if (!cell_of_thread(cd, Cc)) return;
-    const BP<S> bb = bp<S>(B);
-    S s = S(0);
-    const int nk = DIM == 3 ? 2 : 1;
-    for (int dk = 0; dk < nk; ++dk)
-        for (int dj = 0; dj < 2; ++dj)
-            for (int di = 0; di < 2; ++di) {
-                Cell F{2 * Cc.i + di, 2 * Cc.j + dj, DIM == 3 ? 2 * Cc.k + dk : 0, fd.nx, fd.ny, fd.nz};
-                S dg;
-                s += r[F.id()] - apply_at<S, DIM>(F, bb.b, z, ih2, dg);
-            }
-    rc[Cc.id()] = s * S(1.0 / (DIM == 3 ? 8 : 4));
+    constexpr int TY = DIM == 3 ? 2 : 4, TZ = DIM == 3 ? 2 : 1;
+    __shared__ S sh[TZ][TY][BX];
+    const int tx = threadIdx.x, ty = threadIdx.y, tz = threadIdx.z;
+    const int fi = blockIdx.x * BX + tx, fj = blockIdx.y * TY + ty, fk = blockIdx.z * TZ + tz;
+    const bool in = fi < fd.nx && fj < fd.ny && fk < fd.nz;
+    const Cell C = make_cell(fd, in ? fi : 0, in ? fj : 0, in ? fk : 0);
+    S res = S(0);
+    if (in) {
+        S bl[3], bh[3], dg;
+        cf.template faces<DIM>(C, bl, bh);
+        auto Z = [&](int a, int s) { return z[C.off(a, s)]; };
+        const unsigned c = C.id;
+        res = r[c] - apply_at<S, DIM>(bl, bh, Z, z[c], ih2, dg);
+    }
+    res += __shfl_xor(res, 1, 64);
+    sh[tz][ty][tx] = res;
+    __syncthreads();
+    if (in && (tx & 1) == 0 && (ty & 1) == 0 && tz == 0) {
+        S s = sh[0][ty][tx] + sh[0][ty + 1][tx];
+        if (DIM == 3) s += sh[1][ty][tx] + sh[1][ty + 1][tx];
+        const long cc = ((long)(C.k >> 1) * cd.ny + (C.j >> 1)) * cd.nx + (C.i >> 1);
+        const long cmax = (long)cd.nx * cd.ny * cd.nz - 1;
+        rc[cc < cmax ? cc : cmax] = s * S(1.0 / (DIM == 3 ? 8 : 4));
+    }
 }
 
+// coarsest grid: `sweeps` damped Jacobi sweeps from zero in one workgroup;
+// result in z
 template <typename S, int DIM>
-__global__ __launch_bounds__(BLOCK) void k_prolong(Dims fd, Dims cd, const S* __restrict__ zc,
-                                                   S* __restrict__ z,
-                                                   const SolverScalars* __restrict__ sc) {
+__global__ __launch_bounds__(1024) void k_coarse(Dims d, S ih2, S omega, int sweeps,
+                                                 CoefStored<S> cf, const S* __restrict__ r, S* z,
+                                                 S* zt, const SolverScalars* __restrict__ sc) {
     if (sc->done) return;
-    Cell C;
-    if (!cell_of_thread(fd, C)) return;
-    const long pc = ((long)(DIM == 3 ? C.k >> 1 : 0) * cd.ny + (C.j >> 1)) * cd.nx + (C.i >> 1);
-    z[C.id()] += zc[pc];
-}
-
-// coarsest grid: `sweeps` damped Jacobi sweeps from zero, one workgroup
-template <typename S, int DIM>
-__global__ __launch_bounds__(1024) void k_coarse(Dims d, S ih2, S omega, int sweeps, Betas B,
-                                                 const S* __restrict__ r, S* z, S* zt,
-                                                 const SolverScalars* __restrict__ sc) {
-    if (sc->done) return;
-    const BP<S> bb = bp<S>(B);
     const long N = (long)d.nx * d.ny * d.nz;
     for (long q = threadIdx.x; q < N; q += blockDim.x) z[q] = S(0);
     __syncthreads();
@@ -232,15 +321,13 @@ __global__ __launch_bounds__(1024) void k_coarse(Dims d, S ih2, S omega, int swe
     S* dst = zt;
     for (int s = 0; s < sweeps; ++s) {
         for (long q = threadIdx.x; q < N; q += blockDim.x) {
-            Cell C;
-            C.i = (int)(q % d.nx);
-            C.j = (int)((q / d.nx) % d.ny);
-            C.k = (int)(q / ((long)d.nx * d.ny));
-            C.nx = d.nx;
-            C.ny = d.ny;
-            C.nz = d.nz;
-            S dg;
-            const S az = apply_at<S, DIM>(C, bb.b, src, ih2, dg);
+            const Cell C = make_cell(d, (int)(q % d.nx), (int)((q / d.nx) % d.ny),
+                                     (int)(q / ((long)d.nx * d.ny)));
+            S bl[3], bh[3], dg;
+            cf.template faces<DIM>(C, bl, bh);
+            const S* xs = src;
+            auto X = [&](int a, int t) { return xs[C.off(a, t)]; };
+            const S az = apply_at<S, DIM>(bl, bh, X, src[q], ih2, dg);
             dst[q] = src[q] + omega * (r[q] - az) / dg;
         }
         __syncthreads();
@@ -253,134 +340,134 @@ __global__ __launch_bounds__(1024) void k_coarse(Dims d, S ih2, S omega, int swe
     }
 }
 
-// ---------------------------------------------------------------- CG vector ops
-template <typename S, int DIM>
-__global__ __launch_bounds__(BLOCK) void k_apply_dot(Dims d, S ih2, Betas B,
-                                                     const S* __restrict__ p, S* __restrict__ q,
-                                                     const SolverScalars* __restrict__ sc,
-                                                     double* __restrict__ partials) {
+// ---------------------------------------------------------------- CG apply
+// p = z + beta p_old (first: p = z) at the stencil points, q = A p, <p, q>
+template <typename Coef, typename S, int DIM>
+__global__ __launch_bounds__(BLOCK) void k_apply(Dims d, S ih2, Coef cf, int first,
+                                                 const S* __restrict__ z,
+                                                 const S* __restrict__ pold,
+                                                 S* __restrict__ pnew, S* __restrict__ q,
+                                                 const SolverScalars* __restrict__ sc,
+                                                 double* __restrict__ partials) {
     if (sc->done) return;
     Cell C;
     double v[1] = {0.0};
     if (cell_of_thread(d, C)) {
-        const BP<S> bb = bp<S>(B);
-        S dg;
-        const S aq = apply_at<S, DIM>(C, bb.b, p, ih2, dg);
-        const long c = C.id();
+        const S beta = first ? S(0) : S(sc->beta);
+        auto Pn = [&](long t) -> S { return first ? z[t] : z[t] + beta * pold[t]; };
+        auto Pa = [&](int a, int s) { return Pn(C.off(a, s)); };
+        S bl[3], bh[3], dg;
+        cf.template faces<DIM>(C, bl, bh);
+        const unsigned c = C.id;
+        const S pc = Pn(c);
+        const S aq = apply_at<S, DIM>(bl, bh, Pa, pc, ih2, dg);
+        pnew[c] = pc;
         q[c] = aq;
-        v[0] = (double)p[c] * (double)aq;
+        v[0] = (double)pc * (double)aq;
     }
     block_partials<1>(v, partials);
 }
 
-template <typename S, typename X>
-__global__ __launch_bounds__(BLOCK) void k_update_xr(long N, X* __restrict__ x, S* __restrict__ r,
-                                                     const S* __restrict__ p,
-                                                     const S* __restrict__ q,
-                                                     const SolverScalars* __restrict__ sc,
-                                                     double* __restrict__ partials) {
-    if (sc->done) return;
-    const long c = (long)blockIdx.x * BLOCK + threadIdx.x;
-    double v[1] = {0.0};
-    if (c < N) {
-        const double alpha = sc->alpha;
-        x[c] = X((double)x[c] + alpha * (double)p[c]);
-        const S rn = S((double)r[c] - alpha * (double)q[c]);
-        r[c] = rn;
-        v[0] = (double)rn * (double)rn;
-    }
-    block_partials<1>(v, partials);
-}
-
-template <typename S>
-__global__ __launch_bounds__(BLOCK) void k_dot(long N, const S* __restrict__ a,
-                                               const S* __restrict__ b,
-                                               const SolverScalars* __restrict__ sc,
-                                               double* __restrict__ partials) {
-    if (sc->done) return;
-    const long c = (long)blockIdx.x * BLOCK + threadIdx.x;
-    double v[1] = {0.0};
-    if (c < N) v[0] = (double)a[c] * (double)b[c];
-    block_partials<1>(v, partials);
-}
-
-template <typename S>
-__global__ __launch_bounds__(BLOCK) void k_update_p(long N, int first, const S* __restrict__ z,
-                                                    S* __restrict__ p,
-                                                    const SolverScalars* __restrict__ sc) {
-    if (sc->done) return;
-    const long c = (long)blockIdx.x * BLOCK + threadIdx.x;
-    if (c >= N) return;
-    p[c] = first ? z[c] : S((double)z[c] + sc->beta * (double)p[c]);
-}
-
-template <typename S>
-__global__ void k_fill_s(long N, S* __restrict__ x, S v) {
-    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < N) x[c] = v;
-}
+// ---------------------------------------------------------------- small vector kernels
+constexpr int VBLOCKS = 1024;   // grid-stride vector kernels
 
 __global__ __launch_bounds__(BLOCK) void k_correct(long N, double* __restrict__ x,
                                                    const float* __restrict__ e) {
-    const long c = (long)blockIdx.x * BLOCK + threadIdx.x;
-    if (c < N) x[c] += (double)e[c];
+    for (long c = (long)blockIdx.x * BLOCK + threadIdx.x; c < N; c += (long)gridDim.x * BLOCK)
+        x[c] += (double)e[c];
 }
 
 __global__ __launch_bounds__(BLOCK) void k_sum(long N, const double* __restrict__ x,
                                                double* __restrict__ partials) {
-    const long c = (long)blockIdx.x * BLOCK + threadIdx.x;
-    double v[1] = {c < N ? x[c] : 0.0};
+    double v[1] = {0.0};
+    for (long c = (long)blockIdx.x * BLOCK + threadIdx.x; c < N; c += (long)gridDim.x * BLOCK)
+        v[0] += x[c];
     block_partials<1>(v, partials);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_sub_mean(long N, double* __restrict__ x,
                                                     const SolverScalars* __restrict__ sc) {
-    const long c = (long)blockIdx.x * BLOCK + threadIdx.x;
-    if (c < N) x[c] -= sc->sum / (double)N;
+    const double m = sc->sum / (double)N;
+    for (long c = (long)blockIdx.x * BLOCK + threadIdx.x; c < N; c += (long)gridDim.x * BLOCK)
+        x[c] -= m;
+}
+
+template <typename S>
+__global__ __launch_bounds__(BLOCK) void k_fill_s(long N, S* __restrict__ x, S v) {
+    for (long c = (long)blockIdx.x * BLOCK + threadIdx.x; c < N; c += (long)gridDim.x * BLOCK)
+        x[c] = v;
 }
 
 // ---------------------------------------------------------------- finalize
-__global__ __launch_bounds__(BLOCK) void k_finalize(int nb, int nv, int op, double arg, long N,
-                                                    const double* __restrict__ partials,
-                                                    SolverScalars* sc) {
+// One 1024-thread block sums region 0 (nb0 partials) and region 1 (nb1
+// partials at partials + stride) in a fixed order and applies op.
+constexpr int FIN_THREADS = 1024;
+
+__global__ __launch_bounds__(FIN_THREADS) void k_finalize(int nb0, int nb1, long stride, int op,
+                                                          double arg, long N,
+                                                          const double* __restrict__ partials,
+                                                          SolverScalars* sc) {
     const bool skip = (op == FIN_ALPHA || op == FIN_BETA || op == FIN_RZ0) && sc->done;
     if (skip) return;
-    double v[2] = {0.0, 0.0};
-    for (int b = thread_linear(); b < nb; b += BLOCK) {
-        v[0] += partials[b];
-        if (nv > 1) v[1] += partials[(long)nb + b];
+    __shared__ double red[2][FIN_THREADS / 64];
+    const int t = threadIdx.x;
+    double v[2];
+    for (int q = 0; q < 2; ++q) {
+        const int nb = q == 0 ? nb0 : nb1;
+        const double* p = partials + q * stride;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int b = t;
+        for (; b + 3 * FIN_THREADS < nb; b += 4 * FIN_THREADS) {
+            a0 += p[b];
+            a1 += p[b + FIN_THREADS];
+            a2 += p[b + 2 * FIN_THREADS];
+            a3 += p[b + 3 * FIN_THREADS];
+        }
+        for (; b < nb; b += FIN_THREADS) a0 += p[b];
+        v[q] = (a0 + a1) + (a2 + a3);
     }
-    block_sum<2>(v);
-    if (thread_linear() != 0) return;
+    for (int q = 0; q < 2; ++q)
+        for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_down(v[q], o, 64);
+    if ((t & 63) == 0) {
+        red[0][t >> 6] = v[0];
+        red[1][t >> 6] = v[1];
+    }
+    __syncthreads();
+    if (t != 0) return;
+    double s0 = 0.0, s1 = 0.0;
+    for (int w = 0; w < FIN_THREADS / 64; ++w) {
+        s0 += red[0][w];
+        s1 += red[1][w];
+    }
     switch (op) {
-    case FIN_MEAN:
-        sc->mean = v[0] / (double)N;
+    case FIN_MEAN:    // region 0: sum b
+        sc->mean = s0 / (double)N;
         break;
-    case FIN_INIT:
-        sc->ff = v[0];
-        sc->rr = v[1];
+    case FIN_INIT:    // region 0: |f|^2, region 1: |r|^2
+        sc->ff = s0;
+        sc->rr = s1;
         sc->tol2 = arg;
         sc->iters = 0;
-        sc->done = (v[0] == 0.0 || v[1] <= arg * v[0]) ? 1 : 0;
+        sc->done = (s0 == 0.0 || s1 <= arg * s0) ? 1 : 0;
         break;
-    case FIN_RZ0:
-        sc->rz = v[0];
-        if (!(v[0] > 0.0)) sc->done = 1;
+    case FIN_RZ0:     // region 1: <r, z>
+        sc->rz = s1;
+        if (!(s1 > 0.0)) sc->done = 1;
         break;
-    case FIN_ALPHA:
-        sc->pq = v[0];
-        sc->alpha = (v[0] > 0.0) ? sc->rz / v[0] : 0.0;
-        if (!(v[0] > 0.0)) sc->done = 1;
+    case FIN_ALPHA:   // region 0: <p, A p>
+        sc->pq = s0;
+        sc->alpha = (s0 > 0.0) ? sc->rz / s0 : 0.0;
+        if (!(s0 > 0.0)) sc->done = 1;
         break;
-    case FIN_BETA:
-        sc->rr = v[0];
-        sc->beta = v[1] / sc->rz;
-        sc->rz = v[1];
+    case FIN_BETA:    // region 0: |r|^2, region 1: <r, z>
+        sc->rr = s0;
+        sc->beta = s1 / sc->rz;
+        sc->rz = s1;
         sc->iters += 1;
-        if (v[0] <= sc->tol2 * sc->ff || !(v[1] > 0.0)) sc->done = 1;
+        if (s0 <= sc->tol2 * sc->ff || !(s1 > 0.0)) sc->done = 1;
         break;
-    case FIN_SUM:
-        sc->sum = v[0];
+    case FIN_SUM:     // region 0: sum x
+        sc->sum = s0;
         break;
     default:
         break;
@@ -395,141 +482,201 @@ __global__ void k_inner_setup(SolverScalars* sc, double tol2) {
     sc->done = sc->rr > 0.0 ? 0 : 1;
 }
 
-hipError_t launch_finalize(tpf_ctx* c, int nblocks, int nv, int op) {
-    prof_begin(c, PC_FINALIZE, (double)nblocks * nv * 8);
-    k_finalize<<<1, BLOCK, 0, c->stream>>>(nblocks, nv, op, 0.0, c->N, c->partials, c->scal);
+static hipError_t finalize2(tpf_ctx* c, int nb0, int nb1, int op, double arg) {
+    prof_begin(c, PC_FINALIZE, (double)(nb0 + nb1) * 8);
+    k_finalize<<<1, FIN_THREADS, 0, c->stream>>>(nb0, nb1, c->max_blocks, op, arg, c->N,
+                                                 c->partials, c->scal);
     prof_end(c);
     return hipGetLastError();
 }
 
+hipError_t launch_finalize(tpf_ctx* c, int nblocks, int nv, int op) {
+    return finalize2(c, nblocks, nv > 1 ? nblocks : 0, op, 0.0);
+}
+
 // ================================================================== host driver
 
-template <typename S>
+template <typename T, typename S>
 struct Solver {
     tpf_ctx* c;
     int dim;
     S omega;
-    int nu;  // pre = post smoothing sweeps
 
-    Betas betas(int l) const {
-        return Betas{{c->lv[l].beta[0], c->lv[l].beta[1], c->lv[l].beta[2]}};
+    CoefPhi<T, S> coef_phi(const void* phi) const {
+        const Phys P = phys_of(c);
+        return CoefPhi<T, S>{static_cast<const T*>(phi), S(P.rho2), S(P.rho1 - P.rho2), P.clamp};
+    }
+    CoefStored<S> coef(int l) const {
+        return CoefStored<S>{tp<S>(c->lv[l].beta[0]), tp<S>(c->lv[l].beta[1]),
+                             tp<S>(c->lv[l].beta[2])};
     }
     S ih2(int l) const { return S(1.0 / (c->lv[l].h * c->lv[l].h)); }
     dim3 grid(int l) const { return grid_of(c->lv[l].n); }
     Dims dims(int l) const { return dims_of(c->lv[l].n); }
-    double lbytes(int l, int fields) const { return (double)c->lv[l].N * sizeof(S) * fields; }
+    Dims dims_c(int l) const { return l + 1 < c->nlev ? dims(l + 1) : dims(l); }
+    double fb(int l, double fields) const { return (double)c->lv[l].N * sizeof(S) * fields; }
+    // fields moved by the coefficients: phi on the fine level, DIM arrays below
+    double cfields(int l) const { return l == 0 ? (double)sizeof(T) / sizeof(S) : (double)dim; }
+    long nbl(int l) const { return nblocks_of(c->lv[l].n); }
 
     template <int DIM>
     void build_betas_t(const void* phi) {
-        const Phys P = phys_of(c);
         const dim3 b(BX, BY);
-        if (c->mixed)
-            k_beta_fine<float, S, DIM><<<grid(0), b, 0, c->stream>>>(
-                dims(0), P, static_cast<const float*>(phi), tp<S>(c->lv[0].beta[0]),
-                tp<S>(c->lv[0].beta[1]), tp<S>(c->lv[0].beta[2]));
-        else
-            k_beta_fine<double, S, DIM><<<grid(0), b, 0, c->stream>>>(
-                dims(0), P, static_cast<const double*>(phi), tp<S>(c->lv[0].beta[0]),
-                tp<S>(c->lv[0].beta[1]), tp<S>(c->lv[0].beta[2]));
-        for (int l = 1; l < c->nlev; ++l)
+        if (c->nlev < 2) return;
+        k_beta_from_phi<T, S, DIM><<<grid(1), b, 0, c->stream>>>(
+            dims(0), dims(1), coef_phi(phi), tp<S>(c->lv[1].beta[0]), tp<S>(c->lv[1].beta[1]),
+            tp<S>(c->lv[1].beta[2]));
+        for (int l = 2; l < c->nlev; ++l)
             k_beta_coarsen<S, DIM><<<grid(l), b, 0, c->stream>>>(
-                dims(l - 1), dims(l), betas(l - 1), tp<S>(c->lv[l].beta[0]),
+                dims(l - 1), dims(l), coef(l - 1), tp<S>(c->lv[l].beta[0]),
                 tp<S>(c->lv[l].beta[1]), tp<S>(c->lv[l].beta[2]));
     }
     void build_betas(const void* phi) {
         if (dim == 2) build_betas_t<2>(phi); else build_betas_t<3>(phi);
     }
 
-    // z_l ~= A_l^{-1} r_l ; returns the buffer holding the result
-    template <int DIM>
-    S* vcycle_t(int l) {
+    dim3 restrict_block() const { return dim == 3 ? dim3(BX, 2, 2) : dim3(BX, 4, 1); }
+    dim3 restrict_grid(int l) const {
+        const Level& L = c->lv[l];
+        return dim == 3 ? dim3((L.n[0] + BX - 1) / BX, (L.n[1] + 1) / 2, (L.n[2] + 1) / 2)
+                        : dim3((L.n[0] + BX - 1) / BX, (L.n[1] + 3) / 4, 1);
+    }
+
+    // Pre-smoothing and restriction at level l.  The first sweep writes z (A),
+    // the second zt (B), the restriction reads zt.
+    template <int DIM, typename Coef>
+    void level_down(int l, Coef cf, bool fine, bool first_done) {
         Level& L = c->lv[l];
         const dim3 b(BX, BY);
-        const int fine = (l == 0);
         S* z = tp<S>(L.z);
         S* zt = tp<S>(L.zt);
         const S* r = tp<S>(L.r);
-        if (l == c->nlev - 1) {
-            const int mx = L.n[0] > L.n[1] ? L.n[0] : L.n[1];
-            const int sweeps = 8 * (mx > L.n[2] ? mx : L.n[2]);
-            prof_begin(c, PC_COARSE_LEVELS, lbytes(l, 3));
-            k_coarse<S, DIM><<<1, 1024, 0, c->stream>>>(dims(l), ih2(l), S(0.8), sweeps, betas(l), r,
-                                                        z, zt, c->scal);
+        const double cfl = cfields(l);
+        if (!first_done) {
+            prof_begin(c, fine ? PC_F_FIRST0 : PC_COARSE_LEVELS, fb(l, 2 + cfl));
+            k_jac_first<Coef, S, DIM><<<grid(l), b, 0, c->stream>>>(dims(l), ih2(l), omega, cf, r, z, c->scal);
             prof_end(c);
-            return z;
         }
-        const int cls_j = fine ? PC_JACOBI_FINE : PC_COARSE_LEVELS;
-        prof_begin(c, cls_j, lbytes(l, 2 + DIM));
-        k_jacobi0<S, DIM><<<grid(l), b, 0, c->stream>>>(dims(l), ih2(l), omega, betas(l), r, z, c->scal);
+        prof_begin(c, fine ? PC_F_SWEEP : PC_COARSE_LEVELS, fb(l, 3 + cfl));
+        k_jac<Coef, S, DIM, 0, 0><<<grid(l), b, 0, c->stream>>>(dims(l), dims_c(l), ih2(l), omega, cf, r, z,
+                                                                 nullptr, zt, c->scal, nullptr);
         prof_end(c);
-        for (int s = 1; s < nu; ++s) {
-            prof_begin(c, cls_j, lbytes(l, 3 + DIM));
-            k_jacobi<S, DIM><<<grid(l), b, 0, c->stream>>>(dims(l), ih2(l), omega, betas(l), r, z, zt, c->scal);
-            prof_end(c);
-            S* t = z; z = zt; zt = t;
-        }
         Level& Lc = c->lv[l + 1];
-        prof_begin(c, fine ? PC_RESTRICT_FINE : PC_COARSE_LEVELS,
-                   lbytes(l, 2 + DIM) + (double)Lc.N * sizeof(S));
-        k_restrict<S, DIM><<<grid(l + 1), b, 0, c->stream>>>(dims(l), dims(l + 1), ih2(l), betas(l), r,
-                                                             z, tp<S>(Lc.r), c->scal);
+        prof_begin(c, fine ? PC_F_RESTRICT : PC_COARSE_LEVELS, fb(l, 2 + cfl) + (double)Lc.N * sizeof(S));
+        k_restrict<Coef, S, DIM><<<restrict_grid(l), restrict_block(), 0, c->stream>>>(
+            dims(l), dims(l + 1), ih2(l), cf, r, zt, tp<S>(Lc.r), c->scal);
         prof_end(c);
-        S* zc = vcycle_t<DIM>(l + 1);
-        prof_begin(c, fine ? PC_PROLONG_FINE : PC_COARSE_LEVELS, lbytes(l, 2) + (double)Lc.N * sizeof(S));
-        k_prolong<S, DIM><<<grid(l), b, 0, c->stream>>>(dims(l), dims(l + 1), zc, z, c->scal);
-        prof_end(c);
-        for (int s = 0; s < nu; ++s) {
-            prof_begin(c, cls_j, lbytes(l, 3 + DIM));
-            k_jacobi<S, DIM><<<grid(l), b, 0, c->stream>>>(dims(l), ih2(l), omega, betas(l), r, z, zt, c->scal);
-            prof_end(c);
-            S* t = z; z = zt; zt = t;
-        }
-        return z;
     }
-    S* vcycle() { return dim == 2 ? vcycle_t<2>(0) : vcycle_t<3>(0); }
 
-    unsigned vblocks() const { return (unsigned)((c->N + BLOCK - 1) / BLOCK); }
+    // Prolongation-sweep (B + P zc -> A) and last sweep (A -> B) at level l.
+    template <int DIM, typename Coef>
+    void level_up(int l, Coef cf, bool fine, const S* zc, int dot) {
+        Level& L = c->lv[l];
+        const dim3 b(BX, BY);
+        S* z = tp<S>(L.z);
+        S* zt = tp<S>(L.zt);
+        const S* r = tp<S>(L.r);
+        const double cb = (double)c->lv[l + 1].N * sizeof(S);
+        const double cfl = cfields(l);
+        prof_begin(c, fine ? PC_F_PROLONG : PC_COARSE_LEVELS, fb(l, 3 + cfl) + cb);
+        k_jac<Coef, S, DIM, 1, 0><<<grid(l), b, 0, c->stream>>>(dims(l), dims(l + 1), ih2(l), omega, cf, r, zt,
+                                                                 zc, z, c->scal, nullptr);
+        prof_end(c);
+        prof_begin(c, fine ? PC_F_SWEEPDOT : PC_COARSE_LEVELS, fb(l, 3 + cfl));
+        if (dot)
+            k_jac<Coef, S, DIM, 0, 1><<<grid(l), b, 0, c->stream>>>(dims(l), dims_c(l), ih2(l), omega, cf, r, z,
+                                                                     nullptr, zt, c->scal,
+                                                                     c->partials + c->max_blocks);
+        else
+            k_jac<Coef, S, DIM, 0, 0><<<grid(l), b, 0, c->stream>>>(dims(l), dims_c(l), ih2(l), omega, cf, r, z,
+                                                                     nullptr, zt, c->scal, nullptr);
+        prof_end(c);
+    }
 
-    // PCG on level 0 for x (type X), residual already in lv[0].r and the
-    // scalars initialised (ff, rr, tol2, done).  Returns hip error.
+    // V-cycle from level l >= 1 (stored coefficients); the correction ends in zt
+    template <int DIM>
+    const S* vcycle_coarse(int l) {
+        Level& L = c->lv[l];
+        if (l == c->nlev - 1) {
+            const int mx = std::max(L.n[0], std::max(L.n[1], L.n[2]));
+            prof_begin(c, PC_COARSE_LEVELS, fb(l, 3));
+            k_coarse<S, DIM><<<1, 1024, 0, c->stream>>>(dims(l), ih2(l), S(0.8), 8 * mx, coef(l),
+                                                        tp<S>(L.r), tp<S>(L.zt), tp<S>(L.z), c->scal);
+            prof_end(c);
+            return tp<S>(L.zt);
+        }
+        level_down<DIM>(l, coef(l), false, false);
+        const S* zc = vcycle_coarse<DIM>(l + 1);
+        level_up<DIM>(l, coef(l), false, zc, 0);
+        return tp<S>(L.zt);
+    }
+
+    // Full V-cycle from level 0 (phi coefficients), result in lv[0].zt.
+    // first_done: the first pre-smoothing sweep was fused into the PCG update.
+    // dot: the last sweep emits <r, z> partials to region 1.
+    template <int DIM>
+    void vcycle_t(const void* phi, bool first_done) {
+        const CoefPhi<T, S> cf = coef_phi(phi);
+        Level& L = c->lv[0];
+        if (c->nlev == 1) {
+            // no coarsening possible: two Jacobi sweeps (still symmetric)
+            if (!first_done) {
+                prof_begin(c, PC_F_FIRST0, fb(0, 2 + cfields(0)));
+                k_jac_first<CoefPhi<T, S>, S, DIM><<<grid(0), dim3(BX, BY), 0, c->stream>>>(
+                    dims(0), ih2(0), omega, cf, tp<S>(L.r), tp<S>(L.z), c->scal);
+                prof_end(c);
+            }
+            prof_begin(c, PC_F_SWEEPDOT, fb(0, 3 + cfields(0)));
+            k_jac<CoefPhi<T, S>, S, DIM, 0, 1><<<grid(0), dim3(BX, BY), 0, c->stream>>>(
+                dims(0), dims(0), ih2(0), omega, cf, tp<S>(L.r), tp<S>(L.z), nullptr, tp<S>(L.zt),
+                c->scal, c->partials + c->max_blocks);
+            prof_end(c);
+            return;
+        }
+        level_down<DIM>(0, cf, true, first_done);
+        const S* zc = vcycle_coarse<DIM>(1);
+        level_up<DIM>(0, cf, true, zc, 1);
+    }
+    void vcycle(const void* phi, bool first_done) {
+        if (dim == 2) vcycle_t<2>(phi, first_done); else vcycle_t<3>(phi, first_done);
+    }
+
+    // p = z + beta p, q = A p (-> alpha), then x, r update fused with the
+    // first pre-smoothing sweep
+    template <int DIM, typename X>
+    void apply_update(const void* phi, int first, X* x) {
+        const CoefPhi<T, S> cf = coef_phi(phi);
+        const dim3 b(BX, BY);
+        S* pold = tp<S>(c->pv);
+        S* pnew = tp<S>(c->pv2);
+        prof_begin(c, PC_F_APPLY, fb(0, (first ? 1 : 2) + 2 + cfields(0)));
+        k_apply<CoefPhi<T, S>, S, DIM><<<grid(0), b, 0, c->stream>>>(
+            dims(0), ih2(0), cf, first, tp<S>(c->lv[0].zt), pold, pnew, tp<S>(c->qv), c->scal, c->partials);
+        prof_end(c);
+        (void)finalize2(c, (int)nbl(0), 0, FIN_ALPHA, 0.0);
+        prof_begin(c, PC_F_FIRST, fb(0, 5 + cfields(0)) + 2.0 * c->N * sizeof(X));
+        k_jac_first_update<CoefPhi<T, S>, S, X, DIM><<<grid(0), b, 0, c->stream>>>(
+            dims(0), ih2(0), omega, cf, x, tp<S>(c->lv[0].r), pnew, tp<S>(c->qv), tp<S>(c->lv[0].z),
+            c->scal, c->partials);
+        prof_end(c);
+        std::swap(c->pv, c->pv2);
+    }
+
+    // PCG on level 0 for x (type X); residual already in lv[0].r and the
+    // scalars initialised (ff, rr, tol2, done).
     template <typename X>
-    hipError_t pcg(X* x, int maxit, int check_every) {
-        const long N = c->N;
-        const unsigned nbv = vblocks();
-        S* r = tp<S>(c->lv[0].r);
-        S* p = tp<S>(c->pv);
-        S* q = tp<S>(c->qv);
-        const double vb = (double)N * sizeof(S);
-        S* z = vcycle();
-        prof_begin(c, PC_VEC_FINE, 2 * vb);
-        k_dot<S><<<nbv, BLOCK, 0, c->stream>>>(N, r, z, c->scal, c->partials);
-        prof_end(c);
-        (void)launch_finalize(c, (int)nbv, 1, FIN_RZ0);
-        prof_begin(c, PC_VEC_FINE, 2 * vb);
-        k_update_p<S><<<nbv, BLOCK, 0, c->stream>>>(N, 1, z, p, c->scal);
-        prof_end(c);
-        const int nb_apply = (int)nblocks_of(c->n);
+    hipError_t pcg(const void* phi, X* x, int maxit, int check_every) {
+        vcycle(phi, false);                                       // z = M r, <r,z>
+        (void)finalize2(c, 0, (int)nbl(0), FIN_RZ0, 0.0);
         int it = 0;
+        bool first = true;
         while (it < maxit) {
             for (int k = 0; k < check_every && it < maxit; ++k, ++it) {
-                prof_begin(c, PC_APPLY_FINE, vb * (2 + dim));
-                if (dim == 2)
-                    k_apply_dot<S, 2><<<grid(0), dim3(BX, BY), 0, c->stream>>>(dims(0), ih2(0), betas(0), p, q, c->scal, c->partials);
-                else
-                    k_apply_dot<S, 3><<<grid(0), dim3(BX, BY), 0, c->stream>>>(dims(0), ih2(0), betas(0), p, q, c->scal, c->partials);
-                prof_end(c);
-                (void)launch_finalize(c, nb_apply, 1, FIN_ALPHA);
-                prof_begin(c, PC_VEC_FINE, 4 * vb + 2.0 * N * sizeof(X));
-                k_update_xr<S, X><<<nbv, BLOCK, 0, c->stream>>>(N, x, r, p, q, c->scal, c->partials);
-                prof_end(c);
-                z = vcycle();
-                prof_begin(c, PC_VEC_FINE, 2 * vb);
-                k_dot<S><<<nbv, BLOCK, 0, c->stream>>>(N, r, z, c->scal, c->partials + nbv);
-                prof_end(c);
-                (void)launch_finalize(c, (int)nbv, 2, FIN_BETA);
-                prof_begin(c, PC_VEC_FINE, 3 * vb);
-                k_update_p<S><<<nbv, BLOCK, 0, c->stream>>>(N, 0, z, p, c->scal);
-                prof_end(c);
+                if (dim == 2) apply_update<2, X>(phi, first ? 1 : 0, x);
+                else apply_update<3, X>(phi, first ? 1 : 0, x);
+                first = false;
+                vcycle(phi, true);
+                (void)finalize2(c, (int)nbl(0), (int)nbl(0), FIN_BETA, 0.0);
             }
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
@@ -542,18 +689,38 @@ struct Solver {
         }
         return hipGetLastError();
     }
+
+    template <typename R>
+    void residual(const void* phi, R* r) {
+        const CoefPhi<T, S> cf = coef_phi(phi);
+        prof_begin(c, PC_RESID, (double)c->N * (8 + 8 + sizeof(T) + sizeof(R)));
+        if (dim == 2)
+            k_resid<T, S, R, 2><<<grid(0), dim3(BX, BY), 0, c->stream>>>(dims(0), ih2(0), cf, c->b, c->p, r,
+                                                                        c->scal, c->partials, c->max_blocks);
+        else
+            k_resid<T, S, R, 3><<<grid(0), dim3(BX, BY), 0, c->stream>>>(dims(0), ih2(0), cf, c->b, c->p, r,
+                                                                        c->scal, c->partials, c->max_blocks);
+        prof_end(c);
+    }
 };
 
+static unsigned vgrid(long N) {
+    const long nb = (N + BLOCK - 1) / BLOCK;
+    return (unsigned)(nb < VBLOCKS ? nb : VBLOCKS);
+}
+
 hipError_t launch_rhs_mean(tpf_ctx* c) {
-    const unsigned nb = (unsigned)((c->N + BLOCK - 1) / BLOCK);
+    const unsigned nb = vgrid(c->N);
     k_sum<<<nb, BLOCK, 0, c->stream>>>(c->N, c->b, c->partials);
-    return launch_finalize(c, (int)nb, 1, FIN_MEAN);
+    return finalize2(c, (int)nb, 0, FIN_MEAN, 0.0);
 }
 
 static hipError_t remove_mean(tpf_ctx* c, double* x) {
-    const unsigned nb = (unsigned)((c->N + BLOCK - 1) / BLOCK);
+    const unsigned nb = vgrid(c->N);
+    prof_begin(c, PC_VECTOR, (double)c->N * 8 * 3);
     k_sum<<<nb, BLOCK, 0, c->stream>>>(c->N, x, c->partials);
-    hipError_t e = launch_finalize(c, (int)nb, 1, FIN_SUM);
+    prof_end(c);
+    hipError_t e = finalize2(c, (int)nb, 0, FIN_SUM, 0.0);
     if (e != hipSuccess) return e;
     k_sub_mean<<<nb, BLOCK, 0, c->stream>>>(c->N, x, c->scal);
     return hipGetLastError();
@@ -566,30 +733,23 @@ static tpf_status read_scalars(tpf_ctx* c, SolverScalars* s) {
     return TPF_OK;
 }
 
+static double omega_of(int dim) { return dim == 2 ? 0.8 : 6.0 / 7.0; }
+
 // Solve with beta from phi (state precision); right-hand side in c->b with
 // its mean in scal->mean; x = c->p (warm start in, solution out, zero mean).
 tpf_status poisson_solve(tpf_ctx* c, const void* phi, int* iters, double* relres, int* outer) {
     const double rtol = c->P.poisson_rtol;
     const int maxit = c->P.poisson_maxit;
     const int check = 4;
+    const int nb = (int)nblocks_of(c->n);
     SolverScalars s;
     hipError_t e;
     if (!c->mixed) {
-        Solver<double> sv{c, c->dim, c->dim == 2 ? 0.8 : 6.0 / 7.0, 2};
+        Solver<double, double> sv{c, c->dim, omega_of(c->dim)};
         sv.build_betas(phi);
-        prof_begin(c, PC_VEC_FINE, (double)c->N * 8 * (3 + c->dim));
-        if (c->dim == 2)
-            k_resid_init<2><<<grid_of(c->n), dim3(BX, BY), 0, c->stream>>>(
-                dims_of(c->n), 1.0 / (c->h * c->h), sv.betas(0), c->b, c->p,
-                tp<double>(c->lv[0].r), c->scal, c->partials);
-        else
-            k_resid_init<3><<<grid_of(c->n), dim3(BX, BY), 0, c->stream>>>(
-                dims_of(c->n), 1.0 / (c->h * c->h), sv.betas(0), c->b, c->p,
-                tp<double>(c->lv[0].r), c->scal, c->partials);
-        prof_end(c);
-        k_finalize<<<1, BLOCK, 0, c->stream>>>((int)nblocks_of(c->n), 2, FIN_INIT, rtol * rtol, c->N,
-                                               c->partials, c->scal);
-        e = sv.pcg<double>(c->p, maxit, check);
+        sv.residual<double>(phi, tp<double>(c->lv[0].r));
+        (void)finalize2(c, nb, nb, FIN_INIT, rtol * rtol);
+        e = sv.pcg<double>(phi, c->p, maxit, check);
         if (e != hipSuccess) return hip_fail(e, "FP64 PCG");
         e = remove_mean(c, c->p);
         if (e != hipSuccess) return hip_fail(e, "mean removal");
@@ -609,24 +769,15 @@ tpf_status poisson_solve(tpf_ctx* c, const void* phi, int* iters, double* relres
         return TPF_OK;
     }
     // ---- mixed: FP64 defect correction around the FP32 multigrid-PCG
-    Solver<float> sv{c, c->dim, float(c->dim == 2 ? 0.8 : 6.0 / 7.0), 2};
+    Solver<float, float> sv{c, c->dim, float(omega_of(c->dim))};
+    Solver<float, double> s64{c, c->dim, 0.0};
     sv.build_betas(phi);
     const double rin = c->P.poisson_rtol_inner;
     int total = 0;
     const int max_outer = 12;
     for (int o = 0; o < max_outer; ++o) {
-        prof_begin(c, PC_RESID64, (double)c->N * (4 + 8 + 8 + 4));
-        if (c->dim == 2)
-            k_resid64<float, float, 2><<<grid_of(c->n), dim3(BX, BY), 0, c->stream>>>(
-                dims_of(c->n), phys_of(c), static_cast<const float*>(phi), c->b, c->p,
-                tp<float>(c->lv[0].r), c->scal, c->partials);
-        else
-            k_resid64<float, float, 3><<<grid_of(c->n), dim3(BX, BY), 0, c->stream>>>(
-                dims_of(c->n), phys_of(c), static_cast<const float*>(phi), c->b, c->p,
-                tp<float>(c->lv[0].r), c->scal, c->partials);
-        prof_end(c);
-        k_finalize<<<1, BLOCK, 0, c->stream>>>((int)nblocks_of(c->n), 2, FIN_INIT, rtol * rtol, c->N,
-                                               c->partials, c->scal);
+        s64.residual<float>(phi, tp<float>(c->lv[0].r));       // FP64 residual, FP64 beta
+        (void)finalize2(c, nb, nb, FIN_INIT, rtol * rtol);
         tpf_status st = read_scalars(c, &s);
         if (st != TPF_OK) return st;
         if (!std::isfinite(s.ff) || !std::isfinite(s.rr)) {
@@ -642,8 +793,8 @@ tpf_status poisson_solve(tpf_ctx* c, const void* phi, int* iters, double* relres
             return TPF_OK;
         }
         k_inner_setup<<<1, 64, 0, c->stream>>>(c->scal, rin * rin);
-        k_fill_s<float><<<(unsigned)((c->N + 255) / 256), 256, 0, c->stream>>>(c->N, tp<float>(c->ev), 0.0f);
-        e = sv.pcg<float>(tp<float>(c->ev), maxit, check);
+        k_fill_s<float><<<vgrid(c->N), BLOCK, 0, c->stream>>>(c->N, tp<float>(c->ev), 0.0f);
+        e = sv.pcg<float>(phi, tp<float>(c->ev), maxit, check);
         if (e != hipSuccess) return hip_fail(e, "FP32 inner PCG");
         st = read_scalars(c, &s);
         if (st != TPF_OK) return st;
@@ -652,8 +803,8 @@ tpf_status poisson_solve(tpf_ctx* c, const void* phi, int* iters, double* relres
             set_error("inner pressure solve did not converge within poisson_maxit iterations");
             return TPF_ENOCONV;
         }
-        prof_begin(c, PC_VEC_FINE, (double)c->N * (8 + 4 + 8));
-        k_correct<<<(unsigned)((c->N + BLOCK - 1) / BLOCK), BLOCK, 0, c->stream>>>(c->N, c->p, tp<float>(c->ev));
+        prof_begin(c, PC_VECTOR, (double)c->N * (8 + 4 + 8));
+        k_correct<<<vgrid(c->N), BLOCK, 0, c->stream>>>(c->N, c->p, tp<float>(c->ev));
         prof_end(c);
     }
     set_error("pressure defect correction did not converge");

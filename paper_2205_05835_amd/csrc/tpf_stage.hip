@@ -18,7 +18,7 @@ __global__ __launch_bounds__(BLOCK) void k_cell(Dims d, Phys P, const T* __restr
                                                 T* __restrict__ n2, T* __restrict__ mu) {
     Cell C;
     if (!cell_of_thread(d, C)) return;
-    const long c = C.id();
+    const unsigned c = C.id;
     const T f = phi[c];
     const T ih = T(P.inv_h), ih2 = T(0.5 * P.inv_h);
     T g[3] = {T(0), T(0), T(0)};
@@ -49,7 +49,7 @@ __global__ __launch_bounds__(BLOCK) void k_kappa(Dims d, Phys P, const T* __rest
     T s = T(0);
 #pragma unroll
     for (int a = 0; a < DIM; ++a) s += (n[a][C.off(a, 1)] - n[a][C.off(a, -1)]) * ih2;
-    kappa[C.id()] = -s;
+    kappa[C.id] = -s;
 }
 
 // ------------------------------------------------------------------ face fluxes
@@ -69,13 +69,13 @@ __global__ __launch_bounds__(BLOCK) void k_face(Dims d, Phys P, const T* __restr
     const T* u[3] = {u0, u1, u2};
     T* r[3] = {r0, r1, r2};
     T* m[3] = {m0, m1, m2};
-    const long c = C.id();
+    const unsigned c = C.id;
     const T f = phi[c];
     const bool cdi = P.model == MODEL_CDI;
     const T drho = T(P.rho1 - P.rho2);
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-        const long cm = C.off(a, -1);
+        const unsigned cm = C.off(a, -1);
         const T fm = phi[cm];
         const T rho_f = T(0.5) * (rho_of(P, fm) + rho_of(P, f));
         T ra = T(0);
@@ -104,13 +104,13 @@ __global__ __launch_bounds__(BLOCK) void k_phase(Dims d, Phys P, RKArgs rk,
     if (!cell_of_thread(d, C)) return;
     const T* u[3] = {u0, u1, u2};
     const T* r[3] = {r0, r1, r2};
-    const long c = C.id();
+    const unsigned c = C.id;
     const T f = phi[c];
     const T ih = T(P.inv_h);
     T adv = T(0), g = T(0), lap = T(0), gg = T(0);
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-        const long cp = C.off(a, 1), cm = C.off(a, -1);
+        const unsigned cp = C.off(a, 1), cm = C.off(a, -1);
         const T fp = phi[cp], fm = phi[cm];
         const T jhi = u[a][cp] * (T(0.5) * (f + fp));
         const T jlo = u[a][c] * (T(0.5) * (fm + f));
@@ -163,13 +163,13 @@ __global__ __launch_bounds__(BLOCK) void k_momentum(
     const T* m[3] = {m0, m1, m2};
     T* fs[3] = {f0, f1, f2};
     T* Fo[3] = {F0, F1, F2};
-    const long c = C.id();
+    const unsigned c = C.id;
     const T ih = T(P.inv_h);
     const T f = phi[c];
     const T eta_c = visc_of(P, f);
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-        const long cp = C.off(a, 1), cm = C.off(a, -1);
+        const unsigned cp = C.off(a, 1), cm = C.off(a, -1);
         const T fm = phi[cm];
         const T eta_m = visc_of(P, fm);
         const T uac = u[a][c];
@@ -182,13 +182,14 @@ __global__ __launch_bounds__(BLOCK) void k_momentum(
                 hi = (T(0.5) * (m[a][c] + m[a][cp])) * (T(0.5) * (uac + u[a][cp]));
                 lo = (T(0.5) * (m[a][cm] + m[a][c])) * (T(0.5) * (u[a][cm] + uac));
             } else {
-                const long cpb = C.off(b, 1), cmb = C.off(b, -1), cmapb = C.off2(a, -1, b, 1);
+                const unsigned cpb = C.off(b, 1), cmb = C.off(b, -1), cmapb = C.off2(a, -1, b, 1);
                 hi = (T(0.5) * (m[b][cpb] + m[b][cmapb])) * (T(0.5) * (uac + u[a][cpb]));
                 lo = (T(0.5) * (m[b][c] + m[b][cm])) * (T(0.5) * (u[a][cmb] + uac));
             }
             adv += (hi - lo) * ih;
             dm_c += (m[b][C.off(b, 1)] - m[b][c]) * ih;
-            dm_m += (m[b][C.off2(a, -1, b, 1)] - m[b][cm]) * ih;
+            // (c - e_a) + e_b: back to c itself when b == a
+            dm_m += (m[b][b == a ? c : C.off2(a, -1, b, 1)] - m[b][cm]) * ih;
         }
         const T N = adv - uac * (T(0.5) * (dm_m + dm_c));
         // ---- viscous stress
@@ -200,8 +201,8 @@ __global__ __launch_bounds__(BLOCK) void k_momentum(
                 hi = T(2) * eta_c * ((u[a][cp] - uac) * ih);
                 lo = T(2) * eta_m * ((uac - u[a][cm]) * ih);
             } else {
-                const long cpb = C.off(b, 1), cmb = C.off(b, -1);
-                const long cmapb = C.off2(a, -1, b, 1), cmamb = C.off2(a, -1, b, -1);
+                const unsigned cpb = C.off(b, 1), cmb = C.off(b, -1);
+                const unsigned cmapb = C.off2(a, -1, b, 1), cmamb = C.off2(a, -1, b, -1);
                 const T e_pb = visc_of(P, phi[cpb]), e_mapb = visc_of(P, phi[cmapb]);
                 const T e_mb = visc_of(P, phi[cmb]), e_mamb = visc_of(P, phi[cmamb]);
                 const T eta_hi = T(0.25) * (eta_c + eta_m + e_pb + e_mapb);
@@ -238,7 +239,7 @@ __global__ __launch_bounds__(BLOCK) void k_div(Dims d, Phys P, const T* __restri
     double v[1] = {0.0};
     if (cell_of_thread(d, C)) {
         const T* fs[3] = {f0, f1, f2};
-        const long c = C.id();
+        const unsigned c = C.id;
         double s = 0.0;
 #pragma unroll
         for (int a = 0; a < DIM; ++a)
@@ -266,12 +267,12 @@ __global__ __launch_bounds__(BLOCK) void k_project(Dims d, Phys P, RKArgs rk,
     const T* yn[3] = {yn0, yn1, yn2};
     T* acc[3] = {acc0, acc1, acc2};
     T* nx[3] = {nx0, nx1, nx2};
-    const long c = C.id();
+    const unsigned c = C.id;
     const T f = phi[c];
     const double pc = p[c];
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-        const long cm = C.off(a, -1);
+        const unsigned cm = C.off(a, -1);
         const double rho_f = 0.5 * ((double)rho_of(P, phi[cm]) + (double)rho_of(P, f));
         const double gp = (pc - p[cm]) * P.inv_h;
         const T k = T((double)fs[a][c] - gp / rho_f);
@@ -311,7 +312,7 @@ __global__ __launch_bounds__(BLOCK) void k_init_droplet(Dims d, double h, double
     }
     const double q = sqrt(q2);
     const double s = (q2 == 0.0) ? amin : (1.0 - q) * q / sqrt(g2);
-    phi[C.id()] = T(0.5 * (1.0 + tanh(s / (2.0 * eps))));
+    phi[C.id] = T(0.5 * (1.0 + tanh(s / (2.0 * eps))));
 }
 
 template <typename T>
@@ -347,12 +348,12 @@ __global__ __launch_bounds__(BLOCK) void k_diag(Dims d, Phys P, const T* __restr
     double mx[ND_MAX] = {0.0, 0.0, -1e300, -1e300};
     if (cell_of_thread(d, C)) {
         const T* u[3] = {u0, u1, u2};
-        const long c = C.id();
+        const unsigned c = C.id;
         const double f = (double)phi[c];
         double sp2 = 0.0, kin = 0.0, g2 = 0.0, div = 0.0;
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
-            const long cp = C.off(a, 1), cm = C.off(a, -1);
+            const unsigned cp = C.off(a, 1), cm = C.off(a, -1);
             const double ua = (double)u[a][c], uap = (double)u[a][cp];
             const double ub = 0.5 * (ua + uap);
             sp2 += ub * ub;

@@ -240,8 +240,18 @@ class Solver:
         return x.reshape(self.shape), it.value, rr.value
 
     # ---------------------------------------------------------------- profiling
-    def profile_enable(self, on: bool = True):
-        check(lib().tpf_profile_enable(self.ctx, 1 if on else 0), "tpf_profile_enable")
+    def profile_enable(self, mask: int = -1):
+        """Time the kernel classes in the bit mask (-1: all, 0: stop)."""
+        check(lib().tpf_profile_enable(self.ctx, int(mask)), "tpf_profile_enable")
+
+    def profile_classes(self) -> list:
+        out = []
+        for q in range(lib().tpf_profile_classes()):
+            name = ctypes.c_char_p()
+            check(lib().tpf_profile_read(self.ctx, q, ctypes.byref(name), None, None, None),
+                  "tpf_profile_read")
+            out.append(name.value.decode())
+        return out
 
     def profile_read(self) -> dict:
         out = {}
