@@ -16,6 +16,7 @@ constexpr int BLOCK = BX * BY;
 
 struct Dims {
     int nx, ny, nz;
+    int xcd;        // 1: XCD slab tiling of the 1D block grid, 0: tile = block id
 };
 
 // Physical parameters as the kernels consume them.
@@ -48,6 +49,9 @@ struct Cell {
     __device__ __forceinline__ unsigned off(int a, int s) const {
         return min(id + (unsigned)o[a][s > 0], last);
     }
+    // unclamped neighbour (pressure-solver kernels, whose index arithmetic is
+    // checked cell by cell against the wrapped coordinates on the CPU)
+    __device__ __forceinline__ unsigned nb(int a, int s) const { return id + (unsigned)o[a][s > 0]; }
     // c + s e_a + t e_b for a != b only: each offset is the one of cell c, so
     // two shifts compose only when they move along different axes
     __device__ __forceinline__ unsigned off2(int a, int s, int b, int t) const {
@@ -72,14 +76,51 @@ __device__ __forceinline__ Cell make_cell(const Dims& d, int i, int j, int k) {
     return C;
 }
 
-__device__ __forceinline__ bool cell_of_thread(const Dims& d, Cell& C) {
-    const int i = blockIdx.x * BX + threadIdx.x;
-    const int j = blockIdx.y * BY + threadIdx.y;
-    const int k = blockIdx.z;
-    if (i >= d.nx || j >= d.ny) return false;
-    C = make_cell(d, i, j, k);
+// XCD-aware tiling.  Workgroups are dealt to the 8 XCDs round robin by their
+// linear id, and each XCD has its own L2.  Grids are therefore 1D (padded to a
+// multiple of 8) and block b works on tile (b % 8) * (nb / 8) + b / 8: every
+// XCD owns one contiguous run of tiles (a slab of z planes), so the y and z
+// neighbours a stencil reads sit in the same L2.  Tiles are x-fastest.
+constexpr int NXCD = 8;
+
+__device__ __forceinline__ bool block_tile(int xcd, int gx, int gy, int gz, int& bx, int& by, int& bz) {
+    const int nb = gridDim.x;
+    const int b = blockIdx.x;
+    const int tile = xcd ? (b % NXCD) * (nb / NXCD) + b / NXCD : b;
+    if (tile >= gx * gy * gz) return false;
+    bx = tile % gx;
+    by = (tile / gx) % gy;
+    bz = tile / (gx * gy);
     return true;
 }
+
+// the cell of this thread for a (BX x BY x 1) tiling of the grid
+__device__ __forceinline__ bool cell_of_thread(const Dims& d, Cell& C) {
+    int bx, by, bz;
+    if (!block_tile(d.xcd, (d.nx + BX - 1) / BX, (d.ny + BY - 1) / BY, d.nz, bx, by, bz)) return false;
+    const int i = bx * BX + threadIdx.x;
+    const int j = by * BY + threadIdx.y;
+    if (i >= d.nx || j >= d.ny) return false;
+    C = make_cell(d, i, j, bz);
+    return true;
+}
+
+// Loads and stores at a 32-bit element index: the byte offset is formed in
+// 32 bits (grids below 2^29 cells for FP64 fields, 2^30 for FP32), so the
+// access compiles to a scalar base address plus one 32-bit vector offset
+// instead of a 64-bit address per lane.
+template <typename T>
+__device__ __forceinline__ T ld(const T* base, unsigned idx) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (unsigned)(idx * (unsigned)sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ void st(T* base, unsigned idx, T v) {
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (unsigned)(idx * (unsigned)sizeof(T))) = v;
+}
+
+// median of three: clamp in one instruction
+__device__ __forceinline__ float med3(float a, float lo, float hi) { return __builtin_amdgcn_fmed3f(a, lo, hi); }
+__device__ __forceinline__ double med3(double a, double lo, double hi) { return fmin(fmax(a, lo), hi); }
 
 __device__ __forceinline__ int block_linear() {
     return (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;

@@ -14,6 +14,7 @@
 namespace tpf {
 
 static thread_local std::string g_err;
+int g_xcd_tiles = 0;
 
 void set_error(const std::string& msg) { g_err = msg; }
 
@@ -169,6 +170,7 @@ static size_t carve(tpf_ctx* c, char* base) {
     c->pv2 = cv.take((size_t)c->N * ssz);
     c->qv = cv.take((size_t)c->N * ssz);
     c->ev = c->mixed ? cv.take((size_t)c->N * ssz) : nullptr;
+    c->rhoh = cv.take((size_t)c->N * ssz);
     for (int l = 0; l < c->nlev; ++l) {
         Level& L = c->lv[l];
         for (int a = 0; a < 3; ++a) L.beta[a] = a < c->dim ? cv.take((size_t)L.N * ssz) : nullptr;
@@ -219,6 +221,10 @@ static void init_geometry(tpf_ctx* c, const tpf_params* P) {
     c->h = P->length / P->n[0];
     c->mixed = P->precision == TPF_FP32_MIXED;
     c->tsz = c->mixed ? 4 : 8;
+    const char* m = std::getenv("TPF_MARCH");
+    c->march = (m && m[0] == '0') ? 0 : 1;
+    const char* xt = std::getenv("TPF_XCD_TILES");
+    g_xcd_tiles = (xt && xt[0] == '1') ? 1 : 0;
     c->nlev = plan_levels(c);
 }
 

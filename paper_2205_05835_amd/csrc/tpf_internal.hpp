@@ -69,6 +69,7 @@ struct tpf_ctx {
     long N;
     double h;
     int mixed;           // 0: FP64, 1: FP32 state + FP64 pressure
+    int march;           // 3D level 0 uses the z-marching kernels (TPF_MARCH=0 disables)
     size_t tsz;          // bytes per state value
     hipStream_t stream;
     char* ws;
@@ -98,6 +99,7 @@ struct tpf_ctx {
     void* pv2;           // search direction, ping-pong partner
     void* qv;            // A p
     void* ev;            // mixed: inner solution (correction)
+    void* rhoh;          // fine-level half density rho(phi)/2 (solver precision)
     tpf::Level lv[tpf::MAX_LEVELS];
     int nlev;
 
@@ -164,14 +166,17 @@ tpf_status poisson_solve(tpf_ctx* c, const void* phi, int* iters, double* relres
 hipError_t launch_finalize(tpf_ctx* c, int nblocks, int nv, int op);
 hipError_t launch_rhs_mean(tpf_ctx* c);
 
+// 1D grid over gx*gy*gz tiles, padded to a multiple of the XCD count
+inline dim3 tile_grid(long gx, long gy, long gz) {
+    const long nt = gx * gy * gz;
+    return dim3((unsigned)((nt + NXCD - 1) / NXCD * NXCD), 1, 1);
+}
 inline dim3 grid_of(const int n[3]) {
-    return dim3((n[0] + BX - 1) / BX, (n[1] + BY - 1) / BY, n[2]);
+    return tile_grid((n[0] + BX - 1) / BX, (n[1] + BY - 1) / BY, n[2]);
 }
-inline long nblocks_of(const int n[3]) {
-    dim3 g = grid_of(n);
-    return (long)g.x * g.y * g.z;
-}
-inline Dims dims_of(const int n[3]) { return Dims{n[0], n[1], n[2]}; }
+inline long nblocks_of(const int n[3]) { return (long)grid_of(n).x; }
+extern int g_xcd_tiles;   // host copy of the tiling choice (TPF_XCD_TILES=1 enables)
+inline Dims dims_of(const int n[3]) { return Dims{n[0], n[1], n[2], g_xcd_tiles}; }
 Phys phys_of(const tpf_ctx* c);
 
 }  // namespace tpf

@@ -30,6 +30,8 @@
 // two regions (offset 0 and offset max_blocks) summed by one finalize kernel.
 #include <algorithm>
 #include <cmath>
+#include <limits>
+#include <type_traits>
 
 #include "tpf_internal.hpp"
 
@@ -56,29 +58,51 @@ __device__ __forceinline__ void block_partials_2r(double (&v)[2], double* partia
 }
 
 // ---------------------------------------------------------------- coefficients
-// Fine level: beta on the faces of a cell from the density law of phi.  A face
-// between cells lo < hi is always 2 / (rho(lo) + rho(hi)) in that operand
-// order, so both cells of a face see bit-identical coefficients (symmetric A).
+// Fine level: beta on the faces of a cell from the density law of phi.  Both
+// policies return the half density h = rho / 2, and a face between cells
+// lo < hi is always 1 / (h(lo) + h(hi)) in that operand order, so both cells
+// of a face see bit-identical coefficients (symmetric A).  CoefPhi evaluates
+// the law from phi; CoefRho reads h precomputed once per solve.
 template <typename T, typename S>
 struct CoefPhi {
     const T* __restrict__ phi;
-    S rho2, drho;
-    int clamp;
-    __device__ __forceinline__ S rho(unsigned c) const {
-        S f = S(phi[c]);
-        if (clamp) f = f < S(0) ? S(0) : (f > S(1) ? S(1) : f);
-        return rho2 + drho * f;
+    S h2, dh;          // rho2 / 2, (rho1 - rho2) / 2
+    S lo, hi;          // clamp bounds of phi: [0, 1], or +-inf when not clamping
+    __device__ __forceinline__ S hr(unsigned c) const {
+        return h2 + dh * med3(S(ld(phi, c)), lo, hi);
     }
     template <int DIM>
     __device__ __forceinline__ void faces(const Cell& C, S* bl, S* bh) const {
-        const S rc = rho(C.id);
+        const S hc = hr(C.id);
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
-            bl[a] = two_over(rho(C.off(a, -1)) + rc);
-            bh[a] = two_over(rc + rho(C.off(a, 1)));
+            bl[a] = recip(hr(C.nb(a, -1)) + hc);
+            bh[a] = recip(hc + hr(C.nb(a, 1)));
         }
     }
 };
+
+template <typename S>
+struct CoefRho {
+    const S* __restrict__ h;
+    __device__ __forceinline__ S hr(unsigned c) const { return ld(h, c); }
+    template <int DIM>
+    __device__ __forceinline__ void faces(const Cell& C, S* bl, S* bh) const {
+        const S hc = hr(C.id);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            bl[a] = recip(hr(C.nb(a, -1)) + hc);
+            bh[a] = recip(hc + hr(C.nb(a, 1)));
+        }
+    }
+};
+
+// h = rho(phi) / 2 for the fine level, once per solve
+template <typename T, typename S>
+__global__ __launch_bounds__(BLOCK) void k_half_rho(long N, CoefPhi<T, S> cf, S* __restrict__ h) {
+    for (long c = (long)blockIdx.x * BLOCK + threadIdx.x; c < N; c += (long)gridDim.x * BLOCK)
+        h[c] = cf.hr((unsigned)c);
+}
 
 template <typename S>
 struct CoefStored {
@@ -91,8 +115,8 @@ struct CoefStored {
         const unsigned c = C.id;
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
-            bl[a] = b[a][c];
-            bh[a] = b[a][C.off(a, 1)];
+            bl[a] = ld(b[a], c);
+            bh[a] = ld(b[a], C.nb(a, 1));
         }
     }
 };
@@ -114,9 +138,8 @@ __device__ __forceinline__ S apply_at(const S* bl, const S* bh, Fx x, S xc, S ih
 // ---------------------------------------------------------------- coefficients setup
 // stored coefficients of level 1: mean of the fine face coefficients (same law
 // as CoefPhi) over the fine faces covering each coarse face
-template <typename T, typename S, int DIM>
-__global__ __launch_bounds__(BLOCK) void k_beta_from_phi(Dims fd, Dims cd, CoefPhi<T, S> cf, S* b0,
-                                                         S* b1, S* b2) {
+template <typename Coef, typename S, int DIM>
+__global__ __launch_bounds__(BLOCK) void k_beta_from_phi(Dims fd, Dims cd, Coef cf, S* b0, S* b1, S* b2) {
     Cell C;
     if (!cell_of_thread(cd, C)) return;
     S* b[3] = {b0, b1, b2};
@@ -130,7 +153,7 @@ __global__ __launch_bounds__(BLOCK) void k_beta_from_phi(Dims fd, Dims cd, CoefP
             for (int e = 0; e < DIM; ++e)
                 if (e != a) o[e] = (t >> q++) & 1;
             const Cell F = make_cell(fd, i0 + o[0], j0 + o[1], k0 + o[2]);
-            s += two_over(cf.rho(F.off(a, -1)) + cf.rho(F.id));
+            s += recip(cf.hr(F.nb(a, -1)) + cf.hr(F.id));
         }
         b[a][C.id] = s * S(1.0 / (1 << (DIM - 1)));
     }
@@ -163,8 +186,8 @@ __global__ __launch_bounds__(BLOCK) void k_beta_coarsen(Dims fd, Dims cd, CoefSt
 // ---------------------------------------------------------------- residuals
 // r = -(b - mean) - A x in precision S (x and b FP64), stored as R;
 // partials: |f|^2 -> region 0, |r|^2 -> region 1
-template <typename T, typename S, typename R, int DIM>
-__global__ __launch_bounds__(BLOCK) void k_resid(Dims d, S ih2, CoefPhi<T, S> cf,
+template <typename Coef, typename S, typename R, int DIM>
+__global__ __launch_bounds__(BLOCK) void k_resid(Dims d, S ih2, Coef cf,
                                                  const double* __restrict__ b,
                                                  const double* __restrict__ x,
                                                  R* __restrict__ r,
@@ -176,10 +199,10 @@ __global__ __launch_bounds__(BLOCK) void k_resid(Dims d, S ih2, CoefPhi<T, S> cf
         S bl[3], bh[3], dg;
         cf.template faces<DIM>(C, bl, bh);
         const unsigned c = C.id;
-        auto X = [&](int a, int s) { return S(x[C.off(a, s)]); };
-        const double f = -(b[c] - sc->mean);
-        const double rc = f - (double)apply_at<S, DIM>(bl, bh, X, S(x[c]), ih2, dg);
-        r[c] = R(rc);
+        auto X = [&](int a, int s) { return S(ld(x, C.nb(a, s))); };
+        const double f = -(ld(b, c) - sc->mean);
+        const double rc = f - (double)apply_at<S, DIM>(bl, bh, X, S(ld(x, c)), ih2, dg);
+        st(r, c, R(rc));
         v[0] = f * f;
         v[1] = rc * rc;
     }
@@ -200,7 +223,7 @@ __global__ __launch_bounds__(BLOCK) void k_jac_first(Dims d, S ih2, S omega, Coe
 #pragma unroll
     for (int a = 0; a < DIM; ++a) dg += bl[a] + bh[a];
     const unsigned c = C.id;
-    z[c] = omega * r[c] * recip(dg * ih2);
+    st(z, c, omega * ld(r, c) * recip(dg * ih2));
 }
 
 // PCG update fused with the first smoothing sweep of the V-cycle:
@@ -219,15 +242,15 @@ __global__ __launch_bounds__(BLOCK) void k_jac_first_update(Dims d, S ih2, S ome
     if (cell_of_thread(d, C)) {
         const unsigned c = C.id;
         const double alpha = sc->alpha;
-        x[c] = X((double)x[c] + alpha * (double)p[c]);
-        const S rn = S((double)r[c] - alpha * (double)q[c]);
-        r[c] = rn;
+        st(x, c, X((double)ld(x, c) + alpha * (double)ld(p, c)));
+        const S rn = S((double)ld(r, c) - alpha * (double)ld(q, c));
+        st(r, c, rn);
         v[0] = (double)rn * (double)rn;
         S bl[3], bh[3], dg = S(0);
         cf.template faces<DIM>(C, bl, bh);
 #pragma unroll
         for (int a = 0; a < DIM; ++a) dg += bl[a] + bh[a];
-        z[c] = omega * rn * recip(dg * ih2);
+        st(z, c, omega * rn * recip(dg * ih2));
     }
     block_partials<1>(v, partials);
 }
@@ -252,20 +275,20 @@ __global__ __launch_bounds__(BLOCK) void k_jac(Dims d, Dims cd, S ih2, S omega, 
         const int par[3] = {C.i & 1, C.j & 1, C.k & 1};
         auto parent = [&](int a, int s) -> unsigned {
             const bool leaves = (s < 0) ? (par[a] == 0) : (par[a] == 1);
-            return leaves ? Pc.off(a, s) : Pc.id;
+            return leaves ? Pc.nb(a, s) : Pc.id;
         };
         auto Z = [&](int a, int s) -> S {
-            if (!PRO) return z[C.off(a, s)];
-            return z[C.off(a, s)] + zc[parent(a, s)];
+            if (!PRO) return ld(z, C.nb(a, s));
+            return ld(z, C.nb(a, s)) + ld(zc, parent(a, s));
         };
         S bl[3], bh[3], dg;
         cf.template faces<DIM>(C, bl, bh);
         const unsigned c = C.id;
-        const S zcen = PRO ? z[c] + zc[Pc.id] : z[c];
+        const S zcen = PRO ? ld(z, c) + ld(zc, Pc.id) : ld(z, c);
         const S az = apply_at<S, DIM>(bl, bh, Z, zcen, ih2, dg);
-        const S rc = r[c];
+        const S rc = ld(r, c);
         const S out = zcen + omega * (rc - az) * recip(dg);
-        zt[c] = out;
+        st(zt, c, out);
         if (DOT) v[0] = (double)rc * (double)out;
     }
     if (DOT) block_partials<1>(v, partials);
@@ -284,23 +307,26 @@ __global__ __launch_bounds__(BLOCK) void k_restrict(Dims fd, Dims cd, S ih2, Coe
     constexpr int TY = DIM == 3 ? 2 : 4, TZ = DIM == 3 ? 2 : 1;
     __shared__ S sh[TZ][TY][BX];
     const int tx = threadIdx.x, ty = threadIdx.y, tz = threadIdx.z;
-    const int fi = blockIdx.x * BX + tx, fj = blockIdx.y * TY + ty, fk = blockIdx.z * TZ + tz;
-    const bool in = fi < fd.nx && fj < fd.ny && fk < fd.nz;
+    int bx, by, bz;
+    const bool tile = block_tile(fd.xcd, (fd.nx + BX - 1) / BX, (fd.ny + TY - 1) / TY, (fd.nz + TZ - 1) / TZ, bx,
+                                 by, bz);
+    const int fi = bx * BX + tx, fj = by * TY + ty, fk = bz * TZ + tz;
+    const bool in = tile && fi < fd.nx && fj < fd.ny && fk < fd.nz;
     const Cell C = make_cell(fd, in ? fi : 0, in ? fj : 0, in ? fk : 0);
     S res = S(0);
     if (in) {
         S bl[3], bh[3], dg;
         cf.template faces<DIM>(C, bl, bh);
-        auto Z = [&](int a, int s) { return z[C.off(a, s)]; };
+        auto Z = [&](int a, int s) { return ld(z, C.nb(a, s)); };
         const unsigned c = C.id;
-        res = r[c] - apply_at<S, DIM>(bl, bh, Z, z[c], ih2, dg);
+        res = ld(r, c) - apply_at<S, DIM>(bl, bh, Z, ld(z, c), ih2, dg);
     }
     res += __shfl_xor(res, 1, 64);
     sh[tz][ty][tx] = res;
     __syncthreads();
     if (in && (tx & 1) == 0 && (ty & 1) == 0 && tz == 0) {
         S s = sh[0][ty][tx] + sh[0][ty + 1][tx];
-        if (DIM == 3) s += sh[1][ty][tx] + sh[1][ty + 1][tx];
+        if constexpr (DIM == 3) s += sh[1][ty][tx] + sh[1][ty + 1][tx];
         const long cc = ((long)(C.k >> 1) * cd.ny + (C.j >> 1)) * cd.nx + (C.i >> 1);
         const long cmax = (long)cd.nx * cd.ny * cd.nz - 1;
         rc[cc < cmax ? cc : cmax] = s * S(1.0 / (DIM == 3 ? 8 : 4));
@@ -326,7 +352,7 @@ __global__ __launch_bounds__(1024) void k_coarse(Dims d, S ih2, S omega, int swe
             S bl[3], bh[3], dg;
             cf.template faces<DIM>(C, bl, bh);
             const S* xs = src;
-            auto X = [&](int a, int t) { return xs[C.off(a, t)]; };
+            auto X = [&](int a, int t) { return xs[C.nb(a, t)]; };
             const S az = apply_at<S, DIM>(bl, bh, X, src[q], ih2, dg);
             dst[q] = src[q] + omega * (r[q] - az) / dg;
         }
@@ -354,15 +380,15 @@ __global__ __launch_bounds__(BLOCK) void k_apply(Dims d, S ih2, Coef cf, int fir
     double v[1] = {0.0};
     if (cell_of_thread(d, C)) {
         const S beta = first ? S(0) : S(sc->beta);
-        auto Pn = [&](long t) -> S { return first ? z[t] : z[t] + beta * pold[t]; };
-        auto Pa = [&](int a, int s) { return Pn(C.off(a, s)); };
+        auto Pn = [&](unsigned t) -> S { return first ? ld(z, t) : ld(z, t) + beta * ld(pold, t); };
+        auto Pa = [&](int a, int s) { return Pn(C.nb(a, s)); };
         S bl[3], bh[3], dg;
         cf.template faces<DIM>(C, bl, bh);
         const unsigned c = C.id;
         const S pc = Pn(c);
         const S aq = apply_at<S, DIM>(bl, bh, Pa, pc, ih2, dg);
-        pnew[c] = pc;
-        q[c] = aq;
+        st(pnew, c, pc);
+        st(q, c, aq);
         v[0] = (double)pc * (double)aq;
     }
     block_partials<1>(v, partials);
@@ -494,7 +520,377 @@ hipError_t launch_finalize(tpf_ctx* c, int nblocks, int nv, int op) {
     return finalize2(c, nblocks, nv > 1 ? nblocks : 0, op, 0.0);
 }
 
+// ================================================================== 3D level 0, z-marching
+// Block 64 x 4 threads over (x, y); each thread walks kz consecutive z planes
+// of its column.  z-neighbours come from a rolling register window, x
+// neighbours from the adjacent lanes of the wave (a wave is 64 consecutive x
+// cells; the two edge lanes load theirs), y neighbours from loads that mostly
+// hit the rows the block's other waves just read.  Each field is thus read
+// about once from L2 per sweep instead of once per stencil point.
+
+struct Col {
+    int nx, ny, nz;
+    int i, j;                 // column (clamped into the grid for inactive lanes)
+    bool valid;               // lane owns a real column
+    unsigned plane, row;
+    int oxm, oxp, oym, oyp;   // periodic in-plane neighbour offsets
+    int im, ip, jm, jp;       // neighbour coordinates
+    bool sxm, sxp;            // x neighbour held by the adjacent lane
+    int kslab;                // index of this block's slab of kz planes
+    __device__ __forceinline__ void init(const Dims& d, int kz) {
+        nx = d.nx;
+        ny = d.ny;
+        nz = d.nz;
+        const int tx = threadIdx.x;
+        int bx = 0, by = 0;
+        const bool tile = block_tile(d.xcd, (nx + BX - 1) / BX, (ny + BY - 1) / BY, nz / kz, bx, by, kslab);
+        const int i0 = bx * BX + tx, j0 = by * BY + threadIdx.y;
+        if (!tile) kslab = nz / kz;      // empty range: the block only joins its reductions
+        valid = tile && i0 < nx && j0 < ny;
+        i = valid ? i0 : 0;
+        j = valid ? j0 : 0;
+        plane = (unsigned)(nx * ny);
+        row = (unsigned)(j * nx + i);
+        oxm = i == 0 ? nx - 1 : -1;
+        oxp = i == nx - 1 ? 1 - nx : 1;
+        oym = j == 0 ? (ny - 1) * nx : -nx;
+        oyp = j == ny - 1 ? (1 - ny) * nx : nx;
+        im = i == 0 ? nx - 1 : i - 1;
+        ip = i == nx - 1 ? 0 : i + 1;
+        jm = j == 0 ? ny - 1 : j - 1;
+        jp = j == ny - 1 ? 0 : j + 1;
+        sxm = tx > 0 && i > 0;
+        sxp = tx < BX - 1 && i < nx - 1;
+    }
+    __device__ __forceinline__ unsigned at(int k) const { return (unsigned)k * plane + row; }
+    __device__ __forceinline__ int kwrap(int k) const { return k < 0 ? k + nz : (k >= nz ? k - nz : k); }
+};
+
+// value of the lane on the left / right (lanes 0 / 63 get their own back)
+template <typename V>
+__device__ __forceinline__ V lane_m(V v) { return __shfl_up(v, 1, 64); }
+template <typename V>
+__device__ __forceinline__ V lane_p(V v) { return __shfl_down(v, 1, 64); }
+
+// Coefficients and stencil of one cell from the rolling/neighbour values:
+// rho at c and its six neighbours, field at c and its six neighbours.
+template <typename S>
+struct Nbr7 {
+    S c, xm, xp, ym, yp, zm, zp;
+};
+
+template <typename S>
+__device__ __forceinline__ void faces7(const Nbr7<S>& rho, S* bl, S* bh) {
+    bl[0] = recip(rho.xm + rho.c);
+    bh[0] = recip(rho.c + rho.xp);
+    bl[1] = recip(rho.ym + rho.c);
+    bh[1] = recip(rho.c + rho.yp);
+    bl[2] = recip(rho.zm + rho.c);
+    bh[2] = recip(rho.c + rho.zp);
+}
+
+template <typename S>
+__device__ __forceinline__ S apply7(const S* bl, const S* bh, const Nbr7<S>& x, S ih2, S& diag) {
+    const S acc = bl[0] * (x.c - x.xm) - bh[0] * (x.xp - x.c) + bl[1] * (x.c - x.ym) -
+                  bh[1] * (x.yp - x.c) + bl[2] * (x.c - x.zm) - bh[2] * (x.zp - x.c);
+    diag = (bl[0] + bh[0] + bl[1] + bh[1] + bl[2] + bh[2]) * ih2;
+    return acc * ih2;
+}
+
+// Marches the half density and one field F along the column, software
+// pipelined: while plane k is computed, the in-plane neighbours and per-cell
+// operands (pre) of plane k+1 and the column values of plane k+2 are already
+// in flight, so each wave waits for memory about once per block rather than
+// once per plane.  F(idx, i, j, k) returns the field at a cell; pre(c)
+// returns the per-cell operands the body needs; body(k, c, rho7, f7, e) is
+// called once per plane.
+template <typename S>
+struct Side {            // plane neighbours that need loads
+    S hxm, hxp, hym, hyp, fxm, fxp, fym, fyp;
+};
+
+template <typename Coef, typename S, bool WITH_FIELD, typename F, typename Pre, typename Body>
+__device__ __forceinline__ void march(const Col& q, const Coef& cf, int k0, int k1, F fld, Pre pre,
+                                      Body body) {
+    if (k0 >= k1) return;            // padding block of the XCD tiling
+    using E = decltype(pre(0u));
+    auto side = [&](int k) {
+        Side<S> s;
+        const unsigned c = q.at(k);
+        s.hxm = q.sxm ? S(0) : cf.hr(c + q.oxm);
+        s.hxp = q.sxp ? S(0) : cf.hr(c + q.oxp);
+        s.hym = cf.hr(c + q.oym);
+        s.hyp = cf.hr(c + q.oyp);
+        if (WITH_FIELD) {
+            s.fxm = q.sxm ? S(0) : fld(c + q.oxm, q.im, q.j, k);
+            s.fxp = q.sxp ? S(0) : fld(c + q.oxp, q.ip, q.j, k);
+            s.fym = fld(c + q.oym, q.i, q.jm, k);
+            s.fyp = fld(c + q.oyp, q.i, q.jp, k);
+        } else {
+            s.fxm = s.fxp = s.fym = s.fyp = S(0);
+        }
+        return s;
+    };
+    const int km = q.kwrap(k0 - 1), kp = q.kwrap(k0 + 1);
+    S hm = cf.hr(q.at(km)), hc = cf.hr(q.at(k0)), hp = cf.hr(q.at(kp));
+    S fm = S(0), fc = S(0), fp = S(0);
+    if (WITH_FIELD) {
+        fm = fld(q.at(km), q.i, q.j, km);
+        fc = fld(q.at(k0), q.i, q.j, k0);
+        fp = fld(q.at(kp), q.i, q.j, kp);
+    }
+    Side<S> sc = side(k0);
+    E ec = pre(q.at(k0));
+    for (int k = k0; k < k1; ++k) {
+        // issue the loads of the next planes first
+        Side<S> sn = sc;
+        E en = ec;
+        S hpp = hp, fpp = fp;
+        if (k + 1 < k1) {
+            const int kn = q.kwrap(k + 1), knn = q.kwrap(k + 2);
+            sn = side(kn);
+            en = pre(q.at(kn));
+            hpp = cf.hr(q.at(knn));
+            if (WITH_FIELD) fpp = fld(q.at(knn), q.i, q.j, knn);
+        }
+        // plane k from registers and neighbouring lanes
+        const S lhm = lane_m(hc), lhp = lane_p(hc);
+        Nbr7<S> R, X;
+        R.c = hc;
+        R.zm = hm;
+        R.zp = hp;
+        R.xm = q.sxm ? lhm : sc.hxm;
+        R.xp = q.sxp ? lhp : sc.hxp;
+        R.ym = sc.hym;
+        R.yp = sc.hyp;
+        if (WITH_FIELD) {
+            const S lfm = lane_m(fc), lfp = lane_p(fc);
+            X.c = fc;
+            X.zm = fm;
+            X.zp = fp;
+            X.xm = q.sxm ? lfm : sc.fxm;
+            X.xp = q.sxp ? lfp : sc.fxp;
+            X.ym = sc.fym;
+            X.yp = sc.fyp;
+        }
+        body(k, q.at(k), R, X, ec);
+        hm = hc;
+        hc = hp;
+        hp = hpp;
+        fm = fc;
+        fc = fp;
+        fp = fpp;
+        sc = sn;
+        ec = en;
+    }
+}
+
+struct NoPre {};
+
+// sweeps: MODE 0: zt = z + omega (r - A z)/d; 1: same with Z = z + P zc;
+// 2: as 0 and <r, zt> to the partials
+template <typename Coef, typename S, int MODE>
+__global__ __launch_bounds__(BLOCK) void k_fz_jac(Dims d, Dims cd, int kz, S ih2, S omega,
+                                                  Coef cf, const S* __restrict__ r,
+                                                  const S* __restrict__ z,
+                                                  const S* __restrict__ zc, S* __restrict__ zt,
+                                                  const SolverScalars* __restrict__ sc,
+                                                  double* __restrict__ partials) {
+    if (sc->done) return;
+    Col q;
+    q.init(d, kz);
+    const int k0 = q.kslab * kz, k1 = min(k0 + kz, d.nz);
+    auto fld = [&](unsigned idx, int i, int j, int k) -> S {
+        S v = ld(z, idx);
+        if (MODE == 1) v += ld(zc, ((unsigned)(k >> 1) * cd.ny + (j >> 1)) * cd.nx + (i >> 1));
+        return v;
+    };
+    auto pre = [&](unsigned c) -> S { return ld(r, c); };
+    double acc = 0.0;
+    march<Coef, S, true>(q, cf, k0, k1, fld, pre,
+                         [&](int, unsigned c, const Nbr7<S>& R, const Nbr7<S>& X, S rc) {
+        S bl[3], bh[3], dg;
+        faces7(R, bl, bh);
+        const S az = apply7(bl, bh, X, ih2, dg);
+        if (q.valid) {
+            const S out = X.c + omega * (rc - az) * recip(dg);
+            st(zt, c, out);
+            if (MODE == 2) acc += (double)rc * (double)out;
+        }
+    });
+    if (MODE == 2) {
+        double v[1] = {acc};
+        block_partials<1>(v, partials);
+    }
+}
+
+// first sweep from zero: z = omega r / d; UPD: first the PCG update
+// x += alpha p, r -= alpha q with <r, r> to the partials
+template <typename S, typename X>
+struct FirstPre {
+    S r, q, p;
+    X x;
+};
+
+template <typename Coef, typename S, typename X, int UPD>
+__global__ __launch_bounds__(BLOCK) void k_fz_first(Dims d, int kz, S ih2, S omega, Coef cf,
+                                                    X* __restrict__ x, S* __restrict__ r,
+                                                    const S* __restrict__ p,
+                                                    const S* __restrict__ qv, S* __restrict__ z,
+                                                    const SolverScalars* __restrict__ sc,
+                                                    double* __restrict__ partials) {
+    if (sc->done) return;
+    Col q;
+    q.init(d, kz);
+    const int k0 = q.kslab * kz, k1 = min(k0 + kz, d.nz);
+    const double alpha = UPD ? sc->alpha : 0.0;
+    auto none = [](unsigned, int, int, int) { return S(0); };
+    auto pre = [&](unsigned c) {
+        FirstPre<S, X> e;
+        e.r = ld(r, c);
+        if (UPD) {
+            e.q = ld(qv, c);
+            e.p = ld(p, c);
+            e.x = ld(x, c);
+        } else {
+            e.q = e.p = S(0);
+            e.x = X(0);
+        }
+        return e;
+    };
+    double acc = 0.0;
+    march<Coef, S, false>(q, cf, k0, k1, none, pre,
+                          [&](int, unsigned c, const Nbr7<S>& R, const Nbr7<S>&, const FirstPre<S, X>& e) {
+        S bl[3], bh[3];
+        faces7(R, bl, bh);
+        const S dg = (bl[0] + bh[0] + bl[1] + bh[1] + bl[2] + bh[2]) * ih2;
+        if (q.valid) {
+            S rn = e.r;
+            if (UPD) {
+                st(x, c, X((double)e.x + alpha * (double)e.p));
+                rn = S((double)rn - alpha * (double)e.q);
+                st(r, c, rn);
+                acc += (double)rn * (double)rn;
+            }
+            st(z, c, omega * rn * recip(dg));
+        }
+    });
+    if (UPD) {
+        double v[1] = {acc};
+        block_partials<1>(v, partials);
+    }
+}
+
+// p = z + beta p_old (first: p = z), q = A p, <p, q>
+template <typename Coef, typename S>
+__global__ __launch_bounds__(BLOCK) void k_fz_apply(Dims d, int kz, S ih2, Coef cf, int first,
+                                                    const S* __restrict__ z,
+                                                    const S* __restrict__ pold,
+                                                    S* __restrict__ pnew, S* __restrict__ qv,
+                                                    const SolverScalars* __restrict__ sc,
+                                                    double* __restrict__ partials) {
+    if (sc->done) return;
+    Col q;
+    q.init(d, kz);
+    const int k0 = q.kslab * kz, k1 = min(k0 + kz, d.nz);
+    const S beta = first ? S(0) : S(sc->beta);
+    auto fld = [&](unsigned idx, int, int, int) -> S {
+        return first ? ld(z, idx) : ld(z, idx) + beta * ld(pold, idx);
+    };
+    auto pre = [](unsigned) { return NoPre{}; };
+    double acc = 0.0;
+    march<Coef, S, true>(q, cf, k0, k1, fld, pre,
+                         [&](int, unsigned c, const Nbr7<S>& R, const Nbr7<S>& X, NoPre) {
+        S bl[3], bh[3], dg;
+        faces7(R, bl, bh);
+        const S aq = apply7(bl, bh, X, ih2, dg);
+        if (q.valid) {
+            st(pnew, c, X.c);
+            st(qv, c, aq);
+            acc += (double)X.c * (double)aq;
+        }
+    });
+    double v[1] = {acc};
+    block_partials<1>(v, partials);
+}
+
+// coarse rhs = mean over the 2x2x2 children of (r - A z); kz even.  z pairs
+// summed in registers, x pairs by a lane shuffle, y pairs through LDS.
+template <typename Coef, typename S>
+__global__ __launch_bounds__(BLOCK) void k_fz_restrict(Dims d, Dims cd, int kz, S ih2, Coef cf,
+                                                       const S* __restrict__ r,
+                                                       const S* __restrict__ z,
+                                                       S* __restrict__ rc,
+                                                       const SolverScalars* __restrict__ sc) {
+    if (sc->done) return;
+    __shared__ S sh[BY][BX];
+    Col q;
+    q.init(d, kz);
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int k0 = q.kslab * kz, k1 = min(k0 + kz, d.nz);
+    auto fld = [&](unsigned idx, int, int, int) -> S { return ld(z, idx); };
+    auto pre = [&](unsigned c) -> S { return ld(r, c); };
+    const unsigned cmax = (unsigned)(cd.nx * cd.ny * cd.nz - 1);
+    S pair = S(0);
+    march<Coef, S, true>(q, cf, k0, k1, fld, pre,
+                         [&](int k, unsigned, const Nbr7<S>& R, const Nbr7<S>& X, S rv) {
+        S bl[3], bh[3], dg;
+        faces7(R, bl, bh);
+        const S az = apply7(bl, bh, X, ih2, dg);
+        pair += q.valid ? rv - az : S(0);
+        if (k & 1) {
+            S v = pair + __shfl_xor(pair, 1, 64);
+            sh[ty][tx] = v;
+            __syncthreads();
+            if (q.valid && (tx & 1) == 0 && (ty & 1) == 0) {
+                const S s = sh[ty][tx] + sh[ty + 1][tx];
+                const unsigned cc = ((unsigned)(k >> 1) * cd.ny + (q.j >> 1)) * cd.nx + (q.i >> 1);
+                st(rc, min(cc, cmax), s * S(0.125));
+            }
+            __syncthreads();
+            pair = S(0);
+        }
+    });
+}
+
+// r = -(b - mean) - A x (x FP64 read in precision S), stored as R;
+// |f|^2 -> region 0, |r|^2 -> region 1
+template <typename Coef, typename S, typename R>
+__global__ __launch_bounds__(BLOCK) void k_fz_resid(Dims d, int kz, S ih2, Coef cf,
+                                                    const double* __restrict__ b,
+                                                    const double* __restrict__ x,
+                                                    R* __restrict__ r,
+                                                    const SolverScalars* __restrict__ sc,
+                                                    double* __restrict__ partials, long stride) {
+    Col q;
+    q.init(d, kz);
+    const int k0 = q.kslab * kz, k1 = min(k0 + kz, d.nz);
+    const double mean = sc->mean;
+    auto fld = [&](unsigned idx, int, int, int) -> S { return S(ld(x, idx)); };
+    auto pre = [&](unsigned c) -> double { return ld(b, c); };
+    double v[2] = {0.0, 0.0};
+    march<Coef, S, true>(q, cf, k0, k1, fld, pre,
+                         [&](int, unsigned c, const Nbr7<S>& Rh, const Nbr7<S>& X, double bc) {
+        S bl[3], bh[3], dg;
+        faces7(Rh, bl, bh);
+        const S ax = apply7(bl, bh, X, ih2, dg);
+        if (q.valid) {
+            const double f = -(bc - mean);
+            const double rr = f - (double)ax;
+            st(r, c, R(rr));
+            v[0] += f * f;
+            v[1] += rr * rr;
+        }
+    });
+    block_partials_2r(v, partials, stride);
+}
+
 // ================================================================== host driver
+
+static unsigned vgrid(long N) {
+    const long nb = (N + BLOCK - 1) / BLOCK;
+    return (unsigned)(nb < VBLOCKS ? nb : VBLOCKS);
+}
 
 template <typename T, typename S>
 struct Solver {
@@ -504,7 +900,16 @@ struct Solver {
 
     CoefPhi<T, S> coef_phi(const void* phi) const {
         const Phys P = phys_of(c);
-        return CoefPhi<T, S>{static_cast<const T*>(phi), S(P.rho2), S(P.rho1 - P.rho2), P.clamp};
+        const S inf = std::numeric_limits<S>::infinity();
+        return CoefPhi<T, S>{static_cast<const T*>(phi), S(0.5 * P.rho2), S(0.5 * (P.rho1 - P.rho2)),
+                             P.clamp ? S(0) : -inf, P.clamp ? S(1) : inf};
+    }
+    // fine-level coefficients: the half density computed by half_rho()
+    CoefRho<S> coef_fine() const { return CoefRho<S>{tp<S>(c->rhoh)}; }
+    void half_rho(const void* phi) {
+        prof_begin(c, PC_VECTOR, (double)c->N * (sizeof(T) + sizeof(S)));
+        k_half_rho<T, S><<<vgrid(c->N), BLOCK, 0, c->stream>>>(c->N, coef_phi(phi), tp<S>(c->rhoh));
+        prof_end(c);
     }
     CoefStored<S> coef(int l) const {
         return CoefStored<S>{tp<S>(c->lv[l].beta[0]), tp<S>(c->lv[l].beta[1]),
@@ -518,13 +923,32 @@ struct Solver {
     // fields moved by the coefficients: phi on the fine level, DIM arrays below
     double cfields(int l) const { return l == 0 ? (double)sizeof(T) / sizeof(S) : (double)dim; }
     long nbl(int l) const { return nblocks_of(c->lv[l].n); }
+    // level 0 in 3D runs the z-marching kernels: kz planes per block
+    bool march0() const { return dim == 3 && c->march; }
+    int kz() const {
+        const int nz = c->lv[0].n[2];
+        for (int k : {8, 4, 2})
+            if (nz % k == 0) return k;
+        return 1;
+    }
+    dim3 mgrid() const {
+        const Level& L = c->lv[0];
+        return tile_grid((L.n[0] + BX - 1) / BX, (L.n[1] + BY - 1) / BY, L.n[2] / kz());
+    }
+    // blocks of the level-0 kernels that emit partial sums
+    long nb0() const {
+        if (!march0()) return nbl(0);
+        const dim3 g = mgrid();
+        return (long)g.x * g.y * g.z;
+    }
 
     template <int DIM>
     void build_betas_t(const void* phi) {
         const dim3 b(BX, BY);
+        half_rho(phi);
         if (c->nlev < 2) return;
-        k_beta_from_phi<T, S, DIM><<<grid(1), b, 0, c->stream>>>(
-            dims(0), dims(1), coef_phi(phi), tp<S>(c->lv[1].beta[0]), tp<S>(c->lv[1].beta[1]),
+        k_beta_from_phi<CoefRho<S>, S, DIM><<<grid(1), b, 0, c->stream>>>(
+            dims(0), dims(1), coef_fine(), tp<S>(c->lv[1].beta[0]), tp<S>(c->lv[1].beta[1]),
             tp<S>(c->lv[1].beta[2]));
         for (int l = 2; l < c->nlev; ++l)
             k_beta_coarsen<S, DIM><<<grid(l), b, 0, c->stream>>>(
@@ -538,8 +962,8 @@ struct Solver {
     dim3 restrict_block() const { return dim == 3 ? dim3(BX, 2, 2) : dim3(BX, 4, 1); }
     dim3 restrict_grid(int l) const {
         const Level& L = c->lv[l];
-        return dim == 3 ? dim3((L.n[0] + BX - 1) / BX, (L.n[1] + 1) / 2, (L.n[2] + 1) / 2)
-                        : dim3((L.n[0] + BX - 1) / BX, (L.n[1] + 3) / 4, 1);
+        return dim == 3 ? tile_grid((L.n[0] + BX - 1) / BX, (L.n[1] + 1) / 2, (L.n[2] + 1) / 2)
+                        : tile_grid((L.n[0] + BX - 1) / BX, (L.n[1] + 3) / 4, 1);
     }
 
     // Pre-smoothing and restriction at level l.  The first sweep writes z (A),
@@ -550,8 +974,28 @@ struct Solver {
         const dim3 b(BX, BY);
         S* z = tp<S>(L.z);
         S* zt = tp<S>(L.zt);
-        const S* r = tp<S>(L.r);
+        S* r = tp<S>(L.r);
         const double cfl = cfields(l);
+        if constexpr (std::is_same<Coef, CoefRho<S>>::value) {
+            if (DIM == 3 && c->march) {
+                Level& Lc = c->lv[l + 1];
+                if (!first_done) {
+                    prof_begin(c, PC_F_FIRST0, fb(l, 2 + cfl));
+                    k_fz_first<Coef, S, S, 0><<<mgrid(), b, 0, c->stream>>>(dims(0), kz(), ih2(0), omega, cf, nullptr,
+                                                                       r, nullptr, nullptr, z, c->scal, nullptr);
+                    prof_end(c);
+                }
+                prof_begin(c, PC_F_SWEEP, fb(l, 3 + cfl));
+                k_fz_jac<Coef, S, 0><<<mgrid(), b, 0, c->stream>>>(dims(0), dims(1), kz(), ih2(0), omega, cf, r, z,
+                                                               nullptr, zt, c->scal, nullptr);
+                prof_end(c);
+                prof_begin(c, PC_F_RESTRICT, fb(l, 2 + cfl) + (double)Lc.N * sizeof(S));
+                k_fz_restrict<Coef, S><<<mgrid(), b, 0, c->stream>>>(dims(0), dims(1), kz(), ih2(0), cf, r, zt,
+                                                                 tp<S>(Lc.r), c->scal);
+                prof_end(c);
+                return;
+            }
+        }
         if (!first_done) {
             prof_begin(c, fine ? PC_F_FIRST0 : PC_COARSE_LEVELS, fb(l, 2 + cfl));
             k_jac_first<Coef, S, DIM><<<grid(l), b, 0, c->stream>>>(dims(l), ih2(l), omega, cf, r, z, c->scal);
@@ -578,6 +1022,24 @@ struct Solver {
         const S* r = tp<S>(L.r);
         const double cb = (double)c->lv[l + 1].N * sizeof(S);
         const double cfl = cfields(l);
+        if constexpr (std::is_same<Coef, CoefRho<S>>::value) {
+            if (DIM == 3 && c->march) {
+                prof_begin(c, PC_F_PROLONG, fb(l, 3 + cfl) + cb);
+                k_fz_jac<Coef, S, 1><<<mgrid(), b, 0, c->stream>>>(dims(0), dims(1), kz(), ih2(0), omega, cf, r, zt,
+                                                               zc, z, c->scal, nullptr);
+                prof_end(c);
+                prof_begin(c, PC_F_SWEEPDOT, fb(l, 3 + cfl));
+                if (dot)
+                    k_fz_jac<Coef, S, 2><<<mgrid(), b, 0, c->stream>>>(dims(0), dims(1), kz(), ih2(0), omega, cf, r,
+                                                                   z, nullptr, zt, c->scal,
+                                                                   c->partials + c->max_blocks);
+                else
+                    k_fz_jac<Coef, S, 0><<<mgrid(), b, 0, c->stream>>>(dims(0), dims(1), kz(), ih2(0), omega, cf, r,
+                                                                   z, nullptr, zt, c->scal, nullptr);
+                prof_end(c);
+                return;
+            }
+        }
         prof_begin(c, fine ? PC_F_PROLONG : PC_COARSE_LEVELS, fb(l, 3 + cfl) + cb);
         k_jac<Coef, S, DIM, 1, 0><<<grid(l), b, 0, c->stream>>>(dims(l), dims(l + 1), ih2(l), omega, cf, r, zt,
                                                                  zc, z, c->scal, nullptr);
@@ -616,18 +1078,35 @@ struct Solver {
     // dot: the last sweep emits <r, z> partials to region 1.
     template <int DIM>
     void vcycle_t(const void* phi, bool first_done) {
-        const CoefPhi<T, S> cf = coef_phi(phi);
+        const CoefRho<S> cf = coef_fine();
         Level& L = c->lv[0];
+        if (c->nlev == 1 && DIM == 3 && c->march) {
+            // no coarsening possible: two Jacobi sweeps (still symmetric)
+            const dim3 b(BX, BY);
+            if (!first_done) {
+                prof_begin(c, PC_F_FIRST0, fb(0, 2 + cfields(0)));
+                k_fz_first<CoefRho<S>, S, S, 0><<<mgrid(), b, 0, c->stream>>>(dims(0), kz(), ih2(0), omega, cf, nullptr,
+                                                                   tp<S>(L.r), nullptr, nullptr, tp<S>(L.z),
+                                                                   c->scal, nullptr);
+                prof_end(c);
+            }
+            prof_begin(c, PC_F_SWEEPDOT, fb(0, 3 + cfields(0)));
+            k_fz_jac<CoefRho<S>, S, 2><<<mgrid(), b, 0, c->stream>>>(dims(0), dims(0), kz(), ih2(0), omega, cf, tp<S>(L.r),
+                                                           tp<S>(L.z), nullptr, tp<S>(L.zt), c->scal,
+                                                           c->partials + c->max_blocks);
+            prof_end(c);
+            return;
+        }
         if (c->nlev == 1) {
             // no coarsening possible: two Jacobi sweeps (still symmetric)
             if (!first_done) {
                 prof_begin(c, PC_F_FIRST0, fb(0, 2 + cfields(0)));
-                k_jac_first<CoefPhi<T, S>, S, DIM><<<grid(0), dim3(BX, BY), 0, c->stream>>>(
+                k_jac_first<CoefRho<S>, S, DIM><<<grid(0), dim3(BX, BY), 0, c->stream>>>(
                     dims(0), ih2(0), omega, cf, tp<S>(L.r), tp<S>(L.z), c->scal);
                 prof_end(c);
             }
             prof_begin(c, PC_F_SWEEPDOT, fb(0, 3 + cfields(0)));
-            k_jac<CoefPhi<T, S>, S, DIM, 0, 1><<<grid(0), dim3(BX, BY), 0, c->stream>>>(
+            k_jac<CoefRho<S>, S, DIM, 0, 1><<<grid(0), dim3(BX, BY), 0, c->stream>>>(
                 dims(0), dims(0), ih2(0), omega, cf, tp<S>(L.r), tp<S>(L.z), nullptr, tp<S>(L.zt),
                 c->scal, c->partials + c->max_blocks);
             prof_end(c);
@@ -645,17 +1124,31 @@ struct Solver {
     // first pre-smoothing sweep
     template <int DIM, typename X>
     void apply_update(const void* phi, int first, X* x) {
-        const CoefPhi<T, S> cf = coef_phi(phi);
+        const CoefRho<S> cf = coef_fine();
         const dim3 b(BX, BY);
         S* pold = tp<S>(c->pv);
         S* pnew = tp<S>(c->pv2);
+        if (DIM == 3 && c->march) {
+            prof_begin(c, PC_F_APPLY, fb(0, (first ? 1 : 2) + 2 + cfields(0)));
+            k_fz_apply<CoefRho<S>, S><<<mgrid(), b, 0, c->stream>>>(dims(0), kz(), ih2(0), cf, first, tp<S>(c->lv[0].zt),
+                                                          pold, pnew, tp<S>(c->qv), c->scal, c->partials);
+            prof_end(c);
+            (void)finalize2(c, (int)nb0(), 0, FIN_ALPHA, 0.0);
+            prof_begin(c, PC_F_FIRST, fb(0, 5 + cfields(0)) + 2.0 * c->N * sizeof(X));
+            k_fz_first<CoefRho<S>, S, X, 1><<<mgrid(), b, 0, c->stream>>>(dims(0), kz(), ih2(0), omega, cf, x,
+                                                               tp<S>(c->lv[0].r), pnew, tp<S>(c->qv),
+                                                               tp<S>(c->lv[0].z), c->scal, c->partials);
+            prof_end(c);
+            std::swap(c->pv, c->pv2);
+            return;
+        }
         prof_begin(c, PC_F_APPLY, fb(0, (first ? 1 : 2) + 2 + cfields(0)));
-        k_apply<CoefPhi<T, S>, S, DIM><<<grid(0), b, 0, c->stream>>>(
+        k_apply<CoefRho<S>, S, DIM><<<grid(0), b, 0, c->stream>>>(
             dims(0), ih2(0), cf, first, tp<S>(c->lv[0].zt), pold, pnew, tp<S>(c->qv), c->scal, c->partials);
         prof_end(c);
         (void)finalize2(c, (int)nbl(0), 0, FIN_ALPHA, 0.0);
         prof_begin(c, PC_F_FIRST, fb(0, 5 + cfields(0)) + 2.0 * c->N * sizeof(X));
-        k_jac_first_update<CoefPhi<T, S>, S, X, DIM><<<grid(0), b, 0, c->stream>>>(
+        k_jac_first_update<CoefRho<S>, S, X, DIM><<<grid(0), b, 0, c->stream>>>(
             dims(0), ih2(0), omega, cf, x, tp<S>(c->lv[0].r), pnew, tp<S>(c->qv), tp<S>(c->lv[0].z),
             c->scal, c->partials);
         prof_end(c);
@@ -667,7 +1160,7 @@ struct Solver {
     template <typename X>
     hipError_t pcg(const void* phi, X* x, int maxit, int check_every) {
         vcycle(phi, false);                                       // z = M r, <r,z>
-        (void)finalize2(c, 0, (int)nbl(0), FIN_RZ0, 0.0);
+        (void)finalize2(c, 0, (int)nb0(), FIN_RZ0, 0.0);
         int it = 0;
         bool first = true;
         while (it < maxit) {
@@ -676,7 +1169,7 @@ struct Solver {
                 else apply_update<3, X>(phi, first ? 1 : 0, x);
                 first = false;
                 vcycle(phi, true);
-                (void)finalize2(c, (int)nbl(0), (int)nbl(0), FIN_BETA, 0.0);
+                (void)finalize2(c, (int)nb0(), (int)nb0(), FIN_BETA, 0.0);
             }
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
@@ -690,24 +1183,24 @@ struct Solver {
         return hipGetLastError();
     }
 
-    template <typename R>
-    void residual(const void* phi, R* r) {
-        const CoefPhi<T, S> cf = coef_phi(phi);
+    // r = f - A x with the coefficient policy cf (FP64 path: the fine-level
+    // half densities; mixed path: FP64 coefficients straight from phi)
+    template <typename R, typename Coef>
+    void residual(Coef cf, R* r) {
         prof_begin(c, PC_RESID, (double)c->N * (8 + 8 + sizeof(T) + sizeof(R)));
-        if (dim == 2)
-            k_resid<T, S, R, 2><<<grid(0), dim3(BX, BY), 0, c->stream>>>(dims(0), ih2(0), cf, c->b, c->p, r,
-                                                                        c->scal, c->partials, c->max_blocks);
+        if (dim == 3 && c->march)
+            k_fz_resid<Coef, S, R><<<mgrid(), dim3(BX, BY), 0, c->stream>>>(dims(0), kz(), ih2(0), cf, c->b, c->p, r,
+                                                                           c->scal, c->partials, c->max_blocks);
+        else if (dim == 3)
+            k_resid<Coef, S, R, 3><<<grid(0), dim3(BX, BY), 0, c->stream>>>(dims(0), ih2(0), cf, c->b, c->p, r,
+                                                                           c->scal, c->partials, c->max_blocks);
         else
-            k_resid<T, S, R, 3><<<grid(0), dim3(BX, BY), 0, c->stream>>>(dims(0), ih2(0), cf, c->b, c->p, r,
-                                                                        c->scal, c->partials, c->max_blocks);
+            k_resid<Coef, S, R, 2><<<grid(0), dim3(BX, BY), 0, c->stream>>>(dims(0), ih2(0), cf, c->b, c->p, r,
+                                                                           c->scal, c->partials, c->max_blocks);
         prof_end(c);
     }
 };
 
-static unsigned vgrid(long N) {
-    const long nb = (N + BLOCK - 1) / BLOCK;
-    return (unsigned)(nb < VBLOCKS ? nb : VBLOCKS);
-}
 
 hipError_t launch_rhs_mean(tpf_ctx* c) {
     const unsigned nb = vgrid(c->N);
@@ -741,14 +1234,13 @@ tpf_status poisson_solve(tpf_ctx* c, const void* phi, int* iters, double* relres
     const double rtol = c->P.poisson_rtol;
     const int maxit = c->P.poisson_maxit;
     const int check = 4;
-    const int nb = (int)nblocks_of(c->n);
     SolverScalars s;
     hipError_t e;
     if (!c->mixed) {
         Solver<double, double> sv{c, c->dim, omega_of(c->dim)};
         sv.build_betas(phi);
-        sv.residual<double>(phi, tp<double>(c->lv[0].r));
-        (void)finalize2(c, nb, nb, FIN_INIT, rtol * rtol);
+        sv.residual<double>(sv.coef_fine(), tp<double>(c->lv[0].r));
+        (void)finalize2(c, (int)sv.nb0(), (int)sv.nb0(), FIN_INIT, rtol * rtol);
         e = sv.pcg<double>(phi, c->p, maxit, check);
         if (e != hipSuccess) return hip_fail(e, "FP64 PCG");
         e = remove_mean(c, c->p);
@@ -776,8 +1268,8 @@ tpf_status poisson_solve(tpf_ctx* c, const void* phi, int* iters, double* relres
     int total = 0;
     const int max_outer = 12;
     for (int o = 0; o < max_outer; ++o) {
-        s64.residual<float>(phi, tp<float>(c->lv[0].r));       // FP64 residual, FP64 beta
-        (void)finalize2(c, nb, nb, FIN_INIT, rtol * rtol);
+        s64.residual<float>(s64.coef_phi(phi), tp<float>(c->lv[0].r));   // FP64 residual, FP64 beta
+        (void)finalize2(c, (int)s64.nb0(), (int)s64.nb0(), FIN_INIT, rtol * rtol);
         tpf_status st = read_scalars(c, &s);
         if (st != TPF_OK) return st;
         if (!std::isfinite(s.ff) || !std::isfinite(s.rr)) {
