@@ -223,8 +223,10 @@ static void init_geometry(tpf_ctx* c, const tpf_params* P) {
     c->tsz = c->mixed ? 4 : 8;
     const char* m = std::getenv("TPF_MARCH");
     c->march = (m && m[0] == '0') ? 0 : 1;
+    const char* tl = std::getenv("TPF_TAIL");
+    c->no_tail = (tl && tl[0] == '0') ? 1 : 0;
     const char* xt = std::getenv("TPF_XCD_TILES");
-    g_xcd_tiles = (xt && xt[0] == '1') ? 1 : 0;
+    g_xcd_tiles = (xt && xt[0] == '0') ? 0 : 1;
     c->nlev = plan_levels(c);
 }
 

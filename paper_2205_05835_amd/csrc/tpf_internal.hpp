@@ -70,6 +70,7 @@ struct tpf_ctx {
     double h;
     int mixed;           // 0: FP64, 1: FP32 state + FP64 pressure
     int march;           // 3D level 0 uses the z-marching kernels (TPF_MARCH=0 disables)
+    int no_tail;         // TPF_TAIL=0: run every level with separate kernels
     size_t tsz;          // bytes per state value
     hipStream_t stream;
     char* ws;
@@ -175,7 +176,7 @@ inline dim3 grid_of(const int n[3]) {
     return tile_grid((n[0] + BX - 1) / BX, (n[1] + BY - 1) / BY, n[2]);
 }
 inline long nblocks_of(const int n[3]) { return (long)grid_of(n).x; }
-extern int g_xcd_tiles;   // host copy of the tiling choice (TPF_XCD_TILES=1 enables)
+extern int g_xcd_tiles;   // XCD slab tiling of the block grids (TPF_XCD_TILES=0 disables)
 inline Dims dims_of(const int n[3]) { return Dims{n[0], n[1], n[2], g_xcd_tiles}; }
 Phys phys_of(const tpf_ctx* c);
 

@@ -44,7 +44,15 @@ static inline T* tp(void* p) { return static_cast<T*>(p); }
 // reciprocal in FP32 (inner solver of the mixed path)
 __device__ __forceinline__ double two_over(double s) { return 2.0 / s; }
 __device__ __forceinline__ float two_over(float s) { return 2.0f * __builtin_amdgcn_rcpf(s); }
-__device__ __forceinline__ double recip(double s) { return 1.0 / s; }
+// FP64: hardware reciprocal refined by two Newton steps (error within one
+// ulp of 1/s, far cheaper than the IEEE divide sequence)
+__device__ __forceinline__ double recip(double s) {
+    double y = __builtin_amdgcn_rcp(s);
+    double e = fma(-s, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-s, y, 1.0);
+    return fma(y, e, y);
+}
 __device__ __forceinline__ float recip(float s) { return __builtin_amdgcn_rcpf(s); }
 
 // block sums of two values to region 0 and region 1 (stride apart)
@@ -363,6 +371,156 @@ __global__ __launch_bounds__(1024) void k_coarse(Dims d, S ih2, S omega, int swe
     }
     if (src != z) {
         for (long q = threadIdx.x; q < N; q += blockDim.x) z[q] = src[q];
+    }
+}
+
+// ---------------------------------------------------------------- LDS tail
+// The last levels of the V-cycle (every level from `first` down, at most
+// TAIL_MAX_LEVELS, all of them together small enough for LDS) run in one
+// 1024-thread workgroup: r, z and zt of every tail level live in LDS, the
+// face coefficients stay in global memory (L2).  The operations and their
+// order are those of the multi-kernel levels above (two damped Jacobi sweeps
+// before and after, averaging restriction, piecewise-constant prolongation,
+// fixed Jacobi sweeps on the coarsest grid), so the preconditioner remains
+// the same symmetric linear operator; only launches are saved.
+constexpr int TAIL_MAX_LEVELS = 8;
+constexpr size_t TAIL_LDS_BYTES = 64 * 1024;
+
+struct TailDesc {
+    int nlev;
+    int n[TAIL_MAX_LEVELS][3];
+    int off[TAIL_MAX_LEVELS];          // element offset of level l's r; z, zt follow
+    double ih2[TAIL_MAX_LEVELS];
+    const void* beta[TAIL_MAX_LEVELS][3];
+};
+
+template <typename S, int DIM>
+__global__ __launch_bounds__(1024) void k_tail(TailDesc D, S omega, S omega_c, int sweeps,
+                                               const S* __restrict__ rin, S* __restrict__ zout,
+                                               const SolverScalars* __restrict__ sc) {
+    if (sc->done) return;
+    extern __shared__ __align__(16) unsigned char tail_smem[];
+    S* L = reinterpret_cast<S*>(tail_smem);
+    const int t = threadIdx.x, T = blockDim.x;
+    auto dims = [&](int l) { return Dims{D.n[l][0], D.n[l][1], D.n[l][2], 0}; };
+    auto ncell = [&](int l) { return D.n[l][0] * D.n[l][1] * D.n[l][2]; };
+    auto cell = [&](int l, int q) {
+        const Dims d = dims(l);
+        return make_cell(d, q % d.nx, (q / d.nx) % d.ny, q / (d.nx * d.ny));
+    };
+    auto coef = [&](int l) {
+        return CoefStored<S>{static_cast<const S*>(D.beta[l][0]), static_cast<const S*>(D.beta[l][1]),
+                             static_cast<const S*>(D.beta[l][2])};
+    };
+    // one damped Jacobi sweep out = X + w (r - A X) / d, X(a, s) from get
+    auto sweep = [&](int l, S w, auto get, S* out) {
+        const int N = ncell(l);
+        const S* r = L + D.off[l];
+        const S ih2 = S(D.ih2[l]);
+        const CoefStored<S> cf = coef(l);
+        for (int q = t; q < N; q += T) {
+            const Cell C = cell(l, q);
+            S bl[3], bh[3], dg;
+            cf.template faces<DIM>(C, bl, bh);
+            auto X = [&](int a, int s) { return get(C, a, s); };
+            const S xc = get(C, 0, 0);
+            const S az = apply_at<S, DIM>(bl, bh, X, xc, ih2, dg);
+            out[q] = xc + w * (r[q] - az) / dg;
+        }
+        __syncthreads();
+    };
+    {
+        const int N0 = ncell(0);
+        for (int q = t; q < N0; q += T) L[D.off[0] + q] = rin[q];
+        __syncthreads();
+    }
+    // ---- down
+    for (int l = 0; l + 1 < D.nlev; ++l) {
+        const int N = ncell(l);
+        S* r = L + D.off[l];
+        S* z = r + N;
+        S* zt = z + N;
+        const S ih2 = S(D.ih2[l]);
+        const CoefStored<S> cf = coef(l);
+        for (int q = t; q < N; q += T) {            // z = omega r / d
+            const Cell C = cell(l, q);
+            S bl[3], bh[3], dg = S(0);
+            cf.template faces<DIM>(C, bl, bh);
+            for (int a = 0; a < DIM; ++a) dg += bl[a] + bh[a];
+            z[q] = omega * r[q] / (dg * ih2);
+        }
+        __syncthreads();
+        sweep(l, omega, [&](const Cell& C, int a, int s) { return z[s == 0 ? C.id : C.nb(a, s)]; }, zt);
+        // restriction of r - A zt into the next level's r
+        const Dims dc = dims(l + 1);
+        const int Nc = ncell(l + 1);
+        S* rc = L + D.off[l + 1];
+        const Dims df = dims(l);
+        for (int Q = t; Q < Nc; Q += T) {
+            const int I = Q % dc.nx, J = (Q / dc.nx) % dc.ny, K = Q / (dc.nx * dc.ny);
+            S s = S(0);
+            for (int dk = 0; dk < (DIM == 3 ? 2 : 1); ++dk)
+                for (int dj = 0; dj < 2; ++dj)
+                    for (int di = 0; di < 2; ++di) {
+                        const Cell C = make_cell(df, 2 * I + di, 2 * J + dj, DIM == 3 ? 2 * K + dk : 0);
+                        S bl[3], bh[3], dg;
+                        cf.template faces<DIM>(C, bl, bh);
+                        auto X = [&](int a, int s2) { return zt[C.nb(a, s2)]; };
+                        s += r[C.id] - apply_at<S, DIM>(bl, bh, X, zt[C.id], ih2, dg);
+                    }
+            rc[Q] = s * S(1.0 / (DIM == 3 ? 8 : 4));
+        }
+        __syncthreads();
+    }
+    // ---- coarsest: fixed Jacobi sweeps from zero, result in zt
+    {
+        const int l = D.nlev - 1;
+        const int N = ncell(l);
+        S* r = L + D.off[l];
+        S* src = r + 2 * N;   // zt
+        S* dst = r + N;       // z
+        for (int q = t; q < N; q += T) src[q] = S(0);
+        __syncthreads();
+        for (int s = 0; s < sweeps; ++s) {
+            const S* in = src;
+            sweep(l, omega_c, [&](const Cell& C, int a, int s2) { return in[s2 == 0 ? C.id : C.nb(a, s2)]; }, dst);
+            S* tmp = src;
+            src = dst;
+            dst = tmp;
+        }
+        if (src != r + 2 * N) {
+            for (int q = t; q < N; q += T) r[2 * N + q] = src[q];
+            __syncthreads();
+        }
+    }
+    // ---- up
+    for (int l = D.nlev - 2; l >= 0; --l) {
+        const int N = ncell(l);
+        S* r = L + D.off[l];
+        S* z = r + N;
+        S* zt = z + N;
+        const Dims dc = dims(l + 1);
+        const S* zc = L + D.off[l + 1] + 2 * ncell(l + 1);
+        // Z = zt + P zc, then z = Z + omega (r - A Z) / d
+        auto Zp = [&](const Cell& C, int a, int s) -> S {
+            int i = C.i, j = C.j, k = C.k;
+            const Dims df = dims(l);
+            if (s != 0) {
+                if (a == 0) i = wrapc(i + s, df.nx);
+                else if (a == 1) j = wrapc(j + s, df.ny);
+                else k = wrapc(k + s, df.nz);
+            }
+            const int idx = (k * df.ny + j) * df.nx + i;
+            const int pc = ((DIM == 3 ? k >> 1 : 0) * dc.ny + (j >> 1)) * dc.nx + (i >> 1);
+            return zt[idx] + zc[pc];
+        };
+        sweep(l, omega, Zp, z);
+        sweep(l, omega, [&](const Cell& C, int a, int s) { return z[s == 0 ? C.id : C.nb(a, s)]; }, zt);
+    }
+    {
+        const int N0 = ncell(0);
+        const S* zt0 = L + D.off[0] + 2 * N0;
+        for (int q = t; q < N0; q += T) zout[q] = zt0[q];
     }
 }
 
@@ -1055,10 +1213,50 @@ struct Solver {
         prof_end(c);
     }
 
+    // first level of the LDS tail (-1: none): the shallowest level >= 1 from
+    // which all remaining levels fit in TAIL_LDS_BYTES
+    int tail_first() const {
+        if (c->no_tail || c->nlev < 2) return -1;
+        size_t bytes = 0;
+        int first = -1;
+        for (int l = c->nlev - 1; l >= 1 && c->nlev - l <= TAIL_MAX_LEVELS; --l) {
+            bytes += 3 * (size_t)c->lv[l].N * sizeof(S);
+            if (bytes > TAIL_LDS_BYTES) break;
+            first = l;
+        }
+        return first;
+    }
+
+    template <int DIM>
+    const S* tail(int l0) {
+        TailDesc D;
+        D.nlev = c->nlev - l0;
+        int off = 0;
+        for (int q = 0; q < D.nlev; ++q) {
+            const Level& L = c->lv[l0 + q];
+            for (int a = 0; a < 3; ++a) {
+                D.n[q][a] = L.n[a];
+                D.beta[q][a] = L.beta[a];
+            }
+            D.off[q] = off;
+            off += 3 * (int)L.N;
+            D.ih2[q] = 1.0 / (L.h * L.h);
+        }
+        const Level& Ll = c->lv[c->nlev - 1];
+        const int mx = std::max(Ll.n[0], std::max(Ll.n[1], Ll.n[2]));
+        prof_begin(c, PC_COARSE_LEVELS, (double)off * sizeof(S));
+        k_tail<S, DIM><<<1, 1024, (size_t)off * sizeof(S), c->stream>>>(D, omega, S(0.8), 8 * mx,
+                                                                        tp<S>(c->lv[l0].r),
+                                                                        tp<S>(c->lv[l0].zt), c->scal);
+        prof_end(c);
+        return tp<S>(c->lv[l0].zt);
+    }
+
     // V-cycle from level l >= 1 (stored coefficients); the correction ends in zt
     template <int DIM>
     const S* vcycle_coarse(int l) {
         Level& L = c->lv[l];
+        if (l == tail_first()) return tail<DIM>(l);
         if (l == c->nlev - 1) {
             const int mx = std::max(L.n[0], std::max(L.n[1], L.n[2]));
             prof_begin(c, PC_COARSE_LEVELS, fb(l, 3));
