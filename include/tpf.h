@@ -6,8 +6,8 @@
  * field methods" (arXiv 2205.05835).  One time step advances the phase field
  * phi (Eq. 1 with a regularisation g of Table 1: CDI, SB or ISODI) and the
  * incompressible velocity u with a surface tension force on cell faces
- * (energy-based F = mu grad phi of Eq. 5 with mu of Eq. 2, or CSF, or the
- * localized CSF of Eq. 12), momentum advection and viscous diffusion, and a
+ * (energy-based F = mu grad phi of Eq. 4 with mu of Eq. 2, or CSF, or the
+ * localized CSF of Eq. 11), momentum advection and viscous diffusion, and a
  * variable-density pressure projection D(beta G p) = D f*, integrated with
  * classical RK4 on a uniform periodic staggered grid (Sec. 3, opening).
  *
@@ -52,7 +52,7 @@ typedef enum {
 } tpf_status;
 
 typedef enum { TPF_CDI = 0, TPF_SB = 1, TPF_ISODI = 2 } tpf_model;  /* Table 1 */
-typedef enum { TPF_EB = 0, TPF_CSF = 1, TPF_LCSF = 2 } tpf_force;   /* Eq. 5, CSF, Eq. 12 */
+typedef enum { TPF_EB = 0, TPF_CSF = 1, TPF_LCSF = 2 } tpf_force;   /* Eq. 4, CSF, Eq. 11 */
 typedef enum {
     TPF_FP64 = 0,        /* everything in FP64                                   */
     TPF_FP32_MIXED = 1   /* FP32 state, stencils and smoothers; FP64 pressure,

@@ -7,8 +7,8 @@ with the HIP library in ``paper_2205_05835_amd/``.
 
 Method: one time step of the two-phase solver of Mirjalili, Khanwale & Mani
 (arXiv 2205.05835) -- phase-field models of Table 1, chemical potential of
-Eq. 2, surface-tension forces (energy-based Eq. 5, CSF, localized CSF of
-Eq. 12), central second-order staggered-grid operators and classical RK4
+Eq. 2, surface-tension forces (energy-based Eq. 4, CSF, localized CSF of
+Eq. 11), central second-order staggered-grid operators and classical RK4
 (Sec. 3), with a variable-density pressure projection at every stage.
 
 Arrays are numpy float64, C order, shape ``(nz, ny, nx)`` in 3D and

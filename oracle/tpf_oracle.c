@@ -4,7 +4,7 @@
  * Computes one time step of the incompressible two-phase solver assessed in
  * Mirjalili, Khanwale & Mani (arXiv 2205.05835): a second-order phase-field
  * equation (Table 1: CDI, SB, ISODI), the chemical potential (Eq. 2), a
- * surface tension force (energy-based Eq. 5, CSF, or localized CSF Eq. 12),
+ * surface tension force (energy-based Eq. 4, CSF, or localized CSF Eq. 11),
  * momentum advection and diffusion and a variable-density pressure
  * projection, discretised with second-order finite differences on a
  * staggered periodic grid and integrated with classical RK4 (Sec. 3).
@@ -310,13 +310,13 @@ void ora_surface_force(const ora_params* P, const double* phi, double* F0,
             double gphi = opG(P, phi, i, j, k, a);
             double f;
             switch (P->force) {
-            case ORA_EB:   /* F = mu grad phi (Eq. 5), + sign on the momentum RHS */
+            case ORA_EB:   /* F = mu grad phi (Eq. 4), + sign on the momentum RHS */
                 f = opA(P, mu, i, j, k, a) * gphi;
                 break;
             case ORA_CSF:  /* F = sigma kappa grad phi */
                 f = P->sigma * opA(P, kappa, i, j, k, a) * gphi;
                 break;
-            case ORA_LCSF: /* F = sigma_hat kappa phi(1-phi) grad phi (Eq. 12) */
+            case ORA_LCSF: /* F = sigma_hat kappa phi(1-phi) grad phi (Eq. 11) */
                 f = sh_ * opA(P, kappa, i, j, k, a) * opA(P, w, i, j, k, a) * gphi;
                 break;
             default:       /* EB minus the gradient G(mu phi): -A(phi) G(mu) */

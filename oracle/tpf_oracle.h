@@ -22,8 +22,8 @@ extern "C" {
 #endif
 
 enum { ORA_CDI = 0, ORA_SB = 1, ORA_ISODI = 2 };          /* Table 1 */
-enum { ORA_EB = 0, ORA_CSF = 1, ORA_LCSF = 2,             /* Eq. 5, CSF, LCSF */
-       ORA_EB_GAUGE = 3 };  /* -A(phi) G(mu): Eq. 5 minus a face gradient (Eq. 8) */
+enum { ORA_EB = 0, ORA_CSF = 1, ORA_LCSF = 2,             /* Eq. 4, CSF, LCSF */
+       ORA_EB_GAUGE = 3 };  /* -A(phi) G(mu): Eq. 4 minus a face gradient (Eq. 7) */
 
 typedef struct {
     int dim;            /* 2 or 3 */

@@ -65,6 +65,8 @@ static void prof_flush(tpf_ctx* c) {
 void prof_begin(tpf_ctx* c, int cls, double bytes) {
     c->ev_open = 0;
     if (!(c->prof_mask & (1u << cls))) return;
+    c->prof_issued[cls] += 1;
+    c->prof_issued_bytes[cls] += bytes;
     if (c->ev_count == c->ev_cap) prof_flush(c);
     const int q = c->ev_count;
     c->ev_class[q] = cls;
@@ -591,6 +593,10 @@ tpf_status tpf_profile_enable(tpf_ctx* c, int32_t enable) {
             c->prof_ms[q] = 0;
             c->prof_launches[q] = 0;
             c->prof_bytes[q] = 0;
+            c->prof_issued[q] = 0;
+            c->prof_issued_bytes[q] = 0;
+            c->prof_noop[q] = 0;
+            c->prof_noop_bytes[q] = 0;
         }
     }
     return TPF_OK;
@@ -601,10 +607,11 @@ tpf_status tpf_profile_read(tpf_ctx* c, int32_t cls, const char** name, double* 
     if (!c || cls < 0 || cls >= NPROF) { set_error("bad profile class"); return TPF_EINVAL; }
     prof_flush(c);
     if (name) *name = kProfNames[cls];
+    const long work = c->prof_launches[cls] - c->prof_noop[cls];
     if (total_ms) *total_ms = c->prof_ms[cls];
-    if (launches) *launches = c->prof_launches[cls];
+    if (launches) *launches = work;
     if (bytes_per_launch)
-        *bytes_per_launch = c->prof_launches[cls] ? c->prof_bytes[cls] / c->prof_launches[cls] : 0.0;
+        *bytes_per_launch = work > 0 ? (c->prof_bytes[cls] - c->prof_noop_bytes[cls]) / work : 0.0;
     return TPF_OK;
 }
 

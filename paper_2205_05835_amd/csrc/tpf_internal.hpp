@@ -132,6 +132,18 @@ struct tpf_ctx {
     double prof_ms[tpf::NPROF];
     long prof_launches[tpf::NPROF];
     double prof_bytes[tpf::NPROF];
+    // launches issued per class (counted at issue, independent of the event
+    // pool) and the part of them that found the solve already converged and
+    // did no work: those count in the time, not in launches or bytes
+    long prof_issued[tpf::NPROF];
+    double prof_issued_bytes[tpf::NPROF];
+    long prof_noop[tpf::NPROF];
+    double prof_noop_bytes[tpf::NPROF];
+
+    // PCG iterations of the previous solve of each kind (0: FP64 solve,
+    // 1 + o: inner solve of outer iteration o); the host checks convergence
+    // first after that many iterations
+    int pred_iters[4];
 };
 
 namespace tpf {

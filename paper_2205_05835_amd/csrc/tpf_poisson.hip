@@ -32,6 +32,7 @@
 #include <cmath>
 #include <limits>
 #include <type_traits>
+#include <vector>
 
 #include "tpf_internal.hpp"
 
@@ -1354,31 +1355,59 @@ struct Solver {
     }
 
     // PCG on level 0 for x (type X); residual already in lv[0].r and the
-    // scalars initialised (ff, rr, tol2, done).
+    // scalars initialised (ff, rr, tol2, done).  The iterations run ahead of
+    // the host: it reads the done flag first after the iteration count of
+    // the previous solve of the same kind (slot), then every 2 iterations.
+    // Iterations launched after convergence exit at once; the profiler books
+    // them as no-work launches.
     template <typename X>
-    hipError_t pcg(const void* phi, X* x, int maxit, int check_every) {
+    hipError_t pcg(const void* phi, X* x, int maxit, int slot) {
         vcycle(phi, false);                                       // z = M r, <r,z>
         (void)finalize2(c, 0, (int)nb0(), FIN_RZ0, 0.0);
         int it = 0;
         bool first = true;
+        int window = c->pred_iters[slot] > 0 ? c->pred_iters[slot] : 4;
+        snap_.resize((size_t)maxit + 1);
+        SolverScalars s{};
         while (it < maxit) {
-            for (int k = 0; k < check_every && it < maxit; ++k, ++it) {
+            for (int k = 0; k < window && it < maxit; ++k, ++it) {
+                snapshot(snap_[it]);
                 if (dim == 2) apply_update<2, X>(phi, first ? 1 : 0, x);
                 else apply_update<3, X>(phi, first ? 1 : 0, x);
                 first = false;
                 vcycle(phi, true);
                 (void)finalize2(c, (int)nb0(), (int)nb0(), FIN_BETA, 0.0);
             }
+            window = 2;
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
-            int done = 0;
-            e = hipMemcpyAsync(&done, &c->scal->done, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+            e = hipMemcpyAsync(&s, c->scal, sizeof(SolverScalars), hipMemcpyDeviceToHost, c->stream);
             if (e != hipSuccess) return e;
             e = hipStreamSynchronize(c->stream);
             if (e != hipSuccess) return e;
-            if (done) break;
+            if (s.done) break;
         }
+        if (s.done && s.iters < it && s.iters >= 0) {
+            ProfSnap now;
+            snapshot(now);
+            for (int q = 0; q < NPROF; ++q) {
+                c->prof_noop[q] += now.n[q] - snap_[s.iters].n[q];
+                c->prof_noop_bytes[q] += now.b[q] - snap_[s.iters].b[q];
+            }
+        }
+        if (s.done) c->pred_iters[slot] = s.iters;
         return hipGetLastError();
+    }
+    struct ProfSnap {
+        long n[NPROF];
+        double b[NPROF];
+    };
+    std::vector<ProfSnap> snap_;
+    void snapshot(ProfSnap& o) const {
+        for (int q = 0; q < NPROF; ++q) {
+            o.n[q] = c->prof_issued[q];
+            o.b[q] = c->prof_issued_bytes[q];
+        }
     }
 
     // r = f - A x with the coefficient policy cf (FP64 path: the fine-level
@@ -1431,7 +1460,6 @@ static double omega_of(int dim) { return dim == 2 ? 0.8 : 6.0 / 7.0; }
 tpf_status poisson_solve(tpf_ctx* c, const void* phi, int* iters, double* relres, int* outer) {
     const double rtol = c->P.poisson_rtol;
     const int maxit = c->P.poisson_maxit;
-    const int check = 4;
     SolverScalars s;
     hipError_t e;
     if (!c->mixed) {
@@ -1439,7 +1467,7 @@ tpf_status poisson_solve(tpf_ctx* c, const void* phi, int* iters, double* relres
         sv.build_betas(phi);
         sv.residual<double>(sv.coef_fine(), tp<double>(c->lv[0].r));
         (void)finalize2(c, (int)sv.nb0(), (int)sv.nb0(), FIN_INIT, rtol * rtol);
-        e = sv.pcg<double>(phi, c->p, maxit, check);
+        e = sv.pcg<double>(phi, c->p, maxit, 0);
         if (e != hipSuccess) return hip_fail(e, "FP64 PCG");
         e = remove_mean(c, c->p);
         if (e != hipSuccess) return hip_fail(e, "mean removal");
@@ -1484,7 +1512,7 @@ tpf_status poisson_solve(tpf_ctx* c, const void* phi, int* iters, double* relres
         }
         k_inner_setup<<<1, 64, 0, c->stream>>>(c->scal, rin * rin);
         k_fill_s<float><<<vgrid(c->N), BLOCK, 0, c->stream>>>(c->N, tp<float>(c->ev), 0.0f);
-        e = sv.pcg<float>(phi, tp<float>(c->ev), maxit, check);
+        e = sv.pcg<float>(phi, tp<float>(c->ev), maxit, 1 + std::min(o, 2));
         if (e != hipSuccess) return hip_fail(e, "FP32 inner PCG");
         st = read_scalars(c, &s);
         if (st != TPF_OK) return st;

@@ -147,9 +147,9 @@ __global__ __launch_bounds__(BLOCK) void k_phase(Dims d, Phys P, RKArgs rk,
 //        control volume, minus u_a A_a(D m)
 //   V_a: divergence of the full viscous stress eta (grad u + grad u^T); edge
 //        viscosity = mean of the four cells around the edge
-//   F_a: surface tension -- EB: A_a(mu) G_a phi (Eq. 5, + sign on the RHS);
+//   F_a: surface tension -- EB: A_a(mu) G_a phi (Eq. 4, + sign on the RHS);
 //        CSF: sigma A_a(kappa) G_a phi;  LCSF: sigma_hat A_a(kappa)
-//        A_a(phi(1-phi)) G_a phi (Eq. 12)
+//        A_a(phi(1-phi)) G_a phi (Eq. 11)
 template <typename T, int DIM>
 __global__ __launch_bounds__(BLOCK) void k_momentum(
     Dims d, Phys P, const T* __restrict__ phi, const T* __restrict__ u0,

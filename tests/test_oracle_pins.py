@@ -2,7 +2,7 @@
 
 Every test here checks the oracle (oracle/tpf_oracle.c) against something
 other than itself: closed forms derived from Eq. 2 and the tanh profile of its
-footnote, the continuum identities Eqs. 9-12, exact discrete identities
+footnote, the continuum identities Eqs. 8-11, exact discrete identities
 (summation by parts, product rule), exact amplification factors of RK4 on
 Fourier modes, symmetry and conservation.  No GPU is needed.
 """
@@ -139,7 +139,7 @@ def test_chem_potential_planar_front_zero(ora):
 def test_regularization_tanh_circle_steady_order2(ora, model):
     """P2: the tanh circle is an exact continuum steady state of all three
     models of Table 1 at u = 0 (CDI: the face flux vanishes pointwise; SB and
-    ISODI: the terms cancel by Eqs. 9-10); the discrete g -> 0 at order 2."""
+    ISODI: the terms cancel by Eqs. 8-9); the discrete g -> 0 at order 2."""
     eps, R, errs = 0.02, 0.25, []
     for n in (128, 256, 512):
         P = circle_params(ora, n, eps, model=ora.MODELS[model])
@@ -178,11 +178,11 @@ def test_normals_regularised(ora):
     assert np.abs(n0[0]).max() == 0.0 and np.abs(g0).max() == 0.0
 
 
-# ----------------------------------------------------------------- Eqs. 5, 12: forces
+# ----------------------------------------------------------------- Eqs. 4, 11: forces
 
 
 def test_eb_equals_lcsf_at_equilibrium_order2(ora):
-    """P3 (Eq. 12): on the tanh circle the energy-based and localized CSF
+    """P3 (Eq. 11): on the tanh circle the energy-based and localized CSF
     forces coincide in the continuum; discretely F_EB - F_LCSF -> 0 at order 2."""
     eps, R, errs = 0.02, 0.25, []
     for n in (128, 256, 512):
@@ -224,7 +224,7 @@ def test_force_magnitudes_continuum(ora):
 
 
 def test_eb_gauge_identity(ora):
-    """P4 (Eq. 8): mu grad phi differs from -phi grad mu by the gradient of
+    """P4 (Eq. 7): mu grad phi differs from -phi grad mu by the gradient of
     mu phi, which the pressure absorbs.  With uniform density the discrete
     product rule A(mu)G(phi) = G(mu phi) - A(phi)G(mu) is exact, so both forms
     give the same du/dt and pressures that differ by mu phi - mean."""
