@@ -174,6 +174,62 @@ tpf_status tpf_profile_read(tpf_ctx* ctx, int32_t kernel_class, const char** nam
                             double* total_ms, int64_t* launches, double* bytes_per_launch);
 int32_t tpf_profile_classes(void);
 
+/* ------------------------------------------------------------------ batches
+ * Batched persistent form: many independent 2D cases (each its own grid,
+ * properties, model, force and time step; one precision for the whole batch)
+ * advance together, one GPU launch per RK4 step in which one workgroup owns
+ * one case for the whole step, including its pressure solve.  Cases do not
+ * wait for each other: each converges, fails or finishes on its own.  Steps
+ * are replayed from a captured HIP graph (8 launches per replay).
+ *
+ * Workspace: tpf_batch_workspace_bytes() sizes one device buffer (caller
+ * owned, 256-byte aligned) that holds every case's fields.  Case q is
+ * cases[q] of the array given at creation; cases run longest first.
+ */
+typedef struct tpf_batch tpf_batch;
+
+tpf_status tpf_batch_workspace_bytes(const tpf_params* cases, int32_t ncases, size_t* bytes);
+tpf_status tpf_batch_create(const tpf_params* cases, int32_t ncases, void* workspace, size_t ws_bytes,
+                            void* hip_stream, tpf_batch** out);
+tpf_status tpf_batch_destroy(tpf_batch* b);
+
+/* State of case q (FP64 arrays of nx*ny values; host pointers when
+ * on_device = 0).  Resets the case's time, step count, status and pressure
+ * warm start. */
+tpf_status tpf_batch_set_state(tpf_batch* b, int32_t q, const double* phi, const double* u0,
+                               const double* u1, int32_t on_device);
+/* phi of a tanh ellipse (as tpf_init_droplet) for case q, u = 0. */
+tpf_status tpf_batch_init_droplet(tpf_batch* b, int32_t q, const double center[2],
+                                  const double semi_axes[2]);
+/* phi, u of case q and its last projection pressure (any may be NULL). */
+tpf_status tpf_batch_get_state(tpf_batch* b, int32_t q, double* phi, double* u0, double* u1,
+                               double* p, int32_t on_device);
+
+/* nsteps RK4 steps of every live case with its own dt (host array of ncases
+ * values, each > 0).  A case whose step fails (pressure solve not converged,
+ * or a non-finite value) keeps its last completed state and stops; the call
+ * then returns that failure after all steps, and tpf_batch_status() names the
+ * cases.  The other cases are not affected. */
+tpf_status tpf_batch_step(tpf_batch* b, const double* dt, int32_t nsteps);
+/* Per case (arrays of ncases, any may be NULL): status (TPF_OK or the
+ * failure that stopped it), completed steps and time. */
+tpf_status tpf_batch_status(tpf_batch* b, int32_t* status, int64_t* steps, double* t);
+/* Let a stopped case run again (after its state or parameters were fixed). */
+tpf_status tpf_batch_clear_status(tpf_batch* b, int32_t q);
+/* Diagnostics of every case (out: ncases entries), as tpf_diagnostics. */
+tpf_status tpf_batch_diagnostics(tpf_batch* b, tpf_diag* out);
+
+/* Launch shapes: configuration c has `threads` threads per case-workgroup and
+ * keeps the coarsest multigrid levels of each case in up to `lds_bytes` of
+ * LDS.  tpf_batch_tune() times every configuration on the batch (the state is
+ * not advanced), keeps the fastest, and records it in the text file
+ * cache_path (may be NULL) under a key made of the precision and the grid
+ * sizes; a later call with the same key reads the choice back instead. */
+int32_t tpf_batch_configs(void);
+tpf_status tpf_batch_config_info(int32_t config, int32_t* threads, int32_t* lds_bytes);
+tpf_status tpf_batch_set_config(tpf_batch* b, int32_t config);
+tpf_status tpf_batch_tune(tpf_batch* b, const double* dt, const char* cache_path, int32_t* chosen);
+
 const char* tpf_last_error(void);
 const char* tpf_version(void);
 

@@ -1,7 +1,7 @@
 """Build the HIP library libtpf.so for gfx950 (in-tree, next to this file).
 
 Every kernel is compiled with packed-FP32 instructions disabled; the host
-code is plain C++17.  The three translation units are compiled in parallel
+code is plain C++17.  The translation units are compiled in parallel
 and linked into one shared library exporting the C ABI of include/tpf.h.
 """
 from __future__ import annotations
@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtpf.so")
-SOURCES = ["tpf_stage.hip", "tpf_poisson.hip", "tpf_host.hip"]
+SOURCES = ["tpf_stage.hip", "tpf_poisson.hip", "tpf_host.hip", "tpf_batch.hip"]
 ARCH = os.environ.get("TPF_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

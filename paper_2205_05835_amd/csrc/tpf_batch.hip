@@ -1,0 +1,679 @@
+// Host runtime of the batched persistent form (tpf_batch_* of include/tpf.h):
+// workspace carving for many 2D cases, state transfer, one launch per RK4
+// step (replayed from a captured HIP graph), per-case status, diagnostics,
+// and the launch-shape tuner.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <new>
+#include <numeric>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "tpf_batch_kernels.hpp"
+
+namespace tpf {
+
+// Launch shapes the tuner chooses from: threads per case-workgroup and the
+// LDS budget for the coarse multigrid levels of each case.
+struct BConfig {
+    int threads;
+    int lds_bytes;
+};
+static const BConfig kConfigs[] = {{256, 16384}, {512, 32768}, {1024, 61440}, {1024, 0}, {512, 0}};
+constexpr int NCONFIG = sizeof(kConfigs) / sizeof(kConfigs[0]);
+
+}  // namespace tpf
+
+struct tpf_batch {
+    std::vector<tpf_params> P;
+    int ncases;
+    int mixed;
+    size_t tsz, ssz;
+    char* ws;
+    size_t ws_bytes;
+    hipStream_t stream;
+    tpf::BCase* d_cases;
+    int* d_order;
+    tpf::BState* d_states;
+    double* d_dts;
+    double* d_diag;
+    std::vector<tpf::BCase> h_cases;
+    std::vector<int> order;          // cases by decreasing cell count
+    std::vector<double> mass0;
+    int config;                      // index into kConfigs
+    hipGraphExec_t graph;
+    int graph_steps;                 // launches captured in graph (0: none)
+    int graph_config;
+    hipStream_t cap_stream;          // private stream the step graph is captured on
+};
+
+namespace tpf {
+
+static void plan_case_levels(const tpf_params& P, BCase& K) {
+    int n[2] = {P.n[0], P.n[1]};
+    double h = P.length / P.n[0];
+    int L = 0;
+    K.ln[0][0] = n[0];
+    K.ln[0][1] = n[1];
+    K.lh[0] = h;
+    L = 1;
+    const int maxl = P.mg_levels > 0 ? std::min(P.mg_levels, BMAXLEV) : BMAXLEV;
+    while (L < maxl) {
+        if (n[0] % 2 || n[1] % 2 || n[0] < 8 || n[1] < 8) break;
+        n[0] /= 2;
+        n[1] /= 2;
+        h *= 2.0;
+        K.ln[L][0] = n[0];
+        K.ln[L][1] = n[1];
+        K.lh[L] = h;
+        ++L;
+    }
+    K.nlev = L;
+}
+
+// LDS residency of the coarse levels for a budget: the deepest levels whose
+// r, z, zt and two coefficient arrays fit together.
+static void plan_lds(BCase& K, size_t ssz, int budget) {
+    int first = K.nlev;
+    size_t used = 0;
+    for (int l = K.nlev - 1; l >= 0; --l) {
+        const size_t need = 5 * (size_t)K.ln[l][0] * K.ln[l][1] * ssz;
+        if (used + need > (size_t)budget) break;
+        used += need;
+        first = l;
+    }
+    K.lds_first = first;
+    int off = 0;
+    for (int l = first; l < K.nlev; ++l) {
+        K.lds_off[l] = off;
+        off += 5 * K.ln[l][0] * K.ln[l][1];
+    }
+    K.lds_bytes = (int)(off * ssz);
+}
+
+static size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Carve the batch workspace (base == nullptr: size only).
+static size_t carve_batch(tpf_batch* b, char* base) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void* {
+        void* p = base ? base + off : nullptr;
+        off = a256(off + bytes);
+        return p;
+    };
+    const int nc = b->ncases;
+    b->d_cases = (BCase*)take(sizeof(BCase) * nc);
+    b->d_order = (int*)take(sizeof(int) * nc);
+    b->d_states = (BState*)take(sizeof(BState) * nc);
+    b->d_dts = (double*)take(sizeof(double) * nc);
+    b->d_diag = (double*)take(sizeof(double) * nc * (ND_SUM + ND_MAX));
+    b->h_cases.assign(nc, BCase{});
+    for (int q = 0; q < nc; ++q) {
+        const tpf_params& P = b->P[q];
+        BCase& K = b->h_cases[q];
+        const size_t N = (size_t)P.n[0] * P.n[1];
+        const size_t NT = N * b->tsz, NS = N * b->ssz;
+        for (int s = 0; s < 4; ++s)
+            for (int v = 0; v < 3; ++v) K.y[s][v] = take(NT);
+        for (int a = 0; a < 2; ++a) {
+            K.nrm[a] = take(NT);
+            K.rflux[a] = take(NT);
+            K.mflux[a] = take(NT);
+            K.fs[a] = take(NT);
+        }
+        K.mu = take(NT);
+        K.kappa = take(NT);
+        K.b = (double*)take(N * 8);
+        K.p = (double*)take(N * 8);
+        K.pv = take(NS);
+        K.qv = take(NS);
+        K.ev = take(NS);
+        plan_case_levels(P, K);
+        for (int l = 0; l < K.nlev; ++l) {
+            const size_t Nl = (size_t)K.ln[l][0] * K.ln[l][1] * b->ssz;
+            K.lb[l][0] = take(Nl);
+            K.lb[l][1] = take(Nl);
+            K.lz[l] = take(Nl);
+            K.lzt[l] = take(Nl);
+            K.lr[l] = take(Nl);
+        }
+        K.nx = P.n[0];
+        K.ny = P.n[1];
+        K.P = phys_of_params(P);
+        K.maxit = P.poisson_maxit;
+        K.need_mu = P.force == FORCE_EB;
+        K.need_kappa = P.model != MODEL_CDI || P.force != FORCE_EB;
+        K.rtol = P.poisson_rtol;
+        K.rtol_inner = P.poisson_rtol_inner;
+        plan_lds(K, b->ssz, kConfigs[b->config].lds_bytes);
+    }
+    return off;
+}
+
+static int max_lds(const tpf_batch* b) {
+    int m = 0;
+    for (const BCase& K : b->h_cases) m = std::max(m, K.lds_bytes);
+    return m;
+}
+
+static tpf_status upload_cases(tpf_batch* b) {
+    for (BCase& K : b->h_cases) plan_lds(K, b->ssz, kConfigs[b->config].lds_bytes);
+    hipError_t e = hipMemcpyAsync(b->d_cases, b->h_cases.data(), sizeof(BCase) * b->ncases,
+                                  hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return hip_fail(e, "uploading batch descriptors");
+    return TPF_OK;
+}
+
+template <typename T, typename S>
+static hipError_t launch_step_t(tpf_batch* b, int mode, int commit) {
+    const int nt = kConfigs[b->config].threads;
+    const size_t lds = (size_t)max_lds(b);
+    const dim3 g(b->ncases);
+    switch (nt) {
+    case 256:
+        k_batch_step<T, S, 256><<<g, 256, lds, b->stream>>>(b->d_cases, b->d_order, b->d_states, b->d_dts, mode, commit);
+        break;
+    case 512:
+        k_batch_step<T, S, 512><<<g, 512, lds, b->stream>>>(b->d_cases, b->d_order, b->d_states, b->d_dts, mode, commit);
+        break;
+    default:
+        k_batch_step<T, S, 1024><<<g, 1024, lds, b->stream>>>(b->d_cases, b->d_order, b->d_states, b->d_dts, mode, commit);
+        break;
+    }
+    return hipGetLastError();
+}
+
+static hipError_t launch_step(tpf_batch* b, int mode, int commit) {
+    return b->mixed ? launch_step_t<float, float>(b, mode, commit) : launch_step_t<double, double>(b, mode, commit);
+}
+
+template <typename T>
+__global__ void k_bconv_in(long N, const double* __restrict__ src, T* __restrict__ dst) {
+    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < N; q += (long)gridDim.x * blockDim.x)
+        dst[q] = T(src[q]);
+}
+template <typename T>
+__global__ void k_bconv_out(long N, const T* __restrict__ src, double* __restrict__ dst) {
+    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < N; q += (long)gridDim.x * blockDim.x)
+        dst[q] = (double)src[q];
+}
+template <typename T>
+__global__ void k_bfill(long N, T* __restrict__ dst) {
+    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < N; q += (long)gridDim.x * blockDim.x)
+        dst[q] = T(0);
+}
+template <typename T>
+__global__ void k_binit(Dims d, double h, double eps, double c0, double c1, double a0, double a1,
+                        T* __restrict__ phi) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= d.nx * d.ny) return;
+    const Cell C = make_cell(d, q % d.nx, q / d.nx, 0);
+    op_init_droplet<T, 2>(d, C, h, eps, c0, c1, 0.0, a0, a1, 1.0, phi);
+}
+
+static unsigned vblocks(long N) { return (unsigned)std::min<long>((N + 255) / 256, 4096); }
+
+static hipError_t conv_in(tpf_batch* b, long N, const double* src, void* dst) {
+    if (b->mixed) k_bconv_in<float><<<vblocks(N), 256, 0, b->stream>>>(N, src, (float*)dst);
+    else k_bconv_in<double><<<vblocks(N), 256, 0, b->stream>>>(N, src, (double*)dst);
+    return hipGetLastError();
+}
+static hipError_t conv_out(tpf_batch* b, long N, const void* src, double* dst) {
+    if (b->mixed) k_bconv_out<float><<<vblocks(N), 256, 0, b->stream>>>(N, (const float*)src, dst);
+    else k_bconv_out<double><<<vblocks(N), 256, 0, b->stream>>>(N, (const double*)src, dst);
+    return hipGetLastError();
+}
+static hipError_t zero_field(tpf_batch* b, long N, void* dst, size_t esz) {
+    if (esz == 4) k_bfill<float><<<vblocks(N), 256, 0, b->stream>>>(N, (float*)dst);
+    else k_bfill<double><<<vblocks(N), 256, 0, b->stream>>>(N, (double*)dst);
+    return hipGetLastError();
+}
+
+template <int NT>
+static hipError_t launch_diag_nt(tpf_batch* b) {
+    if (b->mixed) k_batch_diag<float, NT><<<b->ncases, NT, 0, b->stream>>>(b->d_cases, b->d_states, b->d_diag);
+    else k_batch_diag<double, NT><<<b->ncases, NT, 0, b->stream>>>(b->d_cases, b->d_states, b->d_diag);
+    return hipGetLastError();
+}
+
+// reset the bookkeeping of case q after its state was set (slots 0 = y_n,
+// 1 = accumulator; pressure warm start 0)
+static tpf_status reset_case(tpf_batch* b, int q) {
+    BState s{};
+    s.yn = 0;
+    s.acc = 1;
+    const BCase& K = b->h_cases[q];
+    const long N = (long)K.nx * K.ny;
+    hipError_t e = zero_field(b, N, K.p, 8);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_states + q, &s, sizeof(BState), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = launch_diag_nt<256>(b);
+    double out[ND_SUM + ND_MAX];
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(out, b->d_diag + (size_t)q * (ND_SUM + ND_MAX), sizeof(out), hipMemcpyDeviceToHost,
+                           b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return hip_fail(e, "resetting batch case");
+    const double h = b->P[q].length / b->P[q].n[0];
+    b->mass0[q] = out[0] * h * h;
+    return TPF_OK;
+}
+
+static void drop_graph(tpf_batch* b) {
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+    b->graph_steps = 0;
+}
+
+// Capture `k` step launches into a graph (stream capture on the batch stream).
+static tpf_status build_graph(tpf_batch* b, int k) {
+    drop_graph(b);
+    hipGraph_t g = nullptr;
+    // captured on a private stream (the caller's may be the legacy default
+    // stream, which cannot be captured); replayed on the caller's stream
+    if (!b->cap_stream) {
+        hipError_t ec = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+        if (ec != hipSuccess) {
+            b->cap_stream = nullptr;
+            return hip_fail(ec, "creating the capture stream");
+        }
+    }
+    const hipStream_t user = b->stream;
+    b->stream = b->cap_stream;
+    hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        b->stream = user;
+        return hip_fail(e, "beginning graph capture");
+    }
+    for (int s = 0; s < k && e == hipSuccess; ++s) e = launch_step(b, 0, 1);
+    hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+    b->stream = user;
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        b->graph = nullptr;
+        return hip_fail(e, "capturing the batch step graph");
+    }
+    b->graph_steps = k;
+    b->graph_config = b->config;
+    return TPF_OK;
+}
+
+static tpf_status read_states(tpf_batch* b, std::vector<BState>& out) {
+    out.resize(b->ncases);
+    hipError_t e = hipMemcpyAsync(out.data(), b->d_states, sizeof(BState) * b->ncases, hipMemcpyDeviceToHost,
+                                  b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return hip_fail(e, "reading batch states");
+    return TPF_OK;
+}
+
+static tpf_status check_case(const tpf_batch* b, int q) {
+    if (!b) { set_error("batch is NULL"); return TPF_EINVAL; }
+    if (q < 0 || q >= b->ncases) { set_error("case index out of range"); return TPF_EINVAL; }
+    return TPF_OK;
+}
+
+}  // namespace tpf
+
+using namespace tpf;
+
+extern "C" {
+
+tpf_status tpf_batch_workspace_bytes(const tpf_params* cases, int32_t ncases, size_t* bytes) {
+    if (!cases || ncases <= 0 || !bytes) { set_error("cases, ncases > 0 and bytes required"); return TPF_EINVAL; }
+    tpf_batch tmp{};
+    tmp.ncases = ncases;
+    tmp.P.resize(ncases);
+    for (int q = 0; q < ncases; ++q) {
+        tpf_status st = resolve_params(&cases[q], &tmp.P[q]);
+        if (st != TPF_OK) return st;
+        if (tmp.P[q].dim != 2) { set_error("batched cases must be 2D"); return TPF_EINVAL; }
+        if (tmp.P[q].precision != tmp.P[0].precision) {
+            set_error("all cases of a batch must use the same precision");
+            return TPF_EINVAL;
+        }
+    }
+    tmp.mixed = tmp.P[0].precision == TPF_FP32_MIXED;
+    tmp.tsz = tmp.mixed ? 4 : 8;
+    tmp.ssz = tmp.tsz;
+    tmp.config = 2;
+    *bytes = carve_batch(&tmp, nullptr);
+    return TPF_OK;
+}
+
+tpf_status tpf_batch_create(const tpf_params* cases, int32_t ncases, void* workspace, size_t ws_bytes,
+                            void* hip_stream, tpf_batch** out) {
+    if (!out) { set_error("out is NULL"); return TPF_EINVAL; }
+    *out = nullptr;
+    size_t need = 0;
+    tpf_status st = tpf_batch_workspace_bytes(cases, ncases, &need);
+    if (st != TPF_OK) return st;
+    if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255)) {
+        set_error("workspace must be a non-NULL 256-byte aligned device pointer");
+        return TPF_EINVAL;
+    }
+    if (ws_bytes < need) {
+        set_error("workspace too small: need " + std::to_string(need) + " bytes");
+        return TPF_ENOMEM;
+    }
+    tpf_batch* b = new (std::nothrow) tpf_batch{};
+    if (!b) { set_error("host allocation failed"); return TPF_ENOMEM; }
+    b->ncases = ncases;
+    b->P.resize(ncases);
+    for (int q = 0; q < ncases; ++q) (void)resolve_params(&cases[q], &b->P[q]);
+    b->mixed = b->P[0].precision == TPF_FP32_MIXED;
+    b->tsz = b->mixed ? 4 : 8;
+    b->ssz = b->tsz;
+    b->config = 2;
+    b->ws = static_cast<char*>(workspace);
+    b->ws_bytes = ws_bytes;
+    b->stream = static_cast<hipStream_t>(hip_stream);
+    carve_batch(b, b->ws);
+    b->order.resize(ncases);
+    std::iota(b->order.begin(), b->order.end(), 0);
+    std::stable_sort(b->order.begin(), b->order.end(), [&](int x, int y) {
+        return (long)b->P[x].n[0] * b->P[x].n[1] > (long)b->P[y].n[0] * b->P[y].n[1];
+    });
+    b->mass0.assign(ncases, 0.0);
+    hipError_t e = hipMemsetAsync(b->ws, 0, need, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_order, b->order.data(), sizeof(int) * ncases, hipMemcpyHostToDevice, b->stream);
+    std::vector<BState> s0(ncases);
+    for (auto& s : s0) {
+        s = BState{};
+        s.yn = 0;
+        s.acc = 1;
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_states, s0.data(), sizeof(BState) * ncases, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) {
+        tpf_status s = hip_fail(e, "batch workspace setup");
+        delete b;
+        return s;
+    }
+    st = upload_cases(b);
+    if (st != TPF_OK) {
+        delete b;
+        return st;
+    }
+    *out = b;
+    return TPF_OK;
+}
+
+tpf_status tpf_batch_destroy(tpf_batch* b) {
+    if (!b) return TPF_OK;
+    drop_graph(b);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    delete b;
+    return TPF_OK;
+}
+
+tpf_status tpf_batch_set_state(tpf_batch* b, int32_t q, const double* phi, const double* u0,
+                               const double* u1, int32_t on_device) {
+    tpf_status st = check_case(b, q);
+    if (st != TPF_OK) return st;
+    if (!phi || !u0 || !u1) { set_error("phi, u0 and u1 are required"); return TPF_EINVAL; }
+    const BCase& K = b->h_cases[q];
+    const long N = (long)K.nx * K.ny;
+    const double* src[3] = {phi, u0, u1};
+    // host arrays are staged through the case's FP64 right-hand-side array,
+    // which holds nothing between steps
+    hipError_t e = hipSuccess;
+    for (int v = 0; v < 3 && e == hipSuccess; ++v) {
+        const double* s = src[v];
+        if (!on_device) {
+            e = hipMemcpyAsync(K.b, src[v], (size_t)N * 8, hipMemcpyHostToDevice, b->stream);
+            s = K.b;
+        }
+        if (e == hipSuccess) e = conv_in(b, N, s, K.y[0][v]);
+        if (e == hipSuccess && !on_device) e = hipStreamSynchronize(b->stream);
+    }
+    if (e != hipSuccess) return hip_fail(e, "batch set_state");
+    return reset_case(b, q);
+}
+
+tpf_status tpf_batch_init_droplet(tpf_batch* b, int32_t q, const double center[2], const double semi_axes[2]) {
+    tpf_status st = check_case(b, q);
+    if (st != TPF_OK) return st;
+    if (!center || !semi_axes) { set_error("center and semi_axes are required"); return TPF_EINVAL; }
+    const BCase& K = b->h_cases[q];
+    const long N = (long)K.nx * K.ny;
+    const Dims d{K.nx, K.ny, 1, 0};
+    const double h = b->P[q].length / b->P[q].n[0];
+    hipError_t e;
+    if (b->mixed)
+        k_binit<float><<<(unsigned)((N + 255) / 256), 256, 0, b->stream>>>(d, h, b->P[q].eps, center[0], center[1],
+                                                                          semi_axes[0], semi_axes[1], (float*)K.y[0][0]);
+    else
+        k_binit<double><<<(unsigned)((N + 255) / 256), 256, 0, b->stream>>>(d, h, b->P[q].eps, center[0], center[1],
+                                                                           semi_axes[0], semi_axes[1], (double*)K.y[0][0]);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = zero_field(b, N, K.y[0][1], b->tsz);
+    if (e == hipSuccess) e = zero_field(b, N, K.y[0][2], b->tsz);
+    if (e != hipSuccess) return hip_fail(e, "batch init_droplet");
+    return reset_case(b, q);
+}
+
+tpf_status tpf_batch_get_state(tpf_batch* b, int32_t q, double* phi, double* u0, double* u1, double* p,
+                               int32_t on_device) {
+    tpf_status st = check_case(b, q);
+    if (st != TPF_OK) return st;
+    std::vector<BState> s;
+    st = read_states(b, s);
+    if (st != TPF_OK) return st;
+    const BCase& K = b->h_cases[q];
+    const long N = (long)K.nx * K.ny;
+    double* dst[3] = {phi, u0, u1};
+    // host arrays are staged through the case's FP64 right-hand-side array
+    hipError_t e = hipSuccess;
+    for (int v = 0; v < 3 && e == hipSuccess; ++v) {
+        if (!dst[v]) continue;
+        double* d = on_device ? dst[v] : K.b;
+        e = conv_out(b, N, K.y[s[q].yn][v], d);
+        if (e == hipSuccess && !on_device) e = hipMemcpyAsync(dst[v], K.b, (size_t)N * 8, hipMemcpyDeviceToHost, b->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    }
+    if (e == hipSuccess && p)
+        e = hipMemcpyAsync(p, K.p, (size_t)N * 8, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                           b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return hip_fail(e, "batch get_state");
+    return TPF_OK;
+}
+
+tpf_status tpf_batch_step(tpf_batch* b, const double* dt, int32_t nsteps) {
+    if (!b || !dt || nsteps < 0) { set_error("batch, dt and nsteps >= 0 required"); return TPF_EINVAL; }
+    for (int q = 0; q < b->ncases; ++q)
+        if (!(dt[q] > 0)) { set_error("every dt must be > 0"); return TPF_EINVAL; }
+    hipError_t e = hipMemcpyAsync(b->d_dts, dt, sizeof(double) * b->ncases, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return hip_fail(e, "uploading time steps");
+    const int G = 8;
+    int done = 0;
+    if (nsteps >= G) {
+        if (!b->graph || b->graph_steps != G || b->graph_config != b->config) {
+            tpf_status st = build_graph(b, G);
+            if (st != TPF_OK) return st;
+        }
+        for (; done + G <= nsteps; done += G) {
+            e = hipGraphLaunch(b->graph, b->stream);
+            if (e != hipSuccess) return hip_fail(e, "batch graph launch");
+        }
+    }
+    for (; done < nsteps; ++done) {
+        e = launch_step(b, 0, 1);
+        if (e != hipSuccess) return hip_fail(e, "batch step launch");
+    }
+    std::vector<BState> s;
+    tpf_status st = read_states(b, s);
+    if (st != TPF_OK) return st;
+    int nfail = 0, first = -1, code = TPF_OK;
+    for (int q = 0; q < b->ncases; ++q)
+        if (s[q].status != TPF_OK) {
+            if (first < 0) {
+                first = q;
+                code = s[q].status;
+            }
+            ++nfail;
+        }
+    if (nfail) {
+        set_error(std::to_string(nfail) + " case(s) stopped (first: case " + std::to_string(first) +
+                  (code == TPF_ENOCONV ? ", pressure solve did not converge" : ", non-finite state") +
+                  "); their state is the last completed step");
+        return (tpf_status)code;
+    }
+    return TPF_OK;
+}
+
+tpf_status tpf_batch_status(tpf_batch* b, int32_t* status, int64_t* steps, double* t) {
+    if (!b) { set_error("batch is NULL"); return TPF_EINVAL; }
+    std::vector<BState> s;
+    tpf_status st = read_states(b, s);
+    if (st != TPF_OK) return st;
+    for (int q = 0; q < b->ncases; ++q) {
+        if (status) status[q] = s[q].status;
+        if (steps) steps[q] = s[q].step;
+        if (t) t[q] = s[q].t;
+    }
+    return TPF_OK;
+}
+
+tpf_status tpf_batch_clear_status(tpf_batch* b, int32_t q) {
+    tpf_status st = check_case(b, q);
+    if (st != TPF_OK) return st;
+    std::vector<BState> s;
+    st = read_states(b, s);
+    if (st != TPF_OK) return st;
+    s[q].status = TPF_OK;
+    s[q].nonfinite = 0;
+    hipError_t e = hipMemcpyAsync(b->d_states + q, &s[q], sizeof(BState), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return hip_fail(e, "clearing case status");
+    return TPF_OK;
+}
+
+tpf_status tpf_batch_diagnostics(tpf_batch* b, tpf_diag* out) {
+    if (!b || !out) { set_error("batch and out are required"); return TPF_EINVAL; }
+    // projection pressure of the current state of every live case
+    hipError_t e = launch_step(b, 1, 0);
+    if (e == hipSuccess) e = launch_diag_nt<256>(b);
+    std::vector<double> d((size_t)b->ncases * (ND_SUM + ND_MAX));
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d.data(), b->d_diag, sizeof(double) * d.size(), hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return hip_fail(e, "batch diagnostics");
+    std::vector<BState> s;
+    tpf_status st = read_states(b, s);
+    if (st != TPF_OK) return st;
+    for (int q = 0; q < b->ncases; ++q) {
+        const double* v = d.data() + (size_t)q * (ND_SUM + ND_MAX);
+        const tpf_params& P = b->P[q];
+        const double h = P.length / P.n[0], h2 = h * h;
+        tpf_diag& o = out[q];
+        o = tpf_diag{};
+        o.t = s[q].t;
+        o.step = s[q].step;
+        o.mass = v[0] * h2;
+        o.mass0 = b->mass0[q];
+        o.ke = v[1] * h2;
+        o.se = v[2] * h2;
+        o.dp = (v[4] > 0 && v[6] > 0) ? v[3] / v[4] - v[5] / v[6] : 0.0;
+        o.umax = v[7];
+        o.div_max = v[8];
+        o.phi_min = -v[9];
+        o.phi_max = v[10];
+        o.ca_inf = P.sigma > 0 ? o.umax * P.visc1 / P.sigma : 0.0;
+        o.poisson_relres = s[q].relres;
+        o.poisson_outer = s[q].outer;
+        o.poisson_inner = s[q].iters;
+    }
+    return TPF_OK;
+}
+
+tpf_status tpf_batch_set_config(tpf_batch* b, int32_t config) {
+    if (!b || config < 0 || config >= NCONFIG) { set_error("bad batch launch configuration"); return TPF_EINVAL; }
+    b->config = config;
+    drop_graph(b);
+    return upload_cases(b);
+}
+
+tpf_status tpf_batch_config_info(int32_t config, int32_t* threads, int32_t* lds_bytes) {
+    if (config < 0 || config >= NCONFIG) { set_error("bad batch launch configuration"); return TPF_EINVAL; }
+    if (threads) *threads = kConfigs[config].threads;
+    if (lds_bytes) *lds_bytes = kConfigs[config].lds_bytes;
+    return TPF_OK;
+}
+
+int32_t tpf_batch_configs(void) { return NCONFIG; }
+
+tpf_status tpf_batch_tune(tpf_batch* b, const double* dt, const char* cache_path, int32_t* chosen) {
+    if (!b || !dt) { set_error("batch and dt are required"); return TPF_EINVAL; }
+    // key: precision and the sorted list of grid sizes
+    std::ostringstream key;
+    key << (b->mixed ? "fp32mixed" : "fp64") << ":" << b->ncases;
+    {
+        std::vector<long> sz(b->ncases);
+        for (int q = 0; q < b->ncases; ++q) sz[q] = (long)b->P[q].n[0] * 100000 + b->P[q].n[1];
+        std::sort(sz.begin(), sz.end());
+        unsigned long long hsh = 1469598103934665603ull;
+        for (long v : sz) hsh = (hsh ^ (unsigned long long)v) * 1099511628211ull;
+        key << ":" << std::hex << hsh;
+    }
+    if (cache_path) {
+        std::ifstream in(cache_path);
+        std::string k;
+        int cfg;
+        while (in >> k >> cfg)
+            if (k == key.str() && cfg >= 0 && cfg < NCONFIG) {
+                if (chosen) *chosen = cfg;
+                return tpf_batch_set_config(b, cfg);
+            }
+    }
+    hipError_t e = hipMemcpyAsync(b->d_dts, dt, sizeof(double) * b->ncases, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return hip_fail(e, "uploading time steps");
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        set_error("hipEventCreate failed");
+        return TPF_EDEVICE;
+    }
+    int best = -1;
+    float best_ms = 0.f;
+    for (int cfg = 0; cfg < NCONFIG; ++cfg) {
+        tpf_status st = tpf_batch_set_config(b, cfg);
+        if (st != TPF_OK) break;
+        e = launch_step(b, 0, 0);                       // warm-up, state not advanced
+        if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+        for (int r = 0; r < 2 && e == hipSuccess; ++r) e = launch_step(b, 0, 0);
+        if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) break;
+        if (best < 0 || ms < best_ms) {
+            best = cfg;
+            best_ms = ms;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(e, "timing batch launch configurations");
+    if (best < 0) return TPF_EDEVICE;
+    if (cache_path) {
+        std::ofstream o(cache_path, std::ios::app);
+        o << key.str() << " " << best << "\n";
+    }
+    if (chosen) *chosen = best;
+    return tpf_batch_set_config(b, best);
+}
+
+}  // extern "C"

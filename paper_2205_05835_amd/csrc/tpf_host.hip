@@ -23,24 +23,26 @@ tpf_status hip_fail(hipError_t e, const char* what) {
     return TPF_EDEVICE;
 }
 
-Phys phys_of(const tpf_ctx* c) {
+Phys phys_of_params(const tpf_params& in) {
     Phys P;
-    P.model = c->P.model;
-    P.force = c->P.force;
-    P.clamp = c->P.clamp_properties;
-    P.h = c->h;
-    P.inv_h = 1.0 / c->h;
-    P.sigma = c->P.sigma;
-    P.sigma_hat = 6.0 * c->P.sigma;
-    P.eps = c->P.eps;
-    P.gamma = c->P.gamma;
-    P.rho1 = c->P.rho1;
-    P.rho2 = c->P.rho2;
-    P.visc1 = c->P.visc1;
-    P.visc2 = c->P.visc2;
-    P.delta2 = c->P.normal_delta * c->P.normal_delta;
+    P.model = in.model;
+    P.force = in.force;
+    P.clamp = in.clamp_properties;
+    P.h = in.length / in.n[0];
+    P.inv_h = 1.0 / P.h;
+    P.sigma = in.sigma;
+    P.sigma_hat = 6.0 * in.sigma;
+    P.eps = in.eps;
+    P.gamma = in.gamma;
+    P.rho1 = in.rho1;
+    P.rho2 = in.rho2;
+    P.visc1 = in.visc1;
+    P.visc2 = in.visc2;
+    P.delta2 = in.normal_delta * in.normal_delta;
     return P;
 }
+
+Phys phys_of(const tpf_ctx* c) { return phys_of_params(c->P); }
 
 // ---------------------------------------------------------------- profiling
 static const char* kProfNames[NPROF] = {
@@ -189,7 +191,7 @@ static size_t carve(tpf_ctx* c, char* base) {
     return cv.off;
 }
 
-static tpf_status resolve(const tpf_params* in, tpf_params* P) {
+tpf_status resolve_params(const tpf_params* in, tpf_params* P) {
     if (!in) { set_error("params is NULL"); return TPF_EINVAL; }
     *P = *in;
     if (P->dim != 2 && P->dim != 3) { set_error("dim must be 2 or 3"); return TPF_EINVAL; }
@@ -246,7 +248,7 @@ int32_t tpf_profile_classes(void) { return NPROF; }
 tpf_status tpf_workspace_bytes(const tpf_params* params, size_t* bytes) {
     if (!bytes) { set_error("bytes is NULL"); return TPF_EINVAL; }
     tpf_params P;
-    tpf_status st = resolve(params, &P);
+    tpf_status st = resolve_params(params, &P);
     if (st != TPF_OK) return st;
     tpf_ctx tmp;
     std::memset(&tmp, 0, sizeof(tmp));
@@ -260,7 +262,7 @@ tpf_status tpf_create(const tpf_params* params, void* workspace, size_t ws_bytes
     if (!out) { set_error("out is NULL"); return TPF_EINVAL; }
     *out = nullptr;
     tpf_params P;
-    tpf_status st = resolve(params, &P);
+    tpf_status st = resolve_params(params, &P);
     if (st != TPF_OK) return st;
     if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255)) {
         set_error("workspace must be a non-NULL 256-byte aligned device pointer");

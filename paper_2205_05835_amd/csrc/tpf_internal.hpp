@@ -8,6 +8,7 @@
 
 #include "../../include/tpf.h"
 #include "tpf_device.hpp"
+#include "tpf_stage_ops.hpp"
 
 namespace tpf {
 
@@ -148,6 +149,9 @@ struct tpf_ctx {
 
 namespace tpf {
 
+// validated copy of a parameter set with the defaults filled in
+tpf_status resolve_params(const tpf_params* in, tpf_params* out);
+Phys phys_of_params(const tpf_params& P);
 void set_error(const std::string& msg);
 tpf_status hip_fail(hipError_t e, const char* what);
 
@@ -156,12 +160,6 @@ void prof_begin(tpf_ctx* c, int cls, double bytes);
 void prof_end(tpf_ctx* c);
 
 // stage kernels (tpf_stage.hip)
-struct RKArgs {
-    int stage;        // 0..3
-    int eval_only;    // 1: write the derivative to out instead of updating
-    double wacc;      // acc (+)= wacc * k
-    double wnext;     // ynext = yn + wnext * k (stages 0-2)
-};
 hipError_t launch_stage_fields(tpf_ctx* c, const void* phi_s, const void* const u_s[3]);
 hipError_t launch_phase_update(tpf_ctx* c, const void* phi_s, const void* const u_s[3],
                                const RKArgs& rk, void* out);

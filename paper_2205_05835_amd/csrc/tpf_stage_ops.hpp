@@ -1,0 +1,345 @@
+// Per-cell bodies of the stage operators, shared by the one-thread-per-cell
+// kernels of the single-case step and the block-stride loops of the batched
+// persistent step.  Each op_* computes the outputs of one cell C.
+//
+// Discrete operators on the staggered periodic grid (Sec. 3):
+//   A_a q[c] = (q[c-e_a] + q[c])/2,  G_a q[c] = (q[c] - q[c-e_a])/h,
+//   D F[c] = sum_a (F_a[c+e_a] - F_a[c])/h,  C_a q[c] = (q[c+e_a]-q[c-e_a])/(2h)
+#pragma once
+#include "tpf_device.hpp"
+
+namespace tpf {
+
+struct RKArgs {
+    int stage;        // 0..3
+    int eval_only;    // 1: write the derivative to out instead of updating
+    double wacc;      // acc (+)= wacc * k
+    double wnext;     // ynext = yn + wnext * k (stages 0-2)
+};
+
+// ------------------------------------------------------------------ normals, mu
+// n_a = C_a phi / sqrt(|C phi|^2 + delta^2)  (Table 1 caption, regularised)
+// mu = (sigma_hat/eps) psi'(phi) - sigma_hat eps L phi   (Eq. 2)
+template <typename T, int DIM>
+__device__ __forceinline__ void op_cell(const Phys& P, const Cell& C, const T* __restrict__ phi,
+                                                T* __restrict__ n0, T* __restrict__ n1,
+                                                T* __restrict__ n2, T* __restrict__ mu) {
+    const unsigned c = C.id;
+    const T f = phi[c];
+    const T ih = T(P.inv_h), ih2 = T(0.5 * P.inv_h);
+    T g[3] = {T(0), T(0), T(0)};
+    T gg = T(0), lap = T(0);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const T fp = phi[C.off(a, 1)], fm = phi[C.off(a, -1)];
+        g[a] = (fp - fm) * ih2;
+        gg += g[a] * g[a];
+        lap += ((fp - f) * ih - (f - fm) * ih) * ih;
+    }
+    const T inv = T(1) / sqrt(gg + T(P.delta2));
+    n0[c] = g[0] * inv;
+    n1[c] = g[1] * inv;
+    if (DIM == 3) n2[c] = g[2] * inv;
+    if (mu) mu[c] = T(P.sigma_hat / P.eps) * dpsi(f) - T(P.sigma_hat * P.eps) * lap;
+}
+
+// kappa = - sum_a C_a n_a   (Eq. 3)
+template <typename T, int DIM>
+__device__ __forceinline__ void op_kappa(const Phys& P, const Cell& C, const T* __restrict__ n0,
+                                                 const T* __restrict__ n1,
+                                                 const T* __restrict__ n2, T* __restrict__ kappa) {
+    const T* n[3] = {n0, n1, n2};
+    const T ih2 = T(0.5 * P.inv_h);
+    T s = T(0);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) s += (n[a][C.off(a, 1)] - n[a][C.off(a, -1)]) * ih2;
+    kappa[C.id] = -s;
+}
+
+// ------------------------------------------------------------------ face fluxes
+// CDI flux r_a = gamma [eps G_a phi - A_a(phi (1 - phi) n_a)]  (Table 1)
+// mass flux m_a = rho_a u_a - (rho1 - rho2) r_a  (CDI; r = 0 otherwise)
+template <typename T, int DIM>
+__device__ __forceinline__ void op_face(const Phys& P, const Cell& C, const T* __restrict__ phi,
+                                                const T* __restrict__ n0, const T* __restrict__ n1,
+                                                const T* __restrict__ n2, const T* __restrict__ u0,
+                                                const T* __restrict__ u1, const T* __restrict__ u2,
+                                                T* __restrict__ r0, T* __restrict__ r1,
+                                                T* __restrict__ r2, T* __restrict__ m0,
+                                                T* __restrict__ m1, T* __restrict__ m2) {
+    const T* n[3] = {n0, n1, n2};
+    const T* u[3] = {u0, u1, u2};
+    T* r[3] = {r0, r1, r2};
+    T* m[3] = {m0, m1, m2};
+    const unsigned c = C.id;
+    const T f = phi[c];
+    const bool cdi = P.model == MODEL_CDI;
+    const T drho = T(P.rho1 - P.rho2);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const unsigned cm = C.off(a, -1);
+        const T fm = phi[cm];
+        const T rho_f = T(0.5) * (rho_of(P, fm) + rho_of(P, f));
+        T ra = T(0);
+        if (cdi) {
+            const T wm = fm * (T(1) - fm) * n[a][cm];
+            const T wc = f * (T(1) - f) * n[a][c];
+            ra = T(P.gamma) * (T(P.eps) * ((f - fm) * T(P.inv_h)) - T(0.5) * (wm + wc));
+            r[a][c] = ra;
+        }
+        m[a][c] = rho_f * u[a][c] - drho * ra;
+    }
+}
+
+// ------------------------------------------------------------------ phase field
+// dphi/dt = -D(u A phi) + g   (Eq. 1), g of Table 1; then the RK4 update.
+template <typename T, int DIM>
+__device__ __forceinline__ void op_phase(const Phys& P, const RKArgs& rk, const Cell& C,
+                                                 const T* __restrict__ phi,
+                                                 const T* __restrict__ u0, const T* __restrict__ u1,
+                                                 const T* __restrict__ u2, const T* __restrict__ r0,
+                                                 const T* __restrict__ r1, const T* __restrict__ r2,
+                                                 const T* __restrict__ kappa,
+                                                 const T* __restrict__ yn, T* __restrict__ acc,
+                                                 T* __restrict__ ynext, int* __restrict__ flags) {
+    const T* u[3] = {u0, u1, u2};
+    const T* r[3] = {r0, r1, r2};
+    const unsigned c = C.id;
+    const T f = phi[c];
+    const T ih = T(P.inv_h);
+    T adv = T(0), g = T(0), lap = T(0), gg = T(0);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const unsigned cp = C.off(a, 1), cm = C.off(a, -1);
+        const T fp = phi[cp], fm = phi[cm];
+        const T jhi = u[a][cp] * (T(0.5) * (f + fp));
+        const T jlo = u[a][c] * (T(0.5) * (fm + f));
+        adv += (jhi - jlo) * ih;
+        if (P.model == MODEL_CDI) {
+            g += (r[a][cp] - r[a][c]) * ih;
+        } else {
+            lap += ((fp - f) * ih - (f - fm) * ih) * ih;
+            const T ga = (fp - fm) * T(0.5 * P.inv_h);
+            gg += ga * ga;
+        }
+    }
+    if (P.model != MODEL_CDI) {
+        const T base = T(P.eps) * lap - dpsi(f) / T(P.eps);
+        const T curv = (P.model == MODEL_SB) ? T(P.eps) * sqrt(gg) * kappa[c]
+                                             : f * (T(1) - f) * kappa[c];
+        g = T(P.gamma) * (base + curv);
+    }
+    const T k = -adv + g;
+    if (rk.eval_only) {
+        ynext[c] = k;
+        return;
+    }
+    const T y0 = yn[c];
+    const T a_new = (rk.stage == 0 ? y0 : acc[c]) + T(rk.wacc) * k;
+    acc[c] = a_new;
+    if (rk.stage < 3) ynext[c] = y0 + T(rk.wnext) * k;
+    else if (!isfinite(a_new)) flags[0] = 1;
+}
+
+// ------------------------------------------------------------------ momentum
+// f*_a = (-N_a + V_a + F_a) / rho_a on face (c, a).
+//   N_a: velocity form of div(m (x) u) with arithmetic-mean fluxes on the u_a
+//        control volume, minus u_a A_a(D m)
+//   V_a: divergence of the full viscous stress eta (grad u + grad u^T); edge
+//        viscosity = mean of the four cells around the edge
+//   F_a: surface tension -- EB: A_a(mu) G_a phi (Eq. 4, + sign on the RHS);
+//        CSF: sigma A_a(kappa) G_a phi;  LCSF: sigma_hat A_a(kappa)
+//        A_a(phi(1-phi)) G_a phi (Eq. 11)
+template <typename T, int DIM>
+__device__ __forceinline__ void op_momentum(const Phys& P, const Cell& C, const T* __restrict__ phi, const T* __restrict__ u0,
+    const T* __restrict__ u1, const T* __restrict__ u2, const T* __restrict__ m0,
+    const T* __restrict__ m1, const T* __restrict__ m2, const T* __restrict__ mu,
+    const T* __restrict__ kappa, T* __restrict__ f0, T* __restrict__ f1, T* __restrict__ f2,
+    T* __restrict__ F0, T* __restrict__ F1, T* __restrict__ F2) {
+    const T* u[3] = {u0, u1, u2};
+    const T* m[3] = {m0, m1, m2};
+    T* fs[3] = {f0, f1, f2};
+    T* Fo[3] = {F0, F1, F2};
+    const unsigned c = C.id;
+    const T ih = T(P.inv_h);
+    const T f = phi[c];
+    const T eta_c = visc_of(P, f);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const unsigned cp = C.off(a, 1), cm = C.off(a, -1);
+        const T fm = phi[cm];
+        const T eta_m = visc_of(P, fm);
+        const T uac = u[a][c];
+        // ---- advection
+        T adv = T(0), dm_c = T(0), dm_m = T(0);
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) {
+            T hi, lo;
+            if (b == a) {
+                hi = (T(0.5) * (m[a][c] + m[a][cp])) * (T(0.5) * (uac + u[a][cp]));
+                lo = (T(0.5) * (m[a][cm] + m[a][c])) * (T(0.5) * (u[a][cm] + uac));
+            } else {
+                const unsigned cpb = C.off(b, 1), cmb = C.off(b, -1), cmapb = C.off2(a, -1, b, 1);
+                hi = (T(0.5) * (m[b][cpb] + m[b][cmapb])) * (T(0.5) * (uac + u[a][cpb]));
+                lo = (T(0.5) * (m[b][c] + m[b][cm])) * (T(0.5) * (u[a][cmb] + uac));
+            }
+            adv += (hi - lo) * ih;
+            dm_c += (m[b][C.off(b, 1)] - m[b][c]) * ih;
+            // (c - e_a) + e_b: back to c itself when b == a
+            dm_m += (m[b][b == a ? c : C.off2(a, -1, b, 1)] - m[b][cm]) * ih;
+        }
+        const T N = adv - uac * (T(0.5) * (dm_m + dm_c));
+        // ---- viscous stress
+        T V = T(0);
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) {
+            T hi, lo;
+            if (b == a) {
+                hi = T(2) * eta_c * ((u[a][cp] - uac) * ih);
+                lo = T(2) * eta_m * ((uac - u[a][cm]) * ih);
+            } else {
+                const unsigned cpb = C.off(b, 1), cmb = C.off(b, -1);
+                const unsigned cmapb = C.off2(a, -1, b, 1), cmamb = C.off2(a, -1, b, -1);
+                const T e_pb = visc_of(P, phi[cpb]), e_mapb = visc_of(P, phi[cmapb]);
+                const T e_mb = visc_of(P, phi[cmb]), e_mamb = visc_of(P, phi[cmamb]);
+                const T eta_hi = T(0.25) * (eta_c + eta_m + e_pb + e_mapb);
+                const T eta_lo = T(0.25) * (e_mb + e_mamb + eta_c + eta_m);
+                hi = eta_hi * ((u[a][cpb] - uac) * ih + (u[b][cpb] - u[b][cmapb]) * ih);
+                lo = eta_lo * ((uac - u[a][cmb]) * ih + (u[b][c] - u[b][cm]) * ih);
+            }
+            V += (hi - lo) * ih;
+        }
+        // ---- surface tension
+        const T gphi = (f - fm) * ih;
+        T F;
+        if (P.force == FORCE_EB) {
+            F = (T(0.5) * (mu[cm] + mu[c])) * gphi;
+        } else if (P.force == FORCE_CSF) {
+            F = T(P.sigma) * (T(0.5) * (kappa[cm] + kappa[c])) * gphi;
+        } else {
+            F = T(P.sigma_hat) * (T(0.5) * (kappa[cm] + kappa[c])) *
+                (T(0.5) * (fm * (T(1) - fm) + f * (T(1) - f))) * gphi;
+        }
+        if (Fo[0]) Fo[a][c] = F;
+        const T rho_f = T(0.5) * (rho_of(P, fm) + rho_of(P, f));
+        fs[a][c] = (-N + V + F) * (T(1) / rho_f);
+    }
+}
+
+// ------------------------------------------------------------------ D f* (FP64)
+template <typename T, int DIM>
+__device__ __forceinline__ double op_div(const Phys& P, const Cell& C, const T* __restrict__ f0,
+                                         const T* __restrict__ f1, const T* __restrict__ f2,
+                                         double* __restrict__ b) {
+    const T* fs[3] = {f0, f1, f2};
+    const unsigned c = C.id;
+    double s = 0.0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) s += ((double)fs[a][C.off(a, 1)] - (double)fs[a][c]) * P.inv_h;
+    b[c] = s;
+    return s;
+}
+
+// ------------------------------------------------------------------ projection
+// du_a/dt = f*_a - beta_a G_a p, then the RK4 update of u_a.
+template <typename T, int DIM>
+__device__ __forceinline__ void op_project(const Phys& P, const RKArgs& rk, const Cell& C,
+                                                   const T* __restrict__ phi,
+                                                   const double* __restrict__ p,
+                                                   const T* __restrict__ f0, const T* __restrict__ f1,
+                                                   const T* __restrict__ f2, const T* yn0,
+                                                   const T* yn1, const T* yn2, T* acc0, T* acc1,
+                                                   T* acc2, T* nx0, T* nx1, T* nx2,
+                                                   int* __restrict__ flags) {
+    const T* fs[3] = {f0, f1, f2};
+    const T* yn[3] = {yn0, yn1, yn2};
+    T* acc[3] = {acc0, acc1, acc2};
+    T* nx[3] = {nx0, nx1, nx2};
+    const unsigned c = C.id;
+    const T f = phi[c];
+    const double pc = p[c];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const unsigned cm = C.off(a, -1);
+        const double rho_f = 0.5 * ((double)rho_of(P, phi[cm]) + (double)rho_of(P, f));
+        const double gp = (pc - p[cm]) * P.inv_h;
+        const T k = T((double)fs[a][c] - gp / rho_f);
+        if (rk.eval_only) {
+            nx[a][c] = k;
+            continue;
+        }
+        const T y0 = yn[a][c];
+        const T a_new = (rk.stage == 0 ? y0 : acc[a][c]) + T(rk.wacc) * k;
+        acc[a][c] = a_new;
+        if (rk.stage < 3) nx[a][c] = y0 + T(rk.wnext) * k;
+        else if (!isfinite(a_new)) flags[0] = 1;
+    }
+}
+
+// ------------------------------------------------------------------ initial droplet
+// phi = [1 + tanh(s/2eps)]/2, s = (1 - q)/|grad q| with q = |x / a| (first-order
+// signed distance to the ellipse/ellipsoid, exact for circles and spheres)
+template <typename T, int DIM>
+__device__ __forceinline__ void op_init_droplet(const Dims& d, const Cell& C, double h, double eps, double c0,
+                                                        double c1, double c2, double a0, double a1,
+                                                        double a2, T* __restrict__ phi) {
+    const double cen[3] = {c0, c1, c2}, ax[3] = {a0, a1, a2};
+    const int v[3] = {C.i, C.j, C.k};
+    const int nn[3] = {d.nx, d.ny, d.nz};
+    double q2 = 0.0, g2 = 0.0, amin = ax[0];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const double L = nn[a] * h;
+        double x = (v[a] + 0.5) * h - cen[a];
+        x -= L * floor(x / L + 0.5);
+        q2 += (x / ax[a]) * (x / ax[a]);
+        g2 += x * x / (ax[a] * ax[a] * ax[a] * ax[a]);
+        amin = fmin(amin, ax[a]);
+    }
+    const double q = sqrt(q2);
+    const double s = (q2 == 0.0) ? amin : (1.0 - q) * q / sqrt(g2);
+    phi[C.id] = T(0.5 * (1.0 + tanh(s / (2.0 * eps))));
+}
+
+// ------------------------------------------------------------------ diagnostics
+// Per-block partials: [0] sum phi, [1] KE density, [2] SE density, [3] sum p
+// (phi>0.99), [4] count in, [5] sum p (phi<0.01), [6] count out; maxima:
+// [7] |u_cell|, [8] |D u|, [9] -min phi, [10] max phi.
+constexpr int ND_SUM = 7, ND_MAX = 4;
+
+template <typename T, int DIM>
+__device__ __forceinline__ void op_diag(const Phys& P, const Cell& C, const T* __restrict__ phi,
+                                        const T* __restrict__ u0, const T* __restrict__ u1,
+                                        const T* __restrict__ u2, const double* __restrict__ p,
+                                        double (&s)[ND_SUM], double (&mx)[ND_MAX]) {
+    const T* u[3] = {u0, u1, u2};
+    const unsigned c = C.id;
+    const double f = (double)phi[c];
+    double sp2 = 0.0, kin = 0.0, g2 = 0.0, div = 0.0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const unsigned cp = C.off(a, 1), cm = C.off(a, -1);
+        const double ua = (double)u[a][c], uap = (double)u[a][cp];
+        const double ub = 0.5 * (ua + uap);
+        sp2 += ub * ub;
+        const double fm = (double)phi[cm];
+        const double rf = 0.5 * ((double)rho_of(P, fm) + (double)rho_of(P, f));
+        kin += 0.5 * rf * ua * ua;
+        const double g = (f - fm) * P.inv_h;
+        g2 += g * g;
+        div += (uap - ua) * P.inv_h;
+    }
+    s[0] = f;
+    s[1] = kin;
+    s[2] = (P.sigma_hat / P.eps) * psi(f) + 0.5 * P.sigma_hat * P.eps * g2;
+    if (p) {
+        if (f > 0.99) { s[3] = p[c]; s[4] = 1.0; }
+        if (f < 0.01) { s[5] = p[c]; s[6] = 1.0; }
+    }
+    mx[0] = sqrt(sp2);
+    mx[1] = fabs(div);
+    mx[2] = -f;
+    mx[3] = f;
+}
+
+}  // namespace tpf

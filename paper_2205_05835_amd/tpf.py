@@ -35,7 +35,10 @@ FIELD = {name: q for q, name in enumerate(FIELDS)}
 EXPORTS = ["tpf_workspace_bytes", "tpf_create", "tpf_destroy", "tpf_set_state", "tpf_init_droplet",
            "tpf_step", "tpf_get_state", "tpf_diagnostics", "tpf_eval_field", "tpf_poisson_solve",
            "tpf_profile_enable", "tpf_profile_read", "tpf_profile_classes", "tpf_last_error",
-           "tpf_version"]
+           "tpf_version", "tpf_batch_workspace_bytes", "tpf_batch_create", "tpf_batch_destroy",
+           "tpf_batch_set_state", "tpf_batch_init_droplet", "tpf_batch_get_state", "tpf_batch_step",
+           "tpf_batch_status", "tpf_batch_clear_status", "tpf_batch_diagnostics", "tpf_batch_configs",
+           "tpf_batch_config_info", "tpf_batch_set_config", "tpf_batch_tune"]
 
 
 class TpfError(RuntimeError):
@@ -100,6 +103,20 @@ def lib():
         "tpf_profile_classes": ([], i32),
         "tpf_last_error": ([], ctypes.c_char_p),
         "tpf_version": ([], ctypes.c_char_p),
+        "tpf_batch_workspace_bytes": ([P, i32, ctypes.POINTER(ctypes.c_size_t)], i32),
+        "tpf_batch_create": ([P, i32, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)], i32),
+        "tpf_batch_destroy": ([vp], i32),
+        "tpf_batch_set_state": ([vp, i32, vp, vp, vp, i32], i32),
+        "tpf_batch_init_droplet": ([vp, i32, dp, dp], i32),
+        "tpf_batch_get_state": ([vp, i32, vp, vp, vp, vp, i32], i32),
+        "tpf_batch_step": ([vp, dp, i32], i32),
+        "tpf_batch_status": ([vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_int64), dp], i32),
+        "tpf_batch_clear_status": ([vp, i32], i32),
+        "tpf_batch_diagnostics": ([vp, ctypes.POINTER(tpf_diag)], i32),
+        "tpf_batch_configs": ([], i32),
+        "tpf_batch_config_info": ([i32, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
+        "tpf_batch_set_config": ([vp, i32], i32),
+        "tpf_batch_tune": ([vp, dp, ctypes.c_char_p, ctypes.POINTER(i32)], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -274,3 +291,116 @@ def solver_for_case(case, **overrides) -> Solver:
               visc1=case.visc1, visc2=case.visc2)
     kw.update(overrides)
     return Solver(make_params(case.n, **kw))
+
+
+def params_for_case(case, **overrides) -> tpf_params:
+    kw = dict(length=case.length, model=case.model, force=case.force, precision=case.precision,
+              sigma=case.sigma, eps=case.eps, gamma=case.gamma, rho1=case.rho1, rho2=case.rho2,
+              visc1=case.visc1, visc2=case.visc2)
+    kw.update(overrides)
+    return make_params(case.n, **kw)
+
+
+def batch_workspace_bytes(params: list) -> int:
+    arr = (tpf_params * len(params))(*params)
+    out = ctypes.c_size_t(0)
+    check(lib().tpf_batch_workspace_bytes(arr, len(params), ctypes.byref(out)), "tpf_batch_workspace_bytes")
+    return int(out.value)
+
+
+def batch_configs() -> list:
+    """[(threads, lds_bytes)] of the batched launch configurations."""
+    out = []
+    for q in range(lib().tpf_batch_configs()):
+        t, b = ctypes.c_int32(), ctypes.c_int32()
+        check(lib().tpf_batch_config_info(q, ctypes.byref(t), ctypes.byref(b)), "tpf_batch_config_info")
+        out.append((t.value, b.value))
+    return out
+
+
+class Batch:
+    """Many independent 2D cases stepped together (one launch per step)."""
+
+    def __init__(self, params: list, stream=None, device=None):
+        import torch
+        self.torch = torch
+        self.params = list(params)
+        self.ncases = len(self.params)
+        self.shapes = [(p.n[1], p.n[0]) for p in self.params]
+        self.device = torch.device(device or "cuda")
+        arr = (tpf_params * self.ncases)(*self.params)
+        nbytes = batch_workspace_bytes(self.params)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        check(lib().tpf_batch_create(arr, self.ncases, ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                                     ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
+              "tpf_batch_create")
+        self.h = h
+
+    def close(self):
+        if self.h:
+            check(lib().tpf_batch_destroy(self.h), "tpf_batch_destroy")
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _dts(self, dt):
+        d = np.ascontiguousarray(np.broadcast_to(np.asarray(dt, dtype=np.float64), (self.ncases,)))
+        return d, d.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+    def set_state(self, q: int, phi, u):
+        N = int(np.prod(self.shapes[q]))
+        a = [_host(phi, N), _host(u[0], N), _host(u[1], N)]
+        ptrs = [x.ctypes.data_as(ctypes.c_void_p) for x in a]
+        check(lib().tpf_batch_set_state(self.h, q, *ptrs, 0), "tpf_batch_set_state")
+
+    def init_droplet(self, q: int, center, semi_axes):
+        c = (ctypes.c_double * 2)(*center[:2])
+        s = (ctypes.c_double * 2)(*semi_axes[:2])
+        check(lib().tpf_batch_init_droplet(self.h, q, c, s), "tpf_batch_init_droplet")
+
+    def get_state(self, q: int, with_pressure: bool = False):
+        shape = self.shapes[q]
+        phi = np.empty(shape)
+        u = [np.empty(shape), np.empty(shape)]
+        p = np.empty(shape) if with_pressure else None
+        ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+        check(lib().tpf_batch_get_state(self.h, q, ptr(phi), ptr(u[0]), ptr(u[1]), ptr(p), 0),
+              "tpf_batch_get_state")
+        return phi, u, p
+
+    def step(self, dt, nsteps: int = 1):
+        d, dp = self._dts(dt)
+        check(lib().tpf_batch_step(self.h, dp, int(nsteps)), "tpf_batch_step")
+
+    def status(self):
+        st = np.zeros(self.ncases, dtype=np.int32)
+        steps = np.zeros(self.ncases, dtype=np.int64)
+        t = np.zeros(self.ncases)
+        check(lib().tpf_batch_status(self.h, st.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                     steps.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                     t.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "tpf_batch_status")
+        return st, steps, t
+
+    def clear_status(self, q: int):
+        check(lib().tpf_batch_clear_status(self.h, q), "tpf_batch_clear_status")
+
+    def diagnostics(self) -> list:
+        out = (tpf_diag * self.ncases)()
+        check(lib().tpf_batch_diagnostics(self.h, out), "tpf_batch_diagnostics")
+        return [out[q].as_dict() for q in range(self.ncases)]
+
+    def set_config(self, config: int):
+        check(lib().tpf_batch_set_config(self.h, int(config)), "tpf_batch_set_config")
+
+    def tune(self, dt, cache_path=None) -> int:
+        d, dp = self._dts(dt)
+        ch = ctypes.c_int32(-1)
+        path = cache_path.encode() if cache_path else None
+        check(lib().tpf_batch_tune(self.h, dp, path, ctypes.byref(ch)), "tpf_batch_tune")
+        return ch.value

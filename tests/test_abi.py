@@ -85,3 +85,20 @@ def test_create_rejects_null_or_small_workspace(tpf):
     st = tpf.lib().tpf_create(ctypes.byref(p), ctypes.c_void_p(256), 16, None, ctypes.byref(ctx))
     assert st == tpf.TPF_ENOMEM
     assert "workspace too small" in tpf.lib().tpf_last_error().decode()
+
+
+def test_batch_workspace_validation(tpf):
+    """Batched cases must be 2D and share one precision; the workspace grows
+    with the cases."""
+    a = tpf.make_params((32, 32))
+    b = tpf.make_params((64, 48))
+    n1 = tpf.batch_workspace_bytes([a])
+    n2 = tpf.batch_workspace_bytes([a, b])
+    assert n2 > n1 > 0
+    with pytest.raises(tpf.TpfError):
+        tpf.batch_workspace_bytes([a, tpf.make_params((8, 8, 8))])
+    with pytest.raises(tpf.TpfError):
+        tpf.batch_workspace_bytes([a, tpf.make_params((32, 32), precision="fp32_mixed")])
+    assert len(tpf.batch_configs()) == tpf.lib().tpf_batch_configs() >= 1
+    for threads, lds in tpf.batch_configs():
+        assert threads in (256, 512, 1024) and 0 <= lds <= 65536 - 1024

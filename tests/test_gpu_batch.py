@@ -1,0 +1,277 @@
+"""GPU tests of the batched persistent form (tpf_batch_*), through the C ABI.
+
+Every case of a batch is compared with the FP64 oracle run on that case
+alone; cases of different size, model, force, density ratio and time step
+share one launch per step.
+"""
+import os
+import sys
+import tempfile
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2205_05835_amd import tpf
+    tpf.lib()
+    return tpf
+
+
+def oparams(ora, case, **kw):
+    base = dict(n=case.n, length=case.length, model=ora.MODELS[case.model],
+                force=ora.FORCES[case.force], sigma=case.sigma, eps=case.eps, gamma=case.gamma,
+                rho1=case.rho1, rho2=case.rho2, visc1=case.visc1, visc2=case.visc2)
+    base.update(kw)
+    return ora.Params(**base)
+
+
+def mixed_cases(precision):
+    C = workloads.Case
+    return [
+        C("b32_cdi_eb", (32, 32), (0.5, 0.5), (0.25, 0.25), 1.0, 0.1, 2e-3, 2e-4, 1.0, 1.0,
+          "CDI", "EB", precision),
+        C("b48_sb_csf", (48, 48), (0.5, 0.5), (0.3, 0.22), 240.0, 0.24, 0.1, 0.001, 1.0, 0.75,
+          "SB", "CSF", precision),
+        C("b40x24_isodi_lcsf", (40, 24), (0.5, 0.3), (0.2, 0.15), 1.0, 0.5, 0.02, 0.01, 0.7, 1.0,
+          "ISODI", "LCSF", precision),
+        C("b16_cdi_lcsf", (16, 16), (0.45, 0.5), (0.3, 0.25), 1.0, 0.01, 0.01, 1e-4, 1.3, 0.9,
+          "CDI", "LCSF", precision),
+        C("b36_cdi_eb", (36, 36), (0.5, 0.55), (0.28, 0.2), 10.0, 1.0, 0.05, 0.005, 2.0, 0.6,
+          "CDI", "EB", precision),
+        C("b64_sb_eb", (64, 64), (0.5, 0.5), (0.25, 0.25), 1.0, 0.1, 2e-3, 2e-4, 1.0, 1.0,
+          "SB", "EB", precision),
+    ]
+
+
+def run_oracle(ora, case, dt, steps, phi0):
+    P = oparams(ora, case)
+    zero = [np.zeros(P.shape)] * 2
+    phi, u, pw = ora.step(P, dt, steps, phi0, zero)
+    _, du, _ = ora.stage(P, phi, u, pw)
+    return P, phi, u, pw, du
+
+
+def uref_of(u, du, dt):
+    return max(max(np.abs(x).max() for x in u), dt * max(np.abs(x).max() for x in du))
+
+
+def test_batch_init_droplet(gpu, ora):
+    cases = mixed_cases("fp64")
+    say(f"batch init_droplet, {len(cases)} cases")
+    b = gpu.Batch([gpu.params_for_case(c) for c in cases])
+    for q, c in enumerate(cases):
+        b.init_droplet(q, c.center, c.semi_axes)
+    for q, c in enumerate(cases):
+        phi, u, _ = b.get_state(q)
+        ref = ora.init_droplet(oparams(ora, c), c.center, c.semi_axes)
+        assert np.abs(phi - ref).max() < 1e-14, c.name
+        assert all(np.abs(x).max() == 0 for x in u)
+
+
+def test_batch_fp64_matches_oracle(gpu, ora):
+    """Six cases of different grids, models, forces, ratios and dt: FP64,
+    3 steps, every case against the oracle to the single-case bounds."""
+    cases = mixed_cases("fp64")
+    steps = 3
+    say(f"batch FP64 parity, {len(cases)} cases x {steps} steps")
+    params = [gpu.params_for_case(c, poisson_rtol=1e-14, poisson_maxit=2000) for c in cases]
+    b = gpu.Batch(params)
+    dts = np.array([c.dt() for c in cases])
+    phi0s = []
+    for q, c in enumerate(cases):
+        phi0 = ora.init_droplet(oparams(ora, c), c.center, c.semi_axes)
+        phi0s.append(phi0)
+        b.set_state(q, phi0, [np.zeros_like(phi0)] * 2)
+    b.step(dts, steps)
+    st, nst, t = b.status()
+    assert (st == 0).all() and (nst == steps).all()
+    assert np.allclose(t, dts * steps, rtol=1e-15)
+    for q, c in enumerate(cases):
+        P, phi_o, u_o, p_o, du_o = run_oracle(ora, c, dts[q], steps, phi0s[q])
+        phi_g, u_g, p_g = b.get_state(q, with_pressure=True)
+        uref = uref_of(u_o, du_o, dts[q])
+        ephi = np.abs(phi_g - phi_o).max()
+        eu = max(np.abs(u_g[a] - u_o[a]).max() for a in range(2)) / uref
+        ep = np.abs(p_g - p_o).max() / np.abs(p_o).max()
+        say(f"  {c.name}: |dphi| {ephi:.2e} |du|/Uref {eu:.2e} |dp|/|p| {ep:.2e}")
+        assert ephi < 1e-12 and eu < 1e-10 and ep < 1e-10, c.name
+
+
+def test_batch_mixed_error_statement(gpu, ora):
+    """FP32-mixed batch against the FP64 oracle (started from the FP32-rounded
+    phi0): the mixed-precision bounds of the single-case path."""
+    cases = mixed_cases("fp32_mixed")
+    steps = 5
+    say(f"batch FP32-mixed error statement, {len(cases)} cases x {steps} steps")
+    b = gpu.Batch([gpu.params_for_case(c) for c in cases])
+    dts = np.array([c.dt() for c in cases])
+    phi0s = []
+    for q, c in enumerate(cases):
+        phi0 = ora.init_droplet(oparams(ora, c), c.center, c.semi_axes)
+        phi0s.append(phi0.astype(np.float32).astype(np.float64))
+        b.set_state(q, phi0s[-1], [np.zeros_like(phi0)] * 2)
+    b.step(dts, steps)
+    for q, c in enumerate(cases):
+        P, phi_o, u_o, p_o, du_o = run_oracle(ora, c, dts[q], steps, phi0s[q])
+        phi_g, u_g, p_g = b.get_state(q, with_pressure=True)
+        uref = uref_of(u_o, du_o, dts[q])
+        ephi = np.abs(phi_g - phi_o).max()
+        eu = max(np.abs(u_g[a] - u_o[a]).max() for a in range(2)) / uref
+        say(f"  {c.name}: |dphi| {ephi:.2e} |du|/Uref {eu:.2e}")
+        assert ephi < 1e-5 and eu < 1e-2, c.name
+
+
+def test_batch_mixed_matches_single_case_path(gpu, ora):
+    """The batched and the single-case FP32-mixed paths compute the same step
+    (they differ in reduction order and preconditioner launch layout only)."""
+    cases = mixed_cases("fp32_mixed")[:3]
+    say("batch vs single-case FP32-mixed")
+    b = gpu.Batch([gpu.params_for_case(c) for c in cases])
+    dts = np.array([c.dt() for c in cases])
+    for q, c in enumerate(cases):
+        b.init_droplet(q, c.center, c.semi_axes)
+    b.step(dts, 4)
+    for q, c in enumerate(cases):
+        s = gpu.solver_for_case(c)
+        s.init_droplet(c.center, c.semi_axes)
+        s.step(dts[q], 4)
+        phi_s, u_s, _ = s.get_state()
+        phi_b, u_b, _ = b.get_state(q)
+        umax = max(np.abs(x).max() for x in u_s) + 1e-300
+        ephi = np.abs(phi_b - phi_s).max()
+        eu = max(np.abs(u_b[a] - u_s[a]).max() for a in range(2)) / umax
+        say(f"  {c.name}: |dphi| {ephi:.2e} |du|/|u| {eu:.2e}")
+        assert ephi < 1e-5 and eu < 1e-2, c.name
+
+
+def test_batch_failure_is_isolated(gpu, ora):
+    """A case whose pressure solve cannot converge stops at its last completed
+    state; the others advance untouched."""
+    cases = mixed_cases("fp64")[:3]
+    say("batch failure isolation")
+    params = [gpu.params_for_case(c, poisson_rtol=1e-14) for c in cases]
+    params[1].poisson_maxit = 1
+    b = gpu.Batch(params)
+    dts = np.array([c.dt() for c in cases])
+    phi0s = []
+    for q, c in enumerate(cases):
+        phi0s.append(ora.init_droplet(oparams(ora, c), c.center, c.semi_axes))
+        b.set_state(q, phi0s[-1], [np.zeros_like(phi0s[-1])] * 2)
+    with pytest.raises(gpu.TpfError) as e:
+        b.step(dts, 2)
+    assert e.value.status == gpu.TPF_ENOCONV
+    st, nst, _ = b.status()
+    assert list(st) == [0, gpu.TPF_ENOCONV, 0]
+    assert list(nst) == [2, 0, 2]
+    phi1, u1, _ = b.get_state(1)
+    assert np.array_equal(phi1, phi0s[1]) and all(np.abs(x).max() == 0 for x in u1)
+    for q in (0, 2):
+        _, phi_o, u_o, _, du_o = run_oracle(ora, cases[q], dts[q], 2, phi0s[q])
+        phi_g, u_g, _ = b.get_state(q)
+        assert np.abs(phi_g - phi_o).max() < 1e-12
+
+
+def test_batch_graph_replay_is_bitwise(gpu):
+    """10 steps in one call (a captured graph of 8 launches, then 2 launches)
+    equal 10 calls of one step, bit for bit."""
+    cases = mixed_cases("fp32_mixed")[:4]
+    say("batch graph replay")
+    dts = np.array([c.dt() for c in cases])
+    outs = []
+    for mode in ("graph", "single"):
+        b = gpu.Batch([gpu.params_for_case(c) for c in cases])
+        for q, c in enumerate(cases):
+            b.init_droplet(q, c.center, c.semi_axes)
+        if mode == "graph":
+            b.step(dts, 10)
+        else:
+            for _ in range(10):
+                b.step(dts, 1)
+        outs.append([b.get_state(q) for q in range(len(cases))])
+        b.close()
+    for q in range(len(cases)):
+        assert np.array_equal(outs[0][q][0], outs[1][q][0])
+        for a in range(2):
+            assert np.array_equal(outs[0][q][1][a], outs[1][q][1][a])
+
+
+def test_batch_launch_configs_agree(gpu, ora):
+    """Every launch configuration computes the same FP64 step (reduction
+    order aside)."""
+    cases = mixed_cases("fp64")[:4]
+    say("batch launch configurations")
+    dts = np.array([c.dt() for c in cases])
+    ref = None
+    for cfg, (threads, lds) in enumerate(gpu.batch_configs()):
+        b = gpu.Batch([gpu.params_for_case(c, poisson_rtol=1e-14) for c in cases])
+        b.set_config(cfg)
+        for q, c in enumerate(cases):
+            b.init_droplet(q, c.center, c.semi_axes)
+        b.step(dts, 2)
+        got = [b.get_state(q) for q in range(len(cases))]
+        b.close()
+        say(f"  config {cfg}: {threads} threads, {lds} B LDS")
+        if ref is None:
+            ref = got
+            continue
+        for q in range(len(cases)):
+            assert np.abs(got[q][0] - ref[q][0]).max() < 1e-13
+            umax = max(np.abs(x).max() for x in ref[q][1]) + 1e-300
+            assert max(np.abs(got[q][1][a] - ref[q][1][a]).max() for a in range(2)) < 1e-9 * umax
+
+
+def test_batch_tuner_cache(gpu):
+    cases = mixed_cases("fp32_mixed")
+    say("batch tuner")
+    dts = np.array([c.dt() for c in cases])
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "tune.txt")
+        b = gpu.Batch([gpu.params_for_case(c) for c in cases])
+        for q, c in enumerate(cases):
+            b.init_droplet(q, c.center, c.semi_axes)
+        chosen = b.tune(dts, path)
+        assert 0 <= chosen < len(gpu.batch_configs())
+        st, nst, _ = b.status()
+        assert (nst == 0).all()                     # tuning does not advance the state
+        lines = open(path).read().split("\n")
+        assert len([x for x in lines if x.strip()]) == 1
+        b2 = gpu.Batch([gpu.params_for_case(c) for c in cases])
+        assert b2.tune(dts, path) == chosen         # read back, not re-timed
+        assert len([x for x in open(path).read().split("\n") if x.strip()]) == 1
+        b.step(dts, 2)
+        assert (b.status()[0] == 0).all()
+
+
+def test_batch_diagnostics_match_single_case(gpu):
+    cases = mixed_cases("fp64")[:3]
+    say("batch diagnostics")
+    dts = np.array([c.dt() for c in cases])
+    b = gpu.Batch([gpu.params_for_case(c, poisson_rtol=1e-14) for c in cases])
+    for q, c in enumerate(cases):
+        b.init_droplet(q, c.center, c.semi_axes)
+    b.step(dts, 3)
+    dg = b.diagnostics()
+    for q, c in enumerate(cases):
+        s = gpu.solver_for_case(c, poisson_rtol=1e-14)
+        s.init_droplet(c.center, c.semi_axes)
+        s.step(dts[q], 3)
+        ds = s.diagnostics()
+        for k in ("mass", "mass0", "se", "phi_min", "phi_max"):
+            assert abs(dg[q][k] - ds[k]) <= 1e-12 * max(abs(ds[k]), 1e-300), (c.name, k)
+        for k in ("ke", "umax", "dp"):
+            assert abs(dg[q][k] - ds[k]) <= 1e-8 * max(abs(ds[k]), 1e-300), (c.name, k)
+        assert dg[q]["step"] == 3
