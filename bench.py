@@ -33,8 +33,7 @@ HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, 8 TB/s
 # for a plain device copy of known size; recorded with a hash of the kernel
 # sources and reported only while the sources still match.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fine_apply_256cubed_traffic.json")
-KERNEL_SOURCES = ("paper_2205_05835_amd/csrc/tpf_poisson.hip", "paper_2205_05835_amd/csrc/tpf_device.hpp",
-                  "paper_2205_05835_amd/csrc/tpf_internal.hpp")
+KERNEL_SOURCES = ("paper_2205_05835_amd/csrc/tpf_poisson.hip", "paper_2205_05835_amd/csrc/tpf_device.hpp")
 
 
 def kernel_source_hash():
@@ -159,6 +158,66 @@ def gpu_run(args):
     return out
 
 
+def batch_run(args):
+    """The batched form on the uneven many-droplet workload: 512 2D drops on
+    grids of 64^2 to 192^2, FP32-mixed, one launch per RK4 step, each case
+    with its own time step; launch shape picked by the tuner."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2205_05835_amd import tpf
+
+    cases = workloads.batched_cases(args.batch_cases)
+    b = tpf.Batch([tpf.params_for_case(c) for c in cases])
+    for q, c in enumerate(cases):
+        b.init_droplet(q, c.center, c.semi_axes)
+    dts = np.array([c.dt() for c in cases])
+    config = b.tune(dts)
+    threads, lds = tpf.batch_configs()[config]
+    failed = None
+    try:
+        b.step(dts, args.batch_warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.step(dts, args.batch_steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    except tpf.TpfError as e:
+        failed = str(e)
+        wall = float("nan")
+    st, nst, _ = b.status()
+    dg = b.diagnostics()
+    cells = sum(c.cells for c in cases)
+    out = {"workload": f"{len(cases)} 2D drops, grids 64^2..192^2 (seeded), FP32-mixed",
+           "cases": len(cases), "cells": cells, "steps": args.batch_steps,
+           "value": round(cells * args.batch_steps / wall, 1) if failed is None else None,
+           "unit": "cell-steps/s", "ms_per_step": round(wall / args.batch_steps * 1e3, 4),
+           "launch_config": {"threads": threads, "lds_bytes": lds},
+           "cases_stopped": int((st != 0).sum()), "error": failed,
+           "phi_min": min(d["phi_min"] for d in dg), "phi_max": max(d["phi_max"] for d in dg),
+           "mean_pcg_iterations_last_solve": float(np.mean([d["poisson_inner"] for d in dg]))}
+    del b
+    if args.batch_compare:
+        # FP32-mixed vs FP64 on a seeded sample of the cases
+        m = args.batch_compare
+        sample = cases[:m]
+        res = {}
+        for prec in ("fp64", "fp32_mixed"):
+            bb = tpf.Batch([tpf.params_for_case(c, precision=prec) for c in sample])
+            for q, c in enumerate(sample):
+                bb.init_droplet(q, c.center, c.semi_axes)
+            bb.step(dts[:m], 5)
+            res[prec] = [bb.get_state(q) for q in range(m)]
+            del bb
+        ephi = max(float(np.abs(res["fp32_mixed"][q][0] - res["fp64"][q][0]).max()) for q in range(m))
+        eu = max(float(max(np.abs(res["fp32_mixed"][q][1][a] - res["fp64"][q][1][a]).max() for a in range(2)) /
+                       (max(np.abs(x).max() for x in res["fp64"][q][1]) + 1e-300)) for q in range(m))
+        out["fp32_vs_fp64_sample"] = {"cases": m, "steps": 5, "phi_max_abs": ephi, "u_max_rel": eu}
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(args):
     """The oracle as it stands, on the host cores, on a bounded sample: the
     same oscillating-drop configuration at 64^3 for 2 RK4 steps."""
@@ -194,6 +253,12 @@ def main():
     ap.add_argument("--cpu-n", type=int, default=64)
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--breakdown-out", default="")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched many-droplet measurement")
+    ap.add_argument("--batch-cases", type=int, default=512)
+    ap.add_argument("--batch-steps", type=int, default=20)
+    ap.add_argument("--batch-warmup", type=int, default=2)
+    ap.add_argument("--batch-compare", type=int, default=16,
+                    help="cases of the FP32-vs-FP64 batch comparison (0: skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -207,6 +272,7 @@ def main():
 
     g = gpu_run(args)
     case = g["case"]
+    batch = None if args.no_batch else batch_run(args)
     cpu = None if args.no_cpu_baseline else cpu_baseline(args)
     dom = g["dom"]
     line = {
@@ -239,6 +305,7 @@ def main():
                                "relres": g["diag"]["poisson_relres"]},
         "fp32_vs_fp64": g.get("fp32_vs_fp64"),
         "adjoint_over_forward": None,
+        "batched": batch,
         "event_ms_per_step": round(g["ev_ms"] / args.steps, 4),
     }
     if args.breakdown_out:
