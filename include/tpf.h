@@ -174,6 +174,44 @@ tpf_status tpf_profile_read(tpf_ctx* ctx, int32_t kernel_class, const char** nam
                             double* total_ms, int64_t* launches, double* bytes_per_launch);
 int32_t tpf_profile_classes(void);
 
+/* ------------------------------------------------------------------ checkpoints
+ * A checkpoint holds the current state (phi, u), the pressure warm start, t
+ * and the step count, in a caller-owned device buffer of
+ * tpf_checkpoint_bytes(); loading it into a context of the same grid and
+ * precision restores that state. */
+tpf_status tpf_checkpoint_bytes(const tpf_ctx* ctx, size_t* bytes);
+tpf_status tpf_save_checkpoint(tpf_ctx* ctx, void* dev_dst);
+tpf_status tpf_load_checkpoint(tpf_ctx* ctx, const void* dev_src);
+
+/* ------------------------------------------------------------------ adjoint
+ * Reverse-mode derivative of the discrete step, written by hand for every
+ * stage operator (2D contexts, CDI model of Table 1, energy-based force of
+ * Eq. 4; other configurations return TPF_EINVAL).  Cotangents are FP64 arrays
+ * of N values laid out as the state (phi at cells, u_a on the lower a-faces);
+ * parameter cotangents are those of sigma and eps (holding the state fixed).
+ *
+ * tpf_stage_adjoint: for one stage evaluation F(y) = (dphi/dt, du/dt) at the
+ * current state y, given the cotangent (lphi, lu0, lu1) of F(y), write
+ * (gphi, gu0, gu1) = F'(y)^T (lphi, lu0, lu1) and ADD dF/d(sigma, eps)^T to
+ * grad_params[0..1].  The state is not changed.
+ *
+ * tpf_step_adjoint: for nsteps steps of size dt starting from the current
+ * state y_0: runs them forward (the context ends at y_nsteps), recording
+ * every stage's input state and pressure on the caller's device buffer
+ * `tape` (tpf_adjoint_tape_bytes(nsteps) bytes), then sweeps back.  On entry
+ * (gphi, gu0, gu1) hold dL/dy_nsteps; on return dL/dy_0, and
+ * dL/d(sigma, eps) over these steps is ADDED to grad_params.  For long
+ * rollouts, checkpoint every K steps and call this once per segment, last
+ * segment first (each from its loaded checkpoint).
+ * on_device: 1 if the cotangent pointers are device pointers. */
+tpf_status tpf_adjoint_tape_bytes(const tpf_ctx* ctx, int32_t nsteps, size_t* bytes);
+tpf_status tpf_stage_adjoint(tpf_ctx* ctx, const double* lphi, const double* lu0, const double* lu1,
+                             double* gphi, double* gu0, double* gu1, double grad_params[2],
+                             int32_t on_device);
+tpf_status tpf_step_adjoint(tpf_ctx* ctx, void* tape, size_t tape_bytes, double dt, int32_t nsteps,
+                            double* gphi, double* gu0, double* gu1, int32_t on_device,
+                            double grad_params[2]);
+
 /* ------------------------------------------------------------------ batches
  * Batched persistent form: many independent 2D cases (each its own grid,
  * properties, model, force and time step; one precision for the whole batch)

@@ -111,7 +111,7 @@ static bool prof_alloc(tpf_ctx* c, int cap) {
 }
 
 // ---------------------------------------------------------------- workspace
-static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Carver {
     char* base;
@@ -188,6 +188,13 @@ static size_t carve(tpf_ctx* c, char* base) {
     c->diag_out = (double*)cv.take(16 * 8);
     c->scal = (SolverScalars*)cv.take(sizeof(SolverScalars));
     c->flags = (int*)cv.take(64);
+    if (c->dim == 2) {
+        c->adj_stride = (long)(align256((size_t)c->N * 8) / 8);
+        c->adj = (double*)cv.take((size_t)ADJ_FIELDS * c->adj_stride * 8 + 256);
+    } else {
+        c->adj = nullptr;
+        c->adj_stride = 0;
+    }
     return cv.off;
 }
 
@@ -385,11 +392,20 @@ static void state_ptrs(tpf_ctx* c, int slot, void** phi, void* u[3]) {
     for (int a = 0; a < 3; ++a) u[a] = c->u[a][slot] ? c->u[a][slot] : c->u[0][slot];
 }
 
-tpf_status tpf_step(tpf_ctx* c, double dt, int32_t nsteps) {
-    if (!c) { set_error("ctx is NULL"); return TPF_EINVAL; }
-    if (!(dt > 0) || nsteps < 0) { set_error("dt must be > 0 and nsteps >= 0"); return TPF_EINVAL; }
+}  // extern "C"
+
+namespace tpf {
+
+static tpf_status copy_async(tpf_ctx* c, void* dst, const void* src, size_t bytes) {
+    hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c->stream);
+    return e == hipSuccess ? TPF_OK : hip_fail(e, "device copy");
+}
+
+tpf_status advance(tpf_ctx* c, double dt, int nsteps, char* tape, size_t stage_bytes) {
     const double wacc[4] = {dt / 6.0, dt / 3.0, dt / 3.0, dt / 6.0};
     const double wnext[4] = {dt / 2.0, dt / 2.0, dt, 0.0};
+    const size_t NT = (size_t)c->N * c->tsz;
+    const size_t fT = align256(NT);
     for (int n = 0; n < nsteps; ++n) {
         hipError_t e = hipMemsetAsync(c->flags, 0, 64, c->stream);
         if (e != hipSuccess) return hip_fail(e, "flag reset");
@@ -401,9 +417,17 @@ tpf_status tpf_step(tpf_ctx* c, double dt, int32_t nsteps) {
             void *u_s[3], *u_o[3];
             state_ptrs(c, in_slot[s], &phi_s, u_s);
             state_ptrs(c, out_slot[s], &phi_o, u_o);
+            char* rec = tape ? tape + ((size_t)n * 4 + s) * stage_bytes : nullptr;
+            if (rec) {
+                tpf_status st = copy_async(c, rec, phi_s, NT);
+                for (int a = 0; a < c->dim && st == TPF_OK; ++a)
+                    st = copy_async(c, rec + (1 + a) * fT, u_s[a], NT);
+                if (st != TPF_OK) return st;
+            }
             RKArgs rk{s, 0, wacc[s], wnext[s]};
             const void* us[3] = {u_s[0], u_s[1], u_s[2]};
             tpf_status st = stage_eval(c, phi_s, us, rk, phi_o, u_o, 0);
+            if (st == TPF_OK && rec) st = copy_async(c, rec + (1 + c->dim) * fT, c->p, (size_t)c->N * 8);
             if (st != TPF_OK) {
                 c->p_valid = 0;
                 return st;
@@ -428,9 +452,21 @@ tpf_status tpf_step(tpf_ctx* c, double dt, int32_t nsteps) {
     return TPF_OK;
 }
 
+}  // namespace tpf
+
+extern "C" {
+
+tpf_status tpf_step(tpf_ctx* c, double dt, int32_t nsteps) {
+    if (!c) { set_error("ctx is NULL"); return TPF_EINVAL; }
+    if (!(dt > 0) || nsteps < 0) { set_error("dt must be > 0 and nsteps >= 0"); return TPF_EINVAL; }
+    return advance(c, dt, nsteps, nullptr, 0);
+}
+
+}  // extern "C"
+
 // Evaluate one stage at the current state without updating it; the
 // derivatives go to the y1 slot and the pressure to c->p.
-static tpf_status eval_current(tpf_ctx* c, int want_force) {
+tpf_status tpf::eval_current(tpf_ctx* c, int want_force) {
     void *phi_s, *phi_o;
     void *u_s[3], *u_o[3];
     state_ptrs(c, c->s_yn, &phi_s, u_s);
@@ -441,6 +477,8 @@ static tpf_status eval_current(tpf_ctx* c, int want_force) {
     if (st == TPF_OK) c->p_valid = 1;
     return st;
 }
+
+extern "C" {
 
 static tpf_status copy_out(tpf_ctx* c, const void* src, int is_double, double* dst, int on_device) {
     hipError_t e;

@@ -141,6 +141,11 @@ struct tpf_ctx {
     long prof_noop[tpf::NPROF];
     double prof_noop_bytes[tpf::NPROF];
 
+    // adjoint scratch (2D contexts): ADJ_FIELDS FP64 cell/face arrays of
+    // adj_stride elements each, then the two parameter-gradient accumulators
+    double* adj;
+    long adj_stride;
+
     // PCG iterations of the previous solve of each kind (0: FP64 solve,
     // 1 + o: inner solve of outer iteration o); the host checks convergence
     // first after that many iterations
@@ -174,6 +179,13 @@ hipError_t launch_diagnostics(tpf_ctx* c, const void* phi, const void* const u[3
 
 // pressure solver (tpf_poisson.hip)
 tpf_status poisson_solve(tpf_ctx* c, const void* phi, int* iters, double* relres, int* outer);
+// advance nsteps RK4 steps; with a tape, record every stage's input state and
+// its pressure (stage_bytes per stage, layout of the adjoint tape)
+tpf_status advance(tpf_ctx* c, double dt, int nsteps, char* tape, size_t stage_bytes);
+// one stage evaluation at the current state (pressure to c->p)
+tpf_status eval_current(tpf_ctx* c, int want_force);
+constexpr int ADJ_FIELDS = 26;
+size_t align256(size_t x);
 hipError_t launch_finalize(tpf_ctx* c, int nblocks, int nv, int op);
 hipError_t launch_rhs_mean(tpf_ctx* c);
 

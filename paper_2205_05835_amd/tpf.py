@@ -38,7 +38,9 @@ EXPORTS = ["tpf_workspace_bytes", "tpf_create", "tpf_destroy", "tpf_set_state", 
            "tpf_version", "tpf_batch_workspace_bytes", "tpf_batch_create", "tpf_batch_destroy",
            "tpf_batch_set_state", "tpf_batch_init_droplet", "tpf_batch_get_state", "tpf_batch_step",
            "tpf_batch_status", "tpf_batch_clear_status", "tpf_batch_diagnostics", "tpf_batch_configs",
-           "tpf_batch_config_info", "tpf_batch_set_config", "tpf_batch_tune"]
+           "tpf_batch_config_info", "tpf_batch_set_config", "tpf_batch_tune", "tpf_checkpoint_bytes",
+           "tpf_save_checkpoint", "tpf_load_checkpoint", "tpf_adjoint_tape_bytes", "tpf_stage_adjoint",
+           "tpf_step_adjoint"]
 
 
 class TpfError(RuntimeError):
@@ -117,6 +119,12 @@ def lib():
         "tpf_batch_config_info": ([i32, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
         "tpf_batch_set_config": ([vp, i32], i32),
         "tpf_batch_tune": ([vp, dp, ctypes.c_char_p, ctypes.POINTER(i32)], i32),
+        "tpf_checkpoint_bytes": ([vp, ctypes.POINTER(ctypes.c_size_t)], i32),
+        "tpf_save_checkpoint": ([vp, vp], i32),
+        "tpf_load_checkpoint": ([vp, vp], i32),
+        "tpf_adjoint_tape_bytes": ([vp, i32, ctypes.POINTER(ctypes.c_size_t)], i32),
+        "tpf_stage_adjoint": ([vp, vp, vp, vp, vp, vp, vp, dp, i32], i32),
+        "tpf_step_adjoint": ([vp, vp, ctypes.c_size_t, ctypes.c_double, i32, vp, vp, vp, i32, dp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -235,6 +243,15 @@ class Solver:
         check(lib().tpf_get_state(self.ctx, ptr(phi), *uu, ptr(p), 0), "tpf_get_state")
         return phi, u, p
 
+    def get_state_device(self):
+        """(phi, [u_a]) as new CUDA float64 tensors of the grid shape."""
+        torch = self.torch
+        phi = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        u = [torch.empty(self.shape, dtype=torch.float64, device=self.device) for _ in range(self.dim)]
+        ptrs = [ctypes.c_void_p(t.data_ptr()) for t in u] + [None] * (3 - self.dim)
+        check(lib().tpf_get_state(self.ctx, ctypes.c_void_p(phi.data_ptr()), *ptrs, None, 1), "tpf_get_state")
+        return phi, u
+
     def diagnostics(self) -> dict:
         d = tpf_diag()
         check(lib().tpf_diagnostics(self.ctx, ctypes.byref(d)), "tpf_diagnostics")
@@ -255,6 +272,62 @@ class Solver:
                                       x.ctypes.data_as(ctypes.c_void_p), 0, ctypes.byref(it),
                                       ctypes.byref(rr)), "tpf_poisson_solve")
         return x.reshape(self.shape), it.value, rr.value
+
+    # ---------------------------------------------------------------- checkpoints
+    def checkpoint_bytes(self) -> int:
+        out = ctypes.c_size_t(0)
+        check(lib().tpf_checkpoint_bytes(self.ctx, ctypes.byref(out)), "tpf_checkpoint_bytes")
+        return int(out.value)
+
+    def save_checkpoint(self, buf=None):
+        """Save the state into a device uint8 tensor (allocated if None)."""
+        if buf is None:
+            buf = self.torch.empty(self.checkpoint_bytes(), dtype=self.torch.uint8, device=self.device)
+        check(lib().tpf_save_checkpoint(self.ctx, ctypes.c_void_p(buf.data_ptr())), "tpf_save_checkpoint")
+        return buf
+
+    def load_checkpoint(self, buf):
+        check(lib().tpf_load_checkpoint(self.ctx, ctypes.c_void_p(buf.data_ptr())), "tpf_load_checkpoint")
+
+    # ---------------------------------------------------------------- adjoint
+    def tape_bytes(self, nsteps: int) -> int:
+        out = ctypes.c_size_t(0)
+        check(lib().tpf_adjoint_tape_bytes(self.ctx, int(nsteps), ctypes.byref(out)), "tpf_adjoint_tape_bytes")
+        return int(out.value)
+
+    def stage_adjoint(self, lphi, lu):
+        """F'(y)^T (lphi, lu) of one stage evaluation at the current state:
+        (gphi, [gu0, gu1], [d/dsigma, d/deps]) as host arrays."""
+        a = [_host(lphi, self.N), _host(lu[0], self.N), _host(lu[1], self.N)]
+        out = [np.empty(self.shape) for _ in range(3)]
+        gp = (ctypes.c_double * 2)(0.0, 0.0)
+        ptr = lambda x: x.ctypes.data_as(ctypes.c_void_p)
+        check(lib().tpf_stage_adjoint(self.ctx, *[ptr(x) for x in a], *[ptr(x) for x in out], gp, 0),
+              "tpf_stage_adjoint")
+        return out[0], out[1:], [gp[0], gp[1]]
+
+    def step_adjoint(self, dt: float, nsteps: int, gphi, gu, tape=None, grad_params=None):
+        """Run nsteps from the current state recording a tape, then sweep
+        back: returns (dL/dphi_0, [dL/du_0], grad_params + dL/d(sigma, eps)).
+        gphi, gu: dL/dy at the end (host arrays or CUDA float64 tensors)."""
+        torch = self.torch
+        if tape is None:
+            tape = torch.empty(max(self.tape_bytes(nsteps), 1), dtype=torch.uint8, device=self.device)
+        gp = (ctypes.c_double * 2)(*(grad_params if grad_params is not None else (0.0, 0.0)))
+        if isinstance(gphi, torch.Tensor):
+            arrs = [gphi.contiguous().clone()] + [x.contiguous().clone() for x in gu]
+            for t in arrs:
+                if t.dtype != torch.float64 or not t.is_cuda:
+                    raise ValueError("device cotangents must be float64 CUDA tensors")
+            ptrs = [ctypes.c_void_p(t.data_ptr()) for t in arrs]
+            check(lib().tpf_step_adjoint(self.ctx, ctypes.c_void_p(tape.data_ptr()), tape.numel(), float(dt),
+                                         int(nsteps), *ptrs, 1, gp), "tpf_step_adjoint")
+            return arrs[0], arrs[1:], [gp[0], gp[1]]
+        arrs = [_host(gphi, self.N).copy(), _host(gu[0], self.N).copy(), _host(gu[1], self.N).copy()]
+        ptrs = [a.ctypes.data_as(ctypes.c_void_p) for a in arrs]
+        check(lib().tpf_step_adjoint(self.ctx, ctypes.c_void_p(tape.data_ptr()), tape.numel(), float(dt),
+                                     int(nsteps), *ptrs, 0, gp), "tpf_step_adjoint")
+        return (arrs[0].reshape(self.shape), [x.reshape(self.shape) for x in arrs[1:]], [gp[0], gp[1]])
 
     # ---------------------------------------------------------------- profiling
     def profile_enable(self, mask: int = -1):
