@@ -218,6 +218,52 @@ def batch_run(args):
     return out
 
 
+def adjoint_run(args):
+    """Adjoint/forward time on the 256^2 oscillating ellipse (0.30, 0.22),
+    density ratio 10, FP32-mixed: a rollout of K steps with a checkpoint every
+    `every` steps, loss = h^2/2 sum (phi_T - phi_target)^2 with the target a
+    seeded perturbed ellipse; backward = checkpoint reloads, recomputation
+    with a tape and the hand-written adjoint sweep."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2205_05835_amd import adjoint, tpf
+
+    case = workloads.oscillating_drop_2d(256, args.adjoint_precision)
+    dt = case.dt()
+    params = tpf.params_for_case(case)
+    s0 = tpf.solver_for_case(case)
+    s0.init_droplet(case.center, case.semi_axes)
+    phi0, u0 = s0.get_state_device()
+    xi = np.random.default_rng(1).normal(size=2)
+    axes = (case.semi_axes[0] * (1 + 0.05 * xi[0]), case.semi_axes[1] * (1 + 0.05 * xi[1]))
+    s0.init_droplet(case.center, axes)
+    tgt, _ = s0.get_state_device()
+    del s0
+    f0 = phi0.clone().requires_grad_(True)
+    uu = [x.clone().requires_grad_(True) for x in u0]
+    sig = torch.tensor(case.sigma, dtype=torch.float64, requires_grad=True)
+    eps = torch.tensor(case.eps, dtype=torch.float64, requires_grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    phi, u = adjoint.rollout(f0, uu, sig, eps, params, dt, args.adjoint_steps, args.adjoint_every)
+    loss = 0.5 * case.h ** 2 * ((phi - tgt) ** 2).sum()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    loss.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    out = {"workload": f"{case.name}, {args.adjoint_precision}, {args.adjoint_steps} steps, "
+                       f"checkpoint every {args.adjoint_every}",
+           "forward_s": round(t1 - t0, 4), "backward_s": round(t2 - t1, 4),
+           "adjoint_over_forward": round((t2 - t1) / (t1 - t0), 4),
+           "loss": float(loss.detach()), "dL_dsigma": float(sig.grad), "dL_deps": float(eps.grad),
+           "dL_dphi0_norm": float(f0.grad.norm())}
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(args):
     """The oracle as it stands, on the host cores, on a bounded sample: the
     same oscillating-drop configuration at 64^3 for 2 RK4 steps."""
@@ -254,6 +300,10 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--breakdown-out", default="")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched many-droplet measurement")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward measurement")
+    ap.add_argument("--adjoint-steps", type=int, default=500)
+    ap.add_argument("--adjoint-every", type=int, default=50)
+    ap.add_argument("--adjoint-precision", default="fp32_mixed", choices=["fp32_mixed", "fp64"])
     ap.add_argument("--batch-cases", type=int, default=512)
     ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--batch-warmup", type=int, default=2)
@@ -273,6 +323,7 @@ def main():
     g = gpu_run(args)
     case = g["case"]
     batch = None if args.no_batch else batch_run(args)
+    adj = None if args.no_adjoint else adjoint_run(args)
     cpu = None if args.no_cpu_baseline else cpu_baseline(args)
     dom = g["dom"]
     line = {
@@ -304,7 +355,8 @@ def main():
         "poisson_last_solve": {"outer": g["diag"]["poisson_outer"], "inner": g["diag"]["poisson_inner"],
                                "relres": g["diag"]["poisson_relres"]},
         "fp32_vs_fp64": g.get("fp32_vs_fp64"),
-        "adjoint_over_forward": None,
+        "adjoint_over_forward": adj["adjoint_over_forward"] if adj else None,
+        "adjoint": adj,
         "batched": batch,
         "event_ms_per_step": round(g["ev_ms"] / args.steps, 4),
     }

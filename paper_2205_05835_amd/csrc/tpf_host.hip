@@ -236,6 +236,8 @@ static void init_geometry(tpf_ctx* c, const tpf_params* P) {
     c->march = (m && m[0] == '0') ? 0 : 1;
     const char* tl = std::getenv("TPF_TAIL");
     c->no_tail = (tl && tl[0] == '0') ? 1 : 0;
+    const char* kzs = std::getenv("TPF_KZ");
+    c->kz_override = kzs ? std::atoi(kzs) : 0;
     const char* xt = std::getenv("TPF_XCD_TILES");
     g_xcd_tiles = (xt && xt[0] == '0') ? 0 : 1;
     c->nlev = plan_levels(c);

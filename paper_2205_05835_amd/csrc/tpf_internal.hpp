@@ -150,6 +150,7 @@ struct tpf_ctx {
     // 1 + o: inner solve of outer iteration o); the host checks convergence
     // first after that many iterations
     int pred_iters[4];
+    int kz_override;     // planes per block of the z-marching kernels (0: automatic)
 };
 
 namespace tpf {

@@ -758,9 +758,8 @@ __device__ __forceinline__ S apply7(const S* bl, const S* bh, const Nbr7<S>& x, 
 
 // Marches the half density and one field F along the column, software
 // pipelined: while plane k is computed, the in-plane neighbours and per-cell
-// operands (pre) of plane k+1 and the column values of plane k+2 are already
-// in flight, so each wave waits for memory about once per block rather than
-// once per plane.  F(idx, i, j, k) returns the field at a cell; pre(c)
+// operands (pre) of planes k+1 and k+2 and the column values up to plane k+3
+// are already in flight, so a wave keeps two planes of loads outstanding.  F(idx, i, j, k) returns the field at a cell; pre(c)
 // returns the per-cell operands the body needs; body(k, c, rho7, f7, e) is
 // called once per plane.
 template <typename S>
@@ -790,57 +789,67 @@ __device__ __forceinline__ void march(const Col& q, const Coef& cf, int k0, int 
         }
         return s;
     };
-    const int km = q.kwrap(k0 - 1), kp = q.kwrap(k0 + 1);
-    S hm = cf.hr(q.at(km)), hc = cf.hr(q.at(k0)), hp = cf.hr(q.at(kp));
-    S fm = S(0), fc = S(0), fp = S(0);
-    if (WITH_FIELD) {
-        fm = fld(q.at(km), q.i, q.j, km);
-        fc = fld(q.at(k0), q.i, q.j, k0);
-        fp = fld(q.at(kp), q.i, q.j, kp);
+    auto hcol = [&](int k) { return cf.hr(q.at(q.kwrap(k))); };
+    auto fcol = [&](int k) {
+        const int kk = q.kwrap(k);
+        return WITH_FIELD ? fld(q.at(kk), q.i, q.j, kk) : S(0);
+    };
+    // column values of planes k-1 .. k+2 and the plane data of k and k+1
+    // are in flight when plane k is computed (two planes of lookahead)
+    S h0 = hcol(k0 - 1), h1 = hcol(k0), h2 = hcol(k0 + 1), h3 = hcol(k0 + 2);
+    S f0 = fcol(k0 - 1), f1 = fcol(k0), f2 = fcol(k0 + 1), f3 = fcol(k0 + 2);
+    Side<S> s0 = side(k0);
+    E e0 = pre(q.at(k0));
+    Side<S> s1 = s0;
+    E e1 = e0;
+    if (k0 + 1 < k1) {
+        s1 = side(k0 + 1);
+        e1 = pre(q.at(k0 + 1));
     }
-    Side<S> sc = side(k0);
-    E ec = pre(q.at(k0));
     for (int k = k0; k < k1; ++k) {
-        // issue the loads of the next planes first
-        Side<S> sn = sc;
-        E en = ec;
-        S hpp = hp, fpp = fp;
-        if (k + 1 < k1) {
-            const int kn = q.kwrap(k + 1), knn = q.kwrap(k + 2);
-            sn = side(kn);
-            en = pre(q.at(kn));
-            hpp = cf.hr(q.at(knn));
-            if (WITH_FIELD) fpp = fld(q.at(knn), q.i, q.j, knn);
+        // issue the loads of plane k+2 (and the column of k+3) first
+        Side<S> s2 = s1;
+        E e2 = e1;
+        S h4 = h3, f4 = f3;
+        if (k + 2 < k1) {
+            s2 = side(k + 2);
+            e2 = pre(q.at(k + 2));
+            h4 = hcol(k + 3);
+            f4 = fcol(k + 3);
         }
         // plane k from registers and neighbouring lanes
-        const S lhm = lane_m(hc), lhp = lane_p(hc);
+        const S lhm = lane_m(h1), lhp = lane_p(h1);
         Nbr7<S> R, X;
-        R.c = hc;
-        R.zm = hm;
-        R.zp = hp;
-        R.xm = q.sxm ? lhm : sc.hxm;
-        R.xp = q.sxp ? lhp : sc.hxp;
-        R.ym = sc.hym;
-        R.yp = sc.hyp;
+        R.c = h1;
+        R.zm = h0;
+        R.zp = h2;
+        R.xm = q.sxm ? lhm : s0.hxm;
+        R.xp = q.sxp ? lhp : s0.hxp;
+        R.ym = s0.hym;
+        R.yp = s0.hyp;
         if (WITH_FIELD) {
-            const S lfm = lane_m(fc), lfp = lane_p(fc);
-            X.c = fc;
-            X.zm = fm;
-            X.zp = fp;
-            X.xm = q.sxm ? lfm : sc.fxm;
-            X.xp = q.sxp ? lfp : sc.fxp;
-            X.ym = sc.fym;
-            X.yp = sc.fyp;
+            const S lfm = lane_m(f1), lfp = lane_p(f1);
+            X.c = f1;
+            X.zm = f0;
+            X.zp = f2;
+            X.xm = q.sxm ? lfm : s0.fxm;
+            X.xp = q.sxp ? lfp : s0.fxp;
+            X.ym = s0.fym;
+            X.yp = s0.fyp;
         }
-        body(k, q.at(k), R, X, ec);
-        hm = hc;
-        hc = hp;
-        hp = hpp;
-        fm = fc;
-        fc = fp;
-        fp = fpp;
-        sc = sn;
-        ec = en;
+        body(k, q.at(k), R, X, e0);
+        h0 = h1;
+        h1 = h2;
+        h2 = h3;
+        h3 = h4;
+        f0 = f1;
+        f1 = f2;
+        f2 = f3;
+        f3 = f4;
+        s0 = s1;
+        s1 = s2;
+        e0 = e1;
+        e1 = e2;
     }
 }
 
@@ -1086,6 +1095,7 @@ struct Solver {
     bool march0() const { return dim == 3 && c->march; }
     int kz() const {
         const int nz = c->lv[0].n[2];
+        if (c->kz_override > 0 && c->kz_override % 2 == 0 && nz % c->kz_override == 0) return c->kz_override;
         for (int k : {8, 4, 2})
             if (nz % k == 0) return k;
         return 1;
