@@ -11,6 +11,7 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: long-running oracle check")
+    config.addinivalue_line("markers", "fullsize: GPU parity at the full workload sizes")
 
 
 @pytest.fixture(scope="session")

@@ -1,0 +1,258 @@
+"""Parity at the full workload sizes, in the launch configuration the
+benchmark times (default kernels, FP32-mixed for the 256^3 drop and the
+512-case batch).
+
+The oracle computes every local operator of a stage at 256^3 cell by cell;
+the pressure solve, which the oracle cannot finish at that size, is checked
+through properties that hold at any size (zero mean, discrete divergence of
+the projected derivative, symmetry of the symmetric drop).  FP32 results are
+compared with FP64 ones to a bound derived from FP32 rounding of the terms
+each operator combines (2^-24 relative per operation, times a margin of
+16).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = [pytest.mark.gpu, pytest.mark.fullsize]
+
+F32 = 2.0 ** -24
+MARGIN = 16.0
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2205_05835_amd import tpf
+    tpf.lib()
+    return tpf
+
+
+def oparams(ora, case, **kw):
+    base = dict(n=case.n, length=case.length, model=ora.MODELS[case.model],
+                force=ora.FORCES[case.force], sigma=case.sigma, eps=case.eps, gamma=case.gamma,
+                rho1=case.rho1, rho2=case.rho2, visc1=case.visc1, visc2=case.visc2)
+    base.update(kw)
+    return ora.Params(**base)
+
+
+def grad_face(q, a, h, dim):
+    """G_a q = (q[c] - q[c - e_a]) / h on the C-order array (axis of a = dim-1-a)."""
+    ax = dim - 1 - a
+    return (q - np.roll(q, 1, axis=ax)) / h
+
+
+def div_faces(F, h, dim):
+    return sum((np.roll(F[a], -1, axis=dim - 1 - a) - F[a]) / h for a in range(dim))
+
+
+def test_fullsize_3d_stage_fields(gpu, ora):
+    """256^3 oscillating drop, FP32-mixed, at the initial state: every local
+    operator against the FP64 oracle on the same (FP32-rounded) phi."""
+    case = workloads.oscillating_drop_3d(256, "fp32_mixed")
+    say(f"full-size stage fields {case.n} FP32-mixed")
+    s = gpu.solver_for_case(case)
+    s.init_droplet(case.center, case.semi_axes)
+    phi, u, _ = s.get_state()
+    assert all(np.abs(x).max() == 0 for x in u)
+    P = oparams(ora, case)
+    h, dim = case.h, 3
+    # oracle, operator by operator
+    n_o, gmag = ora.normals(P, phi)
+    mu_o = ora.chem_potential(P, phi)
+    r_o = ora.cdi_flux(P, phi)
+    dphi_o = ora.phase_rhs(P, phi, u)
+    F_o = ora.surface_force(P, phi)
+    m_o = ora.mass_flux(P, phi, u)
+    f_o = ora.fstar(P, phi, u)
+    b_o = ora.divergence(P, f_o)
+    # term scales of each operator
+    gmax = max(np.abs(grad_face(phi, a, h, dim)).max() for a in range(dim))
+    lap = sum(grad_face(np.roll(phi, -1, axis=dim - 1 - a), a, h, dim) - grad_face(phi, a, h, dim)
+              for a in range(dim)) / h
+    sh = 6.0 * case.sigma
+    s_mu = max(np.abs(sh / case.eps * phi * (1 - phi) * (1 - 2 * phi)).max(), np.abs(sh * case.eps * lap).max())
+    s_r = case.gamma * max(case.eps * gmax, 0.25)
+    s_F = s_mu * gmax
+    beta_max = 1.0 / min(case.rho1, case.rho2)
+    checks = [
+        ("MU", mu_o, s_mu), ("DPHI", dphi_o, 2 * dim * s_r / h),
+        ("CDIFLUX0", r_o[0], s_r), ("CDIFLUX1", r_o[1], s_r), ("CDIFLUX2", r_o[2], s_r),
+        ("MASSFLUX0", m_o[0], abs(case.rho1 - case.rho2) * s_r),
+        ("MASSFLUX1", m_o[1], abs(case.rho1 - case.rho2) * s_r),
+        ("MASSFLUX2", m_o[2], abs(case.rho1 - case.rho2) * s_r),
+        ("FORCE0", F_o[0], s_F), ("FORCE1", F_o[1], s_F), ("FORCE2", F_o[2], s_F),
+        ("FSTAR0", f_o[0], s_F * beta_max), ("FSTAR1", f_o[1], s_F * beta_max),
+        ("FSTAR2", f_o[2], s_F * beta_max), ("DIVFSTAR", b_o, 2 * dim * s_F * beta_max / h),
+    ]
+    for name, ref, scale in checks:
+        got = s.eval_field(name)
+        err = np.abs(got - ref).max()
+        say(f"  {name}: max|err| {err:.3e}  bound {MARGIN * F32 * scale:.3e}  max|ref| {np.abs(ref).max():.3e}")
+        assert err <= MARGIN * F32 * scale, name
+        del got
+    # normals where the gradient is resolved (|n| ~ 1; elsewhere FP32 underflow of g.g is expected)
+    band = gmag > 1e-3 * gmag.max()
+    for a in range(dim):
+        got = s.eval_field(f"NORMAL{a}")
+        err = np.abs(got - n_o[a])[band].max()
+        say(f"  NORMAL{a} (interface band, {band.mean():.2%} of cells): max|err| {err:.3e}")
+        assert err <= 1e-5
+        del got
+    # pressure and projection: properties
+    p = s.eval_field("PRESSURE")
+    du = [s.eval_field(f"DU{a}") for a in range(dim)]
+    assert abs(p.mean()) <= 1e-9 * np.abs(p).max()
+    ddu = div_faces(du, h, dim)
+    say(f"  max|D du| {np.abs(ddu).max():.3e}  max|D f*| {np.abs(b_o).max():.3e}")
+    assert np.abs(ddu).max() <= 1e-5 * np.abs(b_o).max()
+    # the drop (phi = 1) is at higher pressure; ellipsoid (0.30, 0.25, 0.25), sigma = 1:
+    # mean curvature between 2/0.30 and 2/0.25, so dp between ~6 and 8 (+ O(eps) smearing)
+    d = s.diagnostics()
+    say(f"  dp {d['dp']:.4f}")
+    assert 4.0 < d["dp"] < 10.0
+
+
+def test_fullsize_3d_step_properties(gpu):
+    """256^3 drop, two FP32-mixed steps: mass conservation of CDI, bounded phi,
+    the y<->z swap symmetry and the x mirror symmetry of the centred
+    ellipsoid (0.30, 0.25, 0.25), divergence-free velocity."""
+    case = workloads.oscillating_drop_3d(256, "fp32_mixed")
+    say(f"full-size step properties {case.n}")
+    s = gpu.solver_for_case(case)
+    s.init_droplet(case.center, case.semi_axes)
+    s.step(case.dt(), 2)
+    d = s.diagnostics()
+    say(f"  mass drift {abs(d['mass'] - d['mass0']) / d['mass0']:.2e} phi [{d['phi_min']:.3e}, {d['phi_max']:.6f}] "
+        f"umax {d['umax']:.3e} div_max {d['div_max']:.3e}")
+    assert abs(d["mass"] - d["mass0"]) <= 1e-7 * d["mass0"]
+    assert d["phi_min"] > -1e-5 and d["phi_max"] < 1 + 1e-5
+    phi, u, _ = s.get_state()
+    ux, uy, uz = u
+    umax = max(np.abs(x).max() for x in u)
+    assert d["div_max"] * case.h <= 1e-5 * umax
+    # y <-> z swap: phi(z, y, x) = phi(y, z, x); u_y <-> u_z
+    sw = lambda q: np.swapaxes(q, 0, 1)
+    e_phi = np.abs(phi - sw(phi)).max()
+    e_u = max(np.abs(ux - sw(ux)).max(), np.abs(uy - sw(uz)).max()) / umax
+    # x mirror about the centre: cell i <-> N-1-i; x face i <-> face N-i, sign flipped
+    mir = lambda q: q[:, :, ::-1]
+    e_mphi = np.abs(phi - mir(phi)).max()
+    ux_m = -np.roll(ux[:, :, ::-1], 1, axis=2)
+    e_mu = max(np.abs(ux - ux_m).max(), np.abs(uy - mir(uy)).max(), np.abs(uz - mir(uz)).max()) / umax
+    say(f"  swap: phi {e_phi:.2e} u {e_u:.2e}   mirror: phi {e_mphi:.2e} u {e_mu:.2e}")
+    assert e_phi < 1e-6 and e_mphi < 1e-6
+    assert e_u < 1e-4 and e_mu < 1e-4
+
+
+def test_fullsize_2d_ratio1000(gpu, ora):
+    """256^2 static drop at density ratio 1000 and viscosity ratio 100 (the
+    2D size of the model/force comparison), FP64: stage fields of one pair
+    per model against the oracle, and the pressure of one pair."""
+    pairs = [("CDI", "EB"), ("SB", "CSF"), ("ISODI", "LCSF")]
+    for model, force in pairs:
+        case = workloads.static_drop_ratio(256, 0.75, model, force)
+        say(f"full-size 2D {case.name}")
+        P = oparams(ora, case)
+        phi = ora.init_droplet(P, case.center, case.semi_axes)
+        u = workloads.random_velocity(P.shape, 5, amplitude=0.05)
+        s = gpu.solver_for_case(case, poisson_rtol=1e-14, poisson_maxit=4000)
+        s.set_state(phi, u)
+        names = ["DPHI", "FSTAR0", "FSTAR1", "DIVFSTAR", "FORCE0", "FORCE1", "MASSFLUX0", "MASSFLUX1"]
+        refs = {"DPHI": ora.phase_rhs(P, phi, u), "DIVFSTAR": None}
+        f = ora.fstar(P, phi, u)
+        refs["FSTAR0"], refs["FSTAR1"] = f
+        refs["DIVFSTAR"] = ora.divergence(P, f)
+        F = ora.surface_force(P, phi)
+        refs["FORCE0"], refs["FORCE1"] = F
+        m = ora.mass_flux(P, phi, u)
+        refs["MASSFLUX0"], refs["MASSFLUX1"] = m
+        for name in names:
+            got = s.eval_field(name)
+            ref = refs[name]
+            e = np.abs(got - ref).max() / np.abs(ref).max()
+            assert e < 1e-12, (name, e)
+        say(f"  stage fields within 1e-12")
+        if model == "CDI":
+            _, du_o, p_o = ora.stage(P, phi, u)
+            p_g = s.eval_field("PRESSURE")
+            ep = np.abs(p_g - p_o).max() / np.abs(p_o).max()
+            du_g = [s.eval_field(f"DU{a}") for a in range(2)]
+            eu = max(np.abs(du_g[a] - du_o[a]).max() for a in range(2)) / max(np.abs(x).max() for x in du_o)
+            say(f"  pressure {ep:.2e}  du/dt {eu:.2e}")
+            assert ep < 1e-10 and eu < 1e-10
+
+
+def test_fullsize_batch_512(gpu):
+    """The 512-case batch of the benchmark, FP32-mixed, 3 steps: every case
+    completes, conserves mass, stays bounded; one case of each grid size
+    matches the single-case path."""
+    cases = workloads.batched_cases(512)
+    say(f"full-size batch, {len(cases)} cases")
+    b = gpu.Batch([gpu.params_for_case(c) for c in cases])
+    for q, c in enumerate(cases):
+        b.init_droplet(q, c.center, c.semi_axes)
+    dts = np.array([c.dt() for c in cases])
+    b.step(dts, 3)
+    st, nst, _ = b.status()
+    assert (st == 0).all() and (nst == 3).all()
+    dg = b.diagnostics()
+    drift = max(abs(d["mass"] - d["mass0"]) / d["mass0"] for d in dg)
+    lo = min(d["phi_min"] for d in dg)
+    hi = max(d["phi_max"] for d in dg)
+    say(f"  max mass drift {drift:.2e}  phi [{lo:.3e}, {hi:.6f}]")
+    assert drift < 3e-7 and lo > -1e-3 and hi < 1 + 1e-3
+    seen = set()
+    for q, c in enumerate(cases):
+        if c.n[0] in seen:
+            continue
+        seen.add(c.n[0])
+        s = gpu.solver_for_case(c)
+        s.init_droplet(c.center, c.semi_axes)
+        s.step(dts[q], 3)
+        phi_s, u_s, _ = s.get_state()
+        phi_b, u_b, _ = b.get_state(q)
+        umax = max(np.abs(x).max() for x in u_s)
+        ephi = np.abs(phi_b - phi_s).max()
+        eu = max(np.abs(u_b[a] - u_s[a]).max() for a in range(2)) / umax
+        say(f"  case {q} ({c.n[0]}^2): |dphi| {ephi:.2e} |du|/|u| {eu:.2e}")
+        assert ephi < 1e-6 and eu < 1e-5
+
+
+def test_fullsize_adjoint_dot_product(gpu):
+    """The adjoint workload's grid (256^2 ellipse, density ratio 10), FP64:
+    the stage transpose against central differences of the stage."""
+    case = workloads.oscillating_drop_2d(256, "fp64")
+    say(f"full-size stage adjoint {case.n}")
+    s = gpu.solver_for_case(case, poisson_rtol=1e-14, poisson_maxit=4000)
+    s.init_droplet(case.center, case.semi_axes)
+    phi, _, _ = s.get_state()
+    shape = phi.shape
+    u = workloads.random_velocity(shape, 8, amplitude=0.05)
+    lphi = workloads.smooth_field(shape, 9)
+    lu = workloads.random_velocity(shape, 10, amplitude=1.0)
+    v = 4 * phi * (1 - phi) * workloads.smooth_field(shape, 11)
+    v /= np.abs(v).max()
+    vu = workloads.random_velocity(shape, 12, amplitude=1.0)
+    s.set_state(phi, u)
+    gphi, gu, _ = s.stage_adjoint(lphi, lu)
+    hh = 1e-5
+    outs = []
+    for sgn in (1, -1):
+        s.set_state(phi + sgn * hh * v, [u[a] + sgn * hh * vu[a] for a in range(2)])
+        outs.append([s.eval_field("DPHI"), s.eval_field("DU0"), s.eval_field("DU1")])
+    jv = [(outs[0][k] - outs[1][k]) / (2 * hh) for k in range(3)]
+    lhs = sum(float(np.vdot(x.ravel(), y.ravel())) for x, y in zip([lphi] + lu, jv))
+    rhs = sum(float(np.vdot(x.ravel(), y.ravel())) for x, y in zip([gphi] + gu, [v] + vu))
+    say(f"  <l, J v> {lhs:.10e}  <J^T l, v> {rhs:.10e}  rel {abs(lhs - rhs) / abs(lhs):.2e}")
+    assert abs(lhs - rhs) <= 1e-6 * abs(lhs)
