@@ -102,6 +102,7 @@ def gpu_run(args):
 
     # timed region: K steps, events around the dominant class only
     s.profile_enable(1 << dom_bit)
+    s.solver_stats(reset=True)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -115,6 +116,7 @@ def gpu_run(args):
     ev_ms = ev0.elapsed_time(ev1)
     dom = s.profile_read()[dominant]
     s.profile_enable(0)
+    stats = s.solver_stats()
     diag = s.diagnostics()
 
     cells = case.cells
@@ -123,7 +125,7 @@ def gpu_run(args):
     achieved = dom["bytes_per_launch"] / mean_launch_s / 1e9 if mean_launch_s > 0 else 0.0
     out = {
         "case": case, "dt": dt, "value": value, "wall": wall, "ev_ms": ev_ms, "diag": diag,
-        "dominant": dominant, "dom": dom, "achieved": achieved,
+        "dominant": dominant, "dom": dom, "achieved": achieved, "stats": stats,
         "breakdown": {k: round(v["ms"], 4) for k, v in sorted(prof_all.items(), key=lambda kv: -kv[1]["ms"]) if v["launches"]},
         "breakdown_launches": {k: v["launches"] for k, v in prof_all.items() if v["launches"]},
     }
@@ -354,6 +356,9 @@ def main():
         "cpu_baseline": cpu,
         "poisson_last_solve": {"outer": g["diag"]["poisson_outer"], "inner": g["diag"]["poisson_inner"],
                                "relres": g["diag"]["poisson_relres"]},
+        "poisson_timed": {"solves": g["stats"]["solves"],
+                          "outer_per_solve": round(g["stats"]["outer"] / max(g["stats"]["solves"], 1), 3),
+                          "pcg_iterations_per_solve": round(g["stats"]["inner"] / max(g["stats"]["solves"], 1), 3)},
         "fp32_vs_fp64": g.get("fp32_vs_fp64"),
         "adjoint_over_forward": adj["adjoint_over_forward"] if adj else None,
         "adjoint": adj,

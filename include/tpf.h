@@ -162,6 +162,11 @@ tpf_status tpf_eval_field(tpf_ctx* ctx, int32_t field, double* out, int32_t on_d
 tpf_status tpf_poisson_solve(tpf_ctx* ctx, const double* b, double* x, int32_t on_device,
                              int32_t* iters, double* relres);
 
+/* Pressure-solve counters since creation or the last reset: out[0] solves,
+ * out[1] outer (defect-correction) iterations, out[2] PCG iterations.
+ * reset = 1 zeroes them after reading. */
+tpf_status tpf_solver_stats(tpf_ctx* ctx, int64_t out[3], int32_t reset);
+
 /* Per-kernel-class device timing: HIP events recorded on the context stream
  * around every launch of the selected classes (the class list is fixed; see
  * tpf_profile_read for names).  enable = bit mask of classes (bit q selects

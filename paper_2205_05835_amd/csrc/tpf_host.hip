@@ -383,6 +383,9 @@ static tpf_status stage_eval(tpf_ctx* c, const void* phi_s, const void* const u_
     c->last_inner = it;
     c->last_outer = outer;
     c->last_relres = rr;
+    c->stat_solves += 1;
+    c->stat_outer += outer;
+    c->stat_inner += it;
     if (st != TPF_OK) return st;
     e = launch_project_update(c, phi_s, rk, u_out);
     if (e != hipSuccess) return hip_fail(e, "projection");
@@ -618,6 +621,17 @@ tpf_status tpf_poisson_solve(tpf_ctx* c, const double* b, double* x, int32_t on_
                        c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(e, "copy out");
+    return TPF_OK;
+}
+
+tpf_status tpf_solver_stats(tpf_ctx* c, int64_t out[3], int32_t reset) {
+    if (!c) { set_error("ctx is NULL"); return TPF_EINVAL; }
+    if (out) {
+        out[0] = c->stat_solves;
+        out[1] = c->stat_outer;
+        out[2] = c->stat_inner;
+    }
+    if (reset) c->stat_solves = c->stat_outer = c->stat_inner = 0;
     return TPF_OK;
 }
 

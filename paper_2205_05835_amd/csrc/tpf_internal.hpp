@@ -120,6 +120,7 @@ struct tpf_ctx {
     int p_valid;         // ctx->p holds the projection pressure of the current state
     double last_relres;
     int last_outer, last_inner;
+    long long stat_solves, stat_outer, stat_inner;   // pressure solves since the last reset
 
     // profiling: HIP event pairs around the launches of the selected classes
     unsigned prof_mask;

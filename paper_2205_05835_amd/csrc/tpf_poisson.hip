@@ -756,102 +756,117 @@ __device__ __forceinline__ S apply7(const S* bl, const S* bh, const Nbr7<S>& x, 
     return acc * ih2;
 }
 
-// Marches the half density and one field F along the column, software
-// pipelined: while plane k is computed, the in-plane neighbours and per-cell
-// operands (pre) of planes k+1 and k+2 and the column values up to plane k+3
-// are already in flight, so a wave keeps two planes of loads outstanding.  F(idx, i, j, k) returns the field at a cell; pre(c)
-// returns the per-cell operands the body needs; body(k, c, rho7, f7, e) is
-// called once per plane.
-template <typename S>
-struct Side {            // plane neighbours that need loads
-    S hxm, hxp, hym, hyp, fxm, fxp, fym, fyp;
+// Marches the half density and one field along the column through the KZ
+// planes of the block's slab (KZ a compile-time constant, the loop fully
+// unrolled): the column values of planes up to k+3 and the in-plane
+// neighbours and per-cell operands (pre) of planes k+1 and k+2 are in flight
+// while plane k is computed.  Unrolling gives every plane's operands their own
+// registers, so no loaded value is copied before it is used and the memory
+// waits are partial (only for the plane being computed), never a drain.
+// fld(idx, i, j, k) loads the field's raw operands at a cell (type V);
+// comb(V) forms the field value where it is used; pre(c) loads the per-cell
+// operands of the body; body(k, c, rho7, f7, e) computes one plane.
+template <typename S, typename V>
+struct SideV {           // plane neighbours that need loads
+    S hxm, hxp, hym, hyp;
+    V fxm, fxp, fym, fyp;
 };
 
-template <typename Coef, typename S, bool WITH_FIELD, typename F, typename Pre, typename Body>
-__device__ __forceinline__ void march(const Col& q, const Coef& cf, int k0, int k1, F fld, Pre pre,
+template <int KZ, typename Coef, typename S, bool WITH_FIELD, typename F, typename Cmb, typename Pre,
+          typename Body>
+__device__ __forceinline__ void march(const Col& q, const Coef& cf, int k0, F fld, Cmb comb, Pre pre,
                                       Body body) {
-    if (k0 >= k1) return;            // padding block of the XCD tiling
+    using V = decltype(fld(0u, 0, 0, 0));
     using E = decltype(pre(0u));
     auto side = [&](int k) {
-        Side<S> s;
+        SideV<S, V> s;
         const unsigned c = q.at(k);
         s.hxm = q.sxm ? S(0) : cf.hr(c + q.oxm);
         s.hxp = q.sxp ? S(0) : cf.hr(c + q.oxp);
         s.hym = cf.hr(c + q.oym);
         s.hyp = cf.hr(c + q.oyp);
         if (WITH_FIELD) {
-            s.fxm = q.sxm ? S(0) : fld(c + q.oxm, q.im, q.j, k);
-            s.fxp = q.sxp ? S(0) : fld(c + q.oxp, q.ip, q.j, k);
+            s.fxm = q.sxm ? V{} : fld(c + q.oxm, q.im, q.j, k);
+            s.fxp = q.sxp ? V{} : fld(c + q.oxp, q.ip, q.j, k);
             s.fym = fld(c + q.oym, q.i, q.jm, k);
             s.fyp = fld(c + q.oyp, q.i, q.jp, k);
         } else {
-            s.fxm = s.fxp = s.fym = s.fyp = S(0);
+            s.fxm = s.fxp = s.fym = s.fyp = V{};
         }
         return s;
     };
     auto hcol = [&](int k) { return cf.hr(q.at(q.kwrap(k))); };
     auto fcol = [&](int k) {
         const int kk = q.kwrap(k);
-        return WITH_FIELD ? fld(q.at(kk), q.i, q.j, kk) : S(0);
+        return WITH_FIELD ? fld(q.at(kk), q.i, q.j, kk) : V{};
     };
-    // column values of planes k-1 .. k+2 and the plane data of k and k+1
-    // are in flight when plane k is computed (two planes of lookahead)
-    S h0 = hcol(k0 - 1), h1 = hcol(k0), h2 = hcol(k0 + 1), h3 = hcol(k0 + 2);
-    S f0 = fcol(k0 - 1), f1 = fcol(k0), f2 = fcol(k0 + 1), f3 = fcol(k0 + 2);
-    Side<S> s0 = side(k0);
-    E e0 = pre(q.at(k0));
-    Side<S> s1 = s0;
-    E e1 = e0;
-    if (k0 + 1 < k1) {
-        s1 = side(k0 + 1);
-        e1 = pre(q.at(k0 + 1));
+    // h[m], f[m]: column of plane k0 - 1 + m
+    S h[KZ + 2];
+    V f[KZ + 2];
+    SideV<S, V> sd[KZ];
+    E e[KZ];
+#pragma unroll
+    for (int m = 0; m < 4 && m < KZ + 2; ++m) {
+        h[m] = hcol(k0 - 1 + m);
+        f[m] = fcol(k0 - 1 + m);
     }
-    for (int k = k0; k < k1; ++k) {
-        // issue the loads of plane k+2 (and the column of k+3) first
-        Side<S> s2 = s1;
-        E e2 = e1;
-        S h4 = h3, f4 = f3;
-        if (k + 2 < k1) {
-            s2 = side(k + 2);
-            e2 = pre(q.at(k + 2));
-            h4 = hcol(k + 3);
-            f4 = fcol(k + 3);
+#pragma unroll
+    for (int t = 0; t < 2 && t < KZ; ++t) {
+        sd[t] = side(k0 + t);
+        e[t] = pre(q.at(k0 + t));
+    }
+#pragma unroll
+    for (int t = 0; t < KZ; ++t) {
+        if (t + 2 < KZ) {            // loads of plane k+2 and of the column of k+3
+            sd[t + 2] = side(k0 + t + 2);
+            e[t + 2] = pre(q.at(k0 + t + 2));
+            h[t + 4] = hcol(k0 + t + 3);
+            f[t + 4] = fcol(k0 + t + 3);
         }
-        // plane k from registers and neighbouring lanes
-        const S lhm = lane_m(h1), lhp = lane_p(h1);
+        const S hc = h[t + 1];
+        const S lhm = lane_m(hc), lhp = lane_p(hc);
         Nbr7<S> R, X;
-        R.c = h1;
-        R.zm = h0;
-        R.zp = h2;
-        R.xm = q.sxm ? lhm : s0.hxm;
-        R.xp = q.sxp ? lhp : s0.hxp;
-        R.ym = s0.hym;
-        R.yp = s0.hyp;
+        R.c = hc;
+        R.zm = h[t];
+        R.zp = h[t + 2];
+        R.xm = q.sxm ? lhm : sd[t].hxm;
+        R.xp = q.sxp ? lhp : sd[t].hxp;
+        R.ym = sd[t].hym;
+        R.yp = sd[t].hyp;
         if (WITH_FIELD) {
-            const S lfm = lane_m(f1), lfp = lane_p(f1);
-            X.c = f1;
-            X.zm = f0;
-            X.zp = f2;
-            X.xm = q.sxm ? lfm : s0.fxm;
-            X.xp = q.sxp ? lfp : s0.fxp;
-            X.ym = s0.fym;
-            X.yp = s0.fyp;
+            const S fc = comb(f[t + 1]);
+            const S lfm = lane_m(fc), lfp = lane_p(fc);
+            X.c = fc;
+            X.zm = comb(f[t]);
+            X.zp = comb(f[t + 2]);
+            X.xm = q.sxm ? lfm : comb(sd[t].fxm);
+            X.xp = q.sxp ? lfp : comb(sd[t].fxp);
+            X.ym = comb(sd[t].fym);
+            X.yp = comb(sd[t].fyp);
         }
-        body(k, q.at(k), R, X, e0);
-        h0 = h1;
-        h1 = h2;
-        h2 = h3;
-        h3 = h4;
-        f0 = f1;
-        f1 = f2;
-        f2 = f3;
-        f3 = f4;
-        s0 = s1;
-        s1 = s2;
-        e0 = e1;
-        e1 = e2;
+        body(k0 + t, q.at(k0 + t), R, X, e[t]);
     }
 }
+
+// Run march<KZ> for the block's slab with KZ = kz (8 or 16); padding blocks
+// of the XCD tiling (empty slab) do nothing.
+template <typename Coef, typename S, bool WITH_FIELD, typename F, typename Cmb, typename Pre, typename Body>
+__device__ __forceinline__ void march_kz(const Col& q, const Coef& cf, int kz, F fld, Cmb comb, Pre pre,
+                                         Body body) {
+    const int k0 = q.kslab * kz;
+    if (k0 >= q.nz) return;
+    if (kz == 16) march<16, Coef, S, WITH_FIELD>(q, cf, k0, fld, comb, pre, body);
+    else march<8, Coef, S, WITH_FIELD>(q, cf, k0, fld, comb, pre, body);
+}
+
+template <typename S>
+struct Ident {
+    __device__ __forceinline__ S operator()(S v) const { return v; }
+};
+template <typename S>
+struct Pair {
+    S a, b;
+};
 
 struct NoPre {};
 
@@ -867,15 +882,17 @@ __global__ __launch_bounds__(BLOCK) void k_fz_jac(Dims d, Dims cd, int kz, S ih2
     if (sc->done) return;
     Col q;
     q.init(d, kz);
-    const int k0 = q.kslab * kz, k1 = min(k0 + kz, d.nz);
-    auto fld = [&](unsigned idx, int i, int j, int k) -> S {
-        S v = ld(z, idx);
-        if (MODE == 1) v += ld(zc, ((unsigned)(k >> 1) * cd.ny + (j >> 1)) * cd.nx + (i >> 1));
+    // MODE 1: the field is z + P zc, combined where it is used
+    auto fld = [&](unsigned idx, int i, int j, int k) -> Pair<S> {
+        Pair<S> v;
+        v.a = ld(z, idx);
+        v.b = MODE == 1 ? ld(zc, ((unsigned)(k >> 1) * cd.ny + (j >> 1)) * cd.nx + (i >> 1)) : S(0);
         return v;
     };
+    auto comb = [](const Pair<S>& v) -> S { return MODE == 1 ? v.a + v.b : v.a; };
     auto pre = [&](unsigned c) -> S { return ld(r, c); };
     double acc = 0.0;
-    march<Coef, S, true>(q, cf, k0, k1, fld, pre,
+    march_kz<Coef, S, true>(q, cf, kz, fld, comb, pre,
                          [&](int, unsigned c, const Nbr7<S>& R, const Nbr7<S>& X, S rc) {
         S bl[3], bh[3], dg;
         faces7(R, bl, bh);
@@ -910,7 +927,6 @@ __global__ __launch_bounds__(BLOCK) void k_fz_first(Dims d, int kz, S ih2, S ome
     if (sc->done) return;
     Col q;
     q.init(d, kz);
-    const int k0 = q.kslab * kz, k1 = min(k0 + kz, d.nz);
     const double alpha = UPD ? sc->alpha : 0.0;
     auto none = [](unsigned, int, int, int) { return S(0); };
     auto pre = [&](unsigned c) {
@@ -927,7 +943,7 @@ __global__ __launch_bounds__(BLOCK) void k_fz_first(Dims d, int kz, S ih2, S ome
         return e;
     };
     double acc = 0.0;
-    march<Coef, S, false>(q, cf, k0, k1, none, pre,
+    march_kz<Coef, S, false>(q, cf, kz, none, Ident<S>{}, pre,
                           [&](int, unsigned c, const Nbr7<S>& R, const Nbr7<S>&, const FirstPre<S, X>& e) {
         S bl[3], bh[3];
         faces7(R, bl, bh);
@@ -960,14 +976,15 @@ __global__ __launch_bounds__(BLOCK) void k_fz_apply(Dims d, int kz, S ih2, Coef 
     if (sc->done) return;
     Col q;
     q.init(d, kz);
-    const int k0 = q.kslab * kz, k1 = min(k0 + kz, d.nz);
+    // p = z + beta p_old without a branch: on the first iteration p_old is
+    // not read (z stands in for it, with beta = 0)
     const S beta = first ? S(0) : S(sc->beta);
-    auto fld = [&](unsigned idx, int, int, int) -> S {
-        return first ? ld(z, idx) : ld(z, idx) + beta * ld(pold, idx);
-    };
+    const S* po = first ? z : pold;
+    auto fld = [&](unsigned idx, int, int, int) -> Pair<S> { return Pair<S>{ld(z, idx), ld(po, idx)}; };
+    auto comb = [&](const Pair<S>& v) -> S { return v.a + beta * v.b; };
     auto pre = [](unsigned) { return NoPre{}; };
     double acc = 0.0;
-    march<Coef, S, true>(q, cf, k0, k1, fld, pre,
+    march_kz<Coef, S, true>(q, cf, kz, fld, comb, pre,
                          [&](int, unsigned c, const Nbr7<S>& R, const Nbr7<S>& X, NoPre) {
         S bl[3], bh[3], dg;
         faces7(R, bl, bh);
@@ -995,12 +1012,11 @@ __global__ __launch_bounds__(BLOCK) void k_fz_restrict(Dims d, Dims cd, int kz, 
     Col q;
     q.init(d, kz);
     const int tx = threadIdx.x, ty = threadIdx.y;
-    const int k0 = q.kslab * kz, k1 = min(k0 + kz, d.nz);
     auto fld = [&](unsigned idx, int, int, int) -> S { return ld(z, idx); };
     auto pre = [&](unsigned c) -> S { return ld(r, c); };
     const unsigned cmax = (unsigned)(cd.nx * cd.ny * cd.nz - 1);
     S pair = S(0);
-    march<Coef, S, true>(q, cf, k0, k1, fld, pre,
+    march_kz<Coef, S, true>(q, cf, kz, fld, Ident<S>{}, pre,
                          [&](int k, unsigned, const Nbr7<S>& R, const Nbr7<S>& X, S rv) {
         S bl[3], bh[3], dg;
         faces7(R, bl, bh);
@@ -1032,12 +1048,11 @@ __global__ __launch_bounds__(BLOCK) void k_fz_resid(Dims d, int kz, S ih2, Coef 
                                                     double* __restrict__ partials, long stride) {
     Col q;
     q.init(d, kz);
-    const int k0 = q.kslab * kz, k1 = min(k0 + kz, d.nz);
     const double mean = sc->mean;
     auto fld = [&](unsigned idx, int, int, int) -> S { return S(ld(x, idx)); };
     auto pre = [&](unsigned c) -> double { return ld(b, c); };
     double v[2] = {0.0, 0.0};
-    march<Coef, S, true>(q, cf, k0, k1, fld, pre,
+    march_kz<Coef, S, true>(q, cf, kz, fld, Ident<S>{}, pre,
                          [&](int, unsigned c, const Nbr7<S>& Rh, const Nbr7<S>& X, double bc) {
         S bl[3], bh[3], dg;
         faces7(Rh, bl, bh);
@@ -1092,13 +1107,14 @@ struct Solver {
     double cfields(int l) const { return l == 0 ? (double)sizeof(T) / sizeof(S) : (double)dim; }
     long nbl(int l) const { return nblocks_of(c->lv[l].n); }
     // level 0 in 3D runs the z-marching kernels: kz planes per block
-    bool march0() const { return dim == 3 && c->march; }
+    bool march0() const { return dim == 3 && c->march && kz() > 0; }
+    // planes per block of the z-marching kernels: 8 or 16 (the march is
+    // unrolled for these); 0 when nz admits neither (plain kernels then)
     int kz() const {
         const int nz = c->lv[0].n[2];
-        if (c->kz_override > 0 && c->kz_override % 2 == 0 && nz % c->kz_override == 0) return c->kz_override;
-        for (int k : {8, 4, 2})
-            if (nz % k == 0) return k;
-        return 1;
+        if ((c->kz_override == 8 || c->kz_override == 16) && nz % c->kz_override == 0) return c->kz_override;
+        if (nz % 8 == 0) return 8;
+        return 0;
     }
     dim3 mgrid() const {
         const Level& L = c->lv[0];
@@ -1146,7 +1162,7 @@ struct Solver {
         S* r = tp<S>(L.r);
         const double cfl = cfields(l);
         if constexpr (std::is_same<Coef, CoefRho<S>>::value) {
-            if (DIM == 3 && c->march) {
+            if (DIM == 3 && march0()) {
                 Level& Lc = c->lv[l + 1];
                 if (!first_done) {
                     prof_begin(c, PC_F_FIRST0, fb(l, 2 + cfl));
@@ -1192,7 +1208,7 @@ struct Solver {
         const double cb = (double)c->lv[l + 1].N * sizeof(S);
         const double cfl = cfields(l);
         if constexpr (std::is_same<Coef, CoefRho<S>>::value) {
-            if (DIM == 3 && c->march) {
+            if (DIM == 3 && march0()) {
                 prof_begin(c, PC_F_PROLONG, fb(l, 3 + cfl) + cb);
                 k_fz_jac<Coef, S, 1><<<mgrid(), b, 0, c->stream>>>(dims(0), dims(1), kz(), ih2(0), omega, cf, r, zt,
                                                                zc, z, c->scal, nullptr);
@@ -1289,7 +1305,7 @@ struct Solver {
     void vcycle_t(const void* phi, bool first_done) {
         const CoefRho<S> cf = coef_fine();
         Level& L = c->lv[0];
-        if (c->nlev == 1 && DIM == 3 && c->march) {
+        if (c->nlev == 1 && DIM == 3 && march0()) {
             // no coarsening possible: two Jacobi sweeps (still symmetric)
             const dim3 b(BX, BY);
             if (!first_done) {
@@ -1337,7 +1353,7 @@ struct Solver {
         const dim3 b(BX, BY);
         S* pold = tp<S>(c->pv);
         S* pnew = tp<S>(c->pv2);
-        if (DIM == 3 && c->march) {
+        if (DIM == 3 && march0()) {
             prof_begin(c, PC_F_APPLY, fb(0, (first ? 1 : 2) + 2 + cfields(0)));
             k_fz_apply<CoefRho<S>, S><<<mgrid(), b, 0, c->stream>>>(dims(0), kz(), ih2(0), cf, first, tp<S>(c->lv[0].zt),
                                                           pold, pnew, tp<S>(c->qv), c->scal, c->partials);
@@ -1425,7 +1441,7 @@ struct Solver {
     template <typename R, typename Coef>
     void residual(Coef cf, R* r) {
         prof_begin(c, PC_RESID, (double)c->N * (8 + 8 + sizeof(T) + sizeof(R)));
-        if (dim == 3 && c->march)
+        if (march0())
             k_fz_resid<Coef, S, R><<<mgrid(), dim3(BX, BY), 0, c->stream>>>(dims(0), kz(), ih2(0), cf, c->b, c->p, r,
                                                                            c->scal, c->partials, c->max_blocks);
         else if (dim == 3)

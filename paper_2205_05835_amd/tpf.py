@@ -40,7 +40,7 @@ EXPORTS = ["tpf_workspace_bytes", "tpf_create", "tpf_destroy", "tpf_set_state", 
            "tpf_batch_status", "tpf_batch_clear_status", "tpf_batch_diagnostics", "tpf_batch_configs",
            "tpf_batch_config_info", "tpf_batch_set_config", "tpf_batch_tune", "tpf_checkpoint_bytes",
            "tpf_save_checkpoint", "tpf_load_checkpoint", "tpf_adjoint_tape_bytes", "tpf_stage_adjoint",
-           "tpf_step_adjoint"]
+           "tpf_step_adjoint", "tpf_solver_stats"]
 
 
 class TpfError(RuntimeError):
@@ -120,6 +120,7 @@ def lib():
         "tpf_batch_set_config": ([vp, i32], i32),
         "tpf_batch_tune": ([vp, dp, ctypes.c_char_p, ctypes.POINTER(i32)], i32),
         "tpf_checkpoint_bytes": ([vp, ctypes.POINTER(ctypes.c_size_t)], i32),
+        "tpf_solver_stats": ([vp, ctypes.POINTER(ctypes.c_int64), i32], i32),
         "tpf_save_checkpoint": ([vp, vp], i32),
         "tpf_load_checkpoint": ([vp, vp], i32),
         "tpf_adjoint_tape_bytes": ([vp, i32, ctypes.POINTER(ctypes.c_size_t)], i32),
@@ -272,6 +273,12 @@ class Solver:
                                       x.ctypes.data_as(ctypes.c_void_p), 0, ctypes.byref(it),
                                       ctypes.byref(rr)), "tpf_poisson_solve")
         return x.reshape(self.shape), it.value, rr.value
+
+    def solver_stats(self, reset: bool = False) -> dict:
+        """Pressure solves, outer and PCG iterations since the last reset."""
+        out = (ctypes.c_int64 * 3)()
+        check(lib().tpf_solver_stats(self.ctx, out, int(reset)), "tpf_solver_stats")
+        return {"solves": out[0], "outer": out[1], "inner": out[2]}
 
     # ---------------------------------------------------------------- checkpoints
     def checkpoint_bytes(self) -> int:
