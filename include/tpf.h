@@ -76,7 +76,9 @@ typedef struct {
     double visc1, visc2;      /* dynamic viscosities of phase phi=1 and phi=0     */
     double normal_delta;      /* n = g / sqrt(g.g + delta^2); 0 -> 1e-12          */
     double poisson_rtol;      /* stop at ||r|| <= rtol ||rhs||; 0 -> 1e-13 (FP64) or 1e-9 (mixed) */
-    double poisson_rtol_inner;/* FP32 inner PCG tolerance (mixed); 0 -> 1e-4      */
+    double poisson_rtol_inner;/* mixed: smallest relative tolerance asked of an FP32
+                                 inner PCG (each inner solve aims at the outer
+                                 tolerance, but not below this); 0 -> 1e-6       */
     int32_t poisson_maxit;    /* PCG iteration cap per solve; 0 -> 400            */
     int32_t mg_levels;        /* multigrid levels; 0 -> as deep as the grid allows */
 } tpf_params;

@@ -437,10 +437,12 @@ struct BatchBlock {
                 S* e = static_cast<S*>(K.ev);
                 cells(dims(0), [&](const Cell& C) { e[C.id] = S(0); });
                 __syncthreads();
-                const int it = pcg<S>(e, rr, rr, K.rtol_inner * K.rtol_inner, omega);
+                // aim at the outer tolerance, not below rtol_inner (FP32 depth);
+                // an inner solve stopped by maxit still improves the iterate
+                const double tin = fmin(0.1, fmax(K.rtol_inner, 0.5 * K.rtol * sqrt(ff / rr)));
+                const int it = pcg<S>(e, rr, rr, tin * tin, omega);
                 if (it == -2) { status = TPF_ENONFINITE; break; }
-                if (it < 0) { status = TPF_ENOCONV; break; }
-                total += it;
+                total += it < 0 ? K.maxit : it;
                 cells(dims(0), [&](const Cell& C) { K.p[C.id] += (double)e[C.id]; });
                 __syncthreads();
             }

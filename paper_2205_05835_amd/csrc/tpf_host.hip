@@ -216,7 +216,7 @@ tpf_status resolve_params(const tpf_params* in, tpf_params* P) {
     }
     if (P->normal_delta <= 0) P->normal_delta = 1e-12;
     if (P->poisson_rtol <= 0) P->poisson_rtol = P->precision == TPF_FP64 ? 1e-13 : 1e-9;
-    if (P->poisson_rtol_inner <= 0) P->poisson_rtol_inner = 1e-4;
+    if (P->poisson_rtol_inner <= 0) P->poisson_rtol_inner = 1e-6;
     if (P->poisson_maxit <= 0) P->poisson_maxit = 400;
     if (P->mg_levels < 0) { set_error("mg_levels must be >= 0"); return TPF_EINVAL; }
     return TPF_OK;
@@ -236,6 +236,9 @@ static void init_geometry(tpf_ctx* c, const tpf_params* P) {
     c->march = (m && m[0] == '0') ? 0 : 1;
     const char* tl = std::getenv("TPF_TAIL");
     c->no_tail = (tl && tl[0] == '0') ? 1 : 0;
+    const char* mga = std::getenv("TPF_MG_ALPHA");
+    c->mg_alpha = mga ? std::atof(mga) : 1.0;
+    if (!(c->mg_alpha > 0.0 && c->mg_alpha < 2.0)) c->mg_alpha = 1.0;
     const char* kzs = std::getenv("TPF_KZ");
     c->kz_override = kzs ? std::atoi(kzs) : 0;
     const char* xt = std::getenv("TPF_XCD_TILES");

@@ -152,6 +152,7 @@ struct tpf_ctx {
     // first after that many iterations
     int pred_iters[4];
     int kz_override;     // planes per block of the z-marching kernels (0: automatic)
+    double mg_alpha;     // weight of the multigrid coarse-grid correction
 };
 
 namespace tpf {

@@ -307,7 +307,7 @@ __global__ __launch_bounds__(BLOCK) void k_jac(Dims d, Dims cd, S ih2, S omega, 
 // fine cell (coalesced); block 64 x 2 x 2 (3D) or 64 x 4 (2D); x pairs summed
 // with a lane shuffle, y/z pairs through LDS.
 template <typename Coef, typename S, int DIM>
-__global__ __launch_bounds__(BLOCK) void k_restrict(Dims fd, Dims cd, S ih2, Coef cf,
+__global__ __launch_bounds__(BLOCK) void k_restrict(Dims fd, Dims cd, S ih2, S rw, Coef cf,
                                                     const S* __restrict__ r,
                                                     const S* __restrict__ z,
                                                     S* __restrict__ rc,
@@ -338,7 +338,7 @@ __global__ __launch_bounds__(BLOCK) void k_restrict(Dims fd, Dims cd, S ih2, Coe
         if constexpr (DIM == 3) s += sh[1][ty][tx] + sh[1][ty + 1][tx];
         const long cc = ((long)(C.k >> 1) * cd.ny + (C.j >> 1)) * cd.nx + (C.i >> 1);
         const long cmax = (long)cd.nx * cd.ny * cd.nz - 1;
-        rc[cc < cmax ? cc : cmax] = s * S(1.0 / (DIM == 3 ? 8 : 4));
+        rc[cc < cmax ? cc : cmax] = s * rw;
     }
 }
 
@@ -393,6 +393,7 @@ struct TailDesc {
     int off[TAIL_MAX_LEVELS];          // element offset of level l's r; z, zt follow
     double ih2[TAIL_MAX_LEVELS];
     const void* beta[TAIL_MAX_LEVELS][3];
+    double rw;                          // restriction weight
 };
 
 template <typename S, int DIM>
@@ -469,7 +470,7 @@ __global__ __launch_bounds__(1024) void k_tail(TailDesc D, S omega, S omega_c, i
                         auto X = [&](int a, int s2) { return zt[C.nb(a, s2)]; };
                         s += r[C.id] - apply_at<S, DIM>(bl, bh, X, zt[C.id], ih2, dg);
                     }
-            rc[Q] = s * S(1.0 / (DIM == 3 ? 8 : 4));
+            rc[Q] = s * S(D.rw);
         }
         __syncthreads();
     }
@@ -1002,7 +1003,7 @@ __global__ __launch_bounds__(BLOCK) void k_fz_apply(Dims d, int kz, S ih2, Coef 
 // coarse rhs = mean over the 2x2x2 children of (r - A z); kz even.  z pairs
 // summed in registers, x pairs by a lane shuffle, y pairs through LDS.
 template <typename Coef, typename S>
-__global__ __launch_bounds__(BLOCK) void k_fz_restrict(Dims d, Dims cd, int kz, S ih2, Coef cf,
+__global__ __launch_bounds__(BLOCK) void k_fz_restrict(Dims d, Dims cd, int kz, S ih2, S rw, Coef cf,
                                                        const S* __restrict__ r,
                                                        const S* __restrict__ z,
                                                        S* __restrict__ rc,
@@ -1029,7 +1030,7 @@ __global__ __launch_bounds__(BLOCK) void k_fz_restrict(Dims d, Dims cd, int kz, 
             if (q.valid && (tx & 1) == 0 && (ty & 1) == 0) {
                 const S s = sh[ty][tx] + sh[ty + 1][tx];
                 const unsigned cc = ((unsigned)(k >> 1) * cd.ny + (q.j >> 1)) * cd.nx + (q.i >> 1);
-                st(rc, min(cc, cmax), s * S(0.125));
+                st(rc, min(cc, cmax), s * rw);
             }
             __syncthreads();
             pair = S(0);
@@ -1102,6 +1103,10 @@ struct Solver {
     dim3 grid(int l) const { return grid_of(c->lv[l].n); }
     Dims dims(int l) const { return dims_of(c->lv[l].n); }
     Dims dims_c(int l) const { return l + 1 < c->nlev ? dims(l + 1) : dims(l); }
+    // restriction weight: mean over the 2^d children times the coarse-grid
+    // correction weight (the coarse problem is linear, so scaling its
+    // right-hand side scales the correction; R stays proportional to P^T)
+    S rw() const { return S(c->mg_alpha / (dim == 3 ? 8.0 : 4.0)); }
     double fb(int l, double fields) const { return (double)c->lv[l].N * sizeof(S) * fields; }
     // fields moved by the coefficients: phi on the fine level, DIM arrays below
     double cfields(int l) const { return l == 0 ? (double)sizeof(T) / sizeof(S) : (double)dim; }
@@ -1175,7 +1180,7 @@ struct Solver {
                                                                nullptr, zt, c->scal, nullptr);
                 prof_end(c);
                 prof_begin(c, PC_F_RESTRICT, fb(l, 2 + cfl) + (double)Lc.N * sizeof(S));
-                k_fz_restrict<Coef, S><<<mgrid(), b, 0, c->stream>>>(dims(0), dims(1), kz(), ih2(0), cf, r, zt,
+                k_fz_restrict<Coef, S><<<mgrid(), b, 0, c->stream>>>(dims(0), dims(1), kz(), ih2(0), rw(), cf, r, zt,
                                                                  tp<S>(Lc.r), c->scal);
                 prof_end(c);
                 return;
@@ -1193,7 +1198,7 @@ struct Solver {
         Level& Lc = c->lv[l + 1];
         prof_begin(c, fine ? PC_F_RESTRICT : PC_COARSE_LEVELS, fb(l, 2 + cfl) + (double)Lc.N * sizeof(S));
         k_restrict<Coef, S, DIM><<<restrict_grid(l), restrict_block(), 0, c->stream>>>(
-            dims(l), dims(l + 1), ih2(l), cf, r, zt, tp<S>(Lc.r), c->scal);
+            dims(l), dims(l + 1), ih2(l), rw(), cf, r, zt, tp<S>(Lc.r), c->scal);
         prof_end(c);
     }
 
@@ -1258,6 +1263,7 @@ struct Solver {
     const S* tail(int l0) {
         TailDesc D;
         D.nlev = c->nlev - l0;
+        D.rw = (double)rw();
         int off = 0;
         for (int q = 0; q < D.nlev; ++q) {
             const Level& L = c->lv[l0 + q];
@@ -1536,16 +1542,23 @@ tpf_status poisson_solve(tpf_ctx* c, const void* phi, int* iters, double* relres
             if (e != hipSuccess) return hip_fail(e, "mean removal");
             return TPF_OK;
         }
-        k_inner_setup<<<1, 64, 0, c->stream>>>(c->scal, rin * rin);
+        // the inner solve aims straight at the outer tolerance (half of the
+        // reduction it needs), but never below rin, the depth an FP32 PCG
+        // reaches reliably; a further outer pass picks up the rest
+        const double need = 0.5 * rtol * std::sqrt(s.ff / s.rr);
+        const double tin = std::min(0.1, std::max(rin, need));
+        k_inner_setup<<<1, 64, 0, c->stream>>>(c->scal, tin * tin);
         k_fill_s<float><<<vgrid(c->N), BLOCK, 0, c->stream>>>(c->N, tp<float>(c->ev), 0.0f);
         e = sv.pcg<float>(phi, tp<float>(c->ev), maxit, 1 + std::min(o, 2));
         if (e != hipSuccess) return hip_fail(e, "FP32 inner PCG");
         st = read_scalars(c, &s);
         if (st != TPF_OK) return st;
         total += s.iters;
-        if (!s.done) {
-            set_error("inner pressure solve did not converge within poisson_maxit iterations");
-            return TPF_ENOCONV;
+        // an inner solve stopped by maxit (FP32 stagnation) still lowers the
+        // A-norm error: its correction is applied and the outer loop goes on
+        if (!std::isfinite(s.rr)) {
+            set_error("non-finite inner pressure residual");
+            return TPF_ENONFINITE;
         }
         prof_begin(c, PC_VECTOR, (double)c->N * (8 + 4 + 8));
         k_correct<<<vgrid(c->N), BLOCK, 0, c->stream>>>(c->N, c->p, tp<float>(c->ev));
