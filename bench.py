@@ -82,7 +82,7 @@ def gpu_run(args):
     torch.cuda.set_device(0)
     case = workloads.oscillating_drop_3d(args.n, "fp32_mixed")
     dt = case.dt()
-    s = tpf.solver_for_case(case)
+    s = tpf.solver_for_case(case, poisson_rtol_inner=args.poisson_rtol_inner)
     s.init_droplet(case.center, case.semi_axes)
     s.step(dt, args.warmup)
     torch.cuda.synchronize()
@@ -296,6 +296,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=256, help="cells per axis of the drop workload")
     ap.add_argument("--compare-steps", type=int, default=3)
+    ap.add_argument("--poisson-rtol-inner", type=float, default=0.0,
+                    help="floor of the FP32 inner PCG tolerance (0: library default)")
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=64)

@@ -165,9 +165,10 @@ tpf_status tpf_poisson_solve(tpf_ctx* ctx, const double* b, double* x, int32_t o
                              int32_t* iters, double* relres);
 
 /* Pressure-solve counters since creation or the last reset: out[0] solves,
- * out[1] outer (defect-correction) iterations, out[2] PCG iterations.
- * reset = 1 zeroes them after reading. */
-tpf_status tpf_solver_stats(tpf_ctx* ctx, int64_t out[3], int32_t reset);
+ * out[1] outer (defect-correction) iterations, out[2] PCG iterations,
+ * out[3..6] PCG iterations of the last four solves, oldest first (-1: none).
+ * reset = 1 zeroes the counters after reading. */
+tpf_status tpf_solver_stats(tpf_ctx* ctx, int64_t out[7], int32_t reset);
 
 /* Per-kernel-class device timing: HIP events recorded on the context stream
  * around every launch of the selected classes (the class list is fixed; see

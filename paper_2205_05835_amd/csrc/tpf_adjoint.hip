@@ -521,6 +521,7 @@ tpf_status tpf_stage_adjoint(tpf_ctx* c, const double* lphi, const double* lu0, 
     for (int k = 0; k < 3 && st == TPF_OK; ++k) st = vec_out(c, gout[k], out[k], on_device);
     if (st != TPF_OK) return st;
     c->p_valid = 0;
+    c->hist2_valid = 0;
     return add_grad(c, grad_params);
 }
 
@@ -571,6 +572,7 @@ tpf_status tpf_step_adjoint(tpf_ctx* c, void* tape, size_t tape_bytes, double dt
     for (int k = 0; k < 3 && st == TPF_OK; ++k) st = vec_out(c, gio[k], lam[k], on_device);
     if (st != TPF_OK) return st;
     c->p_valid = 0;
+    c->hist2_valid = 0;
     return add_grad(c, grad_params);
 }
 
@@ -628,6 +630,7 @@ tpf_status tpf_load_checkpoint(tpf_ctx* c, const void* src) {
     c->step = h.step;
     c->mass0 = h.mass0;
     c->p_valid = 0;
+    c->hist2_valid = 0;
     return TPF_OK;
 }
 

@@ -169,6 +169,8 @@ static size_t carve(tpf_ctx* c, char* base) {
     c->kappa = cv.take(NT);
     c->b = (double*)cv.take(N8);
     c->p = (double*)cv.take(N8);
+    c->p_hist1 = (double*)cv.take(N8);
+    c->p_hist2 = (double*)cv.take(N8);
     c->r64 = c->mixed ? (double*)cv.take(N8) : nullptr;
     c->pv = cv.take((size_t)c->N * ssz);
     c->pv2 = cv.take((size_t)c->N * ssz);
@@ -324,6 +326,7 @@ static tpf_status finish_set_state(tpf_ctx* c) {
     c->t = 0.0;
     c->step = 0;
     c->p_valid = 0;
+    c->hist2_valid = 0;
     const void* u[3] = {c->u[0][c->s_yn], c->u[1][c->s_yn], c->dim == 3 ? c->u[2][c->s_yn] : c->u[1][c->s_yn]};
     e = launch_diagnostics(c, c->phi[c->s_yn], u, nullptr);
     if (e != hipSuccess) return hip_fail(e, "diagnostics");
@@ -386,6 +389,7 @@ static tpf_status stage_eval(tpf_ctx* c, const void* phi_s, const void* const u_
     c->last_inner = it;
     c->last_outer = outer;
     c->last_relres = rr;
+    c->stat_recent[c->stat_solves % 4] = it;
     c->stat_solves += 1;
     c->stat_outer += outer;
     c->stat_inner += it;
@@ -432,12 +436,23 @@ tpf_status advance(tpf_ctx* c, double dt, int nsteps, char* tape, size_t stage_b
                     st = copy_async(c, rec + (1 + a) * fT, u_s[a], NT);
                 if (st != TPF_OK) return st;
             }
+            // warm start of the pressure solve: the last pressure (stages 1
+            // and 3 sit at the time of the previous stage), extrapolated
+            // linearly in time for stage 2 (t + dt/2, from t and t - dt/2)
+            // and stage 4 (t + dt, from t and t + dt/2)
+            hipError_t ew = hipSuccess;
+            if (s == 1 && c->hist2_valid) ew = launch_extrapolate(c, c->p, c->p_hist2);
+            if (s == 3) ew = launch_extrapolate(c, c->p, c->p_hist1);
+            if (ew != hipSuccess) return hip_fail(ew, "pressure extrapolation");
             RKArgs rk{s, 0, wacc[s], wnext[s]};
             const void* us[3] = {u_s[0], u_s[1], u_s[2]};
             tpf_status st = stage_eval(c, phi_s, us, rk, phi_o, u_o, 0);
+            if (st == TPF_OK && s <= 1)
+                st = copy_async(c, s == 0 ? c->p_hist1 : c->p_hist2, c->p, (size_t)c->N * 8);
             if (st == TPF_OK && rec) st = copy_async(c, rec + (1 + c->dim) * fT, c->p, (size_t)c->N * 8);
             if (st != TPF_OK) {
                 c->p_valid = 0;
+                c->hist2_valid = 0;
                 return st;
             }
         }
@@ -447,9 +462,11 @@ tpf_status advance(tpf_ctx* c, double dt, int nsteps, char* tape, size_t stage_b
         if (e != hipSuccess) return hip_fail(e, "step completion");
         if (flag) {
             c->p_valid = 0;
+            c->hist2_valid = 0;
             set_error("non-finite value produced; state kept at the last completed step");
             return TPF_ENONFINITE;
         }
+        c->hist2_valid = 1;
         const int t = c->s_yn;
         c->s_yn = c->s_acc;
         c->s_acc = t;
@@ -617,6 +634,7 @@ tpf_status tpf_poisson_solve(tpf_ctx* c, const double* b, double* x, int32_t on_
     double rr = 0;
     tpf_status st = poisson_solve(c, c->phi[c->s_yn], &it, &rr, &outer);
     c->p_valid = 0;
+    c->hist2_valid = 0;
     if (iters) *iters = it;
     if (relres) *relres = rr;
     if (st != TPF_OK) return st;
@@ -627,12 +645,16 @@ tpf_status tpf_poisson_solve(tpf_ctx* c, const double* b, double* x, int32_t on_
     return TPF_OK;
 }
 
-tpf_status tpf_solver_stats(tpf_ctx* c, int64_t out[3], int32_t reset) {
+tpf_status tpf_solver_stats(tpf_ctx* c, int64_t out[7], int32_t reset) {
     if (!c) { set_error("ctx is NULL"); return TPF_EINVAL; }
     if (out) {
         out[0] = c->stat_solves;
         out[1] = c->stat_outer;
         out[2] = c->stat_inner;
+        for (int k = 0; k < 4; ++k) {        // oldest first
+            const long long q = c->stat_solves - 4 + k;
+            out[3 + k] = q >= 0 ? c->stat_recent[q % 4] : -1;
+        }
     }
     if (reset) c->stat_solves = c->stat_outer = c->stat_inner = 0;
     return TPF_OK;

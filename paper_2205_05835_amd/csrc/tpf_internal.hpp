@@ -118,9 +118,15 @@ struct tpf_ctx {
     long step;
     double mass0;
     int p_valid;         // ctx->p holds the projection pressure of the current state
+    // pressure history for the warm starts: stage-1 pressure of the current
+    // step (time t_n) and stage-2 pressure of the previous step (t_n - dt/2)
+    double* p_hist1;
+    double* p_hist2;
+    int hist2_valid;
     double last_relres;
     int last_outer, last_inner;
     long long stat_solves, stat_outer, stat_inner;   // pressure solves since the last reset
+    int stat_recent[4];                              // PCG iterations of the last four solves
 
     // profiling: HIP event pairs around the launches of the selected classes
     unsigned prof_mask;
@@ -191,6 +197,7 @@ constexpr int ADJ_FIELDS = 26;
 size_t align256(size_t x);
 hipError_t launch_finalize(tpf_ctx* c, int nblocks, int nv, int op);
 hipError_t launch_rhs_mean(tpf_ctx* c);
+hipError_t launch_extrapolate(tpf_ctx* c, double* x, const double* y);
 
 // 1D grid over gx*gy*gz tiles, padded to a multiple of the XCD count
 inline dim3 tile_grid(long gx, long gy, long gz) {

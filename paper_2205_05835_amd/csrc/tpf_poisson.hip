@@ -557,6 +557,13 @@ __global__ __launch_bounds__(BLOCK) void k_apply(Dims d, S ih2, Coef cf, int fir
 // ---------------------------------------------------------------- small vector kernels
 constexpr int VBLOCKS = 1024;   // grid-stride vector kernels
 
+// x = 2 x - y: linear extrapolation in time of the pressure warm start
+__global__ __launch_bounds__(BLOCK) void k_extrapolate(long N, double* __restrict__ x,
+                                                       const double* __restrict__ y) {
+    for (long c = (long)blockIdx.x * BLOCK + threadIdx.x; c < N; c += (long)gridDim.x * BLOCK)
+        x[c] = 2.0 * x[c] - y[c];
+}
+
 __global__ __launch_bounds__(BLOCK) void k_correct(long N, double* __restrict__ x,
                                                    const float* __restrict__ e) {
     for (long c = (long)blockIdx.x * BLOCK + threadIdx.x; c < N; c += (long)gridDim.x * BLOCK)
@@ -1460,6 +1467,13 @@ struct Solver {
     }
 };
 
+
+hipError_t launch_extrapolate(tpf_ctx* c, double* x, const double* y) {
+    prof_begin(c, PC_VECTOR, (double)c->N * 24);
+    k_extrapolate<<<vgrid(c->N), BLOCK, 0, c->stream>>>(c->N, x, y);
+    prof_end(c);
+    return hipGetLastError();
+}
 
 hipError_t launch_rhs_mean(tpf_ctx* c) {
     const unsigned nb = vgrid(c->N);

@@ -276,9 +276,9 @@ class Solver:
 
     def solver_stats(self, reset: bool = False) -> dict:
         """Pressure solves, outer and PCG iterations since the last reset."""
-        out = (ctypes.c_int64 * 3)()
+        out = (ctypes.c_int64 * 7)()
         check(lib().tpf_solver_stats(self.ctx, out, int(reset)), "tpf_solver_stats")
-        return {"solves": out[0], "outer": out[1], "inner": out[2]}
+        return {"solves": out[0], "outer": out[1], "inner": out[2], "recent": list(out[3:7])}
 
     # ---------------------------------------------------------------- checkpoints
     def checkpoint_bytes(self) -> int:
