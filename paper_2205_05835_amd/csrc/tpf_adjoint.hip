@@ -380,6 +380,7 @@ enum {
     AF_LDM = 21,
     AF_LETA = 22,
     AF_PST = 23,     // stage pressure (single-stage adjoint)
+    AF_Q = 24,       // last adjoint pressure (warm start of the next adjoint solve)
     AF_GRAD = 26     // two accumulators after the fields
 };
 static_assert(AF_PST < ADJ_FIELDS, "adjoint scratch layout");
@@ -422,17 +423,21 @@ static tpf_status stage_vjp_t(tpf_ctx* c, const void* phi_s, const void* const u
     // forward intermediates: normals, mu, CDI and mass fluxes, f*
     hipError_t e = launch_stage_fields(c, phi_s, u3);
     if (e == hipSuccess) e = launch_momentum(c, phi_s, u3, 0);
-    // adjoint pressure: D(beta G q) = D(beta l_du), zero mean, warm start 0
+    // adjoint pressure: D(beta G q) = D(beta l_du), zero mean; warm start:
+    // the adjoint pressure of the previous stage in the sweep
     if (e == hipSuccess)
         k_adj_rhs<T><<<g, b, 0, c->stream>>>(d, P, static_cast<const T*>(phi_s), lk[1], lk[2], c->b, c->partials);
     if (e == hipSuccess) e = hipGetLastError();
     if (e == hipSuccess) e = launch_finalize(c, nb, 1, FIN_MEAN);
-    if (e == hipSuccess) e = hipMemsetAsync(c->p, 0, (size_t)c->N * 8, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->p, af(c, AF_Q), (size_t)c->N * 8, hipMemcpyDeviceToDevice, c->stream);
     if (e != hipSuccess) return hip_fail(e, "adjoint stage setup");
     int it = 0, outer = 0;
     double rr = 0.0;
     tpf_status st = poisson_solve(c, phi_s, &it, &rr, &outer);
     if (st != TPF_OK) return st;
+    e = hipMemcpyAsync(af(c, AF_Q), c->p, (size_t)c->N * 8, hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "adjoint pressure copy");
     const Fwd<T> F = fwd_of<T>(c, phi_s, u_s);
     AdjFields A{lk[0], lk[1], lk[2], p_s, c->p,
                 af(c, AF_LX), af(c, AF_LX + 1), af(c, AF_LRHO), af(c, AF_LRHO + 1),
@@ -468,8 +473,10 @@ static tpf_status vec_out(tpf_ctx* c, double* dst, const double* src, int on_dev
     return e == hipSuccess ? TPF_OK : hip_fail(e, "cotangent copy out");
 }
 
+// zero the parameter accumulators and the adjoint-pressure warm start
 static tpf_status zero_grad(tpf_ctx* c) {
     hipError_t e = hipMemsetAsync(af(c, AF_GRAD), 0, 2 * sizeof(double), c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(af(c, AF_Q), 0, (size_t)c->N * 8, c->stream);
     return e == hipSuccess ? TPF_OK : hip_fail(e, "gradient reset");
 }
 

@@ -171,6 +171,7 @@ static size_t carve(tpf_ctx* c, char* base) {
     c->p = (double*)cv.take(N8);
     c->p_hist1 = (double*)cv.take(N8);
     c->p_hist2 = (double*)cv.take(N8);
+    c->p_hist3 = (double*)cv.take(N8);
     c->r64 = c->mixed ? (double*)cv.take(N8) : nullptr;
     c->pv = cv.take((size_t)c->N * ssz);
     c->pv2 = cv.take((size_t)c->N * ssz);
@@ -436,19 +437,27 @@ tpf_status advance(tpf_ctx* c, double dt, int nsteps, char* tape, size_t stage_b
                     st = copy_async(c, rec + (1 + a) * fT, u_s[a], NT);
                 if (st != TPF_OK) return st;
             }
-            // warm start of the pressure solve: the last pressure (stages 1
-            // and 3 sit at the time of the previous stage), extrapolated
-            // linearly in time for stage 2 (t + dt/2, from t and t - dt/2)
-            // and stage 4 (t + dt, from t and t + dt/2)
+            // warm start of the pressure solve, from the pressures of the
+            // previous stages: stage 1 (time t) takes the last pressure
+            // (stage 4 of the previous step); stage 2 (t + dt/2) extrapolates
+            // linearly from t - dt/2 and t; stage 3 (t + dt/2 again) adds to
+            // the stage-2 pressure the stage-3 minus stage-2 difference of the
+            // previous step; stage 4 (t + dt) extrapolates from t and t + dt/2
             hipError_t ew = hipSuccess;
-            if (s == 1 && c->hist2_valid) ew = launch_extrapolate(c, c->p, c->p_hist2);
-            if (s == 3) ew = launch_extrapolate(c, c->p, c->p_hist1);
+            const long Nn = c->N;
+            if (s == 1 && c->hist2_valid) ew = launch_lincomb(c, c->p, 2.0, c->p, -1.0, c->p_hist2);
+            if (s == 2 && c->hist2_valid) ew = launch_lincomb(c, c->p, 1.0, c->p, 1.0, c->p_hist3);
+            if (s == 3) ew = launch_lincomb(c, c->p, 2.0, c->p, -1.0, c->p_hist1);
             if (ew != hipSuccess) return hip_fail(ew, "pressure extrapolation");
             RKArgs rk{s, 0, wacc[s], wnext[s]};
             const void* us[3] = {u_s[0], u_s[1], u_s[2]};
             tpf_status st = stage_eval(c, phi_s, us, rk, phi_o, u_o, 0);
-            if (st == TPF_OK && s <= 1)
-                st = copy_async(c, s == 0 ? c->p_hist1 : c->p_hist2, c->p, (size_t)c->N * 8);
+            if (st == TPF_OK && s == 0) st = copy_async(c, c->p_hist1, c->p, (size_t)Nn * 8);
+            if (st == TPF_OK && s == 1) st = copy_async(c, c->p_hist2, c->p, (size_t)Nn * 8);
+            if (st == TPF_OK && s == 2) {
+                ew = launch_lincomb(c, c->p_hist3, 1.0, c->p, -1.0, c->p_hist2);
+                if (ew != hipSuccess) st = hip_fail(ew, "pressure history");
+            }
             if (st == TPF_OK && rec) st = copy_async(c, rec + (1 + c->dim) * fT, c->p, (size_t)c->N * 8);
             if (st != TPF_OK) {
                 c->p_valid = 0;

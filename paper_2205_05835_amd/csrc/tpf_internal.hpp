@@ -118,10 +118,13 @@ struct tpf_ctx {
     long step;
     double mass0;
     int p_valid;         // ctx->p holds the projection pressure of the current state
-    // pressure history for the warm starts: stage-1 pressure of the current
-    // step (time t_n) and stage-2 pressure of the previous step (t_n - dt/2)
+    // pressure history for the warm starts: p_hist1 = stage-1 pressure of
+    // the current step (time t_n); p_hist2 = stage-2 pressure (t_n + dt/2,
+    // of the previous step until stage 2 of this one); p_hist3 = stage-3
+    // minus stage-2 pressure of the previous step
     double* p_hist1;
     double* p_hist2;
+    double* p_hist3;
     int hist2_valid;
     double last_relres;
     int last_outer, last_inner;
@@ -197,7 +200,7 @@ constexpr int ADJ_FIELDS = 26;
 size_t align256(size_t x);
 hipError_t launch_finalize(tpf_ctx* c, int nblocks, int nv, int op);
 hipError_t launch_rhs_mean(tpf_ctx* c);
-hipError_t launch_extrapolate(tpf_ctx* c, double* x, const double* y);
+hipError_t launch_lincomb(tpf_ctx* c, double* out, double a, const double* x, double b, const double* y);
 
 // 1D grid over gx*gy*gz tiles, padded to a multiple of the XCD count
 inline dim3 tile_grid(long gx, long gy, long gz) {

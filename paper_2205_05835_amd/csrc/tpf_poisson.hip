@@ -557,11 +557,11 @@ __global__ __launch_bounds__(BLOCK) void k_apply(Dims d, S ih2, Coef cf, int fir
 // ---------------------------------------------------------------- small vector kernels
 constexpr int VBLOCKS = 1024;   // grid-stride vector kernels
 
-// x = 2 x - y: linear extrapolation in time of the pressure warm start
-__global__ __launch_bounds__(BLOCK) void k_extrapolate(long N, double* __restrict__ x,
-                                                       const double* __restrict__ y) {
+// out = a x + b y (out may alias x): pressure warm starts from the history
+__global__ __launch_bounds__(BLOCK) void k_lincomb(long N, double* out, double a, const double* x, double b,
+                                                   const double* y) {
     for (long c = (long)blockIdx.x * BLOCK + threadIdx.x; c < N; c += (long)gridDim.x * BLOCK)
-        x[c] = 2.0 * x[c] - y[c];
+        out[c] = a * x[c] + b * y[c];
 }
 
 __global__ __launch_bounds__(BLOCK) void k_correct(long N, double* __restrict__ x,
@@ -1468,9 +1468,9 @@ struct Solver {
 };
 
 
-hipError_t launch_extrapolate(tpf_ctx* c, double* x, const double* y) {
+hipError_t launch_lincomb(tpf_ctx* c, double* out, double a, const double* x, double b, const double* y) {
     prof_begin(c, PC_VECTOR, (double)c->N * 24);
-    k_extrapolate<<<vgrid(c->N), BLOCK, 0, c->stream>>>(c->N, x, y);
+    k_lincomb<<<vgrid(c->N), BLOCK, 0, c->stream>>>(c->N, out, a, x, b, y);
     prof_end(c);
     return hipGetLastError();
 }
