@@ -130,6 +130,7 @@ static size_t carve_batch(tpf_batch* b, char* base) {
         K.kappa = take(NT);
         K.b = (double*)take(N * 8);
         K.p = (double*)take(N * 8);
+        for (int k = 0; k < 3; ++k) K.ph[k] = (double*)take(N * 8);
         K.pv = take(NS);
         K.qv = take(NS);
         K.ev = take(NS);

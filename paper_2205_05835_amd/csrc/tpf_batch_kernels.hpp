@@ -34,6 +34,7 @@ struct BCase {
     void* kappa;
     double* b;
     double* p;          // pressure (solution and warm start), FP64
+    double* ph[3];      // pressure history for the warm starts (as the single-case step)
     void* pv;           // CG direction (solver precision)
     void* qv;           // A p
     void* ev;           // mixed: inner solution (correction)
@@ -52,7 +53,7 @@ struct BState {
     int status;         // TPF_OK, or the failure that froze the case
     int nonfinite;      // set by the stage ops when a non-finite value appears
     int iters, outer;   // last pressure solve
-    int fails, pad;
+    int fails, hist_valid;   // hist_valid: the pressure history is from a completed step
     double t;
     double relres;      // last pressure solve
     long long step;
@@ -461,6 +462,38 @@ struct BatchBlock {
         return status;
     }
 
+    // ---------------------------------------------------------- warm starts
+    // Pressure warm start of stage s from the pressures of the earlier
+    // stages (the rule of the single-case step): stage 2 extrapolates from
+    // t - dt/2 and t, stage 3 adds the previous step's stage-3 minus stage-2
+    // difference, stage 4 extrapolates from t and t + dt/2.
+    __device__ void warm_start(int s, bool valid) {
+        double* p = K.p;
+        const double* h1 = K.ph[0];
+        const double* h2 = K.ph[1];
+        const double* h3 = K.ph[2];
+        if ((s == 1 || s == 2) && !valid) return;
+        if (s == 0) return;
+        cells(dims(0), [&](const Cell& C) {
+            const unsigned c = C.id;
+            if (s == 1) p[c] = 2.0 * p[c] - h2[c];
+            else if (s == 2) p[c] = p[c] + h3[c];
+            else p[c] = 2.0 * p[c] - h1[c];
+        });
+        __syncthreads();
+    }
+    __device__ void record_pressure(int s) {
+        const double* p = K.p;
+        if (s == 3) return;
+        cells(dims(0), [&](const Cell& C) {
+            const unsigned c = C.id;
+            if (s == 0) K.ph[0][c] = p[c];
+            else if (s == 1) K.ph[1][c] = p[c];
+            else K.ph[2][c] = p[c] - K.ph[1][c];
+        });
+        __syncthreads();
+    }
+
     // ---------------------------------------------------------- one stage
     // (phi, u) in slot `in`: dphi/dt and du/dt with the RK update of rk, the
     // outputs to slot `out` (and to the accumulator).  Returns a status.
@@ -501,8 +534,10 @@ struct BatchBlock {
         __syncthreads();
         cells(d, [&](const Cell& C) { (void)op_div<T, 2>(P, C, f0, f1, nullptr, K.b); });
         __syncthreads();
+        if (!rk.eval_only) warm_start(rk.stage, st->hist_valid != 0);
         const int status = poisson(phi);
         if (status != TPF_OK) return status;
+        if (!rk.eval_only) record_pressure(rk.stage);
         cells(d, [&](const Cell& C) {
             op_project<T, 2>(P, rk, C, phi, K.p, f0, f1, nullptr, static_cast<const T*>(K.y[yn][1]),
                              static_cast<const T*>(K.y[yn][2]), nullptr, static_cast<T*>(K.y[acc][1]),
@@ -556,11 +591,13 @@ __global__ __launch_bounds__(NT) void k_batch_step(const BCase* __restrict__ cas
         if (status == TPF_OK && st->nonfinite) status = TPF_ENONFINITE;
         if (status != TPF_OK) {
             st->status = status;
+            st->hist_valid = 0;
         } else if (commit) {
             st->yn = acc;
             st->acc = yn;
             st->t += dt;
             st->step += 1;
+            st->hist_valid = 1;
         }
         st->nonfinite = 0;
     }
