@@ -508,6 +508,7 @@ tpf_status tpf::eval_current(tpf_ctx* c, int want_force) {
     RKArgs rk{0, 1, 0.0, 0.0};
     const void* us[3] = {u_s[0], u_s[1], u_s[2]};
     tpf_status st = stage_eval(c, phi_s, us, rk, phi_o, u_o, want_force);
+    if (st == TPF_OK) st = gauge_pressure(c);
     if (st == TPF_OK) c->p_valid = 1;
     return st;
 }
@@ -646,6 +647,7 @@ tpf_status tpf_poisson_solve(tpf_ctx* c, const double* b, double* x, int32_t on_
     c->hist2_valid = 0;
     if (iters) *iters = it;
     if (relres) *relres = rr;
+    if (st == TPF_OK) st = gauge_pressure(c);
     if (st != TPF_OK) return st;
     e = hipMemcpyAsync(x, c->p, (size_t)c->N * 8, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
                        c->stream);

@@ -191,6 +191,7 @@ hipError_t launch_diagnostics(tpf_ctx* c, const void* phi, const void* const u[3
 
 // pressure solver (tpf_poisson.hip)
 tpf_status poisson_solve(tpf_ctx* c, const void* phi, int* iters, double* relres, int* outer);
+tpf_status gauge_pressure(tpf_ctx* c);    // subtract the mean of c->p
 // advance nsteps RK4 steps; with a tape, record every stage's input state and
 // its pressure (stage_bytes per stage, layout of the adjoint tape)
 tpf_status advance(tpf_ctx* c, double dt, int nsteps, char* tape, size_t stage_bytes);

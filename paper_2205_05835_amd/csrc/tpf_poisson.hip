@@ -766,9 +766,9 @@ __device__ __forceinline__ S apply7(const S* bl, const S* bh, const Nbr7<S>& x, 
 
 // Marches the half density and one field along the column through the KZ
 // planes of the block's slab (KZ a compile-time constant, the loop fully
-// unrolled): the column values of planes up to k+3 and the in-plane
-// neighbours and per-cell operands (pre) of planes k+1 and k+2 are in flight
-// while plane k is computed.  Unrolling gives every plane's operands their own
+// unrolled): with a lookahead of LA planes, the column values of planes up to
+// k+LA+1 and the in-plane neighbours and per-cell operands (pre) of planes up
+// to k+LA are in flight while plane k is computed.  Unrolling gives every plane's operands their own
 // registers, so no loaded value is copied before it is used and the memory
 // waits are partial (only for the plane being computed), never a drain.
 // fld(idx, i, j, k) loads the field's raw operands at a cell (type V);
@@ -780,10 +780,14 @@ struct SideV {           // plane neighbours that need loads
     V fxm, fxp, fym, fyp;
 };
 
+#ifndef TPF_MARCH_LOOKAHEAD
+#define TPF_MARCH_LOOKAHEAD 2
+#endif
 template <int KZ, typename Coef, typename S, bool WITH_FIELD, typename F, typename Cmb, typename Pre,
           typename Body>
 __device__ __forceinline__ void march(const Col& q, const Coef& cf, int k0, F fld, Cmb comb, Pre pre,
                                       Body body) {
+    constexpr int LA = TPF_MARCH_LOOKAHEAD;     // planes of lookahead (1 or 2)
     using V = decltype(fld(0u, 0, 0, 0));
     using E = decltype(pre(0u));
     auto side = [&](int k) {
@@ -814,22 +818,22 @@ __device__ __forceinline__ void march(const Col& q, const Coef& cf, int k0, F fl
     SideV<S, V> sd[KZ];
     E e[KZ];
 #pragma unroll
-    for (int m = 0; m < 4 && m < KZ + 2; ++m) {
+    for (int m = 0; m < LA + 2 && m < KZ + 2; ++m) {
         h[m] = hcol(k0 - 1 + m);
         f[m] = fcol(k0 - 1 + m);
     }
 #pragma unroll
-    for (int t = 0; t < 2 && t < KZ; ++t) {
+    for (int t = 0; t < LA && t < KZ; ++t) {
         sd[t] = side(k0 + t);
         e[t] = pre(q.at(k0 + t));
     }
 #pragma unroll
     for (int t = 0; t < KZ; ++t) {
-        if (t + 2 < KZ) {            // loads of plane k+2 and of the column of k+3
-            sd[t + 2] = side(k0 + t + 2);
-            e[t + 2] = pre(q.at(k0 + t + 2));
-            h[t + 4] = hcol(k0 + t + 3);
-            f[t + 4] = fcol(k0 + t + 3);
+        if (t + LA < KZ) {           // loads of plane k+LA and of the column of k+LA+1
+            sd[t + LA] = side(k0 + t + LA);
+            e[t + LA] = pre(q.at(k0 + t + LA));
+            h[t + LA + 2] = hcol(k0 + t + LA + 1);
+            f[t + LA + 2] = fcol(k0 + t + LA + 1);
         }
         const S hc = h[t + 1];
         const S lhm = lane_m(hc), lhp = lane_p(hc);
@@ -1501,8 +1505,17 @@ static tpf_status read_scalars(tpf_ctx* c, SolverScalars* s) {
 
 static double omega_of(int dim) { return dim == 2 ? 0.8 : 6.0 / 7.0; }
 
+// Zero-mean gauge of the pressure (Z13 of the readings): applied where the
+// pressure leaves the library.  Inside a step only G p is used, which the
+// gauge does not change, so the solves skip it.
+tpf_status gauge_pressure(tpf_ctx* c) {
+    hipError_t e = remove_mean(c, c->p);
+    return e == hipSuccess ? TPF_OK : hip_fail(e, "mean removal");
+}
+
 // Solve with beta from phi (state precision); right-hand side in c->b with
-// its mean in scal->mean; x = c->p (warm start in, solution out, zero mean).
+// its mean in scal->mean; x = c->p (warm start in, solution out; its mean is
+// whatever the warm start carried, see gauge_pressure).
 tpf_status poisson_solve(tpf_ctx* c, const void* phi, int* iters, double* relres, int* outer) {
     const double rtol = c->P.poisson_rtol;
     const int maxit = c->P.poisson_maxit;
@@ -1515,8 +1528,6 @@ tpf_status poisson_solve(tpf_ctx* c, const void* phi, int* iters, double* relres
         (void)finalize2(c, (int)sv.nb0(), (int)sv.nb0(), FIN_INIT, rtol * rtol);
         e = sv.pcg<double>(phi, c->p, maxit, 0);
         if (e != hipSuccess) return hip_fail(e, "FP64 PCG");
-        e = remove_mean(c, c->p);
-        if (e != hipSuccess) return hip_fail(e, "mean removal");
         tpf_status st = read_scalars(c, &s);
         if (st != TPF_OK) return st;
         if (!std::isfinite(s.ff) || !std::isfinite(s.rr)) {
@@ -1552,8 +1563,6 @@ tpf_status poisson_solve(tpf_ctx* c, const void* phi, int* iters, double* relres
             *outer = o;
             *iters = total;
             *relres = s.ff > 0 ? std::sqrt(s.rr / s.ff) : 0.0;
-            e = remove_mean(c, c->p);
-            if (e != hipSuccess) return hip_fail(e, "mean removal");
             return TPF_OK;
         }
         // the inner solve aims straight at the outer tolerance (half of the
