@@ -242,6 +242,8 @@ static void init_geometry(tpf_ctx* c, const tpf_params* P) {
     const char* mga = std::getenv("TPF_MG_ALPHA");
     c->mg_alpha = mga ? std::atof(mga) : 1.0;
     if (!(c->mg_alpha > 0.0 && c->mg_alpha < 2.0)) c->mg_alpha = 1.0;
+    const char* cs = std::getenv("TPF_COARSE_SWEEPS");
+    c->coarse_sweeps_per_cell = cs ? std::max(0, std::atoi(cs)) : 0;
     const char* kzs = std::getenv("TPF_KZ");
     c->kz_override = kzs ? std::atoi(kzs) : 0;
     const char* xt = std::getenv("TPF_XCD_TILES");

@@ -162,6 +162,7 @@ struct tpf_ctx {
     int pred_iters[4];
     int kz_override;     // planes per block of the z-marching kernels (0: automatic)
     double mg_alpha;     // weight of the multigrid coarse-grid correction
+    int coarse_sweeps_per_cell;   // coarsest-grid Jacobi sweeps per cell of its largest dimension (0: 2)
 };
 
 namespace tpf {

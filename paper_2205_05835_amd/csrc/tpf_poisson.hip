@@ -1118,6 +1118,9 @@ struct Solver {
     // correction weight (the coarse problem is linear, so scaling its
     // right-hand side scales the correction; R stays proportional to P^T)
     S rw() const { return S(c->mg_alpha / (dim == 3 ? 8.0 : 4.0)); }
+    // damped Jacobi sweeps on the coarsest grid (largest dimension mx): 2 mx
+    // by default; more do not lower the PCG iteration count
+    int coarse_sweeps(int mx) const { return (c->coarse_sweeps_per_cell > 0 ? c->coarse_sweeps_per_cell : 2) * mx; }
     double fb(int l, double fields) const { return (double)c->lv[l].N * sizeof(S) * fields; }
     // fields moved by the coefficients: phi on the fine level, DIM arrays below
     double cfields(int l) const { return l == 0 ? (double)sizeof(T) / sizeof(S) : (double)dim; }
@@ -1289,7 +1292,7 @@ struct Solver {
         const Level& Ll = c->lv[c->nlev - 1];
         const int mx = std::max(Ll.n[0], std::max(Ll.n[1], Ll.n[2]));
         prof_begin(c, PC_COARSE_LEVELS, (double)off * sizeof(S));
-        k_tail<S, DIM><<<1, 1024, (size_t)off * sizeof(S), c->stream>>>(D, omega, S(0.8), 8 * mx,
+        k_tail<S, DIM><<<1, 1024, (size_t)off * sizeof(S), c->stream>>>(D, omega, S(0.8), coarse_sweeps(mx),
                                                                         tp<S>(c->lv[l0].r),
                                                                         tp<S>(c->lv[l0].zt), c->scal);
         prof_end(c);
@@ -1304,7 +1307,7 @@ struct Solver {
         if (l == c->nlev - 1) {
             const int mx = std::max(L.n[0], std::max(L.n[1], L.n[2]));
             prof_begin(c, PC_COARSE_LEVELS, fb(l, 3));
-            k_coarse<S, DIM><<<1, 1024, 0, c->stream>>>(dims(l), ih2(l), S(0.8), 8 * mx, coef(l),
+            k_coarse<S, DIM><<<1, 1024, 0, c->stream>>>(dims(l), ih2(l), S(0.8), coarse_sweeps(mx), coef(l),
                                                         tp<S>(L.r), tp<S>(L.zt), tp<S>(L.z), c->scal);
             prof_end(c);
             return tp<S>(L.zt);
