@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, 8 TB/s
 # (FETCH_SIZE, then WRITE_SIZE), each scaled by what the same counter reads
 # for a plain device copy of known size; recorded with a hash of the kernel
 # sources and reported only while the sources still match.
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fine_apply_256cubed_traffic.json")
+TRAFFIC_DIR = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = ("paper_2205_05835_amd/csrc/tpf_poisson.hip", "paper_2205_05835_amd/csrc/tpf_device.hpp")
 
 
@@ -46,10 +46,11 @@ def kernel_source_hash():
 
 
 def recorded_traffic(kernel):
-    """Traffic bytes per launch of `kernel` from the committed counter
-    summary, or None if there is none or the kernel sources changed since."""
+    """Traffic bytes per launch of kernel class `kernel` from the committed
+    counter summary profiles/<class>_256cubed_traffic.json, or None if there
+    is none or the kernel sources changed since."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(os.path.join(TRAFFIC_DIR, f"{kernel}_256cubed_traffic.json")) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None

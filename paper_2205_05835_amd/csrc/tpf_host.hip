@@ -102,9 +102,12 @@ static bool prof_alloc(tpf_ctx* c, int cap) {
     c->ev_class = new (std::nothrow) int[cap];
     c->ev_bytes = new (std::nothrow) double[cap];
     if (!c->ev_a || !c->ev_b || !c->ev_class || !c->ev_bytes) return false;
+    // timing-only events: no system-scope fence (no cache writeback and
+    // invalidation around each timed launch), so the timed kernels run as
+    // they would without them
     for (int q = 0; q < cap; ++q) {
-        if (hipEventCreate(&c->ev_a[q]) != hipSuccess) return false;
-        if (hipEventCreate(&c->ev_b[q]) != hipSuccess) return false;
+        if (hipEventCreateWithFlags(&c->ev_a[q], hipEventDisableSystemFence) != hipSuccess) return false;
+        if (hipEventCreateWithFlags(&c->ev_b[q], hipEventDisableSystemFence) != hipSuccess) return false;
         c->ev_cap = q + 1;
     }
     return true;
