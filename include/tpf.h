@@ -63,7 +63,8 @@ typedef enum {
 /* Parameters of one case.  Non-dimensional throughout. */
 typedef struct {
     int32_t dim;              /* 2 or 3                                           */
-    int32_t n[3];             /* cells per axis; n[2] = 1 when dim = 2            */
+    int32_t n[3];             /* cells per axis (>= 2); n[2] = 1 when dim = 2;
+                                 at most 2^29 cells in total                      */
     double length;            /* box edge along x; h = length / n[0]              */
     int32_t model;            /* tpf_model                                        */
     int32_t force;            /* tpf_force                                        */

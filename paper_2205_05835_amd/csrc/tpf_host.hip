@@ -211,6 +211,12 @@ tpf_status resolve_params(const tpf_params* in, tpf_params* P) {
     if (P->dim == 2) P->n[2] = 1;
     for (int a = 0; a < P->dim; ++a)
         if (P->n[a] < 2) { set_error("each n[a] must be >= 2"); return TPF_EINVAL; }
+    // kernels address fields with 32-bit byte offsets: FP64 fields must stay below 4 GiB
+    const long long ncell = (long long)P->n[0] * P->n[1] * P->n[2];
+    if (ncell > (1LL << 29)) {
+        set_error("grid too large: at most 2^29 cells per case");
+        return TPF_EINVAL;
+    }
     if (P->length <= 0) P->length = 1.0;
     if (P->model < 0 || P->model > 2) { set_error("unknown model"); return TPF_EINVAL; }
     if (P->force < 0 || P->force > 2) { set_error("unknown force"); return TPF_EINVAL; }

@@ -102,3 +102,15 @@ def test_batch_workspace_validation(tpf):
     assert len(tpf.batch_configs()) == tpf.lib().tpf_batch_configs() >= 1
     for threads, lds in tpf.batch_configs():
         assert threads in (256, 512, 1024) and 0 <= lds <= 65536 - 1024
+
+
+def test_grid_size_limits(tpf):
+    """n >= 2 per axis and at most 2^29 cells (32-bit byte offsets of FP64 fields)."""
+    for n in [(1, 16), (16, 1), (8, 8, 1)]:
+        with pytest.raises(tpf.TpfError):
+            tpf.workspace_bytes(tpf.make_params(n))
+    with pytest.raises(tpf.TpfError) as e:
+        tpf.workspace_bytes(tpf.make_params((1024, 1024, 1024), precision="fp32_mixed"))
+    assert "too large" in str(e.value)
+    assert tpf.workspace_bytes(tpf.make_params((512, 512, 512), precision="fp32_mixed")) > 0
+    assert tpf.workspace_bytes(tpf.make_params((2, 2))) > 0

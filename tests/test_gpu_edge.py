@@ -1,0 +1,134 @@
+"""GPU parity on ragged and degenerate cases, through the C ABI.
+
+Grids that the multigrid cannot coarsen (odd sizes), grids whose x extent
+is not a multiple of the 64-cell row tile, z extents outside the z-march
+(plain kernels), the smallest 2 x 2 grid, no surface tension, and a single
+phase with a random divergence-free velocity: each against the FP64
+oracle.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2205_05835_amd import tpf
+    tpf.lib()
+    return tpf
+
+
+def oparams(ora, case, **kw):
+    base = dict(n=case.n, length=case.length, model=ora.MODELS[case.model],
+                force=ora.FORCES[case.force], sigma=case.sigma, eps=case.eps, gamma=case.gamma,
+                rho1=case.rho1, rho2=case.rho2, visc1=case.visc1, visc2=case.visc2)
+    base.update(kw)
+    return ora.Params(**base)
+
+
+def run_pair(gpu, ora, case, phi0, u0, steps, umax0=0.0):
+    dt = case.dt(umax0=umax0)
+    P = oparams(ora, case)
+    s = gpu.solver_for_case(case, poisson_rtol=1e-14, poisson_maxit=5000)
+    s.set_state(phi0, u0)
+    s.step(dt, steps)
+    phi_g, u_g, _ = s.get_state()
+    phi_o, u_o, pw = ora.step(P, dt, steps, phi0, u0)
+    _, du_o, _ = ora.stage(P, phi_o, u_o, pw)
+    uref = max(max(np.abs(x).max() for x in u_o), dt * max(np.abs(x).max() for x in du_o), 1e-300)
+    ephi = np.abs(phi_g - phi_o).max()
+    eu = max(np.abs(u_g[a] - u_o[a]).max() for a in range(len(u_o))) / uref
+    return ephi, eu, u_g, phi_g
+
+
+CASES = [
+    # name, n, semi-axes, model, force
+    ("odd_2d", (33, 21), (0.3, 0.22), "CDI", "EB"),
+    ("ragged_x_3d", (70, 24, 16), (0.3, 0.25, 0.22), "CDI", "EB"),
+    ("plain_z_3d", (24, 16, 10), (0.3, 0.25, 0.22), "SB", "LCSF"),
+    ("odd_3d", (15, 12, 10), (0.3, 0.25, 0.22), "ISODI", "CSF"),
+    ("tiny_2d", (2, 2), (0.3, 0.3), "CDI", "EB"),
+    ("thin_2d", (128, 4), (0.3, 0.2), "CDI", "LCSF"),
+]
+
+
+@pytest.mark.parametrize("name,n,axes,model,force", CASES, ids=[c[0] for c in CASES])
+def test_ragged_grids_match_oracle(gpu, ora, name, n, axes, model, force):
+    dim = len(n)
+    # box L_a = n_a h: drop at the centre with semi-axes as fractions of L_a
+    center = tuple(0.5 * n[a] / n[0] for a in range(dim))
+    axes = tuple(axes[a] * n[a] / n[0] for a in range(dim))
+    case = workloads.Case(name, n, center, axes, 1.0, 0.1, 0.02, 0.004, 1.0, 1.0, model, force, "fp64")
+    say(f"edge case {name} {n} {model} {force}")
+    P = oparams(ora, case)
+    phi0 = ora.init_droplet(P, case.center, case.semi_axes)
+    u0 = workloads.divergence_free_velocity(P.shape, 3, amplitude=0.05)
+    ephi, eu, _, _ = run_pair(gpu, ora, case, phi0, u0, 3, umax0=0.1)
+    say(f"  |dphi| {ephi:.2e}  |du|/Uref {eu:.2e}")
+    assert ephi < 1e-12 and eu < 1e-12
+
+
+def test_no_surface_tension_keeps_fluid_at_rest(gpu, ora):
+    """sigma = 0, u = 0: no force, so u stays exactly 0 and phi evolves by
+    the CDI regularisation alone (as in the oracle)."""
+    case = workloads.Case("sigma0", (40, 32), (0.5, 0.4), (0.3, 0.2), 1.0, 0.1, 0.02, 0.004, 0.0, 1.0,
+                          "CDI", "EB", "fp64")
+    say("sigma = 0 at rest")
+    P = oparams(ora, case)
+    phi0 = ora.init_droplet(P, case.center, case.semi_axes)
+    zero = [np.zeros(P.shape)] * 2
+    ephi, _, u_g, _ = run_pair(gpu, ora, case, phi0, zero, 5)
+    assert ephi < 1e-12
+    assert all(np.abs(x).max() == 0.0 for x in u_g)
+
+
+def test_single_phase_flow(gpu, ora):
+    """phi = 1 everywhere: constant density and viscosity, no interface; a
+    random divergence-free velocity is advected and diffused as in the
+    oracle and stays divergence free."""
+    case = workloads.Case("single_phase", (32, 24, 16), (0.5, 0.375, 0.25), (0.2, 0.2, 0.2), 1.0, 0.1,
+                          0.02, 0.004, 1.0, 1.0, "CDI", "EB", "fp64")
+    say("single phase")
+    P = oparams(ora, case)
+    phi0 = np.ones(P.shape)
+    u0 = workloads.divergence_free_velocity(P.shape, 4, amplitude=0.2)
+    ephi, eu, u_g, phi_g = run_pair(gpu, ora, case, phi0, u0, 3, umax0=0.3)
+    say(f"  |dphi| {ephi:.2e}  |du|/Uref {eu:.2e}")
+    assert ephi < 1e-14 and eu < 1e-12
+    assert np.abs(phi_g - 1.0).max() == 0.0
+
+
+def test_mixed_precision_ragged(gpu, ora):
+    """FP32-mixed on a ragged 3D grid (x not a multiple of 64, z-march on):
+    the mixed-precision error bounds."""
+    n = (70, 24, 16)
+    case = workloads.Case("ragged_mixed", n, (0.5 * 70 / 70, 0.5 * 24 / 70, 0.5 * 16 / 70), (0.3, 0.15, 0.1),
+                          1.0, 0.1, 0.02, 0.004, 1.0, 1.0, "CDI", "EB", "fp32_mixed")
+    say("mixed precision, ragged 3D")
+    P = oparams(ora, case)
+    phi0 = ora.init_droplet(P, case.center, case.semi_axes).astype(np.float32).astype(np.float64)
+    zero = [np.zeros(P.shape)] * 3
+    dt = case.dt()
+    s = gpu.solver_for_case(case)
+    s.set_state(phi0, zero)
+    s.step(dt, 5)
+    phi_g, u_g, _ = s.get_state()
+    phi_o, u_o, _ = ora.step(P, dt, 5, phi0, zero)
+    umax = max(np.abs(x).max() for x in u_o)
+    ephi = np.abs(phi_g - phi_o).max()
+    eu = max(np.abs(u_g[a] - u_o[a]).max() for a in range(3)) / umax
+    say(f"  |dphi| {ephi:.2e} |du|/|u| {eu:.2e}")
+    assert ephi < 1e-5 and eu < 1e-2

@@ -180,7 +180,7 @@ def test_static_drop_64_fp64_200_steps(gpu, ora):
     eu = max(np.abs(u_g[a] - u_o[a]).max() for a in range(2)) / uref
     ep = rel(p_g, p_o)
     say(f"  |dphi| {ephi:.2e}  |du|/Uref {eu:.2e}  |dp|/|p| {ep:.2e}")
-    assert ephi < TOL64 and eu < 1e-10 and ep < 1e-11
+    assert ephi < TOL64 and eu < TOL64 and ep < TOL64
     dg = s.diagnostics()
     do = ora.diagnostics(P, phi_o, u_o, p_o)
     assert abs(dg["mass"] - dg["mass0"]) / dg["mass0"] < 1e-13      # CDI conserves mass
@@ -211,7 +211,9 @@ def test_ratio1000_steps_fp64(gpu, ora, model, force):
     ephi = np.abs(phi_g - phi_o).max()
     eu = max(np.abs(u_g[a] - u_o[a]).max() for a in range(2)) / uref
     say(f"  |dphi| {ephi:.2e}  |du|/Uref {eu:.2e}")
-    assert ephi < TOL64 and eu < 1e-10
+    # density ratio 1000: the projection's condition number (~5e5 here) turns
+    # the 1e-14 solver residual into ~3e-12 in u (measured bound)
+    assert ephi < TOL64 and eu < 1e-11
 
 
 def test_oscillating_drop_3d_fp64(gpu, ora):
@@ -232,7 +234,7 @@ def test_oscillating_drop_3d_fp64(gpu, ora):
     ephi = np.abs(phi_g - phi_o).max()
     eu = max(np.abs(u_g[a] - u_o[a]).max() for a in range(3)) / uref
     say(f"  |dphi| {ephi:.2e}  |du|/Uref {eu:.2e}")
-    assert ephi < TOL64 and eu < 1e-10
+    assert ephi < TOL64 and eu < TOL64
 
 
 def test_mixed_precision_error_statement(gpu, ora):
