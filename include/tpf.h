@@ -82,6 +82,9 @@ typedef struct {
                                  tolerance, but not below this); 0 -> 1e-6       */
     int32_t poisson_maxit;    /* PCG iteration cap per solve; 0 -> 400            */
     int32_t mg_levels;        /* multigrid levels; 0 -> as deep as the grid allows */
+    int32_t adjoint;          /* 1: the workspace also holds the scratch of the
+                                 adjoint calls (11 + 8 dim FP64 fields of N
+                                 values); 0: those calls return TPF_EINVAL   */
 } tpf_params;
 
 /* Scalar diagnostics of the current state (FP64; t and step count included). */
@@ -194,31 +197,35 @@ tpf_status tpf_load_checkpoint(tpf_ctx* ctx, const void* dev_src);
 
 /* ------------------------------------------------------------------ adjoint
  * Reverse-mode derivative of the discrete step, written by hand for every
- * stage operator (2D contexts, CDI model of Table 1, energy-based force of
- * Eq. 4; other configurations return TPF_EINVAL).  Cotangents are FP64 arrays
- * of N values laid out as the state (phi at cells, u_a on the lower a-faces);
- * parameter cotangents are those of sigma and eps (holding the state fixed).
+ * stage operator: 2D and 3D, the CDI, SB and ISODI models of Table 1, and the
+ * energy-based (Eq. 4), CSF and localized CSF (Eq. 11) forces.  The context
+ * must be created with params.adjoint = 1.  Cotangents are FP64 arrays of N
+ * values laid out as the state (phi at cells, u_a on the lower a-faces; the
+ * u2 arguments are ignored in 2D and may be NULL there); parameter cotangents
+ * are those of sigma and eps (holding the state fixed).  The SB term
+ * eps |C phi| kappa is differentiated with d|g|/dg = g/|g|, taken as 0 where
+ * g = 0.
  *
  * tpf_stage_adjoint: for one stage evaluation F(y) = (dphi/dt, du/dt) at the
- * current state y, given the cotangent (lphi, lu0, lu1) of F(y), write
- * (gphi, gu0, gu1) = F'(y)^T (lphi, lu0, lu1) and ADD dF/d(sigma, eps)^T to
+ * current state y, given the cotangent (lphi, lu) of F(y), write
+ * (gphi, gu) = F'(y)^T (lphi, lu) and ADD dF/d(sigma, eps)^T (lphi, lu) to
  * grad_params[0..1].  The state is not changed.
  *
  * tpf_step_adjoint: for nsteps steps of size dt starting from the current
  * state y_0: runs them forward (the context ends at y_nsteps), recording
  * every stage's input state and pressure on the caller's device buffer
  * `tape` (tpf_adjoint_tape_bytes(nsteps) bytes), then sweeps back.  On entry
- * (gphi, gu0, gu1) hold dL/dy_nsteps; on return dL/dy_0, and
- * dL/d(sigma, eps) over these steps is ADDED to grad_params.  For long
- * rollouts, checkpoint every K steps and call this once per segment, last
- * segment first (each from its loaded checkpoint).
+ * (gphi, gu) hold dL/dy_nsteps; on return dL/dy_0, and dL/d(sigma, eps) over
+ * these steps is ADDED to grad_params.  For long rollouts, checkpoint every K
+ * steps and call this once per segment, last segment first (each from its
+ * loaded checkpoint).
  * on_device: 1 if the cotangent pointers are device pointers. */
 tpf_status tpf_adjoint_tape_bytes(const tpf_ctx* ctx, int32_t nsteps, size_t* bytes);
 tpf_status tpf_stage_adjoint(tpf_ctx* ctx, const double* lphi, const double* lu0, const double* lu1,
-                             double* gphi, double* gu0, double* gu1, double grad_params[2],
-                             int32_t on_device);
+                             const double* lu2, double* gphi, double* gu0, double* gu1, double* gu2,
+                             double grad_params[2], int32_t on_device);
 tpf_status tpf_step_adjoint(tpf_ctx* ctx, void* tape, size_t tape_bytes, double dt, int32_t nsteps,
-                            double* gphi, double* gu0, double* gu1, int32_t on_device,
+                            double* gphi, double* gu0, double* gu1, double* gu2, int32_t on_device,
                             double grad_params[2]);
 
 /* ------------------------------------------------------------------ batches

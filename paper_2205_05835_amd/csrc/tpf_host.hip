@@ -194,9 +194,9 @@ static size_t carve(tpf_ctx* c, char* base) {
     c->diag_out = (double*)cv.take(16 * 8);
     c->scal = (SolverScalars*)cv.take(sizeof(SolverScalars));
     c->flags = (int*)cv.take(64);
-    if (c->dim == 2) {
+    if (c->P.adjoint) {
         c->adj_stride = (long)(align256((size_t)c->N * 8) / 8);
-        c->adj = (double*)cv.take((size_t)ADJ_FIELDS * c->adj_stride * 8 + 256);
+        c->adj = (double*)cv.take((size_t)adj_fields(c->dim) * c->adj_stride * 8 + 256);
     } else {
         c->adj = nullptr;
         c->adj_stride = 0;
@@ -231,6 +231,7 @@ tpf_status resolve_params(const tpf_params* in, tpf_params* P) {
     if (P->poisson_rtol_inner <= 0) P->poisson_rtol_inner = 1e-6;
     if (P->poisson_maxit <= 0) P->poisson_maxit = 400;
     if (P->mg_levels < 0) { set_error("mg_levels must be >= 0"); return TPF_EINVAL; }
+    if (P->adjoint != 0 && P->adjoint != 1) { set_error("adjoint must be 0 or 1"); return TPF_EINVAL; }
     return TPF_OK;
 }
 

@@ -151,8 +151,9 @@ struct tpf_ctx {
     long prof_noop[tpf::NPROF];
     double prof_noop_bytes[tpf::NPROF];
 
-    // adjoint scratch (2D contexts): ADJ_FIELDS FP64 cell/face arrays of
-    // adj_stride elements each, then the two parameter-gradient accumulators
+    // adjoint scratch (contexts created with params.adjoint = 1):
+    // adj_fields(dim) FP64 cell/face arrays of adj_stride elements each, then
+    // the two parameter-gradient accumulators
     double* adj;
     long adj_stride;
 
@@ -198,7 +199,9 @@ tpf_status gauge_pressure(tpf_ctx* c);    // subtract the mean of c->p
 tpf_status advance(tpf_ctx* c, double dt, int nsteps, char* tape, size_t stage_bytes);
 // one stage evaluation at the current state (pressure to c->p)
 tpf_status eval_current(tpf_ctx* c, int want_force);
-constexpr int ADJ_FIELDS = 26;
+// FP64 fields of the adjoint scratch: 4 groups of (1 + dim) state
+// cotangents, 4 groups of dim face cotangents and 7 cell fields
+inline int adj_fields(int dim) { return 4 * (1 + dim) + 4 * dim + 7; }
 size_t align256(size_t x);
 hipError_t launch_finalize(tpf_ctx* c, int nblocks, int nv, int op);
 hipError_t launch_rhs_mean(tpf_ctx* c);

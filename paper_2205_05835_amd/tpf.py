@@ -57,7 +57,7 @@ class tpf_params(ctypes.Structure):
                 ("rho2", ctypes.c_double), ("visc1", ctypes.c_double), ("visc2", ctypes.c_double),
                 ("normal_delta", ctypes.c_double), ("poisson_rtol", ctypes.c_double),
                 ("poisson_rtol_inner", ctypes.c_double), ("poisson_maxit", ctypes.c_int32),
-                ("mg_levels", ctypes.c_int32)]
+                ("mg_levels", ctypes.c_int32), ("adjoint", ctypes.c_int32)]
 
 
 class tpf_diag(ctypes.Structure):
@@ -124,8 +124,8 @@ def lib():
         "tpf_save_checkpoint": ([vp, vp], i32),
         "tpf_load_checkpoint": ([vp, vp], i32),
         "tpf_adjoint_tape_bytes": ([vp, i32, ctypes.POINTER(ctypes.c_size_t)], i32),
-        "tpf_stage_adjoint": ([vp, vp, vp, vp, vp, vp, vp, dp, i32], i32),
-        "tpf_step_adjoint": ([vp, vp, ctypes.c_size_t, ctypes.c_double, i32, vp, vp, vp, i32, dp], i32),
+        "tpf_stage_adjoint": ([vp, vp, vp, vp, vp, vp, vp, vp, vp, dp, i32], i32),
+        "tpf_step_adjoint": ([vp, vp, ctypes.c_size_t, ctypes.c_double, i32, vp, vp, vp, vp, i32, dp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -143,7 +143,7 @@ def check(status: int, where: str) -> None:
 def make_params(n, length=1.0, model="CDI", force="EB", precision="fp64", clamp_properties=1,
                 sigma=1.0, eps=None, gamma=1.0, rho1=1.0, rho2=1.0, visc1=0.1, visc2=0.1,
                 normal_delta=1e-12, poisson_rtol=0.0, poisson_rtol_inner=0.0, poisson_maxit=0,
-                mg_levels=0) -> tpf_params:
+                mg_levels=0, adjoint=0) -> tpf_params:
     n = tuple(int(x) for x in n)
     dim = len(n)
     h = length / n[0]
@@ -160,6 +160,7 @@ def make_params(n, length=1.0, model="CDI", force="EB", precision="fp64", clamp_
     p.normal_delta = normal_delta
     p.poisson_rtol, p.poisson_rtol_inner = poisson_rtol, poisson_rtol_inner
     p.poisson_maxit, p.mg_levels = poisson_maxit, mg_levels
+    p.adjoint = int(adjoint)
     return p
 
 
@@ -304,13 +305,14 @@ class Solver:
 
     def stage_adjoint(self, lphi, lu):
         """F'(y)^T (lphi, lu) of one stage evaluation at the current state:
-        (gphi, [gu0, gu1], [d/dsigma, d/deps]) as host arrays."""
-        a = [_host(lphi, self.N), _host(lu[0], self.N), _host(lu[1], self.N)]
-        out = [np.empty(self.shape) for _ in range(3)]
+        (gphi, [gu_a], [d/dsigma, d/deps]) as host arrays."""
+        a = [_host(lphi, self.N)] + [_host(lu[k], self.N) for k in range(self.dim)]
+        out = [np.empty(self.shape) for _ in range(1 + self.dim)]
         gp = (ctypes.c_double * 2)(0.0, 0.0)
         ptr = lambda x: x.ctypes.data_as(ctypes.c_void_p)
-        check(lib().tpf_stage_adjoint(self.ctx, *[ptr(x) for x in a], *[ptr(x) for x in out], gp, 0),
-              "tpf_stage_adjoint")
+        ins = [ptr(x) for x in a] + [None] * (3 - self.dim)
+        outs = [ptr(x) for x in out] + [None] * (3 - self.dim)
+        check(lib().tpf_stage_adjoint(self.ctx, *ins, *outs, gp, 0), "tpf_stage_adjoint")
         return out[0], out[1:], [gp[0], gp[1]]
 
     def step_adjoint(self, dt: float, nsteps: int, gphi, gu, tape=None, grad_params=None):
@@ -321,17 +323,18 @@ class Solver:
         if tape is None:
             tape = torch.empty(max(self.tape_bytes(nsteps), 1), dtype=torch.uint8, device=self.device)
         gp = (ctypes.c_double * 2)(*(grad_params if grad_params is not None else (0.0, 0.0)))
+        pad = [None] * (3 - self.dim)
         if isinstance(gphi, torch.Tensor):
-            arrs = [gphi.contiguous().clone()] + [x.contiguous().clone() for x in gu]
+            arrs = [gphi.contiguous().clone()] + [gu[k].contiguous().clone() for k in range(self.dim)]
             for t in arrs:
                 if t.dtype != torch.float64 or not t.is_cuda:
                     raise ValueError("device cotangents must be float64 CUDA tensors")
-            ptrs = [ctypes.c_void_p(t.data_ptr()) for t in arrs]
+            ptrs = [ctypes.c_void_p(t.data_ptr()) for t in arrs] + pad
             check(lib().tpf_step_adjoint(self.ctx, ctypes.c_void_p(tape.data_ptr()), tape.numel(), float(dt),
                                          int(nsteps), *ptrs, 1, gp), "tpf_step_adjoint")
             return arrs[0], arrs[1:], [gp[0], gp[1]]
-        arrs = [_host(gphi, self.N).copy(), _host(gu[0], self.N).copy(), _host(gu[1], self.N).copy()]
-        ptrs = [a.ctypes.data_as(ctypes.c_void_p) for a in arrs]
+        arrs = [_host(gphi, self.N).copy()] + [_host(gu[k], self.N).copy() for k in range(self.dim)]
+        ptrs = [a.ctypes.data_as(ctypes.c_void_p) for a in arrs] + pad
         check(lib().tpf_step_adjoint(self.ctx, ctypes.c_void_p(tape.data_ptr()), tape.numel(), float(dt),
                                      int(nsteps), *ptrs, 0, gp), "tpf_step_adjoint")
         return (arrs[0].reshape(self.shape), [x.reshape(self.shape) for x in arrs[1:]], [gp[0], gp[1]])

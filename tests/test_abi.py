@@ -40,7 +40,7 @@ def test_struct_layout_matches_header(tpf):
     P = tpf.tpf_params
     assert P.length.offset == 16
     assert P.sigma.offset == 40
-    assert P.poisson_maxit.offset == 120 and ctypes.sizeof(P) == 128
+    assert P.poisson_maxit.offset == 120 and P.adjoint.offset == 128 and ctypes.sizeof(P) == 136
     D = tpf.tpf_diag
     assert D.poisson_outer.offset == 104 and ctypes.sizeof(D) == 112
 
@@ -114,3 +114,20 @@ def test_grid_size_limits(tpf):
     assert "too large" in str(e.value)
     assert tpf.workspace_bytes(tpf.make_params((512, 512, 512), precision="fp32_mixed")) > 0
     assert tpf.workspace_bytes(tpf.make_params((2, 2))) > 0
+
+
+def test_adjoint_scratch_is_opt_in(tpf):
+    """params.adjoint = 1 adds 11 + 8 dim FP64 fields of N values (plus 256
+    bytes of accumulators) to the workspace; other values are rejected."""
+    for n in [(64, 48), (16, 12, 8)]:
+        N = 1
+        for x in n:
+            N *= x
+        base = tpf.workspace_bytes(tpf.make_params(n))
+        adj = tpf.workspace_bytes(tpf.make_params(n, adjoint=1))
+        fields = 11 + 8 * len(n)
+        stride = (N * 8 + 255) // 256 * 256
+        assert fields * stride <= adj - base <= fields * stride + 512
+    with pytest.raises(tpf.TpfError) as e:
+        tpf.workspace_bytes(tpf.make_params((32, 32), adjoint=2))
+    assert e.value.status == tpf.TPF_EINVAL

@@ -1,9 +1,10 @@
-"""GPU tests of the hand-written adjoint (2D, CDI, energy-based force).
+"""GPU tests of the hand-written adjoint (2D and 3D, every model and force).
 
 Checks, all through the C ABI:
   * the transpose of one stage evaluation against central differences of
     the forward stage (the dot-product test <l, J v> = <J^T l, v>), for the
-    state and for sigma and eps;
+    state and for sigma and eps, for all nine model/force pairs in 2D and
+    three in 3D;
   * the adjoint of several RK4 steps against central differences of the GPU
     forward and of the FP64 oracle's forward (the oracle's gradient);
   * checkpointed rollouts through torch.autograd equal one-segment adjoints;
@@ -17,6 +18,9 @@ import pytest
 import workloads
 
 pytestmark = pytest.mark.gpu
+
+PAIRS_2D = [(m, f) for m in ("CDI", "SB", "ISODI") for f in ("EB", "CSF", "LCSF")]
+PAIRS_3D = [("CDI", "EB"), ("SB", "CSF"), ("ISODI", "LCSF")]
 
 
 def say(msg):
@@ -34,9 +38,12 @@ def gpu():
     return tpf
 
 
-def small_case(n=(32, 24), precision="fp64"):
-    return workloads.Case(f"adj_{n[0]}x{n[1]}", n, (0.5, 0.3), (0.3, 0.17), 1.0, 0.1, 0.02, 0.004,
-                          1.0, 1.0, "CDI", "EB", precision)
+def small_case(n=(32, 24), precision="fp64", model="CDI", force="EB"):
+    if len(n) == 2:
+        return workloads.Case(f"adj_{n[0]}x{n[1]}", n, (0.5, 0.3), (0.3, 0.17), 1.0, 0.1, 0.02, 0.004,
+                              1.0, 1.0, model, force, precision)
+    return workloads.Case(f"adj_{n[0]}x{n[1]}x{n[2]}", n, (0.5, 0.35, 0.3), (0.27, 0.2, 0.17), 1.0, 0.1,
+                          0.02, 0.004, 1.0, 1.0, model, force, precision)
 
 
 def oparams(ora, case, **kw):
@@ -60,7 +67,7 @@ def state(ora, case, seed=0):
 
 
 def direction(case, phi, seed):
-    shape = (case.n[1], case.n[0])
+    shape = tuple(reversed(case.n))
     v = 4 * phi * (1 - phi) * workloads.smooth_field(shape, seed)
     v = v / np.abs(v).max()
     vu = workloads.random_velocity(shape, seed + 5, amplitude=1.0)
@@ -70,21 +77,25 @@ def direction(case, phi, seed):
 def solver(gpu, case, **kw):
     kw.setdefault("poisson_rtol", 1e-14)
     kw.setdefault("poisson_maxit", 2000)
+    kw.setdefault("adjoint", 1)
     return gpu.solver_for_case(case, **kw)
 
 
 def stage_out(s, phi, u):
     s.set_state(phi, u)
-    return s.eval_field("DPHI"), [s.eval_field("DU0"), s.eval_field("DU1")]
+    return s.eval_field("DPHI"), [s.eval_field(f"DU{a}") for a in range(len(u))]
 
 
 def dot(a, b):
     return float(sum(np.vdot(x.ravel(), y.ravel()) for x, y in zip(a, b)))
 
 
-def test_stage_adjoint_dot_product(gpu, ora):
-    case = small_case()
-    say(f"stage adjoint dot-product test {case.n}")
+@pytest.mark.parametrize("n,model,force", [((32, 24), m, f) for m, f in PAIRS_2D] +
+                         [((16, 12, 10), m, f) for m, f in PAIRS_3D])
+def test_stage_adjoint_dot_product(gpu, ora, n, model, force):
+    case = small_case(n, model=model, force=force)
+    dim = len(n)
+    say(f"stage adjoint dot-product test {case.n} {model} {force}")
     phi, u = state(ora, case)
     shape = phi.shape
     lphi = workloads.smooth_field(shape, 11)
@@ -94,9 +105,9 @@ def test_stage_adjoint_dot_product(gpu, ora):
     s.set_state(phi, u)
     gphi, gu, gp = s.stage_adjoint(lphi, lu)
     h = 1e-5
-    fp = stage_out(s, phi + h * v, [u[a] + h * vu[a] for a in range(2)])
-    fm = stage_out(s, phi - h * v, [u[a] - h * vu[a] for a in range(2)])
-    jv = [(fp[0] - fm[0]) / (2 * h)] + [(fp[1][a] - fm[1][a]) / (2 * h) for a in range(2)]
+    fp = stage_out(s, phi + h * v, [u[a] + h * vu[a] for a in range(dim)])
+    fm = stage_out(s, phi - h * v, [u[a] - h * vu[a] for a in range(dim)])
+    jv = [(fp[0] - fm[0]) / (2 * h)] + [(fp[1][a] - fm[1][a]) / (2 * h) for a in range(dim)]
     lhs = dot([lphi] + lu, jv)
     rhs = dot([gphi] + gu, [v] + vu)
     say(f"  <l, J v> {lhs:.12e}  <J^T l, v> {rhs:.12e}  rel {abs(lhs - rhs) / abs(lhs):.2e}")
@@ -107,30 +118,42 @@ def test_stage_adjoint_dot_product(gpu, ora):
         dh = 1e-5 if name == "sigma" else 1e-5 * base
         outs = []
         for sgn in (1, -1):
-            s2 = solver(gpu, case, **{name: base + sgn * dh})
+            kw = {"sigma": base + sgn * dh} if name == "sigma" else {"eps": base + sgn * dh}
+            s2 = solver(gpu, case, adjoint=0, **kw)
             outs.append(stage_out(s2, phi, u))
-        jp = [(outs[0][0] - outs[1][0]) / (2 * dh)] + [(outs[0][1][a] - outs[1][1][a]) / (2 * dh) for a in range(2)]
+        jp = [(outs[0][0] - outs[1][0]) / (2 * dh)] + [(outs[0][1][a] - outs[1][1][a]) / (2 * dh)
+                                                       for a in range(dim)]
         fd = dot([lphi] + lu, jp)
         say(f"  d/d{name}: FD {fd:.12e}  adjoint {gp[k]:.12e}  rel {abs(fd - gp[k]) / abs(fd):.2e}")
         assert abs(fd - gp[k]) <= 1e-6 * abs(fd)
 
 
+def test_adjoint_needs_scratch(gpu):
+    """A context created without params.adjoint refuses the adjoint calls."""
+    case = small_case()
+    s = solver(gpu, case, adjoint=0)
+    s.init_droplet(case.center, case.semi_axes)
+    with pytest.raises(gpu.TpfError) as e:
+        s.tape_bytes(1)
+    assert e.value.status == gpu.TPF_EINVAL
+
+
 def loss_and_seed(case, phi_t, u_t, tgt, c_u=0.1):
-    h2 = case.h ** 2
-    L = 0.5 * h2 * float(np.sum((phi_t - tgt) ** 2)) + 0.5 * c_u * h2 * sum(float(np.sum(x * x)) for x in u_t)
-    return L, h2 * (phi_t - tgt), [c_u * h2 * x for x in u_t]
+    hd = case.h ** case.dim
+    L = 0.5 * hd * float(np.sum((phi_t - tgt) ** 2)) + 0.5 * c_u * hd * sum(float(np.sum(x * x)) for x in u_t)
+    return L, hd * (phi_t - tgt), [c_u * hd * x for x in u_t]
 
 
 def target_of(ora, case):
     P = oparams(ora, case)
     rng = np.random.default_rng(1)
-    xi = rng.normal(size=2)
-    ax = (case.semi_axes[0] * (1 + 0.05 * xi[0]), case.semi_axes[1] * (1 + 0.05 * xi[1]))
+    xi = rng.normal(size=case.dim)
+    ax = tuple(case.semi_axes[a] * (1 + 0.05 * xi[a]) for a in range(case.dim))
     return ora.init_droplet(P, case.center, ax)
 
 
 def gpu_loss(gpu, case, phi0, u0, tgt, steps, dt, **kw):
-    s = solver(gpu, case, **kw)
+    s = solver(gpu, case, adjoint=0, **kw)
     s.set_state(phi0, u0)
     s.step(dt, steps)
     phi, u, _ = s.get_state()
@@ -143,12 +166,21 @@ def ora_loss(ora, case, phi0, u0, tgt, steps, dt, **kw):
     return loss_and_seed(case, phi, u, tgt)[0]
 
 
-@pytest.mark.parametrize("reference", ["gpu", "oracle"])
-def test_step_adjoint_against_finite_differences(gpu, ora, reference):
-    case = small_case() if reference == "gpu" else small_case((24, 20))
+STEP_CASES = [
+    ("gpu", (32, 24), "CDI", "EB"), ("gpu", (32, 24), "SB", "CSF"), ("gpu", (32, 24), "ISODI", "LCSF"),
+    ("gpu", (16, 12, 8), "CDI", "EB"), ("gpu", (16, 12, 8), "SB", "LCSF"),
+    ("oracle", (24, 20), "CDI", "EB"), ("oracle", (24, 20), "ISODI", "CSF"), ("oracle", (24, 20), "SB", "LCSF"),
+    ("oracle", (12, 10, 8), "ISODI", "EB"),
+]
+
+
+@pytest.mark.parametrize("reference,n,model,force", STEP_CASES)
+def test_step_adjoint_against_finite_differences(gpu, ora, reference, n, model, force):
+    case = small_case(n, model=model, force=force)
+    dim = case.dim
     steps = 4 if reference == "gpu" else 3
     dt = case.dt(umax0=0.2)
-    say(f"step adjoint vs {reference} central differences {case.n} x {steps}")
+    say(f"step adjoint vs {reference} central differences {case.n} {model} {force} x {steps}")
     phi0, u0 = state(ora, case, seed=3)
     tgt = target_of(ora, case)
     s = solver(gpu, case)
@@ -167,7 +199,8 @@ def test_step_adjoint_against_finite_differences(gpu, ora, reference):
     # phi0 direction, u0 direction
     fd_phi = (L(phi0 + h * v, u0) - L(phi0 - h * v, u0)) / (2 * h)
     ad_phi = float(np.vdot(g0.ravel(), v.ravel()))
-    fd_u = (L(phi0, [u0[a] + h * vu[a] for a in range(2)]) - L(phi0, [u0[a] - h * vu[a] for a in range(2)])) / (2 * h)
+    fd_u = (L(phi0, [u0[a] + h * vu[a] for a in range(dim)]) -
+            L(phi0, [u0[a] - h * vu[a] for a in range(dim)])) / (2 * h)
     ad_u = dot(gu0, vu)
     fd_s = (L(phi0, u0, sigma=case.sigma + h) - L(phi0, u0, sigma=case.sigma - h)) / (2 * h)
     he = h * case.eps
@@ -179,48 +212,52 @@ def test_step_adjoint_against_finite_differences(gpu, ora, reference):
         assert rel < 2e-5, name
 
 
-def test_rollout_checkpoints_and_autograd(gpu, ora):
+@pytest.mark.parametrize("n,model,force,steps,every", [((32, 24), "CDI", "EB", 12, 5),
+                                                       ((16, 12, 8), "SB", "CSF", 5, 2)])
+def test_rollout_checkpoints_and_autograd(gpu, ora, n, model, force, steps, every):
     import torch
     from paper_2205_05835_amd import adjoint
-    case = small_case()
-    steps = 12
+    case = small_case(n, model=model, force=force)
+    dim = case.dim
     dt = case.dt(umax0=0.2)
-    say(f"autograd rollout {case.n} x {steps}, checkpoints every 5 vs one segment")
+    say(f"autograd rollout {case.n} {model} {force} x {steps}, checkpoints every {every} vs one segment")
     phi0, u0 = state(ora, case, seed=4)
     tgt = torch.tensor(target_of(ora, case), device="cuda")
     params = gpu.params_for_case(case, poisson_rtol=1e-14, poisson_maxit=2000)
+    hd = case.h ** dim
     grads = []
-    for every in (5, steps):
+    for ev in (every, steps):
         f0 = torch.tensor(phi0, device="cuda", requires_grad=True)
         uu = [torch.tensor(x, device="cuda", requires_grad=True) for x in u0]
         sig = torch.tensor(case.sigma, dtype=torch.float64, requires_grad=True)
         eps = torch.tensor(case.eps, dtype=torch.float64, requires_grad=True)
-        phi, u = adjoint.rollout(f0, uu, sig, eps, params, dt, steps, every)
-        loss = 0.5 * case.h ** 2 * ((phi - tgt) ** 2).sum() + 0.05 * case.h ** 2 * sum((x * x).sum() for x in u)
+        phi, u = adjoint.rollout(f0, uu, sig, eps, params, dt, steps, ev)
+        loss = 0.5 * hd * ((phi - tgt) ** 2).sum() + 0.05 * hd * sum((x * x).sum() for x in u)
         loss.backward()
-        grads.append([f0.grad.cpu().numpy(), uu[0].grad.cpu().numpy(), uu[1].grad.cpu().numpy(),
-                      float(sig.grad), float(eps.grad)])
-    for k in range(3):
+        grads.append([f0.grad.cpu().numpy()] + [x.grad.cpu().numpy() for x in uu] +
+                     [float(sig.grad), float(eps.grad)])
+    for k in range(1 + dim):
         scale = np.abs(grads[1][k]).max()
         assert np.abs(grads[0][k] - grads[1][k]).max() <= 1e-12 * scale, k
-    for k in (3, 4):
+    for k in (1 + dim, 2 + dim):
         assert abs(grads[0][k] - grads[1][k]) <= 1e-12 * abs(grads[1][k]), k
-    say(f"  dL/dsigma {grads[0][3]:.10e} dL/deps {grads[0][4]:.10e}")
+    say(f"  dL/dsigma {grads[0][1 + dim]:.10e} dL/deps {grads[0][2 + dim]:.10e}")
 
 
-def test_mixed_precision_adjoint(gpu, ora):
-    case64 = small_case()
-    case32 = small_case(precision="fp32_mixed")
+@pytest.mark.parametrize("n,model,force", [((32, 24), "CDI", "EB"), ((16, 12, 8), "ISODI", "LCSF")])
+def test_mixed_precision_adjoint(gpu, ora, n, model, force):
+    case64 = small_case(n, model=model, force=force)
+    case32 = small_case(n, precision="fp32_mixed", model=model, force=force)
     steps = 4
     dt = case64.dt(umax0=0.2)
-    say("FP32-mixed adjoint vs FP64 adjoint")
+    say(f"FP32-mixed adjoint vs FP64 adjoint {n} {model} {force}")
     phi0, u0 = state(ora, case64, seed=5)
     phi0 = phi0.astype(np.float32).astype(np.float64)
     u0 = [x.astype(np.float32).astype(np.float64) for x in u0]
     tgt = target_of(ora, case64)
     out = {}
     for name, case in (("fp64", case64), ("fp32", case32)):
-        s = solver(gpu, case) if name == "fp64" else gpu.solver_for_case(case)
+        s = solver(gpu, case) if name == "fp64" else gpu.solver_for_case(case, adjoint=1)
         s.set_state(phi0, u0)
         s.step(dt, steps)
         phi_t, u_t, _ = s.get_state()

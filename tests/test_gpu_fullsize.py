@@ -234,7 +234,7 @@ def test_fullsize_adjoint_dot_product(gpu):
     the stage transpose against central differences of the stage."""
     case = workloads.oscillating_drop_2d(256, "fp64")
     say(f"full-size stage adjoint {case.n}")
-    s = gpu.solver_for_case(case, poisson_rtol=1e-14, poisson_maxit=4000)
+    s = gpu.solver_for_case(case, poisson_rtol=1e-14, poisson_maxit=4000, adjoint=1)
     s.init_droplet(case.center, case.semi_axes)
     phi, _, _ = s.get_state()
     shape = phi.shape
