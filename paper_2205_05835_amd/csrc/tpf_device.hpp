@@ -105,6 +105,23 @@ __device__ __forceinline__ bool cell_of_thread(const Dims& d, Cell& C) {
     return true;
 }
 
+// z-chunked tiling of the stage kernels: the grid has ceil(nz / kz) tiles in
+// z and the block of tile (bx, by, kc) handles its BX x BY cells in planes
+// kc kz ... kc kz + kz - 1, bottom to top.  The z neighbours one plane reads
+// are read again by the same block in the next plane shortly after, so they
+// come from L2 instead of HBM.
+template <typename F>
+__device__ __forceinline__ void for_cells_zchunk(const Dims& d, int kz, F&& body) {
+    int bx, by, bz;
+    if (!block_tile(d.xcd, (d.nx + BX - 1) / BX, (d.ny + BY - 1) / BY, (d.nz + kz - 1) / kz, bx, by, bz))
+        return;
+    const int i = bx * BX + threadIdx.x;
+    const int j = by * BY + threadIdx.y;
+    if (i >= d.nx || j >= d.ny) return;
+    const int k0 = bz * kz, k1 = min(d.nz, k0 + kz);
+    for (int k = k0; k < k1; ++k) body(make_cell(d, i, j, k));
+}
+
 // Loads and stores at a 32-bit element index: the byte offset is formed in
 // 32 bits (grids below 2^29 cells for FP64 fields, 2^30 for FP32), so the
 // access compiles to a scalar base address plus one 32-bit vector offset
@@ -144,8 +161,9 @@ __device__ __forceinline__ T psi(T f) {
 }
 template <typename T>
 __device__ __forceinline__ T clamp01(const Phys& P, T f) {
-    if (!P.clamp) return f;
-    return f < T(0) ? T(0) : (f > T(1) ? T(1) : f);
+    // wave-uniform bounds: without the clamp the interval is the whole line
+    const T lo = P.clamp ? T(0) : T(-INFINITY), hi = P.clamp ? T(1) : T(INFINITY);
+    return med3(f, lo, hi);
 }
 // linear mixture laws, phase 1 = phi 1
 template <typename T>

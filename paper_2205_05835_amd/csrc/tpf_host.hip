@@ -48,7 +48,7 @@ Phys phys_of(const tpf_ctx* c) { return phys_of_params(c->P); }
 static const char* kProfNames[NPROF] = {
     "stage_cell", "stage_kappa", "stage_face", "stage_phase", "stage_momentum", "stage_div",
     "stage_project", "fine_apply", "fine_update_sweep1", "fine_sweep1", "fine_sweep2",
-    "fine_restrict", "fine_prolong_sweep3", "fine_sweep4_dot", "mg_coarse_levels",
+    "fine_restrict", "fine_prolong", "fine_sweep4_dot", "mg_coarse_levels",
     "residual", "reduce_finalize", "vector"};
 
 static void prof_flush(tpf_ctx* c) {
@@ -189,7 +189,7 @@ static size_t carve(tpf_ctx* c, char* base) {
         L.r = cv.take((size_t)L.N * ssz);
     }
     c->max_blocks = std::max(nblocks_of(c->n), (long)((c->N + BLOCK - 1) / BLOCK));
-    c->partials = (double*)cv.take((size_t)c->max_blocks * 2 * 8);
+    c->partials = (double*)cv.take((size_t)c->max_blocks * 3 * 8);
     c->diag_part = (double*)cv.take((size_t)nblocks_of(c->n) * 11 * 8);
     c->diag_out = (double*)cv.take(16 * 8);
     c->scal = (SolverScalars*)cv.take(sizeof(SolverScalars));
@@ -256,6 +256,9 @@ static void init_geometry(tpf_ctx* c, const tpf_params* P) {
     c->coarse_sweeps_per_cell = cs ? std::max(0, std::atoi(cs)) : 0;
     const char* kzs = std::getenv("TPF_KZ");
     c->kz_override = kzs ? std::atoi(kzs) : 0;
+    const char* skz = std::getenv("TPF_STAGE_KZ");
+    c->stage_kz = skz ? std::atoi(skz) : (c->dim == 3 ? 8 : 1);
+    c->stage_kz = std::min(std::max(c->stage_kz, 1), 64);
     const char* xt = std::getenv("TPF_XCD_TILES");
     g_xcd_tiles = (xt && xt[0] == '0') ? 0 : 1;
     c->nlev = plan_levels(c);

@@ -37,7 +37,7 @@ enum FinOp {
     FIN_INIT = 1,   // v0 = ff, v1 = rr     -> ff, rr, done = rr <= tol2 ff
     FIN_RZ0 = 2,    // v0 = rz              -> rz (first), keeps done
     FIN_ALPHA = 3,  // v0 = pq              -> alpha = rz / pq
-    FIN_BETA = 4,   // v0 = rr, v1 = rz_new -> beta, rz, rr, done, iters++
+    FIN_BETA = 4,   // v0 = rr, v1 = rz_new, v2 = <A p, z_new> -> beta = -v2 / pq, rz, rr, done, iters++
     FIN_SUM = 5     // v0 = sum x           -> sum
 };
 
@@ -162,6 +162,7 @@ struct tpf_ctx {
     // first after that many iterations
     int pred_iters[4];
     int kz_override;     // planes per block of the z-marching kernels (0: automatic)
+    int stage_kz;        // planes per block of the z-chunked stage kernels
     double mg_alpha;     // weight of the multigrid coarse-grid correction
     int coarse_sweeps_per_cell;   // coarsest-grid Jacobi sweeps per cell of its largest dimension (0: 2)
 };
@@ -216,6 +217,10 @@ inline dim3 grid_of(const int n[3]) {
     return tile_grid((n[0] + BX - 1) / BX, (n[1] + BY - 1) / BY, n[2]);
 }
 inline long nblocks_of(const int n[3]) { return (long)grid_of(n).x; }
+// grid of the z-chunked stage kernels (kz planes per block)
+inline dim3 zchunk_grid(const int n[3], int kz) {
+    return tile_grid((n[0] + BX - 1) / BX, (n[1] + BY - 1) / BY, (n[2] + kz - 1) / kz);
+}
 extern int g_xcd_tiles;   // XCD slab tiling of the block grids (TPF_XCD_TILES=0 disables)
 inline Dims dims_of(const int n[3]) { return Dims{n[0], n[1], n[2], g_xcd_tiles}; }
 Phys phys_of(const tpf_ctx* c);

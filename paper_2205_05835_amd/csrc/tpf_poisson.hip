@@ -264,43 +264,120 @@ __global__ __launch_bounds__(BLOCK) void k_jac_first_update(Dims d, S ih2, S ome
     block_partials<1>(v, partials);
 }
 
-// zt = Z + omega (r - A Z) / d, with Z = z (PRO = 0) or Z = z + P zc (PRO = 1:
-// piecewise-constant prolongation of the coarse correction formed on the
-// fly); DOT = 1 also emits <r, zt> to region 1.
-template <typename Coef, typename S, int DIM, int PRO, int DOT>
-__global__ __launch_bounds__(BLOCK) void k_jac(Dims d, Dims cd, S ih2, S omega, Coef cf,
+template <typename S>
+struct Vec2;
+template <>
+struct Vec2<float> { using type = float2; };
+template <>
+struct Vec2<double> { using type = double2; };
+
+// zt = z + omega (r - A z) / d; DOT = 1 also emits <r, zt> to region 1 and
+// <q, zt> to region 2 (stride apart) for the flexible-CG update.
+template <typename Coef, typename S, int DIM, int DOT>
+__global__ __launch_bounds__(BLOCK) void k_jac(Dims d, S ih2, S omega, Coef cf,
                                                const S* __restrict__ r, const S* __restrict__ z,
-                                               const S* __restrict__ zc, S* __restrict__ zt,
+                                               S* __restrict__ zt, const S* __restrict__ qv,
                                                const SolverScalars* __restrict__ sc,
-                                               double* __restrict__ partials) {
+                                               double* __restrict__ partials, long stride) {
     if (sc->done) return;
     Cell C;
-    double v[1] = {0.0};
+    double v[2] = {0.0, 0.0};
     if (cell_of_thread(d, C)) {
-        // parent of c + s e_a on the coarse grid: the parent of c itself when
-        // the shift stays inside the same 2x2x2 family, else its neighbour
-        Cell Pc;
-        if (PRO) Pc = make_cell(cd, C.i >> 1, C.j >> 1, DIM == 3 ? C.k >> 1 : 0);
-        const int par[3] = {C.i & 1, C.j & 1, C.k & 1};
-        auto parent = [&](int a, int s) -> unsigned {
-            const bool leaves = (s < 0) ? (par[a] == 0) : (par[a] == 1);
-            return leaves ? Pc.nb(a, s) : Pc.id;
-        };
-        auto Z = [&](int a, int s) -> S {
-            if (!PRO) return ld(z, C.nb(a, s));
-            return ld(z, C.nb(a, s)) + ld(zc, parent(a, s));
-        };
+        auto Z = [&](int a, int s) -> S { return ld(z, C.nb(a, s)); };
         S bl[3], bh[3], dg;
         cf.template faces<DIM>(C, bl, bh);
         const unsigned c = C.id;
-        const S zcen = PRO ? ld(z, c) + ld(zc, Pc.id) : ld(z, c);
+        const S zcen = ld(z, c);
         const S az = apply_at<S, DIM>(bl, bh, Z, zcen, ih2, dg);
         const S rc = ld(r, c);
         const S out = zcen + omega * (rc - az) * recip(dg);
         st(zt, c, out);
-        if (DOT) v[0] = (double)rc * (double)out;
+        if (DOT) {
+            v[0] = (double)rc * (double)out;
+            v[1] = (double)ld(qv, c) * (double)out;
+        }
     }
-    if (DOT) block_partials<1>(v, partials);
+    if (DOT) block_partials_2r(v, partials, stride);
+}
+
+// Cell-centred multilinear interpolation of a coarse field at fine cell
+// (i, j, k): along each axis the fine cell 2I + s takes 3/4 of coarse cell I
+// and 1/4 of the coarse neighbour on its own side (I - 1 for s = 0, I + 1 for
+// s = 1), periodic; the weights multiply across axes.
+template <typename S, int DIM>
+__device__ __forceinline__ S prolong_at(const Dims& cd, const S* zc, int i, int j, int k) {
+    const int I = i >> 1, J = j >> 1, K = DIM == 3 ? k >> 1 : 0;
+    const int I2 = wrapc(I + ((i & 1) ? 1 : -1), cd.nx);
+    const int J2 = wrapc(J + ((j & 1) ? 1 : -1), cd.ny);
+    const int K2 = DIM == 3 ? wrapc(K + ((k & 1) ? 1 : -1), cd.nz) : 0;
+    auto at = [&](int a, int b, int e) { return zc[(e * cd.ny + b) * cd.nx + a]; };
+    const S w1 = S(0.75), w2 = S(0.25);
+    const S s0 = w1 * (w1 * at(I, J, K) + w2 * at(I2, J, K)) + w2 * (w1 * at(I, J2, K) + w2 * at(I2, J2, K));
+    if (DIM == 2) return s0;
+    const S s1 = w1 * (w1 * at(I, J, K2) + w2 * at(I2, J, K2)) + w2 * (w1 * at(I, J2, K2) + w2 * at(I2, J2, K2));
+    return w1 * s0 + w2 * s1;
+}
+
+// z += P zc (the coarse-grid correction, interpolated).  One thread per
+// coarse cell writes its 2^DIM children: the 3^DIM coarse values around the
+// cell are read once and interpolated axis by axis (x, then y, then z), and
+// each fine row pair (2I, 2I + 1) is one 2-element access (coalesced across
+// the wave).
+template <typename S, int DIM>
+__global__ __launch_bounds__(BLOCK) void k_prolong(Dims fd, Dims cd, const S* __restrict__ zc,
+                                                   S* __restrict__ z, const SolverScalars* __restrict__ sc) {
+    if (sc->done) return;
+    Cell Q;
+    if (!cell_of_thread(cd, Q)) return;
+    using S2 = typename Vec2<S>::type;
+    constexpr int NZ = DIM == 3 ? 3 : 1;
+    const S w1 = S(0.75), w2 = S(0.25);
+    // x pass: for each coarse row (J + dj, K + dk), the values at the two
+    // fine x positions 2I and 2I + 1
+    S xl[NZ][3], xh[NZ][3];
+#pragma unroll
+    for (int dk = 0; dk < NZ; ++dk)
+#pragma unroll
+        for (int dj = 0; dj < 3; ++dj) {
+            unsigned q = Q.id;
+            if (DIM == 3 && dk != 1) q += (unsigned)Q.o[2][dk > 1];
+            if (dj != 1) q += (unsigned)Q.o[1][dj > 1];
+            const int row = (int)q - Q.i;       // first cell of that coarse row
+            const S cm = ld(zc, (unsigned)(row + (Q.i == 0 ? cd.nx - 1 : Q.i - 1)));
+            const S c0 = ld(zc, q);
+            const S cp = ld(zc, (unsigned)(row + (Q.i == cd.nx - 1 ? 0 : Q.i + 1)));
+            xl[dk][dj] = w1 * c0 + w2 * cm;
+            xh[dk][dj] = w1 * c0 + w2 * cp;
+        }
+    const int fi = 2 * Q.i;
+#pragma unroll
+    for (int sz = 0; sz < (DIM == 3 ? 2 : 1); ++sz)
+#pragma unroll
+        for (int sy = 0; sy < 2; ++sy) {
+            // y pass (rows J and J -+ 1), then z pass (planes K and K -+ 1)
+            auto ypass = [&](int dk, S& lo, S& hi) {
+                const int dj = sy ? 2 : 0;
+                lo = w1 * xl[dk][1] + w2 * xl[dk][dj];
+                hi = w1 * xh[dk][1] + w2 * xh[dk][dj];
+            };
+            S lo, hi;
+            if (DIM == 3) {
+                S l0, h0, l1, h1;
+                ypass(1, l0, h0);
+                ypass(sz ? 2 : 0, l1, h1);
+                lo = w1 * l0 + w2 * l1;
+                hi = w1 * h0 + w2 * h1;
+            } else {
+                ypass(0, lo, hi);
+            }
+            const int fj = 2 * Q.j + sy, fk = DIM == 3 ? 2 * Q.k + sz : 0;
+            const unsigned f = (unsigned)((fk * fd.ny + fj) * fd.nx + fi);
+            S2* p = reinterpret_cast<S2*>(reinterpret_cast<char*>(z) + (unsigned)(f * (unsigned)sizeof(S)));
+            S2 v = *p;
+            v.x += lo;
+            v.y += hi;
+            *p = v;
+        }
 }
 
 // coarse rhs = mean over the 2^DIM children of (r - A z).  One thread per
@@ -381,9 +458,9 @@ __global__ __launch_bounds__(1024) void k_coarse(Dims d, S ih2, S omega, int swe
 // 1024-thread workgroup: r, z and zt of every tail level live in LDS, the
 // face coefficients stay in global memory (L2).  The operations and their
 // order are those of the multi-kernel levels above (two damped Jacobi sweeps
-// before and after, averaging restriction, piecewise-constant prolongation,
-// fixed Jacobi sweeps on the coarsest grid), so the preconditioner remains
-// the same symmetric linear operator; only launches are saved.
+// before and after, averaging restriction, multilinear prolongation, fixed
+// Jacobi sweeps on the coarsest grid), so the preconditioner remains the same
+// linear operator; only launches are saved.
 constexpr int TAIL_MAX_LEVELS = 8;
 constexpr size_t TAIL_LDS_BYTES = 64 * 1024;
 
@@ -503,20 +580,13 @@ __global__ __launch_bounds__(1024) void k_tail(TailDesc D, S omega, S omega_c, i
         S* zt = z + N;
         const Dims dc = dims(l + 1);
         const S* zc = L + D.off[l + 1] + 2 * ncell(l + 1);
-        // Z = zt + P zc, then z = Z + omega (r - A Z) / d
-        auto Zp = [&](const Cell& C, int a, int s) -> S {
-            int i = C.i, j = C.j, k = C.k;
-            const Dims df = dims(l);
-            if (s != 0) {
-                if (a == 0) i = wrapc(i + s, df.nx);
-                else if (a == 1) j = wrapc(j + s, df.ny);
-                else k = wrapc(k + s, df.nz);
-            }
-            const int idx = (k * df.ny + j) * df.nx + i;
-            const int pc = ((DIM == 3 ? k >> 1 : 0) * dc.ny + (j >> 1)) * dc.nx + (i >> 1);
-            return zt[idx] + zc[pc];
-        };
-        sweep(l, omega, Zp, z);
+        // zt += P zc, then two sweeps zt -> z -> zt
+        for (int q = t; q < N; q += T) {
+            const Cell C = cell(l, q);
+            zt[q] += prolong_at<S, DIM>(dc, zc, C.i, C.j, C.k);
+        }
+        __syncthreads();
+        sweep(l, omega, [&](const Cell& C, int a, int s) { return zt[s == 0 ? C.id : C.nb(a, s)]; }, z);
         sweep(l, omega, [&](const Cell& C, int a, int s) { return z[s == 0 ? C.id : C.nb(a, s)]; }, zt);
     }
     {
@@ -596,17 +666,17 @@ __global__ __launch_bounds__(BLOCK) void k_fill_s(long N, S* __restrict__ x, S v
 // partials at partials + stride) in a fixed order and applies op.
 constexpr int FIN_THREADS = 1024;
 
-__global__ __launch_bounds__(FIN_THREADS) void k_finalize(int nb0, int nb1, long stride, int op,
+__global__ __launch_bounds__(FIN_THREADS) void k_finalize(int nb0, int nb1, int nb2, long stride, int op,
                                                           double arg, long N,
                                                           const double* __restrict__ partials,
                                                           SolverScalars* sc) {
     const bool skip = (op == FIN_ALPHA || op == FIN_BETA || op == FIN_RZ0) && sc->done;
     if (skip) return;
-    __shared__ double red[2][FIN_THREADS / 64];
+    __shared__ double red[3][FIN_THREADS / 64];
     const int t = threadIdx.x;
-    double v[2];
-    for (int q = 0; q < 2; ++q) {
-        const int nb = q == 0 ? nb0 : nb1;
+    double v[3];
+    for (int q = 0; q < 3; ++q) {
+        const int nb = q == 0 ? nb0 : (q == 1 ? nb1 : nb2);
         const double* p = partials + q * stride;
         double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
         int b = t;
@@ -619,18 +689,17 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finalize(int nb0, int nb1, long
         for (; b < nb; b += FIN_THREADS) a0 += p[b];
         v[q] = (a0 + a1) + (a2 + a3);
     }
-    for (int q = 0; q < 2; ++q)
+    for (int q = 0; q < 3; ++q)
         for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_down(v[q], o, 64);
-    if ((t & 63) == 0) {
-        red[0][t >> 6] = v[0];
-        red[1][t >> 6] = v[1];
-    }
+    if ((t & 63) == 0)
+        for (int q = 0; q < 3; ++q) red[q][t >> 6] = v[q];
     __syncthreads();
     if (t != 0) return;
-    double s0 = 0.0, s1 = 0.0;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     for (int w = 0; w < FIN_THREADS / 64; ++w) {
         s0 += red[0][w];
         s1 += red[1][w];
+        s2 += red[2][w];
     }
     switch (op) {
     case FIN_MEAN:    // region 0: sum b
@@ -652,9 +721,11 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finalize(int nb0, int nb1, long
         sc->alpha = (s0 > 0.0) ? sc->rz / s0 : 0.0;
         if (!(s0 > 0.0)) sc->done = 1;
         break;
-    case FIN_BETA:    // region 0: |r|^2, region 1: <r, z>
+    case FIN_BETA:    // region 0: |r|^2, region 1: <r, z>, region 2: <A p, z>
+        // flexible CG: the new direction z + beta p is made A-orthogonal to
+        // p (the preconditioner need not be symmetric)
         sc->rr = s0;
-        sc->beta = s1 / sc->rz;
+        sc->beta = (sc->pq > 0.0) ? -s2 / sc->pq : 0.0;
         sc->rz = s1;
         sc->iters += 1;
         if (s0 <= sc->tol2 * sc->ff || !(s1 > 0.0)) sc->done = 1;
@@ -675,12 +746,15 @@ __global__ void k_inner_setup(SolverScalars* sc, double tol2) {
     sc->done = sc->rr > 0.0 ? 0 : 1;
 }
 
-static hipError_t finalize2(tpf_ctx* c, int nb0, int nb1, int op, double arg) {
-    prof_begin(c, PC_FINALIZE, (double)(nb0 + nb1) * 8);
-    k_finalize<<<1, FIN_THREADS, 0, c->stream>>>(nb0, nb1, c->max_blocks, op, arg, c->N,
+static hipError_t finalize3(tpf_ctx* c, int nb0, int nb1, int nb2, int op, double arg) {
+    prof_begin(c, PC_FINALIZE, (double)(nb0 + nb1 + nb2) * 8);
+    k_finalize<<<1, FIN_THREADS, 0, c->stream>>>(nb0, nb1, nb2, c->max_blocks, op, arg, c->N,
                                                  c->partials, c->scal);
     prof_end(c);
     return hipGetLastError();
+}
+static hipError_t finalize2(tpf_ctx* c, int nb0, int nb1, int op, double arg) {
+    return finalize3(c, nb0, nb1, 0, op, arg);
 }
 
 hipError_t launch_finalize(tpf_ctx* c, int nblocks, int nv, int op) {
@@ -882,43 +956,36 @@ struct Pair {
 
 struct NoPre {};
 
-// sweeps: MODE 0: zt = z + omega (r - A z)/d; 1: same with Z = z + P zc;
-// 2: as 0 and <r, zt> to the partials
+// sweep zt = z + omega (r - A z)/d; MODE 2 also emits <r, zt> to region 1
+// and <q, zt> to region 2 (stride apart) for the flexible-CG update
 template <typename Coef, typename S, int MODE>
-__global__ __launch_bounds__(BLOCK) void k_fz_jac(Dims d, Dims cd, int kz, S ih2, S omega,
-                                                  Coef cf, const S* __restrict__ r,
-                                                  const S* __restrict__ z,
-                                                  const S* __restrict__ zc, S* __restrict__ zt,
+__global__ __launch_bounds__(BLOCK) void k_fz_jac(Dims d, int kz, S ih2, S omega, Coef cf,
+                                                  const S* __restrict__ r,
+                                                  const S* __restrict__ z, S* __restrict__ zt,
+                                                  const S* __restrict__ qv,
                                                   const SolverScalars* __restrict__ sc,
-                                                  double* __restrict__ partials) {
+                                                  double* __restrict__ partials, long stride) {
     if (sc->done) return;
     Col q;
     q.init(d, kz);
-    // MODE 1: the field is z + P zc, combined where it is used
-    auto fld = [&](unsigned idx, int i, int j, int k) -> Pair<S> {
-        Pair<S> v;
-        v.a = ld(z, idx);
-        v.b = MODE == 1 ? ld(zc, ((unsigned)(k >> 1) * cd.ny + (j >> 1)) * cd.nx + (i >> 1)) : S(0);
-        return v;
-    };
-    auto comb = [](const Pair<S>& v) -> S { return MODE == 1 ? v.a + v.b : v.a; };
-    auto pre = [&](unsigned c) -> S { return ld(r, c); };
-    double acc = 0.0;
-    march_kz<Coef, S, true>(q, cf, kz, fld, comb, pre,
-                         [&](int, unsigned c, const Nbr7<S>& R, const Nbr7<S>& X, S rc) {
+    auto fld = [&](unsigned idx, int, int, int) -> S { return ld(z, idx); };
+    auto pre = [&](unsigned c) -> Pair<S> { return Pair<S>{ld(r, c), MODE == 2 ? ld(qv, c) : S(0)}; };
+    double v[2] = {0.0, 0.0};
+    march_kz<Coef, S, true>(q, cf, kz, fld, Ident<S>{}, pre,
+                         [&](int, unsigned c, const Nbr7<S>& R, const Nbr7<S>& X, const Pair<S>& e) {
         S bl[3], bh[3], dg;
         faces7(R, bl, bh);
         const S az = apply7(bl, bh, X, ih2, dg);
         if (q.valid) {
-            const S out = X.c + omega * (rc - az) * recip(dg);
+            const S out = X.c + omega * (e.a - az) * recip(dg);
             st(zt, c, out);
-            if (MODE == 2) acc += (double)rc * (double)out;
+            if (MODE == 2) {
+                v[0] += (double)e.a * (double)out;
+                v[1] += (double)e.b * (double)out;
+            }
         }
     });
-    if (MODE == 2) {
-        double v[1] = {acc};
-        block_partials<1>(v, partials);
-    }
+    if (MODE == 2) block_partials_2r(v, partials, stride);
 }
 
 // first sweep from zero: z = omega r / d; UPD: first the PCG update
@@ -1113,7 +1180,6 @@ struct Solver {
     S ih2(int l) const { return S(1.0 / (c->lv[l].h * c->lv[l].h)); }
     dim3 grid(int l) const { return grid_of(c->lv[l].n); }
     Dims dims(int l) const { return dims_of(c->lv[l].n); }
-    Dims dims_c(int l) const { return l + 1 < c->nlev ? dims(l + 1) : dims(l); }
     // restriction weight: mean over the 2^d children times the coarse-grid
     // correction weight (the coarse problem is linear, so scaling its
     // right-hand side scales the correction; R stays proportional to P^T)
@@ -1190,8 +1256,8 @@ struct Solver {
                     prof_end(c);
                 }
                 prof_begin(c, PC_F_SWEEP, fb(l, 3 + cfl));
-                k_fz_jac<Coef, S, 0><<<mgrid(), b, 0, c->stream>>>(dims(0), dims(1), kz(), ih2(0), omega, cf, r, z,
-                                                               nullptr, zt, c->scal, nullptr);
+                k_fz_jac<Coef, S, 0><<<mgrid(), b, 0, c->stream>>>(dims(0), kz(), ih2(0), omega, cf, r, z, zt,
+                                                               nullptr, c->scal, nullptr, 0);
                 prof_end(c);
                 prof_begin(c, PC_F_RESTRICT, fb(l, 2 + cfl) + (double)Lc.N * sizeof(S));
                 k_fz_restrict<Coef, S><<<mgrid(), b, 0, c->stream>>>(dims(0), dims(1), kz(), ih2(0), rw(), cf, r, zt,
@@ -1206,8 +1272,8 @@ struct Solver {
             prof_end(c);
         }
         prof_begin(c, fine ? PC_F_SWEEP : PC_COARSE_LEVELS, fb(l, 3 + cfl));
-        k_jac<Coef, S, DIM, 0, 0><<<grid(l), b, 0, c->stream>>>(dims(l), dims_c(l), ih2(l), omega, cf, r, z,
-                                                                 nullptr, zt, c->scal, nullptr);
+        k_jac<Coef, S, DIM, 0><<<grid(l), b, 0, c->stream>>>(dims(l), ih2(l), omega, cf, r, z, zt, nullptr,
+                                                              c->scal, nullptr, 0);
         prof_end(c);
         Level& Lc = c->lv[l + 1];
         prof_begin(c, fine ? PC_F_RESTRICT : PC_COARSE_LEVELS, fb(l, 2 + cfl) + (double)Lc.N * sizeof(S));
@@ -1216,7 +1282,8 @@ struct Solver {
         prof_end(c);
     }
 
-    // Prolongation-sweep (B + P zc -> A) and last sweep (A -> B) at level l.
+    // Prolongation (B += P zc) and the two post-smoothing sweeps (B -> A,
+    // A -> B) at level l; dot: the last sweep emits the flexible-CG dots.
     template <int DIM, typename Coef>
     void level_up(int l, Coef cf, bool fine, const S* zc, int dot) {
         Level& L = c->lv[l];
@@ -1224,38 +1291,42 @@ struct Solver {
         S* z = tp<S>(L.z);
         S* zt = tp<S>(L.zt);
         const S* r = tp<S>(L.r);
+        const S* qv = tp<S>(c->qv);
+        double* part = c->partials + c->max_blocks;
+        const long stride = c->max_blocks;
         const double cb = (double)c->lv[l + 1].N * sizeof(S);
         const double cfl = cfields(l);
+        prof_begin(c, fine ? PC_F_PROLONG : PC_COARSE_LEVELS, fb(l, 2) + cb);
+        k_prolong<S, DIM><<<grid(l + 1), b, 0, c->stream>>>(dims(l), dims(l + 1), zc, zt, c->scal);
+        prof_end(c);
         if constexpr (std::is_same<Coef, CoefRho<S>>::value) {
             if (DIM == 3 && march0()) {
-                prof_begin(c, PC_F_PROLONG, fb(l, 3 + cfl) + cb);
-                k_fz_jac<Coef, S, 1><<<mgrid(), b, 0, c->stream>>>(dims(0), dims(1), kz(), ih2(0), omega, cf, r, zt,
-                                                               zc, z, c->scal, nullptr);
+                prof_begin(c, PC_F_SWEEP, fb(l, 3 + cfl));
+                k_fz_jac<Coef, S, 0><<<mgrid(), b, 0, c->stream>>>(dims(0), kz(), ih2(0), omega, cf, r, zt, z,
+                                                               nullptr, c->scal, nullptr, 0);
                 prof_end(c);
-                prof_begin(c, PC_F_SWEEPDOT, fb(l, 3 + cfl));
+                prof_begin(c, PC_F_SWEEPDOT, fb(l, 3 + (dot ? 1 : 0) + cfl));
                 if (dot)
-                    k_fz_jac<Coef, S, 2><<<mgrid(), b, 0, c->stream>>>(dims(0), dims(1), kz(), ih2(0), omega, cf, r,
-                                                                   z, nullptr, zt, c->scal,
-                                                                   c->partials + c->max_blocks);
+                    k_fz_jac<Coef, S, 2><<<mgrid(), b, 0, c->stream>>>(dims(0), kz(), ih2(0), omega, cf, r, z, zt,
+                                                                   qv, c->scal, part, stride);
                 else
-                    k_fz_jac<Coef, S, 0><<<mgrid(), b, 0, c->stream>>>(dims(0), dims(1), kz(), ih2(0), omega, cf, r,
-                                                                   z, nullptr, zt, c->scal, nullptr);
+                    k_fz_jac<Coef, S, 0><<<mgrid(), b, 0, c->stream>>>(dims(0), kz(), ih2(0), omega, cf, r, z, zt,
+                                                                   nullptr, c->scal, nullptr, 0);
                 prof_end(c);
                 return;
             }
         }
-        prof_begin(c, fine ? PC_F_PROLONG : PC_COARSE_LEVELS, fb(l, 3 + cfl) + cb);
-        k_jac<Coef, S, DIM, 1, 0><<<grid(l), b, 0, c->stream>>>(dims(l), dims(l + 1), ih2(l), omega, cf, r, zt,
-                                                                 zc, z, c->scal, nullptr);
+        prof_begin(c, fine ? PC_F_SWEEP : PC_COARSE_LEVELS, fb(l, 3 + cfl));
+        k_jac<Coef, S, DIM, 0><<<grid(l), b, 0, c->stream>>>(dims(l), ih2(l), omega, cf, r, zt, z, nullptr,
+                                                              c->scal, nullptr, 0);
         prof_end(c);
-        prof_begin(c, fine ? PC_F_SWEEPDOT : PC_COARSE_LEVELS, fb(l, 3 + cfl));
+        prof_begin(c, fine ? PC_F_SWEEPDOT : PC_COARSE_LEVELS, fb(l, 3 + (dot ? 1 : 0) + cfl));
         if (dot)
-            k_jac<Coef, S, DIM, 0, 1><<<grid(l), b, 0, c->stream>>>(dims(l), dims_c(l), ih2(l), omega, cf, r, z,
-                                                                     nullptr, zt, c->scal,
-                                                                     c->partials + c->max_blocks);
+            k_jac<Coef, S, DIM, 1><<<grid(l), b, 0, c->stream>>>(dims(l), ih2(l), omega, cf, r, z, zt, qv,
+                                                                  c->scal, part, stride);
         else
-            k_jac<Coef, S, DIM, 0, 0><<<grid(l), b, 0, c->stream>>>(dims(l), dims_c(l), ih2(l), omega, cf, r, z,
-                                                                     nullptr, zt, c->scal, nullptr);
+            k_jac<Coef, S, DIM, 0><<<grid(l), b, 0, c->stream>>>(dims(l), ih2(l), omega, cf, r, z, zt, nullptr,
+                                                                  c->scal, nullptr, 0);
         prof_end(c);
     }
 
@@ -1336,9 +1407,9 @@ struct Solver {
                 prof_end(c);
             }
             prof_begin(c, PC_F_SWEEPDOT, fb(0, 3 + cfields(0)));
-            k_fz_jac<CoefRho<S>, S, 2><<<mgrid(), b, 0, c->stream>>>(dims(0), dims(0), kz(), ih2(0), omega, cf, tp<S>(L.r),
-                                                           tp<S>(L.z), nullptr, tp<S>(L.zt), c->scal,
-                                                           c->partials + c->max_blocks);
+            k_fz_jac<CoefRho<S>, S, 2><<<mgrid(), b, 0, c->stream>>>(dims(0), kz(), ih2(0), omega, cf, tp<S>(L.r),
+                                                           tp<S>(L.z), tp<S>(L.zt), tp<S>(c->qv), c->scal,
+                                                           c->partials + c->max_blocks, c->max_blocks);
             prof_end(c);
             return;
         }
@@ -1351,9 +1422,9 @@ struct Solver {
                 prof_end(c);
             }
             prof_begin(c, PC_F_SWEEPDOT, fb(0, 3 + cfields(0)));
-            k_jac<CoefRho<S>, S, DIM, 0, 1><<<grid(0), dim3(BX, BY), 0, c->stream>>>(
-                dims(0), dims(0), ih2(0), omega, cf, tp<S>(L.r), tp<S>(L.z), nullptr, tp<S>(L.zt),
-                c->scal, c->partials + c->max_blocks);
+            k_jac<CoefRho<S>, S, DIM, 1><<<grid(0), dim3(BX, BY), 0, c->stream>>>(
+                dims(0), ih2(0), omega, cf, tp<S>(L.r), tp<S>(L.z), tp<S>(L.zt), tp<S>(c->qv),
+                c->scal, c->partials + c->max_blocks, c->max_blocks);
             prof_end(c);
             return;
         }
@@ -1422,7 +1493,7 @@ struct Solver {
                 else apply_update<3, X>(phi, first ? 1 : 0, x);
                 first = false;
                 vcycle(phi, true);
-                (void)finalize2(c, (int)nb0(), (int)nb0(), FIN_BETA, 0.0);
+                (void)finalize3(c, (int)nb0(), (int)nb0(), (int)nb0(), FIN_BETA, 0.0);
             }
             window = 2;
             hipError_t e = hipGetLastError();

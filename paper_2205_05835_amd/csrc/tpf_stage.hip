@@ -8,38 +8,34 @@ namespace tpf {
 // ------------------------------------------------------------------ kernels
 // One thread per cell; the bodies are the op_* functions of tpf_stage_ops.hpp.
 template <typename T, int DIM>
-__global__ __launch_bounds__(BLOCK) void k_cell(Dims d, Phys P, const T* __restrict__ phi,
+__global__ __launch_bounds__(BLOCK) void k_cell(Dims d, int kz, Phys P, const T* __restrict__ phi,
                                                 T* __restrict__ n0, T* __restrict__ n1,
                                                 T* __restrict__ n2, T* __restrict__ mu) {
-    Cell C;
-    if (!cell_of_thread(d, C)) return;
-    op_cell<T, DIM>(P, C, phi, n0, n1, n2, mu);
+    for_cells_zchunk(d, kz, [&](const Cell& C) { op_cell<T, DIM>(P, C, phi, n0, n1, n2, mu); });
 }
 
 template <typename T, int DIM>
-__global__ __launch_bounds__(BLOCK) void k_kappa(Dims d, Phys P, const T* __restrict__ n0,
+__global__ __launch_bounds__(BLOCK) void k_kappa(Dims d, int kz, Phys P, const T* __restrict__ n0,
                                                  const T* __restrict__ n1,
                                                  const T* __restrict__ n2, T* __restrict__ kappa) {
-    Cell C;
-    if (!cell_of_thread(d, C)) return;
-    op_kappa<T, DIM>(P, C, n0, n1, n2, kappa);
+    for_cells_zchunk(d, kz, [&](const Cell& C) { op_kappa<T, DIM>(P, C, n0, n1, n2, kappa); });
 }
 
 template <typename T, int DIM>
-__global__ __launch_bounds__(BLOCK) void k_face(Dims d, Phys P, const T* __restrict__ phi,
+__global__ __launch_bounds__(BLOCK) void k_face(Dims d, int kz, Phys P, const T* __restrict__ phi,
                                                 const T* __restrict__ n0, const T* __restrict__ n1,
                                                 const T* __restrict__ n2, const T* __restrict__ u0,
                                                 const T* __restrict__ u1, const T* __restrict__ u2,
                                                 T* __restrict__ r0, T* __restrict__ r1,
                                                 T* __restrict__ r2, T* __restrict__ m0,
                                                 T* __restrict__ m1, T* __restrict__ m2) {
-    Cell C;
-    if (!cell_of_thread(d, C)) return;
-    op_face<T, DIM>(P, C, phi, n0, n1, n2, u0, u1, u2, r0, r1, r2, m0, m1, m2);
+    for_cells_zchunk(d, kz, [&](const Cell& C) {
+        op_face<T, DIM>(P, C, phi, n0, n1, n2, u0, u1, u2, r0, r1, r2, m0, m1, m2);
+    });
 }
 
 template <typename T, int DIM>
-__global__ __launch_bounds__(BLOCK) void k_phase(Dims d, Phys P, RKArgs rk,
+__global__ __launch_bounds__(BLOCK) void k_phase(Dims d, int kz, Phys P, RKArgs rk,
                                                  const T* __restrict__ phi,
                                                  const T* __restrict__ u0, const T* __restrict__ u1,
                                                  const T* __restrict__ u2, const T* __restrict__ r0,
@@ -47,21 +43,21 @@ __global__ __launch_bounds__(BLOCK) void k_phase(Dims d, Phys P, RKArgs rk,
                                                  const T* __restrict__ kappa,
                                                  const T* __restrict__ yn, T* __restrict__ acc,
                                                  T* __restrict__ ynext, int* __restrict__ flags) {
-    Cell C;
-    if (!cell_of_thread(d, C)) return;
-    op_phase<T, DIM>(P, rk, C, phi, u0, u1, u2, r0, r1, r2, kappa, yn, acc, ynext, flags);
+    for_cells_zchunk(d, kz, [&](const Cell& C) {
+        op_phase<T, DIM>(P, rk, C, phi, u0, u1, u2, r0, r1, r2, kappa, yn, acc, ynext, flags);
+    });
 }
 
 template <typename T, int DIM>
 __global__ __launch_bounds__(BLOCK) void k_momentum(
-    Dims d, Phys P, const T* __restrict__ phi, const T* __restrict__ u0,
+    Dims d, int kz, Phys P, const T* __restrict__ phi, const T* __restrict__ u0,
     const T* __restrict__ u1, const T* __restrict__ u2, const T* __restrict__ m0,
     const T* __restrict__ m1, const T* __restrict__ m2, const T* __restrict__ mu,
     const T* __restrict__ kappa, T* __restrict__ f0, T* __restrict__ f1, T* __restrict__ f2,
     T* __restrict__ F0, T* __restrict__ F1, T* __restrict__ F2) {
-    Cell C;
-    if (!cell_of_thread(d, C)) return;
-    op_momentum<T, DIM>(P, C, phi, u0, u1, u2, m0, m1, m2, mu, kappa, f0, f1, f2, F0, F1, F2);
+    for_cells_zchunk(d, kz, [&](const Cell& C) {
+        op_momentum<T, DIM>(P, C, phi, u0, u1, u2, m0, m1, m2, mu, kappa, f0, f1, f2, F0, F1, F2);
+    });
 }
 
 // b = D f* in FP64, plus the block sums of b (for the mean)
@@ -77,7 +73,7 @@ __global__ __launch_bounds__(BLOCK) void k_div(Dims d, Phys P, const T* __restri
 }
 
 template <typename T, int DIM>
-__global__ __launch_bounds__(BLOCK) void k_project(Dims d, Phys P, RKArgs rk,
+__global__ __launch_bounds__(BLOCK) void k_project(Dims d, int kz, Phys P, RKArgs rk,
                                                    const T* __restrict__ phi,
                                                    const double* __restrict__ p,
                                                    const T* __restrict__ f0, const T* __restrict__ f1,
@@ -85,9 +81,9 @@ __global__ __launch_bounds__(BLOCK) void k_project(Dims d, Phys P, RKArgs rk,
                                                    const T* yn1, const T* yn2, T* acc0, T* acc1,
                                                    T* acc2, T* nx0, T* nx1, T* nx2,
                                                    int* __restrict__ flags) {
-    Cell C;
-    if (!cell_of_thread(d, C)) return;
-    op_project<T, DIM>(P, rk, C, phi, p, f0, f1, f2, yn0, yn1, yn2, acc0, acc1, acc2, nx0, nx1, nx2, flags);
+    for_cells_zchunk(d, kz, [&](const Cell& C) {
+        op_project<T, DIM>(P, rk, C, phi, p, f0, f1, f2, yn0, yn1, yn2, acc0, acc1, acc2, nx0, nx1, nx2, flags);
+    });
 }
 
 template <typename T, int DIM>
@@ -162,16 +158,17 @@ template <typename T, int DIM>
 static hipError_t stage_fields_impl(tpf_ctx* c, const void* phi_s) {
     const Phys P = phys_of(c);
     const Dims d = dims_of(c->n);
-    const dim3 g = grid_of(c->n), b(BX, BY);
+    const int kz = c->stage_kz;
+    const dim3 g = zchunk_grid(c->n, kz), b(BX, BY);
     const bool need_mu = c->P.force == FORCE_EB;
     const bool need_kappa = c->P.model != MODEL_CDI || c->P.force != FORCE_EB;
     prof_begin(c, PC_CELL, (double)c->N * c->tsz * (1 + DIM + (need_mu ? 1 : 0)));
-    k_cell<T, DIM><<<g, b, 0, c->stream>>>(d, P, ctp<T>(phi_s), tp<T>(c->nrm[0]), tp<T>(c->nrm[1]),
+    k_cell<T, DIM><<<g, b, 0, c->stream>>>(d, kz, P, ctp<T>(phi_s), tp<T>(c->nrm[0]), tp<T>(c->nrm[1]),
                                            tp<T>(c->nrm[2]), need_mu ? tp<T>(c->mu) : nullptr);
     prof_end(c);
     if (need_kappa) {
         prof_begin(c, PC_KAPPA, (double)c->N * c->tsz * (DIM + 1));
-        k_kappa<T, DIM><<<g, b, 0, c->stream>>>(d, P, ctp<T>(c->nrm[0]), ctp<T>(c->nrm[1]),
+        k_kappa<T, DIM><<<g, b, 0, c->stream>>>(d, kz, P, ctp<T>(c->nrm[0]), ctp<T>(c->nrm[1]),
                                                 ctp<T>(c->nrm[2]), tp<T>(c->kappa));
         prof_end(c);
     }
@@ -182,11 +179,12 @@ template <typename T, int DIM>
 static hipError_t face_impl(tpf_ctx* c, const void* phi_s, const void* const u_s[3]) {
     const Phys P = phys_of(c);
     const Dims d = dims_of(c->n);
-    const dim3 g = grid_of(c->n), b(BX, BY);
+    const int kz = c->stage_kz;
+    const dim3 g = zchunk_grid(c->n, kz), b(BX, BY);
     const int cdi = c->P.model == MODEL_CDI;
     prof_begin(c, PC_FACE, (double)c->N * c->tsz * (1 + DIM * (cdi ? 4 : 2)));
     k_face<T, DIM><<<g, b, 0, c->stream>>>(
-        d, P, ctp<T>(phi_s), ctp<T>(c->nrm[0]), ctp<T>(c->nrm[1]), ctp<T>(c->nrm[2]),
+        d, kz, P, ctp<T>(phi_s), ctp<T>(c->nrm[0]), ctp<T>(c->nrm[1]), ctp<T>(c->nrm[2]),
         ctp<T>(u_s[0]), ctp<T>(u_s[1]), ctp<T>(u_s[2]), tp<T>(c->rflux[0]), tp<T>(c->rflux[1]),
         tp<T>(c->rflux[2]), tp<T>(c->mflux[0]), tp<T>(c->mflux[1]), tp<T>(c->mflux[2]));
     prof_end(c);
@@ -209,13 +207,14 @@ template <typename T, int DIM>
 static hipError_t phase_impl(tpf_ctx* c, const void* phi_s, const void* const u_s[3],
                              const RKArgs& rk, void* out) {
     const Phys P = phys_of(c);
-    const dim3 g = grid_of(c->n), b(BX, BY);
+    const int kz = c->stage_kz;
+    const dim3 g = zchunk_grid(c->n, kz), b(BX, BY);
     const int cdi = c->P.model == MODEL_CDI;
     T* yn = tp<T>(c->phi[c->s_yn]);
     T* acc = tp<T>(c->phi[c->s_acc]);
     prof_begin(c, PC_PHASE, (double)c->N * c->tsz * (1 + DIM + (cdi ? DIM : 1) + (rk.eval_only ? 1 : 3 + (rk.stage < 3))));
     k_phase<T, DIM><<<g, b, 0, c->stream>>>(
-        dims_of(c->n), P, rk, ctp<T>(phi_s), ctp<T>(u_s[0]), ctp<T>(u_s[1]), ctp<T>(u_s[2]),
+        dims_of(c->n), kz, P, rk, ctp<T>(phi_s), ctp<T>(u_s[0]), ctp<T>(u_s[1]), ctp<T>(u_s[2]),
         ctp<T>(c->rflux[0]), ctp<T>(c->rflux[1]), ctp<T>(c->rflux[2]), ctp<T>(c->kappa), yn, acc,
         tp<T>(out), c->flags);
     prof_end(c);
@@ -234,10 +233,11 @@ hipError_t launch_phase_update(tpf_ctx* c, const void* phi_s, const void* const 
 template <typename T, int DIM>
 static hipError_t mom_impl(tpf_ctx* c, const void* phi_s, const void* const u_s[3], int want_force) {
     const Phys P = phys_of(c);
-    const dim3 g = grid_of(c->n), b(BX, BY);
+    const int kz = c->stage_kz;
+    const dim3 g = zchunk_grid(c->n, kz), b(BX, BY);
     prof_begin(c, PC_MOM, (double)c->N * c->tsz * (1 + 3 * DIM + 1));
     k_momentum<T, DIM><<<g, b, 0, c->stream>>>(
-        dims_of(c->n), P, ctp<T>(phi_s), ctp<T>(u_s[0]), ctp<T>(u_s[1]), ctp<T>(u_s[2]),
+        dims_of(c->n), kz, P, ctp<T>(phi_s), ctp<T>(u_s[0]), ctp<T>(u_s[1]), ctp<T>(u_s[2]),
         ctp<T>(c->mflux[0]), ctp<T>(c->mflux[1]), ctp<T>(c->mflux[2]), ctp<T>(c->mu),
         ctp<T>(c->kappa), tp<T>(c->fs[0]), tp<T>(c->fs[1]), tp<T>(c->fs[2]),
         want_force ? tp<T>(c->force[0]) : nullptr, tp<T>(c->force[1]), tp<T>(c->force[2]));
@@ -275,11 +275,12 @@ hipError_t launch_divergence(tpf_ctx* c) {
 template <typename T, int DIM>
 static hipError_t proj_impl(tpf_ctx* c, const void* phi_s, const RKArgs& rk, void* const out[3]) {
     const Phys P = phys_of(c);
-    const dim3 g = grid_of(c->n), b(BX, BY);
+    const int kz = c->stage_kz;
+    const dim3 g = zchunk_grid(c->n, kz), b(BX, BY);
     const int yn = c->s_yn, ac = c->s_acc;
     prof_begin(c, PC_PROJ, (double)c->N * (c->tsz * (1 + DIM + (rk.eval_only ? DIM : DIM * (3 + (rk.stage < 3)))) + 8));
     k_project<T, DIM><<<g, b, 0, c->stream>>>(
-        dims_of(c->n), P, rk, ctp<T>(phi_s), c->p, ctp<T>(c->fs[0]), ctp<T>(c->fs[1]),
+        dims_of(c->n), kz, P, rk, ctp<T>(phi_s), c->p, ctp<T>(c->fs[0]), ctp<T>(c->fs[1]),
         ctp<T>(c->fs[2]), ctp<T>(c->u[0][yn]), ctp<T>(c->u[1][yn]), ctp<T>(c->u[2][yn]),
         tp<T>(c->u[0][ac]), tp<T>(c->u[1][ac]), tp<T>(c->u[2][ac]), tp<T>(out[0]), tp<T>(out[1]),
         tp<T>(out[2]), c->flags);

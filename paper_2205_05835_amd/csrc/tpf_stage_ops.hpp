@@ -25,22 +25,22 @@ __device__ __forceinline__ void op_cell(const Phys& P, const Cell& C, const T* _
                                                 T* __restrict__ n0, T* __restrict__ n1,
                                                 T* __restrict__ n2, T* __restrict__ mu) {
     const unsigned c = C.id;
-    const T f = phi[c];
+    const T f = ld(phi, c);
     const T ih = T(P.inv_h), ih2 = T(0.5 * P.inv_h);
     T g[3] = {T(0), T(0), T(0)};
     T gg = T(0), lap = T(0);
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-        const T fp = phi[C.off(a, 1)], fm = phi[C.off(a, -1)];
+        const T fp = ld(phi, C.off(a, 1)), fm = ld(phi, C.off(a, -1));
         g[a] = (fp - fm) * ih2;
         gg += g[a] * g[a];
         lap += ((fp - f) * ih - (f - fm) * ih) * ih;
     }
     const T inv = T(1) / sqrt(gg + T(P.delta2));
-    n0[c] = g[0] * inv;
-    n1[c] = g[1] * inv;
-    if (DIM == 3) n2[c] = g[2] * inv;
-    if (mu) mu[c] = T(P.sigma_hat / P.eps) * dpsi(f) - T(P.sigma_hat * P.eps) * lap;
+    st(n0, c, g[0] * inv);
+    st(n1, c, g[1] * inv);
+    if (DIM == 3) st(n2, c, g[2] * inv);
+    if (mu) st(mu, c, T(P.sigma_hat / P.eps) * dpsi(f) - T(P.sigma_hat * P.eps) * lap);
 }
 
 // kappa = - sum_a C_a n_a   (Eq. 3)
@@ -52,8 +52,8 @@ __device__ __forceinline__ void op_kappa(const Phys& P, const Cell& C, const T* 
     const T ih2 = T(0.5 * P.inv_h);
     T s = T(0);
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) s += (n[a][C.off(a, 1)] - n[a][C.off(a, -1)]) * ih2;
-    kappa[C.id] = -s;
+    for (int a = 0; a < DIM; ++a) s += (ld(n[a], C.off(a, 1)) - ld(n[a], C.off(a, -1))) * ih2;
+    st(kappa, C.id, -s);
 }
 
 // ------------------------------------------------------------------ face fluxes
@@ -72,22 +72,22 @@ __device__ __forceinline__ void op_face(const Phys& P, const Cell& C, const T* _
     T* r[3] = {r0, r1, r2};
     T* m[3] = {m0, m1, m2};
     const unsigned c = C.id;
-    const T f = phi[c];
+    const T f = ld(phi, c);
     const bool cdi = P.model == MODEL_CDI;
     const T drho = T(P.rho1 - P.rho2);
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
         const unsigned cm = C.off(a, -1);
-        const T fm = phi[cm];
+        const T fm = ld(phi, cm);
         const T rho_f = T(0.5) * (rho_of(P, fm) + rho_of(P, f));
         T ra = T(0);
         if (cdi) {
-            const T wm = fm * (T(1) - fm) * n[a][cm];
-            const T wc = f * (T(1) - f) * n[a][c];
+            const T wm = fm * (T(1) - fm) * ld(n[a], cm);
+            const T wc = f * (T(1) - f) * ld(n[a], c);
             ra = T(P.gamma) * (T(P.eps) * ((f - fm) * T(P.inv_h)) - T(0.5) * (wm + wc));
-            r[a][c] = ra;
+            st(r[a], c, ra);
         }
-        m[a][c] = rho_f * u[a][c] - drho * ra;
+        st(m[a], c, rho_f * ld(u[a], c) - drho * ra);
     }
 }
 
@@ -105,18 +105,18 @@ __device__ __forceinline__ void op_phase(const Phys& P, const RKArgs& rk, const 
     const T* u[3] = {u0, u1, u2};
     const T* r[3] = {r0, r1, r2};
     const unsigned c = C.id;
-    const T f = phi[c];
+    const T f = ld(phi, c);
     const T ih = T(P.inv_h);
     T adv = T(0), g = T(0), lap = T(0), gg = T(0);
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
         const unsigned cp = C.off(a, 1), cm = C.off(a, -1);
-        const T fp = phi[cp], fm = phi[cm];
-        const T jhi = u[a][cp] * (T(0.5) * (f + fp));
-        const T jlo = u[a][c] * (T(0.5) * (fm + f));
+        const T fp = ld(phi, cp), fm = ld(phi, cm);
+        const T jhi = ld(u[a], cp) * (T(0.5) * (f + fp));
+        const T jlo = ld(u[a], c) * (T(0.5) * (fm + f));
         adv += (jhi - jlo) * ih;
         if (P.model == MODEL_CDI) {
-            g += (r[a][cp] - r[a][c]) * ih;
+            g += (ld(r[a], cp) - ld(r[a], c)) * ih;
         } else {
             lap += ((fp - f) * ih - (f - fm) * ih) * ih;
             const T ga = (fp - fm) * T(0.5 * P.inv_h);
@@ -125,19 +125,19 @@ __device__ __forceinline__ void op_phase(const Phys& P, const RKArgs& rk, const 
     }
     if (P.model != MODEL_CDI) {
         const T base = T(P.eps) * lap - dpsi(f) / T(P.eps);
-        const T curv = (P.model == MODEL_SB) ? T(P.eps) * sqrt(gg) * kappa[c]
-                                             : f * (T(1) - f) * kappa[c];
+        const T curv = (P.model == MODEL_SB) ? T(P.eps) * sqrt(gg) * ld(kappa, c)
+                                             : f * (T(1) - f) * ld(kappa, c);
         g = T(P.gamma) * (base + curv);
     }
     const T k = -adv + g;
     if (rk.eval_only) {
-        ynext[c] = k;
+        st(ynext, c, k);
         return;
     }
-    const T y0 = yn[c];
-    const T a_new = (rk.stage == 0 ? y0 : acc[c]) + T(rk.wacc) * k;
-    acc[c] = a_new;
-    if (rk.stage < 3) ynext[c] = y0 + T(rk.wnext) * k;
+    const T y0 = ld(yn, c);
+    const T a_new = (rk.stage == 0 ? y0 : ld(acc, c)) + T(rk.wacc) * k;
+    st(acc, c, a_new);
+    if (rk.stage < 3) st(ynext, c, y0 + T(rk.wnext) * k);
     else if (!isfinite(a_new)) flags[0] = 1;
 }
 
@@ -162,67 +162,58 @@ __device__ __forceinline__ void op_momentum(const Phys& P, const Cell& C, const 
     T* Fo[3] = {F0, F1, F2};
     const unsigned c = C.id;
     const T ih = T(P.inv_h);
-    const T f = phi[c];
-    const T eta_c = visc_of(P, f);
+    const T v2 = T(P.visc2), dv = T(P.visc1 - P.visc2);
+    const T f = ld(phi, c);
+    const T clc = clamp01(P, f);
+    auto cl = [&](unsigned q) { return clamp01(P, ld(phi, q)); };
+    // h D m at c, shared by the faces of c
+    T dmc = T(0);
+#pragma unroll
+    for (int b = 0; b < DIM; ++b) dmc += ld(m[b], C.off(b, 1)) - ld(m[b], c);
+    // The sums below are the terms of N_a, V_a and F_a with the factors 1/2,
+    // 1/4 and 1/h of the averages and differences taken out: N_a = Nh / h,
+    // V_a = Vh2 / h^2, F_a = Fh / h.
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
         const unsigned cp = C.off(a, 1), cm = C.off(a, -1);
-        const T fm = phi[cm];
-        const T eta_m = visc_of(P, fm);
-        const T uac = u[a][c];
-        // ---- advection
-        T adv = T(0), dm_c = T(0), dm_m = T(0);
+        const T fm = ld(phi, cm);
+        const T clm = clamp01(P, fm);
+        const T uac = ld(u[a], c), uap = ld(u[a], cp), uam = ld(u[a], cm);
+        // ---- advection: fluxes are products of two-point sums (x 1/4)
+        T adv4 = (ld(m[a], c) + ld(m[a], cp)) * (uac + uap) - (ld(m[a], cm) + ld(m[a], c)) * (uam + uac);
+        T dmm = ld(m[a], c) - ld(m[a], cm);      // h D m at c - e_a
+        // ---- viscous stress (x 1/h^2); edge viscosity v2 + dv/4 (sum of four clamped phi)
+        T vh2 = T(2) * ((v2 + dv * clc) * (uap - uac) - (v2 + dv * clm) * (uac - uam));
 #pragma unroll
         for (int b = 0; b < DIM; ++b) {
-            T hi, lo;
-            if (b == a) {
-                hi = (T(0.5) * (m[a][c] + m[a][cp])) * (T(0.5) * (uac + u[a][cp]));
-                lo = (T(0.5) * (m[a][cm] + m[a][c])) * (T(0.5) * (u[a][cm] + uac));
-            } else {
-                const unsigned cpb = C.off(b, 1), cmb = C.off(b, -1), cmapb = C.off2(a, -1, b, 1);
-                hi = (T(0.5) * (m[b][cpb] + m[b][cmapb])) * (T(0.5) * (uac + u[a][cpb]));
-                lo = (T(0.5) * (m[b][c] + m[b][cm])) * (T(0.5) * (u[a][cmb] + uac));
-            }
-            adv += (hi - lo) * ih;
-            dm_c += (m[b][C.off(b, 1)] - m[b][c]) * ih;
-            // (c - e_a) + e_b: back to c itself when b == a
-            dm_m += (m[b][b == a ? c : C.off2(a, -1, b, 1)] - m[b][cm]) * ih;
+            if (b == a) continue;
+            const unsigned cpb = C.off(b, 1), cmb = C.off(b, -1);
+            const unsigned cmapb = C.off2(a, -1, b, 1), cmamb = C.off2(a, -1, b, -1);
+            const T uapb = ld(u[a], cpb), uamb = ld(u[a], cmb);
+            const T mbc = ld(m[b], c), mbm = ld(m[b], cm), mbmp = ld(m[b], cmapb);
+            adv4 += (ld(m[b], cpb) + mbmp) * (uac + uapb) - (mbc + mbm) * (uamb + uac);
+            dmm += mbmp - mbm;
+            const T cc = clc + clm;
+            const T e_hi = v2 + T(0.25) * dv * (cc + cl(cpb) + cl(cmapb));
+            const T e_lo = v2 + T(0.25) * dv * (cc + cl(cmb) + cl(cmamb));
+            vh2 += e_hi * ((uapb - uac) + (ld(u[b], cpb) - ld(u[b], cmapb))) -
+                   e_lo * ((uac - uamb) + (ld(u[b], c) - ld(u[b], cm)));
         }
-        const T N = adv - uac * (T(0.5) * (dm_m + dm_c));
-        // ---- viscous stress
-        T V = T(0);
-#pragma unroll
-        for (int b = 0; b < DIM; ++b) {
-            T hi, lo;
-            if (b == a) {
-                hi = T(2) * eta_c * ((u[a][cp] - uac) * ih);
-                lo = T(2) * eta_m * ((uac - u[a][cm]) * ih);
-            } else {
-                const unsigned cpb = C.off(b, 1), cmb = C.off(b, -1);
-                const unsigned cmapb = C.off2(a, -1, b, 1), cmamb = C.off2(a, -1, b, -1);
-                const T e_pb = visc_of(P, phi[cpb]), e_mapb = visc_of(P, phi[cmapb]);
-                const T e_mb = visc_of(P, phi[cmb]), e_mamb = visc_of(P, phi[cmamb]);
-                const T eta_hi = T(0.25) * (eta_c + eta_m + e_pb + e_mapb);
-                const T eta_lo = T(0.25) * (e_mb + e_mamb + eta_c + eta_m);
-                hi = eta_hi * ((u[a][cpb] - uac) * ih + (u[b][cpb] - u[b][cmapb]) * ih);
-                lo = eta_lo * ((uac - u[a][cmb]) * ih + (u[b][c] - u[b][cm]) * ih);
-            }
-            V += (hi - lo) * ih;
-        }
-        // ---- surface tension
-        const T gphi = (f - fm) * ih;
-        T F;
+        const T nh = T(0.25) * adv4 - T(0.5) * uac * (dmm + dmc);
+        // ---- surface tension (x 1/h)
+        const T gh = f - fm;
+        T fh;
         if (P.force == FORCE_EB) {
-            F = (T(0.5) * (mu[cm] + mu[c])) * gphi;
+            fh = T(0.5) * (ld(mu, cm) + ld(mu, c)) * gh;
         } else if (P.force == FORCE_CSF) {
-            F = T(P.sigma) * (T(0.5) * (kappa[cm] + kappa[c])) * gphi;
+            fh = T(0.5 * P.sigma) * (ld(kappa, cm) + ld(kappa, c)) * gh;
         } else {
-            F = T(P.sigma_hat) * (T(0.5) * (kappa[cm] + kappa[c])) *
-                (T(0.5) * (fm * (T(1) - fm) + f * (T(1) - f))) * gphi;
+            fh = T(0.25 * P.sigma_hat) * (ld(kappa, cm) + ld(kappa, c)) *
+                 (fm * (T(1) - fm) + f * (T(1) - f)) * gh;
         }
-        if (Fo[0]) Fo[a][c] = F;
-        const T rho_f = T(0.5) * (rho_of(P, fm) + rho_of(P, f));
-        fs[a][c] = (-N + V + F) * (T(1) / rho_f);
+        if (Fo[0]) st(Fo[a], c, fh * ih);
+        const T rho_f = T(P.rho2) + T(0.5 * (P.rho1 - P.rho2)) * (clm + clc);
+        st(fs[a], c, ((fh - nh) * ih + vh2 * (ih * ih)) / rho_f);
     }
 }
 
@@ -235,7 +226,7 @@ __device__ __forceinline__ double op_div(const Phys& P, const Cell& C, const T* 
     const unsigned c = C.id;
     double s = 0.0;
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) s += ((double)fs[a][C.off(a, 1)] - (double)fs[a][c]) * P.inv_h;
+    for (int a = 0; a < DIM; ++a) s += ((double)ld(fs[a], C.off(a, 1)) - (double)ld(fs[a], c)) * P.inv_h;
     b[c] = s;
     return s;
 }
@@ -256,22 +247,22 @@ __device__ __forceinline__ void op_project(const Phys& P, const RKArgs& rk, cons
     T* acc[3] = {acc0, acc1, acc2};
     T* nx[3] = {nx0, nx1, nx2};
     const unsigned c = C.id;
-    const T f = phi[c];
-    const double pc = p[c];
+    const T f = ld(phi, c);
+    const double pc = ld(p, c);
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
         const unsigned cm = C.off(a, -1);
-        const double rho_f = 0.5 * ((double)rho_of(P, phi[cm]) + (double)rho_of(P, f));
-        const double gp = (pc - p[cm]) * P.inv_h;
-        const T k = T((double)fs[a][c] - gp / rho_f);
+        const double rho_f = 0.5 * ((double)rho_of(P, ld(phi, cm)) + (double)rho_of(P, f));
+        const double gp = (pc - ld(p, cm)) * P.inv_h;
+        const T k = T((double)ld(fs[a], c) - gp / rho_f);
         if (rk.eval_only) {
-            nx[a][c] = k;
+            st(nx[a], c, k);
             continue;
         }
-        const T y0 = yn[a][c];
-        const T a_new = (rk.stage == 0 ? y0 : acc[a][c]) + T(rk.wacc) * k;
-        acc[a][c] = a_new;
-        if (rk.stage < 3) nx[a][c] = y0 + T(rk.wnext) * k;
+        const T y0 = ld(yn[a], c);
+        const T a_new = (rk.stage == 0 ? y0 : ld(acc[a], c)) + T(rk.wacc) * k;
+        st(acc[a], c, a_new);
+        if (rk.stage < 3) st(nx[a], c, y0 + T(rk.wnext) * k);
         else if (!isfinite(a_new)) flags[0] = 1;
     }
 }
