@@ -474,7 +474,7 @@ struct TailDesc {
 };
 
 template <typename S, int DIM>
-__global__ __launch_bounds__(1024) void k_tail(TailDesc D, S omega, S omega_c, int sweeps,
+__global__ __launch_bounds__(1024) void k_tail(TailDesc D, S w1, S w2, S omega_c, int sweeps,
                                                const S* __restrict__ rin, S* __restrict__ zout,
                                                const SolverScalars* __restrict__ sc) {
     if (sc->done) return;
@@ -526,10 +526,10 @@ __global__ __launch_bounds__(1024) void k_tail(TailDesc D, S omega, S omega_c, i
             S bl[3], bh[3], dg = S(0);
             cf.template faces<DIM>(C, bl, bh);
             for (int a = 0; a < DIM; ++a) dg += bl[a] + bh[a];
-            z[q] = omega * r[q] / (dg * ih2);
+            z[q] = w1 * r[q] / (dg * ih2);
         }
         __syncthreads();
-        sweep(l, omega, [&](const Cell& C, int a, int s) { return z[s == 0 ? C.id : C.nb(a, s)]; }, zt);
+        sweep(l, w2, [&](const Cell& C, int a, int s) { return z[s == 0 ? C.id : C.nb(a, s)]; }, zt);
         // restriction of r - A zt into the next level's r
         const Dims dc = dims(l + 1);
         const int Nc = ncell(l + 1);
@@ -586,8 +586,8 @@ __global__ __launch_bounds__(1024) void k_tail(TailDesc D, S omega, S omega_c, i
             zt[q] += prolong_at<S, DIM>(dc, zc, C.i, C.j, C.k);
         }
         __syncthreads();
-        sweep(l, omega, [&](const Cell& C, int a, int s) { return zt[s == 0 ? C.id : C.nb(a, s)]; }, z);
-        sweep(l, omega, [&](const Cell& C, int a, int s) { return z[s == 0 ? C.id : C.nb(a, s)]; }, zt);
+        sweep(l, w2, [&](const Cell& C, int a, int s) { return zt[s == 0 ? C.id : C.nb(a, s)]; }, z);
+        sweep(l, w1, [&](const Cell& C, int a, int s) { return z[s == 0 ? C.id : C.nb(a, s)]; }, zt);
     }
     {
         const int N0 = ncell(0);
@@ -1158,7 +1158,7 @@ template <typename T, typename S>
 struct Solver {
     tpf_ctx* c;
     int dim;
-    S omega;
+    S w1, w2;       // damped-Jacobi weights of the two sweeps before (w1, w2) and after (w2, w1)
 
     CoefPhi<T, S> coef_phi(const void* phi) const {
         const Phys P = phys_of(c);
@@ -1251,12 +1251,12 @@ struct Solver {
                 Level& Lc = c->lv[l + 1];
                 if (!first_done) {
                     prof_begin(c, PC_F_FIRST0, fb(l, 2 + cfl));
-                    k_fz_first<Coef, S, S, 0><<<mgrid(), b, 0, c->stream>>>(dims(0), kz(), ih2(0), omega, cf, nullptr,
+                    k_fz_first<Coef, S, S, 0><<<mgrid(), b, 0, c->stream>>>(dims(0), kz(), ih2(0), w1, cf, nullptr,
                                                                        r, nullptr, nullptr, z, c->scal, nullptr);
                     prof_end(c);
                 }
                 prof_begin(c, PC_F_SWEEP, fb(l, 3 + cfl));
-                k_fz_jac<Coef, S, 0><<<mgrid(), b, 0, c->stream>>>(dims(0), kz(), ih2(0), omega, cf, r, z, zt,
+                k_fz_jac<Coef, S, 0><<<mgrid(), b, 0, c->stream>>>(dims(0), kz(), ih2(0), w2, cf, r, z, zt,
                                                                nullptr, c->scal, nullptr, 0);
                 prof_end(c);
                 prof_begin(c, PC_F_RESTRICT, fb(l, 2 + cfl) + (double)Lc.N * sizeof(S));
@@ -1268,11 +1268,11 @@ struct Solver {
         }
         if (!first_done) {
             prof_begin(c, fine ? PC_F_FIRST0 : PC_COARSE_LEVELS, fb(l, 2 + cfl));
-            k_jac_first<Coef, S, DIM><<<grid(l), b, 0, c->stream>>>(dims(l), ih2(l), omega, cf, r, z, c->scal);
+            k_jac_first<Coef, S, DIM><<<grid(l), b, 0, c->stream>>>(dims(l), ih2(l), w1, cf, r, z, c->scal);
             prof_end(c);
         }
         prof_begin(c, fine ? PC_F_SWEEP : PC_COARSE_LEVELS, fb(l, 3 + cfl));
-        k_jac<Coef, S, DIM, 0><<<grid(l), b, 0, c->stream>>>(dims(l), ih2(l), omega, cf, r, z, zt, nullptr,
+        k_jac<Coef, S, DIM, 0><<<grid(l), b, 0, c->stream>>>(dims(l), ih2(l), w2, cf, r, z, zt, nullptr,
                                                               c->scal, nullptr, 0);
         prof_end(c);
         Level& Lc = c->lv[l + 1];
@@ -1302,30 +1302,30 @@ struct Solver {
         if constexpr (std::is_same<Coef, CoefRho<S>>::value) {
             if (DIM == 3 && march0()) {
                 prof_begin(c, PC_F_SWEEP, fb(l, 3 + cfl));
-                k_fz_jac<Coef, S, 0><<<mgrid(), b, 0, c->stream>>>(dims(0), kz(), ih2(0), omega, cf, r, zt, z,
+                k_fz_jac<Coef, S, 0><<<mgrid(), b, 0, c->stream>>>(dims(0), kz(), ih2(0), w2, cf, r, zt, z,
                                                                nullptr, c->scal, nullptr, 0);
                 prof_end(c);
                 prof_begin(c, PC_F_SWEEPDOT, fb(l, 3 + (dot ? 1 : 0) + cfl));
                 if (dot)
-                    k_fz_jac<Coef, S, 2><<<mgrid(), b, 0, c->stream>>>(dims(0), kz(), ih2(0), omega, cf, r, z, zt,
+                    k_fz_jac<Coef, S, 2><<<mgrid(), b, 0, c->stream>>>(dims(0), kz(), ih2(0), w1, cf, r, z, zt,
                                                                    qv, c->scal, part, stride);
                 else
-                    k_fz_jac<Coef, S, 0><<<mgrid(), b, 0, c->stream>>>(dims(0), kz(), ih2(0), omega, cf, r, z, zt,
+                    k_fz_jac<Coef, S, 0><<<mgrid(), b, 0, c->stream>>>(dims(0), kz(), ih2(0), w1, cf, r, z, zt,
                                                                    nullptr, c->scal, nullptr, 0);
                 prof_end(c);
                 return;
             }
         }
         prof_begin(c, fine ? PC_F_SWEEP : PC_COARSE_LEVELS, fb(l, 3 + cfl));
-        k_jac<Coef, S, DIM, 0><<<grid(l), b, 0, c->stream>>>(dims(l), ih2(l), omega, cf, r, zt, z, nullptr,
+        k_jac<Coef, S, DIM, 0><<<grid(l), b, 0, c->stream>>>(dims(l), ih2(l), w2, cf, r, zt, z, nullptr,
                                                               c->scal, nullptr, 0);
         prof_end(c);
         prof_begin(c, fine ? PC_F_SWEEPDOT : PC_COARSE_LEVELS, fb(l, 3 + (dot ? 1 : 0) + cfl));
         if (dot)
-            k_jac<Coef, S, DIM, 1><<<grid(l), b, 0, c->stream>>>(dims(l), ih2(l), omega, cf, r, z, zt, qv,
+            k_jac<Coef, S, DIM, 1><<<grid(l), b, 0, c->stream>>>(dims(l), ih2(l), w1, cf, r, z, zt, qv,
                                                                   c->scal, part, stride);
         else
-            k_jac<Coef, S, DIM, 0><<<grid(l), b, 0, c->stream>>>(dims(l), ih2(l), omega, cf, r, z, zt, nullptr,
+            k_jac<Coef, S, DIM, 0><<<grid(l), b, 0, c->stream>>>(dims(l), ih2(l), w1, cf, r, z, zt, nullptr,
                                                                   c->scal, nullptr, 0);
         prof_end(c);
     }
@@ -1363,7 +1363,7 @@ struct Solver {
         const Level& Ll = c->lv[c->nlev - 1];
         const int mx = std::max(Ll.n[0], std::max(Ll.n[1], Ll.n[2]));
         prof_begin(c, PC_COARSE_LEVELS, (double)off * sizeof(S));
-        k_tail<S, DIM><<<1, 1024, (size_t)off * sizeof(S), c->stream>>>(D, omega, S(0.8), coarse_sweeps(mx),
+        k_tail<S, DIM><<<1, 1024, (size_t)off * sizeof(S), c->stream>>>(D, w1, w2, S(0.8), coarse_sweeps(mx),
                                                                         tp<S>(c->lv[l0].r),
                                                                         tp<S>(c->lv[l0].zt), c->scal);
         prof_end(c);
@@ -1401,13 +1401,13 @@ struct Solver {
             const dim3 b(BX, BY);
             if (!first_done) {
                 prof_begin(c, PC_F_FIRST0, fb(0, 2 + cfields(0)));
-                k_fz_first<CoefRho<S>, S, S, 0><<<mgrid(), b, 0, c->stream>>>(dims(0), kz(), ih2(0), omega, cf, nullptr,
+                k_fz_first<CoefRho<S>, S, S, 0><<<mgrid(), b, 0, c->stream>>>(dims(0), kz(), ih2(0), w1, cf, nullptr,
                                                                    tp<S>(L.r), nullptr, nullptr, tp<S>(L.z),
                                                                    c->scal, nullptr);
                 prof_end(c);
             }
             prof_begin(c, PC_F_SWEEPDOT, fb(0, 3 + cfields(0)));
-            k_fz_jac<CoefRho<S>, S, 2><<<mgrid(), b, 0, c->stream>>>(dims(0), kz(), ih2(0), omega, cf, tp<S>(L.r),
+            k_fz_jac<CoefRho<S>, S, 2><<<mgrid(), b, 0, c->stream>>>(dims(0), kz(), ih2(0), w2, cf, tp<S>(L.r),
                                                            tp<S>(L.z), tp<S>(L.zt), tp<S>(c->qv), c->scal,
                                                            c->partials + c->max_blocks, c->max_blocks);
             prof_end(c);
@@ -1418,12 +1418,12 @@ struct Solver {
             if (!first_done) {
                 prof_begin(c, PC_F_FIRST0, fb(0, 2 + cfields(0)));
                 k_jac_first<CoefRho<S>, S, DIM><<<grid(0), dim3(BX, BY), 0, c->stream>>>(
-                    dims(0), ih2(0), omega, cf, tp<S>(L.r), tp<S>(L.z), c->scal);
+                    dims(0), ih2(0), w1, cf, tp<S>(L.r), tp<S>(L.z), c->scal);
                 prof_end(c);
             }
             prof_begin(c, PC_F_SWEEPDOT, fb(0, 3 + cfields(0)));
             k_jac<CoefRho<S>, S, DIM, 1><<<grid(0), dim3(BX, BY), 0, c->stream>>>(
-                dims(0), ih2(0), omega, cf, tp<S>(L.r), tp<S>(L.z), tp<S>(L.zt), tp<S>(c->qv),
+                dims(0), ih2(0), w2, cf, tp<S>(L.r), tp<S>(L.z), tp<S>(L.zt), tp<S>(c->qv),
                 c->scal, c->partials + c->max_blocks, c->max_blocks);
             prof_end(c);
             return;
@@ -1451,7 +1451,7 @@ struct Solver {
             prof_end(c);
             (void)finalize2(c, (int)nb0(), 0, FIN_ALPHA, 0.0);
             prof_begin(c, PC_F_FIRST, fb(0, 5 + cfields(0)) + 2.0 * c->N * sizeof(X));
-            k_fz_first<CoefRho<S>, S, X, 1><<<mgrid(), b, 0, c->stream>>>(dims(0), kz(), ih2(0), omega, cf, x,
+            k_fz_first<CoefRho<S>, S, X, 1><<<mgrid(), b, 0, c->stream>>>(dims(0), kz(), ih2(0), w1, cf, x,
                                                                tp<S>(c->lv[0].r), pnew, tp<S>(c->qv),
                                                                tp<S>(c->lv[0].z), c->scal, c->partials);
             prof_end(c);
@@ -1465,7 +1465,7 @@ struct Solver {
         (void)finalize2(c, (int)nbl(0), 0, FIN_ALPHA, 0.0);
         prof_begin(c, PC_F_FIRST, fb(0, 5 + cfields(0)) + 2.0 * c->N * sizeof(X));
         k_jac_first_update<CoefRho<S>, S, X, DIM><<<grid(0), b, 0, c->stream>>>(
-            dims(0), ih2(0), omega, cf, x, tp<S>(c->lv[0].r), pnew, tp<S>(c->qv), tp<S>(c->lv[0].z),
+            dims(0), ih2(0), w1, cf, x, tp<S>(c->lv[0].r), pnew, tp<S>(c->qv), tp<S>(c->lv[0].z),
             c->scal, c->partials);
         prof_end(c);
         std::swap(c->pv, c->pv2);
@@ -1577,7 +1577,19 @@ static tpf_status read_scalars(tpf_ctx* c, SolverScalars* s) {
     return TPF_OK;
 }
 
-static double omega_of(int dim) { return dim == 2 ? 0.8 : 6.0 / 7.0; }
+// Damped-Jacobi weights of the two smoothing sweeps.  3D: the roots of the
+// degree-2 Chebyshev polynomial on [1/2, 2] (the spectrum of D^-1 A lies in
+// (0, 2]; the sweeps damp its upper three quarters): 1 / (5/4 -+ (3/4) cos(pi/4)).
+// 2D: 0.8 twice (the Chebyshev pair measured no better there).
+static void weights_of(int dim, double& w1, double& w2) {
+    if (dim == 2) {
+        w1 = w2 = 0.8;
+        return;
+    }
+    const double c = 0.75 * std::cos(M_PI / 4.0);
+    w1 = 1.0 / (1.25 + c);
+    w2 = 1.0 / (1.25 - c);
+}
 
 // Zero-mean gauge of the pressure (Z13 of the readings): applied where the
 // pressure leaves the library.  Inside a step only G p is used, which the
@@ -1596,7 +1608,9 @@ tpf_status poisson_solve(tpf_ctx* c, const void* phi, int* iters, double* relres
     SolverScalars s;
     hipError_t e;
     if (!c->mixed) {
-        Solver<double, double> sv{c, c->dim, omega_of(c->dim)};
+        double w1, w2;
+        weights_of(c->dim, w1, w2);
+        Solver<double, double> sv{c, c->dim, w1, w2};
         sv.build_betas(phi);
         sv.residual<double>(sv.coef_fine(), tp<double>(c->lv[0].r));
         (void)finalize2(c, (int)sv.nb0(), (int)sv.nb0(), FIN_INIT, rtol * rtol);
@@ -1618,7 +1632,9 @@ tpf_status poisson_solve(tpf_ctx* c, const void* phi, int* iters, double* relres
         return TPF_OK;
     }
     // ---- mixed: FP64 defect correction around the FP32 multigrid-PCG
-    Solver<float, float> sv{c, c->dim, float(omega_of(c->dim))};
+    double w1, w2;
+    weights_of(c->dim, w1, w2);
+    Solver<float, float> sv{c, c->dim, float(w1), float(w2)};
     Solver<float, double> s64{c, c->dim, 0.0};
     sv.build_betas(phi);
     const double rin = c->P.poisson_rtol_inner;
