@@ -46,7 +46,7 @@ Phys phys_of(const tpf_ctx* c) { return phys_of_params(c->P); }
 
 // ---------------------------------------------------------------- profiling
 static const char* kProfNames[NPROF] = {
-    "stage_cell", "stage_kappa", "stage_face", "stage_phase", "stage_momentum", "stage_div",
+    "stage_cell", "stage_kappa", "stage_face", "stage_phase", "stage_phase_momentum", "stage_div",
     "stage_project", "fine_apply", "fine_update_sweep1", "fine_sweep1", "fine_sweep2",
     "fine_restrict", "fine_prolong", "fine_sweep4_dot", "mg_coarse_levels",
     "residual", "reduce_finalize", "vector"};
@@ -395,8 +395,7 @@ tpf_status tpf_init_droplet(tpf_ctx* c, const double center[3], const double sem
 static tpf_status stage_eval(tpf_ctx* c, const void* phi_s, const void* const u_s[3], const RKArgs& rk,
                              void* phi_out, void* const u_out[3], int want_force) {
     hipError_t e = launch_stage_fields(c, phi_s, u_s);
-    if (e == hipSuccess) e = launch_phase_update(c, phi_s, u_s, rk, phi_out);
-    if (e == hipSuccess) e = launch_momentum(c, phi_s, u_s, want_force);
+    if (e == hipSuccess) e = launch_phase_momentum(c, phi_s, u_s, rk, phi_out, want_force);
     if (e == hipSuccess) e = launch_divergence(c);
     if (e != hipSuccess) return hip_fail(e, "stage kernels");
     int it = 0, outer = 0;

@@ -181,9 +181,10 @@ void prof_end(tpf_ctx* c);
 
 // stage kernels (tpf_stage.hip)
 hipError_t launch_stage_fields(tpf_ctx* c, const void* phi_s, const void* const u_s[3]);
-hipError_t launch_phase_update(tpf_ctx* c, const void* phi_s, const void* const u_s[3],
-                               const RKArgs& rk, void* out);
 hipError_t launch_momentum(tpf_ctx* c, const void* phi_s, const void* const u_s[3], int want_force);
+// phase update and momentum right-hand side fused (one pass over phi and u)
+hipError_t launch_phase_momentum(tpf_ctx* c, const void* phi_s, const void* const u_s[3], const RKArgs& rk,
+                                 void* out, int want_force);
 hipError_t launch_divergence(tpf_ctx* c);
 hipError_t launch_project_update(tpf_ctx* c, const void* phi_s, const RKArgs& rk, void* const out[3]);
 hipError_t launch_init_droplet(tpf_ctx* c, const double center[3], const double axes[3]);

@@ -35,20 +35,6 @@ __global__ __launch_bounds__(BLOCK) void k_face(Dims d, int kz, Phys P, const T*
 }
 
 template <typename T, int DIM>
-__global__ __launch_bounds__(BLOCK) void k_phase(Dims d, int kz, Phys P, RKArgs rk,
-                                                 const T* __restrict__ phi,
-                                                 const T* __restrict__ u0, const T* __restrict__ u1,
-                                                 const T* __restrict__ u2, const T* __restrict__ r0,
-                                                 const T* __restrict__ r1, const T* __restrict__ r2,
-                                                 const T* __restrict__ kappa,
-                                                 const T* __restrict__ yn, T* __restrict__ acc,
-                                                 T* __restrict__ ynext, int* __restrict__ flags) {
-    for_cells_zchunk(d, kz, [&](const Cell& C) {
-        op_phase<T, DIM>(P, rk, C, phi, u0, u1, u2, r0, r1, r2, kappa, yn, acc, ynext, flags);
-    });
-}
-
-template <typename T, int DIM>
 __global__ __launch_bounds__(BLOCK) void k_momentum(
     Dims d, int kz, Phys P, const T* __restrict__ phi, const T* __restrict__ u0,
     const T* __restrict__ u1, const T* __restrict__ u2, const T* __restrict__ m0,
@@ -56,6 +42,23 @@ __global__ __launch_bounds__(BLOCK) void k_momentum(
     const T* __restrict__ kappa, T* __restrict__ f0, T* __restrict__ f1, T* __restrict__ f2,
     T* __restrict__ F0, T* __restrict__ F1, T* __restrict__ F2) {
     for_cells_zchunk(d, kz, [&](const Cell& C) {
+        op_momentum<T, DIM>(P, C, phi, u0, u1, u2, m0, m1, m2, mu, kappa, f0, f1, f2, F0, F1, F2);
+    });
+}
+
+// the phase-field update and the momentum right-hand side of one cell in one
+// pass: both read phi and u at the same cells
+template <typename T, int DIM>
+__global__ __launch_bounds__(BLOCK) void k_phase_momentum(
+    Dims d, int kz, Phys P, RKArgs rk, const T* __restrict__ phi, const T* __restrict__ u0,
+    const T* __restrict__ u1, const T* __restrict__ u2, const T* __restrict__ r0,
+    const T* __restrict__ r1, const T* __restrict__ r2, const T* __restrict__ kappa,
+    const T* __restrict__ yn, T* __restrict__ acc, T* __restrict__ ynext, int* __restrict__ flags,
+    const T* __restrict__ m0, const T* __restrict__ m1, const T* __restrict__ m2,
+    const T* __restrict__ mu, T* __restrict__ f0, T* __restrict__ f1, T* __restrict__ f2,
+    T* __restrict__ F0, T* __restrict__ F1, T* __restrict__ F2) {
+    for_cells_zchunk(d, kz, [&](const Cell& C) {
+        op_phase<T, DIM>(P, rk, C, phi, u0, u1, u2, r0, r1, r2, kappa, yn, acc, ynext, flags);
         op_momentum<T, DIM>(P, C, phi, u0, u1, u2, m0, m1, m2, mu, kappa, f0, f1, f2, F0, F1, F2);
     });
 }
@@ -204,33 +207,6 @@ hipError_t launch_stage_fields(tpf_ctx* c, const void* phi_s, const void* const 
 }
 
 template <typename T, int DIM>
-static hipError_t phase_impl(tpf_ctx* c, const void* phi_s, const void* const u_s[3],
-                             const RKArgs& rk, void* out) {
-    const Phys P = phys_of(c);
-    const int kz = c->stage_kz;
-    const dim3 g = zchunk_grid(c->n, kz), b(BX, BY);
-    const int cdi = c->P.model == MODEL_CDI;
-    T* yn = tp<T>(c->phi[c->s_yn]);
-    T* acc = tp<T>(c->phi[c->s_acc]);
-    prof_begin(c, PC_PHASE, (double)c->N * c->tsz * (1 + DIM + (cdi ? DIM : 1) + (rk.eval_only ? 1 : 3 + (rk.stage < 3))));
-    k_phase<T, DIM><<<g, b, 0, c->stream>>>(
-        dims_of(c->n), kz, P, rk, ctp<T>(phi_s), ctp<T>(u_s[0]), ctp<T>(u_s[1]), ctp<T>(u_s[2]),
-        ctp<T>(c->rflux[0]), ctp<T>(c->rflux[1]), ctp<T>(c->rflux[2]), ctp<T>(c->kappa), yn, acc,
-        tp<T>(out), c->flags);
-    prof_end(c);
-    return hipGetLastError();
-}
-
-hipError_t launch_phase_update(tpf_ctx* c, const void* phi_s, const void* const u_s[3],
-                               const RKArgs& rk, void* out) {
-    if (c->mixed)
-        return c->dim == 2 ? phase_impl<float, 2>(c, phi_s, u_s, rk, out)
-                           : phase_impl<float, 3>(c, phi_s, u_s, rk, out);
-    return c->dim == 2 ? phase_impl<double, 2>(c, phi_s, u_s, rk, out)
-                       : phase_impl<double, 3>(c, phi_s, u_s, rk, out);
-}
-
-template <typename T, int DIM>
 static hipError_t mom_impl(tpf_ctx* c, const void* phi_s, const void* const u_s[3], int want_force) {
     const Phys P = phys_of(c);
     const int kz = c->stage_kz;
@@ -251,6 +227,37 @@ hipError_t launch_momentum(tpf_ctx* c, const void* phi_s, const void* const u_s[
                            : mom_impl<float, 3>(c, phi_s, u_s, want_force);
     return c->dim == 2 ? mom_impl<double, 2>(c, phi_s, u_s, want_force)
                        : mom_impl<double, 3>(c, phi_s, u_s, want_force);
+}
+
+template <typename T, int DIM>
+static hipError_t phase_mom_impl(tpf_ctx* c, const void* phi_s, const void* const u_s[3], const RKArgs& rk,
+                                 void* out, int want_force) {
+    const Phys P = phys_of(c);
+    const int kz = c->stage_kz;
+    const dim3 g = zchunk_grid(c->n, kz), b(BX, BY);
+    const int cdi = c->P.model == MODEL_CDI;
+    T* yn = tp<T>(c->phi[c->s_yn]);
+    T* acc = tp<T>(c->phi[c->s_acc]);
+    // phi and u once; r (CDI) or kappa, phase history; m, mu or kappa; f* out
+    const double phase = 1 + (cdi ? DIM : 1) + (rk.eval_only ? 1 : 3 + (rk.stage < 3));
+    prof_begin(c, PC_MOM, (double)c->N * c->tsz * (1 + DIM + phase - 1 + DIM + 1 + DIM));
+    k_phase_momentum<T, DIM><<<g, b, 0, c->stream>>>(
+        dims_of(c->n), kz, P, rk, ctp<T>(phi_s), ctp<T>(u_s[0]), ctp<T>(u_s[1]), ctp<T>(u_s[2]),
+        ctp<T>(c->rflux[0]), ctp<T>(c->rflux[1]), ctp<T>(c->rflux[2]), ctp<T>(c->kappa), yn, acc, tp<T>(out),
+        c->flags, ctp<T>(c->mflux[0]), ctp<T>(c->mflux[1]), ctp<T>(c->mflux[2]), ctp<T>(c->mu),
+        tp<T>(c->fs[0]), tp<T>(c->fs[1]), tp<T>(c->fs[2]), want_force ? tp<T>(c->force[0]) : nullptr,
+        tp<T>(c->force[1]), tp<T>(c->force[2]));
+    prof_end(c);
+    return hipGetLastError();
+}
+
+hipError_t launch_phase_momentum(tpf_ctx* c, const void* phi_s, const void* const u_s[3], const RKArgs& rk,
+                                 void* out, int want_force) {
+    if (c->mixed)
+        return c->dim == 2 ? phase_mom_impl<float, 2>(c, phi_s, u_s, rk, out, want_force)
+                           : phase_mom_impl<float, 3>(c, phi_s, u_s, rk, out, want_force);
+    return c->dim == 2 ? phase_mom_impl<double, 2>(c, phi_s, u_s, rk, out, want_force)
+                       : phase_mom_impl<double, 3>(c, phi_s, u_s, rk, out, want_force);
 }
 
 template <typename T, int DIM>

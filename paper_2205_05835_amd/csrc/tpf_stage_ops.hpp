@@ -18,6 +18,32 @@ struct RKArgs {
 };
 
 // ------------------------------------------------------------------ normals, mu
+// central gradient g = C phi at cell Q and 1 / sqrt(|g|^2 + delta^2)
+template <typename T, int DIM>
+__device__ __forceinline__ T grad_inv(const Phys& P, const Cell& Q, const T* __restrict__ phi, T (&g)[3]) {
+    const T ih2 = T(0.5 * P.inv_h);
+    T gg = T(0);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        g[a] = (ld(phi, Q.off(a, 1)) - ld(phi, Q.off(a, -1))) * ih2;
+        gg += g[a] * g[a];
+    }
+    return T(1) / sqrt(gg + T(P.delta2));
+}
+
+// L phi at cell C (5- or 7-point)
+template <typename T, int DIM>
+__device__ __forceinline__ T lap_at(const Phys& P, const Cell& C, const T* __restrict__ phi, T f) {
+    const T ih = T(P.inv_h);
+    T lap = T(0);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const T fp = ld(phi, C.off(a, 1)), fm = ld(phi, C.off(a, -1));
+        lap += ((fp - f) * ih - (f - fm) * ih) * ih;
+    }
+    return lap;
+}
+
 // n_a = C_a phi / sqrt(|C phi|^2 + delta^2)  (Table 1 caption, regularised)
 // mu = (sigma_hat/eps) psi'(phi) - sigma_hat eps L phi   (Eq. 2)
 template <typename T, int DIM>
@@ -26,21 +52,12 @@ __device__ __forceinline__ void op_cell(const Phys& P, const Cell& C, const T* _
                                                 T* __restrict__ n2, T* __restrict__ mu) {
     const unsigned c = C.id;
     const T f = ld(phi, c);
-    const T ih = T(P.inv_h), ih2 = T(0.5 * P.inv_h);
     T g[3] = {T(0), T(0), T(0)};
-    T gg = T(0), lap = T(0);
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-        const T fp = ld(phi, C.off(a, 1)), fm = ld(phi, C.off(a, -1));
-        g[a] = (fp - fm) * ih2;
-        gg += g[a] * g[a];
-        lap += ((fp - f) * ih - (f - fm) * ih) * ih;
-    }
-    const T inv = T(1) / sqrt(gg + T(P.delta2));
+    const T inv = grad_inv<T, DIM>(P, C, phi, g);
     st(n0, c, g[0] * inv);
     st(n1, c, g[1] * inv);
     if (DIM == 3) st(n2, c, g[2] * inv);
-    if (mu) st(mu, c, T(P.sigma_hat / P.eps) * dpsi(f) - T(P.sigma_hat * P.eps) * lap);
+    if (mu) st(mu, c, T(P.sigma_hat / P.eps) * dpsi(f) - T(P.sigma_hat * P.eps) * lap_at<T, DIM>(P, C, phi, f));
 }
 
 // kappa = - sum_a C_a n_a   (Eq. 3)
