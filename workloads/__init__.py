@@ -183,3 +183,20 @@ def divergence_free_velocity(shape, seed: int, amplitude: float = 0.1):
     uy = (_fwd(A[0], 2, 3) - _fwd(A[2], 0, 3)) / h
     uz = (_fwd(A[1], 0, 3) - _fwd(A[0], 1, 3)) / h
     return [np.ascontiguousarray(x) for x in (ux, uy, uz)]
+
+
+# ---------------------------------------------------------------- implicit ISODI step
+def implicit_drop(n=(256, 256), eps_over_h: float = 1.5) -> Case:
+    """Drop for the backward-Euler phase-field step with the ISODI model:
+    a circle (sphere) of radius 0.3 of the box centred in the unit box, eps =
+    1.5 h, gamma = 1, FP64; the velocity is ``divergence_free_velocity`` of
+    amplitude 0.5 (half of gamma, the bound the paper keeps gamma above)."""
+    dim = len(n)
+    return Case(f"implicit_drop_{'x'.join(map(str, n))}", tuple(n), (0.5,) * dim, (0.3,) * dim,
+                1.0, 1.0, 0.01, 0.01, 1.0, eps_over_h, "ISODI", "EB", "fp64", gamma=1.0)
+
+
+def implicit_dt(case: Case, multiple: float) -> float:
+    """multiple x h^2 / (2 dim gamma eps): the forward-Euler stability limit of
+    the regularisation diffusion gamma eps L."""
+    return multiple * case.h ** 2 / (2 * case.dim * case.gamma * case.eps)
