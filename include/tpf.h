@@ -228,6 +228,52 @@ tpf_status tpf_step_adjoint(tpf_ctx* ctx, void* tape, size_t tape_bytes, double 
                             double* gphi, double* gu0, double* gu1, double* gu2, int32_t on_device,
                             double grad_params[2]);
 
+/* ------------------------------------------------------------------ implicit ISODI step
+ * Backward-Euler step of the phase-field equation (Eq. 1) with the ISODI
+ * regularisation of Table 1, the model the paper introduces so that a fully
+ * implicit step can be solved by Newton's method (the paragraph after
+ * Table 1; the paper gives no implicit scheme, this is the plain backward
+ * Euler reading of one).  With the face velocity u of the current state held
+ * fixed, one step solves
+ *     F(phi) = phi - phi_old - dt R(phi) = 0,
+ * R the right-hand side of Eq. 1 with the same discrete operators as the RK4
+ * stage, by Newton's method with the Jacobian of F (including the
+ * derivative of the regularised normals, taken with |C phi| floored at
+ * 1e-10 / h where it is smaller; F itself is exact), each linear system solved by
+ * BiCGStab with a diagonal preconditioner to a relative residual
+ * krylov_rtol, and the Newton step shortened by halving until ||F||_2
+ * decreases (Armijo backtracking, at most 10 halvings).  The context must be FP64 (precision TPF_FP64) with model
+ * TPF_ISODI.
+ *
+ * tpf_implicit_phase_step: advances phi of the context's state by nsteps such
+ * steps of size dt >= 0, in place; u, the pressure, t and the step counter
+ * are unchanged.  opts may be NULL (all defaults).  A step succeeds when
+ * max_c |F| <= newton_tol.  If Newton does not get there within newton_maxit
+ * iterations the call returns TPF_ENOCONV, and TPF_ENONFINITE if F becomes
+ * NaN/Inf; either way phi is rolled back to its value at the start of the
+ * failing step (earlier steps of the call are kept).  info (may be NULL)
+ * receives the iteration counts.  For dt >= 2 eps / gamma the pointwise part
+ * of F stops being monotone and the root reached from phi_old need not be
+ * unique.  Uses the stage scratch of
+ * the context: no other call on the same context may run concurrently. */
+typedef struct {
+    double newton_tol;     /* stop at max |F| <= newton_tol (units of phi); 0 -> 1e-12      */
+    double krylov_rtol;    /* relative residual of each linear solve, in [0, 1); 0 -> 1e-6  */
+    int32_t newton_maxit;  /* Newton iterations per step; 0 -> 30                           */
+    int32_t krylov_maxit;  /* BiCGStab iterations per Newton iteration; 0 -> 400            */
+} tpf_implicit_opts;
+
+typedef struct {
+    int32_t newton_iters;  /* Newton iterations of the last step                            */
+    int32_t krylov_iters;  /* BiCGStab iterations of the last step (summed over Newton)     */
+    double residual;       /* max |F| when the last step stopped                            */
+    int64_t newton_total;  /* over all steps of the call                                    */
+    int64_t krylov_total;
+} tpf_implicit_info;
+
+tpf_status tpf_implicit_phase_step(tpf_ctx* ctx, double dt, int32_t nsteps, const tpf_implicit_opts* opts,
+                                   tpf_implicit_info* info);
+
 /* ------------------------------------------------------------------ batches
  * Batched persistent form: many independent 2D cases (each its own grid,
  * properties, model, force and time step; one precision for the whole batch)

@@ -20,7 +20,9 @@ The oracle solves F = 0 by Newton's method.  The Jacobian dF/dphi is formed
 column by column from central differences of ``phase_rhs`` and the Newton
 system is solved densely: slow, for small grids only, and independent of how
 the operator is built.  The Jacobian only steers the iteration; the answer is
-the root of F, and the loop stops on max |F| alone.
+the root of F, and the loop stops on max |F| alone.  The difference step is
+small (1e-9) because the regularised normals change fast where |C phi| is
+small, and a wide step smooths that change out of the Jacobian.
 """
 from __future__ import annotations
 
@@ -36,7 +38,7 @@ def be_residual(P: Params, dt: float, phi, phi_old, u):
 
 
 def isodi_backward_euler(P: Params, dt: float, phi_old, u, tol: float = 1e-13, maxit: int = 40,
-                         fd_step: float = 1e-7):
+                         fd_step: float = 1e-9):
     """One backward-Euler step of Eq. 1 with the ISODI regularisation.
 
     Returns (phi_new, newton_iterations, max |F| at phi_new).  Raises if max |F|

@@ -15,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtpf.so")
-SOURCES = ["tpf_stage.hip", "tpf_poisson.hip", "tpf_host.hip", "tpf_batch.hip", "tpf_adjoint.hip"]
+SOURCES = ["tpf_stage.hip", "tpf_poisson.hip", "tpf_host.hip", "tpf_batch.hip", "tpf_adjoint.hip",
+           "tpf_implicit.hip"]
 ARCH = os.environ.get("TPF_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -49,7 +49,8 @@ static const char* kProfNames[NPROF] = {
     "stage_cell", "stage_kappa", "stage_face", "stage_phase", "stage_phase_momentum", "stage_div",
     "stage_project", "fine_apply", "fine_update_sweep1", "fine_sweep1", "fine_sweep2",
     "fine_restrict", "fine_prolong", "fine_sweep4_dot", "mg_coarse_levels",
-    "residual", "reduce_finalize", "vector"};
+    "residual", "reduce_finalize", "vector", "imp_normals", "imp_residual", "imp_dn", "imp_apply",
+    "imp_vector", "imp_finalize"};
 
 static void prof_flush(tpf_ctx* c) {
     if (c->ev_count == 0) return;
@@ -194,6 +195,7 @@ static size_t carve(tpf_ctx* c, char* base) {
     c->diag_out = (double*)cv.take(16 * 8);
     c->scal = (SolverScalars*)cv.take(sizeof(SolverScalars));
     c->flags = (int*)cv.take(64);
+    c->imp_scal = cv.take(256);
     if (c->P.adjoint) {
         c->adj_stride = (long)(align256((size_t)c->N * 8) / 8);
         c->adj = (double*)cv.take((size_t)adj_fields(c->dim) * c->adj_stride * 8 + 256);

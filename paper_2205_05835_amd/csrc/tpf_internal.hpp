@@ -57,7 +57,9 @@ struct Level {
 enum ProfClass {
     PC_CELL = 0, PC_KAPPA, PC_FACE, PC_PHASE, PC_MOM, PC_DIV, PC_PROJ,
     PC_F_APPLY, PC_F_FIRST, PC_F_FIRST0, PC_F_SWEEP, PC_F_RESTRICT, PC_F_PROLONG, PC_F_SWEEPDOT,
-    PC_COARSE_LEVELS, PC_RESID, PC_FINALIZE, PC_VECTOR, PC_COUNT
+    PC_COARSE_LEVELS, PC_RESID, PC_FINALIZE, PC_VECTOR,
+    // backward-Euler ISODI phase-field step
+    PC_IMP_NORMALS, PC_IMP_RESIDUAL, PC_IMP_DN, PC_IMP_APPLY, PC_IMP_VECTOR, PC_IMP_FINALIZE, PC_COUNT
 };
 constexpr int NPROF = PC_COUNT;
 
@@ -110,6 +112,7 @@ struct tpf_ctx {
     long max_blocks;
     tpf::SolverScalars* scal;   // device
     int* flags;                 // device: [0] non-finite seen
+    void* imp_scal;             // device: scalars of the implicit phase-field step (256 bytes)
     double* diag_part;          // per-block diagnostic partials
     double* diag_out;           // finalized diagnostics
 

@@ -40,7 +40,7 @@ EXPORTS = ["tpf_workspace_bytes", "tpf_create", "tpf_destroy", "tpf_set_state", 
            "tpf_batch_status", "tpf_batch_clear_status", "tpf_batch_diagnostics", "tpf_batch_configs",
            "tpf_batch_config_info", "tpf_batch_set_config", "tpf_batch_tune", "tpf_checkpoint_bytes",
            "tpf_save_checkpoint", "tpf_load_checkpoint", "tpf_adjoint_tape_bytes", "tpf_stage_adjoint",
-           "tpf_step_adjoint", "tpf_solver_stats"]
+           "tpf_step_adjoint", "tpf_solver_stats", "tpf_implicit_phase_step"]
 
 
 class TpfError(RuntimeError):
@@ -58,6 +58,20 @@ class tpf_params(ctypes.Structure):
                 ("normal_delta", ctypes.c_double), ("poisson_rtol", ctypes.c_double),
                 ("poisson_rtol_inner", ctypes.c_double), ("poisson_maxit", ctypes.c_int32),
                 ("mg_levels", ctypes.c_int32), ("adjoint", ctypes.c_int32)]
+
+
+class tpf_implicit_opts(ctypes.Structure):
+    _fields_ = [("newton_tol", ctypes.c_double), ("krylov_rtol", ctypes.c_double),
+                ("newton_maxit", ctypes.c_int32), ("krylov_maxit", ctypes.c_int32)]
+
+
+class tpf_implicit_info(ctypes.Structure):
+    _fields_ = [("newton_iters", ctypes.c_int32), ("krylov_iters", ctypes.c_int32),
+                ("residual", ctypes.c_double), ("newton_total", ctypes.c_int64),
+                ("krylov_total", ctypes.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class tpf_diag(ctypes.Structure):
@@ -126,6 +140,8 @@ def lib():
         "tpf_adjoint_tape_bytes": ([vp, i32, ctypes.POINTER(ctypes.c_size_t)], i32),
         "tpf_stage_adjoint": ([vp, vp, vp, vp, vp, vp, vp, vp, vp, dp, i32], i32),
         "tpf_step_adjoint": ([vp, vp, ctypes.c_size_t, ctypes.c_double, i32, vp, vp, vp, vp, i32, dp], i32),
+        "tpf_implicit_phase_step": ([vp, ctypes.c_double, i32, ctypes.POINTER(tpf_implicit_opts),
+                                     ctypes.POINTER(tpf_implicit_info)], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -234,6 +250,16 @@ class Solver:
 
     def step(self, dt: float, nsteps: int = 1):
         check(lib().tpf_step(self.ctx, float(dt), int(nsteps)), "tpf_step")
+
+    def implicit_phase_step(self, dt: float, nsteps: int = 1, newton_tol: float = 0.0,
+                            krylov_rtol: float = 0.0, newton_maxit: int = 0, krylov_maxit: int = 0) -> dict:
+        """Backward-Euler ISODI phase-field steps (tpf_implicit_phase_step);
+        returns the iteration counts."""
+        o = tpf_implicit_opts(float(newton_tol), float(krylov_rtol), int(newton_maxit), int(krylov_maxit))
+        info = tpf_implicit_info()
+        check(lib().tpf_implicit_phase_step(self.ctx, float(dt), int(nsteps), ctypes.byref(o),
+                                            ctypes.byref(info)), "tpf_implicit_phase_step")
+        return info.as_dict()
 
     def get_state(self, with_pressure: bool = False):
         """Host numpy copies: (phi, [u_a], p or None), C-order grid shape."""

@@ -43,6 +43,10 @@ def test_struct_layout_matches_header(tpf):
     assert P.poisson_maxit.offset == 120 and P.adjoint.offset == 128 and ctypes.sizeof(P) == 136
     D = tpf.tpf_diag
     assert D.poisson_outer.offset == 104 and ctypes.sizeof(D) == 112
+    O = tpf.tpf_implicit_opts
+    assert O.newton_maxit.offset == 16 and ctypes.sizeof(O) == 24
+    info = tpf.tpf_implicit_info
+    assert info.residual.offset == 8 and info.krylov_total.offset == 24 and ctypes.sizeof(info) == 32
 
 
 @pytest.mark.parametrize("bad", [

@@ -189,8 +189,8 @@ def divergence_free_velocity(shape, seed: int, amplitude: float = 0.1):
 def implicit_drop(n=(256, 256), eps_over_h: float = 1.5) -> Case:
     """Drop for the backward-Euler phase-field step with the ISODI model:
     a circle (sphere) of radius 0.3 of the box centred in the unit box, eps =
-    1.5 h, gamma = 1, FP64; the velocity is ``divergence_free_velocity`` of
-    amplitude 0.5 (half of gamma, the bound the paper keeps gamma above)."""
+    1.5 h, gamma = 1, FP64; the velocity is ``implicit_velocity`` (max |u_a| =
+    0.5: half of gamma, the bound the paper keeps gamma above)."""
     dim = len(n)
     return Case(f"implicit_drop_{'x'.join(map(str, n))}", tuple(n), (0.5,) * dim, (0.3,) * dim,
                 1.0, 1.0, 0.01, 0.01, 1.0, eps_over_h, "ISODI", "EB", "fp64", gamma=1.0)
@@ -200,3 +200,10 @@ def implicit_dt(case: Case, multiple: float) -> float:
     """multiple x h^2 / (2 dim gamma eps): the forward-Euler stability limit of
     the regularisation diffusion gamma eps L."""
     return multiple * case.h ** 2 / (2 * case.dim * case.gamma * case.eps)
+
+
+def implicit_velocity(shape, seed: int, umax: float = 0.5):
+    """``divergence_free_velocity`` scaled so that max_a max |u_a| = umax."""
+    u = divergence_free_velocity(shape, seed, amplitude=1.0)
+    m = max(float(np.abs(x).max()) for x in u)
+    return [np.ascontiguousarray(x * (umax / m)) for x in u]
