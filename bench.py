@@ -36,10 +36,14 @@ TRAFFIC_DIR = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = ("paper_2205_05835_amd/csrc/tpf_poisson.hip", "paper_2205_05835_amd/csrc/tpf_device.hpp")
 
 
-def kernel_source_hash():
+IMPLICIT_SOURCES = ("paper_2205_05835_amd/csrc/tpf_implicit.hip", "paper_2205_05835_amd/csrc/tpf_device.hpp",
+                    "paper_2205_05835_amd/csrc/tpf_stage_ops.hpp")
+
+
+def kernel_source_hash(kernel=""):
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in (IMPLICIT_SOURCES if kernel.startswith("imp_") else KERNEL_SOURCES):
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -54,7 +58,7 @@ def recorded_traffic(kernel):
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    if rec.get("class") != kernel or rec.get("source_hash") != kernel_source_hash():
+    if rec.get("class") != kernel or rec.get("source_hash") != kernel_source_hash(kernel):
         return None
     return rec.get("traffic_bytes_per_launch")
 
@@ -267,6 +271,66 @@ def adjoint_run(args):
     return out
 
 
+def implicit_run(args):
+    """Backward-Euler ISODI phase-field steps (Newton + BiCGStab, FP64) on the
+    n^3 drop of radius 0.3 in the unit box, eps = 1.5 h, gamma = 1, under a
+    seeded divergence-free velocity with max |u_a| = 0.5, dt = `mult` x the
+    forward-Euler limit of the regularisation diffusion.  One untimed step,
+    one attributed step (every kernel class timed), then the timed steps with
+    events around the dominant kernel class only."""
+    import torch
+
+    import workloads
+    from paper_2205_05835_amd import tpf
+
+    n = args.implicit_n
+    case = workloads.implicit_drop((n, n, n))
+    dt = workloads.implicit_dt(case, args.implicit_mult)
+    s = tpf.solver_for_case(case)
+    s.init_droplet(case.center, case.semi_axes)
+    phi, _ = s.get_state_device()
+    u = [torch.from_numpy(x).to(s.device) for x in
+         workloads.implicit_velocity(tuple(reversed(case.n)), seed=21)]
+    s.set_state(phi, u)
+    del phi, u
+    s.implicit_phase_step(dt, 1)
+    s.profile_enable(-1)
+    s.implicit_phase_step(dt, 1)
+    prof_all = s.profile_read()
+    s.profile_enable(0)
+    names = s.profile_classes()
+    single = {k: v for k, v in prof_all.items()
+              if k.startswith("imp_") and k not in ("imp_vector", "imp_finalize") and v["launches"]}
+    dominant = max(single, key=lambda k: single[k]["ms"])
+    s.profile_enable(1 << names.index(dominant))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = s.implicit_phase_step(dt, args.implicit_steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    dom = s.profile_read()[dominant]
+    s.profile_enable(0)
+    mean_s = dom["ms"] / max(dom["launches"], 1) * 1e-3
+    achieved = dom["bytes_per_launch"] / mean_s / 1e9 if mean_s > 0 else 0.0
+    steps = args.implicit_steps
+    out = {"workload": f"{case.name}, ISODI, FP64, dt = {args.implicit_mult} x h^2/(2 dim gamma eps)",
+           "dt": dt, "steps": steps, "value": round(case.cells * steps / wall, 1), "unit": "cell-steps/s",
+           "ms_per_step": round(wall / steps * 1e3, 3),
+           "newton_per_step": round(info["newton_total"] / steps, 3),
+           "krylov_per_step": round(info["krylov_total"] / steps, 3),
+           "residual": info["residual"],
+           "roofline": {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1),
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                        "traffic": recorded_traffic(dominant),
+                        "bytes_per_launch": dom["bytes_per_launch"],
+                        "mean_launch_us": round(mean_s * 1e6, 3), "launches": dom["launches"]},
+           "breakdown_ms_one_step": {k: round(v["ms"], 3) for k, v in
+                                     sorted(prof_all.items(), key=lambda kv: -kv[1]["ms"]) if v["launches"]}}
+    del s
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(args):
     """The oracle as it stands, on the host cores, on a bounded sample: the
     same oscillating-drop configuration at 64^3 for 2 RK4 steps."""
@@ -314,6 +378,11 @@ def main():
     ap.add_argument("--batch-warmup", type=int, default=2)
     ap.add_argument("--batch-compare", type=int, default=16,
                     help="cases of the FP32-vs-FP64 batch comparison (0: skip)")
+    ap.add_argument("--no-implicit", action="store_true",
+                    help="skip the backward-Euler ISODI phase-field measurement")
+    ap.add_argument("--implicit-n", type=int, default=256)
+    ap.add_argument("--implicit-steps", type=int, default=3)
+    ap.add_argument("--implicit-mult", type=float, default=10.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -329,6 +398,7 @@ def main():
     case = g["case"]
     batch = None if args.no_batch else batch_run(args)
     adj = None if args.no_adjoint else adjoint_run(args)
+    imp = None if args.no_implicit else implicit_run(args)
     cpu = None if args.no_cpu_baseline else cpu_baseline(args)
     dom = g["dom"]
     line = {
@@ -366,6 +436,7 @@ def main():
         "adjoint_over_forward": adj["adjoint_over_forward"] if adj else None,
         "adjoint": adj,
         "batched": batch,
+        "implicit_isodi": imp,
         "event_ms_per_step": round(g["ev_ms"] / args.steps, 4),
     }
     if args.breakdown_out:

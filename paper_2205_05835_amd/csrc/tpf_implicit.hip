@@ -32,6 +32,7 @@
 // them back to test convergence.
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "tpf_internal.hpp"
 
@@ -423,6 +424,18 @@ void bicgstab_iteration(const Launch& L, const ImpFields& F, double dt, double m
     fin(L, IMP_RHO, 0.0, sc);
 }
 
+// launches and bytes issued per profiling class so far
+struct ProfSnap {
+    long n[NPROF];
+    double b[NPROF];
+};
+void snapshot(const tpf_ctx* c, ProfSnap& o) {
+    for (int q = 0; q < NPROF; ++q) {
+        o.n[q] = c->prof_issued[q];
+        o.b[q] = c->prof_issued_bytes[q];
+    }
+}
+
 tpf_status read_scal(tpf_ctx* c, ImpScal* host) {
     hipError_t e = hipMemcpyAsync(host, c->imp_scal, sizeof(ImpScal), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -440,6 +453,7 @@ tpf_status implicit_steps(tpf_ctx* c, double dt, int nsteps, const tpf_implicit_
     const size_t bytes = (size_t)c->N * 8;
     const int chunk = 4;   // BiCGStab iterations queued between convergence checks
     const int LS_MAX = 10;  // halvings of the Newton step in the line search
+    std::vector<ProfSnap> snaps((size_t)o.krylov_maxit + chunk);
     for (int n = 0; n < nsteps; ++n) {
         hipError_t e = hipMemcpyAsync(F.phi_old, F.phi, bytes, hipMemcpyDeviceToDevice, c->stream);
         if (e != hipSuccess) return hip_fail(e, "implicit step copy");
@@ -466,16 +480,29 @@ tpf_status implicit_steps(tpf_ctx* c, double dt, int nsteps, const tpf_implicit_
                 break;
             }
             const double ff = h.rr0;
-            int done = h.done;
+            int done = h.done, queued = 0;
             for (int it = 0; !done && it < o.krylov_maxit; it += chunk) {
                 const int k = std::min(chunk, o.krylov_maxit - it);
-                for (int q = 0; q < k; ++q) bicgstab_iteration<DIM>(L, F, dt, mshift, sc);
+                for (int q = 0; q < k; ++q, ++queued) {
+                    snapshot(c, snaps[queued]);
+                    bicgstab_iteration<DIM>(L, F, dt, mshift, sc);
+                }
                 if ((e = hipGetLastError()) != hipSuccess) break;
                 if ((st = read_scal(c, &h)) != TPF_OK) break;
                 done = h.done;
             }
             if (e != hipSuccess) { st = hip_fail(e, "implicit Krylov solve"); break; }
             if (st != TPF_OK) break;
+            // iterations queued after convergence returned at once: they count
+            // in the timed total but not as working launches or bytes
+            if (h.iters < queued) {
+                ProfSnap now;
+                snapshot(c, now);
+                for (int q = 0; q < NPROF; ++q) {
+                    c->prof_noop[q] += now.n[q] - snaps[h.iters].n[q];
+                    c->prof_noop_bytes[q] += now.b[q] - snaps[h.iters].b[q];
+                }
+            }
             if (h.iters == 0) {
                 set_error("implicit phase-field step: BiCGStab broke down in its first iteration; phi rolled back");
                 st = TPF_ENOCONV;
