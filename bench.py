@@ -383,6 +383,8 @@ def main():
     ap.add_argument("--implicit-n", type=int, default=256)
     ap.add_argument("--implicit-steps", type=int, default=3)
     ap.add_argument("--implicit-mult", type=float, default=10.0)
+    ap.add_argument("--implicit-only", action="store_true",
+                    help="only the backward-Euler ISODI measurement (its own JSON line; for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -394,6 +396,9 @@ def main():
               "(the multi-GPU decomposition is a design, not an implementation)", file=sys.stderr)
         sys.exit(2)
 
+    if args.implicit_only:
+        print(json.dumps({"implicit_isodi": implicit_run(args)}))
+        return
     g = gpu_run(args)
     case = g["case"]
     batch = None if args.no_batch else batch_run(args)
