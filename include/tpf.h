@@ -240,9 +240,10 @@ tpf_status tpf_step_adjoint(tpf_ctx* ctx, void* tape, size_t tape_bytes, double 
  * stage, by Newton's method with the Jacobian of F (including the
  * derivative of the regularised normals, taken with |C phi| floored at
  * 1e-10 / h where it is smaller; F itself is exact), each linear system solved by
- * BiCGStab with a diagonal preconditioner to a relative residual
- * krylov_rtol, and the Newton step shortened by halving until ||F||_2
- * decreases (Armijo backtracking, at most 10 halvings).  The context must be FP64 (precision TPF_FP64) with model
+ * BiCGStab with a diagonal preconditioner to a relative residual that
+ * follows Newton's progress (Eisenstat-Walker) or a fixed krylov_rtol, and
+ * the Newton step shortened by halving until ||F||_2 decreases (Armijo
+ * backtracking, at most 10 halvings).  The context must be FP64 (precision TPF_FP64) with model
  * TPF_ISODI.
  *
  * tpf_implicit_phase_step: advances phi of the context's state by nsteps such
@@ -258,7 +259,7 @@ tpf_status tpf_step_adjoint(tpf_ctx* ctx, void* tape, size_t tape_bytes, double 
  * the context: no other call on the same context may run concurrently. */
 typedef struct {
     double newton_tol;     /* stop at max |F| <= newton_tol (units of phi); 0 -> 1e-12      */
-    double krylov_rtol;    /* relative residual of each linear solve, in [0, 1); 0 -> 1e-6  */
+    double krylov_rtol;    /* relative residual of each linear solve, in [0, 1); 0 -> adaptive */
     int32_t newton_maxit;  /* Newton iterations per step; 0 -> 30                           */
     int32_t krylov_maxit;  /* BiCGStab iterations per Newton iteration; 0 -> 400            */
 } tpf_implicit_opts;

@@ -22,8 +22,11 @@
 //
 // J is not symmetric (transport, and the curvature term), so each Newton
 // system is solved by BiCGStab with a Jacobi (diagonal) right preconditioner
-// M = c + 2 dim dt gamma eps / h^2 to a relative residual krylov_rtol; the
-// step is then shortened by halving until ||F||_2 decreases (Armijo).
+// M = c + 2 dim dt gamma eps / h^2, to a relative residual eta that follows
+// the progress of Newton (Eisenstat and Walker's second choice: loose while
+// ||F|| is large, tight as it falls, never tighter than newton_tol needs), or
+// a fixed krylov_rtol; the step is then shortened by halving until ||F||_2
+// decreases (Armijo).
 //
 // Every field is FP64 and every kernel is one thread per cell on the
 // z-chunked tiling of the stage kernels; reductions write per-block partials
@@ -449,7 +452,9 @@ tpf_status implicit_steps(tpf_ctx* c, double dt, int nsteps, const tpf_implicit_
     L.nb = (int)L.grid.x;
     ImpScal* sc = (ImpScal*)c->imp_scal;
     const double mshift = 2.0 * DIM * dt * L.P.gamma * L.P.eps * L.P.inv_h * L.P.inv_h;
+    // fixed forcing term, or 0: adaptive (set per Newton iteration below)
     const double tol2 = o.krylov_rtol * o.krylov_rtol;
+    const bool adaptive = o.krylov_rtol == 0.0;
     const size_t bytes = (size_t)c->N * 8;
     const int chunk = 4;   // BiCGStab iterations queued between convergence checks
     const int LS_MAX = 10;  // halvings of the Newton step in the line search
@@ -458,6 +463,7 @@ tpf_status implicit_steps(tpf_ctx* c, double dt, int nsteps, const tpf_implicit_
         hipError_t e = hipMemcpyAsync(F.phi_old, F.phi, bytes, hipMemcpyDeviceToDevice, c->stream);
         if (e != hipSuccess) return hip_fail(e, "implicit step copy");
         int newton = 0, krylov = 0;
+        double eta_prev = 0.1, fn_prev = 0.0, eta2 = 0.0;
         tpf_status st = TPF_OK;
         // F and the Newton system at the current iterate
         ImpScal h;
@@ -480,6 +486,25 @@ tpf_status implicit_steps(tpf_ctx* c, double dt, int nsteps, const tpf_implicit_
                 break;
             }
             const double ff = h.rr0;
+            if (adaptive) {
+                // Eisenstat-Walker choice 2 (gamma 0.9, exponent (1 + sqrt 5)/2)
+                // with their safeguard, capped at 0.1, and floored where a
+                // linear residual of 0.1 newton_tol in 2-norm (hence in max
+                // norm) is already met
+                const double fn = std::sqrt(ff), ex = 1.6180339887498949;
+                double eta = 0.1;
+                if (newton > 0) {
+                    eta = 0.9 * std::pow(fn / fn_prev, ex);
+                    const double sg = 0.9 * std::pow(eta_prev, ex);
+                    if (sg > 0.1) eta = std::max(eta, sg);
+                }
+                eta = std::max(std::min(eta, 0.1), std::min(0.5, 0.1 * o.newton_tol / fn));
+                eta_prev = eta;
+                fn_prev = fn;
+                eta2 = eta * eta;
+                e = hipMemcpyAsync(&sc->tol2, &eta2, sizeof(double), hipMemcpyHostToDevice, c->stream);
+                if (e != hipSuccess) { st = hip_fail(e, "implicit forcing term"); break; }
+            }
             int done = h.done, queued = 0;
             for (int it = 0; !done && it < o.krylov_maxit; it += chunk) {
                 const int k = std::min(chunk, o.krylov_maxit - it);
@@ -569,7 +594,6 @@ extern "C" tpf_status tpf_implicit_phase_step(tpf_ctx* c, double dt, int32_t nst
         return TPF_EINVAL;
     }
     if (o.newton_tol == 0.0) o.newton_tol = 1e-12;
-    if (o.krylov_rtol == 0.0) o.krylov_rtol = 1e-6;
     if (o.newton_maxit == 0) o.newton_maxit = 30;
     if (o.krylov_maxit == 0) o.krylov_maxit = 400;
     if (info) *info = tpf_implicit_info{};

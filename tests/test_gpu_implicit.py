@@ -78,9 +78,11 @@ def test_implicit_three_steps_match_oracle(gpu, ora):
     ref = phi0
     for _ in range(3):
         ref, _, _ = implicit.isodi_backward_euler(P, dt, ref, u, tol=1e-12)
-    s, phi, _, info = gpu_step(gpu, case, phi0, u, dt, nsteps=3)
-    assert info["newton_total"] >= 3
-    assert np.abs(phi - ref).max() < 3 * TOL
+    for rtol in (0.0, 1e-6):          # adaptive forcing, fixed forcing
+        s, phi, _, info = gpu_step(gpu, case, phi0, u, dt, nsteps=3, krylov_rtol=rtol)
+        say(f"  krylov_rtol {rtol}: {info}")
+        assert info["newton_total"] >= 3
+        assert np.abs(phi - ref).max() < 3 * TOL
 
 
 @pytest.mark.fullsize
