@@ -135,6 +135,9 @@ def gpu_run(args):
         "breakdown_launches": {k: v["launches"] for k, v in prof_all.items() if v["launches"]},
     }
     out["step_ms_attribution"] = sum(v["ms"] for v in prof_all.values())
+    # algorithmic bytes of one whole step (every working launch of the
+    # attributed step), against the wall time per timed step
+    out["step_bytes"] = sum(v["launches"] * v["bytes_per_launch"] for v in prof_all.values())
 
     if not args.no_fp64_compare:
         m = args.compare_steps
@@ -443,6 +446,10 @@ def main():
         "batched": batch,
         "implicit_isodi": imp,
         "event_ms_per_step": round(g["ev_ms"] / args.steps, 4),
+        "step_hbm": {"algorithmic_gb_per_step": round(g["step_bytes"] / 1e9, 3),
+                     "achieved": round(g["step_bytes"] / (g["wall"] / args.steps) / 1e9, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(g["step_bytes"] / (g["wall"] / args.steps) / 1e9 / HBM_PEAK_GBS, 4)},
     }
     if args.breakdown_out:
         with open(args.breakdown_out, "w") as f:
