@@ -371,6 +371,26 @@ def test_advection_kinetic_energy_identity(ora, dim, shape):
 
 
 @pytest.mark.parametrize("dim,shape", [(2, (10, 12)), (3, (4, 5, 6))])
+def test_advection_conserves_momentum(ora, dim, shape):
+    """The conservative part N_a + u_a A_a(D m) is a difference of fluxes on
+    the u_a control volumes, so on a periodic grid its sum over the faces of
+    each axis vanishes for any m and u: the velocity form moves no momentum
+    rho u when d rho/dt = -D m.  A wrong sign of the u A(D m) term or a
+    mis-indexed flux leaves a non-zero sum."""
+    n = tuple(reversed(shape))
+    P = ora.Params(n=n)
+    m = [workloads.noise_field(shape, 120 + a) for a in range(dim)]
+    u = [workloads.noise_field(shape, 140 + a) for a in range(dim)]
+    N = ora.advection(P, m, u)
+    Dm = sum((roll(m[a], a, 1, dim) - m[a]) / P.h for a in range(dim))
+    for a in range(dim):
+        cons = N[a] + u[a] * 0.5 * (roll(Dm, a, -1, dim) + Dm)
+        scale = np.abs(N[a]).max() * N[a].size
+        assert abs(np.sum(cons)) < 1e-13 * scale
+        assert np.abs(cons).max() > 1e-3 * np.abs(N[a]).max()     # not trivially zero
+
+
+@pytest.mark.parametrize("dim,shape", [(2, (10, 12)), (3, (4, 5, 6))])
 def test_advection_uniform_velocity_is_zero(ora, dim, shape):
     """For a uniform velocity, N = U.div(m) - U A(D m) vanishes for any mass flux."""
     P = ora.Params(n=tuple(reversed(shape)))
