@@ -86,9 +86,10 @@ def test_implicit_three_steps_match_oracle(gpu, ora):
 
 
 @pytest.mark.fullsize
-@pytest.mark.parametrize("n", [(256, 256), (128, 128, 128)])
+@pytest.mark.parametrize("n", [(256, 256), (128, 128, 128), (256, 256, 256)])
 def test_implicit_step_fullsize_residual(gpu, ora, n):
-    """At 256^2 and 128^3 the oracle's F at the GPU's root must vanish."""
+    """At 256^2, 128^3 and the 256^3 of the benchmark the oracle's F at the
+    GPU's root must vanish."""
     case, P, phi0, u = setup(ora, n, seed=13)
     dt = workloads.implicit_dt(case, 10.0)
     say(f"implicit full size {n} dt={dt:.3e}")
