@@ -274,6 +274,50 @@ def adjoint_run(args):
     return out
 
 
+def fixed_run(args):
+    """The same 256^3 step with a fixed amount of pressure-solver work
+    (TPF_FIXED_PCG=outer,inner: that many defect-correction passes of that
+    many PCG iterations each, no convergence test), so that cell-steps/s can
+    be compared across solver versions whatever their iteration counts."""
+    import torch
+
+    import workloads
+    from paper_2205_05835_amd import tpf
+
+    case = workloads.oscillating_drop_3d(args.n, "fp32_mixed")
+    dt = case.dt()
+    os.environ["TPF_FIXED_PCG"] = args.fixed_pcg
+    try:
+        s = tpf.solver_for_case(case)
+    finally:
+        del os.environ["TPF_FIXED_PCG"]
+    s.init_droplet(case.center, case.semi_axes)
+    s.step(dt, 1)
+    s.profile_enable(-1)
+    s.step(dt, 1)
+    prof = s.profile_read()
+    s.profile_enable(0)
+    step_bytes = sum(v["launches"] * v["bytes_per_launch"] for v in prof.values())
+    s.solver_stats(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(dt, args.fixed_steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stats = s.solver_stats()
+    out = {"outer_inner": args.fixed_pcg, "steps": args.fixed_steps,
+           "value": round(case.cells * args.fixed_steps / wall, 1), "unit": "cell-steps/s",
+           "ms_per_step": round(wall / args.fixed_steps * 1e3, 4),
+           "pcg_iterations_per_solve": round(stats["inner"] / max(stats["solves"], 1), 3),
+           "outer_per_solve": round(stats["outer"] / max(stats["solves"], 1), 3),
+           "step_hbm": {"algorithmic_gb_per_step": round(step_bytes / 1e9, 3),
+                        "achieved": round(step_bytes / (wall / args.fixed_steps) / 1e9, 1), "unit": "GB/s",
+                        "frac": round(step_bytes / (wall / args.fixed_steps) / 1e9 / HBM_PEAK_GBS, 4)}}
+    del s
+    torch.cuda.empty_cache()
+    return out
+
+
 def implicit_run(args):
     """Backward-Euler ISODI phase-field steps (Newton + BiCGStab, FP64) on the
     n^3 drop of radius 0.3 in the unit box, eps = 1.5 h, gamma = 1, under a
@@ -381,6 +425,10 @@ def main():
     ap.add_argument("--batch-warmup", type=int, default=2)
     ap.add_argument("--batch-compare", type=int, default=16,
                     help="cases of the FP32-vs-FP64 batch comparison (0: skip)")
+    ap.add_argument("--no-fixed", action="store_true",
+                    help="skip the fixed-iteration (comparable-work) measurement")
+    ap.add_argument("--fixed-pcg", default="2,6", help="outer,inner of the fixed-iteration measurement")
+    ap.add_argument("--fixed-steps", type=int, default=5)
     ap.add_argument("--no-implicit", action="store_true",
                     help="skip the backward-Euler ISODI phase-field measurement")
     ap.add_argument("--implicit-n", type=int, default=256)
@@ -407,6 +455,7 @@ def main():
     batch = None if args.no_batch else batch_run(args)
     adj = None if args.no_adjoint else adjoint_run(args)
     imp = None if args.no_implicit else implicit_run(args)
+    fixed = None if args.no_fixed else fixed_run(args)
     cpu = None if args.no_cpu_baseline else cpu_baseline(args)
     dom = g["dom"]
     line = {
@@ -445,6 +494,7 @@ def main():
         "adjoint": adj,
         "batched": batch,
         "implicit_isodi": imp,
+        "fixed_iterations": fixed,
         "event_ms_per_step": round(g["ev_ms"] / args.steps, 4),
         "step_hbm": {"algorithmic_gb_per_step": round(g["step_bytes"] / 1e9, 3),
                      "achieved": round(g["step_bytes"] / (g["wall"] / args.steps) / 1e9, 1),

@@ -261,6 +261,11 @@ static void init_geometry(tpf_ctx* c, const tpf_params* P) {
     const char* skz = std::getenv("TPF_STAGE_KZ");
     c->stage_kz = skz ? std::atoi(skz) : (c->dim == 3 ? 8 : 1);
     c->stage_kz = std::min(std::max(c->stage_kz, 1), 64);
+    // fixed-iteration measurement mode "outer,inner" (0: off)
+    const char* fx = std::getenv("TPF_FIXED_PCG");
+    c->fixed_outer = c->fixed_inner = 0;
+    if (fx && std::sscanf(fx, "%d,%d", &c->fixed_outer, &c->fixed_inner) != 2) c->fixed_outer = c->fixed_inner = 0;
+    if (c->fixed_outer < 1 || c->fixed_inner < 1) c->fixed_outer = c->fixed_inner = 0;
     const char* xt = std::getenv("TPF_XCD_TILES");
     g_xcd_tiles = (xt && xt[0] == '0') ? 0 : 1;
     c->nlev = plan_levels(c);

@@ -168,6 +168,11 @@ struct tpf_ctx {
     int stage_kz;        // planes per block of the z-chunked stage kernels
     double mg_alpha;     // weight of the multigrid coarse-grid correction
     int coarse_sweeps_per_cell;   // coarsest-grid Jacobi sweeps per cell of its largest dimension (0: 2)
+    // measurement mode with a fixed amount of solver work per pressure solve
+    // (TPF_FIXED_PCG=outer,inner): exactly fixed_outer defect-correction passes
+    // of exactly fixed_inner PCG iterations (FP64: one PCG of fixed_inner), no
+    // convergence test; 0: off
+    int fixed_outer, fixed_inner;
 };
 
 namespace tpf {

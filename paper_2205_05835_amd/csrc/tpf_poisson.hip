@@ -1611,10 +1611,11 @@ tpf_status poisson_solve(tpf_ctx* c, const void* phi, int* iters, double* relres
         double w1, w2;
         weights_of(c->dim, w1, w2);
         Solver<double, double> sv{c, c->dim, w1, w2};
+        const bool fixed = c->fixed_inner > 0;
         sv.build_betas(phi);
         sv.residual<double>(sv.coef_fine(), tp<double>(c->lv[0].r));
-        (void)finalize2(c, (int)sv.nb0(), (int)sv.nb0(), FIN_INIT, rtol * rtol);
-        e = sv.pcg<double>(phi, c->p, maxit, 0);
+        (void)finalize2(c, (int)sv.nb0(), (int)sv.nb0(), FIN_INIT, fixed ? 0.0 : rtol * rtol);
+        e = sv.pcg<double>(phi, c->p, fixed ? c->fixed_inner : maxit, 0);
         if (e != hipSuccess) return hip_fail(e, "FP64 PCG");
         tpf_status st = read_scalars(c, &s);
         if (st != TPF_OK) return st;
@@ -1625,7 +1626,7 @@ tpf_status poisson_solve(tpf_ctx* c, const void* phi, int* iters, double* relres
         *iters = s.iters;
         *outer = 1;
         *relres = s.ff > 0 ? std::sqrt(s.rr / s.ff) : 0.0;
-        if (!s.done) {
+        if (!s.done && !fixed) {
             set_error("pressure solve did not converge within poisson_maxit iterations");
             return TPF_ENOCONV;
         }
@@ -1639,17 +1640,20 @@ tpf_status poisson_solve(tpf_ctx* c, const void* phi, int* iters, double* relres
     sv.build_betas(phi);
     const double rin = c->P.poisson_rtol_inner;
     int total = 0;
-    const int max_outer = 12;
+    // fixed-iteration mode: exactly fixed_outer passes of fixed_inner PCG
+    // iterations, then one more residual for the reported relres
+    const bool fixed = c->fixed_inner > 0;
+    const int max_outer = fixed ? c->fixed_outer + 1 : 12;
     for (int o = 0; o < max_outer; ++o) {
         s64.residual<float>(s64.coef_phi(phi), tp<float>(c->lv[0].r));   // FP64 residual, FP64 beta
-        (void)finalize2(c, (int)s64.nb0(), (int)s64.nb0(), FIN_INIT, rtol * rtol);
+        (void)finalize2(c, (int)s64.nb0(), (int)s64.nb0(), FIN_INIT, fixed ? 0.0 : rtol * rtol);
         tpf_status st = read_scalars(c, &s);
         if (st != TPF_OK) return st;
         if (!std::isfinite(s.ff) || !std::isfinite(s.rr)) {
             set_error("non-finite pressure right-hand side or residual");
             return TPF_ENONFINITE;
         }
-        if (s.done) {
+        if (s.done || (fixed && o == c->fixed_outer)) {
             *outer = o;
             *iters = total;
             *relres = s.ff > 0 ? std::sqrt(s.rr / s.ff) : 0.0;
@@ -1659,10 +1663,10 @@ tpf_status poisson_solve(tpf_ctx* c, const void* phi, int* iters, double* relres
         // reduction it needs), but never below rin, the depth an FP32 PCG
         // reaches reliably; a further outer pass picks up the rest
         const double need = 0.5 * rtol * std::sqrt(s.ff / s.rr);
-        const double tin = std::min(0.1, std::max(rin, need));
+        const double tin = fixed ? 0.0 : std::min(0.1, std::max(rin, need));
         k_inner_setup<<<1, 64, 0, c->stream>>>(c->scal, tin * tin);
         k_fill_s<float><<<vgrid(c->N), BLOCK, 0, c->stream>>>(c->N, tp<float>(c->ev), 0.0f);
-        e = sv.pcg<float>(phi, tp<float>(c->ev), maxit, 1 + std::min(o, 2));
+        e = sv.pcg<float>(phi, tp<float>(c->ev), fixed ? c->fixed_inner : maxit, 1 + std::min(o, 2));
         if (e != hipSuccess) return hip_fail(e, "FP32 inner PCG");
         st = read_scalars(c, &s);
         if (st != TPF_OK) return st;

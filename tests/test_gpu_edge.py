@@ -132,3 +132,33 @@ def test_mixed_precision_ragged(gpu, ora):
     eu = max(np.abs(u_g[a] - u_o[a]).max() for a in range(3)) / umax
     say(f"  |dphi| {ephi:.2e} |du|/|u| {eu:.2e}")
     assert ephi < 1e-5 and eu < 1e-2
+
+
+@pytest.mark.parametrize("precision,fixed,outer,inner", [("fp32_mixed", "2,3", 2, 6), ("fp64", "1,5", 1, 5)])
+def test_fixed_iteration_mode(gpu, precision, fixed, outer, inner):
+    """TPF_FIXED_PCG=outer,inner (the comparable-work measurement mode) runs
+    exactly that many defect-correction passes and PCG iterations per solve,
+    and its state stays close to the converged one."""
+    import os
+    case = workloads.oscillating_drop_3d(32, precision)
+    dt = case.dt()
+    say(f"fixed-iteration mode {precision} {fixed}")
+    ref = gpu.solver_for_case(case)
+    ref.init_droplet(case.center, case.semi_axes)
+    ref.step(dt, 2)
+    os.environ["TPF_FIXED_PCG"] = fixed
+    try:
+        s = gpu.solver_for_case(case)
+    finally:
+        del os.environ["TPF_FIXED_PCG"]
+    s.init_droplet(case.center, case.semi_axes)
+    s.solver_stats(reset=True)
+    s.step(dt, 2)
+    st = s.solver_stats()
+    assert st["solves"] == 8
+    assert st["outer"] == 8 * outer and st["inner"] == 8 * inner
+    a, ua, _ = s.get_state()
+    b, ub, _ = ref.get_state()
+    assert np.abs(a - b).max() < 1e-6
+    umax = max(np.abs(x).max() for x in ub)
+    assert max(np.abs(x - y).max() for x, y in zip(ua, ub)) < 0.05 * umax
