@@ -266,6 +266,14 @@ static void init_geometry(tpf_ctx* c, const tpf_params* P) {
     c->fixed_outer = c->fixed_inner = 0;
     if (fx && std::sscanf(fx, "%d,%d", &c->fixed_outer, &c->fixed_inner) != 2) c->fixed_outer = c->fixed_inner = 0;
     if (c->fixed_outer < 1 || c->fixed_inner < 1) c->fixed_outer = c->fixed_inner = 0;
+    // LDS-staged phase/momentum pass: on by default for FP32 state (its FP64
+    // form needs 104 KB of LDS and runs one block per CU); TPF_STAGE_LDS=0|1
+    // overrides
+    const char* sl = std::getenv("TPF_STAGE_LDS");
+    c->stage_lds = sl ? (sl[0] == '1' ? 1 : 0) : (P->precision == TPF_FP32_MIXED ? 1 : 0);
+    const char* slk = std::getenv("TPF_STAGE_LDS_KZ");
+    c->stage_lds_kz = slk ? std::atoi(slk) : 32;
+    c->stage_lds_kz = std::min(std::max(c->stage_lds_kz, 1), 256);
     const char* xt = std::getenv("TPF_XCD_TILES");
     g_xcd_tiles = (xt && xt[0] == '0') ? 0 : 1;
     c->nlev = plan_levels(c);

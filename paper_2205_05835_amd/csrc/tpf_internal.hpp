@@ -166,6 +166,8 @@ struct tpf_ctx {
     int pred_iters[4];
     int kz_override;     // planes per block of the z-marching kernels (0: automatic)
     int stage_kz;        // planes per block of the z-chunked stage kernels
+    int stage_lds;       // 3D phase/momentum pass with its neighbourhoods staged in LDS
+    int stage_lds_kz;    // planes per block of that pass
     double mg_alpha;     // weight of the multigrid coarse-grid correction
     int coarse_sweeps_per_cell;   // coarsest-grid Jacobi sweeps per cell of its largest dimension (0: 2)
     // measurement mode with a fixed amount of solver work per pressure solve

@@ -63,6 +63,115 @@ __global__ __launch_bounds__(BLOCK) void k_phase_momentum(
     });
 }
 
+// The same pass with the neighbourhoods staged in LDS (3D).  A block owns a
+// BX x BY column piece of kz planes.  It keeps a ring of three z planes
+// (k - 1, k, k + 1) of every field it reads neighbours of (phi, u, m, mu or
+// kappa, and r for CDI), each plane its BX x BY tile plus a one-cell halo, and
+// copies one new plane per step from HBM with coalesced loads; every stencil
+// point, diagonals included, is then read from LDS.  One global load per
+// field and cell (plus halo and the two extra planes of the ring) instead of
+// one per stencil point.
+template <typename T>
+using Tile = T[BY + 2][BX + 2];
+
+template <typename T, unsigned MASK>
+struct LAcc {
+    const Cell& C;
+    const T* p[F_NF];
+    const Tile<T>* t[3];   // planes k - 1, k, k + 1; t[z][slot(f)]
+    int lx, ly;            // this cell in the tile (halo offset 1)
+    static constexpr bool staged(int f) { return (MASK >> f) & 1u; }
+    static constexpr int slot(int f) { return __builtin_popcount(MASK & ((1u << f) - 1u)); }
+    __device__ __forceinline__ T c(int f) const { return staged(f) ? t[1][slot(f)][ly][lx] : ld(p[f], C.id); }
+    __device__ __forceinline__ T nb(int f, int a, int s) const {
+        if (!staged(f)) return ld(p[f], C.off(a, s));
+        return t[1 + (a == 2 ? s : 0)][slot(f)][ly + (a == 1 ? s : 0)][lx + (a == 0 ? s : 0)];
+    }
+    __device__ __forceinline__ T nb2(int f, int a, int s, int b, int u) const {
+        if (!staged(f)) return ld(p[f], C.off2(a, s, b, u));
+        return t[1 + (a == 2 ? s : 0) + (b == 2 ? u : 0)][slot(f)][ly + (a == 1 ? s : 0) + (b == 1 ? u : 0)]
+                [lx + (a == 0 ? s : 0) + (b == 0 ? u : 0)];
+    }
+};
+
+template <typename T, bool CDI, bool EB>
+__global__ __launch_bounds__(BLOCK) void k_phase_momentum_lds(
+    Dims d, int kz, Phys P, RKArgs rk, const T* __restrict__ phi, const T* __restrict__ u0,
+    const T* __restrict__ u1, const T* __restrict__ u2, const T* __restrict__ r0,
+    const T* __restrict__ r1, const T* __restrict__ r2, const T* __restrict__ kappa,
+    const T* __restrict__ yn, T* __restrict__ acc, T* __restrict__ ynext, int* __restrict__ flags,
+    const T* __restrict__ m0, const T* __restrict__ m1, const T* __restrict__ m2,
+    const T* __restrict__ mu, T* __restrict__ f0, T* __restrict__ f1, T* __restrict__ f2,
+    T* __restrict__ F0, T* __restrict__ F1, T* __restrict__ F2) {
+    constexpr unsigned MASK = (1u << F_PHI) | (7u << F_U0) | (7u << F_M0) | (EB ? (1u << F_MU) : (1u << F_KAP)) |
+                              (CDI ? (7u << F_R0) : 0u);
+    constexpr int NS = __builtin_popcount(MASK);
+    using A_t = LAcc<T, MASK>;
+    __shared__ Tile<T> ring[3][NS];
+    int bx, by, bz;
+    if (!block_tile(d.xcd, (d.nx + BX - 1) / BX, (d.ny + BY - 1) / BY, (d.nz + kz - 1) / kz, bx, by, bz)) return;
+    const int tid = threadIdx.y * BX + threadIdx.x;
+    const int i = bx * BX + threadIdx.x, j = by * BY + threadIdx.y;
+    const bool valid = i < d.nx && j < d.ny;
+    const int k0 = bz * kz, k1 = min(d.nz, k0 + kz);
+    const T* p[F_NF] = {phi, u0, u1, u2, m0, m1, m2, mu, kappa, r0, r1, r2};
+    // Each thread copies tile positions tid and tid + BLOCK (when inside the
+    // (BX + 2) x (BY + 2) tile).  Positions are periodic; for a ragged tile
+    // the positions past the grid land on the periodic neighbours of its last
+    // valid cells.
+    constexpr int TP = (BX + 2) * (BY + 2);
+    unsigned pos[2];
+    int py[2], px[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int e = min(tid + h * BLOCK, TP - 1);
+        py[h] = e / (BX + 2);
+        px[h] = e - py[h] * (BX + 2);
+        const int gi = (bx * BX + px[h] - 1 + d.nx) % d.nx;
+        const int gj = (by * BY + py[h] - 1 + d.ny) % d.ny;
+        pos[h] = (unsigned)(gj * d.nx + gi);
+    }
+    const bool second = tid + BLOCK < TP;
+    const unsigned plane = (unsigned)(d.nx * d.ny);
+    T pre[2][NS];
+    // load plane q (periodic in z) into registers / store them to ring slot r
+    auto load = [&](int q) {
+        const unsigned base = (unsigned)((q + d.nz) % d.nz) * plane;
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int f = 0; f < F_NF; ++f)
+                if ((MASK >> f) & 1u) pre[h][A_t::slot(f)] = ld(p[f], base + pos[h]);
+    };
+    auto store = [&](int r) {
+#pragma unroll
+        for (int f = 0; f < F_NF; ++f)
+            if ((MASK >> f) & 1u) {
+                ring[r][A_t::slot(f)][py[0]][px[0]] = pre[0][A_t::slot(f)];
+                if (second) ring[r][A_t::slot(f)][py[1]][px[1]] = pre[1][A_t::slot(f)];
+            }
+    };
+    load(k0 - 1);
+    store(0);
+    load(k0);
+    store(1);
+    load(k0 + 1);
+    for (int k = k0; k < k1; ++k) {
+        const int rm = (k - k0) % 3, rc = (k - k0 + 1) % 3, rp = (k - k0 + 2) % 3;
+        store(rp);                 // plane k + 1, into the slot plane k - 2 used
+        __syncthreads();
+        if (k + 1 < k1) load(k + 2);   // in flight while plane k is computed
+        if (valid) {
+            const Cell C = make_cell(d, i, j, k);
+            const A_t A{C, {phi, u0, u1, u2, m0, m1, m2, mu, kappa, r0, r1, r2}, {ring[rm], ring[rc], ring[rp]},
+                        (int)threadIdx.x + 1, (int)threadIdx.y + 1};
+            op_phase_g<T, 3>(P, rk, C, A, yn, acc, ynext, flags);
+            op_momentum_g<T, 3>(P, C, A, f0, f1, f2, F0, F1, F2);
+        }
+        __syncthreads();           // plane k - 1's slot is free for plane k + 2
+    }
+}
+
 // b = D f* in FP64, plus the block sums of b (for the mean)
 template <typename T, int DIM>
 __global__ __launch_bounds__(BLOCK) void k_div(Dims d, Phys P, const T* __restrict__ f0,
@@ -241,6 +350,21 @@ static hipError_t phase_mom_impl(tpf_ctx* c, const void* phi_s, const void* cons
     // phi and u once; r (CDI) or kappa, phase history; m, mu or kappa; f* out
     const double phase = 1 + (cdi ? DIM : 1) + (rk.eval_only ? 1 : 3 + (rk.stage < 3));
     prof_begin(c, PC_MOM, (double)c->N * c->tsz * (1 + DIM + phase - 1 + DIM + 1 + DIM));
+    if (DIM == 3 && c->stage_lds) {
+        const int lkz = c->stage_lds_kz;
+        const dim3 lg = zchunk_grid(c->n, lkz);
+        const bool eb = c->P.force == TPF_EB;
+        auto kern = cdi ? (eb ? k_phase_momentum_lds<T, true, true> : k_phase_momentum_lds<T, true, false>)
+                        : (eb ? k_phase_momentum_lds<T, false, true> : k_phase_momentum_lds<T, false, false>);
+        kern<<<lg, b, 0, c->stream>>>(
+            dims_of(c->n), lkz, P, rk, ctp<T>(phi_s), ctp<T>(u_s[0]), ctp<T>(u_s[1]), ctp<T>(u_s[2]),
+            ctp<T>(c->rflux[0]), ctp<T>(c->rflux[1]), ctp<T>(c->rflux[2]), ctp<T>(c->kappa), yn, acc, tp<T>(out),
+            c->flags, ctp<T>(c->mflux[0]), ctp<T>(c->mflux[1]), ctp<T>(c->mflux[2]), ctp<T>(c->mu),
+            tp<T>(c->fs[0]), tp<T>(c->fs[1]), tp<T>(c->fs[2]), want_force ? tp<T>(c->force[0]) : nullptr,
+            tp<T>(c->force[1]), tp<T>(c->force[2]));
+        prof_end(c);
+        return hipGetLastError();
+    }
     k_phase_momentum<T, DIM><<<g, b, 0, c->stream>>>(
         dims_of(c->n), kz, P, rk, ctp<T>(phi_s), ctp<T>(u_s[0]), ctp<T>(u_s[1]), ctp<T>(u_s[2]),
         ctp<T>(c->rflux[0]), ctp<T>(c->rflux[1]), ctp<T>(c->rflux[2]), ctp<T>(c->kappa), yn, acc, tp<T>(out),

@@ -108,32 +108,42 @@ __device__ __forceinline__ void op_face(const Phys& P, const Cell& C, const T* _
     }
 }
 
+// ------------------------------------------------------------------ field access
+// The phase and momentum bodies read their neighbour values through an
+// accessor: G (global memory, a Cell's periodic offsets) here, or one that
+// serves the in-plane neighbours of a z-plane from an LDS tile.  f is one of
+// the field ids below; a, b are axes and s, t in {-1, +1}.
+enum { F_PHI = 0, F_U0, F_U1, F_U2, F_M0, F_M1, F_M2, F_MU, F_KAP, F_R0, F_R1, F_R2, F_NF };
+
+template <typename T>
+struct GAcc {
+    const Cell& C;
+    const T* p[F_NF];
+    __device__ __forceinline__ T c(int f) const { return ld(p[f], C.id); }
+    __device__ __forceinline__ T nb(int f, int a, int s) const { return ld(p[f], C.off(a, s)); }
+    __device__ __forceinline__ T nb2(int f, int a, int s, int b, int t) const {
+        return ld(p[f], C.off2(a, s, b, t));
+    }
+};
+
 // ------------------------------------------------------------------ phase field
 // dphi/dt = -D(u A phi) + g   (Eq. 1), g of Table 1; then the RK4 update.
-template <typename T, int DIM>
-__device__ __forceinline__ void op_phase(const Phys& P, const RKArgs& rk, const Cell& C,
-                                                 const T* __restrict__ phi,
-                                                 const T* __restrict__ u0, const T* __restrict__ u1,
-                                                 const T* __restrict__ u2, const T* __restrict__ r0,
-                                                 const T* __restrict__ r1, const T* __restrict__ r2,
-                                                 const T* __restrict__ kappa,
-                                                 const T* __restrict__ yn, T* __restrict__ acc,
-                                                 T* __restrict__ ynext, int* __restrict__ flags) {
-    const T* u[3] = {u0, u1, u2};
-    const T* r[3] = {r0, r1, r2};
+template <typename T, int DIM, typename Acc>
+__device__ __forceinline__ void op_phase_g(const Phys& P, const RKArgs& rk, const Cell& C, const Acc& G,
+                                           const T* __restrict__ yn, T* __restrict__ acc,
+                                           T* __restrict__ ynext, int* __restrict__ flags) {
     const unsigned c = C.id;
-    const T f = ld(phi, c);
+    const T f = G.c(F_PHI);
     const T ih = T(P.inv_h);
     T adv = T(0), g = T(0), lap = T(0), gg = T(0);
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-        const unsigned cp = C.off(a, 1), cm = C.off(a, -1);
-        const T fp = ld(phi, cp), fm = ld(phi, cm);
-        const T jhi = ld(u[a], cp) * (T(0.5) * (f + fp));
-        const T jlo = ld(u[a], c) * (T(0.5) * (fm + f));
+        const T fp = G.nb(F_PHI, a, 1), fm = G.nb(F_PHI, a, -1);
+        const T jhi = G.nb(F_U0 + a, a, 1) * (T(0.5) * (f + fp));
+        const T jlo = G.c(F_U0 + a) * (T(0.5) * (fm + f));
         adv += (jhi - jlo) * ih;
         if (P.model == MODEL_CDI) {
-            g += (ld(r[a], cp) - ld(r[a], c)) * ih;
+            g += (G.nb(F_R0 + a, a, 1) - G.c(F_R0 + a)) * ih;
         } else {
             lap += ((fp - f) * ih - (f - fm) * ih) * ih;
             const T ga = (fp - fm) * T(0.5 * P.inv_h);
@@ -142,8 +152,8 @@ __device__ __forceinline__ void op_phase(const Phys& P, const RKArgs& rk, const 
     }
     if (P.model != MODEL_CDI) {
         const T base = T(P.eps) * lap - dpsi(f) / T(P.eps);
-        const T curv = (P.model == MODEL_SB) ? T(P.eps) * sqrt(gg) * ld(kappa, c)
-                                             : f * (T(1) - f) * ld(kappa, c);
+        const T curv = (P.model == MODEL_SB) ? T(P.eps) * sqrt(gg) * G.c(F_KAP)
+                                             : f * (T(1) - f) * G.c(F_KAP);
         g = T(P.gamma) * (base + curv);
     }
     const T k = -adv + g;
@@ -158,6 +168,19 @@ __device__ __forceinline__ void op_phase(const Phys& P, const RKArgs& rk, const 
     else if (!isfinite(a_new)) flags[0] = 1;
 }
 
+template <typename T, int DIM>
+__device__ __forceinline__ void op_phase(const Phys& P, const RKArgs& rk, const Cell& C,
+                                                 const T* __restrict__ phi,
+                                                 const T* __restrict__ u0, const T* __restrict__ u1,
+                                                 const T* __restrict__ u2, const T* __restrict__ r0,
+                                                 const T* __restrict__ r1, const T* __restrict__ r2,
+                                                 const T* __restrict__ kappa,
+                                                 const T* __restrict__ yn, T* __restrict__ acc,
+                                                 T* __restrict__ ynext, int* __restrict__ flags) {
+    const GAcc<T> G{C, {phi, u0, u1, u2, nullptr, nullptr, nullptr, nullptr, kappa, r0, r1, r2}};
+    op_phase_g<T, DIM>(P, rk, C, G, yn, acc, ynext, flags);
+}
+
 // ------------------------------------------------------------------ momentum
 // f*_a = (-N_a + V_a + F_a) / rho_a on face (c, a).
 //   N_a: velocity form of div(m (x) u) with arithmetic-mean fluxes on the u_a
@@ -167,71 +190,74 @@ __device__ __forceinline__ void op_phase(const Phys& P, const RKArgs& rk, const 
 //   F_a: surface tension -- EB: A_a(mu) G_a phi (Eq. 4, + sign on the RHS);
 //        CSF: sigma A_a(kappa) G_a phi;  LCSF: sigma_hat A_a(kappa)
 //        A_a(phi(1-phi)) G_a phi (Eq. 11)
-template <typename T, int DIM>
-__device__ __forceinline__ void op_momentum(const Phys& P, const Cell& C, const T* __restrict__ phi, const T* __restrict__ u0,
-    const T* __restrict__ u1, const T* __restrict__ u2, const T* __restrict__ m0,
-    const T* __restrict__ m1, const T* __restrict__ m2, const T* __restrict__ mu,
-    const T* __restrict__ kappa, T* __restrict__ f0, T* __restrict__ f1, T* __restrict__ f2,
-    T* __restrict__ F0, T* __restrict__ F1, T* __restrict__ F2) {
-    const T* u[3] = {u0, u1, u2};
-    const T* m[3] = {m0, m1, m2};
+template <typename T, int DIM, typename Acc>
+__device__ __forceinline__ void op_momentum_g(const Phys& P, const Cell& C, const Acc& G, T* __restrict__ f0,
+                                              T* __restrict__ f1, T* __restrict__ f2, T* __restrict__ F0,
+                                              T* __restrict__ F1, T* __restrict__ F2) {
     T* fs[3] = {f0, f1, f2};
     T* Fo[3] = {F0, F1, F2};
     const unsigned c = C.id;
     const T ih = T(P.inv_h);
     const T v2 = T(P.visc2), dv = T(P.visc1 - P.visc2);
-    const T f = ld(phi, c);
+    const T f = G.c(F_PHI);
     const T clc = clamp01(P, f);
-    auto cl = [&](unsigned q) { return clamp01(P, ld(phi, q)); };
     // h D m at c, shared by the faces of c
     T dmc = T(0);
 #pragma unroll
-    for (int b = 0; b < DIM; ++b) dmc += ld(m[b], C.off(b, 1)) - ld(m[b], c);
+    for (int b = 0; b < DIM; ++b) dmc += G.nb(F_M0 + b, b, 1) - G.c(F_M0 + b);
     // The sums below are the terms of N_a, V_a and F_a with the factors 1/2,
     // 1/4 and 1/h of the averages and differences taken out: N_a = Nh / h,
     // V_a = Vh2 / h^2, F_a = Fh / h.
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-        const unsigned cp = C.off(a, 1), cm = C.off(a, -1);
-        const T fm = ld(phi, cm);
+        const T fm = G.nb(F_PHI, a, -1);
         const T clm = clamp01(P, fm);
-        const T uac = ld(u[a], c), uap = ld(u[a], cp), uam = ld(u[a], cm);
+        const T uac = G.c(F_U0 + a), uap = G.nb(F_U0 + a, a, 1), uam = G.nb(F_U0 + a, a, -1);
         // ---- advection: fluxes are products of two-point sums (x 1/4)
-        T adv4 = (ld(m[a], c) + ld(m[a], cp)) * (uac + uap) - (ld(m[a], cm) + ld(m[a], c)) * (uam + uac);
-        T dmm = ld(m[a], c) - ld(m[a], cm);      // h D m at c - e_a
+        const T mac = G.c(F_M0 + a), mam = G.nb(F_M0 + a, a, -1);
+        T adv4 = (mac + G.nb(F_M0 + a, a, 1)) * (uac + uap) - (mam + mac) * (uam + uac);
+        T dmm = mac - mam;      // h D m at c - e_a
         // ---- viscous stress (x 1/h^2); edge viscosity v2 + dv/4 (sum of four clamped phi)
         T vh2 = T(2) * ((v2 + dv * clc) * (uap - uac) - (v2 + dv * clm) * (uac - uam));
 #pragma unroll
         for (int b = 0; b < DIM; ++b) {
             if (b == a) continue;
-            const unsigned cpb = C.off(b, 1), cmb = C.off(b, -1);
-            const unsigned cmapb = C.off2(a, -1, b, 1), cmamb = C.off2(a, -1, b, -1);
-            const T uapb = ld(u[a], cpb), uamb = ld(u[a], cmb);
-            const T mbc = ld(m[b], c), mbm = ld(m[b], cm), mbmp = ld(m[b], cmapb);
-            adv4 += (ld(m[b], cpb) + mbmp) * (uac + uapb) - (mbc + mbm) * (uamb + uac);
+            const T uapb = G.nb(F_U0 + a, b, 1), uamb = G.nb(F_U0 + a, b, -1);
+            const T mbc = G.c(F_M0 + b), mbm = G.nb(F_M0 + b, a, -1), mbmp = G.nb2(F_M0 + b, a, -1, b, 1);
+            adv4 += (G.nb(F_M0 + b, b, 1) + mbmp) * (uac + uapb) - (mbc + mbm) * (uamb + uac);
             dmm += mbmp - mbm;
             const T cc = clc + clm;
-            const T e_hi = v2 + T(0.25) * dv * (cc + cl(cpb) + cl(cmapb));
-            const T e_lo = v2 + T(0.25) * dv * (cc + cl(cmb) + cl(cmamb));
-            vh2 += e_hi * ((uapb - uac) + (ld(u[b], cpb) - ld(u[b], cmapb))) -
-                   e_lo * ((uac - uamb) + (ld(u[b], c) - ld(u[b], cm)));
+            const T e_hi = v2 + T(0.25) * dv * (cc + clamp01(P, G.nb(F_PHI, b, 1)) + clamp01(P, G.nb2(F_PHI, a, -1, b, 1)));
+            const T e_lo = v2 + T(0.25) * dv * (cc + clamp01(P, G.nb(F_PHI, b, -1)) + clamp01(P, G.nb2(F_PHI, a, -1, b, -1)));
+            vh2 += e_hi * ((uapb - uac) + (G.nb(F_U0 + b, b, 1) - G.nb2(F_U0 + b, a, -1, b, 1))) -
+                   e_lo * ((uac - uamb) + (G.c(F_U0 + b) - G.nb(F_U0 + b, a, -1)));
         }
         const T nh = T(0.25) * adv4 - T(0.5) * uac * (dmm + dmc);
         // ---- surface tension (x 1/h)
         const T gh = f - fm;
         T fh;
         if (P.force == FORCE_EB) {
-            fh = T(0.5) * (ld(mu, cm) + ld(mu, c)) * gh;
+            fh = T(0.5) * (G.nb(F_MU, a, -1) + G.c(F_MU)) * gh;
         } else if (P.force == FORCE_CSF) {
-            fh = T(0.5 * P.sigma) * (ld(kappa, cm) + ld(kappa, c)) * gh;
+            fh = T(0.5 * P.sigma) * (G.nb(F_KAP, a, -1) + G.c(F_KAP)) * gh;
         } else {
-            fh = T(0.25 * P.sigma_hat) * (ld(kappa, cm) + ld(kappa, c)) *
+            fh = T(0.25 * P.sigma_hat) * (G.nb(F_KAP, a, -1) + G.c(F_KAP)) *
                  (fm * (T(1) - fm) + f * (T(1) - f)) * gh;
         }
         if (Fo[0]) st(Fo[a], c, fh * ih);
         const T rho_f = T(P.rho2) + T(0.5 * (P.rho1 - P.rho2)) * (clm + clc);
         st(fs[a], c, ((fh - nh) * ih + vh2 * (ih * ih)) / rho_f);
     }
+}
+
+template <typename T, int DIM>
+__device__ __forceinline__ void op_momentum(const Phys& P, const Cell& C, const T* __restrict__ phi, const T* __restrict__ u0,
+    const T* __restrict__ u1, const T* __restrict__ u2, const T* __restrict__ m0,
+    const T* __restrict__ m1, const T* __restrict__ m2, const T* __restrict__ mu,
+    const T* __restrict__ kappa, T* __restrict__ f0, T* __restrict__ f1, T* __restrict__ f2,
+    T* __restrict__ F0, T* __restrict__ F1, T* __restrict__ F2) {
+    const GAcc<T> G{C, {phi, u0, u1, u2, m0, m1, m2, mu, kappa, nullptr, nullptr, nullptr}};
+    op_momentum_g<T, DIM>(P, C, G, f0, f1, f2, F0, F1, F2);
 }
 
 // ------------------------------------------------------------------ D f* (FP64)

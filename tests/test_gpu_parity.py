@@ -121,6 +121,31 @@ def test_stage_fields_fp64(gpu, ora, dim, model, force):
         assert e < TOL64, (name, e)
 
 
+@pytest.mark.parametrize("model,force", [("CDI", "EB"), ("CDI", "CSF"), ("SB", "EB"), ("ISODI", "LCSF")])
+@pytest.mark.parametrize("n", [(24, 16, 20), (70, 12, 40)])
+def test_stage_fields_fp64_lds_pass(gpu, ora, model, force, n):
+    """The 3D phase/momentum pass with its neighbourhoods staged in LDS (the
+    FP32 default; forced here on FP64 contexts, TPF_STAGE_LDS=1) gives the
+    oracle's dphi/dt and f* to the FP64 bound: one z chunk with a ragged x
+    tile, and two x tiles with two z chunks (32 + 8 planes)."""
+    import os
+    case = small_case(3, model, force, n=n, ratio=1000.0)
+    say(f"stage_fields LDS pass {case.name} {case.n}")
+    P = oparams(ora, case)
+    phi = ora.init_droplet(P, case.center, case.semi_axes)
+    u = workloads.random_velocity(P.shape, 4, amplitude=0.05)
+    os.environ["TPF_STAGE_LDS"] = "1"
+    try:
+        s = gpu.solver_for_case(case, poisson_rtol=1e-14)
+    finally:
+        del os.environ["TPF_STAGE_LDS"]
+    s.set_state(phi, u)
+    for name, fn in [("DPHI", lambda: ora.phase_rhs(P, phi, u))] + [
+            (f"FSTAR{a}", (lambda a=a: ora.fstar(P, phi, u)[a])) for a in range(3)]:
+        e = rel(s.eval_field(name), fn())
+        assert e < TOL64, (name, e)
+
+
 @pytest.mark.parametrize("dim", [2, 3])
 def test_pressure_and_projection_fp64(gpu, ora, dim):
     """a6-a7: projection pressure (zero mean) and projected du/dt."""
