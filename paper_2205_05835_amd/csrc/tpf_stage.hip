@@ -63,6 +63,120 @@ __global__ __launch_bounds__(BLOCK) void k_phase_momentum(
     });
 }
 
+// k_cell and k_face in one pass (3D), from a ring of three phi planes in LDS.
+// Per z plane k the block first forms the normals of its BX x BY tile and of
+// the cells one below it in x and y (the c - e_a a face needs) into a
+// two-plane LDS ring of n, then the face fluxes r (CDI) and m of its cells,
+// with n_a(c - e_z) from the ring's previous plane.  phi is read once per
+// cell (plus halo), n and mu are written once, and n is not read back.  The
+// arithmetic is that of op_cell and op_face.
+template <typename T, bool CDI, bool MU>
+__global__ __launch_bounds__(BLOCK) void k_cell_face_lds(
+    Dims d, int kz, Phys P, const T* __restrict__ phi, const T* __restrict__ u0, const T* __restrict__ u1,
+    const T* __restrict__ u2, T* __restrict__ n0, T* __restrict__ n1, T* __restrict__ n2, T* __restrict__ mu,
+    T* __restrict__ r0, T* __restrict__ r1, T* __restrict__ r2, T* __restrict__ m0, T* __restrict__ m1,
+    T* __restrict__ m2) {
+    constexpr int PX = BX + 3, PY = BY + 3;   // phi tile: tile x/y index X in [-2, BX] at column X + 2
+    constexpr int NX = BX + 1, NY = BY + 1;   // n tile: X in [-1, BX - 1] at column X + 1
+    __shared__ T fr[3][PY][PX];
+    __shared__ T nr[2][3][NY][NX];
+    int bx, by, bz;
+    if (!block_tile(d.xcd, (d.nx + BX - 1) / BX, (d.ny + BY - 1) / BY, (d.nz + kz - 1) / kz, bx, by, bz)) return;
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * BX + tx;
+    const int i = bx * BX + tx, j = by * BY + ty;
+    const bool valid = i < d.nx && j < d.ny;
+    const int k0 = bz * kz, k1 = min(d.nz, k0 + kz);
+    const unsigned plane = (unsigned)(d.nx * d.ny);
+    const T* u[3] = {u0, u1, u2};
+    T* nout[3] = {n0, n1, n2};
+    T* rout[3] = {r0, r1, r2};
+    T* mout[3] = {m0, m1, m2};
+    // phi plane q (periodic) into ring slot (q - k0 + 3) % 3; tile positions
+    // past the grid land on periodic neighbours of the last valid cells
+    auto stage = [&](int q) {
+        const unsigned base = (unsigned)((q + d.nz) % d.nz) * plane;
+        T(*dst)[PX] = fr[(q - k0 + 3) % 3];
+        for (int e = tid; e < PX * PY; e += BLOCK) {
+            const int py = e / PX, px = e - py * PX;
+            const int gi = (bx * BX + px - 2 + 2 * d.nx) % d.nx;
+            const int gj = (by * BY + py - 2 + 2 * d.ny) % d.ny;
+            dst[py][px] = ld(phi, base + (unsigned)(gj * d.nx + gi));
+        }
+    };
+    const T ih = T(P.inv_h), ih2 = T(0.5 * P.inv_h);
+    // normals of plane q (tile and the low halo) from ring planes q - 1, q, q + 1
+    auto normals = [&](int q) {
+        const T(*fm)[PX] = fr[(q - 1 - k0 + 3) % 3];
+        const T(*fc)[PX] = fr[(q - k0 + 3) % 3];
+        const T(*fp)[PX] = fr[(q + 1 - k0 + 3) % 3];
+        const int sl = (q - k0 + 2) % 2;
+        for (int e = tid; e < NX * NY; e += BLOCK) {
+            const int ny_ = e / NX, nx_ = e - ny_ * NX;
+            const int cx = nx_ + 1, cy = ny_ + 1;        // phi tile column / row of this cell
+            T g[3];
+            g[0] = (fc[cy][cx + 1] - fc[cy][cx - 1]) * ih2;
+            g[1] = (fc[cy + 1][cx] - fc[cy - 1][cx]) * ih2;
+            g[2] = (fp[cy][cx] - fm[cy][cx]) * ih2;
+            T gg = T(0);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) gg += g[a] * g[a];
+            const T inv = T(1) / sqrt(gg + T(P.delta2));
+#pragma unroll
+            for (int a = 0; a < 3; ++a) nr[sl][a][ny_][nx_] = g[a] * inv;
+        }
+    };
+    stage(k0 - 2);
+    stage(k0 - 1);
+    stage(k0);
+    __syncthreads();
+    normals(k0 - 1);
+    __syncthreads();
+    stage(k0 + 1);                      // into the slot of plane k0 - 2
+    for (int k = k0; k < k1; ++k) {
+        __syncthreads();                // phi planes k - 1, k, k + 1 are in the ring
+        normals(k);
+        __syncthreads();
+        if (valid) {
+            const T(*fm)[PX] = fr[(k - 1 - k0 + 3) % 3];
+            const T(*fc)[PX] = fr[(k - k0 + 3) % 3];
+            const T(*fp)[PX] = fr[(k + 1 - k0 + 3) % 3];
+            const int sc = (k - k0 + 2) % 2, sm = (k - 1 - k0 + 2) % 2;
+            const int cx = tx + 2, cy = ty + 2;         // phi tile
+            const int qx = tx + 1, qy = ty + 1;         // n tile
+            const unsigned c = (unsigned)k * plane + (unsigned)(j * d.nx + i);
+            const T f = fc[cy][cx];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) st(nout[a], c, nr[sc][a][qy][qx]);
+            if (MU) {
+                const T fxp = fc[cy][cx + 1], fxm = fc[cy][cx - 1], fyp = fc[cy + 1][cx], fym = fc[cy - 1][cx];
+                const T fzp = fp[cy][cx], fzm = fm[cy][cx];
+                T lap = T(0);
+                lap += ((fxp - f) * ih - (f - fxm) * ih) * ih;
+                lap += ((fyp - f) * ih - (f - fym) * ih) * ih;
+                lap += ((fzp - f) * ih - (f - fzm) * ih) * ih;
+                st(mu, c, T(P.sigma_hat / P.eps) * dpsi(f) - T(P.sigma_hat * P.eps) * lap);
+            }
+            const T drho = T(P.rho1 - P.rho2);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const T fm_ = a == 0 ? fc[cy][cx - 1] : (a == 1 ? fc[cy - 1][cx] : fm[cy][cx]);
+                const T rho_f = T(0.5) * (rho_of(P, fm_) + rho_of(P, f));
+                T ra = T(0);
+                if (CDI) {
+                    const T nam = a == 0 ? nr[sc][0][qy][qx - 1] : (a == 1 ? nr[sc][1][qy - 1][qx] : nr[sm][2][qy][qx]);
+                    const T wm = fm_ * (T(1) - fm_) * nam;
+                    const T wc = f * (T(1) - f) * nr[sc][a][qy][qx];
+                    ra = T(P.gamma) * (T(P.eps) * ((f - fm_) * T(P.inv_h)) - T(0.5) * (wm + wc));
+                    st(rout[a], c, ra);
+                }
+                st(mout[a], c, rho_f * ld(u[a], c) - drho * ra);
+            }
+        }
+        __syncthreads();                // plane k - 1's phi and n slots are free
+        if (k + 2 <= k1) stage(k + 2);  // into the slot of plane k - 1
+    }
+}
+
 // The same pass with the neighbourhoods staged in LDS (3D).  A block owns a
 // BX x BY column piece of kz planes.  It keeps a ring of three z planes
 // (k - 1, k, k + 1) of every field it reads neighbours of (phi, u, m, mu or
@@ -303,8 +417,38 @@ static hipError_t face_impl(tpf_ctx* c, const void* phi_s, const void* const u_s
     return hipGetLastError();
 }
 
+// the LDS form of k_cell + k_face, then k_kappa where kappa is needed (3D)
+template <typename T>
+static hipError_t cell_face_lds_impl(tpf_ctx* c, const void* phi_s, const void* const u_s[3]) {
+    const Phys P = phys_of(c);
+    const Dims d = dims_of(c->n);
+    const int lkz = c->stage_lds_kz;
+    const dim3 lg = zchunk_grid(c->n, lkz), b(BX, BY);
+    const bool cdi = c->P.model == MODEL_CDI, need_mu = c->P.force == FORCE_EB;
+    const bool need_kappa = !cdi || !need_mu;
+    prof_begin(c, PC_FACE, (double)c->N * c->tsz * (1 + 3 + 3 + (need_mu ? 1 : 0) + 3 * (cdi ? 2 : 1)));
+    auto kern = cdi ? (need_mu ? k_cell_face_lds<T, true, true> : k_cell_face_lds<T, true, false>)
+                    : (need_mu ? k_cell_face_lds<T, false, true> : k_cell_face_lds<T, false, false>);
+    kern<<<lg, b, 0, c->stream>>>(d, lkz, P, ctp<T>(phi_s), ctp<T>(u_s[0]), ctp<T>(u_s[1]), ctp<T>(u_s[2]),
+                                  tp<T>(c->nrm[0]), tp<T>(c->nrm[1]), tp<T>(c->nrm[2]), tp<T>(c->mu),
+                                  tp<T>(c->rflux[0]), tp<T>(c->rflux[1]), tp<T>(c->rflux[2]), tp<T>(c->mflux[0]),
+                                  tp<T>(c->mflux[1]), tp<T>(c->mflux[2]));
+    prof_end(c);
+    if (need_kappa) {
+        const int kz = c->stage_kz;
+        const dim3 g = zchunk_grid(c->n, kz);
+        prof_begin(c, PC_KAPPA, (double)c->N * c->tsz * 4);
+        k_kappa<T, 3><<<g, b, 0, c->stream>>>(d, kz, P, ctp<T>(c->nrm[0]), ctp<T>(c->nrm[1]), ctp<T>(c->nrm[2]),
+                                              tp<T>(c->kappa));
+        prof_end(c);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_stage_fields(tpf_ctx* c, const void* phi_s, const void* const u_s[3]) {
     hipError_t e;
+    if (c->dim == 3 && c->stage_lds)
+        return c->mixed ? cell_face_lds_impl<float>(c, phi_s, u_s) : cell_face_lds_impl<double>(c, phi_s, u_s);
     if (c->mixed) {
         e = c->dim == 2 ? stage_fields_impl<float, 2>(c, phi_s) : stage_fields_impl<float, 3>(c, phi_s);
         if (e != hipSuccess) return e;

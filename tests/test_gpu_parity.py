@@ -124,10 +124,11 @@ def test_stage_fields_fp64(gpu, ora, dim, model, force):
 @pytest.mark.parametrize("model,force", [("CDI", "EB"), ("CDI", "CSF"), ("SB", "EB"), ("ISODI", "LCSF")])
 @pytest.mark.parametrize("n", [(24, 16, 20), (70, 12, 40)])
 def test_stage_fields_fp64_lds_pass(gpu, ora, model, force, n):
-    """The 3D phase/momentum pass with its neighbourhoods staged in LDS (the
-    FP32 default; forced here on FP64 contexts, TPF_STAGE_LDS=1) gives the
-    oracle's dphi/dt and f* to the FP64 bound: one z chunk with a ragged x
-    tile, and two x tiles with two z chunks (32 + 8 planes)."""
+    """The 3D LDS passes (the FP32 default; forced here on FP64 contexts,
+    TPF_STAGE_LDS=1): normals, mu or kappa, CDI and mass fluxes from the
+    fused cell/face pass, dphi/dt and f* from the phase/momentum pass, to the
+    FP64 bound: one z chunk with a ragged x tile, and two x tiles with two z
+    chunks (32 + 8 planes)."""
     import os
     case = small_case(3, model, force, n=n, ratio=1000.0)
     say(f"stage_fields LDS pass {case.name} {case.n}")
@@ -140,8 +141,17 @@ def test_stage_fields_fp64_lds_pass(gpu, ora, model, force, n):
     finally:
         del os.environ["TPF_STAGE_LDS"]
     s.set_state(phi, u)
-    for name, fn in [("DPHI", lambda: ora.phase_rhs(P, phi, u))] + [
-            (f"FSTAR{a}", (lambda a=a: ora.fstar(P, phi, u)[a])) for a in range(3)]:
+    checks = [("DPHI", lambda: ora.phase_rhs(P, phi, u))]
+    checks += [(f"FSTAR{a}", (lambda a=a: ora.fstar(P, phi, u)[a])) for a in range(3)]
+    checks += [(f"NORMAL{a}", (lambda a=a: ora.normals(P, phi)[0][a])) for a in range(3)]
+    checks += [(f"MASSFLUX{a}", (lambda a=a: ora.mass_flux(P, phi, u)[a])) for a in range(3)]
+    if model == "CDI":
+        checks += [(f"CDIFLUX{a}", (lambda a=a: ora.cdi_flux(P, phi)[a])) for a in range(3)]
+    if force == "EB":
+        checks += [("MU", lambda: ora.chem_potential(P, phi))]
+    else:
+        checks += [("KAPPA", lambda: ora.curvature(P, phi))]
+    for name, fn in checks:
         e = rel(s.eval_field(name), fn())
         assert e < TOL64, (name, e)
 
