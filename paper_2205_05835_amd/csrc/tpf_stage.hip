@@ -188,23 +188,34 @@ __global__ __launch_bounds__(BLOCK) void k_cell_face_lds(
 template <typename T>
 using Tile = T[BY + 2][BX + 2];
 
-template <typename T, unsigned MASK>
+template <typename T, unsigned RMASK, unsigned OMASK>
 struct LAcc {
     const Cell& C;
     const T* p[F_NF];
-    const Tile<T>* t[3];   // planes k - 1, k, k + 1; t[z][slot(f)]
+    const Tile<T>* t[3];   // ring fields (RMASK), planes k - 1, k, k + 1: t[z][slot(f)]
+    const Tile<T>* t1;     // single-plane fields (OMASK), plane k: t1[slot1(f)]
     int lx, ly;            // this cell in the tile (halo offset 1)
-    static constexpr bool staged(int f) { return (MASK >> f) & 1u; }
-    static constexpr int slot(int f) { return __builtin_popcount(MASK & ((1u << f) - 1u)); }
-    __device__ __forceinline__ T c(int f) const { return staged(f) ? t[1][slot(f)][ly][lx] : ld(p[f], C.id); }
+    static constexpr bool ring(int f) { return (RMASK >> f) & 1u; }
+    static constexpr bool one(int f) { return (OMASK >> f) & 1u; }
+    static constexpr int slot(int f) { return __builtin_popcount(RMASK & ((1u << f) - 1u)); }
+    static constexpr int slot1(int f) { return __builtin_popcount(OMASK & ((1u << f) - 1u)); }
+    __device__ __forceinline__ T c(int f) const {
+        if (ring(f)) return t[1][slot(f)][ly][lx];
+        if (one(f)) return t1[slot1(f)][ly][lx];
+        return ld(p[f], C.id);
+    }
     __device__ __forceinline__ T nb(int f, int a, int s) const {
-        if (!staged(f)) return ld(p[f], C.off(a, s));
-        return t[1 + (a == 2 ? s : 0)][slot(f)][ly + (a == 1 ? s : 0)][lx + (a == 0 ? s : 0)];
+        if (ring(f)) return t[1 + (a == 2 ? s : 0)][slot(f)][ly + (a == 1 ? s : 0)][lx + (a == 0 ? s : 0)];
+        if (one(f) && a != 2) return t1[slot1(f)][ly + (a == 1 ? s : 0)][lx + (a == 0 ? s : 0)];
+        return ld(p[f], C.off(a, s));
     }
     __device__ __forceinline__ T nb2(int f, int a, int s, int b, int u) const {
-        if (!staged(f)) return ld(p[f], C.off2(a, s, b, u));
-        return t[1 + (a == 2 ? s : 0) + (b == 2 ? u : 0)][slot(f)][ly + (a == 1 ? s : 0) + (b == 1 ? u : 0)]
-                [lx + (a == 0 ? s : 0) + (b == 0 ? u : 0)];
+        if (ring(f))
+            return t[1 + (a == 2 ? s : 0) + (b == 2 ? u : 0)][slot(f)][ly + (a == 1 ? s : 0) + (b == 1 ? u : 0)]
+                    [lx + (a == 0 ? s : 0) + (b == 0 ? u : 0)];
+        if (one(f) && a != 2 && b != 2)
+            return t1[slot1(f)][ly + (a == 1 ? s : 0) + (b == 1 ? u : 0)][lx + (a == 0 ? s : 0) + (b == 0 ? u : 0)];
+        return ld(p[f], C.off2(a, s, b, u));
     }
 };
 
@@ -217,11 +228,15 @@ __global__ __launch_bounds__(BLOCK) void k_phase_momentum_lds(
     const T* __restrict__ m0, const T* __restrict__ m1, const T* __restrict__ m2,
     const T* __restrict__ mu, T* __restrict__ f0, T* __restrict__ f1, T* __restrict__ f2,
     T* __restrict__ F0, T* __restrict__ F1, T* __restrict__ F2) {
-    constexpr unsigned MASK = (1u << F_PHI) | (7u << F_U0) | (7u << F_M0) | (EB ? (1u << F_MU) : (1u << F_KAP)) |
-                              (CDI ? (7u << F_R0) : 0u);
-    constexpr int NS = __builtin_popcount(MASK);
-    using A_t = LAcc<T, MASK>;
+    // three-plane ring: the fields read at z neighbours and z diagonals;
+    // one plane: the fields read only in-plane (their c - e_z or c + e_z
+    // values come from memory)
+    constexpr unsigned RMASK = (1u << F_PHI) | (7u << F_U0) | (7u << F_M0);
+    constexpr unsigned OMASK = (EB ? (1u << F_MU) : (1u << F_KAP)) | (CDI ? ((1u << F_R0) | (1u << F_R1)) : 0u);
+    constexpr int NS = __builtin_popcount(RMASK), NS1 = __builtin_popcount(OMASK);
+    using A_t = LAcc<T, RMASK, OMASK>;
     __shared__ Tile<T> ring[3][NS];
+    __shared__ Tile<T> tile1[NS1];
     int bx, by, bz;
     if (!block_tile(d.xcd, (d.nx + BX - 1) / BX, (d.ny + BY - 1) / BY, (d.nz + kz - 1) / kz, bx, by, bz)) return;
     const int tid = threadIdx.y * BX + threadIdx.x;
@@ -247,42 +262,54 @@ __global__ __launch_bounds__(BLOCK) void k_phase_momentum_lds(
     }
     const bool second = tid + BLOCK < TP;
     const unsigned plane = (unsigned)(d.nx * d.ny);
-    T pre[2][NS];
-    // load plane q (periodic in z) into registers / store them to ring slot r
-    auto load = [&](int q) {
+    T pre[2][NS], pre1[2][NS1 > 0 ? NS1 : 1];
+    // ring fields of plane q and single-plane fields of plane q1 (periodic in
+    // z) into registers; stored to ring slot r and the single tile
+    auto load = [&](int q, int q1) {
         const unsigned base = (unsigned)((q + d.nz) % d.nz) * plane;
+        const unsigned base1 = (unsigned)((q1 + d.nz) % d.nz) * plane;
 #pragma unroll
         for (int h = 0; h < 2; ++h)
 #pragma unroll
-            for (int f = 0; f < F_NF; ++f)
-                if ((MASK >> f) & 1u) pre[h][A_t::slot(f)] = ld(p[f], base + pos[h]);
+            for (int f = 0; f < F_NF; ++f) {
+                if ((RMASK >> f) & 1u) pre[h][A_t::slot(f)] = ld(p[f], base + pos[h]);
+                if ((OMASK >> f) & 1u) pre1[h][A_t::slot1(f)] = ld(p[f], base1 + pos[h]);
+            }
     };
-    auto store = [&](int r) {
+    auto store = [&](int r, bool with1) {
 #pragma unroll
-        for (int f = 0; f < F_NF; ++f)
-            if ((MASK >> f) & 1u) {
+        for (int f = 0; f < F_NF; ++f) {
+            if ((RMASK >> f) & 1u) {
                 ring[r][A_t::slot(f)][py[0]][px[0]] = pre[0][A_t::slot(f)];
                 if (second) ring[r][A_t::slot(f)][py[1]][px[1]] = pre[1][A_t::slot(f)];
             }
+            if (with1 && ((OMASK >> f) & 1u)) {
+                tile1[A_t::slot1(f)][py[0]][px[0]] = pre1[0][A_t::slot1(f)];
+                if (second) tile1[A_t::slot1(f)][py[1]][px[1]] = pre1[1][A_t::slot1(f)];
+            }
+        }
     };
-    load(k0 - 1);
-    store(0);
-    load(k0);
-    store(1);
-    load(k0 + 1);
+    load(k0 - 1, k0);
+    store(0, false);
+    load(k0, k0);
+    store(1, true);
+    load(k0 + 1, k0 + 1);
     for (int k = k0; k < k1; ++k) {
         const int rm = (k - k0) % 3, rc = (k - k0 + 1) % 3, rp = (k - k0 + 2) % 3;
-        store(rp);                 // plane k + 1, into the slot plane k - 2 used
+        // ring plane k + 1 into the slot plane k - 2 used, and (after the
+        // first plane, whose single tile the prologue stored) the
+        // single-plane fields of plane k, both loaded one step earlier
+        store(rp, k > k0);
         __syncthreads();
-        if (k + 1 < k1) load(k + 2);   // in flight while plane k is computed
+        if (k + 1 < k1) load(k + 2, k + 1);   // in flight while plane k is computed
         if (valid) {
             const Cell C = make_cell(d, i, j, k);
             const A_t A{C, {phi, u0, u1, u2, m0, m1, m2, mu, kappa, r0, r1, r2}, {ring[rm], ring[rc], ring[rp]},
-                        (int)threadIdx.x + 1, (int)threadIdx.y + 1};
+                        tile1, (int)threadIdx.x + 1, (int)threadIdx.y + 1};
             op_phase_g<T, 3>(P, rk, C, A, yn, acc, ynext, flags);
             op_momentum_g<T, 3>(P, C, A, f0, f1, f2, F0, F1, F2);
         }
-        __syncthreads();           // plane k - 1's slot is free for plane k + 2
+        __syncthreads();           // plane k - 1's ring slot and the single tile are free
     }
 }
 
