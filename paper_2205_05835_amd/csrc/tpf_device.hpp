@@ -134,6 +134,16 @@ template <typename T>
 __device__ __forceinline__ void st(T* base, unsigned idx, T v) {
     *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (unsigned)(idx * (unsigned)sizeof(T))) = v;
 }
+// Streaming (nontemporal) store for full-grid outputs that the writing
+// launch never reads back.  Measured per kernel: it shortens the fine-level
+// solver passes and the phase/momentum update (their outputs no longer
+// displace the inputs still to be read from the caches), but slows the
+// kernels whose consumer re-reads the output at once from the memory-side
+// cache (the prolongation, the normals/chemical-potential pass), which keep st.
+template <typename T>
+__device__ __forceinline__ void stn(T* base, unsigned idx, T v) {
+    __builtin_nontemporal_store(v, reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (unsigned)(idx * (unsigned)sizeof(T))));
+}
 
 // median of three: clamp in one instruction
 __device__ __forceinline__ float med3(float a, float lo, float hi) { return __builtin_amdgcn_fmed3f(a, lo, hi); }

@@ -978,7 +978,7 @@ __global__ __launch_bounds__(BLOCK) void k_fz_jac(Dims d, int kz, S ih2, S omega
         const S az = apply7(bl, bh, X, ih2, dg);
         if (q.valid) {
             const S out = X.c + omega * (e.a - az) * recip(dg);
-            st(zt, c, out);
+            stn(zt, c, out);
             if (MODE == 2) {
                 v[0] += (double)e.a * (double)out;
                 v[1] += (double)e.b * (double)out;
@@ -1030,12 +1030,12 @@ __global__ __launch_bounds__(BLOCK) void k_fz_first(Dims d, int kz, S ih2, S ome
         if (q.valid) {
             S rn = e.r;
             if (UPD) {
-                st(x, c, X((double)e.x + alpha * (double)e.p));
+                stn(x, c, X((double)e.x + alpha * (double)e.p));
                 rn = S((double)rn - alpha * (double)e.q);
-                st(r, c, rn);
+                stn(r, c, rn);
                 acc += (double)rn * (double)rn;
             }
-            st(z, c, omega * rn * recip(dg));
+            stn(z, c, omega * rn * recip(dg));
         }
     });
     if (UPD) {
@@ -1069,8 +1069,8 @@ __global__ __launch_bounds__(BLOCK) void k_fz_apply(Dims d, int kz, S ih2, Coef 
         faces7(R, bl, bh);
         const S aq = apply7(bl, bh, X, ih2, dg);
         if (q.valid) {
-            st(pnew, c, X.c);
-            st(qv, c, aq);
+            stn(pnew, c, X.c);
+            stn(qv, c, aq);
             acc += (double)X.c * (double)aq;
         }
     });
@@ -1108,7 +1108,7 @@ __global__ __launch_bounds__(BLOCK) void k_fz_restrict(Dims d, Dims cd, int kz, 
             if (q.valid && (tx & 1) == 0 && (ty & 1) == 0) {
                 const S s = sh[ty][tx] + sh[ty + 1][tx];
                 const unsigned cc = ((unsigned)(k >> 1) * cd.ny + (q.j >> 1)) * cd.nx + (q.i >> 1);
-                st(rc, min(cc, cmax), s * rw);
+                stn(rc, min(cc, cmax), s * rw);
             }
             __syncthreads();
             pair = S(0);

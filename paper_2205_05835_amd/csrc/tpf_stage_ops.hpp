@@ -158,13 +158,13 @@ __device__ __forceinline__ void op_phase_g(const Phys& P, const RKArgs& rk, cons
     }
     const T k = -adv + g;
     if (rk.eval_only) {
-        st(ynext, c, k);
+        stn(ynext, c, k);
         return;
     }
     const T y0 = ld(yn, c);
     const T a_new = (rk.stage == 0 ? y0 : ld(acc, c)) + T(rk.wacc) * k;
-    st(acc, c, a_new);
-    if (rk.stage < 3) st(ynext, c, y0 + T(rk.wnext) * k);
+    stn(acc, c, a_new);
+    if (rk.stage < 3) stn(ynext, c, y0 + T(rk.wnext) * k);
     else if (!isfinite(a_new)) flags[0] = 1;
 }
 
@@ -244,9 +244,9 @@ __device__ __forceinline__ void op_momentum_g(const Phys& P, const Cell& C, cons
             fh = T(0.25 * P.sigma_hat) * (G.nb(F_KAP, a, -1) + G.c(F_KAP)) *
                  (fm * (T(1) - fm) + f * (T(1) - f)) * gh;
         }
-        if (Fo[0]) st(Fo[a], c, fh * ih);
+        if (Fo[0]) stn(Fo[a], c, fh * ih);
         const T rho_f = T(P.rho2) + T(0.5 * (P.rho1 - P.rho2)) * (clm + clc);
-        st(fs[a], c, ((fh - nh) * ih + vh2 * (ih * ih)) / rho_f);
+        stn(fs[a], c, ((fh - nh) * ih + vh2 * (ih * ih)) / rho_f);
     }
 }
 
@@ -299,13 +299,13 @@ __device__ __forceinline__ void op_project(const Phys& P, const RKArgs& rk, cons
         const double gp = (pc - ld(p, cm)) * P.inv_h;
         const T k = T((double)ld(fs[a], c) - gp / rho_f);
         if (rk.eval_only) {
-            st(nx[a], c, k);
+            stn(nx[a], c, k);
             continue;
         }
         const T y0 = ld(yn[a], c);
         const T a_new = (rk.stage == 0 ? y0 : ld(acc[a], c)) + T(rk.wacc) * k;
-        st(acc[a], c, a_new);
-        if (rk.stage < 3) st(nx[a], c, y0 + T(rk.wnext) * k);
+        stn(acc[a], c, a_new);
+        if (rk.stage < 3) stn(nx[a], c, y0 + T(rk.wnext) * k);
         else if (!isfinite(a_new)) flags[0] = 1;
     }
 }
