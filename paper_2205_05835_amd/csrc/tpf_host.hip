@@ -274,6 +274,11 @@ static void init_geometry(tpf_ctx* c, const tpf_params* P) {
     const char* slk = std::getenv("TPF_STAGE_LDS_KZ");
     c->stage_lds_kz = slk ? std::atoi(slk) : 32;
     c->stage_lds_kz = std::min(std::max(c->stage_lds_kz, 1), 256);
+    // fused coarse levels of the 3D V-cycle: on by default for FP32 solver
+    // levels (the FP64 tiles need 88 KB of LDS, one block per CU);
+    // TPF_COARSE_FUSED=0|1 overrides
+    const char* cfz = std::getenv("TPF_COARSE_FUSED");
+    c->coarse_fused = cfz ? (cfz[0] == '1' ? 1 : 0) : (P->precision == TPF_FP32_MIXED ? 1 : 0);
     const char* xt = std::getenv("TPF_XCD_TILES");
     g_xcd_tiles = (xt && xt[0] == '0') ? 0 : 1;
     c->nlev = plan_levels(c);

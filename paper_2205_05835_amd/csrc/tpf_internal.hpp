@@ -168,6 +168,7 @@ struct tpf_ctx {
     int stage_kz;        // planes per block of the z-chunked stage kernels
     int stage_lds;       // 3D phase/momentum pass with its neighbourhoods staged in LDS
     int stage_lds_kz;    // planes per block of that pass
+    int coarse_fused;    // 3D stored-coefficient levels: one fused launch down and one up
     double mg_alpha;     // weight of the multigrid coarse-grid correction
     int coarse_sweeps_per_cell;   // coarsest-grid Jacobi sweeps per cell of its largest dimension (0: 2)
     // measurement mode with a fixed amount of solver work per pressure solve
