@@ -1029,6 +1029,26 @@ __global__ void k_inner_setup(SolverScalars* sc, double tol2) {
     sc->done = sc->rr > 0.0 ? 0 : 1;
 }
 
+// The first inner solve's set-up without a host round trip: the inner
+// tolerance from the outer residual just finalized, by the rule of the mixed
+// solve (half the reduction the outer tolerance needs, clamped to [rin, 0.1];
+// 0 in the fixed-iteration mode).  An outer residual that already meets the
+// tolerance, or is not finite, leaves the inner solve done before it starts,
+// with iters = -1 and the outer ||f||^2, ||r||^2 kept for the host.
+__global__ void k_inner_setup_first(SolverScalars* sc, double rtol, double rin, int fixed) {
+    if (threadIdx.x != 0) return;
+    const double ff = sc->ff, rr = sc->rr;
+    if (sc->done || !isfinite(ff) || !isfinite(rr)) {
+        sc->done = 1;
+        sc->iters = -1;
+        return;
+    }
+    const double tin = fixed ? 0.0 : fmin(0.1, fmax(rin, 0.5 * rtol * sqrt(ff / rr)));
+    sc->ff = rr;
+    sc->tol2 = tin * tin;
+    sc->done = rr > 0.0 ? 0 : 1;
+}
+
 static hipError_t finalize3(tpf_ctx* c, int nb0, int nb1, int nb2, int op, double arg) {
     prof_begin(c, PC_FINALIZE, (double)(nb0 + nb1 + nb2) * 8);
     k_finalize<<<1, FIN_THREADS, 0, c->stream>>>(nb0, nb1, nb2, c->max_blocks, op, arg, c->N,
@@ -1779,7 +1799,7 @@ struct Solver {
     // Iterations launched after convergence exit at once; the profiler books
     // them as no-work launches.
     template <typename X>
-    hipError_t pcg(const void* phi, X* x, int maxit, int slot) {
+    hipError_t pcg(const void* phi, X* x, int maxit, int slot, SolverScalars* last, bool* have_last) {
         vcycle(phi, false);                                       // z = M r, <r,z>
         (void)finalize2(c, 0, (int)nb0(), FIN_RZ0, 0.0);
         int it = 0;
@@ -1803,17 +1823,22 @@ struct Solver {
             if (e != hipSuccess) return e;
             e = hipStreamSynchronize(c->stream);
             if (e != hipSuccess) return e;
+            *have_last = true;
             if (s.done) break;
         }
-        if (s.done && s.iters < it && s.iters >= 0) {
+        // iters = -1: done before the first iteration (k_inner_setup_first)
+        const int useful = s.iters < 0 ? 0 : s.iters;
+        if (s.done && useful < it) {
             ProfSnap now;
             snapshot(now);
             for (int q = 0; q < NPROF; ++q) {
-                c->prof_noop[q] += now.n[q] - snap_[s.iters].n[q];
-                c->prof_noop_bytes[q] += now.b[q] - snap_[s.iters].b[q];
+                c->prof_noop[q] += now.n[q] - snap_[useful].n[q];
+                c->prof_noop_bytes[q] += now.b[q] - snap_[useful].b[q];
             }
         }
-        if (s.done) c->pred_iters[slot] = s.iters;
+        if (s.done && s.iters >= 0) c->pred_iters[slot] = s.iters;
+        // nothing is launched after the last read: it holds the final scalars
+        *last = s;
         return hipGetLastError();
     }
     struct ProfSnap {
@@ -1916,10 +1941,13 @@ tpf_status poisson_solve(tpf_ctx* c, const void* phi, int* iters, double* relres
         sv.build_betas(phi);
         sv.residual<double>(sv.coef_fine(), tp<double>(c->lv[0].r));
         (void)finalize2(c, (int)sv.nb0(), (int)sv.nb0(), FIN_INIT, fixed ? 0.0 : rtol * rtol);
-        e = sv.pcg<double>(phi, c->p, fixed ? c->fixed_inner : maxit, 0);
+        bool have = false;
+        e = sv.pcg<double>(phi, c->p, fixed ? c->fixed_inner : maxit, 0, &s, &have);
         if (e != hipSuccess) return hip_fail(e, "FP64 PCG");
-        tpf_status st = read_scalars(c, &s);
-        if (st != TPF_OK) return st;
+        if (!have) {
+            tpf_status st = read_scalars(c, &s);
+            if (st != TPF_OK) return st;
+        }
         if (!std::isfinite(s.ff) || !std::isfinite(s.rr)) {
             set_error("non-finite pressure right-hand side or residual");
             return TPF_ENONFINITE;
@@ -1948,29 +1976,49 @@ tpf_status poisson_solve(tpf_ctx* c, const void* phi, int* iters, double* relres
     for (int o = 0; o < max_outer; ++o) {
         s64.residual<float>(s64.coef_phi(phi), tp<float>(c->lv[0].r));   // FP64 residual, FP64 beta
         (void)finalize2(c, (int)s64.nb0(), (int)s64.nb0(), FIN_INIT, fixed ? 0.0 : rtol * rtol);
-        tpf_status st = read_scalars(c, &s);
-        if (st != TPF_OK) return st;
-        if (!std::isfinite(s.ff) || !std::isfinite(s.rr)) {
-            set_error("non-finite pressure right-hand side or residual");
-            return TPF_ENONFINITE;
+        // the inner solve aims straight at the outer tolerance (half of the
+        // reduction it needs), but never below rin, the depth an FP32 PCG
+        // reaches reliably; a further outer pass picks up the rest.  The
+        // first pass (a converged start is rare) sets this up on the device
+        // and reads the outer residual with the inner solve's scalars; later
+        // passes read it first, to stop without another inner solve.
+        if (o == 0) {
+            k_inner_setup_first<<<1, 64, 0, c->stream>>>(c->scal, rtol, rin, fixed ? 1 : 0);
+        } else {
+            tpf_status st = read_scalars(c, &s);
+            if (st != TPF_OK) return st;
+            if (!std::isfinite(s.ff) || !std::isfinite(s.rr)) {
+                set_error("non-finite pressure right-hand side or residual");
+                return TPF_ENONFINITE;
+            }
+            if (s.done || (fixed && o == c->fixed_outer)) {
+                *outer = o;
+                *iters = total;
+                *relres = s.ff > 0 ? std::sqrt(s.rr / s.ff) : 0.0;
+                return TPF_OK;
+            }
+            const double need = 0.5 * rtol * std::sqrt(s.ff / s.rr);
+            const double tin = fixed ? 0.0 : std::min(0.1, std::max(rin, need));
+            k_inner_setup<<<1, 64, 0, c->stream>>>(c->scal, tin * tin);
         }
-        if (s.done || (fixed && o == c->fixed_outer)) {
-            *outer = o;
-            *iters = total;
+        k_fill_s<float><<<vgrid(c->N), BLOCK, 0, c->stream>>>(c->N, tp<float>(c->ev), 0.0f);
+        bool have = false;
+        e = sv.pcg<float>(phi, tp<float>(c->ev), fixed ? c->fixed_inner : maxit, 1 + std::min(o, 2), &s, &have);
+        if (e != hipSuccess) return hip_fail(e, "FP32 inner PCG");
+        if (!have) {
+            tpf_status st = read_scalars(c, &s);
+            if (st != TPF_OK) return st;
+        }
+        if (s.iters < 0) {                 // decided by the outer residual of pass 0
+            if (!std::isfinite(s.ff) || !std::isfinite(s.rr)) {
+                set_error("non-finite pressure right-hand side or residual");
+                return TPF_ENONFINITE;
+            }
+            *outer = 0;
+            *iters = 0;
             *relres = s.ff > 0 ? std::sqrt(s.rr / s.ff) : 0.0;
             return TPF_OK;
         }
-        // the inner solve aims straight at the outer tolerance (half of the
-        // reduction it needs), but never below rin, the depth an FP32 PCG
-        // reaches reliably; a further outer pass picks up the rest
-        const double need = 0.5 * rtol * std::sqrt(s.ff / s.rr);
-        const double tin = fixed ? 0.0 : std::min(0.1, std::max(rin, need));
-        k_inner_setup<<<1, 64, 0, c->stream>>>(c->scal, tin * tin);
-        k_fill_s<float><<<vgrid(c->N), BLOCK, 0, c->stream>>>(c->N, tp<float>(c->ev), 0.0f);
-        e = sv.pcg<float>(phi, tp<float>(c->ev), fixed ? c->fixed_inner : maxit, 1 + std::min(o, 2));
-        if (e != hipSuccess) return hip_fail(e, "FP32 inner PCG");
-        st = read_scalars(c, &s);
-        if (st != TPF_OK) return st;
         total += s.iters;
         // an inner solve stopped by maxit (FP32 stagnation) still lowers the
         // A-norm error: its correction is applied and the outer loop goes on
