@@ -21,7 +21,9 @@
  *   The caller owns all device memory.  tpf_workspace_bytes() sizes one
  *   device buffer that the caller allocates and passes to tpf_create(); the
  *   library carves every field, multigrid level and reduction scratch out of
- *   it and never allocates device memory itself.  All work is issued on the
+ *   it and never allocates device memory itself (each context holds one
+ *   small pinned host buffer, through which the kernels hand the solver's
+ *   convergence scalars to the host).  All work is issued on the
  *   hip_stream given at creation (NULL = the legacy default stream).
  *   Host-side arrays passed to set/get functions are read or written before
  *   the call returns and are never retained.  Arrays exchanged across the ABI

@@ -344,6 +344,26 @@ tpf_status tpf_create(const tpf_params* params, void* workspace, size_t ws_bytes
         delete c;
         return s;
     }
+    // pinned, fine-grained host buffer for the solver scalars (the host then
+    // polls it instead of copying and synchronising the stream);
+    // TPF_HOST_POLL=0, or a failed allocation, keeps the copy
+    c->pub = c->pub_dev = nullptr;
+    c->pub_token = 0;
+    const char* hp = std::getenv("TPF_HOST_POLL");
+    if (!(hp && hp[0] == '0')) {
+        void* hbuf = nullptr;
+        if (hipHostMalloc(&hbuf, sizeof(PubScalars), hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess) {
+            void* dbuf = nullptr;
+            if (hipHostGetDevicePointer(&dbuf, hbuf, 0) == hipSuccess) {
+                std::memset(hbuf, 0, sizeof(PubScalars));
+                c->pub = static_cast<PubScalars*>(hbuf);
+                c->pub_dev = static_cast<PubScalars*>(dbuf);
+            } else {
+                (void)hipHostFree(hbuf);
+            }
+        }
+        (void)hipGetLastError();
+    }
     *out = c;
     return TPF_OK;
 }
@@ -352,6 +372,7 @@ tpf_status tpf_destroy(tpf_ctx* c) {
     if (!c) return TPF_OK;
     (void)hipStreamSynchronize(c->stream);
     prof_free(c);
+    if (c->pub) (void)hipHostFree(c->pub);
     delete c;
     return TPF_OK;
 }

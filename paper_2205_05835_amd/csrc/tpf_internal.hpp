@@ -31,6 +31,15 @@ struct SolverScalars {
     int pad[2];
 };
 
+// The solver scalars as a kernel publishes them into pinned host memory:
+// token is written last, after a system-scope fence, so a host that reads
+// the token it asked for then reads a complete copy.
+struct PubScalars {
+    SolverScalars s;
+    int token;
+    int pad[3];
+};
+
 // Finalize operations on reduced partial sums (one single-block kernel).
 enum FinOp {
     FIN_MEAN = 0,   // v0 = sum b           -> mean = v0 / N
@@ -169,6 +178,9 @@ struct tpf_ctx {
     int stage_lds;       // 3D phase/momentum pass with its neighbourhoods staged in LDS
     int stage_lds_kz;    // planes per block of that pass
     int coarse_fused;    // 3D stored-coefficient levels: one fused launch down and one up
+    tpf::PubScalars* pub;     // pinned host buffer for the solver scalars (null: copy and synchronise)
+    tpf::PubScalars* pub_dev; // its device address
+    int pub_token;       // last token asked for
     double mg_alpha;     // weight of the multigrid coarse-grid correction
     int coarse_sweeps_per_cell;   // coarsest-grid Jacobi sweeps per cell of its largest dimension (0: 2)
     // measurement mode with a fixed amount of solver work per pressure solve
