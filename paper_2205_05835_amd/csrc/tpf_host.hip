@@ -506,7 +506,9 @@ tpf_status advance(tpf_ctx* c, double dt, int nsteps, char* tape, size_t stage_b
             if (ew != hipSuccess) return hip_fail(ew, "pressure extrapolation");
             RKArgs rk{s, 0, wacc[s], wnext[s]};
             const void* us[3] = {u_s[0], u_s[1], u_s[2]};
+            c->rk_stage = s;
             tpf_status st = stage_eval(c, phi_s, us, rk, phi_o, u_o, 0);
+            c->rk_stage = 0;
             if (st == TPF_OK && s == 0) st = copy_async(c, c->p_hist1, c->p, (size_t)Nn * 8);
             if (st == TPF_OK && s == 1) st = copy_async(c, c->p_hist2, c->p, (size_t)Nn * 8);
             if (st == TPF_OK && s == 2) {
@@ -521,8 +523,7 @@ tpf_status advance(tpf_ctx* c, double dt, int nsteps, char* tape, size_t stage_b
             }
         }
         int flag = 0;
-        e = hipMemcpyAsync(&flag, c->flags, sizeof(int), hipMemcpyDeviceToHost, c->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        e = fetch_flag(c, &flag);
         if (e != hipSuccess) return hip_fail(e, "step completion");
         if (flag) {
             c->p_valid = 0;

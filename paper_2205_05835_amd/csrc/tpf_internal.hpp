@@ -37,8 +37,10 @@ struct SolverScalars {
 struct PubScalars {
     SolverScalars s;
     int token;
-    int pad[3];
+    int flag;      // the step's non-finite flag (k_publish_flag)
+    int pad[2];
 };
+
 
 // Finalize operations on reduced partial sums (one single-block kernel).
 enum FinOp {
@@ -172,7 +174,8 @@ struct tpf_ctx {
     // PCG iterations of the previous solve of each kind (0: FP64 solve,
     // 1 + o: inner solve of outer iteration o); the host checks convergence
     // first after that many iterations
-    int pred_iters[4];
+    int pred_iters[4][4];   // PCG iterations of the last solve of each kind (slot) and RK stage
+    int rk_stage;           // RK stage of the solve under way (0 outside a step)
     int kz_override;     // planes per block of the z-marching kernels (0: automatic)
     int stage_kz;        // planes per block of the z-chunked stage kernels
     int stage_lds;       // 3D phase/momentum pass with its neighbourhoods staged in LDS
@@ -231,6 +234,9 @@ size_t align256(size_t x);
 hipError_t launch_finalize(tpf_ctx* c, int nblocks, int nv, int op);
 hipError_t launch_rhs_mean(tpf_ctx* c);
 hipError_t launch_lincomb(tpf_ctx* c, double* out, double a, const double* x, double b, const double* y);
+// the step's non-finite flag as it stands after the work queued so far
+// (through the pinned buffer when there is one)
+hipError_t fetch_flag(tpf_ctx* c, int* flag);
 
 // 1D grid over gx*gy*gz tiles, padded to a multiple of the XCD count
 inline dim3 tile_grid(long gx, long gy, long gz) {

@@ -1059,6 +1059,50 @@ __global__ void k_publish(const SolverScalars* __restrict__ sc, PubScalars* out,
     *reinterpret_cast<volatile int*>(&out->token) = token;
 }
 
+__global__ void k_publish_flag(const int* __restrict__ flags, PubScalars* out, int token) {
+    if (threadIdx.x != 0) return;
+    out->flag = flags[0];
+    __threadfence_system();
+    *reinterpret_cast<volatile int*>(&out->token) = token;
+}
+
+// spin until the pinned buffer carries `token` (false: the stream drained
+// without it, or *err holds the stream's error)
+static bool wait_token(tpf_ctx* c, int token, hipError_t* err) {
+    const volatile int* tk = &c->pub->token;
+    *err = hipSuccess;
+    for (long spin = 1;; ++spin) {
+        if (*tk == token) break;
+        if ((spin & 1023) == 0) {
+            const hipError_t e = hipStreamQuery(c->stream);
+            if (e == hipSuccess) return *tk == token;
+            if (e != hipErrorNotReady) {
+                *err = e;
+                return false;
+            }
+        }
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+    return true;
+}
+
+hipError_t fetch_flag(tpf_ctx* c, int* flag) {
+    if (c->pub) {
+        const int token = ++c->pub_token;
+        k_publish_flag<<<1, 64, 0, c->stream>>>(c->flags, c->pub_dev, token);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        if (wait_token(c, token, &e)) {
+            *flag = *const_cast<const volatile int*>(&c->pub->flag);
+            return hipSuccess;
+        }
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = hipMemcpyAsync(flag, c->flags, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    return e;
+}
+
 // The solver scalars as they stand after the work queued so far.  With the
 // pinned buffer a kernel publishes them and the host spins on the token (a
 // stream synchronisation would add a copy kernel and a host wake-up, ≈ 50 us
@@ -1070,27 +1114,11 @@ hipError_t fetch_scalars(tpf_ctx* c, SolverScalars* out) {
         k_publish<<<1, 64, 0, c->stream>>>(c->scal, c->pub_dev, token);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        const volatile int* tk = &c->pub->token;
-        bool seen = false;
-        for (long spin = 1; !seen; ++spin) {
-            if (*tk == token) {
-                seen = true;
-                break;
-            }
-            if ((spin & 1023) == 0) {
-                e = hipStreamQuery(c->stream);
-                if (e == hipSuccess) {
-                    seen = *tk == token;
-                    break;
-                }
-                if (e != hipErrorNotReady) return e;
-            }
-        }
-        if (seen) {
-            std::atomic_thread_fence(std::memory_order_acquire);
+        if (wait_token(c, token, &e)) {
             std::memcpy(out, const_cast<const SolverScalars*>(&c->pub->s), sizeof(SolverScalars));
             return hipSuccess;
         }
+        if (e != hipSuccess) return e;
         // the stream drained without the token showing: read it the plain way
     }
     hipError_t e = hipMemcpyAsync(out, c->scal, sizeof(SolverScalars), hipMemcpyDeviceToHost, c->stream);
@@ -1844,7 +1872,9 @@ struct Solver {
     // PCG on level 0 for x (type X); residual already in lv[0].r and the
     // scalars initialised (ff, rr, tol2, done).  The iterations run ahead of
     // the host: it reads the done flag first after the iteration count of
-    // the previous solve of the same kind (slot), then every 2 iterations.
+    // the previous solve of the same kind (slot) in the same RK stage (the
+    // counts repeat from step to step stage by stage, e.g. 3, 4, 4, 4), then
+    // every 2 iterations.
     // Iterations launched after convergence exit at once; the profiler books
     // them as no-work launches.
     template <typename X>
@@ -1853,7 +1883,8 @@ struct Solver {
         (void)finalize2(c, 0, (int)nb0(), FIN_RZ0, 0.0);
         int it = 0;
         bool first = true;
-        int window = c->pred_iters[slot] > 0 ? c->pred_iters[slot] : 4;
+        int& pred = c->pred_iters[slot][c->rk_stage & 3];
+        int window = pred > 0 ? pred : 4;
         snap_.resize((size_t)maxit + 1);
         SolverScalars s{};
         while (it < maxit) {
@@ -1883,7 +1914,7 @@ struct Solver {
                 c->prof_noop_bytes[q] += now.b[q] - snap_[useful].b[q];
             }
         }
-        if (s.done && s.iters >= 0) c->pred_iters[slot] = s.iters;
+        if (s.done && s.iters >= 0) pred = s.iters;
         // nothing is launched after the last read: it holds the final scalars
         *last = s;
         return hipGetLastError();
