@@ -452,8 +452,7 @@ void snapshot(const tpf_ctx* c, ProfSnap& o) {
 }
 
 tpf_status read_scal(tpf_ctx* c, ImpScal* host) {
-    hipError_t e = hipMemcpyAsync(host, c->imp_scal, sizeof(ImpScal), hipMemcpyDeviceToHost, c->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    const hipError_t e = fetch_bytes(c, c->imp_scal, sizeof(ImpScal), host);
     return e == hipSuccess ? TPF_OK : hip_fail(e, "implicit step scalars");
 }
 

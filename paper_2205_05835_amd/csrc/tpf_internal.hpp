@@ -237,6 +237,9 @@ hipError_t launch_lincomb(tpf_ctx* c, double* out, double a, const double* x, do
 // the step's non-finite flag as it stands after the work queued so far
 // (through the pinned buffer when there is one)
 hipError_t fetch_flag(tpf_ctx* c, int* flag);
+// nbytes of device memory to the host after the work queued so far (through
+// the pinned buffer when there is one and the bytes fit it)
+hipError_t fetch_bytes(tpf_ctx* c, const void* dev, size_t nbytes, void* host);
 
 // 1D grid over gx*gy*gz tiles, padded to a multiple of the XCD count
 inline dim3 tile_grid(long gx, long gy, long gz) {

@@ -1086,6 +1086,34 @@ static bool wait_token(tpf_ctx* c, int token, hipError_t* err) {
     return true;
 }
 
+// nbytes (a multiple of 4, at most sizeof(SolverScalars)) of device memory
+// into the pinned buffer, the token last
+__global__ void k_publish_words(const unsigned* __restrict__ src, int nwords, PubScalars* out, int token) {
+    if (threadIdx.x != 0) return;
+    unsigned* dst = reinterpret_cast<unsigned*>(&out->s);
+    for (int i = 0; i < nwords; ++i) dst[i] = src[i];
+    __threadfence_system();
+    *reinterpret_cast<volatile int*>(&out->token) = token;
+}
+
+hipError_t fetch_bytes(tpf_ctx* c, const void* dev, size_t nbytes, void* host) {
+    if (c->pub && nbytes % 4 == 0 && nbytes <= sizeof(SolverScalars)) {
+        const int token = ++c->pub_token;
+        k_publish_words<<<1, 64, 0, c->stream>>>(static_cast<const unsigned*>(dev), (int)(nbytes / 4), c->pub_dev,
+                                                 token);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        if (wait_token(c, token, &e)) {
+            std::memcpy(host, const_cast<const SolverScalars*>(&c->pub->s), nbytes);
+            return hipSuccess;
+        }
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = hipMemcpyAsync(host, dev, nbytes, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    return e;
+}
+
 hipError_t fetch_flag(tpf_ctx* c, int* flag) {
     if (c->pub) {
         const int token = ++c->pub_token;
