@@ -473,6 +473,7 @@ struct TailDesc {
     int off[TAIL_MAX_LEVELS];          // element offset of level l's r; z, zt follow
     double ih2[TAIL_MAX_LEVELS];
     const void* beta[TAIL_MAX_LEVELS][3];
+    int lg[TAIL_MAX_LEVELS][2];         // log2 nx, log2 (nx ny) when both are powers of two, else -1
     double rw;                          // restriction weight
 };
 
@@ -486,9 +487,24 @@ __global__ __launch_bounds__(1024) void k_tail(TailDesc D, S w1, S w2, S omega_c
     const int t = threadIdx.x, T = blockDim.x;
     auto dims = [&](int l) { return Dims{D.n[l][0], D.n[l][1], D.n[l][2], 0}; };
     auto ncell = [&](int l) { return D.n[l][0] * D.n[l][1] * D.n[l][2]; };
-    auto cell = [&](int l, int q) {
+    // (i, j, k) of cell q of level l: shifts and masks when nx and ny are
+    // powers of two (D.lg[l] >= 0, the usual case), else divisions
+    auto ijk = [&](int l, int q, int& i, int& j, int& k) {
         const Dims d = dims(l);
-        return make_cell(d, q % d.nx, (q / d.nx) % d.ny, q / (d.nx * d.ny));
+        if (D.lg[l][0] >= 0) {
+            i = q & (d.nx - 1);
+            j = (q >> D.lg[l][0]) & (d.ny - 1);
+            k = q >> D.lg[l][1];
+        } else {
+            i = q % d.nx;
+            j = (q / d.nx) % d.ny;
+            k = q / (d.nx * d.ny);
+        }
+    };
+    auto cell = [&](int l, int q) {
+        int i, j, k;
+        ijk(l, q, i, j, k);
+        return make_cell(dims(l), i, j, k);
     };
     auto coef = [&](int l) {
         return CoefStored<S>{static_cast<const S*>(D.beta[l][0]), static_cast<const S*>(D.beta[l][1]),
@@ -539,7 +555,8 @@ __global__ __launch_bounds__(1024) void k_tail(TailDesc D, S w1, S w2, S omega_c
         S* rc = L + D.off[l + 1];
         const Dims df = dims(l);
         for (int Q = t; Q < Nc; Q += T) {
-            const int I = Q % dc.nx, J = (Q / dc.nx) % dc.ny, K = Q / (dc.nx * dc.ny);
+            int I, J, K;
+            ijk(l + 1, Q, I, J, K);
             S s = S(0);
             for (int dk = 0; dk < (DIM == 3 ? 2 : 1); ++dk)
                 for (int dj = 0; dj < 2; ++dj)
@@ -1766,6 +1783,14 @@ struct Solver {
             }
             D.off[q] = off;
             off += 3 * (int)L.N;
+            auto lg2 = [](int v) {
+                int e = 0;
+                while ((1 << e) < v) ++e;
+                return (1 << e) == v ? e : -1;
+            };
+            const int lx = lg2(L.n[0]), ly = lg2(L.n[1]);
+            D.lg[q][0] = lx >= 0 && ly >= 0 ? lx : -1;
+            D.lg[q][1] = lx >= 0 && ly >= 0 ? lx + ly : -1;
             D.ih2[q] = 1.0 / (L.h * L.h);
         }
         const Level& Ll = c->lv[c->nlev - 1];
