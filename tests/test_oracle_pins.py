@@ -98,6 +98,74 @@ def test_init_ellipse_zero_level_set(ora):
     assert phi.max() < 1.0 and phi.min() > 0.0
 
 
+def test_init_ellipse_on_axes_is_exact_tanh(ora):
+    """Reading Z19 on the semi-axes: with the centre on a cell centre, the
+    first-order distance (1 - q)/|grad q| reduces exactly to a_k - |x_k| on the
+    k-th axis (the signed distance of the tanh profile in the footnote of
+    Eq. 2, measured from the axis vertex), and to min_k a_k at the centre, so
+    phi is the 1D tanh profile there to round-off.  2D ellipse and 3D
+    ellipsoid with unequal semi-axes."""
+    for dim, n, eps, axes in ((2, 128, 0.05, (0.3, 0.22)), (3, 48, 0.06, (0.3, 0.25, 0.2))):
+        h = 1.0 / n
+        P = ora.Params(n=(n,) * dim, eps=eps)
+        ic = n // 2
+        centre = ((ic + 0.5) * h,) * dim
+        phi = ora.init_droplet(P, centre, axes)
+        x = (np.arange(n) + 0.5) * h - centre[0]
+        off = x != 0.0
+        for k in range(dim):
+            idx = [ic] * dim
+            idx[dim - 1 - k] = slice(None)         # C order: physical axis k is array axis dim-1-k
+            line = phi[tuple(idx)]
+            exact = tanh_phi(np.abs(x), axes[k], eps)
+            np.testing.assert_allclose(line[off], exact[off], rtol=0, atol=1e-15)
+        assert phi[(ic,) * dim] == pytest.approx(tanh_phi(0.0, min(axes), eps), abs=1e-15)
+
+
+def ellipse_signed_distance(X, Y, a, b):
+    """Exact signed distance to the ellipse (x/a)^2 + (y/b)^2 = 1 (positive
+    inside): the nearest boundary point a(cos t, sin t) by a dense search in t,
+    then Newton on the orthogonality condition."""
+    Xf, Yf = X.ravel(), Y.ravel()
+    t = np.linspace(0.0, 2 * np.pi, 4097)[:-1]
+    tt = np.empty_like(Xf)
+    for s in range(0, Xf.size, 2048):
+        d2 = (Xf[s:s + 2048, None] - a * np.cos(t)) ** 2 + (Yf[s:s + 2048, None] - b * np.sin(t)) ** 2
+        tt[s:s + 2048] = t[d2.argmin(axis=1)]
+    for _ in range(30):
+        c, sn = np.cos(tt), np.sin(tt)
+        f = -(a * c - Xf) * a * sn + (b * sn - Yf) * b * c
+        fp = (a * sn) ** 2 - (a * c - Xf) * a * c + (b * c) ** 2 - (b * sn - Yf) * b * sn
+        tt = tt - f / fp
+    d = np.hypot(Xf - a * np.cos(tt), Yf - b * np.sin(tt))
+    inside = (Xf / a) ** 2 + (Yf / b) ** 2 < 1.0
+    return np.where(inside, d, -d).reshape(X.shape)
+
+
+def test_init_ellipse_distance_second_order(ora):
+    """Reading Z19 off the axes: the first-order distance s recovered from phi
+    (s = 2 eps atanh(2 phi - 1)) differs from the exact signed distance d to
+    the ellipse by O(d^2) near it: the error in a band |d| < w falls 4x when w
+    halves, and |s - d| / d^2 stays bounded."""
+    n, eps, (a, b) = 128, 0.05, (0.3, 0.22)
+    h = 1.0 / n
+    P = ora.Params(n=(n, n), eps=eps)
+    centre = (0.5 * n * h + 0.3 * h, 0.5 * n * h - 0.2 * h)   # off the grid's symmetry lines
+    phi = ora.init_droplet(P, centre, (a, b))
+    s = 2.0 * eps * np.arctanh(2.0 * phi - 1.0)
+    X = ((np.arange(n) + 0.5) * h - centre[0])[None, :] * np.ones((n, 1))
+    Y = ((np.arange(n) + 0.5) * h - centre[1])[:, None] * np.ones((1, n))
+    d = ellipse_signed_distance(X, Y, a, b)
+    errs, ratios = [], []
+    for w in (0.04, 0.02, 0.01):
+        m = np.abs(d) < w
+        e = np.abs(s - d)[m]
+        errs.append(e.max())
+        ratios.append((e / np.maximum(d[m] ** 2, 1e-300)).max())
+    assert min(orders(errs)) > 1.8, errs
+    assert max(ratios) < 0.5, ratios
+
+
 # ----------------------------------------------------------------- Eq. 2: chemical potential
 
 
@@ -148,6 +216,37 @@ def test_regularization_tanh_circle_steady_order2(ora, model):
         errs.append(np.abs(g)[r < 0.45].max())
     o = orders(errs)
     assert min(o) > 1.8, (errs, o)
+
+
+@pytest.mark.parametrize("model", ["SB", "ISODI"])
+def test_regularization_off_equilibrium_order2(ora, model):
+    """Table 1 away from equilibrium, where the SB and ISODI curvature terms
+    differ.  For a tanh circle/sphere of width eps' = 1.5 eps (not the model's
+    eps), |grad phi| = phi(1-phi)/eps', kappa = (d-1)/r and
+    L phi = (1-2phi) phi(1-phi)/eps'^2 - (d-1) phi(1-phi)/(eps' r), so the
+    continuum right-hand sides are
+        g_SB    = gamma phi(1-phi)(1-2phi)(eps/eps'^2 - 1/eps)
+        g_ISODI = g_SB + gamma phi(1-phi)(d-1)(1 - eps/eps')/r.
+    Eq. 8 makes the two agree only at eps' = eps; here each discrete g
+    converges to its own value at order 2 (band 0.1 < r < 0.4, away from the
+    1/r singularity of kappa at the centre)."""
+    R = 0.25
+    for dim, ns, eps in ((2, (128, 256, 512), 0.02), (3, (48, 96, 192), 0.04)):
+        ew, errs = 1.5 * eps, []
+        for n in ns:
+            P = circle_params(ora, n, eps, dim=dim, model=ora.MODELS[model], gamma=1.0)
+            r = radius(P)
+            phi = tanh_phi(r, R, ew)
+            w = phi * (1 - phi)
+            exact = w * (1 - 2 * phi) * (eps / ew ** 2 - 1 / eps)
+            if model == "ISODI":
+                exact = exact + w * (dim - 1) * (1 - eps / ew) / r
+            g = ora.regularization(P, phi)
+            m = (r > 0.1) & (r < 0.4)
+            errs.append(np.abs(g - exact)[m].max())
+        o = orders(errs)
+        assert o[-1] > 1.8 and min(o) > 1.5, (dim, errs, o)
+        assert errs[-1] < 2e-3 * np.abs(exact[m]).max() * (4 if dim == 3 else 1), (dim, errs)
 
 
 def test_curvature_circle_order2(ora):
