@@ -26,6 +26,10 @@ CFLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
+# debug builds only: clamp every stage-kernel neighbour index to the grid
+# (the periodic offsets are checked cell by cell on the CPU by tests/index_check.cpp)
+if os.environ.get("TPF_BOUNDS_CLAMP") == "1":
+    CFLAGS.append("-DTPF_BOUNDS_CLAMP")
 
 
 def _compile(src: str, obj: str) -> None:

@@ -6,18 +6,9 @@
 
 #include <cstdint>
 
+#include "tpf_index.hpp"
+
 namespace tpf {
-
-// 256-thread blocks laid out as 64 consecutive x cells (one wave64 = one
-// coalesced row segment) by 4 rows in y; grid z walks the z planes.
-constexpr int BX = 64;
-constexpr int BY = 4;
-constexpr int BLOCK = BX * BY;
-
-struct Dims {
-    int nx, ny, nz;
-    int xcd;        // 1: XCD slab tiling of the 1D block grid, 0: tile = block id
-};
 
 // Physical parameters as the kernels consume them.
 struct Phys {
@@ -28,70 +19,8 @@ struct Phys {
 enum { MODEL_CDI = 0, MODEL_SB = 1, MODEL_ISODI = 2 };
 enum { FORCE_EB = 0, FORCE_CSF = 1, FORCE_LCSF = 2 };
 
-// wrap an index that is at most one period out of range
-__device__ __forceinline__ int wrapc(int v, int n) {
-    v = v < 0 ? v + n : v;
-    return v >= n ? v - n : v;
-}
-
-// A cell and the offsets of its six periodic neighbours; a, b are physical
-// axes (0 = x).  Indices are 32-bit (grids up to 2^31 cells): neighbour
-// addressing is one integer add, and the loads use a scalar base plus a
-// 32-bit vector offset.
-// Every neighbour index is clamped to [0, N-1] (one v_min_u32): the periodic
-// offsets below always land inside the grid, and the clamp makes an access
-// outside the array impossible even if they did not.
-struct Cell {
-    int i, j, k;
-    unsigned id;
-    unsigned last;  // N - 1
-    int o[3][2];    // o[a][0]: offset to c - e_a, o[a][1]: offset to c + e_a
-    __device__ __forceinline__ unsigned off(int a, int s) const {
-        return min(id + (unsigned)o[a][s > 0], last);
-    }
-    // unclamped neighbour (pressure-solver kernels, whose index arithmetic is
-    // checked cell by cell against the wrapped coordinates on the CPU)
-    __device__ __forceinline__ unsigned nb(int a, int s) const { return id + (unsigned)o[a][s > 0]; }
-    // c + s e_a + t e_b for a != b only: each offset is the one of cell c, so
-    // two shifts compose only when they move along different axes
-    __device__ __forceinline__ unsigned off2(int a, int s, int b, int t) const {
-        return min(id + (unsigned)o[a][s > 0] + (unsigned)o[b][t > 0], last);
-    }
-};
-
-__device__ __forceinline__ Cell make_cell(const Dims& d, int i, int j, int k) {
-    Cell C;
-    C.i = i;
-    C.j = j;
-    C.k = k;
-    const int nx = d.nx, plane = d.nx * d.ny;
-    C.id = (unsigned)((k * d.ny + j) * nx + i);
-    C.last = (unsigned)(plane * d.nz - 1);
-    C.o[0][0] = i == 0 ? nx - 1 : -1;
-    C.o[0][1] = i == nx - 1 ? 1 - nx : 1;
-    C.o[1][0] = j == 0 ? (d.ny - 1) * nx : -nx;
-    C.o[1][1] = j == d.ny - 1 ? (1 - d.ny) * nx : nx;
-    C.o[2][0] = k == 0 ? (d.nz - 1) * plane : -plane;
-    C.o[2][1] = k == d.nz - 1 ? (1 - d.nz) * plane : plane;
-    return C;
-}
-
-// XCD-aware tiling.  Workgroups are dealt to the 8 XCDs round robin by their
-// linear id, and each XCD has its own L2.  Grids are therefore 1D (padded to a
-// multiple of 8) and block b works on tile (b % 8) * (nb / 8) + b / 8: every
-// XCD owns one contiguous run of tiles (a slab of z planes), so the y and z
-// neighbours a stencil reads sit in the same L2.  Tiles are x-fastest.
-constexpr int NXCD = 8;
-
 __device__ __forceinline__ bool block_tile(int xcd, int gx, int gy, int gz, int& bx, int& by, int& bz) {
-    const int nb = gridDim.x;
-    const int b = blockIdx.x;
-    const int tile = xcd ? (b % NXCD) * (nb / NXCD) + b / NXCD : b;
-    if (tile >= gx * gy * gz) return false;
-    bx = tile % gx;
-    by = (tile / gx) % gy;
-    bz = tile / (gx * gy);
-    return true;
+    return tile_coords(tile_of_block(xcd, (int)gridDim.x, (int)blockIdx.x), gx, gy, gz, bx, by, bz);
 }
 
 // the cell of this thread for a (BX x BY x 1) tiling of the grid

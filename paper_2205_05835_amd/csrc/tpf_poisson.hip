@@ -550,7 +550,6 @@ __global__ __launch_bounds__(1024) void k_tail(TailDesc D, S w1, S w2, S omega_c
         __syncthreads();
         sweep(l, w2, [&](const Cell& C, int a, int s) { return z[s == 0 ? C.id : C.nb(a, s)]; }, zt);
         // restriction of r - A zt into the next level's r
-        const Dims dc = dims(l + 1);
         const int Nc = ncell(l + 1);
         S* rc = L + D.off[l + 1];
         const Dims df = dims(l);
@@ -1194,42 +1193,22 @@ hipError_t launch_finalize(tpf_ctx* c, int nblocks, int nv, int op) {
 // hit the rows the block's other waves just read.  Each field is thus read
 // about once from L2 per sweep instead of once per stencil point.
 
-struct Col {
-    int nx, ny, nz;
-    int i, j;                 // column (clamped into the grid for inactive lanes)
+struct Col : ColIndex {
     bool valid;               // lane owns a real column
-    unsigned plane, row;
-    int oxm, oxp, oym, oyp;   // periodic in-plane neighbour offsets
-    int im, ip, jm, jp;       // neighbour coordinates
     bool sxm, sxp;            // x neighbour held by the adjacent lane
     int kslab;                // index of this block's slab of kz planes
     __device__ __forceinline__ void init(const Dims& d, int kz) {
-        nx = d.nx;
-        ny = d.ny;
-        nz = d.nz;
         const int tx = threadIdx.x;
         int bx = 0, by = 0;
-        const bool tile = block_tile(d.xcd, (nx + BX - 1) / BX, (ny + BY - 1) / BY, nz / kz, bx, by, kslab);
+        const bool tile = block_tile(d.xcd, (d.nx + BX - 1) / BX, (d.ny + BY - 1) / BY, d.nz / kz, bx, by, kslab);
         const int i0 = bx * BX + tx, j0 = by * BY + threadIdx.y;
-        if (!tile) kslab = nz / kz;      // empty range: the block only joins its reductions
-        valid = tile && i0 < nx && j0 < ny;
-        i = valid ? i0 : 0;
-        j = valid ? j0 : 0;
-        plane = (unsigned)(nx * ny);
-        row = (unsigned)(j * nx + i);
-        oxm = i == 0 ? nx - 1 : -1;
-        oxp = i == nx - 1 ? 1 - nx : 1;
-        oym = j == 0 ? (ny - 1) * nx : -nx;
-        oyp = j == ny - 1 ? (1 - ny) * nx : nx;
-        im = i == 0 ? nx - 1 : i - 1;
-        ip = i == nx - 1 ? 0 : i + 1;
-        jm = j == 0 ? ny - 1 : j - 1;
-        jp = j == ny - 1 ? 0 : j + 1;
+        if (!tile) kslab = d.nz / kz;      // empty range: the block only joins its reductions
+        valid = tile && i0 < d.nx && j0 < d.ny;
+        // inactive lanes take column (0, 0), so every offset stays in the grid
+        set(d.nx, d.ny, d.nz, valid ? i0 : 0, valid ? j0 : 0);
         sxm = tx > 0 && i > 0;
         sxp = tx < BX - 1 && i < nx - 1;
     }
-    __device__ __forceinline__ unsigned at(int k) const { return (unsigned)k * plane + row; }
-    __device__ __forceinline__ int kwrap(int k) const { return k < 0 ? k + nz : (k >= nz ? k - nz : k); }
 };
 
 // value of the lane on the left / right (lanes 0 / 63 get their own back)
