@@ -136,6 +136,35 @@ tpf_status tpf_init_droplet(tpf_ctx* ctx, const double center[3], const double s
  * completed step. */
 tpf_status tpf_step(tpf_ctx* ctx, double dt, int32_t nsteps);
 
+/* Zero-copy access to the state inside the caller's workspace.  The state is
+ * the (phi, u) of the problem statement (Sec. 3.1: given phi and u, advance
+ * and report) and the projection pressure p.
+ *
+ * tpf_field_offset: byte offset from the workspace base of field `field`
+ * (tpf_state_field below) and its element type (tpf_dtype: TPF_DTYPE_F32
+ * for phi and u of a TPF_FP32_MIXED context, TPF_DTYPE_F64 otherwise; p is
+ * always TPF_DTYPE_F64).  The array has N = nx*ny*nz elements in the layout
+ * above, contiguous.  Offsets are multiples of 256.  The state alternates
+ * between two slots of the workspace each RK4 step, so the offsets of phi and
+ * u hold until the next tpf_step or tpf_step_adjoint (ask again after
+ * either; tpf_load_checkpoint and tpf_implicit_phase_step write the current
+ * slot in place).  p holds the zero-mean
+ * projection pressure of the current state once tpf_get_state (with p),
+ * tpf_diagnostics or tpf_eval_field has run since the state last changed;
+ * otherwise it holds the last solve's iterate.  Returns TPF_EINVAL for an
+ * unknown field or a velocity component beyond dim.
+ *
+ * tpf_state_changed: after the caller wrote phi and/or u in place (stream
+ * ordered before this call), do what tpf_set_state does after its copy:
+ * reset t, the step count, the pressure and its warm start, and record mass0.
+ * Synchronises the stream. */
+typedef enum {
+    TPF_STATE_PHI = 0, TPF_STATE_U0 = 1, TPF_STATE_U1 = 2, TPF_STATE_U2 = 3, TPF_STATE_P = 4
+} tpf_state_field;
+typedef enum { TPF_DTYPE_F64 = 0, TPF_DTYPE_F32 = 1 } tpf_dtype;
+tpf_status tpf_field_offset(const tpf_ctx* ctx, int32_t field, size_t* byte_offset, int32_t* dtype);
+tpf_status tpf_state_changed(tpf_ctx* ctx);
+
 /* Copy the state out (any pointer may be NULL to skip it).  p is the
  * projection pressure of the current state (computed on demand by one stage
  * evaluation, zero mean). */

@@ -31,8 +31,13 @@ class Rollout(torch.autograd.Function):
             raise ValueError(f"{p.dim}D case needs {p.dim} velocity components, got {len(u0)}")
         s = tpf.Solver(p)
         dev = s.device
-        s.set_state(phi0.detach().to(dev, torch.float64).contiguous(),
-                    [x.detach().to(dev, torch.float64).contiguous() for x in u0])
+        # the initial state is written straight into the workspace (the views
+        # round to the state's precision as tpf_set_state would)
+        vphi, vu, _ = s.state_views()
+        vphi.copy_(phi0.detach().reshape(s.shape))
+        for a in range(p.dim):
+            vu[a].copy_(u0[a].detach().reshape(s.shape))
+        s.state_changed()
         ckpts = []
         done = 0
         while done < nsteps:
@@ -40,7 +45,9 @@ class Rollout(torch.autograd.Function):
             ckpts.append((s.save_checkpoint(), k))
             s.step(dt, k)
             done += k
-        phi, u = s.get_state_device()
+        vphi, vu, _ = s.state_views()
+        phi = vphi.to(torch.float64, copy=True)
+        u = [x.to(torch.float64, copy=True) for x in vu]
         ctx.solver, ctx.ckpts, ctx.dt = s, ckpts, dt
         ctx.meta = (phi0.device, sigma.device if torch.is_tensor(sigma) else None,
                     eps.device if torch.is_tensor(eps) else None)

@@ -418,6 +418,33 @@ tpf_status tpf_set_state(tpf_ctx* c, const double* phi, const double* u0, const 
     return finish_set_state(c);
 }
 
+tpf_status tpf_field_offset(const tpf_ctx* c, int32_t field, size_t* byte_offset, int32_t* dtype) {
+    if (!c || !byte_offset || !dtype) { set_error("tpf_field_offset: NULL argument"); return TPF_EINVAL; }
+    const void* ptr = nullptr;
+    int32_t ty = c->mixed ? TPF_DTYPE_F32 : TPF_DTYPE_F64;
+    if (field == TPF_STATE_PHI) {
+        ptr = c->phi[c->s_yn];
+    } else if (field >= TPF_STATE_U0 && field <= TPF_STATE_U2) {
+        const int a = field - TPF_STATE_U0;
+        if (a >= c->dim) { set_error("velocity component beyond dim"); return TPF_EINVAL; }
+        ptr = c->u[a][c->s_yn];
+    } else if (field == TPF_STATE_P) {
+        ptr = c->p;
+        ty = TPF_DTYPE_F64;
+    } else {
+        set_error("unknown state field");
+        return TPF_EINVAL;
+    }
+    *byte_offset = (size_t)(static_cast<const char*>(ptr) - c->ws);
+    *dtype = ty;
+    return TPF_OK;
+}
+
+tpf_status tpf_state_changed(tpf_ctx* c) {
+    if (!c) { set_error("ctx is NULL"); return TPF_EINVAL; }
+    return finish_set_state(c);
+}
+
 tpf_status tpf_init_droplet(tpf_ctx* c, const double center[3], const double semi_axes[3]) {
     if (!c || !center || !semi_axes) { set_error("tpf_init_droplet: NULL argument"); return TPF_EINVAL; }
     for (int a = 0; a < c->dim; ++a)

@@ -40,7 +40,11 @@ EXPORTS = ["tpf_workspace_bytes", "tpf_create", "tpf_destroy", "tpf_set_state", 
            "tpf_batch_status", "tpf_batch_clear_status", "tpf_batch_diagnostics", "tpf_batch_configs",
            "tpf_batch_config_info", "tpf_batch_set_config", "tpf_batch_tune", "tpf_checkpoint_bytes",
            "tpf_save_checkpoint", "tpf_load_checkpoint", "tpf_adjoint_tape_bytes", "tpf_stage_adjoint",
-           "tpf_step_adjoint", "tpf_solver_stats", "tpf_implicit_phase_step"]
+           "tpf_step_adjoint", "tpf_solver_stats", "tpf_implicit_phase_step", "tpf_field_offset",
+           "tpf_state_changed"]
+
+TPF_STATE_PHI, TPF_STATE_U0, TPF_STATE_U1, TPF_STATE_U2, TPF_STATE_P = 0, 1, 2, 3, 4
+TPF_DTYPE_F64, TPF_DTYPE_F32 = 0, 1
 
 
 class TpfError(RuntimeError):
@@ -108,6 +112,8 @@ def lib():
         "tpf_create": ([P, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)], i32),
         "tpf_destroy": ([vp], i32),
         "tpf_set_state": ([vp, vp, vp, vp, vp, i32], i32),
+        "tpf_field_offset": ([vp, i32, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(i32)], i32),
+        "tpf_state_changed": ([vp], i32),
         "tpf_init_droplet": ([vp, dp, dp], i32),
         "tpf_step": ([vp, ctypes.c_double, i32], i32),
         "tpf_get_state": ([vp, vp, vp, vp, vp, vp, i32], i32),
@@ -242,6 +248,34 @@ class Solver:
         arrs = [_host(phi, self.N)] + [_host(x, self.N) for x in u]
         ptrs = [a.ctypes.data_as(ctypes.c_void_p) for a in arrs] + [None] * (4 - len(arrs))
         check(lib().tpf_set_state(self.ctx, *ptrs[:4], 0), "tpf_set_state")
+
+    def field_offset(self, field: int):
+        """(byte offset in the workspace, tpf_dtype) of a state field."""
+        off = ctypes.c_size_t(0)
+        ty = ctypes.c_int32(0)
+        check(lib().tpf_field_offset(self.ctx, int(field), ctypes.byref(off), ctypes.byref(ty)),
+              "tpf_field_offset")
+        return int(off.value), ty.value
+
+    def _view(self, field: int):
+        torch = self.torch
+        off, ty = self.field_offset(field)
+        dt, esz = (torch.float32, 4) if ty == TPF_DTYPE_F32 else (torch.float64, 8)
+        return self.workspace[off:off + self.N * esz].view(dt).view(self.shape)
+
+    def state_views(self):
+        """Zero-copy tensors over the current state inside the workspace:
+        (phi, [u_a], p), in the state's own precision (p always float64).
+        phi and u move to the other state slot at every step: take new views
+        after step()/step_adjoint().  After writing phi or u through them,
+        call state_changed()."""
+        phi = self._view(TPF_STATE_PHI)
+        u = [self._view(TPF_STATE_U0 + a) for a in range(self.dim)]
+        return phi, u, self._view(TPF_STATE_P)
+
+    def state_changed(self):
+        """Bookkeeping of tpf_set_state after an in-place write of the state."""
+        check(lib().tpf_state_changed(self.ctx), "tpf_state_changed")
 
     def init_droplet(self, center, semi_axes):
         c = (ctypes.c_double * 3)(*(list(center) + [0.0] * (3 - len(center))))
