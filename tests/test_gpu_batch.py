@@ -111,6 +111,64 @@ def test_batch_fp64_matches_oracle(gpu, ora):
         assert ephi < 1e-12 and eu < 1e-11 and ep < 1e-12, c.name
 
 
+def all_pair_cases():
+    """The nine model x force pairs of Table 1 / Eqs. 4, 11 and CSF, one case
+    each, on grids and boxes of several shapes: box edges 1, 2 pi (the
+    standing wave's box) and 2, non-square grids, density ratios 1 to 1000."""
+    C = workloads.Case
+    L = 2.0 * np.pi
+    return [
+        C("p_cdi_eb", (32, 24), (0.5, 0.3), (0.25, 0.2), 1.0, 0.1, 2e-3, 2e-4, 1.0, 1.0, "CDI", "EB", "fp64"),
+        C("p_cdi_csf", (24, 24), (0.5, 0.5), (0.3, 0.25), 240.0, 0.24, 0.1, 0.001, 1.0, 0.75, "CDI", "CSF", "fp64"),
+        C("p_cdi_lcsf", (32, 32), (0.5 * L, 0.5 * L), (0.25 * L, 0.2 * L), 1.0, 1.0, 0.01, 0.01, 1.0, 1.0,
+          "CDI", "LCSF", "fp64", length=L),
+        C("p_sb_eb", (40, 20), (1.0, 0.5), (0.5, 0.3), 2.0, 1.0, 0.02, 0.01, 0.8, 0.9, "SB", "EB", "fp64",
+          length=2.0),
+        C("p_sb_csf", (20, 28), (0.5, 0.7), (0.3, 0.25), 10.0, 1.0, 0.02, 0.004, 1.5, 1.0, "SB", "CSF", "fp64"),
+        C("p_sb_lcsf", (28, 28), (0.5, 0.5), (0.3, 0.22), 1.0, 0.01, 0.01, 1e-4, 1.0, 0.8, "SB", "LCSF", "fp64"),
+        C("p_isodi_eb", (24, 32), (0.5, 0.6), (0.3, 0.3), 1.0, 0.001, 0.01, 1e-5, 1.0, 0.75, "ISODI", "EB",
+          "fp64"),
+        C("p_isodi_csf", (32, 32), (0.5 * L, 0.5 * L), (0.3 * L, 0.22 * L), 3.0, 1.0, 0.03, 0.01, 2.0, 1.0,
+          "ISODI", "CSF", "fp64", length=L),
+        C("p_isodi_lcsf", (36, 20), (0.4, 0.3), (0.3, 0.2), 1.0, 0.5, 0.02, 0.01, 0.7, 1.0, "ISODI", "LCSF",
+          "fp64"),
+    ]
+
+
+def test_batch_fp64_all_pairs_matches_oracle(gpu, ora):
+    """All nine model/force pairs in one FP64 batch, with a seeded
+    divergence-free initial velocity (advection and viscous terms active),
+    4 steps, each case against the oracle."""
+    cases = all_pair_cases()
+    steps = 4
+    say(f"batch FP64 parity, all pairs, {len(cases)} cases x {steps} steps")
+    params = [gpu.params_for_case(c, poisson_rtol=1e-14, poisson_maxit=4000) for c in cases]
+    b = gpu.Batch(params)
+    init, dts = [], []
+    for q, c in enumerate(cases):
+        P = oparams(ora, c)
+        phi0 = ora.init_droplet(P, c.center, c.semi_axes)
+        u0 = workloads.divergence_free_velocity(P.shape, 20 + q, amplitude=0.01 * c.length)
+        init.append((phi0, u0))
+        dts.append(c.dt(umax0=max(np.abs(x).max() for x in u0)))
+        b.set_state(q, phi0, u0)
+    dts = np.array(dts)
+    b.step(dts, steps)
+    st, nst, _ = b.status()
+    assert (st == 0).all() and (nst == steps).all()
+    for q, c in enumerate(cases):
+        P = oparams(ora, c)
+        phi_o, u_o, p_o = ora.step(P, dts[q], steps, *init[q])     # p: the last stage's pressure
+        _, du_o, _ = ora.stage(P, phi_o, u_o, p_o)
+        phi_g, u_g, p_g = b.get_state(q, with_pressure=True)
+        uref = uref_of(u_o, du_o, dts[q])
+        ephi = np.abs(phi_g - phi_o).max()
+        eu = max(np.abs(u_g[a] - u_o[a]).max() for a in range(2)) / uref
+        ep = np.abs(p_g - p_o).max() / np.abs(p_o).max()
+        say(f"  {c.name}: |dphi| {ephi:.2e} |du|/Uref {eu:.2e} |dp|/|p| {ep:.2e}")
+        assert ephi < 1e-12 and eu < 1e-11 and ep < 1e-11, c.name
+
+
 def test_batch_mixed_error_statement(gpu, ora):
     """FP32-mixed batch against the FP64 oracle (started from the FP32-rounded
     phi0): the mixed-precision bounds of the single-case path."""

@@ -1,0 +1,153 @@
+"""Element-by-element oracle parity of the pressure and of whole RK4 steps on
+the oscillating ellipsoid at 96^3 (the 3D workload's geometry and properties,
+density ratio 10, CDI + energy-based force), the largest grid the FP64 oracle
+steps in about a minute.
+
+The FP64 path runs twice: with the separate stored-coefficient multigrid
+kernels and the global-memory stage kernels (TPF_COARSE_FUSED=0,
+TPF_STAGE_LDS=0), and with the fused coarse levels and the LDS stage passes
+the FP32 benchmark runs by default (=1, =1).  At 96^3 the multigrid has the
+levels 96^3 (z-marching fine kernels), 48^3 and 24^3 (stored coefficients,
+fused or separate) and the LDS tail below.  A divergence-free seeded velocity
+keeps advection and viscous stresses active.  The FP32-mixed default path is
+compared with the same oracle run at the bounds the FP32 rounding allows.
+
+Tolerances (reading Z14): phi absolute; u relative to
+U_ref = max(|u|, dt |du/dt|); p and du/dt relative to their max.  Both
+solvers stop at a relative residual of 1e-14; the operator's condition
+number here is about d n^2 / pi^2 x density ratio = 2.8e4, which bounds how
+far two converged solutions can differ.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = [pytest.mark.gpu, pytest.mark.fullsize]
+
+N = 96
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2205_05835_amd import tpf
+    tpf.lib()
+    return tpf
+
+
+def rel(a, b):
+    s = np.abs(b).max()
+    return np.abs(a - b).max() / (s if s > 0 else 1.0)
+
+
+@pytest.fixture(scope="module")
+def setup(ora):
+    case = workloads.oscillating_drop_3d(N, "fp64")
+    P = ora.Params(n=case.n, length=case.length, model=ora.MODELS[case.model],
+                   force=ora.FORCES[case.force], sigma=case.sigma, eps=case.eps, gamma=case.gamma,
+                   rho1=case.rho1, rho2=case.rho2, visc1=case.visc1, visc2=case.visc2)
+    phi0 = ora.init_droplet(P, case.center, case.semi_axes)
+    u0 = workloads.divergence_free_velocity(P.shape, 9, amplitude=0.02)
+    umax0 = max(np.abs(x).max() for x in u0)
+    dt = case.dt(umax0=umax0)
+    return case, P, phi0, u0, dt
+
+
+@pytest.fixture(scope="module")
+def oracle_stage(ora, setup):
+    case, P, phi0, u0, dt = setup
+    say(f"oracle stage {N}^3 ({ora.threads()} threads)")
+    return ora.stage(P, phi0, u0)
+
+
+@pytest.fixture(scope="module")
+def oracle_steps(ora, setup):
+    case, P, phi0, u0, dt = setup
+    say(f"oracle 2 steps {N}^3 ({ora.threads()} threads)")
+    phi2, u2, pw = ora.step(P, dt, 2, phi0, u0)
+    _, du2, p2 = ora.stage(P, phi2, u2, pw)
+    return phi2, u2, du2, p2
+
+
+VARIANTS = [pytest.param(("0", "0"), id="separate-levels-global-stage"),
+            pytest.param(("1", "1"), id="fused-levels-lds-stage")]
+
+
+@pytest.fixture
+def kernels(monkeypatch, request):
+    fused, lds = request.param
+    monkeypatch.setenv("TPF_COARSE_FUSED", fused)
+    monkeypatch.setenv("TPF_STAGE_LDS", lds)
+    return fused, lds
+
+
+@pytest.mark.parametrize("kernels", VARIANTS, indirect=True)
+def test_stage_pressure_96cubed_fp64(gpu, ora, setup, oracle_stage, kernels):
+    """One stage at the initial state: the projection pressure, du/dt and
+    dphi/dt against the oracle's stage evaluation."""
+    case, P, phi0, u0, dt = setup
+    d_o, du_o, p_o = oracle_stage
+    say(f"stage {N}^3 fp64 fused={kernels[0]} lds={kernels[1]}")
+    s = gpu.solver_for_case(case, poisson_rtol=1e-14, poisson_maxit=2000)
+    s.set_state(phi0, u0)
+    p_g = s.eval_field("PRESSURE")
+    ep = rel(p_g, p_o)
+    edu = max(rel(s.eval_field(f"DU{a}"), du_o[a]) for a in range(3))
+    ed = rel(s.eval_field("DPHI"), d_o)
+    say(f"  |dp|/|p| {ep:.2e}  |ddu|/|du| {edu:.2e}  |ddphi|/|dphi| {ed:.2e}")
+    assert abs(p_g.mean()) < 1e-13 * np.abs(p_o).max()
+    assert ed < 1e-12
+    assert ep < 1e-11 and edu < 1e-11
+
+
+@pytest.mark.parametrize("kernels", VARIANTS, indirect=True)
+def test_two_steps_96cubed_fp64(gpu, ora, setup, oracle_steps, kernels):
+    """Two RK4 steps (eight pressure solves): phi, u and the final
+    projection pressure against the oracle."""
+    case, P, phi0, u0, dt = setup
+    phi_o, u_o, du_o, p_o = oracle_steps
+    say(f"2 steps {N}^3 fp64 fused={kernels[0]} lds={kernels[1]}")
+    s = gpu.solver_for_case(case, poisson_rtol=1e-14, poisson_maxit=2000)
+    s.set_state(phi0, u0)
+    s.step(dt, 2)
+    phi_g, u_g, p_g = s.get_state(with_pressure=True)
+    uref = max(max(np.abs(x).max() for x in u_o), dt * max(np.abs(x).max() for x in du_o))
+    ephi = np.abs(phi_g - phi_o).max()
+    eu = max(np.abs(u_g[a] - u_o[a]).max() for a in range(3)) / uref
+    ep = rel(p_g, p_o)
+    say(f"  |dphi| {ephi:.2e}  |du|/Uref {eu:.2e}  |dp|/|p| {ep:.2e}")
+    assert ephi < 1e-12 and eu < 1e-12 and ep < 1e-11
+
+
+def test_two_steps_96cubed_fp32_mixed(gpu, ora, setup, oracle_steps):
+    """The FP32-mixed default path (LDS stage passes, fused coarse levels,
+    FP64 defect correction) against the FP64 oracle on the same initial state
+    rounded to FP32: phi to 1e-6 absolute, u to 1e-3 of U_ref and p to 1e-5
+    relative.  Bounds: phi and u are stored in FP32 (2^-24 relative), the
+    explicit terms of du/dt cancel to ~1e-3 of their size at this velocity, and
+    p is solved to 1e-9 relative in FP64."""
+    case, P, phi0, u0, dt = setup
+    phi_o, u_o, du_o, p_o = oracle_steps
+    say(f"2 steps {N}^3 fp32_mixed")
+    c32 = workloads.oscillating_drop_3d(N, "fp32_mixed")
+    s = gpu.solver_for_case(c32)
+    s.set_state(phi0, u0)
+    s.step(dt, 2)
+    phi_g, u_g, p_g = s.get_state(with_pressure=True)
+    uref = max(max(np.abs(x).max() for x in u_o), dt * max(np.abs(x).max() for x in du_o))
+    ephi = np.abs(phi_g - phi_o).max()
+    eu = max(np.abs(u_g[a] - u_o[a]).max() for a in range(3)) / uref
+    ep = rel(p_g, p_o)
+    say(f"  |dphi| {ephi:.2e}  |du|/Uref {eu:.2e}  |dp|/|p| {ep:.2e}")
+    assert ephi < 1e-6 and eu < 1e-3 and ep < 1e-5
