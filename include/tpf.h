@@ -175,6 +175,27 @@ tpf_status tpf_get_state(tpf_ctx* ctx, double* phi, double* u0, double* u1, doub
  * projection pressure of the current state (one stage evaluation). */
 tpf_status tpf_diagnostics(tpf_ctx* ctx, tpf_diag* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * diagnostics of tpf_diagnostics for a state held in the caller's own device
+ * arrays, with no context and no workspace.  params describes the grid and
+ * properties (validated as for tpf_create).  phi, u0, u1 (u2 in 3D; ignored
+ * in 2D) are FP64 device arrays of N = nx*ny*nz values in the layout above;
+ * p (FP64, N values, may be NULL: dp is then NaN) is the pressure to measure
+ * dp with.  Work is issued on hip_stream (NULL = legacy default stream) and
+ * the call synchronises it before filling *out (host memory).  mass0 and
+ * poisson_relres are NaN and t, step and the Poisson counters 0: they belong
+ * to a context.  The reduction's block partials live in a static device
+ * array of the library (5.5 MiB on every device the library runs on, held
+ * until the process ends), so the grid may have at most 65536 tiles of
+ * 64 x 4 cells, ceil(nx/64) * ceil(ny/4) * nz <= 65536 (256^3 and 4096^2
+ * fit); larger grids return TPF_EINVAL.  The call allocates nothing.  Calls
+ * that overlap on one device (from two host threads or two streams) share
+ * that array and race. */
+tpf_status tpf_diagnostics_noalloc(const tpf_params* params, const double* phi, const double* u0,
+                                   const double* u1, const double* u2, const double* p, void* hip_stream,
+                                   tpf_diag* out);
+
 /* Fields of one stage evaluation at the current state, for verification of
  * each operator.  out: N doubles (host if on_device = 0). */
 typedef enum {

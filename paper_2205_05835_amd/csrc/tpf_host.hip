@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -237,6 +238,11 @@ tpf_status resolve_params(const tpf_params* in, tpf_params* P) {
     return TPF_OK;
 }
 
+int xcd_tiles_from_env() {
+    const char* xt = std::getenv("TPF_XCD_TILES");
+    return (xt && xt[0] == '0') ? 0 : 1;
+}
+
 static void init_geometry(tpf_ctx* c, const tpf_params* P) {
     c->P = *P;
     c->dim = P->dim;
@@ -279,8 +285,7 @@ static void init_geometry(tpf_ctx* c, const tpf_params* P) {
     // TPF_COARSE_FUSED=0|1 overrides
     const char* cfz = std::getenv("TPF_COARSE_FUSED");
     c->coarse_fused = cfz ? (cfz[0] == '1' ? 1 : 0) : (P->precision == TPF_FP32_MIXED ? 1 : 0);
-    const char* xt = std::getenv("TPF_XCD_TILES");
-    g_xcd_tiles = (xt && xt[0] == '0') ? 0 : 1;
+    g_xcd_tiles = xcd_tiles_from_env();
     c->nlev = plan_levels(c);
 }
 
@@ -787,6 +792,98 @@ tpf_status tpf_profile_read(tpf_ctx* c, int32_t cls, const char** name, double* 
     if (launches) *launches = work;
     if (bytes_per_launch)
         *bytes_per_launch = work > 0 ? (c->prof_bytes[cls] - c->prof_noop_bytes[cls]) / work : 0.0;
+    return TPF_OK;
+}
+
+}  // extern "C"
+
+// ================================================================== no-allocation diagnostics
+// tpf_diagnostics_noalloc keeps the block partials and the final sums of its
+// reduction in this file-scope device array: no hipMalloc, no workspace.  The
+// host side never uses the array's name as an address; it asks the runtime
+// once per device for the array's device address (scratch_dev) and passes
+// that to the kernels.
+namespace tpf {
+constexpr long kNoAllocBlocks = 65536;                       // 64 x 4-cell tiles
+constexpr long kNoAllocValues = ND_SUM + ND_MAX;
+constexpr size_t kNoAllocDoubles = (size_t)kNoAllocValues * kNoAllocBlocks + 32;
+}  // namespace tpf
+
+static __device__ __align__(256) double scratch[tpf::kNoAllocDoubles];
+
+namespace tpf {
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_dev[kMaxDevices];
+
+// device address of `scratch` on the current device, looked up once per device
+static tpf_status scratch_dev(double** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("device index beyond the scratch table");
+        return TPF_EDEVICE;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "scratch address");
+        g_scratch_dev[dev] = static_cast<double*>(ptr);
+    }
+    *out = g_scratch_dev[dev];
+    return TPF_OK;
+}
+}  // namespace tpf
+
+extern "C" {
+
+tpf_status tpf_diagnostics_noalloc(const tpf_params* params, const double* phi, const double* u0,
+                                   const double* u1, const double* u2, const double* p, void* hip_stream,
+                                   tpf_diag* out) {
+    tpf_params P;
+    tpf_status st = resolve_params(params, &P);
+    if (st != TPF_OK) return st;
+    if (!phi || !u0 || !u1 || (P.dim == 3 && !u2) || !out) {
+        set_error("tpf_diagnostics_noalloc: NULL argument");
+        return TPF_EINVAL;
+    }
+    const int n[3] = {P.n[0], P.n[1], P.dim == 3 ? P.n[2] : 1};
+    const long nb = nblocks_of(n);
+    if (nb > kNoAllocBlocks) {
+        set_error("tpf_diagnostics_noalloc: grid needs " + std::to_string(nb) + " blocks of 64 x 4 cells, the "
+                  "static scratch holds " + std::to_string(kNoAllocBlocks));
+        return TPF_EINVAL;
+    }
+    double* sc = nullptr;
+    st = scratch_dev(&sc);
+    if (st != TPF_OK) return st;
+    double* part = sc;
+    double* fin = sc + kNoAllocValues * kNoAllocBlocks;
+    g_xcd_tiles = xcd_tiles_from_env();
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const void* u[3] = {u0, u1, P.dim == 3 ? u2 : nullptr};
+    // every partial the final sum reads is written by this call's first
+    // kernel, so nothing in the scratch needs clearing
+    hipError_t e = launch_diagnostics_arrays(stream, P.dim, n, 0, phys_of_params(P), phi, u, p, part, fin);
+    double v[kNoAllocValues];
+    if (e == hipSuccess) e = hipMemcpyAsync(v, fin, sizeof(v), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "tpf_diagnostics_noalloc");
+    const double hd = std::pow(P.length / P.n[0], P.dim);
+    std::memset(out, 0, sizeof(*out));
+    out->mass = hd * v[0];
+    out->mass0 = NAN;
+    out->ke = hd * v[1];
+    out->se = hd * v[2];
+    out->dp = (p && v[4] > 0 && v[6] > 0) ? v[3] / v[4] - v[5] / v[6] : NAN;
+    out->umax = v[7];
+    out->ca_inf = P.sigma > 0 ? v[7] * P.visc1 / P.sigma : NAN;
+    out->div_max = v[8];
+    out->phi_min = -v[9];
+    out->phi_max = v[10];
+    out->poisson_relres = NAN;
     return TPF_OK;
 }
 

@@ -218,6 +218,13 @@ hipError_t launch_convert_in(tpf_ctx* c, const double* src, void* dst);
 hipError_t launch_convert_out(tpf_ctx* c, const void* src, double* dst);
 hipError_t launch_zero_state(tpf_ctx* c, void* dst);
 hipError_t launch_diagnostics(tpf_ctx* c, const void* phi, const void* const u[3], const double* p);
+// the same reduction on explicit arrays (fp32: phi and u are float) into the
+// block partials `part` (ND_SUM + ND_MAX values per block of grid_of(n)) and
+// the final sums `out` (ND_SUM + ND_MAX values)
+hipError_t launch_diagnostics_arrays(hipStream_t st, int dim, const int n[3], int fp32, const Phys& P,
+                                     const void* phi, const void* const u[3], const double* p, double* part,
+                                     double* out);
+int xcd_tiles_from_env();
 
 // pressure solver (tpf_poisson.hip)
 tpf_status poisson_solve(tpf_ctx* c, const void* phi, int* iters, double* relres, int* outer);

@@ -635,19 +635,28 @@ hipError_t launch_zero_state(tpf_ctx* c, void* dst) {
 }
 
 template <typename T, int DIM>
-static hipError_t diag_impl(tpf_ctx* c, const void* phi, const void* const u[3], const double* p) {
-    const Phys P = phys_of(c);
-    const dim3 g = grid_of(c->n), b(BX, BY);
-    k_diag<T, DIM><<<g, b, 0, c->stream>>>(dims_of(c->n), P, ctp<T>(phi), ctp<T>(u[0]),
-                                           ctp<T>(u[1]), ctp<T>(u[2]), p, c->diag_part);
-    k_diag_final<<<1, BLOCK, 0, c->stream>>>((int)nblocks_of(c->n), c->diag_part, c->diag_out);
+static hipError_t diag_impl(hipStream_t st, const int n[3], const Phys& P, const void* phi,
+                            const void* const u[3], const double* p, double* part, double* out) {
+    const dim3 g = grid_of(n), b(BX, BY);
+    k_diag<T, DIM><<<g, b, 0, st>>>(dims_of(n), P, ctp<T>(phi), ctp<T>(u[0]), ctp<T>(u[1]),
+                                    ctp<T>(u[2] ? u[2] : u[1]), p, part);
+    k_diag_final<<<1, BLOCK, 0, st>>>((int)nblocks_of(n), part, out);
     return hipGetLastError();
 }
 
+hipError_t launch_diagnostics_arrays(hipStream_t st, int dim, const int n[3], int fp32, const Phys& P,
+                                     const void* phi, const void* const u[3], const double* p, double* part,
+                                     double* out) {
+    if (fp32)
+        return dim == 2 ? diag_impl<float, 2>(st, n, P, phi, u, p, part, out)
+                        : diag_impl<float, 3>(st, n, P, phi, u, p, part, out);
+    return dim == 2 ? diag_impl<double, 2>(st, n, P, phi, u, p, part, out)
+                    : diag_impl<double, 3>(st, n, P, phi, u, p, part, out);
+}
+
 hipError_t launch_diagnostics(tpf_ctx* c, const void* phi, const void* const u[3], const double* p) {
-    if (c->mixed)
-        return c->dim == 2 ? diag_impl<float, 2>(c, phi, u, p) : diag_impl<float, 3>(c, phi, u, p);
-    return c->dim == 2 ? diag_impl<double, 2>(c, phi, u, p) : diag_impl<double, 3>(c, phi, u, p);
+    return launch_diagnostics_arrays(c->stream, c->dim, c->n, c->mixed, phys_of(c), phi, u, p, c->diag_part,
+                                     c->diag_out);
 }
 
 }  // namespace tpf

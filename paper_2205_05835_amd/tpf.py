@@ -41,7 +41,7 @@ EXPORTS = ["tpf_workspace_bytes", "tpf_create", "tpf_destroy", "tpf_set_state", 
            "tpf_batch_config_info", "tpf_batch_set_config", "tpf_batch_tune", "tpf_checkpoint_bytes",
            "tpf_save_checkpoint", "tpf_load_checkpoint", "tpf_adjoint_tape_bytes", "tpf_stage_adjoint",
            "tpf_step_adjoint", "tpf_solver_stats", "tpf_implicit_phase_step", "tpf_field_offset",
-           "tpf_state_changed"]
+           "tpf_state_changed", "tpf_diagnostics_noalloc"]
 
 TPF_STATE_PHI, TPF_STATE_U0, TPF_STATE_U1, TPF_STATE_U2, TPF_STATE_P = 0, 1, 2, 3, 4
 TPF_DTYPE_F64, TPF_DTYPE_F32 = 0, 1
@@ -114,6 +114,7 @@ def lib():
         "tpf_set_state": ([vp, vp, vp, vp, vp, i32], i32),
         "tpf_field_offset": ([vp, i32, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(i32)], i32),
         "tpf_state_changed": ([vp], i32),
+        "tpf_diagnostics_noalloc": ([P, vp, vp, vp, vp, vp, vp, ctypes.POINTER(tpf_diag)], i32),
         "tpf_init_droplet": ([vp, dp, dp], i32),
         "tpf_step": ([vp, ctypes.c_double, i32], i32),
         "tpf_get_state": ([vp, vp, vp, vp, vp, vp, i32], i32),
