@@ -188,6 +188,7 @@ def batch_run(args):
     failed = None
     try:
         b.step(dts, args.batch_warmup)
+        b.solver_stats(reset=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         b.step(dts, args.batch_steps)
@@ -196,6 +197,7 @@ def batch_run(args):
     except tpf.TpfError as e:
         failed = str(e)
         wall = float("nan")
+    stats = b.solver_stats()
     st, nst, _ = b.status()
     dg = b.diagnostics()
     cells = sum(c.cells for c in cases)
@@ -207,6 +209,31 @@ def batch_run(args):
            "cases_stopped": int((st != 0).sum()), "error": failed,
            "phi_min": min(d["phi_min"] for d in dg), "phi_max": max(d["phi_max"] for d in dg),
            "mean_pcg_iterations_last_solve": float(np.mean([d["poisson_inner"] for d in dg]))}
+    # Roofline by the 2D mixed-precision byte model (one pass per operator,
+    # units of one FP32 field sweep): per RK stage 27 + 6 units for the stage
+    # operators and the projection, and per pressure solve 42 units per
+    # defect-correction pass plus 43 per PCG iteration (V-cycle included),
+    # with each case's counted passes and iterations of the timed steps.
+    units = np.array([132.0 * args.batch_steps + 42.0 * stats["outer"][q] + 43.0 * stats["inner"][q]
+                      for q in range(len(cases))])
+    cells_q = np.array([c.cells for c in cases], dtype=np.float64)
+    alg_bytes = float((units * cells_q * 4.0).sum()) / args.batch_steps
+    # FP32-mixed fields per case: 12 state + 10 stage + 3 solver (4 B), b, p and
+    # 3 pressure histories (8 B), 5 per multigrid level (4/3 of the fine grid)
+    ws_case = cells_q * (25 * 4 + 5 * 8 + 5 * 4 * 4.0 / 3.0)
+    if failed is None:
+        ach = alg_bytes / (wall / args.batch_steps) / 1e9
+        out["roofline"] = {
+            "bound": "hbm", "model": "2D byte model: 132 units/step + 42 per outer pass + 43 per PCG iteration",
+            "algorithmic_gb_per_step": round(alg_bytes / 1e9, 3), "achieved": round(ach, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+            "pcg_iterations_per_solve": round(float(stats["inner"].sum() / max(stats["solves"].sum(), 1)), 3),
+            "outer_per_solve": round(float(stats["outer"].sum() / max(stats["solves"].sum(), 1)), 3),
+            "working_set_gb": round(float(ws_case.sum()) / 1e9, 3),
+            "largest_case_working_set_mb": round(float(ws_case.max()) / 1e6, 2),
+            "cache_resident": False,
+            "note": "the batch's working set is several times the 256 MB last-level cache and all cases "
+                    "run at once, so the model's bytes come from HBM"}
     del b
     if args.batch_compare:
         # FP32-mixed vs FP64 on a seeded sample of the cases

@@ -374,14 +374,25 @@ tpf_status tpf_batch_diagnostics(tpf_batch* b, tpf_diag* out);
 
 /* Launch shapes: configuration c has `threads` threads per case-workgroup and
  * keeps the coarsest multigrid levels of each case in up to `lds_bytes` of
- * LDS.  tpf_batch_tune() times every configuration on the batch (the state is
- * not advanced), keeps the fastest, and records it in the text file
- * cache_path (may be NULL) under a key made of the precision and the grid
- * sizes; a later call with the same key reads the choice back instead. */
+ * LDS (some configurations reserve their whole LDS budget so that a large
+ * case gets a CU to itself).  tpf_batch_tune() times every configuration on
+ * one stage evaluation of every live case (the state, the pressure warm start
+ * and the statuses are left as they were), keeps the fastest, and records it
+ * in the text file cache_path (may be NULL) under a key made of a hash of the
+ * library's sources, the precision and the grid sizes; a later call with the
+ * same key reads the choice back instead.  If a case's pressure solve fails
+ * during the timing, the fastest configuration is still set and the call
+ * returns TPF_ENOCONV naming the case (which keeps running). */
 int32_t tpf_batch_configs(void);
 tpf_status tpf_batch_config_info(int32_t config, int32_t* threads, int32_t* lds_bytes);
 tpf_status tpf_batch_set_config(tpf_batch* b, int32_t config);
 tpf_status tpf_batch_tune(tpf_batch* b, const double* dt, const char* cache_path, int32_t* chosen);
+
+/* Pressure-solve counters of every case since creation or the last reset
+ * (arrays of ncases values, any may be NULL): solves, outer
+ * (defect-correction) iterations and PCG iterations, summed over the solves.
+ * reset = 1 zeroes them after reading. */
+tpf_status tpf_batch_solver_stats(tpf_batch* b, int64_t* solves, int64_t* outer, int64_t* inner, int32_t reset);
 
 const char* tpf_last_error(void);
 const char* tpf_version(void);

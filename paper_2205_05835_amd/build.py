@@ -32,8 +32,21 @@ if os.environ.get("TPF_BOUNDS_CLAMP") == "1":
     CFLAGS.append("-DTPF_BOUNDS_CLAMP")
 
 
+def source_hash() -> str:
+    """16 hex digits over the library's sources (kernels, host code, header):
+    built into the library so that caches keyed on it (the batch tuner's)
+    are not reused across source changes."""
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".hpp")))
+    for f in files + [os.path.join("..", "..", "include", "tpf.h")]:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
 def _compile(src: str, obj: str) -> None:
-    cmd = [HIPCC, *CFLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *CFLAGS, f'-DTPF_SRC_HASH="{source_hash()}"', "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")

@@ -20,11 +20,16 @@ namespace tpf {
 
 // Launch shapes the tuner chooses from: threads per case-workgroup and the
 // LDS budget for the coarse multigrid levels of each case.
+// `reserve` launches with the whole budget as dynamic LDS even where the
+// cases need less, which caps the workgroups per CU (96 KB: one per CU, so a
+// large case has its CU to itself).
 struct BConfig {
     int threads;
     int lds_bytes;
+    int reserve;
 };
-static const BConfig kConfigs[] = {{256, 16384}, {512, 32768}, {1024, 61440}, {1024, 0}, {512, 0}};
+static const BConfig kConfigs[] = {{256, 16384, 0}, {512, 32768, 0}, {1024, 61440, 0}, {1024, 0, 0},
+                                   {512, 0, 0},     {1024, 98304, 1}, {512, 98304, 1}};
 constexpr int NCONFIG = sizeof(kConfigs) / sizeof(kConfigs[0]);
 
 }  // namespace tpf
@@ -132,6 +137,7 @@ static size_t carve_batch(tpf_batch* b, char* base) {
         K.p = (double*)take(N * 8);
         for (int k = 0; k < 3; ++k) K.ph[k] = (double*)take(N * 8);
         K.pv = take(NS);
+        K.pv2 = take(NS);
         K.qv = take(NS);
         K.ev = take(NS);
         plan_case_levels(P, K);
@@ -171,23 +177,27 @@ static tpf_status upload_cases(tpf_batch* b) {
     return TPF_OK;
 }
 
+template <typename T, typename S, int NT>
+static hipError_t launch_step_nt(tpf_batch* b, size_t lds, int mode, int commit) {
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch_step<T, S, NT>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    k_batch_step<T, S, NT><<<dim3(b->ncases), NT, lds, b->stream>>>(b->d_cases, b->d_order, b->d_states, b->d_dts,
+                                                                   mode, commit);
+    return hipGetLastError();
+}
+
 template <typename T, typename S>
 static hipError_t launch_step_t(tpf_batch* b, int mode, int commit) {
     const int nt = kConfigs[b->config].threads;
-    const size_t lds = (size_t)max_lds(b);
-    const dim3 g(b->ncases);
+    const size_t lds = kConfigs[b->config].reserve ? (size_t)kConfigs[b->config].lds_bytes : (size_t)max_lds(b);
     switch (nt) {
-    case 256:
-        k_batch_step<T, S, 256><<<g, 256, lds, b->stream>>>(b->d_cases, b->d_order, b->d_states, b->d_dts, mode, commit);
-        break;
-    case 512:
-        k_batch_step<T, S, 512><<<g, 512, lds, b->stream>>>(b->d_cases, b->d_order, b->d_states, b->d_dts, mode, commit);
-        break;
-    default:
-        k_batch_step<T, S, 1024><<<g, 1024, lds, b->stream>>>(b->d_cases, b->d_order, b->d_states, b->d_dts, mode, commit);
-        break;
+    case 256: return launch_step_nt<T, S, 256>(b, lds, mode, commit);
+    case 512: return launch_step_nt<T, S, 512>(b, lds, mode, commit);
+    default: return launch_step_nt<T, S, 1024>(b, lds, mode, commit);
     }
-    return hipGetLastError();
 }
 
 static hipError_t launch_step(tpf_batch* b, int mode, int commit) {
@@ -616,11 +626,30 @@ tpf_status tpf_batch_config_info(int32_t config, int32_t* threads, int32_t* lds_
 
 int32_t tpf_batch_configs(void) { return NCONFIG; }
 
+// Copy every case's pressure (the warm start of its next step) into its
+// scratch state slot 3 (which holds nothing between steps; N FP64 values fit
+// in its phi array in FP64, in its phi and u_x arrays in FP32), or back.
+static hipError_t stash_pressures(tpf_batch* b, bool restore) {
+    hipError_t e = hipSuccess;
+    for (int q = 0; q < b->ncases && e == hipSuccess; ++q) {
+        const BCase& K = b->h_cases[q];
+        const size_t NT = (size_t)K.nx * K.ny * b->tsz;
+        char* pb = reinterpret_cast<char*>(K.p);
+        const int parts = b->tsz == 8 ? 1 : 2;
+        for (int h = 0; h < parts && e == hipSuccess; ++h) {
+            void* slot = K.y[3][h];
+            e = restore ? hipMemcpyAsync(pb + h * NT, slot, NT, hipMemcpyDeviceToDevice, b->stream)
+                        : hipMemcpyAsync(slot, pb + h * NT, NT, hipMemcpyDeviceToDevice, b->stream);
+        }
+    }
+    return e;
+}
+
 tpf_status tpf_batch_tune(tpf_batch* b, const double* dt, const char* cache_path, int32_t* chosen) {
     if (!b || !dt) { set_error("batch and dt are required"); return TPF_EINVAL; }
-    // key: precision and the sorted list of grid sizes
+    // key: build of the kernel sources, precision and the sorted list of grid sizes
     std::ostringstream key;
-    key << (b->mixed ? "fp32mixed" : "fp64") << ":" << b->ncases;
+    key << TPF_SRC_HASH << ":" << (b->mixed ? "fp32mixed" : "fp64") << ":" << b->ncases;
     {
         std::vector<long> sz(b->ncases);
         for (int q = 0; q < b->ncases; ++q) sz[q] = (long)b->P[q].n[0] * 100000 + b->P[q].n[1];
@@ -642,19 +671,34 @@ tpf_status tpf_batch_tune(tpf_batch* b, const double* dt, const char* cache_path
     hipError_t e = hipMemcpyAsync(b->d_dts, dt, sizeof(double) * b->ncases, hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return hip_fail(e, "uploading time steps");
+    std::vector<BState> before, after;
+    tpf_status st = read_states(b, before);
+    if (st != TPF_OK) return st;
+    // The timed launches are stage evaluations of the current state (mode 1):
+    // they write the scratch fields and the pressure of every live case and
+    // nothing else, so the pressures are stashed before and put back after,
+    // and the tuned batch continues exactly as an untuned one.
+    e = stash_pressures(b, false);
+    if (e != hipSuccess) return hip_fail(e, "saving pressures for tuning");
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
         set_error("hipEventCreate failed");
         return TPF_EDEVICE;
     }
+    const int start = b->config;
     int best = -1;
     float best_ms = 0.f;
     for (int cfg = 0; cfg < NCONFIG; ++cfg) {
-        tpf_status st = tpf_batch_set_config(b, cfg);
+        st = tpf_batch_set_config(b, cfg);
         if (st != TPF_OK) break;
-        e = launch_step(b, 0, 0);                       // warm-up, state not advanced
-        if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
-        for (int r = 0; r < 2 && e == hipSuccess; ++r) e = launch_step(b, 0, 0);
+        e = launch_step(b, 1, 0);                       // warm-up
+        if (e != hipSuccess) {                          // shape not launchable here: skip it
+            (void)hipGetLastError();
+            e = hipSuccess;
+            continue;
+        }
+        e = hipEventRecord(e0, b->stream);
+        for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch_step(b, 1, 0);
         if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         float ms = 0.f;
@@ -667,14 +711,57 @@ tpf_status tpf_batch_tune(tpf_batch* b, const double* dt, const char* cache_path
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    if (e == hipSuccess) e = stash_pressures(b, true);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return hip_fail(e, "timing batch launch configurations");
-    if (best < 0) return TPF_EDEVICE;
+    if (st != TPF_OK) return st;
+    if (best < 0) {
+        (void)tpf_batch_set_config(b, start);
+        set_error("no batch launch configuration could be launched");
+        return TPF_EDEVICE;
+    }
+    st = read_states(b, after);
+    if (st != TPF_OK) return st;
+    // a case whose stage evaluation failed during tuning is reported (its
+    // state is untouched and it keeps running)
+    int nfail = 0, first = -1;
+    for (int q = 0; q < b->ncases; ++q)
+        if (after[q].fails != before[q].fails) {
+            if (first < 0) first = q;
+            ++nfail;
+        }
     if (cache_path) {
         std::ofstream o(cache_path, std::ios::app);
         o << key.str() << " " << best << "\n";
     }
     if (chosen) *chosen = best;
-    return tpf_batch_set_config(b, best);
+    st = tpf_batch_set_config(b, best);
+    if (st == TPF_OK && nfail) {
+        set_error(std::to_string(nfail) + " case(s) failed a pressure solve while tuning (first: case " +
+                  std::to_string(first) + "); launch configuration " + std::to_string(best) + " is set");
+        return TPF_ENOCONV;
+    }
+    return st;
+}
+
+tpf_status tpf_batch_solver_stats(tpf_batch* b, int64_t* solves, int64_t* outer, int64_t* inner, int32_t reset) {
+    if (!b) { set_error("batch is NULL"); return TPF_EINVAL; }
+    std::vector<BState> s;
+    tpf_status st = read_states(b, s);
+    if (st != TPF_OK) return st;
+    for (int q = 0; q < b->ncases; ++q) {
+        if (solves) solves[q] = s[q].solves;
+        if (outer) outer[q] = s[q].outer_total;
+        if (inner) inner[q] = s[q].inner_total;
+        s[q].solves = s[q].outer_total = s[q].inner_total = 0;
+    }
+    if (reset) {
+        hipError_t e = hipMemcpyAsync(b->d_states, s.data(), sizeof(BState) * b->ncases, hipMemcpyHostToDevice,
+                                      b->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+        if (e != hipSuccess) return hip_fail(e, "resetting batch solver counters");
+    }
+    return TPF_OK;
 }
 
 }  // extern "C"

@@ -35,7 +35,8 @@ struct BCase {
     double* b;
     double* p;          // pressure (solution and warm start), FP64
     double* ph[3];      // pressure history for the warm starts (as the single-case step)
-    void* pv;           // CG direction (solver precision)
+    void* pv;           // CG directions (solver precision), two buffers used in turn
+    void* pv2;
     void* qv;           // A p
     void* ev;           // mixed: inner solution (correction)
     void* lb[BMAXLEV][2];   // face coefficients per level (global)
@@ -58,6 +59,7 @@ struct BState {
     double relres;      // last pressure solve
     long long step;
     double mass0;
+    long long solves, outer_total, inner_total;   // pressure solves and their iterations since the last reset
 };
 
 // ------------------------------------------------------------------ reductions
@@ -125,6 +127,32 @@ __device__ __forceinline__ S bapply(const BLev<S>& L, const Cell& C, const S* x,
     return acc * L.ih2;
 }
 
+// The operands of (A x)[c]: x at c and its four neighbours, the face
+// coefficients of c's four faces.  Loaded apart from the arithmetic so that
+// a thread can have the loads of several cells in flight (BatchBlock::cells_g).
+template <typename S>
+struct Stencil {
+    S xc, xw, xe, xs, xn, bl0, bh0, bl1, bh1;
+    __device__ __forceinline__ void load(const BLev<S>& L, const Cell& C, const S* x) {
+        const unsigned c = C.id;
+        bl0 = L.b0[c];
+        bh0 = L.b0[C.nb(0, 1)];
+        bl1 = L.b1[c];
+        bh1 = L.b1[C.nb(1, 1)];
+        xc = x[c];
+        xw = x[C.nb(0, -1)];
+        xe = x[C.nb(0, 1)];
+        xs = x[C.nb(1, -1)];
+        xn = x[C.nb(1, 1)];
+    }
+    // the arithmetic of bapply, term for term
+    __device__ __forceinline__ S apply(S ih2, S& dg) const {
+        const S acc = bl0 * (xc - xw) - bh0 * (xe - xc) + bl1 * (xc - xs) - bh1 * (xn - xc);
+        dg = (bl0 + bh0 + bl1 + bh1) * ih2;
+        return acc * ih2;
+    }
+};
+
 template <typename T, typename S, int NT>
 struct BatchBlock {
     const BCase& K;
@@ -137,6 +165,35 @@ struct BatchBlock {
     __device__ __forceinline__ void cells(const Dims& d, F f) const {
         for (int j = threadIdx.x / 64; j < d.ny; j += NT / 64)
             for (int i = threadIdx.x % 64; i < d.nx; i += 64) f(make_cell(d, i, j, 0));
+    }
+
+    // The same cells, visited in groups of UG: f(C, on) gets the group's UG
+    // cells (on[u] false past the grid) and reads the operands of all of them
+    // before it computes and stores any, so one thread has UG cells' loads in
+    // flight at once instead of one.  A workgroup owns a whole case, and at
+    // 36 cells per thread on a 192^2 grid the one-cell-at-a-time loop waits
+    // out one memory latency per cell.  The visiting order (and so the order
+    // of every per-thread sum) is that of cells().
+    static constexpr int UG = 4;
+    template <int U = UG, typename F>
+    __device__ __forceinline__ void cells_g(const Dims& d, F f) const {
+        const int gx = (d.nx + 63) / 64;
+        const int j0 = threadIdx.x / 64, i0 = threadIdx.x % 64;
+        const int rows = j0 < d.ny ? (d.ny - j0 + NT / 64 - 1) / (NT / 64) : 0;
+        const int nt = gx * rows;
+        for (int t0 = 0; t0 < nt; t0 += U) {
+            Cell C[U];
+            bool on[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int t = t0 + u;
+                const int jj = t / gx;
+                const int i = (t - jj * gx) * 64 + i0, j = j0 + jj * (NT / 64);
+                on[u] = t < nt && i < d.nx;
+                C[u] = make_cell(d, on[u] ? i : 0, on[u] ? j : 0, 0);
+            }
+            f(C, on);
+        }
     }
 
     __device__ __forceinline__ Dims dims(int l) const { return Dims{K.ln[l][0], K.ln[l][1], 1, 0}; }
@@ -209,9 +266,62 @@ struct BatchBlock {
         __syncthreads();
     }
 
+    // dst = src + omega (r - A src) / d on level L (one damped Jacobi sweep)
+    // (dot: also sum <r, dst> over the thread's cells into *dot)
+    __device__ __forceinline__ void jacobi(const BLev<S>& L, const S* src, S* dst, S omega,
+                                           double* dot = nullptr) const {
+        cells_g(L.d, [&](const Cell* C, const bool* on) {
+            Stencil<S> v[UG];
+            S r[UG];
+#pragma unroll
+            for (int u = 0; u < UG; ++u)
+                if (on[u]) {
+                    v[u].load(L, C[u], src);
+                    r[u] = L.r[C[u].id];
+                }
+#pragma unroll
+            for (int u = 0; u < UG; ++u)
+                if (on[u]) {
+                    S dg;
+                    const S az = v[u].apply(L.ih2, dg);
+                    const S zn = v[u].xc + omega * (r[u] - az) / dg;
+                    dst[C[u].id] = zn;
+                    if (dot) *dot += (double)r[u] * (double)zn;
+                }
+        });
+    }
+
+    // ---------------------------------------------------------- coarsest grid
+    // The same damped Jacobi sweeps from zero as the workgroup loop, for a
+    // coarsest grid of at most 64 cells: the first wave holds it, one cell
+    // per lane, and each sweep reads the four neighbours' values from their
+    // lanes (cross-lane permutes), so the sweeps need no workgroup barrier.
+    // Lanes past the grid mirror cell 0 and write nothing.  Result in zt.
+    __device__ __forceinline__ void coarsest_in_wave(const BLev<S>& L, int N, int sweeps, S wc) const {
+        if (threadIdx.x >= 64) return;
+        const int lane = threadIdx.x;
+        const int q = lane < N ? lane : 0;
+        const Cell C = make_cell(L.d, q % L.d.nx, q / L.d.nx, 0);
+        const S bl0 = L.b0[q], bh0 = L.b0[C.nb(0, 1)];
+        const S bl1 = L.b1[q], bh1 = L.b1[C.nb(1, 1)];
+        const S r = L.r[q];
+        const S dg = (bl0 + bh0 + bl1 + bh1) * L.ih2;
+        const int lw = (int)C.nb(0, -1), le = (int)C.nb(0, 1), ls = (int)C.nb(1, -1), ln = (int)C.nb(1, 1);
+        S z = S(0);
+        for (int s = 0; s < sweeps; ++s) {
+            const S zw = __shfl(z, lw, 64), ze = __shfl(z, le, 64);
+            const S zs = __shfl(z, ls, 64), zn = __shfl(z, ln, 64);
+            const S az = (bl0 * (z - zw) - bh0 * (ze - z) + bl1 * (z - zs) - bh1 * (zn - z)) * L.ih2;
+            z = z + wc * (r - az) / dg;
+        }
+        if (lane < N) L.zt[q] = z;
+    }
+
     // ---------------------------------------------------------- V-cycle
     // z = M r on level 0 (r in lev(0).r); the result ends in lev(0).zt.
-    __device__ void vcycle(S omega) {
+    // Returns <r, zt> of level 0 (summed by the last sweep, per thread in cell
+    // order, then over the workgroup).
+    __device__ __forceinline__ double vcycle(S omega) {
         const int nl = K.nlev;
         if (nl == 1) {
             const BLev<S> L = lev(0);
@@ -227,21 +337,33 @@ struct BatchBlock {
                 L.zt[C.id] = L.z[C.id] + omega * (L.r[C.id] - az) / dg;
             });
             __syncthreads();
-            return;
+            double rz = 0.0;
+            cells(L.d, [&](const Cell& C) { rz += (double)L.r[C.id] * (double)L.zt[C.id]; });
+            return bsum<NT>(rz, red);
         }
         for (int l = 0; l + 1 < nl; ++l) {
             const BLev<S> L = lev(l);
-            cells(L.d, [&](const Cell& C) {            // z = omega r / d
-                const unsigned c = C.id;
-                const S dg = (L.b0[c] + L.b0[C.nb(0, 1)] + L.b1[c] + L.b1[C.nb(1, 1)]) * L.ih2;
-                L.z[c] = omega * L.r[c] / dg;
+            cells_g(L.d, [&](const Cell* C, const bool* on) {      // z = omega r / d
+                S b0l[UG], b0h[UG], b1l[UG], b1h[UG], r[UG];
+#pragma unroll
+                for (int u = 0; u < UG; ++u)
+                    if (on[u]) {
+                        const unsigned c = C[u].id;
+                        b0l[u] = L.b0[c];
+                        b0h[u] = L.b0[C[u].nb(0, 1)];
+                        b1l[u] = L.b1[c];
+                        b1h[u] = L.b1[C[u].nb(1, 1)];
+                        r[u] = L.r[c];
+                    }
+#pragma unroll
+                for (int u = 0; u < UG; ++u)
+                    if (on[u]) {
+                        const S dg = (b0l[u] + b0h[u] + b1l[u] + b1h[u]) * L.ih2;
+                        L.z[C[u].id] = omega * r[u] / dg;
+                    }
             });
             __syncthreads();
-            cells(L.d, [&](const Cell& C) {            // zt = z + omega (r - A z) / d
-                S dg;
-                const S az = bapply(L, C, L.z, dg);
-                L.zt[C.id] = L.z[C.id] + omega * (L.r[C.id] - az) / dg;
-            });
+            jacobi(L, L.z, L.zt, omega);                            // zt = z + omega (r - A z) / d
             __syncthreads();
             const BLev<S> Lc = lev(l + 1);
             cells(Lc.d, [&](const Cell& Cc) {          // rc = mean of children of (r - A zt)
@@ -261,6 +383,10 @@ struct BatchBlock {
             const int N = ncell(nl - 1);
             const int sweeps = 8 * max(L.d.nx, L.d.ny);
             const S wc = S(0.8);
+            if (N <= 64) {
+                coarsest_in_wave(L, N, sweeps, wc);
+                __syncthreads();
+            } else {
             for (int q = threadIdx.x; q < N; q += NT) L.zt[q] = S(0);
             __syncthreads();
             S* src = L.zt;
@@ -280,33 +406,52 @@ struct BatchBlock {
                 for (int q = threadIdx.x; q < N; q += NT) L.zt[q] = src[q];
                 __syncthreads();
             }
+            }
         }
         for (int l = nl - 2; l >= 0; --l) {
             const BLev<S> L = lev(l);
             const BLev<S> Lc = lev(l + 1);
             // Z = zt + P zc, then z = Z + omega (r - A Z) / d, zt = z + omega (r - A z) / d
-            cells(L.d, [&](const Cell& C) {
+            cells_g(L.d, [&](const Cell* C, const bool* on) {
                 auto Z = [&](int i, int j) {
                     const int ii = wrapc(i, L.d.nx), jj = wrapc(j, L.d.ny);
                     return L.zt[jj * L.d.nx + ii] + Lc.zt[(jj >> 1) * Lc.d.nx + (ii >> 1)];
                 };
-                const unsigned c = C.id;
-                const S bl0 = L.b0[c], bh0 = L.b0[C.nb(0, 1)];
-                const S bl1 = L.b1[c], bh1 = L.b1[C.nb(1, 1)];
-                const S zc = Z(C.i, C.j);
-                const S az = (bl0 * (zc - Z(C.i - 1, C.j)) - bh0 * (Z(C.i + 1, C.j) - zc) +
-                              bl1 * (zc - Z(C.i, C.j - 1)) - bh1 * (Z(C.i, C.j + 1) - zc)) * L.ih2;
-                const S dg = (bl0 + bh0 + bl1 + bh1) * L.ih2;
-                L.z[c] = zc + omega * (L.r[c] - az) / dg;
+                Stencil<S> v[UG];
+                S r[UG];
+#pragma unroll
+                for (int u = 0; u < UG; ++u)
+                    if (on[u]) {
+                        const unsigned c = C[u].id;
+                        const int i = C[u].i, j = C[u].j;
+                        v[u].bl0 = L.b0[c];
+                        v[u].bh0 = L.b0[C[u].nb(0, 1)];
+                        v[u].bl1 = L.b1[c];
+                        v[u].bh1 = L.b1[C[u].nb(1, 1)];
+                        v[u].xc = Z(i, j);
+                        v[u].xw = Z(i - 1, j);
+                        v[u].xe = Z(i + 1, j);
+                        v[u].xs = Z(i, j - 1);
+                        v[u].xn = Z(i, j + 1);
+                        r[u] = L.r[c];
+                    }
+#pragma unroll
+                for (int u = 0; u < UG; ++u)
+                    if (on[u]) {
+                        S dg;
+                        const S az = v[u].apply(L.ih2, dg);
+                        L.z[C[u].id] = v[u].xc + omega * (r[u] - az) / dg;
+                    }
             });
             __syncthreads();
-            cells(L.d, [&](const Cell& C) {
-                S dg;
-                const S az = bapply(L, C, L.z, dg);
-                L.zt[C.id] = L.z[C.id] + omega * (L.r[C.id] - az) / dg;
-            });
-            __syncthreads();
+            if (l > 0) {
+                jacobi(L, L.z, L.zt, omega);
+                __syncthreads();
+            }
         }
+        double rz = 0.0;
+        jacobi(lev(0), lev(0).z, lev(0).zt, omega, &rz);
+        return bsum<NT>(rz, red);
     }
 
     // ---------------------------------------------------------- PCG
@@ -317,50 +462,85 @@ struct BatchBlock {
     __device__ int pcg(X* x, double ff, double rr, double tol2, S omega) {
         if (ff == 0.0 || rr <= tol2 * ff) return 0;
         const BLev<S> L = lev(0);
-        S* p = static_cast<S*>(K.pv);
+        S* p = static_cast<S*>(K.pv);      // direction of the last iteration
+        S* pn = static_cast<S*>(K.pv2);    // direction of this iteration
         S* q = static_cast<S*>(K.qv);
-        vcycle(omega);
-        double rz = 0.0;
-        cells(L.d, [&](const Cell& C) {
-            const S z = L.zt[C.id];
-            p[C.id] = z;
-            rz += (double)L.r[C.id] * (double)z;
-        });
-        rz = bsum<NT>(rz, red);
+        double rz = 0.0, beta = 0.0;
+        const S* pold = L.zt;              // first direction: zt + 0 zt = zt
         for (int it = 0; it < K.maxit; ++it) {
+            // preconditioned residual (one call site: the V-cycle is inlined once)
+            const double rzn = vcycle(omega);
+            if (it > 0) {
+                beta = rzn / rz;
+                S* cur = pn;               // the last iteration's direction is this one's p
+                pn = p;
+                p = cur;
+                pold = p;
+            }
+            rz = rzn;
             if (!(rz > 0.0)) return isfinite(rz) ? it : -2;
+            // new direction pn = zt + beta p at c and its four neighbours, q = A pn
             double pq = 0.0;
-            cells(L.d, [&](const Cell& C) {
-                S dg;
-                const S a = bapply(L, C, p, dg);
-                q[C.id] = a;
-                pq += (double)p[C.id] * (double)a;
+            cells_g<2>(L.d, [&](const Cell* C, const bool* on) {
+                S zc[2][5], pc[2][5], bb[2][4];
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+                    if (on[u]) {
+                        const unsigned nb5[5] = {C[u].id, C[u].nb(0, -1), C[u].nb(0, 1), C[u].nb(1, -1),
+                                                 C[u].nb(1, 1)};
+#pragma unroll
+                        for (int k = 0; k < 5; ++k) {
+                            zc[u][k] = L.zt[nb5[k]];
+                            pc[u][k] = pold[nb5[k]];
+                        }
+                        bb[u][0] = L.b0[C[u].id];
+                        bb[u][1] = L.b0[nb5[2]];
+                        bb[u][2] = L.b1[C[u].id];
+                        bb[u][3] = L.b1[nb5[4]];
+                    }
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+                    if (on[u]) {
+                        S v5[5];
+#pragma unroll
+                        for (int k = 0; k < 5; ++k) v5[k] = S((double)zc[u][k] + beta * (double)pc[u][k]);
+                        Stencil<S> st{v5[0], v5[1], v5[2], v5[3], v5[4], bb[u][0], bb[u][1], bb[u][2], bb[u][3]};
+                        S dg;
+                        const S a = st.apply(L.ih2, dg);
+                        pn[C[u].id] = v5[0];
+                        q[C[u].id] = a;
+                        pq += (double)v5[0] * (double)a;
+                    }
             });
             pq = bsum<NT>(pq, red);
             if (!(pq > 0.0)) return isfinite(pq) ? it : -2;
             const double alpha = rz / pq;
             double r2 = 0.0;
-            cells(L.d, [&](const Cell& C) {
-                const unsigned c = C.id;
-                x[c] = X((double)x[c] + alpha * (double)p[c]);
-                const S rn = S((double)L.r[c] - alpha * (double)q[c]);
-                L.r[c] = rn;
-                r2 += (double)rn * (double)rn;
+            cells_g(L.d, [&](const Cell* C, const bool* on) {
+                X xv[UG];
+                S pv[UG], rv[UG], qv[UG];
+#pragma unroll
+                for (int u = 0; u < UG; ++u)
+                    if (on[u]) {
+                        const unsigned c = C[u].id;
+                        xv[u] = x[c];
+                        pv[u] = pn[c];
+                        rv[u] = L.r[c];
+                        qv[u] = q[c];
+                    }
+#pragma unroll
+                for (int u = 0; u < UG; ++u)
+                    if (on[u]) {
+                        const unsigned c = C[u].id;
+                        x[c] = X((double)xv[u] + alpha * (double)pv[u]);
+                        const S rn = S((double)rv[u] - alpha * (double)qv[u]);
+                        L.r[c] = rn;
+                        r2 += (double)rn * (double)rn;
+                    }
             });
             r2 = bsum<NT>(r2, red);
             if (!isfinite(r2)) return -2;
             if (r2 <= tol2 * ff) return it + 1;
-            vcycle(omega);
-            double rzn = 0.0;
-            cells(L.d, [&](const Cell& C) { rzn += (double)L.r[C.id] * (double)L.zt[C.id]; });
-            rzn = bsum<NT>(rzn, red);
-            const double beta = rzn / rz;
-            rz = rzn;
-            cells(L.d, [&](const Cell& C) {
-                const unsigned c = C.id;
-                p[c] = S((double)L.zt[c] + beta * (double)p[c]);
-            });
-            __syncthreads();
         }
         return -1;
     }
@@ -378,32 +558,53 @@ struct BatchBlock {
         const double* x = K.p;
         ff = 0.0;
         rr = 0.0;
-        cells(L.d, [&](const Cell& C) {
-            const unsigned c = C.id;
-            const double f = -(b[c] - mean);
-            double ax;
-            if (FROM_PHI) {
-                auto hr = [&](unsigned q) {
-                    const double v = (double)phi[q];
-                    return h2 + dh * (P.clamp ? fmin(fmax(v, 0.0), 1.0) : v);
-                };
-                const double hc = hr(c);
-                const double bl0 = 1.0 / (hr(C.nb(0, -1)) + hc), bh0 = 1.0 / (hc + hr(C.nb(0, 1)));
-                const double bl1 = 1.0 / (hr(C.nb(1, -1)) + hc), bh1 = 1.0 / (hc + hr(C.nb(1, 1)));
-                const double xc = x[c];
-                ax = (bl0 * (xc - x[C.nb(0, -1)]) - bh0 * (x[C.nb(0, 1)] - xc) +
-                      bl1 * (xc - x[C.nb(1, -1)]) - bh1 * (x[C.nb(1, 1)] - xc)) * ih2;
-            } else {
-                const double bl0 = L.b0[c], bh0 = L.b0[C.nb(0, 1)];
-                const double bl1 = L.b1[c], bh1 = L.b1[C.nb(1, 1)];
-                const double xc = x[c];
-                ax = (bl0 * (xc - x[C.nb(0, -1)]) - bh0 * (x[C.nb(0, 1)] - xc) +
-                      bl1 * (xc - x[C.nb(1, -1)]) - bh1 * (x[C.nb(1, 1)] - xc)) * ih2;
-            }
-            const double r = f - ax;
-            L.r[c] = S(r);
-            ff += f * f;
-            rr += r * r;
+        cells_g<2>(L.d, [&](const Cell* C, const bool* on) {
+            // operands of two cells first: b, x at the cell and its four
+            // neighbours, and phi there (FROM_PHI) or the stored coefficients
+            double bv[2], x5[2][5], c5[2][5];
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+                if (on[u]) {
+                    const unsigned nb5[5] = {C[u].id, C[u].nb(0, -1), C[u].nb(0, 1), C[u].nb(1, -1), C[u].nb(1, 1)};
+                    bv[u] = b[C[u].id];
+#pragma unroll
+                    for (int k = 0; k < 5; ++k) {
+                        x5[u][k] = x[nb5[k]];
+                        if (FROM_PHI) c5[u][k] = (double)phi[nb5[k]];
+                    }
+                    if (!FROM_PHI) {
+                        c5[u][0] = L.b0[C[u].id];
+                        c5[u][1] = L.b0[nb5[2]];
+                        c5[u][2] = L.b1[C[u].id];
+                        c5[u][3] = L.b1[nb5[4]];
+                    }
+                }
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+                if (on[u]) {
+                    const double f = -(bv[u] - mean);
+                    double bl0, bh0, bl1, bh1;
+                    if (FROM_PHI) {
+                        auto hr = [&](double v) { return h2 + dh * (P.clamp ? fmin(fmax(v, 0.0), 1.0) : v); };
+                        const double hc = hr(c5[u][0]);
+                        bl0 = 1.0 / (hr(c5[u][1]) + hc);
+                        bh0 = 1.0 / (hc + hr(c5[u][2]));
+                        bl1 = 1.0 / (hr(c5[u][3]) + hc);
+                        bh1 = 1.0 / (hc + hr(c5[u][4]));
+                    } else {
+                        bl0 = c5[u][0];
+                        bh0 = c5[u][1];
+                        bl1 = c5[u][2];
+                        bh1 = c5[u][3];
+                    }
+                    const double xc = x5[u][0];
+                    const double ax = (bl0 * (xc - x5[u][1]) - bh0 * (x5[u][2] - xc) + bl1 * (xc - x5[u][3]) -
+                                       bh1 * (x5[u][4] - xc)) * ih2;
+                    const double r = f - ax;
+                    L.r[C[u].id] = S(r);
+                    ff += f * f;
+                    rr += r * r;
+                }
         });
         bsum2<NT>(ff, rr, red);
     }
@@ -413,7 +614,14 @@ struct BatchBlock {
     __device__ int poisson(const T* phi) {
         const S omega = S(0.8);
         double mean = 0.0;
-        cells(dims(0), [&](const Cell& C) { mean += K.b[C.id]; });
+        cells_g(dims(0), [&](const Cell* C, const bool* on) {
+            double v[UG];
+#pragma unroll
+            for (int u = 0; u < UG; ++u) v[u] = on[u] ? K.b[C[u].id] : 0.0;
+#pragma unroll
+            for (int u = 0; u < UG; ++u)
+                if (on[u]) mean += v[u];
+        });
         mean = bsum<NT>(mean, red) / (double)ncell(0);
         build_betas(phi);
         int total = 0, outer = 0, status = TPF_OK;
@@ -444,19 +652,49 @@ struct BatchBlock {
                 const int it = pcg<S>(e, rr, rr, tin * tin, omega);
                 if (it == -2) { status = TPF_ENONFINITE; break; }
                 total += it < 0 ? K.maxit : it;
-                cells(dims(0), [&](const Cell& C) { K.p[C.id] += (double)e[C.id]; });
+                cells_g(dims(0), [&](const Cell* C, const bool* on) {
+                    double pv[UG];
+                    S ev[UG];
+#pragma unroll
+                    for (int u = 0; u < UG; ++u)
+                        if (on[u]) {
+                            pv[u] = K.p[C[u].id];
+                            ev[u] = e[C[u].id];
+                        }
+#pragma unroll
+                    for (int u = 0; u < UG; ++u)
+                        if (on[u]) K.p[C[u].id] = pv[u] + (double)ev[u];
+                });
                 __syncthreads();
             }
         }
         // zero-mean gauge
         double sx = 0.0;
-        cells(dims(0), [&](const Cell& C) { sx += K.p[C.id]; });
+        cells_g(dims(0), [&](const Cell* C, const bool* on) {
+            double v[UG];
+#pragma unroll
+            for (int u = 0; u < UG; ++u) v[u] = on[u] ? K.p[C[u].id] : 0.0;
+#pragma unroll
+            for (int u = 0; u < UG; ++u)
+                if (on[u]) sx += v[u];
+        });
         sx = bsum<NT>(sx, red) / (double)ncell(0);
-        cells(dims(0), [&](const Cell& C) { K.p[C.id] -= sx; });
+        cells_g(dims(0), [&](const Cell* C, const bool* on) {
+            double v[UG];
+#pragma unroll
+            for (int u = 0; u < UG; ++u)
+                if (on[u]) v[u] = K.p[C[u].id];
+#pragma unroll
+            for (int u = 0; u < UG; ++u)
+                if (on[u]) K.p[C[u].id] = v[u] - sx;
+        });
         __syncthreads();
         if (threadIdx.x == 0) {
             st->iters = total;
             st->outer = outer;
+            st->solves += 1;
+            st->outer_total += outer;
+            st->inner_total += total;
             st->relres = ff > 0.0 ? sqrt(rr / ff) : 0.0;
         }
         return status;

@@ -41,7 +41,7 @@ EXPORTS = ["tpf_workspace_bytes", "tpf_create", "tpf_destroy", "tpf_set_state", 
            "tpf_batch_config_info", "tpf_batch_set_config", "tpf_batch_tune", "tpf_checkpoint_bytes",
            "tpf_save_checkpoint", "tpf_load_checkpoint", "tpf_adjoint_tape_bytes", "tpf_stage_adjoint",
            "tpf_step_adjoint", "tpf_solver_stats", "tpf_implicit_phase_step", "tpf_field_offset",
-           "tpf_state_changed", "tpf_diagnostics_noalloc"]
+           "tpf_state_changed", "tpf_diagnostics_noalloc", "tpf_batch_solver_stats"]
 
 TPF_STATE_PHI, TPF_STATE_U0, TPF_STATE_U1, TPF_STATE_U2, TPF_STATE_P = 0, 1, 2, 3, 4
 TPF_DTYPE_F64, TPF_DTYPE_F32 = 0, 1
@@ -140,6 +140,8 @@ def lib():
         "tpf_batch_config_info": ([i32, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
         "tpf_batch_set_config": ([vp, i32], i32),
         "tpf_batch_tune": ([vp, dp, ctypes.c_char_p, ctypes.POINTER(i32)], i32),
+        "tpf_batch_solver_stats": ([vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                    ctypes.POINTER(ctypes.c_int64), i32], i32),
         "tpf_checkpoint_bytes": ([vp, ctypes.POINTER(ctypes.c_size_t)], i32),
         "tpf_solver_stats": ([vp, ctypes.POINTER(ctypes.c_int64), i32], i32),
         "tpf_save_checkpoint": ([vp, vp], i32),
@@ -541,6 +543,14 @@ class Batch:
 
     def set_config(self, config: int):
         check(lib().tpf_batch_set_config(self.h, int(config)), "tpf_batch_set_config")
+
+    def solver_stats(self, reset: bool = False) -> dict:
+        """Per-case pressure solves and their outer and PCG iterations since
+        the last reset (numpy int64 arrays)."""
+        out = [np.zeros(self.ncases, dtype=np.int64) for _ in range(3)]
+        ptrs = [x.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)) for x in out]
+        check(lib().tpf_batch_solver_stats(self.h, *ptrs, int(reset)), "tpf_batch_solver_stats")
+        return {"solves": out[0], "outer": out[1], "inner": out[2]}
 
     def tune(self, dt, cache_path=None) -> int:
         d, dp = self._dts(dt)

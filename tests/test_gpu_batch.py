@@ -314,6 +314,53 @@ def test_batch_tuner_cache(gpu):
         assert (b.status()[0] == 0).all()
 
 
+def test_batch_tuning_leaves_the_run_unchanged(gpu):
+    """Tuning between steps times stage evaluations only: with the same launch
+    configuration afterwards, a tuned batch steps bit for bit like an untuned
+    one (state, pressure warm start, status and step count untouched)."""
+    cases = mixed_cases("fp32_mixed")
+    say("batch tuning is invisible")
+    dts = np.array([c.dt() for c in cases])
+    runs = []
+    for tune in (False, True):
+        b = gpu.Batch([gpu.params_for_case(c) for c in cases])
+        b.set_config(2)
+        for q, c in enumerate(cases):
+            b.init_droplet(q, c.center, c.semi_axes)
+        b.step(dts, 2)
+        if tune:
+            b.tune(dts, None)
+            b.set_config(2)
+        b.step(dts, 3)
+        st, nst, t = b.status()
+        assert (st == 0).all() and (nst == 5).all()
+        runs.append([b.get_state(q, with_pressure=True) for q in range(len(cases))])
+        b.close()
+    for q in range(len(cases)):
+        for k in (0, 2):
+            assert np.array_equal(runs[0][q][k], runs[1][q][k]), (q, k)
+        for a in range(2):
+            assert np.array_equal(runs[0][q][1][a], runs[1][q][1][a]), (q, a)
+
+
+def test_batch_solver_stats(gpu):
+    """Per-case pressure-solve counters: four solves per step, PCG
+    iterations counted, zero after a reset."""
+    cases = mixed_cases("fp32_mixed")
+    say("batch solver counters")
+    dts = np.array([c.dt() for c in cases])
+    b = gpu.Batch([gpu.params_for_case(c) for c in cases])
+    for q, c in enumerate(cases):
+        b.init_droplet(q, c.center, c.semi_axes)
+    b.solver_stats(reset=True)
+    b.step(dts, 3)
+    s = b.solver_stats(reset=True)
+    assert (s["solves"] == 12).all()
+    assert (s["inner"] >= s["outer"]).all() and (s["inner"] > 0).all()
+    z = b.solver_stats()
+    assert (z["solves"] == 0).all() and (z["inner"] == 0).all()
+
+
 def test_batch_diagnostics_match_single_case(gpu):
     cases = mixed_cases("fp64")[:3]
     say("batch diagnostics")
@@ -333,3 +380,35 @@ def test_batch_diagnostics_match_single_case(gpu):
         for k in ("ke", "umax", "dp"):
             assert abs(dg[q][k] - ds[k]) <= 1e-8 * max(abs(ds[k]), 1e-300), (c.name, k)
         assert dg[q]["step"] == 3
+
+
+@pytest.mark.fullsize
+def test_batch_workload_sample_against_oracle(gpu, ora):
+    """The 512-drop batched workload (FP32-mixed, its launch configuration
+    picked by the tuner): a seeded sample of 16 of its cases
+    (default_rng(3)), 2 steps, against the FP64 oracle on each case from the
+    same FP32-rounded initial phi: phi to 1e-5, u to 1e-2 of its max (the
+    single-case mixed-precision bounds)."""
+    cases = workloads.batched_cases(512)
+    pick = sorted(int(q) for q in np.random.default_rng(3).choice(len(cases), 16, replace=False))
+    say(f"batch workload: 512 cases, oracle sample {pick}")
+    b = gpu.Batch([gpu.params_for_case(c) for c in cases])
+    for q, c in enumerate(cases):
+        b.init_droplet(q, c.center, c.semi_axes)
+    dts = np.array([c.dt() for c in cases])
+    b.tune(dts)
+    phi0 = {q: b.get_state(q)[0] for q in pick}      # FP32-rounded initial phi
+    b.step(dts, 2)
+    worst_phi = worst_u = 0.0
+    for q in pick:
+        c = cases[q]
+        P = oparams(ora, c)
+        phi_o, u_o, _ = ora.step(P, dts[q], 2, phi0[q], [np.zeros(P.shape)] * 2)
+        phi_g, u_g, _ = b.get_state(q)
+        umax = max(np.abs(x).max() for x in u_o)
+        ephi = np.abs(phi_g - phi_o).max()
+        eu = max(np.abs(u_g[a] - u_o[a]).max() for a in range(2)) / umax
+        worst_phi, worst_u = max(worst_phi, ephi), max(worst_u, eu)
+        say(f"  case {q} {c.n}: |dphi| {ephi:.2e} |du|/|u| {eu:.2e}")
+        assert ephi < 1e-5 and eu < 1e-2, q
+    say(f"  worst: |dphi| {worst_phi:.2e} |du|/|u| {worst_u:.2e}")
