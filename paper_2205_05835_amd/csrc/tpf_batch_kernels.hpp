@@ -548,8 +548,11 @@ struct BatchBlock {
     // r = f - A x with f = -(b - mean) on level 0; FP64 coefficients straight
     // from phi when R64 (the outer residual of the mixed path), else the
     // stored level-0 coefficients.  r stored in precision S.  ff, rr out.
+    // aa: | |A||x| |^2, the squared sum of the face-flux magnitudes per cell
+    // (the rounding level of the explicit FP64 residual, as in the
+    // single-case solver)
     template <bool FROM_PHI>
-    __device__ void residual(const T* phi, double mean, double& ff, double& rr) {
+    __device__ void residual(const T* phi, double mean, double& ff, double& rr, double& aa) {
         const BLev<S> L = lev(0);
         const Phys& P = K.P;
         const double h2 = 0.5 * P.rho2, dh = 0.5 * (P.rho1 - P.rho2);
@@ -558,6 +561,7 @@ struct BatchBlock {
         const double* x = K.p;
         ff = 0.0;
         rr = 0.0;
+        aa = 0.0;
         cells_g<2>(L.d, [&](const Cell* C, const bool* on) {
             // operands of two cells first: b, x at the cell and its four
             // neighbours, and phi there (FROM_PHI) or the stored coefficients
@@ -604,9 +608,13 @@ struct BatchBlock {
                     L.r[C[u].id] = S(r);
                     ff += f * f;
                     rr += r * r;
+                    const double am = (fabs(bl0 * (xc - x5[u][1])) + fabs(bh0 * (x5[u][2] - xc)) +
+                                       fabs(bl1 * (xc - x5[u][3])) + fabs(bh1 * (x5[u][4] - xc))) * ih2;
+                    aa += am * am;
                 }
         });
         bsum2<NT>(ff, rr, red);
+        aa = bsum<NT>(aa, red);
     }
 
     // Pressure solve for the current b (FP64, mean removed here): returns
@@ -625,9 +633,11 @@ struct BatchBlock {
         mean = bsum<NT>(mean, red) / (double)ncell(0);
         build_betas(phi);
         int total = 0, outer = 0, status = TPF_OK;
-        double ff = 0.0, rr = 0.0;
+        double ff = 0.0, rr = 0.0, aa = 0.0;
+        // squared rounding level of the explicit residual (16 ulps of |A||x|)
+        const double fl2 = (16.0 * 0x1p-53) * (16.0 * 0x1p-53);
         if constexpr (sizeof(T) == 8) {
-            residual<false>(phi, mean, ff, rr);
+            residual<false>(phi, mean, ff, rr, aa);
             if (!isfinite(ff) || !isfinite(rr)) status = TPF_ENONFINITE;
             else {
                 const int it = pcg<double>(K.p, ff, rr, K.rtol * K.rtol, omega);
@@ -635,14 +645,14 @@ struct BatchBlock {
                 else if (it < 0) status = TPF_ENOCONV;
                 else total = it;
                 outer = 1;
-                residual<false>(phi, mean, ff, rr);
+                residual<false>(phi, mean, ff, rr, aa);
             }
         } else {
             status = TPF_ENOCONV;
             for (int o = 0; o < 12; ++o) {
-                residual<true>(phi, mean, ff, rr);
+                residual<true>(phi, mean, ff, rr, aa);
                 if (!isfinite(ff) || !isfinite(rr)) { status = TPF_ENONFINITE; break; }
-                if (ff == 0.0 || rr <= K.rtol * K.rtol * ff) { status = TPF_OK; outer = o; break; }
+                if (ff == 0.0 || rr <= K.rtol * K.rtol * ff || rr <= fl2 * aa) { status = TPF_OK; outer = o; break; }
                 S* e = static_cast<S*>(K.ev);
                 cells(dims(0), [&](const Cell& C) { e[C.id] = S(0); });
                 __syncthreads();

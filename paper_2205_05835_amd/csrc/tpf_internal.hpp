@@ -26,6 +26,7 @@ struct SolverScalars {
     double alpha, beta;
     double tol2;       // stop when rr <= tol2 * ff
     double sum;        // generic sum (mean removal)
+    double floor2;     // explicit residuals: squared rounding level of their FP64 evaluation
     int done;          // PCG finished (converged, or no work)
     int iters;         // PCG iterations performed
     int pad[2];
@@ -45,7 +46,8 @@ struct PubScalars {
 // Finalize operations on reduced partial sums (one single-block kernel).
 enum FinOp {
     FIN_MEAN = 0,   // v0 = sum b           -> mean = v0 / N
-    FIN_INIT = 1,   // v0 = ff, v1 = rr     -> ff, rr, done = rr <= tol2 ff
+    FIN_INIT = 1,   // v0 = ff, v1 = rr, v2 = |A||x| squared -> ff, rr, floor2,
+                    //                  done = rr <= max(tol2 ff, floor2)
     FIN_RZ0 = 2,    // v0 = rz              -> rz (first), keeps done
     FIN_ALPHA = 3,  // v0 = pq              -> alpha = rz / pq
     FIN_BETA = 4,   // v0 = rr, v1 = rz_new, v2 = <A p, z_new> -> beta = -v2 / pq, rz, rr, done, iters++

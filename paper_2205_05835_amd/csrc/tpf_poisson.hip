@@ -36,6 +36,9 @@
 #include <type_traits>
 #include <vector>
 
+#include <cstdio>
+#include <string>
+
 #include "tpf_internal.hpp"
 
 namespace tpf {
@@ -66,6 +69,32 @@ __device__ __forceinline__ void block_partials_2r(double (&v)[2], double* partia
         partials[b] = v[0];
         partials[stride + b] = v[1];
     }
+}
+__device__ __forceinline__ void block_partials_3r(double (&v)[3], double* partials, long stride) {
+    block_sum<3>(v);
+    if (thread_linear() == 0) {
+        const int b = block_linear();
+        partials[b] = v[0];
+        partials[stride + b] = v[1];
+        partials[2 * stride + b] = v[2];
+    }
+}
+
+// The rounding level of an explicitly evaluated residual f - A x: each cell's
+// value is a sum of face fluxes beta (x_nb - x_c) / h^2 that can be much
+// larger than the result (a smooth pressure with a large jump, a density
+// ratio of 1000), and FP64 evaluates it to within a few ulps of the sum of
+// their magnitudes.  A solve whose explicit residual reaches
+// RESID_FLOOR_ULPS u |A||x| (u = 2^-53, norms over all cells) is as
+// converged as FP64 can tell.
+constexpr double RESID_FLOOR_ULPS = 16.0;
+template <typename S, int DIM, typename Fx>
+__device__ __forceinline__ double abs_flux_sum(const S* bl, const S* bh, Fx x, S xc, S ih2) {
+    double s = 0.0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+        s += fabs((double)bl[a] * (double)(xc - x(a, -1))) + fabs((double)bh[a] * (double)(x(a, 1) - xc));
+    return s * (double)ih2;
 }
 
 // ---------------------------------------------------------------- coefficients
@@ -205,19 +234,22 @@ __global__ __launch_bounds__(BLOCK) void k_resid(Dims d, S ih2, Coef cf,
                                                  const SolverScalars* __restrict__ sc,
                                                  double* __restrict__ partials, long stride) {
     Cell C;
-    double v[2] = {0.0, 0.0};
+    double v[3] = {0.0, 0.0, 0.0};
     if (cell_of_thread(d, C)) {
         S bl[3], bh[3], dg;
         cf.template faces<DIM>(C, bl, bh);
         const unsigned c = C.id;
         auto X = [&](int a, int s) { return S(ld(x, C.nb(a, s))); };
         const double f = -(ld(b, c) - sc->mean);
-        const double rc = f - (double)apply_at<S, DIM>(bl, bh, X, S(ld(x, c)), ih2, dg);
+        const S xc = S(ld(x, c));
+        const double rc = f - (double)apply_at<S, DIM>(bl, bh, X, xc, ih2, dg);
         st(r, c, R(rc));
         v[0] = f * f;
         v[1] = rc * rc;
+        const double ax = abs_flux_sum<S, DIM>(bl, bh, X, xc, ih2);
+        v[2] = ax * ax;
     }
-    block_partials_2r(v, partials, stride);
+    block_partials_3r(v, partials, stride);
 }
 
 // ---------------------------------------------------------------- smoothing
@@ -1006,12 +1038,13 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finalize(int nb0, int nb1, int 
     case FIN_MEAN:    // region 0: sum b
         sc->mean = s0 / (double)N;
         break;
-    case FIN_INIT:    // region 0: |f|^2, region 1: |r|^2
+    case FIN_INIT:    // region 0: |f|^2, region 1: |r|^2, region 2: | |A||x| |^2
         sc->ff = s0;
         sc->rr = s1;
         sc->tol2 = arg;
         sc->iters = 0;
-        sc->done = (s0 == 0.0 || s1 <= arg * s0) ? 1 : 0;
+        sc->floor2 = (RESID_FLOOR_ULPS * 0x1p-53) * (RESID_FLOOR_ULPS * 0x1p-53) * s2;
+        sc->done = (s0 == 0.0 || s1 <= arg * s0 || (arg > 0.0 && s1 <= sc->floor2)) ? 1 : 0;
         break;
     case FIN_RZ0:     // region 1: <r, z>
         sc->rz = s1;
@@ -1534,7 +1567,7 @@ __global__ __launch_bounds__(BLOCK) void k_fz_resid(Dims d, int kz, S ih2, Coef 
     const double mean = sc->mean;
     auto fld = [&](unsigned idx, int, int, int) -> S { return S(ld(x, idx)); };
     auto pre = [&](unsigned c) -> double { return ld(b, c); };
-    double v[2] = {0.0, 0.0};
+    double v[3] = {0.0, 0.0, 0.0};
     march_kz<Coef, S, true>(q, cf, kz, fld, Ident<S>{}, pre,
                          [&](int, unsigned c, const Nbr7<S>& Rh, const Nbr7<S>& X, double bc) {
         S bl[3], bh[3], dg;
@@ -1546,9 +1579,14 @@ __global__ __launch_bounds__(BLOCK) void k_fz_resid(Dims d, int kz, S ih2, Coef 
             st(r, c, R(rr));
             v[0] += f * f;
             v[1] += rr * rr;
+            const double aa = (fabs((double)bl[0] * (double)(X.c - X.xm)) + fabs((double)bh[0] * (double)(X.xp - X.c)) +
+                               fabs((double)bl[1] * (double)(X.c - X.ym)) + fabs((double)bh[1] * (double)(X.yp - X.c)) +
+                               fabs((double)bl[2] * (double)(X.c - X.zm)) + fabs((double)bh[2] * (double)(X.zp - X.c))) *
+                              (double)ih2;
+            v[2] += aa * aa;
         }
     });
-    block_partials_2r(v, partials, stride);
+    block_partials_3r(v, partials, stride);
 }
 
 // ================================================================== host driver
@@ -2049,7 +2087,7 @@ tpf_status poisson_solve(tpf_ctx* c, const void* phi, int* iters, double* relres
         const bool fixed = c->fixed_inner > 0;
         sv.build_betas(phi);
         sv.residual<double>(sv.coef_fine(), tp<double>(c->lv[0].r));
-        (void)finalize2(c, (int)sv.nb0(), (int)sv.nb0(), FIN_INIT, fixed ? 0.0 : rtol * rtol);
+        (void)finalize3(c, (int)sv.nb0(), (int)sv.nb0(), (int)sv.nb0(), FIN_INIT, fixed ? 0.0 : rtol * rtol);
         bool have = false;
         e = sv.pcg<double>(phi, c->p, fixed ? c->fixed_inner : maxit, 0, &s, &have);
         if (e != hipSuccess) return hip_fail(e, "FP64 PCG");
@@ -2082,9 +2120,10 @@ tpf_status poisson_solve(tpf_ctx* c, const void* phi, int* iters, double* relres
     // iterations, then one more residual for the reported relres
     const bool fixed = c->fixed_inner > 0;
     const int max_outer = fixed ? c->fixed_outer + 1 : 12;
+    std::string trail;      // relative outer residual after each pass, for the failure message
     for (int o = 0; o < max_outer; ++o) {
         s64.residual<float>(s64.coef_phi(phi), tp<float>(c->lv[0].r));   // FP64 residual, FP64 beta
-        (void)finalize2(c, (int)s64.nb0(), (int)s64.nb0(), FIN_INIT, fixed ? 0.0 : rtol * rtol);
+        (void)finalize3(c, (int)s64.nb0(), (int)s64.nb0(), (int)s64.nb0(), FIN_INIT, fixed ? 0.0 : rtol * rtol);
         // the inner solve aims straight at the outer tolerance (half of the
         // reduction it needs), but never below rin, the depth an FP32 PCG
         // reaches reliably; a further outer pass picks up the rest.  The
@@ -2106,6 +2145,10 @@ tpf_status poisson_solve(tpf_ctx* c, const void* phi, int* iters, double* relres
                 *relres = s.ff > 0 ? std::sqrt(s.rr / s.ff) : 0.0;
                 return TPF_OK;
             }
+            char buf[48];
+            std::snprintf(buf, sizeof(buf), " %.2e (floor %.1e)", s.ff > 0 ? std::sqrt(s.rr / s.ff) : 0.0,
+                          s.ff > 0 ? std::sqrt(s.floor2 / s.ff) : 0.0);
+            trail += buf;
             const double need = 0.5 * rtol * std::sqrt(s.ff / s.rr);
             const double tin = fixed ? 0.0 : std::min(0.1, std::max(rin, need));
             k_inner_setup<<<1, 64, 0, c->stream>>>(c->scal, tin * tin);
@@ -2139,7 +2182,7 @@ tpf_status poisson_solve(tpf_ctx* c, const void* phi, int* iters, double* relres
         k_correct<<<vgrid(c->N), BLOCK, 0, c->stream>>>(c->N, c->p, tp<float>(c->ev));
         prof_end(c);
     }
-    set_error("pressure defect correction did not converge");
+    set_error("pressure defect correction did not converge (relative residual after each pass:" + trail + ")");
     return TPF_ENOCONV;
 }
 

@@ -151,3 +151,35 @@ def test_two_steps_96cubed_fp32_mixed(gpu, ora, setup, oracle_steps):
     ep = rel(p_g, p_o)
     say(f"  |dphi| {ephi:.2e}  |du|/Uref {eu:.2e}  |dp|/|p| {ep:.2e}")
     assert ephi < 1e-6 and eu < 1e-3 and ep < 1e-5
+
+
+def test_ratio1000_static_drop_256sq_50_steps_fp64(gpu, ora):
+    """The density-ratio-1000 static drop at full size (256^2, eps = 0.51 h,
+    the boundedness edge; CDI + energy-based force; FP64), 50 RK4 steps (200
+    pressure solves) against the oracle.  Condition number of the projection
+    here ~ d n^2 / pi^2 x 1000 = 1.3e7; measured: phi 2e-15, u 6e-14 of U_ref,
+    p 1e-14, dp 4e-14 (bounds 1e-12)."""
+    case = workloads.static_drop_ratio(256, 0.51, "CDI", "EB")
+    P = ora.Params(n=case.n, length=case.length, model=ora.MODELS[case.model],
+                   force=ora.FORCES[case.force], sigma=case.sigma, eps=case.eps, gamma=case.gamma,
+                   rho1=case.rho1, rho2=case.rho2, visc1=case.visc1, visc2=case.visc2)
+    phi0 = ora.init_droplet(P, case.center, case.semi_axes)
+    zero = [np.zeros(P.shape)] * 2
+    dt, steps = case.dt(), 50
+    say(f"ratio-1000 drop 256^2, 50 steps: oracle ({ora.threads()} threads)")
+    phi_o, u_o, pw = ora.step(P, dt, steps, phi0, zero)
+    _, du_o, p_o = ora.stage(P, phi_o, u_o, pw)
+    s = gpu.solver_for_case(case, poisson_rtol=1e-14, poisson_maxit=4000)
+    s.set_state(phi0, zero)
+    s.step(dt, steps)
+    phi_g, u_g, p_g = s.get_state(with_pressure=True)
+    uref = max(max(np.abs(x).max() for x in u_o), dt * max(np.abs(x).max() for x in du_o))
+    ephi = np.abs(phi_g - phi_o).max()
+    eu = max(np.abs(u_g[a] - u_o[a]).max() for a in range(2)) / uref
+    ep = rel(p_g, p_o)
+    dg = s.diagnostics()
+    do = ora.diagnostics(P, phi_o, u_o, p_o)
+    edp = abs(dg["dp"] - do["dp"]) / abs(do["dp"])
+    say(f"  |dphi| {ephi:.2e}  |du|/Uref {eu:.2e}  |dp|/|p| {ep:.2e}  dp {dg['dp']:.6f} (err {edp:.1e})")
+    assert ephi < 1e-12 and eu < 1e-12 and ep < 1e-12 and edp < 1e-12
+    assert abs(dg["mass"] - dg["mass0"]) / dg["mass0"] < 1e-13
