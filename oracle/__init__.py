@@ -53,7 +53,8 @@ class _P(ctypes.Structure):
                 ("rho1", ctypes.c_double), ("rho2", ctypes.c_double),
                 ("visc1", ctypes.c_double), ("visc2", ctypes.c_double),
                 ("delta", ctypes.c_double), ("clamp", ctypes.c_int),
-                ("poisson_rtol", ctypes.c_double), ("poisson_maxit", ctypes.c_int)]
+                ("poisson_rtol", ctypes.c_double), ("poisson_maxit", ctypes.c_int),
+                ("walls", ctypes.c_int)]
 
 
 @dataclass
@@ -74,6 +75,7 @@ class Params:
     clamp: int = 1
     poisson_rtol: float = 1e-14
     poisson_maxit: int = 200000
+    walls: int = 0           # bit a: free-slip walls at both ends of axis a (x = bit 0)
 
     @property
     def dim(self) -> int:
@@ -95,7 +97,8 @@ class Params:
         n3 = list(self.n) + [1] * (3 - len(self.n))
         return _P(self.dim, (ctypes.c_int * 3)(*n3), self.h, int(self.model), int(self.force),
                   self.sigma, self.epsilon, self.gamma, self.rho1, self.rho2, self.visc1,
-                  self.visc2, self.delta, int(self.clamp), self.poisson_rtol, self.poisson_maxit)
+                  self.visc2, self.delta, int(self.clamp), self.poisson_rtol, self.poisson_maxit,
+                  int(self.walls))
 
 
 _lib = None

@@ -18,6 +18,13 @@
  *   C_a q[c] = (q[c+e_a] - q[c-e_a]) / (2h)     central cell gradient
  *   L        = D o G
  *
+ * An axis is periodic, or bounded by free-slip walls at both ends (the box
+ * of Sec. 3.1 and the top and bottom of Sec. 3.2).  A free-slip wall is a
+ * mirror plane of the solution: values outside the box are read from the
+ * mirror image (fetch() below), which makes the normal velocity, the normal
+ * derivative of the tangential velocity and of phi, and the normal pressure
+ * gradient vanish on the wall.
+ *
  * Everything is written for clarity, not speed: full temporaries, no fusion.
  * Loops are parallelised over grid rows with OpenMP; every reduction is
  * summed per row and then over rows in a fixed order, so results do not
@@ -50,17 +57,52 @@ static long at(const ora_params* P, int i, int j, int k) {
     return ((long)k * P->n[1] + j) * P->n[0] + i;
 }
 
-/* index of cell (i,j,k) + s e_a + t e_b */
-static long sh2(const ora_params* P, int i, int j, int k, int a, int s, int b, int t) {
+/* Boundary rules.  A periodic axis wraps.  A walled axis a reads values
+ * outside the box from the mirror image in the wall: a cell field is even
+ * (cell -1-m holds cell m, cell n+m holds cell n-1-m); the a-component of a
+ * cell vector (a normal) is odd; a face field normal to a is odd about the
+ * wall faces 0 and n, which hold 0 (face -m holds minus face m); a face field
+ * normal to another axis is even like a cell field. */
+enum { K_CELL = 0, K_ODD = 1, K_FACE = 2 };
+#define KIND_ODD(a) (K_ODD + 4 * (a))    /* cell vector component along a */
+#define KIND_FACE(a) (K_FACE + 4 * (a))  /* face field normal to axis a   */
+
+static int walled(const ora_params* P, int a) { return a < P->dim && ((P->walls >> a) & 1); }
+
+/* value of field q (kind) at cell or face (i, j, k), at most two cells outside the box */
+static double fetch(const ora_params* P, const double* q, int kind, int i, int j, int k) {
+    int v[3] = {i, j, k};
+    double sign = 1.0;
+    const int base = kind & 3, ax = kind >> 2;
+    for (int a = 0; a < 3; ++a) {
+        const int n = P->n[a];
+        if (!walled(P, a)) {
+            v[a] = wrapi(v[a], n);
+        } else if (base == K_FACE && ax == a) {
+            if (v[a] == 0 || v[a] == n) return 0.0;
+            if (v[a] < 0) { v[a] = -v[a]; sign = -sign; }
+            else if (v[a] > n) { v[a] = 2 * n - v[a]; sign = -sign; }
+        } else {
+            const int odd = base == K_ODD && ax == a;
+            if (v[a] < 0) { v[a] = -1 - v[a]; if (odd) sign = -sign; }
+            else if (v[a] >= n) { v[a] = 2 * n - 1 - v[a]; if (odd) sign = -sign; }
+        }
+    }
+    return sign * q[((long)v[2] * P->n[1] + v[1]) * P->n[0] + v[0]];
+}
+
+/* q (kind) at (i,j,k) + s e_a, and at (i,j,k) + s e_a + t e_b */
+static double fsh(const ora_params* P, const double* q, int kind, int i, int j, int k, int a, int s) {
+    int v[3] = {i, j, k};
+    v[a] += s;
+    return fetch(P, q, kind, v[0], v[1], v[2]);
+}
+static double fsh2(const ora_params* P, const double* q, int kind, int i, int j, int k, int a, int s,
+                   int b, int t) {
     int v[3] = {i, j, k};
     v[a] += s;
     v[b] += t;
-    return at(P, v[0], v[1], v[2]);
-}
-
-/* index of cell (i,j,k) + s e_a */
-static long sh(const ora_params* P, int i, int j, int k, int a, int s) {
-    return sh2(P, i, j, k, a, s, a, 0);
+    return fetch(P, q, kind, v[0], v[1], v[2]);
 }
 
 #define FOR_CELLS(P)                                             \
@@ -133,7 +175,7 @@ static double visc_of(const ora_params* P, double f) {
 
 /* face density A_a rho and its inverse beta_a on face (c, a) */
 static double rho_face(const ora_params* P, const double* phi, int i, int j, int k, int a) {
-    return 0.5 * (rho_of(P, phi[sh(P, i, j, k, a, -1)]) + rho_of(P, phi[at(P, i, j, k)]));
+    return 0.5 * (rho_of(P, fsh(P, phi, K_CELL, i, j, k, a, -1)) + rho_of(P, phi[at(P, i, j, k)]));
 }
 static double beta_face(const ora_params* P, const double* phi, int i, int j, int k, int a) {
     return 1.0 / rho_face(P, phi, i, j, k, a);
@@ -143,27 +185,30 @@ static double beta_face(const ora_params* P, const double* phi, int i, int j, in
 /* discrete operators                                                     */
 /* ---------------------------------------------------------------------- */
 
-static double opA(const ora_params* P, const double* q, int i, int j, int k, int a) {
-    return 0.5 * (q[sh(P, i, j, k, a, -1)] + q[at(P, i, j, k)]);
+/* A_a q (q of the given kind), G_a q and L q of a cell field, C_a q */
+static double opA(const ora_params* P, const double* q, int kind, int i, int j, int k, int a) {
+    return 0.5 * (fsh(P, q, kind, i, j, k, a, -1) + fetch(P, q, kind, i, j, k));
 }
 static double opG(const ora_params* P, const double* q, int i, int j, int k, int a) {
-    return (q[at(P, i, j, k)] - q[sh(P, i, j, k, a, -1)]) / P->h;
+    return (fetch(P, q, K_CELL, i, j, k) - fsh(P, q, K_CELL, i, j, k, a, -1)) / P->h;
 }
-static double opC(const ora_params* P, const double* q, int i, int j, int k, int a) {
-    return (q[sh(P, i, j, k, a, 1)] - q[sh(P, i, j, k, a, -1)]) / (2.0 * P->h);
+static double opC(const ora_params* P, const double* q, int kind, int i, int j, int k, int a) {
+    return (fsh(P, q, kind, i, j, k, a, 1) - fsh(P, q, kind, i, j, k, a, -1)) / (2.0 * P->h);
 }
+/* D F of face fields F_a (normal to a) */
 static double opD(const ora_params* P, double* const F[3], int i, int j, int k) {
     double s = 0.0;
     for (int a = 0; a < P->dim; ++a)
-        s += (F[a][sh(P, i, j, k, a, 1)] - F[a][at(P, i, j, k)]) / P->h;
+        s += (fsh(P, F[a], KIND_FACE(a), i, j, k, a, 1) - fetch(P, F[a], KIND_FACE(a), i, j, k)) / P->h;
     return s;
 }
 /* L = D o G written out */
 static double opL(const ora_params* P, const double* q, int i, int j, int k) {
     double s = 0.0;
+    const double qc = fetch(P, q, K_CELL, i, j, k);
     for (int a = 0; a < P->dim; ++a) {
-        double gp = (q[sh(P, i, j, k, a, 1)] - q[at(P, i, j, k)]) / P->h;
-        double gm = (q[at(P, i, j, k)] - q[sh(P, i, j, k, a, -1)]) / P->h;
+        double gp = (fsh(P, q, K_CELL, i, j, k, a, 1) - qc) / P->h;
+        double gm = (qc - fsh(P, q, K_CELL, i, j, k, a, -1)) / P->h;
         s += (gp - gm) / P->h;
     }
     return s;
@@ -187,7 +232,7 @@ void ora_normals(const ora_params* P, const double* phi, double* nx, double* ny,
         long c = at(P, i, j, k);
         double g[3] = {0.0, 0.0, 0.0}, gg = 0.0;
         for (int a = 0; a < P->dim; ++a) {
-            g[a] = opC(P, phi, i, j, k, a);
+            g[a] = opC(P, phi, K_CELL, i, j, k, a);
             gg += g[a] * g[a];
         }
         double den = sqrt(gg + P->delta * P->delta);
@@ -203,7 +248,7 @@ void ora_curvature(const ora_params* P, const double* phi, double* kappa) {
     ora_normals(P, phi, n[0], n[1], n[2], NULL);
     FOR_CELLS(P) {
         double s = 0.0;
-        for (int a = 0; a < P->dim; ++a) s += opC(P, n[a], i, j, k, a);
+        for (int a = 0; a < P->dim; ++a) s += opC(P, n[a], KIND_ODD(a), i, j, k, a);
         kappa[at(P, i, j, k)] = -s;
     }
     for (int a = 0; a < 3; ++a) free(n[a]);
@@ -239,7 +284,7 @@ void ora_cdi_flux(const ora_params* P, const double* phi, double* r0, double* r1
     FOR_CELLS(P) {
         long c = at(P, i, j, k);
         for (int a = 0; a < P->dim; ++a)
-            r[a][c] = P->gamma * (P->eps * opG(P, phi, i, j, k, a) - opA(P, w[a], i, j, k, a));
+            r[a][c] = P->gamma * (P->eps * opG(P, phi, i, j, k, a) - opA(P, w[a], KIND_ODD(a), i, j, k, a));
     }
     for (int a = 0; a < 3; ++a) { free(n[a]); free(w[a]); }
 }
@@ -276,7 +321,8 @@ void ora_phase_rhs(const ora_params* P, const double* phi, const double* u0,
     double* g = alloc0(P);
     FOR_CELLS(P) {
         long c = at(P, i, j, k);
-        for (int a = 0; a < P->dim; ++a) J[a][c] = u[a][c] * opA(P, phi, i, j, k, a);
+        for (int a = 0; a < P->dim; ++a)
+            J[a][c] = fetch(P, u[a], KIND_FACE(a), i, j, k) * opA(P, phi, K_CELL, i, j, k, a);
     }
     ora_regularization(P, phi, g);
     FOR_CELLS(P) {
@@ -311,16 +357,16 @@ void ora_surface_force(const ora_params* P, const double* phi, double* F0,
             double f;
             switch (P->force) {
             case ORA_EB:   /* F = mu grad phi (Eq. 4), + sign on the momentum RHS */
-                f = opA(P, mu, i, j, k, a) * gphi;
+                f = opA(P, mu, K_CELL, i, j, k, a) * gphi;
                 break;
             case ORA_CSF:  /* F = sigma kappa grad phi */
-                f = P->sigma * opA(P, kappa, i, j, k, a) * gphi;
+                f = P->sigma * opA(P, kappa, K_CELL, i, j, k, a) * gphi;
                 break;
             case ORA_LCSF: /* F = sigma_hat kappa phi(1-phi) grad phi (Eq. 11) */
-                f = sh_ * opA(P, kappa, i, j, k, a) * opA(P, w, i, j, k, a) * gphi;
+                f = sh_ * opA(P, kappa, K_CELL, i, j, k, a) * opA(P, w, K_CELL, i, j, k, a) * gphi;
                 break;
             default:       /* EB minus the gradient G(mu phi): -A(phi) G(mu) */
-                f = -opA(P, phi, i, j, k, a) * opG(P, mu, i, j, k, a);
+                f = -opA(P, phi, K_CELL, i, j, k, a) * opG(P, mu, i, j, k, a);
                 break;
             }
             F[a][c] = f;
@@ -347,7 +393,8 @@ void ora_mass_flux(const ora_params* P, const double* phi, const double* u0,
     FOR_CELLS(P) {
         long c = at(P, i, j, k);
         for (int a = 0; a < P->dim; ++a)
-            m[a][c] = rho_face(P, phi, i, j, k, a) * u[a][c] - (P->rho1 - P->rho2) * r[a][c];
+            m[a][c] = rho_face(P, phi, i, j, k, a) * fetch(P, u[a], KIND_FACE(a), i, j, k) -
+                      (P->rho1 - P->rho2) * r[a][c];
     }
     for (int a = 0; a < 3; ++a) free(r[a]);
 }
@@ -367,23 +414,27 @@ void ora_advection(const ora_params* P, const double* m0, const double* m1,
     FOR_CELLS(P) {
         long c = at(P, i, j, k);
         for (int a = 0; a < P->dim; ++a) {
+            const int fa = KIND_FACE(a);
             double s = 0.0;
             for (int b = 0; b < P->dim; ++b) {
                 double phi_hi, phi_lo;
                 if (b == a) {
-                    long cp = sh(P, i, j, k, a, 1), cm = sh(P, i, j, k, a, -1);
-                    phi_hi = 0.5 * (m[a][c] + m[a][cp]) * 0.5 * (u[a][c] + u[a][cp]);
-                    phi_lo = 0.5 * (m[a][cm] + m[a][c]) * 0.5 * (u[a][cm] + u[a][c]);
+                    double mc = fetch(P, m[a], fa, i, j, k), uc = fetch(P, u[a], fa, i, j, k);
+                    double mp = fsh(P, m[a], fa, i, j, k, a, 1), up = fsh(P, u[a], fa, i, j, k, a, 1);
+                    double mm = fsh(P, m[a], fa, i, j, k, a, -1), um = fsh(P, u[a], fa, i, j, k, a, -1);
+                    phi_hi = 0.5 * (mc + mp) * 0.5 * (uc + up);
+                    phi_lo = 0.5 * (mm + mc) * 0.5 * (um + uc);
                 } else {
+                    const int fb = KIND_FACE(b);
                     /* edge flux at (c) and at (c - e_b) */
-                    phi_hi = 0.5 * (m[b][sh(P, i, j, k, b, 1)] + m[b][sh2(P, i, j, k, a, -1, b, 1)]) *
-                             0.5 * (u[a][c] + u[a][sh(P, i, j, k, b, 1)]);
-                    phi_lo = 0.5 * (m[b][c] + m[b][sh(P, i, j, k, a, -1)]) *
-                             0.5 * (u[a][sh(P, i, j, k, b, -1)] + u[a][c]);
+                    phi_hi = 0.5 * (fsh(P, m[b], fb, i, j, k, b, 1) + fsh2(P, m[b], fb, i, j, k, a, -1, b, 1)) *
+                             0.5 * (fetch(P, u[a], fa, i, j, k) + fsh(P, u[a], fa, i, j, k, b, 1));
+                    phi_lo = 0.5 * (fetch(P, m[b], fb, i, j, k) + fsh(P, m[b], fb, i, j, k, a, -1)) *
+                             0.5 * (fsh(P, u[a], fa, i, j, k, b, -1) + fetch(P, u[a], fa, i, j, k));
                 }
                 s += (phi_hi - phi_lo) / P->h;
             }
-            N[a][c] = s - u[a][c] * opA(P, Dm, i, j, k, a);
+            N[a][c] = s - fetch(P, u[a], fa, i, j, k) * opA(P, Dm, K_CELL, i, j, k, a);
         }
     }
     free(Dm);
@@ -400,10 +451,10 @@ void ora_viscosity_field(const ora_params* P, const double* phi, double* visc) {
  * edge viscosity = mean of the 4 cells around the edge */
 static double edge_tau(const ora_params* P, const double* eta, const double* const u[3],
                        int a, int b, int i, int j, int k) {
-    double eta_e = 0.25 * (eta[at(P, i, j, k)] + eta[sh(P, i, j, k, a, -1)] +
-                           eta[sh(P, i, j, k, b, 1)] + eta[sh2(P, i, j, k, a, -1, b, 1)]);
-    double dua_db = (u[a][sh(P, i, j, k, b, 1)] - u[a][at(P, i, j, k)]) / P->h;
-    double dub_da = (u[b][sh(P, i, j, k, b, 1)] - u[b][sh2(P, i, j, k, a, -1, b, 1)]) / P->h;
+    double eta_e = 0.25 * (fetch(P, eta, K_CELL, i, j, k) + fsh(P, eta, K_CELL, i, j, k, a, -1) +
+                           fsh(P, eta, K_CELL, i, j, k, b, 1) + fsh2(P, eta, K_CELL, i, j, k, a, -1, b, 1));
+    double dua_db = (fsh(P, u[a], KIND_FACE(a), i, j, k, b, 1) - fetch(P, u[a], KIND_FACE(a), i, j, k)) / P->h;
+    double dub_da = (fsh(P, u[b], KIND_FACE(b), i, j, k, b, 1) - fsh2(P, u[b], KIND_FACE(b), i, j, k, a, -1, b, 1)) / P->h;
     return eta_e * (dua_db + dub_da);
 }
 
@@ -416,12 +467,14 @@ void ora_viscous(const ora_params* P, const double* eta, const double* u0,
     FOR_CELLS(P) {
         long c = at(P, i, j, k);
         for (int a = 0; a < P->dim; ++a) {
+            const int fa = KIND_FACE(a);
             double s = 0.0;
             for (int b = 0; b < P->dim; ++b) {
                 if (b == a) {
-                    long cp = sh(P, i, j, k, a, 1), cm = sh(P, i, j, k, a, -1);
-                    double t_hi = 2.0 * eta[c] * (u[a][cp] - u[a][c]) / P->h;   /* at cell c     */
-                    double t_lo = 2.0 * eta[cm] * (u[a][c] - u[a][cm]) / P->h;  /* at cell c-e_a */
+                    double uc = fetch(P, u[a], fa, i, j, k);
+                    double t_hi = 2.0 * eta[c] * (fsh(P, u[a], fa, i, j, k, a, 1) - uc) / P->h;   /* at cell c     */
+                    double t_lo = 2.0 * fsh(P, eta, K_CELL, i, j, k, a, -1) *
+                                  (uc - fsh(P, u[a], fa, i, j, k, a, -1)) / P->h;               /* at cell c-e_a */
                     s += (t_hi - t_lo) / P->h;
                 } else {
                     int v[3] = {i, j, k};
@@ -468,6 +521,8 @@ void ora_fstar(const ora_params* P, const double* phi, const double* u0,
 /* variable-density pressure Poisson equation                             */
 /* ---------------------------------------------------------------------- */
 
+/* beta_a on every face (reads through fetch() give 0 on wall faces: no
+ * flux through a wall) */
 static void face_betas(const ora_params* P, const double* phi, double* beta[3]) {
     FOR_CELLS(P) {
         long c = at(P, i, j, k);
@@ -481,9 +536,9 @@ static void apply_with(const ora_params* P, double* const beta[3], const double*
         long c = at(P, i, j, k);
         double s = 0.0;
         for (int a = 0; a < P->dim; ++a) {
-            long cp = sh(P, i, j, k, a, 1);
-            double flux_hi = beta[a][cp] * (x[cp] - x[c]) / P->h;
-            double flux_lo = beta[a][c] * opG(P, x, i, j, k, a);
+            double flux_hi = fsh(P, beta[a], KIND_FACE(a), i, j, k, a, 1) *
+                             (fsh(P, x, K_CELL, i, j, k, a, 1) - x[c]) / P->h;
+            double flux_lo = fetch(P, beta[a], KIND_FACE(a), i, j, k) * opG(P, x, i, j, k, a);
             s += (flux_hi - flux_lo) / P->h;
         }
         y[c] = s;
@@ -513,7 +568,8 @@ int ora_poisson_solve(const ora_params* P, const double* phi, const double* b,
     FOR_CELLS(P) {
         long c = at(P, i, j, k);
         double s = 0.0;
-        for (int a = 0; a < P->dim; ++a) s += beta[a][c] + beta[a][sh(P, i, j, k, a, 1)];
+        for (int a = 0; a < P->dim; ++a)
+            s += fetch(P, beta[a], KIND_FACE(a), i, j, k) + fsh(P, beta[a], KIND_FACE(a), i, j, k, a, 1);
         dg[c] = s / h2;
     }
     double bmean = dot(P, b, NULL) / (double)N;
@@ -647,7 +703,7 @@ void ora_init_droplet(const ora_params* P, const double center[3],
         double q2 = 0.0, g2 = 0.0, amin = semi_axes[0];
         for (int a = 0; a < P->dim; ++a) {
             double x = (v[a] + 0.5) * P->h - center[a];
-            x -= Lx[a] * floor(x / Lx[a] + 0.5);
+            if (!walled(P, a)) x -= Lx[a] * floor(x / Lx[a] + 0.5);   /* minimum image */
             q2 += (x / semi_axes[a]) * (x / semi_axes[a]);
             g2 += x * x / (semi_axes[a] * semi_axes[a] * semi_axes[a] * semi_axes[a]);
             if (semi_axes[a] < amin) amin = semi_axes[a];
@@ -675,13 +731,13 @@ void ora_diagnostics(const ora_params* P, const double* phi, const double* u0,
         long c = at(P, i, j, k);
         double s2 = 0.0, kin = 0.0, grad2 = 0.0, div = 0.0;
         for (int a = 0; a < P->dim; ++a) {
-            long cp = sh(P, i, j, k, a, 1);
-            double ubar = 0.5 * (u[a][c] + u[a][cp]);    /* cell-averaged velocity */
+            double uc = fetch(P, u[a], KIND_FACE(a), i, j, k), up = fsh(P, u[a], KIND_FACE(a), i, j, k, a, 1);
+            double ubar = 0.5 * (uc + up);    /* cell-averaged velocity */
             s2 += ubar * ubar;
-            kin += 0.5 * rho_face(P, phi, i, j, k, a) * u[a][c] * u[a][c];
+            kin += 0.5 * rho_face(P, phi, i, j, k, a) * uc * uc;
             double g = opG(P, phi, i, j, k, a);
             grad2 += g * g;
-            div += (u[a][cp] - u[a][c]) / P->h;
+            div += (up - uc) / P->h;
         }
         speed[c] = sqrt(s2);
         ke[c] = kin;

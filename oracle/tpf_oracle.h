@@ -9,7 +9,8 @@
  * library under paper_2205_05835_amd/) never links, includes or calls it, and
  * this file includes nothing from the product.
  *
- * Grid: uniform, periodic, cells indexed c = (k*ny + j)*nx + i (x fastest).
+ * Grid: uniform, cells indexed c = (k*ny + j)*nx + i (x fastest); each axis
+ * periodic, or bounded by free-slip walls at both ends (ora_params.walls).
  * phi, p, mu, kappa live at cell centres; the velocity component u_a[c] lives
  * on the LOWER a-face of cell c, between c - e_a and c (staggered MAC grid,
  * Sec. 3 opening paragraph).  In 2D, n[2] = 1 and only axes 0,1 are used.
@@ -40,6 +41,7 @@ typedef struct {
     int clamp;          /* clamp phi to [0,1] inside the property laws */
     double poisson_rtol;/* stop when ||r||_2 <= rtol ||rhs||_2 */
     int poisson_maxit;
+    int walls;          /* bit a set: free-slip walls at both ends of axis a, else periodic */
 } ora_params;
 
 /* -- operators (each writes full arrays of n[0]*n[1]*n[2] doubles) -------- */

@@ -85,6 +85,22 @@ def test_init_is_tanh_of_signed_distance(ora):
     np.testing.assert_allclose(phi3, tanh_phi(radius(P3), 0.3, 0.05), rtol=0, atol=1e-15)
 
 
+def test_init_near_wall_has_no_periodic_image(ora):
+    """Across a walled axis the box has no periodic image: a drop centred near
+    the wall at x = 0 is the tanh of the plain distance (the periodic box
+    sees the drop's image from across x = 1 instead)."""
+    n, eps, R, cx = 40, 0.04, 0.2, 0.12
+    Pw = circle_params(ora, n, eps, walls=1)
+    Pp = circle_params(ora, n, eps)
+    x = (np.arange(n) + 0.5) / n
+    r = np.sqrt((x[None, :] - cx) ** 2 + (x[:, None] - 0.5) ** 2)
+    rp = np.sqrt((np.minimum(np.abs(x[None, :] - cx), 1 - np.abs(x[None, :] - cx))) ** 2 + (x[:, None] - 0.5) ** 2)
+    phiw = ora.init_droplet(Pw, (cx, 0.5), (R, R))
+    np.testing.assert_allclose(phiw, tanh_phi(r, R, eps), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(ora.init_droplet(Pp, (cx, 0.5), (R, R)), tanh_phi(rp, R, eps), rtol=0, atol=1e-15)
+    assert np.abs(tanh_phi(r, R, eps) - tanh_phi(rp, R, eps)).max() > 1e-3
+
+
 def test_init_ellipse_zero_level_set(ora):
     """The first-order distance keeps the exact ellipse as the phi = 1/2 set
     and its gradient there equals the exact signed-distance gradient."""
@@ -782,3 +798,95 @@ def test_diagnostics_velocity(ora):
     assert d["ca_inf"] == pytest.approx(0.5 * 0.2 / 2.0)
     assert d["ke"] == pytest.approx(0.5 * 3.0 * 0.25)
     assert d["div_max"] == 0.0
+
+
+# ----------------------------------------------------------------- free-slip walls
+
+
+def mirror_double(P, q, kind, axes):
+    """Extend q over the doubled periodic box in which the walled box is the
+    lower half along each physical axis in `axes`: cell fields and face fields
+    tangential to the wall are mirrored evenly; the face field normal to the
+    wall is mirrored oddly about the wall faces, which hold 0."""
+    for a in axes:
+        ax = P.dim - 1 - a
+        if kind == a:
+            n = q.shape[ax]
+            lo = np.take(q, [0], axis=ax)
+            assert np.all(lo == 0.0)
+            q = np.concatenate([q, np.zeros_like(lo), -np.flip(np.take(q, range(1, n), axis=ax), ax)], ax)
+        else:
+            q = np.concatenate([q, np.flip(q, ax)], ax)
+    return q
+
+
+def lower_half(P, q, axes):
+    for a in axes:
+        ax = P.dim - 1 - a
+        q = np.take(q, range(q.shape[ax] // 2), axis=ax)
+    return q
+
+
+def walled_state(P, seed, amp=0.05):
+    """A drop touching nothing, plus a random velocity that is 0 on the wall faces."""
+    phi = ora_init_off_centre(P)
+    u = workloads.random_velocity(P.shape, seed, amp)
+    for a in range(P.dim):
+        if (P.walls >> a) & 1:
+            idx = [slice(None)] * P.dim
+            idx[P.dim - 1 - a] = 0
+            u[a][tuple(idx)] = 0.0
+    return phi, u
+
+
+def ora_init_off_centre(P):
+    import oracle as o
+    ext = [m * P.h for m in P.n]
+    centre = [0.43 * e for e in ext]
+    semi = [0.24 * min(ext), 0.19 * min(ext), 0.21 * min(ext)][:P.dim]
+    return o.init_droplet(P, centre, semi)
+
+
+@pytest.mark.parametrize("n,walls", [((24, 20), 3), ((24, 20), 1), ((20, 24), 2),
+                                     ((12, 10, 8), 5), ((10, 8, 8), 7)])
+@pytest.mark.parametrize("model,force", [(m, f) for m in ("CDI", "SB", "ISODI") for f in ("EB", "CSF", "LCSF")])
+def test_walls_equal_mirror_doubled_periodic_box(ora, n, walls, model, force):
+    """A box with free-slip walls evolves exactly like the lower half of the
+    periodic box of twice its size that holds the state and its mirror image
+    (the even/odd reflections of the wall rules).  The walled oracle reads
+    outside the box through its boundary rules; the doubled box is the pinned
+    periodic oracle on an explicitly mirrored array.  Three RK4 steps of every
+    model/force pair at density ratio 20, in 2D and 3D."""
+    if len(n) == 3 and (model, force) not in (("CDI", "EB"), ("SB", "CSF"), ("ISODI", "LCSF")):
+        pytest.skip("3D: one pair per model")
+    kw = dict(eps=1.1 / n[0], rho1=20.0, rho2=1.0, visc1=0.02, visc2=0.004, sigma=0.7,
+              model=ora.MODELS[model], force=ora.FORCES[force])
+    P = ora.Params(n=n, walls=walls, **kw)
+    axes = [a for a in range(len(n)) if (walls >> a) & 1]
+    n2 = tuple(m * (2 if a in axes else 1) for a, m in enumerate(n))
+    P2 = ora.Params(n=n2, length=P.h * n2[0], **kw)
+    assert P2.h == P.h
+    phi0, u0 = walled_state(P, 17)
+    phi2 = mirror_double(P, phi0, -1, axes)
+    u2 = [mirror_double(P, u0[a], a, axes) for a in range(P.dim)]
+    dt = 2e-4
+    phi, u, p = ora.step(P, dt, 3, phi0, u0)
+    phiD, uD, pD = ora.step(P2, dt, 3, phi2, u2)
+    us = max(np.abs(x).max() for x in u)
+    assert us > 1e-3
+    np.testing.assert_allclose(phi, lower_half(P, phiD, axes), rtol=0, atol=1e-13)
+    for a in range(P.dim):
+        np.testing.assert_allclose(u[a], lower_half(P, uD[a], axes), rtol=0, atol=1e-10 * us)
+    ps = np.abs(p).max()
+    np.testing.assert_allclose(p, lower_half(P, pD, axes), rtol=0, atol=1e-10 * ps)
+    # the doubled box keeps its mirror symmetry, and the wall faces stay shut
+    for a in axes:
+        idx = [slice(None)] * P.dim
+        idx[P.dim - 1 - a] = 0
+        assert np.all(u[a][tuple(idx)] == 0.0)
+    d = ora.diagnostics(P, phi, u, p)
+    dD = ora.diagnostics(P2, phiD, uD, pD)
+    scale = 2 ** len(axes)
+    assert d["mass"] == pytest.approx(dD["mass"] / scale, rel=1e-13)
+    assert d["ke"] == pytest.approx(dD["ke"] / scale, rel=1e-9)
+    assert d["umax"] == pytest.approx(dD["umax"], rel=1e-9)
