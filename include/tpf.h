@@ -9,7 +9,8 @@
  * (energy-based F = mu grad phi of Eq. 4 with mu of Eq. 2, or CSF, or the
  * localized CSF of Eq. 11), momentum advection and viscous diffusion, and a
  * variable-density pressure projection D(beta G p) = D f*, integrated with
- * classical RK4 on a uniform periodic staggered grid (Sec. 3, opening).
+ * classical RK4 on a uniform staggered grid, periodic or (batched calls)
+ * closed by free-slip walls per axis (Sec. 3, opening; Secs. 3.1, 3.2).
  *
  * Grid and layout (every array handed across this ABI):
  *   cells (nx, ny, nz), nz = 1 in 2D, equal spacing h = length / nx on all
@@ -87,6 +88,16 @@ typedef struct {
     int32_t adjoint;          /* 1: the workspace also holds the scratch of the
                                  adjoint calls (11 + 8 dim FP64 fields of N
                                  values); 0: those calls return TPF_EINVAL   */
+    int32_t walls;            /* bit a (x = bit 0) set: free-slip walls at both
+                                 ends of axis a instead of periodicity (the box
+                                 of Sec. 3.1, the top and bottom of Sec. 3.2).
+                                 A wall is a mirror plane: no flow through it
+                                 (u_a on the wall faces a-index 0 is taken as
+                                 0 whatever the array holds, and the step
+                                 leaves it unchanged), no normal gradient of
+                                 phi, p or the tangential velocity, no shear.
+                                 Batched calls only; single-case contexts
+                                 return TPF_EINVAL for walls != 0            */
 } tpf_params;
 
 /* Scalar diagnostics of the current state (FP64; t and step count included). */

@@ -51,6 +51,7 @@ struct tpf_batch {
     std::vector<int> order;          // cases by decreasing cell count
     std::vector<double> mass0;
     int config;                      // index into kConfigs
+    int walled;                      // some case has free-slip walls
     hipGraphExec_t graph;
     int graph_steps;                 // launches captured in graph (0: none)
     int graph_config;
@@ -153,6 +154,7 @@ static size_t carve_batch(tpf_batch* b, char* base) {
         K.ny = P.n[1];
         K.P = phys_of_params(P);
         K.maxit = P.poisson_maxit;
+        K.walls = P.walls;
         K.need_mu = P.force == FORCE_EB;
         K.need_kappa = P.model != MODEL_CDI || P.force != FORCE_EB;
         K.rtol = P.poisson_rtol;
@@ -177,16 +179,23 @@ static tpf_status upload_cases(tpf_batch* b) {
     return TPF_OK;
 }
 
-template <typename T, typename S, int NT>
-static hipError_t launch_step_nt(tpf_batch* b, size_t lds, int mode, int commit) {
+template <typename T, typename S, int NT, bool W>
+static hipError_t launch_step_ntw(tpf_batch* b, size_t lds, int mode, int commit) {
     if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch_step<T, S, NT>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch_step<T, S, NT, W>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    k_batch_step<T, S, NT><<<dim3(b->ncases), NT, lds, b->stream>>>(b->d_cases, b->d_order, b->d_states, b->d_dts,
-                                                                   mode, commit);
+    k_batch_step<T, S, NT, W><<<dim3(b->ncases), NT, lds, b->stream>>>(b->d_cases, b->d_order, b->d_states,
+                                                                      b->d_dts, mode, commit);
     return hipGetLastError();
+}
+
+// the wall-aware variant only when some case has walls
+template <typename T, typename S, int NT>
+static hipError_t launch_step_nt(tpf_batch* b, size_t lds, int mode, int commit) {
+    return b->walled ? launch_step_ntw<T, S, NT, true>(b, lds, mode, commit)
+                     : launch_step_ntw<T, S, NT, false>(b, lds, mode, commit);
 }
 
 template <typename T, typename S>
@@ -379,7 +388,10 @@ tpf_status tpf_batch_create(const tpf_params* cases, int32_t ncases, void* works
     if (!b) { set_error("host allocation failed"); return TPF_ENOMEM; }
     b->ncases = ncases;
     b->P.resize(ncases);
-    for (int q = 0; q < ncases; ++q) (void)resolve_params(&cases[q], &b->P[q]);
+    for (int q = 0; q < ncases; ++q) {
+        (void)resolve_params(&cases[q], &b->P[q]);
+        if (b->P[q].walls) b->walled = 1;
+    }
     b->mixed = b->P[0].precision == TPF_FP32_MIXED;
     b->tsz = b->mixed ? 4 : 8;
     b->ssz = b->tsz;
@@ -458,7 +470,7 @@ tpf_status tpf_batch_init_droplet(tpf_batch* b, int32_t q, const double center[2
     if (!center || !semi_axes) { set_error("center and semi_axes are required"); return TPF_EINVAL; }
     const BCase& K = b->h_cases[q];
     const long N = (long)K.nx * K.ny;
-    const Dims d{K.nx, K.ny, 1, 0};
+    const Dims d{K.nx, K.ny, 1, 0, K.walls};
     const double h = b->P[q].length / b->P[q].n[0];
     hipError_t e;
     if (b->mixed)

@@ -10,6 +10,14 @@
 // shared between cases, so a case converges, fails or finishes on its own:
 // there is no host synchronisation inside a step.  The coarsest multigrid
 // levels of each case live in LDS.
+//
+// A case may close either axis with free-slip walls.  The stage operators
+// read across them by the mirror rules of the operator bodies (the level-0
+// cells carry wall bits); the pressure operator is closed by zero face
+// coefficients on the wall faces of every level (a coarse wall face is the
+// mean of two zero fine faces), so the periodic neighbour a solver kernel
+// reads across a wall is multiplied by zero and the multigrid, the CG and
+// the gauge run unchanged.
 #pragma once
 #include <limits>
 
@@ -23,6 +31,7 @@ constexpr int BMAXLEV = 10;
 struct BCase {
     Phys P;
     int nx, ny, nlev, maxit;
+    int walls;          // bit a: free-slip walls at both ends of axis a
     int need_mu, need_kappa, lds_first, lds_bytes;
     double rtol, rtol_inner;
     void* y[4][3];      // state slots: phi, u_x, u_y
@@ -153,18 +162,21 @@ struct Stencil {
     }
 };
 
-template <typename T, typename S, int NT>
+// W: some case of the batch has walls (the kernel variant that reads wall
+// bits; without it every wall test folds away at compile time)
+template <typename T, typename S, int NT, bool W>
 struct BatchBlock {
     const BCase& K;
     BState* st;
     double* red;
     S* lds;
 
-    // the cells of a (nx, ny) grid, 64 consecutive x per wave
+    // the cells of a (nx, ny) grid, 64 consecutive x per wave (with the
+    // wall bits of d)
     template <typename F>
     __device__ __forceinline__ void cells(const Dims& d, F f) const {
         for (int j = threadIdx.x / 64; j < d.ny; j += NT / 64)
-            for (int i = threadIdx.x % 64; i < d.nx; i += 64) f(make_cell(d, i, j, 0));
+            for (int i = threadIdx.x % 64; i < d.nx; i += 64) f(make_cell_w(d, i, j, 0));
     }
 
     // The same cells, visited in groups of UG: f(C, on) gets the group's UG
@@ -190,13 +202,17 @@ struct BatchBlock {
                 const int jj = t / gx;
                 const int i = (t - jj * gx) * 64 + i0, j = j0 + jj * (NT / 64);
                 on[u] = t < nt && i < d.nx;
-                C[u] = make_cell(d, on[u] ? i : 0, on[u] ? j : 0, 0);
+                C[u] = make_cell_w(d, on[u] ? i : 0, on[u] ? j : 0, 0);
             }
             f(C, on);
         }
     }
 
-    __device__ __forceinline__ Dims dims(int l) const { return Dims{K.ln[l][0], K.ln[l][1], 1, 0}; }
+    // level l; level 0 carries the case's walls (the coarse levels need none:
+    // their solver kernels read periodic neighbours only)
+    __device__ __forceinline__ Dims dims(int l) const {
+        return Dims{K.ln[l][0], K.ln[l][1], 1, 0, (W && l == 0) ? K.walls : 0};
+    }
     __device__ __forceinline__ int ncell(int l) const { return K.ln[l][0] * K.ln[l][1]; }
 
     __device__ __forceinline__ BLev<S> lev(int l) const {
@@ -223,8 +239,9 @@ struct BatchBlock {
 
     // ---------------------------------------------------------- coefficients
     // fine level: beta_a = 1 / (h(c - e_a) + h(c)), h = rho(phi) / 2 with the
-    // clamped linear law; coarser levels: mean of the two fine faces covering
-    // each coarse face.  Then the LDS-resident levels receive their copies.
+    // clamped linear law, and 0 on wall faces; coarser levels: mean of the
+    // two fine faces covering each coarse face.  Then the LDS-resident levels
+    // receive their copies.
     __device__ void build_betas(const T* phi) {
         const Phys& P = K.P;
         const S h2 = S(0.5 * P.rho2), dh = S(0.5 * (P.rho1 - P.rho2));
@@ -235,8 +252,8 @@ struct BatchBlock {
         cells(dims(0), [&](const Cell& C) {
             auto hr = [&](unsigned q) { return h2 + dh * med3(S(phi[q]), lo, hi); };
             const S hc = hr(C.id);
-            b0[C.id] = S(1) / (hr(C.nb(0, -1)) + hc);
-            b1[C.id] = S(1) / (hr(C.nb(1, -1)) + hc);
+            b0[C.id] = C.wall(0, -1) ? S(0) : S(1) / (hr(C.nb(0, -1)) + hc);
+            b1[C.id] = C.wall(1, -1) ? S(0) : S(1) / (hr(C.nb(1, -1)) + hc);
         });
         __syncthreads();
         for (int l = 1; l < K.nlev; ++l) {
@@ -591,10 +608,11 @@ struct BatchBlock {
                     if (FROM_PHI) {
                         auto hr = [&](double v) { return h2 + dh * (P.clamp ? fmin(fmax(v, 0.0), 1.0) : v); };
                         const double hc = hr(c5[u][0]);
-                        bl0 = 1.0 / (hr(c5[u][1]) + hc);
-                        bh0 = 1.0 / (hc + hr(c5[u][2]));
-                        bl1 = 1.0 / (hr(c5[u][3]) + hc);
-                        bh1 = 1.0 / (hc + hr(c5[u][4]));
+                        const Cell& Q = C[u];
+                        bl0 = Q.wall(0, -1) ? 0.0 : 1.0 / (hr(c5[u][1]) + hc);
+                        bh0 = Q.wall(0, 1) ? 0.0 : 1.0 / (hc + hr(c5[u][2]));
+                        bl1 = Q.wall(1, -1) ? 0.0 : 1.0 / (hr(c5[u][3]) + hc);
+                        bh1 = Q.wall(1, 1) ? 0.0 : 1.0 / (hc + hr(c5[u][4]));
                     } else {
                         bl0 = c5[u][0];
                         bh0 = c5[u][1];
@@ -801,7 +819,7 @@ struct BatchBlock {
 // the current state (mode 1: one stage evaluation, outputs to slot 2).
 // Block b owns case order[b].  commit = 0 computes the step without
 // advancing the state (used by the tuner).
-template <typename T, typename S, int NT>
+template <typename T, typename S, int NT, bool W>
 __global__ __launch_bounds__(NT) void k_batch_step(const BCase* __restrict__ cases,
                                                    const int* __restrict__ order,
                                                    BState* __restrict__ states,
@@ -813,7 +831,7 @@ __global__ __launch_bounds__(NT) void k_batch_step(const BCase* __restrict__ cas
     const BCase& K = cases[q];
     BState* st = states + q;
     if (st->status != TPF_OK) return;
-    BatchBlock<T, S, NT> B{K, st, red, reinterpret_cast<S*>(batch_smem)};
+    BatchBlock<T, S, NT, W> B{K, st, red, reinterpret_cast<S*>(batch_smem)};
     const int yn = st->yn, acc = st->acc;
     __syncthreads();
     if (mode == 1) {
@@ -861,14 +879,14 @@ __global__ __launch_bounds__(NT) void k_batch_diag(const BCase* __restrict__ cas
     const int q = blockIdx.x;
     const BCase& K = cases[q];
     const int yn = states[q].yn;
-    const Dims d{K.nx, K.ny, 1, 0};
+    const Dims d{K.nx, K.ny, 1, 0, K.walls};
     double s[ND_SUM] = {0, 0, 0, 0, 0, 0, 0};
     double mx[ND_MAX] = {0.0, 0.0, -1e300, -1e300};
     for (int j = threadIdx.x / 64; j < d.ny; j += NT / 64)
         for (int i = threadIdx.x % 64; i < d.nx; i += 64) {
             double s1[ND_SUM] = {0, 0, 0, 0, 0, 0, 0};
             double m1[ND_MAX] = {0.0, 0.0, -1e300, -1e300};
-            op_diag<T, 2>(K.P, make_cell(d, i, j, 0), static_cast<const T*>(K.y[yn][0]),
+            op_diag<T, 2>(K.P, make_cell_w(d, i, j, 0), static_cast<const T*>(K.y[yn][0]),
                           static_cast<const T*>(K.y[yn][1]), static_cast<const T*>(K.y[yn][2]), nullptr,
                           K.p, s1, m1);
             for (int k = 0; k < ND_SUM; ++k) s[k] += s1[k];

@@ -235,6 +235,22 @@ tpf_status resolve_params(const tpf_params* in, tpf_params* P) {
     if (P->poisson_maxit <= 0) P->poisson_maxit = 400;
     if (P->mg_levels < 0) { set_error("mg_levels must be >= 0"); return TPF_EINVAL; }
     if (P->adjoint != 0 && P->adjoint != 1) { set_error("adjoint must be 0 or 1"); return TPF_EINVAL; }
+    if (P->walls < 0 || P->walls >= (1 << P->dim)) {
+        set_error("walls: one bit per axis of the grid (bit 0 = x)");
+        return TPF_EINVAL;
+    }
+    return TPF_OK;
+}
+
+// The single-case contexts run periodic boxes only; free-slip walls are a
+// feature of the batched calls.
+static tpf_status single_case_params(const tpf_params* in, tpf_params* P) {
+    tpf_status st = resolve_params(in, P);
+    if (st != TPF_OK) return st;
+    if (P->walls != 0) {
+        set_error("free-slip walls (params.walls) are supported by the batched calls only");
+        return TPF_EINVAL;
+    }
     return TPF_OK;
 }
 
@@ -303,7 +319,7 @@ int32_t tpf_profile_classes(void) { return NPROF; }
 tpf_status tpf_workspace_bytes(const tpf_params* params, size_t* bytes) {
     if (!bytes) { set_error("bytes is NULL"); return TPF_EINVAL; }
     tpf_params P;
-    tpf_status st = resolve_params(params, &P);
+    tpf_status st = single_case_params(params, &P);
     if (st != TPF_OK) return st;
     tpf_ctx tmp;
     std::memset(&tmp, 0, sizeof(tmp));
@@ -317,7 +333,7 @@ tpf_status tpf_create(const tpf_params* params, void* workspace, size_t ws_bytes
     if (!out) { set_error("out is NULL"); return TPF_EINVAL; }
     *out = nullptr;
     tpf_params P;
-    tpf_status st = resolve_params(params, &P);
+    tpf_status st = single_case_params(params, &P);
     if (st != TPF_OK) return st;
     if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255)) {
         set_error("workspace must be a non-NULL 256-byte aligned device pointer");
@@ -843,7 +859,7 @@ tpf_status tpf_diagnostics_noalloc(const tpf_params* params, const double* phi, 
                                    const double* u1, const double* u2, const double* p, void* hip_stream,
                                    tpf_diag* out) {
     tpf_params P;
-    tpf_status st = resolve_params(params, &P);
+    tpf_status st = single_case_params(params, &P);
     if (st != TPF_OK) return st;
     if (!phi || !u0 || !u1 || (P.dim == 3 && !u2) || !out) {
         set_error("tpf_diagnostics_noalloc: NULL argument");

@@ -264,7 +264,7 @@ inline dim3 zchunk_grid(const int n[3], int kz) {
     return tile_grid((n[0] + BX - 1) / BX, (n[1] + BY - 1) / BY, (n[2] + kz - 1) / kz);
 }
 extern int g_xcd_tiles;   // XCD slab tiling of the block grids (TPF_XCD_TILES=0 disables)
-inline Dims dims_of(const int n[3]) { return Dims{n[0], n[1], n[2], g_xcd_tiles}; }
+inline Dims dims_of(const int n[3]) { return Dims{n[0], n[1], n[2], g_xcd_tiles, 0}; }
 Phys phys_of(const tpf_ctx* c);
 
 }  // namespace tpf

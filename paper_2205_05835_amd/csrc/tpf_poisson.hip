@@ -517,7 +517,7 @@ __global__ __launch_bounds__(1024) void k_tail(TailDesc D, S w1, S w2, S omega_c
     extern __shared__ __align__(16) unsigned char tail_smem[];
     S* L = reinterpret_cast<S*>(tail_smem);
     const int t = threadIdx.x, T = blockDim.x;
-    auto dims = [&](int l) { return Dims{D.n[l][0], D.n[l][1], D.n[l][2], 0}; };
+    auto dims = [&](int l) { return Dims{D.n[l][0], D.n[l][1], D.n[l][2], 0, 0}; };
     auto ncell = [&](int l) { return D.n[l][0] * D.n[l][1] * D.n[l][2]; };
     // (i, j, k) of cell q of level l: shifts and masks when nx and ny are
     // powers of two (D.lg[l] >= 0, the usual case), else divisions

@@ -2,9 +2,17 @@
 // kernels of the single-case step and the block-stride loops of the batched
 // persistent step.  Each op_* computes the outputs of one cell C.
 //
-// Discrete operators on the staggered periodic grid (Sec. 3):
+// Discrete operators on the staggered grid (Sec. 3):
 //   A_a q[c] = (q[c-e_a] + q[c])/2,  G_a q[c] = (q[c] - q[c-e_a])/h,
 //   D F[c] = sum_a (F_a[c+e_a] - F_a[c])/h,  C_a q[c] = (q[c+e_a]-q[c-e_a])/(2h)
+//
+// Each axis is periodic or closed by free-slip walls at both ends (cells
+// with wall bits, tpf_index.hpp).  A free-slip wall is a mirror plane of the
+// solution: across it a cell field reads its even image (Cell::off), the
+// component of the normal along the wall's axis its odd image, and a face
+// field normal to the wall is 0 on the wall faces.  The bodies write 0 to
+// the face outputs that lie on a wall (fluxes, f*, the velocity update), so
+// the wall faces of u stay as they were set.
 #pragma once
 #include "tpf_device.hpp"
 
@@ -69,7 +77,11 @@ __device__ __forceinline__ void op_kappa(const Phys& P, const Cell& C, const T* 
     const T ih2 = T(0.5 * P.inv_h);
     T s = T(0);
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) s += (ld(n[a], C.off(a, 1)) - ld(n[a], C.off(a, -1))) * ih2;
+    for (int a = 0; a < DIM; ++a) {
+        // n_a is odd across a wall normal to a: its image there is -n_a(c)
+        const T np = ld(n[a], C.off(a, 1)), nm = ld(n[a], C.off(a, -1));
+        s += ((C.wall(a, 1) ? -np : np) - (C.wall(a, -1) ? -nm : nm)) * ih2;
+    }
     st(kappa, C.id, -s);
 }
 
@@ -97,32 +109,61 @@ __device__ __forceinline__ void op_face(const Phys& P, const Cell& C, const T* _
         const unsigned cm = C.off(a, -1);
         const T fm = ld(phi, cm);
         const T rho_f = T(0.5) * (rho_of(P, fm) + rho_of(P, f));
+        const bool shut = C.wall(a, -1);   // face on a wall: no flux
         T ra = T(0);
         if (cdi) {
             const T wm = fm * (T(1) - fm) * ld(n[a], cm);
             const T wc = f * (T(1) - f) * ld(n[a], c);
-            ra = T(P.gamma) * (T(P.eps) * ((f - fm) * T(P.inv_h)) - T(0.5) * (wm + wc));
+            ra = shut ? T(0) : T(P.gamma) * (T(P.eps) * ((f - fm) * T(P.inv_h)) - T(0.5) * (wm + wc));
             st(r[a], c, ra);
         }
-        st(m[a], c, rho_f * ld(u[a], c) - drho * ra);
+        st(m[a], c, shut ? T(0) : rho_f * ld(u[a], c) - drho * ra);
     }
 }
 
 // ------------------------------------------------------------------ field access
 // The phase and momentum bodies read their neighbour values through an
-// accessor: G (global memory, a Cell's periodic offsets) here, or one that
-// serves the in-plane neighbours of a z-plane from an LDS tile.  f is one of
-// the field ids below; a, b are axes and s, t in {-1, +1}.
+// accessor: G (global memory, a Cell's offsets) here, or one that serves the
+// in-plane neighbours of a z-plane from an LDS tile.  f is one of the field
+// ids below; a, b are axes and s, t in {-1, +1}.
 enum { F_PHI = 0, F_U0, F_U1, F_U2, F_M0, F_M1, F_M2, F_MU, F_KAP, F_R0, F_R1, F_R2, F_NF };
+
+// the axis a face field is normal to (u_a, m_a, r_a), or -1 for a cell field
+__device__ __forceinline__ int normal_of(int f) {
+    return (f >= F_U0 && f <= F_U2) ? f - F_U0
+         : (f >= F_M0 && f <= F_M2) ? f - F_M0
+         : (f >= F_R0 && f <= F_R2) ? f - F_R0 : -1;
+}
 
 template <typename T>
 struct GAcc {
     const Cell& C;
     const T* p[F_NF];
-    __device__ __forceinline__ T c(int f) const { return ld(p[f], C.id); }
-    __device__ __forceinline__ T nb(int f, int a, int s) const { return ld(p[f], C.off(a, s)); }
+    // A face field normal to axis n, read dn faces above the cell's own lower
+    // n-face (dn in -1..1), is 0 on a wall face: the lower face of the first
+    // cell (dn = 0 there, dn = -1 from the second cell), the upper face of
+    // the last (dn = +1).  (From the first cell dn = -1 is past the wall; it
+    // feeds only the wall face's own outputs, which are written as 0.)
+    __device__ __forceinline__ bool shut(int f, int dn) const {
+        const int n = normal_of(f);
+        if (n < 0) return false;
+        if (dn > 0) return C.wall(n, 1);
+        return C.wall(n, -1) || (dn < 0 && C.second(n));
+    }
+    // (the load is unconditional and the wall test a select: the loads of a
+    // body stay free to be issued together)
+    __device__ __forceinline__ T c(int f) const {
+        const T v = ld(p[f], C.id);
+        return shut(f, 0) ? T(0) : v;
+    }
+    __device__ __forceinline__ T nb(int f, int a, int s) const {
+        const T v = ld(p[f], C.off(a, s));
+        return shut(f, a == normal_of(f) ? s : 0) ? T(0) : v;
+    }
     __device__ __forceinline__ T nb2(int f, int a, int s, int b, int t) const {
-        return ld(p[f], C.off2(a, s, b, t));
+        const int n = normal_of(f);
+        const T v = ld(p[f], C.off2(a, s, b, t));
+        return shut(f, (a == n ? s : 0) + (b == n ? t : 0)) ? T(0) : v;
     }
 };
 
@@ -244,9 +285,10 @@ __device__ __forceinline__ void op_momentum_g(const Phys& P, const Cell& C, cons
             fh = T(0.25 * P.sigma_hat) * (G.nb(F_KAP, a, -1) + G.c(F_KAP)) *
                  (fm * (T(1) - fm) + f * (T(1) - f)) * gh;
         }
-        if (Fo[0]) stn(Fo[a], c, fh * ih);
+        const bool shut = C.wall(a, -1);   // face on a wall: f* = 0
+        if (Fo[0]) stn(Fo[a], c, shut ? T(0) : fh * ih);
         const T rho_f = T(P.rho2) + T(0.5 * (P.rho1 - P.rho2)) * (clm + clc);
-        stn(fs[a], c, ((fh - nh) * ih + vh2 * (ih * ih)) / rho_f);
+        stn(fs[a], c, shut ? T(0) : ((fh - nh) * ih + vh2 * (ih * ih)) / rho_f);
     }
 }
 
@@ -269,7 +311,11 @@ __device__ __forceinline__ double op_div(const Phys& P, const Cell& C, const T* 
     const unsigned c = C.id;
     double s = 0.0;
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) s += ((double)ld(fs[a], C.off(a, 1)) - (double)ld(fs[a], c)) * P.inv_h;
+    for (int a = 0; a < DIM; ++a) {
+        const double hi = C.wall(a, 1) ? 0.0 : (double)ld(fs[a], C.off(a, 1));
+        const double lo = C.wall(a, -1) ? 0.0 : (double)ld(fs[a], c);
+        s += (hi - lo) * P.inv_h;
+    }
     b[c] = s;
     return s;
 }
@@ -297,7 +343,7 @@ __device__ __forceinline__ void op_project(const Phys& P, const RKArgs& rk, cons
         const unsigned cm = C.off(a, -1);
         const double rho_f = 0.5 * ((double)rho_of(P, ld(phi, cm)) + (double)rho_of(P, f));
         const double gp = (pc - ld(p, cm)) * P.inv_h;
-        const T k = T((double)ld(fs[a], c) - gp / rho_f);
+        const T k = C.wall(a, -1) ? T(0) : T((double)ld(fs[a], c) - gp / rho_f);   // wall face: u stays
         if (rk.eval_only) {
             stn(nx[a], c, k);
             continue;
@@ -312,7 +358,8 @@ __device__ __forceinline__ void op_project(const Phys& P, const RKArgs& rk, cons
 
 // ------------------------------------------------------------------ initial droplet
 // phi = [1 + tanh(s/2eps)]/2, s = (1 - q)/|grad q| with q = |x / a| (first-order
-// signed distance to the ellipse/ellipsoid, exact for circles and spheres)
+// signed distance to the ellipse/ellipsoid, exact for circles and spheres);
+// the nearest periodic image along periodic axes, none across walled ones
 template <typename T, int DIM>
 __device__ __forceinline__ void op_init_droplet(const Dims& d, const Cell& C, double h, double eps, double c0,
                                                         double c1, double c2, double a0, double a1,
@@ -325,7 +372,7 @@ __device__ __forceinline__ void op_init_droplet(const Dims& d, const Cell& C, do
     for (int a = 0; a < DIM; ++a) {
         const double L = nn[a] * h;
         double x = (v[a] + 0.5) * h - cen[a];
-        x -= L * floor(x / L + 0.5);
+        if (!((d.walls >> a) & 1)) x -= L * floor(x / L + 0.5);
         q2 += (x / ax[a]) * (x / ax[a]);
         g2 += x * x / (ax[a] * ax[a] * ax[a] * ax[a]);
         amin = fmin(amin, ax[a]);
@@ -353,7 +400,8 @@ __device__ __forceinline__ void op_diag(const Phys& P, const Cell& C, const T* _
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
         const unsigned cp = C.off(a, 1), cm = C.off(a, -1);
-        const double ua = (double)u[a][c], uap = (double)u[a][cp];
+        const double ua = C.wall(a, -1) ? 0.0 : (double)u[a][c];
+        const double uap = C.wall(a, 1) ? 0.0 : (double)u[a][cp];
         const double ub = 0.5 * (ua + uap);
         sp2 += ub * ub;
         const double fm = (double)phi[cm];

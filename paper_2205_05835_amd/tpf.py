@@ -61,7 +61,7 @@ class tpf_params(ctypes.Structure):
                 ("rho2", ctypes.c_double), ("visc1", ctypes.c_double), ("visc2", ctypes.c_double),
                 ("normal_delta", ctypes.c_double), ("poisson_rtol", ctypes.c_double),
                 ("poisson_rtol_inner", ctypes.c_double), ("poisson_maxit", ctypes.c_int32),
-                ("mg_levels", ctypes.c_int32), ("adjoint", ctypes.c_int32)]
+                ("mg_levels", ctypes.c_int32), ("adjoint", ctypes.c_int32), ("walls", ctypes.c_int32)]
 
 
 class tpf_implicit_opts(ctypes.Structure):
@@ -168,7 +168,7 @@ def check(status: int, where: str) -> None:
 def make_params(n, length=1.0, model="CDI", force="EB", precision="fp64", clamp_properties=1,
                 sigma=1.0, eps=None, gamma=1.0, rho1=1.0, rho2=1.0, visc1=0.1, visc2=0.1,
                 normal_delta=1e-12, poisson_rtol=0.0, poisson_rtol_inner=0.0, poisson_maxit=0,
-                mg_levels=0, adjoint=0) -> tpf_params:
+                mg_levels=0, adjoint=0, walls=0) -> tpf_params:
     n = tuple(int(x) for x in n)
     dim = len(n)
     h = length / n[0]
@@ -186,6 +186,7 @@ def make_params(n, length=1.0, model="CDI", force="EB", precision="fp64", clamp_
     p.poisson_rtol, p.poisson_rtol_inner = poisson_rtol, poisson_rtol_inner
     p.poisson_maxit, p.mg_levels = poisson_maxit, mg_levels
     p.adjoint = int(adjoint)
+    p.walls = int(walls)
     return p
 
 

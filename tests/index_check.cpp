@@ -1,8 +1,10 @@
-// CPU check of the library's periodic index arithmetic (tpf_index.hpp, the
+// CPU check of the library's index arithmetic (tpf_index.hpp, the
 // same header the kernels include, compiled here for the host).  For every
 // cell of each grid given on the command line (nx ny nz ...) it checks:
 //   - Cell::off / nb / off2 (a != b) against the wrapped coordinates, and
 //     that every neighbour index lies in [0, N);
+//   - with free-slip walls on any set of axes (make_cell_w): off / off2
+//     against the mirrored coordinates, nb still wrapped, the wall bits;
 //   - ColIndex (z-marching columns): in-plane offsets and neighbour
 //     coordinates against the wrapped coordinates, kwrap at both ends;
 //   - the XCD block -> tile map: with the grid padded to a multiple of 8
@@ -61,6 +63,57 @@ static int check_cells(const Dims& d) {
     return 0;
 }
 
+// the mirror image of coordinate v on an axis of n cells walled at both ends
+static int mirrored(int v, int n) { return v < 0 ? -1 - v : (v >= n ? 2 * n - 1 - v : v); }
+
+// make_cell_w for every wall mask of the grid's axes: off / off2 read the
+// mirror image across a walled axis and wrap across the others; nb() wraps
+// everywhere; wall(a, s) is set exactly on the first and last cell of a
+// walled axis
+static int check_walls(const Dims& d0) {
+    const int n[3] = {d0.nx, d0.ny, d0.nz};
+    for (int walls = 1; walls < 8; ++walls) {
+        Dims d = d0;
+        d.walls = walls;
+        auto want_at = [&](int v0, int v1, int v2) {
+            int v[3] = {v0, v1, v2};
+            for (int a = 0; a < 3; ++a)
+                if ((walls >> a) & 1) v[a] = mirrored(v[a], n[a]);
+            return wrapped(d, v[0], v[1], v[2]);
+        };
+        for (int k = 0; k < d.nz; ++k)
+            for (int j = 0; j < d.ny; ++j)
+                for (int i = 0; i < d.nx; ++i) {
+                    const Cell C = make_cell_w(d, i, j, k);
+                    const int c[3] = {i, j, k};
+                    for (int a = 0; a < 3; ++a)
+                        for (int s = -1; s <= 1; s += 2) {
+                            const bool wl = ((walls >> a) & 1) && (s < 0 ? c[a] == 0 : c[a] == n[a] - 1);
+                            if (C.wall(a, s) != wl) return fail("wall bit", d.nx, d.ny, d.nz, i, j, k, C.wall(a, s), wl);
+                            const bool w2 = ((walls >> a) & 1) && c[a] == 1;
+                            if (C.second(a) != w2) return fail("wall second", d.nx, d.ny, d.nz, i, j, k, C.second(a), w2);
+                            int v[3] = {i, j, k};
+                            v[a] += s;
+                            if ((long)C.off(a, s) != want_at(v[0], v[1], v[2]))
+                                return fail("wall off", d.nx, d.ny, d.nz, i, j, k, C.off(a, s), want_at(v[0], v[1], v[2]));
+                            if ((long)C.nb(a, s) != wrapped(d, v[0], v[1], v[2]))
+                                return fail("wall nb", d.nx, d.ny, d.nz, i, j, k, C.nb(a, s), wrapped(d, v[0], v[1], v[2]));
+                            for (int b = 0; b < 3; ++b) {
+                                if (b == a) continue;
+                                for (int t = -1; t <= 1; t += 2) {
+                                    int w[3] = {v[0], v[1], v[2]};
+                                    w[b] += t;
+                                    if ((long)C.off2(a, s, b, t) != want_at(w[0], w[1], w[2]))
+                                        return fail("wall off2", d.nx, d.ny, d.nz, i, j, k, C.off2(a, s, b, t),
+                                                    want_at(w[0], w[1], w[2]));
+                                }
+                            }
+                        }
+                }
+    }
+    return 0;
+}
+
 static int check_columns(const Dims& d) {
     for (int j = 0; j < d.ny; ++j)
         for (int i = 0; i < d.nx; ++i) {
@@ -110,8 +163,9 @@ static int check_tiles(int gx, int gy, int gz) {
 int main(int argc, char** argv) {
     long cells = 0;
     for (int q = 1; q + 2 < argc; q += 3) {
-        const Dims d{std::atoi(argv[q]), std::atoi(argv[q + 1]), std::atoi(argv[q + 2]), 1};
+        const Dims d{std::atoi(argv[q]), std::atoi(argv[q + 1]), std::atoi(argv[q + 2]), 1, 0};
         if (check_cells(d) || check_columns(d)) return 1;
+        if ((long)d.nx * d.ny * d.nz <= 100000 && check_walls(d)) return 1;
         // the tilings the kernels launch: 64 x 4 tiles per plane, z-chunks of 1, 8 and 32 planes
         for (int kz : {1, 8, 32})
             if (check_tiles((d.nx + BX - 1) / BX, (d.ny + BY - 1) / BY, (d.nz + kz - 1) / kz)) return 1;

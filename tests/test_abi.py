@@ -40,7 +40,8 @@ def test_struct_layout_matches_header(tpf):
     P = tpf.tpf_params
     assert P.length.offset == 16
     assert P.sigma.offset == 40
-    assert P.poisson_maxit.offset == 120 and P.adjoint.offset == 128 and ctypes.sizeof(P) == 136
+    assert P.poisson_maxit.offset == 120 and P.adjoint.offset == 128 and P.walls.offset == 132
+    assert ctypes.sizeof(P) == 136
     D = tpf.tpf_diag
     assert D.poisson_outer.offset == 104 and ctypes.sizeof(D) == 112
     O = tpf.tpf_implicit_opts
@@ -136,3 +137,20 @@ def test_adjoint_scratch_is_opt_in(tpf):
     with pytest.raises(tpf.TpfError) as e:
         tpf.workspace_bytes(tpf.make_params((32, 32), adjoint=2))
     assert e.value.status == tpf.TPF_EINVAL
+
+
+def test_walls_validation(tpf):
+    """params.walls: one bit per axis of the grid; batched cases only (the
+    single-case calls reject any wall)."""
+    for bad in (-1, 4, 8):
+        with pytest.raises(tpf.TpfError) as e:
+            tpf.batch_workspace_bytes([tpf.make_params((32, 32), walls=bad)])
+        assert e.value.status == tpf.TPF_EINVAL
+    with pytest.raises(tpf.TpfError):
+        tpf.batch_workspace_bytes([tpf.make_params((8, 8, 8), walls=4)])
+    ok = tpf.batch_workspace_bytes([tpf.make_params((32, 32), walls=w) for w in range(4)])
+    assert ok == tpf.batch_workspace_bytes([tpf.make_params((32, 32))] * 4)
+    for n, w in (((32, 32), 1), ((16, 16, 16), 4)):
+        with pytest.raises(tpf.TpfError) as e:
+            tpf.workspace_bytes(tpf.make_params(n, walls=w))
+        assert e.value.status == tpf.TPF_EINVAL and "batched" in str(e.value)

@@ -1,11 +1,12 @@
-"""CPU check of the kernels' periodic index arithmetic.
+"""CPU check of the kernels' index arithmetic (periodic and walled).
 
 The neighbour offsets of every stage and solver kernel come from
 paper_2205_05835_amd/csrc/tpf_index.hpp.  The kernels do not clamp them (a
 debug build with TPF_BOUNDS_CLAMP does), so their correctness rests on this
 test: tests/index_check.cpp includes that same header, compiled for the host
 with g++, and checks every cell of odd, ragged, 2-cell and workload-sized
-grids against the wrapped coordinates, plus the XCD block -> tile map.
+grids against the wrapped coordinates (and, with free-slip walls on any set
+of axes, against the mirrored ones), plus the XCD block -> tile map.
 """
 import os
 import subprocess
@@ -51,3 +52,19 @@ def test_checker_catches_a_wrong_offset(checker, tmp_path):
                     os.path.join(ROOT, "tests", "index_check.cpp")], check=True)
     r = subprocess.run([exe, "33", "21", "1"], capture_output=True, text=True)
     assert r.returncode == 1 and "MISMATCH off" in r.stdout
+
+
+def test_checker_catches_a_wrong_wall_offset(checker, tmp_path):
+    """A planted mistake in the wall rule (the upper wall read periodically)
+    must fail the wall check."""
+    src = open(os.path.join(CSRC, "tpf_index.hpp")).read()
+    bad = src.replace("if (v[a] == n[a] - 1) C.wl |= 2u << (4 * a);", "")
+    assert bad != src
+    d = tmp_path / "badw"
+    d.mkdir()
+    (d / "tpf_index.hpp").write_text(bad)
+    exe = str(tmp_path / "index_check_badw")
+    subprocess.run(["g++", "-O2", "-std=c++17", "-I", str(d), "-o", exe,
+                    os.path.join(ROOT, "tests", "index_check.cpp")], check=True)
+    r = subprocess.run([exe, "6", "5", "1"], capture_output=True, text=True)
+    assert r.returncode == 1 and "MISMATCH wall" in r.stdout

@@ -890,3 +890,21 @@ def test_walls_equal_mirror_doubled_periodic_box(ora, n, walls, model, force):
     assert d["mass"] == pytest.approx(dD["mass"] / scale, rel=1e-13)
     assert d["ke"] == pytest.approx(dD["ke"] / scale, rel=1e-9)
     assert d["umax"] == pytest.approx(dD["umax"], rel=1e-9)
+
+
+def test_walls_read_wall_faces_as_zero(ora):
+    """The wall faces carry no flow whatever the velocity array holds there:
+    junk on them changes nothing else and is left in place."""
+    n = (20, 16)
+    P = ora.Params(n=n, walls=3, eps=1.2 / 20, rho1=10.0, rho2=1.0, visc1=0.02, visc2=0.004, force=ora.CSF)
+    phi0, u0 = walled_state(P, 5)
+    uj = [x.copy() for x in u0]
+    uj[0][:, 0] = 0.37
+    uj[1][0, :] = -0.21
+    f0, v0, p0 = ora.step(P, 2e-4, 2, phi0, u0)
+    f1, v1, p1 = ora.step(P, 2e-4, 2, phi0, uj)
+    assert np.array_equal(f0, f1) and np.array_equal(p0, p1)
+    assert np.all(v1[0][:, 0] == 0.37) and np.all(v1[1][0, :] == -0.21)
+    v1[0][:, 0] = 0.0
+    v1[1][0, :] = 0.0
+    assert np.array_equal(v0[0], v1[0]) and np.array_equal(v0[1], v1[1])
