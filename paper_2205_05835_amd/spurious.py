@@ -3,10 +3,10 @@ the GPU, with every case of the study in one batched launch per step.
 
 Setup (Sec. 3.1): a drop of diameter D = 0.4 at the centre of the unit box,
 equal densities rho = 300 and viscosities visc = 0.1, sigma = 1 (La =
-sigma rho D / visc^2 = 12000), u = 0 at t = 0.  Readings where the paper is
-silent or where this build differs: the box is periodic (the paper uses
-free-slip walls), gamma = 1, and the time step is the smallest stable step
-of all cases (every case takes the same steps).  The measured quantity is
+sigma rho D / visc^2 = 12000), u = 0 at t = 0, free-slip walls on all four
+sides (--box periodic runs the periodic unit box instead).  Readings where
+the paper is silent: gamma = 1, and the time step is the smallest stable
+step of all cases (every case takes the same steps).  The measured quantity is
 Ca_inf = max|u| visc / sigma (max over cells of the cell-averaged velocity)
 against t* = sigma t / (visc D).
 
@@ -53,7 +53,7 @@ def stable_dt(n: int, eps: float, gamma: float, cfl: float = 0.1) -> float:
                0.5 * math.sqrt(2.0 * RHO * h ** 3 / (4.0 * math.pi * SIGMA)))
 
 
-def build_cases(ns, gamma, precision):
+def build_cases(ns, gamma, precision, walls=3):
     cases = []
     for panel in ("fixed", "sharp"):
         for n in ns:
@@ -62,7 +62,7 @@ def build_cases(ns, gamma, precision):
                     eps = eps_of(panel, n)
                     p = tpf.make_params((n, n), length=1.0, model=model, force=force, precision=precision,
                                         sigma=SIGMA, eps=eps, gamma=gamma, rho1=RHO, rho2=RHO,
-                                        visc1=VISC, visc2=VISC)
+                                        visc1=VISC, visc2=VISC, walls=walls)
                     cases.append({"panel": panel, "n": n, "model": model, "force": force, "eps": eps,
                                   "params": p})
     return cases
@@ -76,13 +76,15 @@ def main(argv=None):
     ap.add_argument("--t-sample", type=float, default=10.0, help="t* between history samples")
     ap.add_argument("--gamma", type=float, default=1.0)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_mixed"])
+    ap.add_argument("--box", default="walls", choices=["walls", "periodic"],
+                    help="free-slip walls on all sides (Sec. 3.1) or a periodic box")
     ap.add_argument("--out", required=True)
     args = ap.parse_args(argv)
     import torch
     if not torch.cuda.is_available():
         sys.exit("the study runs on the GPU")
     tpf.lib()
-    cases = build_cases(args.n, args.gamma, args.precision)
+    cases = build_cases(args.n, args.gamma, args.precision, 3 if args.box == "walls" else 0)
     dt = min(stable_dt(c["n"], c["eps"], args.gamma) for c in cases)
     tscale = VISC * DIAM / SIGMA            # t = t* visc D / sigma
     steps_per_sample = max(1, int(round(args.t_sample * tscale / dt)))
@@ -110,9 +112,9 @@ def main(argv=None):
         print(f"t* = {s * args.t_sample:7.1f}  wall {time.perf_counter() - t0:7.1f} s  stopped cases {bad}",
               flush=True)
     k_rep = int(round(args.t_report / args.t_sample))
+    box = "unit square, free-slip walls" if args.box == "walls" else "periodic unit square"
     out = {"setup": {"rho": RHO, "visc": VISC, "sigma": SIGMA, "diameter": DIAM, "gamma": args.gamma,
-                     "precision": args.precision, "dt": dt, "box": "periodic unit square",
-                     "t_report": args.t_report},
+                     "precision": args.precision, "dt": dt, "box": box, "t_report": args.t_report},
            "tstar": tstar,
            "cases": [{"panel": c["panel"], "n": c["n"], "model": c["model"], "force": c["force"],
                       "eps": c["eps"], "ca_inf": hist[q],

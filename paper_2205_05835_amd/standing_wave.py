@@ -8,13 +8,9 @@ y0 = pi, A0 = 2 pi / 100 (wavelength 2 pi, k = 1); rho1 = rho2 = 1, kinematic
 viscosity 0.064720863 in both phases, sigma = 2, dt = 0.003, u = 0 at t = 0.
 The amplitude is measured at x = dx/2.
 
-The library's grids are periodic in every direction.  A free-slip wall is a
-mirror plane: the solution of the walled problem, reflected about y = 2 pi,
-is the solution of the periodic problem on 2 pi x 4 pi whose initial state
-is that reflection (phi even, u_x even and u_y odd about the plane; the
-staggered operators keep the symmetry, so u_y = 0 and d u_x / dy = 0 stay
-exact on both planes).  The study therefore runs N x 2N periodic grids with
-the interface and its mirror image at y = 3 pi + A0 cos(x - dx/2).
+Every case runs on an N x N grid with free-slip walls on the y axis (walls =
+2 in the case parameters): no flow through y = 0 and y = 2 pi, no shear and
+no normal gradient of phi there.
 
 Readings: eps = 1/32 is taken in units of the box edge (eps = 2 pi / 32, so
 eps / dx = N / 32, which is 2 at N = 64 as the text states); the
@@ -81,22 +77,21 @@ def eps_of(panel: str, n: int) -> float:
 
 
 def initial_phi(n: int, eps: float) -> np.ndarray:
-    """phi on the N x 2N grid (C order [y][x]): 1 below the interface and
-    above its mirror, from the wave-height function of Sec. 3.2."""
+    """phi on the N x N grid (C order [y][x]): 1 below the interface, from
+    the wave-height function of Sec. 3.2."""
     h = L / n
     x = (np.arange(n) + 0.5) * h
-    y = (np.arange(2 * n) + 0.5) * h
-    ym = np.where(y <= 2.0 * math.pi, y, 4.0 * math.pi - y)[:, None]
-    height = ym - Y0 + A0 * np.cos(x - 0.5 * h)[None, :]
+    y = (np.arange(n) + 0.5) * h
+    height = y[:, None] - Y0 + A0 * np.cos(x - 0.5 * h)[None, :]
     return 0.5 * (1.0 - np.tanh(height / (2.0 * eps)))
 
 
 def amplitude(phi: np.ndarray, n: int) -> float:
     """y0 minus the interface height in the first column (x = dx/2), the
-    height being the column integral of phi over the lower half of the box
-    (phi goes from 1 to 0 across the interface; for a symmetric profile the
-    integral is the height of its midpoint, and the midpoint rule is far more
-    accurate than locating phi = 1/2 between two cell centres)."""
+    height being the column integral of phi from the bottom wall (phi goes
+    from 1 to 0 across the interface; for a symmetric profile the integral is
+    the height of its midpoint, and the midpoint rule is far more accurate
+    than locating phi = 1/2 between two cell centres)."""
     h = L / n
     return Y0 - h * float(np.sum(phi[:n, 0]))
 
@@ -109,9 +104,9 @@ def build_cases(ns, gamma, precision):
             for model in MODELS:
                 for force in FORCES:
                     eps = eps_of(panel, n)
-                    p = tpf.make_params((n, 2 * n), length=L, model=model, force=force, precision=precision,
+                    p = tpf.make_params((n, n), length=L, model=model, force=force, precision=precision,
                                         sigma=SIGMA, eps=eps, gamma=gamma, rho1=RHO, rho2=RHO,
-                                        visc1=NU * RHO, visc2=NU * RHO)
+                                        visc1=NU * RHO, visc2=NU * RHO, walls=2)
                     cases.append({"panel": panel, "n": n, "model": model, "force": force, "eps": eps,
                                   "params": p})
     return cases
@@ -135,7 +130,7 @@ def main(argv=None):
     batch = tpf.Batch([c["params"] for c in cases])
     for q, c in enumerate(cases):
         n = c["n"]
-        zero = np.zeros((2 * n, n))
+        zero = np.zeros((n, n))
         batch.set_state(q, initial_phi(n, c["eps"]), [zero, zero])
     nsamples = int(round(args.t_end / (DT * args.sample_steps)))
     print(f"{len(cases)} cases, dt = {DT}, {args.sample_steps} steps per sample, {nsamples} samples", flush=True)
@@ -165,7 +160,7 @@ def main(argv=None):
         if s % 10 == 0 or s == nsamples:
             print(f"t = {times[-1]:7.3f}  wall {time.perf_counter() - t0:7.1f} s", flush=True)
     exact = (A0 * prosperetti(np.array(times), 1.0, NU, RHO, RHO, SIGMA)).tolist()
-    out = {"setup": {"box": "2 pi x 4 pi periodic (the walled 2 pi x 2 pi box and its mirror image)",
+    out = {"setup": {"box": "2 pi x 2 pi, periodic in x, free-slip walls at y = 0 and 2 pi",
                      "rho": RHO, "nu": NU, "sigma": SIGMA, "dt": DT, "A0": A0, "gamma": args.gamma,
                      "precision": args.precision},
            "t": times, "exact": exact, "cases": []}

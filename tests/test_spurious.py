@@ -19,6 +19,7 @@ def test_case_set_and_parameters():
         else:   # the refinement path of Sec. 3.1: dx = sqrt(32) eps^(3/2)
             assert math.isclose(h, math.sqrt(32.0) * c["eps"] ** 1.5, rel_tol=1e-12)
         p = c["params"]
+        assert p.walls == 3                                 # free-slip walls on all sides (Sec. 3.1)
         assert p.rho1 == p.rho2 == 300.0 and p.visc1 == p.visc2 == 0.1 and p.sigma == 1.0
         # La = sigma rho D / visc^2 = 12000 (Sec. 3.1)
         assert math.isclose(p.sigma * p.rho1 * sp.DIAM / p.visc1 ** 2, 12000.0)
@@ -39,6 +40,7 @@ def test_short_study_on_gpu(tmp_path):
              "--out", str(out)])
     d = json.loads(out.read_text())
     assert d["tstar"] == [0.0, 1.0, 2.0]
+    assert "walls" in d["setup"]["box"]
     assert len(d["cases"]) == 36
     for c in d["cases"]:
         assert c["ca_inf"][0] == 0.0                       # u = 0 at t = 0
