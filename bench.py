@@ -405,27 +405,58 @@ def implicit_run(args):
     return out
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(args):
     """The oracle as it stands, on the host cores, on a bounded sample: the
-    same oscillating-drop configuration at 64^3 for 2 RK4 steps."""
+    same oscillating-drop configuration at 64^3 for 2 RK4 steps on all the
+    oracle's threads (the value), and at 48^3 for 1 step on one thread and
+    on all of them (the parallel speed-up of the oracle on this host)."""
     import numpy as np
 
     import oracle
     import workloads
 
+    def run(n, steps):
+        c = workloads.oscillating_drop_3d(n, "fp64")
+        P = oracle.Params(n=c.n, eps=c.eps, rho1=c.rho1, rho2=c.rho2, visc1=c.visc1, visc2=c.visc2,
+                          sigma=c.sigma)
+        phi = oracle.init_droplet(P, c.center, c.semi_axes)
+        zero = [np.zeros(P.shape)] * 3
+        t0 = time.perf_counter()
+        oracle.step(P, c.dt(), steps, phi, zero)
+        t = time.perf_counter() - t0
+        return c.cells * steps / t, t
+
     n, steps = args.cpu_n, args.cpu_steps
-    c = workloads.oscillating_drop_3d(n, "fp64")
-    P = oracle.Params(n=c.n, eps=c.eps, rho1=c.rho1, rho2=c.rho2, visc1=c.visc1, visc2=c.visc2,
-                      sigma=c.sigma)
-    phi = oracle.init_droplet(P, c.center, c.semi_axes)
-    zero = [np.zeros(P.shape)] * 3
-    t0 = time.perf_counter()
-    oracle.step(P, c.dt(), steps, phi, zero)
-    t = time.perf_counter() - t0
-    return {"value": c.cells * steps / t, "unit": "cell-steps/s", "cores": oracle.threads(),
-            "kind": "oracle",
-            "sample": f"{steps} RK4 steps of the same drop configuration at {n}^3 "
-                      f"(FP64, Jacobi-PCG pressure to 1e-14), {t:.1f} s"}
+    cores = oracle.threads()
+    value, t = run(n, steps)
+    out = {"value": value, "unit": "cell-steps/s", "cores": cores, "kind": "oracle",
+           "sample": f"{steps} RK4 steps of the same drop configuration at {n}^3 "
+                     f"(FP64, Jacobi-PCG pressure to 1e-14), {t:.1f} s",
+           "cpu_model": cpu_model()}
+    if args.cpu_single_n > 0:
+        many, t_many = run(args.cpu_single_n, 1)
+        prev = oracle.set_threads(1)
+        try:
+            one, t_one = run(args.cpu_single_n, 1)
+        finally:
+            oracle.set_threads(prev)
+        out["threads_1_vs_all"] = {
+            "sample": f"1 RK4 step at {args.cpu_single_n}^3", "unit": "cell-steps/s",
+            "threads_1": one, "seconds_1": round(t_one, 2),
+            f"threads_{cores}": many, f"seconds_{cores}": round(t_many, 2)}
+    return out
 
 
 def main():
@@ -441,6 +472,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=64)
     ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-single-n", type=int, default=48,
+                    help="grid of the one-thread vs all-threads oracle sample (0: skip)")
     ap.add_argument("--breakdown-out", default="")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched many-droplet measurement")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward measurement")

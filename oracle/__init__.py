@@ -135,6 +135,8 @@ def lib():
         }
         L.ora_threads.argtypes = []
         L.ora_threads.restype = ctypes.c_int
+        L.ora_set_threads.argtypes = [ctypes.c_int]
+        L.ora_set_threads.restype = ctypes.c_int
         for name, args in sig.items():
             f = getattr(L, name)
             f.argtypes = args
@@ -146,6 +148,11 @@ def lib():
 def threads() -> int:
     """OpenMP threads the oracle uses (OMP_NUM_THREADS or all host cores)."""
     return int(lib().ora_threads())
+
+
+def set_threads(n: int) -> int:
+    """Use n OpenMP threads from now on; returns the previous count."""
+    return int(lib().ora_set_threads(int(n)))
 
 
 def _ptr(a):

@@ -774,3 +774,10 @@ void ora_diagnostics(const ora_params* P, const double* phi, const double* u0,
 }
 
 int ora_threads(void) { return omp_get_max_threads(); }
+
+/* set the OpenMP thread count of later calls; returns the previous count */
+int ora_set_threads(int n) {
+    const int prev = omp_get_max_threads();
+    if (n > 0) omp_set_num_threads(n);
+    return prev;
+}

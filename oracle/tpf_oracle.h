@@ -97,6 +97,7 @@ void ora_diagnostics(const ora_params* P, const double* phi, const double* u0,
 
 /* number of OpenMP threads the oracle's parallel loops use */
 int ora_threads(void);
+int ora_set_threads(int n);
 
 #ifdef __cplusplus
 }
