@@ -428,38 +428,25 @@ struct BatchBlock {
         for (int l = nl - 2; l >= 0; --l) {
             const BLev<S> L = lev(l);
             const BLev<S> Lc = lev(l + 1);
-            // Z = zt + P zc, then z = Z + omega (r - A Z) / d, zt = z + omega (r - A z) / d
+            // zt += P zc (piecewise constant), then z = zt + omega (r - A zt) / d and
+            // zt = z + omega (r - A z) / d.  Two passes instead of one that forms
+            // zt + P zc at all five stencil points: a workgroup owns the case, and
+            // the fused pass held 15 loads per cell in registers, which cost more
+            // latency than the extra barrier.
             cells_g(L.d, [&](const Cell* C, const bool* on) {
-                auto Z = [&](int i, int j) {
-                    const int ii = wrapc(i, L.d.nx), jj = wrapc(j, L.d.ny);
-                    return L.zt[jj * L.d.nx + ii] + Lc.zt[(jj >> 1) * Lc.d.nx + (ii >> 1)];
-                };
-                Stencil<S> v[UG];
-                S r[UG];
+                S zf[UG], zc[UG];
 #pragma unroll
                 for (int u = 0; u < UG; ++u)
                     if (on[u]) {
-                        const unsigned c = C[u].id;
-                        const int i = C[u].i, j = C[u].j;
-                        v[u].bl0 = L.b0[c];
-                        v[u].bh0 = L.b0[C[u].nb(0, 1)];
-                        v[u].bl1 = L.b1[c];
-                        v[u].bh1 = L.b1[C[u].nb(1, 1)];
-                        v[u].xc = Z(i, j);
-                        v[u].xw = Z(i - 1, j);
-                        v[u].xe = Z(i + 1, j);
-                        v[u].xs = Z(i, j - 1);
-                        v[u].xn = Z(i, j + 1);
-                        r[u] = L.r[c];
+                        zf[u] = L.zt[C[u].id];
+                        zc[u] = Lc.zt[(C[u].j >> 1) * Lc.d.nx + (C[u].i >> 1)];
                     }
 #pragma unroll
                 for (int u = 0; u < UG; ++u)
-                    if (on[u]) {
-                        S dg;
-                        const S az = v[u].apply(L.ih2, dg);
-                        L.z[C[u].id] = v[u].xc + omega * (r[u] - az) / dg;
-                    }
+                    if (on[u]) L.zt[C[u].id] = zf[u] + zc[u];
             });
+            __syncthreads();
+            jacobi(L, L.zt, L.z, omega);
             __syncthreads();
             if (l > 0) {
                 jacobi(L, L.z, L.zt, omega);
@@ -496,37 +483,35 @@ struct BatchBlock {
             }
             rz = rzn;
             if (!(rz > 0.0)) return isfinite(rz) ? it : -2;
-            // new direction pn = zt + beta p at c and its four neighbours, q = A pn
-            double pq = 0.0;
-            cells_g<2>(L.d, [&](const Cell* C, const bool* on) {
-                S zc[2][5], pc[2][5], bb[2][4];
+            // new direction pn = zt + beta p, then q = A pn and <pn, q> (two
+            // passes: the same values as forming pn at the five stencil points)
+            const S sb = S(beta);
+            cells_g(L.d, [&](const Cell* C, const bool* on) {
+                S zv[UG], pv[UG];
 #pragma unroll
-                for (int u = 0; u < 2; ++u)
+                for (int u = 0; u < UG; ++u)
                     if (on[u]) {
-                        const unsigned nb5[5] = {C[u].id, C[u].nb(0, -1), C[u].nb(0, 1), C[u].nb(1, -1),
-                                                 C[u].nb(1, 1)};
-#pragma unroll
-                        for (int k = 0; k < 5; ++k) {
-                            zc[u][k] = L.zt[nb5[k]];
-                            pc[u][k] = pold[nb5[k]];
-                        }
-                        bb[u][0] = L.b0[C[u].id];
-                        bb[u][1] = L.b0[nb5[2]];
-                        bb[u][2] = L.b1[C[u].id];
-                        bb[u][3] = L.b1[nb5[4]];
+                        zv[u] = L.zt[C[u].id];
+                        pv[u] = pold[C[u].id];
                     }
 #pragma unroll
-                for (int u = 0; u < 2; ++u)
-                    if (on[u]) {
-                        S v5[5];
+                for (int u = 0; u < UG; ++u)
+                    if (on[u]) pn[C[u].id] = zv[u] + sb * pv[u];
+            });
+            __syncthreads();
+            double pq = 0.0;
+            cells_g(L.d, [&](const Cell* C, const bool* on) {
+                Stencil<S> v[UG];
 #pragma unroll
-                        for (int k = 0; k < 5; ++k) v5[k] = S((double)zc[u][k] + beta * (double)pc[u][k]);
-                        Stencil<S> st{v5[0], v5[1], v5[2], v5[3], v5[4], bb[u][0], bb[u][1], bb[u][2], bb[u][3]};
+                for (int u = 0; u < UG; ++u)
+                    if (on[u]) v[u].load(L, C[u], pn);
+#pragma unroll
+                for (int u = 0; u < UG; ++u)
+                    if (on[u]) {
                         S dg;
-                        const S a = st.apply(L.ih2, dg);
-                        pn[C[u].id] = v5[0];
+                        const S a = v[u].apply(L.ih2, dg);
                         q[C[u].id] = a;
-                        pq += (double)v5[0] * (double)a;
+                        pq += (double)v[u].xc * (double)a;
                     }
             });
             pq = bsum<NT>(pq, red);
@@ -549,8 +534,8 @@ struct BatchBlock {
                 for (int u = 0; u < UG; ++u)
                     if (on[u]) {
                         const unsigned c = C[u].id;
-                        x[c] = X((double)xv[u] + alpha * (double)pv[u]);
-                        const S rn = S((double)rv[u] - alpha * (double)qv[u]);
+                        x[c] = xv[u] + X(alpha) * X(pv[u]);
+                        const S rn = rv[u] - S(alpha) * qv[u];
                         L.r[c] = rn;
                         r2 += (double)rn * (double)rn;
                     }

@@ -131,7 +131,7 @@ def test_batch_walls_all_pairs_match_oracle(gpu, ora):
         got = b.get_state(q, with_pressure=True)
         ephi, eu, ep = errors(ora, oparams(ora, c, w), dts[q], steps, init[q], got)
         say(f"  {c.name} walls {w}: |dphi| {ephi:.2e} |du|/Uref {eu:.2e} |dp|/|p| {ep:.2e}")
-        assert ephi < 1e-12 and eu < 1e-11 and ep < 1e-11, c.name
+        assert ephi < 1e-12 and eu < 1e-11 and ep < 1e-12, c.name
         for a in range(2):
             if (w >> a) & 1:
                 face = got[1][a][:, 0] if a == 0 else got[1][a][0, :]
