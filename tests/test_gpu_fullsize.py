@@ -190,7 +190,7 @@ def test_fullsize_2d_ratio1000(gpu, ora):
             du_g = [s.eval_field(f"DU{a}") for a in range(2)]
             eu = max(np.abs(du_g[a] - du_o[a]).max() for a in range(2)) / max(np.abs(x).max() for x in du_o)
             say(f"  pressure {ep:.2e}  du/dt {eu:.2e}")
-            assert ep < 1e-10 and eu < 1e-10
+            assert ep < 1e-12 and eu < 1e-12
 
 
 def test_fullsize_batch_512(gpu):

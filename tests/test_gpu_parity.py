@@ -168,10 +168,13 @@ def test_pressure_and_projection_fp64(gpu, ora, dim):
     s.set_state(phi, u)
     d_o, du_o, p_o = ora.stage(P, phi, u)
     p_g = s.eval_field("PRESSURE")
-    assert rel(p_g, p_o) < 1e-11
+    edu = [rel(s.eval_field(f"DU{a}"), du_o[a]) for a in range(dim)]
+    say(f"  p rel {rel(p_g, p_o):.2e}  du rel {max(edu):.2e}")
+    # density ratio 1000 (measured: p 3e-15, du/dt 1.3e-13)
+    assert rel(p_g, p_o) < 1e-12
     assert abs(p_g.mean()) < 1e-12 * np.abs(p_o).max()
     for a in range(dim):
-        assert rel(s.eval_field(f"DU{a}"), du_o[a]) < 1e-11, a
+        assert edu[a] < 1e-12, a
     assert rel(s.eval_field("DPHI"), d_o) < TOL64
 
 
@@ -188,9 +191,9 @@ def test_poisson_solve_fp64(gpu, ora, dim, n):
     b = workloads.noise_field(P.shape, 17)
     x_g, it, rr = s.poisson_solve(b)
     x_o, _, _ = ora.poisson_solve(P, phi, b)
-    say(f"  iterations {it} relres {rr:.2e}")
+    say(f"  iterations {it} relres {rr:.2e}  x rel {rel(x_g, x_o):.2e}")
     assert rr <= 1e-14
-    assert rel(x_g, x_o) < 1e-11
+    assert rel(x_g, x_o) < 1e-12
     res = ora.poisson_apply(P, phi, x_g) - (b - b.mean())
     assert np.abs(res).max() < 1e-12 * np.abs(b).max()
 
