@@ -200,9 +200,9 @@ def test_fullsize_batch_512(gpu):
     (single-workgroup stage loops and a classical-CG solve against fused
     kernels and a flexible-CG solve): du/dt is a small difference of the
     surface force and the pressure gradient, each rounded in FP32, so the
-    velocities of two FP32 paths agree to the FP32-vs-FP64 error of either
-    (up to 1.8e-4 of max|u| on the batch sample of the benchmark), not to
-    rounding; the bound is 1e-4 of max|u|."""
+    velocities of two FP32 paths agree to the FP32-vs-FP64 error of either,
+    not to rounding.  Measured after 3 steps: phi to 6e-8, u to 5.2e-6 of
+    max|u|; the bounds are 1e-6 and 2e-5."""
     cases = workloads.batched_cases(512)
     say(f"full-size batch, {len(cases)} cases")
     b = gpu.Batch([gpu.params_for_case(c) for c in cases])
@@ -232,7 +232,7 @@ def test_fullsize_batch_512(gpu):
         ephi = np.abs(phi_b - phi_s).max()
         eu = max(np.abs(u_b[a] - u_s[a]).max() for a in range(2)) / umax
         say(f"  case {q} ({c.n[0]}^2): |dphi| {ephi:.2e} |du|/|u| {eu:.2e}")
-        assert ephi < 1e-6 and eu < 1e-4
+        assert ephi < 1e-6 and eu < 2e-5
 
 
 def test_fullsize_adjoint_dot_product(gpu):
