@@ -387,8 +387,9 @@ tpf_status tpf_batch_diagnostics(tpf_batch* b, tpf_diag* out);
  * keeps the coarsest multigrid levels of each case in up to `lds_bytes` of
  * LDS (some configurations reserve their whole LDS budget so that a large
  * case gets a CU to itself).  tpf_batch_tune() times every configuration on
- * one stage evaluation of every live case (the state, the pressure warm start
- * and the statuses are left as they were), keeps the fastest, and records it
+ * uncommitted RK4 steps of every live case with the time steps dt (the state,
+ * the pressures and their history and the statuses are left as they were;
+ * the pressures pass through host memory meanwhile), keeps the fastest, and records it
  * in the text file cache_path (may be NULL) under a key made of a hash of the
  * library's sources, the precision and the grid sizes; a later call with the
  * same key reads the choice back instead.  If a case's pressure solve fails

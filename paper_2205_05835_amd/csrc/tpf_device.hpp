@@ -23,14 +23,17 @@ __device__ __forceinline__ bool block_tile(int xcd, int gx, int gy, int gz, int&
     return tile_coords(tile_of_block(xcd, (int)gridDim.x, (int)blockIdx.x), gx, gy, gz, bx, by, bz);
 }
 
-// the cell of this thread for a (BX x BY x 1) tiling of the grid
+// the cell of this thread for a (BX x BY x 1) tiling of the grid; W: with
+// the wall bits of d.walls (kernels instantiated for boxes with walls; the
+// periodic instantiations carry none, so their wall tests fold away)
+template <bool W = false>
 __device__ __forceinline__ bool cell_of_thread(const Dims& d, Cell& C) {
     int bx, by, bz;
     if (!block_tile(d.xcd, (d.nx + BX - 1) / BX, (d.ny + BY - 1) / BY, d.nz, bx, by, bz)) return false;
     const int i = bx * BX + threadIdx.x;
     const int j = by * BY + threadIdx.y;
     if (i >= d.nx || j >= d.ny) return false;
-    C = make_cell(d, i, j, bz);
+    C = W ? make_cell_w(d, i, j, bz) : make_cell(d, i, j, bz);
     return true;
 }
 
@@ -39,7 +42,7 @@ __device__ __forceinline__ bool cell_of_thread(const Dims& d, Cell& C) {
 // kc kz ... kc kz + kz - 1, bottom to top.  The z neighbours one plane reads
 // are read again by the same block in the next plane shortly after, so they
 // come from L2 instead of HBM.
-template <typename F>
+template <bool W = false, typename F>
 __device__ __forceinline__ void for_cells_zchunk(const Dims& d, int kz, F&& body) {
     int bx, by, bz;
     if (!block_tile(d.xcd, (d.nx + BX - 1) / BX, (d.ny + BY - 1) / BY, (d.nz + kz - 1) / kz, bx, by, bz))
@@ -48,7 +51,7 @@ __device__ __forceinline__ void for_cells_zchunk(const Dims& d, int kz, F&& body
     const int j = by * BY + threadIdx.y;
     if (i >= d.nx || j >= d.ny) return;
     const int k0 = bz * kz, k1 = min(d.nz, k0 + kz);
-    for (int k = k0; k < k1; ++k) body(make_cell(d, i, j, k));
+    for (int k = k0; k < k1; ++k) body(W ? make_cell_w(d, i, j, k) : make_cell(d, i, j, k));
 }
 
 // Loads and stores at a 32-bit element index: the byte offset is formed in

@@ -242,13 +242,13 @@ tpf_status resolve_params(const tpf_params* in, tpf_params* P) {
     return TPF_OK;
 }
 
-// The single-case contexts run periodic boxes only; free-slip walls are a
-// feature of the batched calls.
+// Single-case contexts: the adjoint scratch is for periodic boxes only (the
+// hand-written transpose has no wall rules).
 static tpf_status single_case_params(const tpf_params* in, tpf_params* P) {
     tpf_status st = resolve_params(in, P);
     if (st != TPF_OK) return st;
-    if (P->walls != 0) {
-        set_error("free-slip walls (params.walls) are supported by the batched calls only");
+    if (P->walls != 0 && P->adjoint) {
+        set_error("the adjoint calls need a periodic box (params.walls = 0)");
         return TPF_EINVAL;
     }
     return TPF_OK;
@@ -293,6 +293,10 @@ static void init_geometry(tpf_ctx* c, const tpf_params* P) {
     // overrides
     const char* sl = std::getenv("TPF_STAGE_LDS");
     c->stage_lds = sl ? (sl[0] == '1' ? 1 : 0) : (P->precision == TPF_FP32_MIXED ? 1 : 0);
+    // free-slip walls: the global-memory stage kernels (their accessors apply
+    // the wall rules; the LDS tiles are filled periodically)
+    c->walls = P->walls;
+    if (c->walls) c->stage_lds = 0;
     const char* slk = std::getenv("TPF_STAGE_LDS_KZ");
     c->stage_lds_kz = slk ? std::atoi(slk) : 32;
     c->stage_lds_kz = std::min(std::max(c->stage_lds_kz, 1), 256);
@@ -882,7 +886,7 @@ tpf_status tpf_diagnostics_noalloc(const tpf_params* params, const double* phi, 
     const void* u[3] = {u0, u1, P.dim == 3 ? u2 : nullptr};
     // every partial the final sum reads is written by this call's first
     // kernel, so nothing in the scratch needs clearing
-    hipError_t e = launch_diagnostics_arrays(stream, P.dim, n, 0, phys_of_params(P), phi, u, p, part, fin);
+    hipError_t e = launch_diagnostics_arrays(stream, P.dim, n, P.walls, 0, phys_of_params(P), phi, u, p, part, fin);
     double v[kNoAllocValues];
     if (e == hipSuccess) e = hipMemcpyAsync(v, fin, sizeof(v), hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);

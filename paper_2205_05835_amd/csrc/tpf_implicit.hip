@@ -601,6 +601,7 @@ extern "C" tpf_status tpf_implicit_phase_step(tpf_ctx* c, double dt, int32_t nst
         return TPF_EINVAL;
     }
     if (c->mixed) { set_error("the implicit phase-field step needs an FP64 context"); return TPF_EINVAL; }
+    if (c->walls) { set_error("the implicit phase-field step needs a periodic box (params.walls = 0)"); return TPF_EINVAL; }
     if (!(dt >= 0.0) || !std::isfinite(dt) || nsteps < 0) {
         set_error("dt must be finite and >= 0, nsteps >= 0");
         return TPF_EINVAL;

@@ -181,6 +181,7 @@ struct tpf_ctx {
     int kz_override;     // planes per block of the z-marching kernels (0: automatic)
     int stage_kz;        // planes per block of the z-chunked stage kernels
     int stage_lds;       // 3D phase/momentum pass with its neighbourhoods staged in LDS
+    int walls;           // bit a: free-slip walls at both ends of axis a
     int stage_lds_kz;    // planes per block of that pass
     int coarse_fused;    // 3D stored-coefficient levels: one fused launch down and one up
     tpf::PubScalars* pub;     // pinned host buffer for the solver scalars (null: copy and synchronise)
@@ -223,7 +224,7 @@ hipError_t launch_diagnostics(tpf_ctx* c, const void* phi, const void* const u[3
 // the same reduction on explicit arrays (fp32: phi and u are float) into the
 // block partials `part` (ND_SUM + ND_MAX values per block of grid_of(n)) and
 // the final sums `out` (ND_SUM + ND_MAX values)
-hipError_t launch_diagnostics_arrays(hipStream_t st, int dim, const int n[3], int fp32, const Phys& P,
+hipError_t launch_diagnostics_arrays(hipStream_t st, int dim, const int n[3], int walls, int fp32, const Phys& P,
                                      const void* phi, const void* const u[3], const double* p, double* part,
                                      double* out);
 int xcd_tiles_from_env();
@@ -264,7 +265,7 @@ inline dim3 zchunk_grid(const int n[3], int kz) {
     return tile_grid((n[0] + BX - 1) / BX, (n[1] + BY - 1) / BY, (n[2] + kz - 1) / kz);
 }
 extern int g_xcd_tiles;   // XCD slab tiling of the block grids (TPF_XCD_TILES=0 disables)
-inline Dims dims_of(const int n[3]) { return Dims{n[0], n[1], n[2], g_xcd_tiles, 0}; }
+inline Dims dims_of(const int n[3], int walls = 0) { return Dims{n[0], n[1], n[2], g_xcd_tiles, walls}; }
 Phys phys_of(const tpf_ctx* c);
 
 }  // namespace tpf

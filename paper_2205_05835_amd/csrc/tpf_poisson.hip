@@ -102,9 +102,12 @@ __device__ __forceinline__ double abs_flux_sum(const S* bl, const S* bh, Fx x, S
 // policies return the half density h = rho / 2, and a face between cells
 // lo < hi is always 1 / (h(lo) + h(hi)) in that operand order, so both cells
 // of a face see bit-identical coefficients (symmetric A).  CoefPhi evaluates
-// the law from phi; CoefRho reads h precomputed once per solve.
-template <typename T, typename S>
+// the law from phi; CoefRho reads h precomputed once per solve.  A face on a
+// free-slip wall (the cell's wall bits) has coefficient 0: no flux through
+// the wall, and the wrapped neighbour read there drops out.
+template <typename T, typename S, bool W = false>
 struct CoefPhi {
+    static constexpr bool kWalls = W;     // cells carry wall bits (boxes with walls)
     const T* __restrict__ phi;
     S h2, dh;          // rho2 / 2, (rho1 - rho2) / 2
     S lo, hi;          // clamp bounds of phi: [0, 1], or +-inf when not clamping
@@ -118,12 +121,17 @@ struct CoefPhi {
         for (int a = 0; a < DIM; ++a) {
             bl[a] = recip(hr(C.nb(a, -1)) + hc);
             bh[a] = recip(hc + hr(C.nb(a, 1)));
+            if constexpr (W) {
+                bl[a] = C.wall(a, -1) ? S(0) : bl[a];
+                bh[a] = C.wall(a, 1) ? S(0) : bh[a];
+            }
         }
     }
 };
 
-template <typename S>
+template <typename S, bool W = false>
 struct CoefRho {
+    static constexpr bool kWalls = W;
     const S* __restrict__ h;
     __device__ __forceinline__ S hr(unsigned c) const { return ld(h, c); }
     template <int DIM>
@@ -133,19 +141,24 @@ struct CoefRho {
         for (int a = 0; a < DIM; ++a) {
             bl[a] = recip(hr(C.nb(a, -1)) + hc);
             bh[a] = recip(hc + hr(C.nb(a, 1)));
+            if constexpr (W) {
+                bl[a] = C.wall(a, -1) ? S(0) : bl[a];
+                bh[a] = C.wall(a, 1) ? S(0) : bh[a];
+            }
         }
     }
 };
 
 // h = rho(phi) / 2 for the fine level, once per solve
-template <typename T, typename S>
-__global__ __launch_bounds__(BLOCK) void k_half_rho(long N, CoefPhi<T, S> cf, S* __restrict__ h) {
+template <typename T, typename S, bool W>
+__global__ __launch_bounds__(BLOCK) void k_half_rho(long N, CoefPhi<T, S, W> cf, S* __restrict__ h) {
     for (long c = (long)blockIdx.x * BLOCK + threadIdx.x; c < N; c += (long)gridDim.x * BLOCK)
         h[c] = cf.hr((unsigned)c);
 }
 
 template <typename S>
 struct CoefStored {
+    static constexpr bool kWalls = false;   // wall faces hold stored zeros
     const S* __restrict__ b0;
     const S* __restrict__ b1;
     const S* __restrict__ b2;
@@ -181,7 +194,7 @@ __device__ __forceinline__ S apply_at(const S* bl, const S* bh, Fx x, S xc, S ih
 template <typename Coef, typename S, int DIM>
 __global__ __launch_bounds__(BLOCK) void k_beta_from_phi(Dims fd, Dims cd, Coef cf, S* b0, S* b1, S* b2) {
     Cell C;
-    if (!cell_of_thread(cd, C)) return;
+    if (!cell_of_thread<Coef::kWalls>(cd, C)) return;
     S* b[3] = {b0, b1, b2};
     const int i0 = 2 * C.i, j0 = 2 * C.j, k0 = DIM == 3 ? 2 * C.k : 0;
 #pragma unroll
@@ -192,8 +205,10 @@ __global__ __launch_bounds__(BLOCK) void k_beta_from_phi(Dims fd, Dims cd, Coef 
             int q = 0;
             for (int e = 0; e < DIM; ++e)
                 if (e != a) o[e] = (t >> q++) & 1;
-            const Cell F = make_cell(fd, i0 + o[0], j0 + o[1], k0 + o[2]);
-            s += recip(cf.hr(F.nb(a, -1)) + cf.hr(F.id));
+            const Cell F = Coef::kWalls ? make_cell_w(fd, i0 + o[0], j0 + o[1], k0 + o[2])
+                                        : make_cell(fd, i0 + o[0], j0 + o[1], k0 + o[2]);
+            const S f = recip(cf.hr(F.nb(a, -1)) + cf.hr(F.id));
+            s += F.wall(a, -1) ? S(0) : f;
         }
         b[a][C.id] = s * S(1.0 / (1 << (DIM - 1)));
     }
@@ -235,7 +250,7 @@ __global__ __launch_bounds__(BLOCK) void k_resid(Dims d, S ih2, Coef cf,
                                                  double* __restrict__ partials, long stride) {
     Cell C;
     double v[3] = {0.0, 0.0, 0.0};
-    if (cell_of_thread(d, C)) {
+    if (cell_of_thread<Coef::kWalls>(d, C)) {
         S bl[3], bh[3], dg;
         cf.template faces<DIM>(C, bl, bh);
         const unsigned c = C.id;
@@ -260,7 +275,7 @@ __global__ __launch_bounds__(BLOCK) void k_jac_first(Dims d, S ih2, S omega, Coe
                                                      const SolverScalars* __restrict__ sc) {
     if (sc->done) return;
     Cell C;
-    if (!cell_of_thread(d, C)) return;
+    if (!cell_of_thread<Coef::kWalls>(d, C)) return;
     S bl[3], bh[3], dg = S(0);
     cf.template faces<DIM>(C, bl, bh);
 #pragma unroll
@@ -282,7 +297,7 @@ __global__ __launch_bounds__(BLOCK) void k_jac_first_update(Dims d, S ih2, S ome
     if (sc->done) return;
     Cell C;
     double v[1] = {0.0};
-    if (cell_of_thread(d, C)) {
+    if (cell_of_thread<Coef::kWalls>(d, C)) {
         const unsigned c = C.id;
         const double alpha = sc->alpha;
         st(x, c, X((double)ld(x, c) + alpha * (double)ld(p, c)));
@@ -316,7 +331,7 @@ __global__ __launch_bounds__(BLOCK) void k_jac(Dims d, S ih2, S omega, Coef cf,
     if (sc->done) return;
     Cell C;
     double v[2] = {0.0, 0.0};
-    if (cell_of_thread(d, C)) {
+    if (cell_of_thread<Coef::kWalls>(d, C)) {
         auto Z = [&](int a, int s) -> S { return ld(z, C.nb(a, s)); };
         S bl[3], bh[3], dg;
         cf.template faces<DIM>(C, bl, bh);
@@ -433,7 +448,8 @@ __global__ __launch_bounds__(BLOCK) void k_restrict(Dims fd, Dims cd, S ih2, S r
                                  by, bz);
     const int fi = bx * BX + tx, fj = by * TY + ty, fk = bz * TZ + tz;
     const bool in = tile && fi < fd.nx && fj < fd.ny && fk < fd.nz;
-    const Cell C = make_cell(fd, in ? fi : 0, in ? fj : 0, in ? fk : 0);
+    const Cell C = Coef::kWalls ? make_cell_w(fd, in ? fi : 0, in ? fj : 0, in ? fk : 0)
+                                : make_cell(fd, in ? fi : 0, in ? fj : 0, in ? fk : 0);
     S res = S(0);
     if (in) {
         S bl[3], bh[3], dg;
@@ -941,7 +957,7 @@ __global__ __launch_bounds__(BLOCK) void k_apply(Dims d, S ih2, Coef cf, int fir
     if (sc->done) return;
     Cell C;
     double v[1] = {0.0};
-    if (cell_of_thread(d, C)) {
+    if (cell_of_thread<Coef::kWalls>(d, C)) {
         const S beta = first ? S(0) : S(sc->beta);
         auto Pn = [&](unsigned t) -> S { return first ? ld(z, t) : ld(z, t) + beta * ld(pold, t); };
         auto Pa = [&](int a, int s) { return Pn(C.nb(a, s)); };
@@ -1230,6 +1246,8 @@ struct Col : ColIndex {
     bool valid;               // lane owns a real column
     bool sxm, sxp;            // x neighbour held by the adjacent lane
     int kslab;                // index of this block's slab of kz planes
+    unsigned wxy;             // column next to a wall: 1 x-, 2 x+, 4 y-, 8 y+
+    bool wz;                  // walls at both ends of z
     __device__ __forceinline__ void init(const Dims& d, int kz) {
         const int tx = threadIdx.x;
         int bx = 0, by = 0;
@@ -1241,6 +1259,10 @@ struct Col : ColIndex {
         set(d.nx, d.ny, d.nz, valid ? i0 : 0, valid ? j0 : 0);
         sxm = tx > 0 && i > 0;
         sxp = tx < BX - 1 && i < nx - 1;
+        wxy = 0u;
+        if (d.walls & 1) wxy |= (i == 0 ? 1u : 0u) | (i == nx - 1 ? 2u : 0u);
+        if (d.walls & 2) wxy |= (j == 0 ? 4u : 0u) | (j == ny - 1 ? 8u : 0u);
+        wz = (d.walls & 4) != 0;
     }
 };
 
@@ -1255,16 +1277,17 @@ __device__ __forceinline__ V lane_p(V v) { return __shfl_down(v, 1, 64); }
 template <typename S>
 struct Nbr7 {
     S c, xm, xp, ym, yp, zm, zp;
+    unsigned wm;    // faces on a free-slip wall: 1 x-, 2 x+, 4 y-, 8 y+, 16 z-, 32 z+ (coefficient 0)
 };
 
 template <typename S>
 __device__ __forceinline__ void faces7(const Nbr7<S>& rho, S* bl, S* bh) {
-    bl[0] = recip(rho.xm + rho.c);
-    bh[0] = recip(rho.c + rho.xp);
-    bl[1] = recip(rho.ym + rho.c);
-    bh[1] = recip(rho.c + rho.yp);
-    bl[2] = recip(rho.zm + rho.c);
-    bh[2] = recip(rho.c + rho.zp);
+    bl[0] = (rho.wm & 1u) ? S(0) : recip(rho.xm + rho.c);
+    bh[0] = (rho.wm & 2u) ? S(0) : recip(rho.c + rho.xp);
+    bl[1] = (rho.wm & 4u) ? S(0) : recip(rho.ym + rho.c);
+    bh[1] = (rho.wm & 8u) ? S(0) : recip(rho.c + rho.yp);
+    bl[2] = (rho.wm & 16u) ? S(0) : recip(rho.zm + rho.c);
+    bh[2] = (rho.wm & 32u) ? S(0) : recip(rho.c + rho.zp);
 }
 
 template <typename S>
@@ -1349,6 +1372,11 @@ __device__ __forceinline__ void march(const Col& q, const Coef& cf, int k0, F fl
         const S hc = h[t + 1];
         const S lhm = lane_m(hc), lhp = lane_p(hc);
         Nbr7<S> R, X;
+        if constexpr (Coef::kWalls)
+            R.wm = q.wxy | (q.wz && k0 + t == 0 ? 16u : 0u) | (q.wz && k0 + t == q.nz - 1 ? 32u : 0u);
+        else
+            R.wm = 0u;
+        X.wm = 0u;
         R.c = hc;
         R.zm = h[t];
         R.zp = h[t + 2];
@@ -1596,23 +1624,25 @@ static unsigned vgrid(long N) {
     return (unsigned)(nb < VBLOCKS ? nb : VBLOCKS);
 }
 
-template <typename T, typename S>
+// W: the context's box has walls (the level-0 coefficient policies, and so
+// every level-0 kernel, are instantiated with wall bits)
+template <typename T, typename S, bool W = false>
 struct Solver {
     tpf_ctx* c;
     int dim;
     S w1, w2;       // damped-Jacobi weights of the two sweeps before (w1, w2) and after (w2, w1)
 
-    CoefPhi<T, S> coef_phi(const void* phi) const {
+    CoefPhi<T, S, W> coef_phi(const void* phi) const {
         const Phys P = phys_of(c);
         const S inf = std::numeric_limits<S>::infinity();
-        return CoefPhi<T, S>{static_cast<const T*>(phi), S(0.5 * P.rho2), S(0.5 * (P.rho1 - P.rho2)),
+        return CoefPhi<T, S, W>{static_cast<const T*>(phi), S(0.5 * P.rho2), S(0.5 * (P.rho1 - P.rho2)),
                              P.clamp ? S(0) : -inf, P.clamp ? S(1) : inf};
     }
     // fine-level coefficients: the half density computed by half_rho()
-    CoefRho<S> coef_fine() const { return CoefRho<S>{tp<S>(c->rhoh)}; }
+    CoefRho<S, W> coef_fine() const { return CoefRho<S, W>{tp<S>(c->rhoh)}; }
     void half_rho(const void* phi) {
         prof_begin(c, PC_VECTOR, (double)c->N * (sizeof(T) + sizeof(S)));
-        k_half_rho<T, S><<<vgrid(c->N), BLOCK, 0, c->stream>>>(c->N, coef_phi(phi), tp<S>(c->rhoh));
+        k_half_rho<T, S, W><<<vgrid(c->N), BLOCK, 0, c->stream>>>(c->N, coef_phi(phi), tp<S>(c->rhoh));
         prof_end(c);
     }
     CoefStored<S> coef(int l) const {
@@ -1621,7 +1651,9 @@ struct Solver {
     }
     S ih2(int l) const { return S(1.0 / (c->lv[l].h * c->lv[l].h)); }
     dim3 grid(int l) const { return grid_of(c->lv[l].n); }
-    Dims dims(int l) const { return dims_of(c->lv[l].n); }
+    // level 0 carries the walls (its coefficients are formed from rho; the
+    // stored coefficients of the coarse levels hold the zeros already)
+    Dims dims(int l) const { return dims_of(c->lv[l].n, l == 0 ? c->walls : 0); }
     // restriction weight: mean over the 2^d children times the coarse-grid
     // correction weight (the coarse problem is linear, so scaling its
     // right-hand side scales the correction; R stays proportional to P^T)
@@ -1659,7 +1691,7 @@ struct Solver {
         const dim3 b(BX, BY);
         half_rho(phi);
         if (c->nlev < 2) return;
-        k_beta_from_phi<CoefRho<S>, S, DIM><<<grid(1), b, 0, c->stream>>>(
+        k_beta_from_phi<CoefRho<S, W>, S, DIM><<<grid(1), b, 0, c->stream>>>(
             dims(0), dims(1), coef_fine(), tp<S>(c->lv[1].beta[0]), tp<S>(c->lv[1].beta[1]),
             tp<S>(c->lv[1].beta[2]));
         for (int l = 2; l < c->nlev; ++l)
@@ -1688,7 +1720,7 @@ struct Solver {
         S* zt = tp<S>(L.zt);
         S* r = tp<S>(L.r);
         const double cfl = cfields(l);
-        if constexpr (std::is_same<Coef, CoefRho<S>>::value) {
+        if constexpr (std::is_same<Coef, CoefRho<S, W>>::value) {
             if (DIM == 3 && march0()) {
                 Level& Lc = c->lv[l + 1];
                 if (!first_done) {
@@ -1741,7 +1773,7 @@ struct Solver {
         prof_begin(c, fine ? PC_F_PROLONG : PC_COARSE_LEVELS, fb(l, 2) + cb);
         k_prolong<S, DIM><<<grid(l + 1), b, 0, c->stream>>>(dims(l), dims(l + 1), zc, zt, c->scal);
         prof_end(c);
-        if constexpr (std::is_same<Coef, CoefRho<S>>::value) {
+        if constexpr (std::is_same<Coef, CoefRho<S, W>>::value) {
             if (DIM == 3 && march0()) {
                 prof_begin(c, PC_F_SWEEP, fb(l, 3 + cfl));
                 k_fz_jac<Coef, S, 0><<<mgrid(), b, 0, c->stream>>>(dims(0), kz(), ih2(0), w2, cf, r, zt, z,
@@ -1862,20 +1894,20 @@ struct Solver {
     // dot: the last sweep emits <r, z> partials to region 1.
     template <int DIM>
     void vcycle_t(const void* phi, bool first_done) {
-        const CoefRho<S> cf = coef_fine();
+        const auto cf = coef_fine();
         Level& L = c->lv[0];
         if (c->nlev == 1 && DIM == 3 && march0()) {
             // no coarsening possible: two Jacobi sweeps (still symmetric)
             const dim3 b(BX, BY);
             if (!first_done) {
                 prof_begin(c, PC_F_FIRST0, fb(0, 2 + cfields(0)));
-                k_fz_first<CoefRho<S>, S, S, 0><<<mgrid(), b, 0, c->stream>>>(dims(0), kz(), ih2(0), w1, cf, nullptr,
+                k_fz_first<CoefRho<S, W>, S, S, 0><<<mgrid(), b, 0, c->stream>>>(dims(0), kz(), ih2(0), w1, cf, nullptr,
                                                                    tp<S>(L.r), nullptr, nullptr, tp<S>(L.z),
                                                                    c->scal, nullptr);
                 prof_end(c);
             }
             prof_begin(c, PC_F_SWEEPDOT, fb(0, 3 + cfields(0)));
-            k_fz_jac<CoefRho<S>, S, 2><<<mgrid(), b, 0, c->stream>>>(dims(0), kz(), ih2(0), w2, cf, tp<S>(L.r),
+            k_fz_jac<CoefRho<S, W>, S, 2><<<mgrid(), b, 0, c->stream>>>(dims(0), kz(), ih2(0), w2, cf, tp<S>(L.r),
                                                            tp<S>(L.z), tp<S>(L.zt), tp<S>(c->qv), c->scal,
                                                            c->partials + c->max_blocks, c->max_blocks);
             prof_end(c);
@@ -1885,12 +1917,12 @@ struct Solver {
             // no coarsening possible: two Jacobi sweeps (still symmetric)
             if (!first_done) {
                 prof_begin(c, PC_F_FIRST0, fb(0, 2 + cfields(0)));
-                k_jac_first<CoefRho<S>, S, DIM><<<grid(0), dim3(BX, BY), 0, c->stream>>>(
+                k_jac_first<CoefRho<S, W>, S, DIM><<<grid(0), dim3(BX, BY), 0, c->stream>>>(
                     dims(0), ih2(0), w1, cf, tp<S>(L.r), tp<S>(L.z), c->scal);
                 prof_end(c);
             }
             prof_begin(c, PC_F_SWEEPDOT, fb(0, 3 + cfields(0)));
-            k_jac<CoefRho<S>, S, DIM, 1><<<grid(0), dim3(BX, BY), 0, c->stream>>>(
+            k_jac<CoefRho<S, W>, S, DIM, 1><<<grid(0), dim3(BX, BY), 0, c->stream>>>(
                 dims(0), ih2(0), w2, cf, tp<S>(L.r), tp<S>(L.z), tp<S>(L.zt), tp<S>(c->qv),
                 c->scal, c->partials + c->max_blocks, c->max_blocks);
             prof_end(c);
@@ -1908,18 +1940,18 @@ struct Solver {
     // first pre-smoothing sweep
     template <int DIM, typename X>
     void apply_update(const void* phi, int first, X* x) {
-        const CoefRho<S> cf = coef_fine();
+        const auto cf = coef_fine();
         const dim3 b(BX, BY);
         S* pold = tp<S>(c->pv);
         S* pnew = tp<S>(c->pv2);
         if (DIM == 3 && march0()) {
             prof_begin(c, PC_F_APPLY, fb(0, (first ? 1 : 2) + 2 + cfields(0)));
-            k_fz_apply<CoefRho<S>, S><<<mgrid(), b, 0, c->stream>>>(dims(0), kz(), ih2(0), cf, first, tp<S>(c->lv[0].zt),
+            k_fz_apply<CoefRho<S, W>, S><<<mgrid(), b, 0, c->stream>>>(dims(0), kz(), ih2(0), cf, first, tp<S>(c->lv[0].zt),
                                                           pold, pnew, tp<S>(c->qv), c->scal, c->partials);
             prof_end(c);
             (void)finalize2(c, (int)nb0(), 0, FIN_ALPHA, 0.0);
             prof_begin(c, PC_F_FIRST, fb(0, 5 + cfields(0)) + 2.0 * c->N * sizeof(X));
-            k_fz_first<CoefRho<S>, S, X, 1><<<mgrid(), b, 0, c->stream>>>(dims(0), kz(), ih2(0), w1, cf, x,
+            k_fz_first<CoefRho<S, W>, S, X, 1><<<mgrid(), b, 0, c->stream>>>(dims(0), kz(), ih2(0), w1, cf, x,
                                                                tp<S>(c->lv[0].r), pnew, tp<S>(c->qv),
                                                                tp<S>(c->lv[0].z), c->scal, c->partials);
             prof_end(c);
@@ -1927,12 +1959,12 @@ struct Solver {
             return;
         }
         prof_begin(c, PC_F_APPLY, fb(0, (first ? 1 : 2) + 2 + cfields(0)));
-        k_apply<CoefRho<S>, S, DIM><<<grid(0), b, 0, c->stream>>>(
+        k_apply<CoefRho<S, W>, S, DIM><<<grid(0), b, 0, c->stream>>>(
             dims(0), ih2(0), cf, first, tp<S>(c->lv[0].zt), pold, pnew, tp<S>(c->qv), c->scal, c->partials);
         prof_end(c);
         (void)finalize2(c, (int)nbl(0), 0, FIN_ALPHA, 0.0);
         prof_begin(c, PC_F_FIRST, fb(0, 5 + cfields(0)) + 2.0 * c->N * sizeof(X));
-        k_jac_first_update<CoefRho<S>, S, X, DIM><<<grid(0), b, 0, c->stream>>>(
+        k_jac_first_update<CoefRho<S, W>, S, X, DIM><<<grid(0), b, 0, c->stream>>>(
             dims(0), ih2(0), w1, cf, x, tp<S>(c->lv[0].r), pnew, tp<S>(c->qv), tp<S>(c->lv[0].z),
             c->scal, c->partials);
         prof_end(c);
@@ -2075,7 +2107,8 @@ tpf_status gauge_pressure(tpf_ctx* c) {
 // Solve with beta from phi (state precision); right-hand side in c->b with
 // its mean in scal->mean; x = c->p (warm start in, solution out; its mean is
 // whatever the warm start carried, see gauge_pressure).
-tpf_status poisson_solve(tpf_ctx* c, const void* phi, int* iters, double* relres, int* outer) {
+template <bool W>
+static tpf_status poisson_solve_t(tpf_ctx* c, const void* phi, int* iters, double* relres, int* outer) {
     const double rtol = c->P.poisson_rtol;
     const int maxit = c->P.poisson_maxit;
     SolverScalars s;
@@ -2083,13 +2116,13 @@ tpf_status poisson_solve(tpf_ctx* c, const void* phi, int* iters, double* relres
     if (!c->mixed) {
         double w1, w2;
         weights_of(c->dim, w1, w2);
-        Solver<double, double> sv{c, c->dim, w1, w2};
+        Solver<double, double, W> sv{c, c->dim, w1, w2};
         const bool fixed = c->fixed_inner > 0;
         sv.build_betas(phi);
-        sv.residual<double>(sv.coef_fine(), tp<double>(c->lv[0].r));
+        sv.template residual<double>(sv.coef_fine(), tp<double>(c->lv[0].r));
         (void)finalize3(c, (int)sv.nb0(), (int)sv.nb0(), (int)sv.nb0(), FIN_INIT, fixed ? 0.0 : rtol * rtol);
         bool have = false;
-        e = sv.pcg<double>(phi, c->p, fixed ? c->fixed_inner : maxit, 0, &s, &have);
+        e = sv.template pcg<double>(phi, c->p, fixed ? c->fixed_inner : maxit, 0, &s, &have);
         if (e != hipSuccess) return hip_fail(e, "FP64 PCG");
         if (!have) {
             tpf_status st = read_scalars(c, &s);
@@ -2111,8 +2144,8 @@ tpf_status poisson_solve(tpf_ctx* c, const void* phi, int* iters, double* relres
     // ---- mixed: FP64 defect correction around the FP32 multigrid-PCG
     double w1, w2;
     weights_of(c->dim, w1, w2);
-    Solver<float, float> sv{c, c->dim, float(w1), float(w2)};
-    Solver<float, double> s64{c, c->dim, 0.0};
+    Solver<float, float, W> sv{c, c->dim, float(w1), float(w2)};
+    Solver<float, double, W> s64{c, c->dim, 0.0};
     sv.build_betas(phi);
     const double rin = c->P.poisson_rtol_inner;
     int total = 0;
@@ -2122,7 +2155,7 @@ tpf_status poisson_solve(tpf_ctx* c, const void* phi, int* iters, double* relres
     const int max_outer = fixed ? c->fixed_outer + 1 : 12;
     std::string trail;      // relative outer residual after each pass, for the failure message
     for (int o = 0; o < max_outer; ++o) {
-        s64.residual<float>(s64.coef_phi(phi), tp<float>(c->lv[0].r));   // FP64 residual, FP64 beta
+        s64.template residual<float>(s64.coef_phi(phi), tp<float>(c->lv[0].r));   // FP64 residual, FP64 beta
         (void)finalize3(c, (int)s64.nb0(), (int)s64.nb0(), (int)s64.nb0(), FIN_INIT, fixed ? 0.0 : rtol * rtol);
         // the inner solve aims straight at the outer tolerance (half of the
         // reduction it needs), but never below rin, the depth an FP32 PCG
@@ -2155,7 +2188,7 @@ tpf_status poisson_solve(tpf_ctx* c, const void* phi, int* iters, double* relres
         }
         k_fill_s<float><<<vgrid(c->N), BLOCK, 0, c->stream>>>(c->N, tp<float>(c->ev), 0.0f);
         bool have = false;
-        e = sv.pcg<float>(phi, tp<float>(c->ev), fixed ? c->fixed_inner : maxit, 1 + std::min(o, 2), &s, &have);
+        e = sv.template pcg<float>(phi, tp<float>(c->ev), fixed ? c->fixed_inner : maxit, 1 + std::min(o, 2), &s, &have);
         if (e != hipSuccess) return hip_fail(e, "FP32 inner PCG");
         if (!have) {
             tpf_status st = read_scalars(c, &s);
@@ -2184,6 +2217,11 @@ tpf_status poisson_solve(tpf_ctx* c, const void* phi, int* iters, double* relres
     }
     set_error("pressure defect correction did not converge (relative residual after each pass:" + trail + ")");
     return TPF_ENOCONV;
+}
+
+tpf_status poisson_solve(tpf_ctx* c, const void* phi, int* iters, double* relres, int* outer) {
+    return c->walls ? poisson_solve_t<true>(c, phi, iters, relres, outer)
+                    : poisson_solve_t<false>(c, phi, iters, relres, outer);
 }
 
 }  // namespace tpf

@@ -7,21 +7,21 @@ namespace tpf {
 
 // ------------------------------------------------------------------ kernels
 // One thread per cell; the bodies are the op_* functions of tpf_stage_ops.hpp.
-template <typename T, int DIM>
+template <typename T, int DIM, bool W = false>
 __global__ __launch_bounds__(BLOCK) void k_cell(Dims d, int kz, Phys P, const T* __restrict__ phi,
                                                 T* __restrict__ n0, T* __restrict__ n1,
                                                 T* __restrict__ n2, T* __restrict__ mu) {
-    for_cells_zchunk(d, kz, [&](const Cell& C) { op_cell<T, DIM>(P, C, phi, n0, n1, n2, mu); });
+    for_cells_zchunk<W>(d, kz, [&](const Cell& C) { op_cell<T, DIM>(P, C, phi, n0, n1, n2, mu); });
 }
 
-template <typename T, int DIM>
+template <typename T, int DIM, bool W = false>
 __global__ __launch_bounds__(BLOCK) void k_kappa(Dims d, int kz, Phys P, const T* __restrict__ n0,
                                                  const T* __restrict__ n1,
                                                  const T* __restrict__ n2, T* __restrict__ kappa) {
-    for_cells_zchunk(d, kz, [&](const Cell& C) { op_kappa<T, DIM>(P, C, n0, n1, n2, kappa); });
+    for_cells_zchunk<W>(d, kz, [&](const Cell& C) { op_kappa<T, DIM>(P, C, n0, n1, n2, kappa); });
 }
 
-template <typename T, int DIM>
+template <typename T, int DIM, bool W = false>
 __global__ __launch_bounds__(BLOCK) void k_face(Dims d, int kz, Phys P, const T* __restrict__ phi,
                                                 const T* __restrict__ n0, const T* __restrict__ n1,
                                                 const T* __restrict__ n2, const T* __restrict__ u0,
@@ -29,26 +29,26 @@ __global__ __launch_bounds__(BLOCK) void k_face(Dims d, int kz, Phys P, const T*
                                                 T* __restrict__ r0, T* __restrict__ r1,
                                                 T* __restrict__ r2, T* __restrict__ m0,
                                                 T* __restrict__ m1, T* __restrict__ m2) {
-    for_cells_zchunk(d, kz, [&](const Cell& C) {
+    for_cells_zchunk<W>(d, kz, [&](const Cell& C) {
         op_face<T, DIM>(P, C, phi, n0, n1, n2, u0, u1, u2, r0, r1, r2, m0, m1, m2);
     });
 }
 
-template <typename T, int DIM>
+template <typename T, int DIM, bool W = false>
 __global__ __launch_bounds__(BLOCK) void k_momentum(
     Dims d, int kz, Phys P, const T* __restrict__ phi, const T* __restrict__ u0,
     const T* __restrict__ u1, const T* __restrict__ u2, const T* __restrict__ m0,
     const T* __restrict__ m1, const T* __restrict__ m2, const T* __restrict__ mu,
     const T* __restrict__ kappa, T* __restrict__ f0, T* __restrict__ f1, T* __restrict__ f2,
     T* __restrict__ F0, T* __restrict__ F1, T* __restrict__ F2) {
-    for_cells_zchunk(d, kz, [&](const Cell& C) {
+    for_cells_zchunk<W>(d, kz, [&](const Cell& C) {
         op_momentum<T, DIM>(P, C, phi, u0, u1, u2, m0, m1, m2, mu, kappa, f0, f1, f2, F0, F1, F2);
     });
 }
 
 // the phase-field update and the momentum right-hand side of one cell in one
 // pass: both read phi and u at the same cells
-template <typename T, int DIM>
+template <typename T, int DIM, bool W = false>
 __global__ __launch_bounds__(BLOCK) void k_phase_momentum(
     Dims d, int kz, Phys P, RKArgs rk, const T* __restrict__ phi, const T* __restrict__ u0,
     const T* __restrict__ u1, const T* __restrict__ u2, const T* __restrict__ r0,
@@ -57,7 +57,7 @@ __global__ __launch_bounds__(BLOCK) void k_phase_momentum(
     const T* __restrict__ m0, const T* __restrict__ m1, const T* __restrict__ m2,
     const T* __restrict__ mu, T* __restrict__ f0, T* __restrict__ f1, T* __restrict__ f2,
     T* __restrict__ F0, T* __restrict__ F1, T* __restrict__ F2) {
-    for_cells_zchunk(d, kz, [&](const Cell& C) {
+    for_cells_zchunk<W>(d, kz, [&](const Cell& C) {
         op_phase<T, DIM>(P, rk, C, phi, u0, u1, u2, r0, r1, r2, kappa, yn, acc, ynext, flags);
         op_momentum<T, DIM>(P, C, phi, u0, u1, u2, m0, m1, m2, mu, kappa, f0, f1, f2, F0, F1, F2);
     });
@@ -314,18 +314,18 @@ __global__ __launch_bounds__(BLOCK) void k_phase_momentum_lds(
 }
 
 // b = D f* in FP64, plus the block sums of b (for the mean)
-template <typename T, int DIM>
+template <typename T, int DIM, bool W = false>
 __global__ __launch_bounds__(BLOCK) void k_div(Dims d, Phys P, const T* __restrict__ f0,
                                                const T* __restrict__ f1,
                                                const T* __restrict__ f2, double* __restrict__ b,
                                                double* __restrict__ partials) {
     Cell C;
     double v[1] = {0.0};
-    if (cell_of_thread(d, C)) v[0] = op_div<T, DIM>(P, C, f0, f1, f2, b);
+    if (cell_of_thread<W>(d, C)) v[0] = op_div<T, DIM>(P, C, f0, f1, f2, b);
     block_partials<1>(v, partials);
 }
 
-template <typename T, int DIM>
+template <typename T, int DIM, bool W = false>
 __global__ __launch_bounds__(BLOCK) void k_project(Dims d, int kz, Phys P, RKArgs rk,
                                                    const T* __restrict__ phi,
                                                    const double* __restrict__ p,
@@ -334,7 +334,7 @@ __global__ __launch_bounds__(BLOCK) void k_project(Dims d, int kz, Phys P, RKArg
                                                    const T* yn1, const T* yn2, T* acc0, T* acc1,
                                                    T* acc2, T* nx0, T* nx1, T* nx2,
                                                    int* __restrict__ flags) {
-    for_cells_zchunk(d, kz, [&](const Cell& C) {
+    for_cells_zchunk<W>(d, kz, [&](const Cell& C) {
         op_project<T, DIM>(P, rk, C, phi, p, f0, f1, f2, yn0, yn1, yn2, acc0, acc1, acc2, nx0, nx1, nx2, flags);
     });
 }
@@ -365,7 +365,7 @@ __global__ void k_fill(long N, T* __restrict__ dst, T v) {
 }
 
 // ------------------------------------------------------------------ diagnostics
-template <typename T, int DIM>
+template <typename T, int DIM, bool W = false>
 __global__ __launch_bounds__(BLOCK) void k_diag(Dims d, Phys P, const T* __restrict__ phi,
                                                 const T* __restrict__ u0, const T* __restrict__ u1,
                                                 const T* __restrict__ u2,
@@ -374,7 +374,7 @@ __global__ __launch_bounds__(BLOCK) void k_diag(Dims d, Phys P, const T* __restr
     Cell C;
     double s[ND_SUM] = {0, 0, 0, 0, 0, 0, 0};
     double mx[ND_MAX] = {0.0, 0.0, -1e300, -1e300};
-    if (cell_of_thread(d, C)) op_diag<T, DIM>(P, C, phi, u0, u1, u2, p, s, mx);
+    if (cell_of_thread<W>(d, C)) op_diag<T, DIM>(P, C, phi, u0, u1, u2, p, s, mx);
     block_sum<ND_SUM>(s);
     block_max<ND_MAX>(mx);
     if (thread_linear() == 0) {
@@ -407,36 +407,42 @@ static inline T* tp(void* p) { return static_cast<T*>(p); }
 template <typename T>
 static inline const T* ctp(const void* p) { return static_cast<const T*>(p); }
 
-template <typename T, int DIM>
+template <typename T, int DIM, bool W>
 static hipError_t stage_fields_impl(tpf_ctx* c, const void* phi_s) {
     const Phys P = phys_of(c);
-    const Dims d = dims_of(c->n);
+    const Dims d = dims_of(c->n, c->walls);
     const int kz = c->stage_kz;
     const dim3 g = zchunk_grid(c->n, kz), b(BX, BY);
     const bool need_mu = c->P.force == FORCE_EB;
     const bool need_kappa = c->P.model != MODEL_CDI || c->P.force != FORCE_EB;
     prof_begin(c, PC_CELL, (double)c->N * c->tsz * (1 + DIM + (need_mu ? 1 : 0)));
-    k_cell<T, DIM><<<g, b, 0, c->stream>>>(d, kz, P, ctp<T>(phi_s), tp<T>(c->nrm[0]), tp<T>(c->nrm[1]),
+    k_cell<T, DIM, W><<<g, b, 0, c->stream>>>(d, kz, P, ctp<T>(phi_s), tp<T>(c->nrm[0]), tp<T>(c->nrm[1]),
                                            tp<T>(c->nrm[2]), need_mu ? tp<T>(c->mu) : nullptr);
     prof_end(c);
     if (need_kappa) {
         prof_begin(c, PC_KAPPA, (double)c->N * c->tsz * (DIM + 1));
-        k_kappa<T, DIM><<<g, b, 0, c->stream>>>(d, kz, P, ctp<T>(c->nrm[0]), ctp<T>(c->nrm[1]),
+        k_kappa<T, DIM, W><<<g, b, 0, c->stream>>>(d, kz, P, ctp<T>(c->nrm[0]), ctp<T>(c->nrm[1]),
                                                 ctp<T>(c->nrm[2]), tp<T>(c->kappa));
         prof_end(c);
     }
     return hipGetLastError();
 }
 
-template <typename T, int DIM>
+// the instantiation with or without wall bits
+template <typename T, int DIM, typename... A>
+static hipError_t stage_fields_impl_w(tpf_ctx* c, A... a) {
+    return c->walls ? stage_fields_impl<T, DIM, true>(c, a...) : stage_fields_impl<T, DIM, false>(c, a...);
+}
+
+template <typename T, int DIM, bool W>
 static hipError_t face_impl(tpf_ctx* c, const void* phi_s, const void* const u_s[3]) {
     const Phys P = phys_of(c);
-    const Dims d = dims_of(c->n);
+    const Dims d = dims_of(c->n, c->walls);
     const int kz = c->stage_kz;
     const dim3 g = zchunk_grid(c->n, kz), b(BX, BY);
     const int cdi = c->P.model == MODEL_CDI;
     prof_begin(c, PC_FACE, (double)c->N * c->tsz * (1 + DIM * (cdi ? 4 : 2)));
-    k_face<T, DIM><<<g, b, 0, c->stream>>>(
+    k_face<T, DIM, W><<<g, b, 0, c->stream>>>(
         d, kz, P, ctp<T>(phi_s), ctp<T>(c->nrm[0]), ctp<T>(c->nrm[1]), ctp<T>(c->nrm[2]),
         ctp<T>(u_s[0]), ctp<T>(u_s[1]), ctp<T>(u_s[2]), tp<T>(c->rflux[0]), tp<T>(c->rflux[1]),
         tp<T>(c->rflux[2]), tp<T>(c->mflux[0]), tp<T>(c->mflux[1]), tp<T>(c->mflux[2]));
@@ -444,11 +450,17 @@ static hipError_t face_impl(tpf_ctx* c, const void* phi_s, const void* const u_s
     return hipGetLastError();
 }
 
+// the instantiation with or without wall bits
+template <typename T, int DIM, typename... A>
+static hipError_t face_impl_w(tpf_ctx* c, A... a) {
+    return c->walls ? face_impl<T, DIM, true>(c, a...) : face_impl<T, DIM, false>(c, a...);
+}
+
 // the LDS form of k_cell + k_face, then k_kappa where kappa is needed (3D)
 template <typename T>
 static hipError_t cell_face_lds_impl(tpf_ctx* c, const void* phi_s, const void* const u_s[3]) {
     const Phys P = phys_of(c);
-    const Dims d = dims_of(c->n);
+    const Dims d = dims_of(c->n, c->walls);
     const int lkz = c->stage_lds_kz;
     const dim3 lg = zchunk_grid(c->n, lkz), b(BX, BY);
     const bool cdi = c->P.model == MODEL_CDI, need_mu = c->P.force == FORCE_EB;
@@ -477,23 +489,23 @@ hipError_t launch_stage_fields(tpf_ctx* c, const void* phi_s, const void* const 
     if (c->dim == 3 && c->stage_lds)
         return c->mixed ? cell_face_lds_impl<float>(c, phi_s, u_s) : cell_face_lds_impl<double>(c, phi_s, u_s);
     if (c->mixed) {
-        e = c->dim == 2 ? stage_fields_impl<float, 2>(c, phi_s) : stage_fields_impl<float, 3>(c, phi_s);
+        e = c->dim == 2 ? stage_fields_impl_w<float, 2>(c, phi_s) : stage_fields_impl_w<float, 3>(c, phi_s);
         if (e != hipSuccess) return e;
-        return c->dim == 2 ? face_impl<float, 2>(c, phi_s, u_s) : face_impl<float, 3>(c, phi_s, u_s);
+        return c->dim == 2 ? face_impl_w<float, 2>(c, phi_s, u_s) : face_impl_w<float, 3>(c, phi_s, u_s);
     }
-    e = c->dim == 2 ? stage_fields_impl<double, 2>(c, phi_s) : stage_fields_impl<double, 3>(c, phi_s);
+    e = c->dim == 2 ? stage_fields_impl_w<double, 2>(c, phi_s) : stage_fields_impl_w<double, 3>(c, phi_s);
     if (e != hipSuccess) return e;
-    return c->dim == 2 ? face_impl<double, 2>(c, phi_s, u_s) : face_impl<double, 3>(c, phi_s, u_s);
+    return c->dim == 2 ? face_impl_w<double, 2>(c, phi_s, u_s) : face_impl_w<double, 3>(c, phi_s, u_s);
 }
 
-template <typename T, int DIM>
+template <typename T, int DIM, bool W>
 static hipError_t mom_impl(tpf_ctx* c, const void* phi_s, const void* const u_s[3], int want_force) {
     const Phys P = phys_of(c);
     const int kz = c->stage_kz;
     const dim3 g = zchunk_grid(c->n, kz), b(BX, BY);
     prof_begin(c, PC_MOM, (double)c->N * c->tsz * (1 + 3 * DIM + 1));
-    k_momentum<T, DIM><<<g, b, 0, c->stream>>>(
-        dims_of(c->n), kz, P, ctp<T>(phi_s), ctp<T>(u_s[0]), ctp<T>(u_s[1]), ctp<T>(u_s[2]),
+    k_momentum<T, DIM, W><<<g, b, 0, c->stream>>>(
+        dims_of(c->n, c->walls), kz, P, ctp<T>(phi_s), ctp<T>(u_s[0]), ctp<T>(u_s[1]), ctp<T>(u_s[2]),
         ctp<T>(c->mflux[0]), ctp<T>(c->mflux[1]), ctp<T>(c->mflux[2]), ctp<T>(c->mu),
         ctp<T>(c->kappa), tp<T>(c->fs[0]), tp<T>(c->fs[1]), tp<T>(c->fs[2]),
         want_force ? tp<T>(c->force[0]) : nullptr, tp<T>(c->force[1]), tp<T>(c->force[2]));
@@ -501,15 +513,21 @@ static hipError_t mom_impl(tpf_ctx* c, const void* phi_s, const void* const u_s[
     return hipGetLastError();
 }
 
-hipError_t launch_momentum(tpf_ctx* c, const void* phi_s, const void* const u_s[3], int want_force) {
-    if (c->mixed)
-        return c->dim == 2 ? mom_impl<float, 2>(c, phi_s, u_s, want_force)
-                           : mom_impl<float, 3>(c, phi_s, u_s, want_force);
-    return c->dim == 2 ? mom_impl<double, 2>(c, phi_s, u_s, want_force)
-                       : mom_impl<double, 3>(c, phi_s, u_s, want_force);
+// the instantiation with or without wall bits
+template <typename T, int DIM, typename... A>
+static hipError_t mom_impl_w(tpf_ctx* c, A... a) {
+    return c->walls ? mom_impl<T, DIM, true>(c, a...) : mom_impl<T, DIM, false>(c, a...);
 }
 
-template <typename T, int DIM>
+hipError_t launch_momentum(tpf_ctx* c, const void* phi_s, const void* const u_s[3], int want_force) {
+    if (c->mixed)
+        return c->dim == 2 ? mom_impl_w<float, 2>(c, phi_s, u_s, want_force)
+                           : mom_impl_w<float, 3>(c, phi_s, u_s, want_force);
+    return c->dim == 2 ? mom_impl_w<double, 2>(c, phi_s, u_s, want_force)
+                       : mom_impl_w<double, 3>(c, phi_s, u_s, want_force);
+}
+
+template <typename T, int DIM, bool W>
 static hipError_t phase_mom_impl(tpf_ctx* c, const void* phi_s, const void* const u_s[3], const RKArgs& rk,
                                  void* out, int want_force) {
     const Phys P = phys_of(c);
@@ -528,7 +546,7 @@ static hipError_t phase_mom_impl(tpf_ctx* c, const void* phi_s, const void* cons
         auto kern = cdi ? (eb ? k_phase_momentum_lds<T, true, true> : k_phase_momentum_lds<T, true, false>)
                         : (eb ? k_phase_momentum_lds<T, false, true> : k_phase_momentum_lds<T, false, false>);
         kern<<<lg, b, 0, c->stream>>>(
-            dims_of(c->n), lkz, P, rk, ctp<T>(phi_s), ctp<T>(u_s[0]), ctp<T>(u_s[1]), ctp<T>(u_s[2]),
+            dims_of(c->n, c->walls), lkz, P, rk, ctp<T>(phi_s), ctp<T>(u_s[0]), ctp<T>(u_s[1]), ctp<T>(u_s[2]),
             ctp<T>(c->rflux[0]), ctp<T>(c->rflux[1]), ctp<T>(c->rflux[2]), ctp<T>(c->kappa), yn, acc, tp<T>(out),
             c->flags, ctp<T>(c->mflux[0]), ctp<T>(c->mflux[1]), ctp<T>(c->mflux[2]), ctp<T>(c->mu),
             tp<T>(c->fs[0]), tp<T>(c->fs[1]), tp<T>(c->fs[2]), want_force ? tp<T>(c->force[0]) : nullptr,
@@ -536,8 +554,8 @@ static hipError_t phase_mom_impl(tpf_ctx* c, const void* phi_s, const void* cons
         prof_end(c);
         return hipGetLastError();
     }
-    k_phase_momentum<T, DIM><<<g, b, 0, c->stream>>>(
-        dims_of(c->n), kz, P, rk, ctp<T>(phi_s), ctp<T>(u_s[0]), ctp<T>(u_s[1]), ctp<T>(u_s[2]),
+    k_phase_momentum<T, DIM, W><<<g, b, 0, c->stream>>>(
+        dims_of(c->n, c->walls), kz, P, rk, ctp<T>(phi_s), ctp<T>(u_s[0]), ctp<T>(u_s[1]), ctp<T>(u_s[2]),
         ctp<T>(c->rflux[0]), ctp<T>(c->rflux[1]), ctp<T>(c->rflux[2]), ctp<T>(c->kappa), yn, acc, tp<T>(out),
         c->flags, ctp<T>(c->mflux[0]), ctp<T>(c->mflux[1]), ctp<T>(c->mflux[2]), ctp<T>(c->mu),
         tp<T>(c->fs[0]), tp<T>(c->fs[1]), tp<T>(c->fs[2]), want_force ? tp<T>(c->force[0]) : nullptr,
@@ -546,43 +564,55 @@ static hipError_t phase_mom_impl(tpf_ctx* c, const void* phi_s, const void* cons
     return hipGetLastError();
 }
 
+// the instantiation with or without wall bits
+template <typename T, int DIM, typename... A>
+static hipError_t phase_mom_impl_w(tpf_ctx* c, A... a) {
+    return c->walls ? phase_mom_impl<T, DIM, true>(c, a...) : phase_mom_impl<T, DIM, false>(c, a...);
+}
+
 hipError_t launch_phase_momentum(tpf_ctx* c, const void* phi_s, const void* const u_s[3], const RKArgs& rk,
                                  void* out, int want_force) {
     if (c->mixed)
-        return c->dim == 2 ? phase_mom_impl<float, 2>(c, phi_s, u_s, rk, out, want_force)
-                           : phase_mom_impl<float, 3>(c, phi_s, u_s, rk, out, want_force);
-    return c->dim == 2 ? phase_mom_impl<double, 2>(c, phi_s, u_s, rk, out, want_force)
-                       : phase_mom_impl<double, 3>(c, phi_s, u_s, rk, out, want_force);
+        return c->dim == 2 ? phase_mom_impl_w<float, 2>(c, phi_s, u_s, rk, out, want_force)
+                           : phase_mom_impl_w<float, 3>(c, phi_s, u_s, rk, out, want_force);
+    return c->dim == 2 ? phase_mom_impl_w<double, 2>(c, phi_s, u_s, rk, out, want_force)
+                       : phase_mom_impl_w<double, 3>(c, phi_s, u_s, rk, out, want_force);
 }
 
-template <typename T, int DIM>
+template <typename T, int DIM, bool W>
 static hipError_t div_impl(tpf_ctx* c) {
     const Phys P = phys_of(c);
     const dim3 g = grid_of(c->n), b(BX, BY);
     prof_begin(c, PC_DIV, (double)c->N * (c->tsz * DIM + 8));
-    k_div<T, DIM><<<g, b, 0, c->stream>>>(dims_of(c->n), P, ctp<T>(c->fs[0]), ctp<T>(c->fs[1]),
+    k_div<T, DIM, W><<<g, b, 0, c->stream>>>(dims_of(c->n, c->walls), P, ctp<T>(c->fs[0]), ctp<T>(c->fs[1]),
                                           ctp<T>(c->fs[2]), c->b, c->partials);
     prof_end(c);
     return hipGetLastError();
 }
 
+// the instantiation with or without wall bits
+template <typename T, int DIM, typename... A>
+static hipError_t div_impl_w(tpf_ctx* c, A... a) {
+    return c->walls ? div_impl<T, DIM, true>(c, a...) : div_impl<T, DIM, false>(c, a...);
+}
+
 hipError_t launch_divergence(tpf_ctx* c) {
     hipError_t e;
-    if (c->mixed) e = c->dim == 2 ? div_impl<float, 2>(c) : div_impl<float, 3>(c);
-    else e = c->dim == 2 ? div_impl<double, 2>(c) : div_impl<double, 3>(c);
+    if (c->mixed) e = c->dim == 2 ? div_impl_w<float, 2>(c) : div_impl_w<float, 3>(c);
+    else e = c->dim == 2 ? div_impl_w<double, 2>(c) : div_impl_w<double, 3>(c);
     if (e != hipSuccess) return e;
     return launch_finalize(c, (int)nblocks_of(c->n), 1, FIN_MEAN);
 }
 
-template <typename T, int DIM>
+template <typename T, int DIM, bool W>
 static hipError_t proj_impl(tpf_ctx* c, const void* phi_s, const RKArgs& rk, void* const out[3]) {
     const Phys P = phys_of(c);
     const int kz = c->stage_kz;
     const dim3 g = zchunk_grid(c->n, kz), b(BX, BY);
     const int yn = c->s_yn, ac = c->s_acc;
     prof_begin(c, PC_PROJ, (double)c->N * (c->tsz * (1 + DIM + (rk.eval_only ? DIM : DIM * (3 + (rk.stage < 3)))) + 8));
-    k_project<T, DIM><<<g, b, 0, c->stream>>>(
-        dims_of(c->n), kz, P, rk, ctp<T>(phi_s), c->p, ctp<T>(c->fs[0]), ctp<T>(c->fs[1]),
+    k_project<T, DIM, W><<<g, b, 0, c->stream>>>(
+        dims_of(c->n, c->walls), kz, P, rk, ctp<T>(phi_s), c->p, ctp<T>(c->fs[0]), ctp<T>(c->fs[1]),
         ctp<T>(c->fs[2]), ctp<T>(c->u[0][yn]), ctp<T>(c->u[1][yn]), ctp<T>(c->u[2][yn]),
         tp<T>(c->u[0][ac]), tp<T>(c->u[1][ac]), tp<T>(c->u[2][ac]), tp<T>(out[0]), tp<T>(out[1]),
         tp<T>(out[2]), c->flags);
@@ -590,15 +620,21 @@ static hipError_t proj_impl(tpf_ctx* c, const void* phi_s, const RKArgs& rk, voi
     return hipGetLastError();
 }
 
+// the instantiation with or without wall bits
+template <typename T, int DIM, typename... A>
+static hipError_t proj_impl_w(tpf_ctx* c, A... a) {
+    return c->walls ? proj_impl<T, DIM, true>(c, a...) : proj_impl<T, DIM, false>(c, a...);
+}
+
 hipError_t launch_project_update(tpf_ctx* c, const void* phi_s, const RKArgs& rk, void* const out[3]) {
     if (c->mixed)
-        return c->dim == 2 ? proj_impl<float, 2>(c, phi_s, rk, out) : proj_impl<float, 3>(c, phi_s, rk, out);
-    return c->dim == 2 ? proj_impl<double, 2>(c, phi_s, rk, out) : proj_impl<double, 3>(c, phi_s, rk, out);
+        return c->dim == 2 ? proj_impl_w<float, 2>(c, phi_s, rk, out) : proj_impl_w<float, 3>(c, phi_s, rk, out);
+    return c->dim == 2 ? proj_impl_w<double, 2>(c, phi_s, rk, out) : proj_impl_w<double, 3>(c, phi_s, rk, out);
 }
 
 hipError_t launch_init_droplet(tpf_ctx* c, const double center[3], const double axes[3]) {
     const dim3 g = grid_of(c->n), b(BX, BY);
-    const Dims d = dims_of(c->n);
+    const Dims d = dims_of(c->n, c->walls);
     void* dst = c->phi[c->s_yn];
     const double eps = c->P.eps;
 #define TPF_INIT(T, D)                                                                        \
@@ -634,28 +670,34 @@ hipError_t launch_zero_state(tpf_ctx* c, void* dst) {
     return hipGetLastError();
 }
 
-template <typename T, int DIM>
-static hipError_t diag_impl(hipStream_t st, const int n[3], const Phys& P, const void* phi,
+template <typename T, int DIM, bool W>
+static hipError_t diag_impl(hipStream_t st, const int n[3], int walls, const Phys& P, const void* phi,
                             const void* const u[3], const double* p, double* part, double* out) {
     const dim3 g = grid_of(n), b(BX, BY);
-    k_diag<T, DIM><<<g, b, 0, st>>>(dims_of(n), P, ctp<T>(phi), ctp<T>(u[0]), ctp<T>(u[1]),
+    k_diag<T, DIM, W><<<g, b, 0, st>>>(dims_of(n, walls), P, ctp<T>(phi), ctp<T>(u[0]), ctp<T>(u[1]),
                                     ctp<T>(u[2] ? u[2] : u[1]), p, part);
     k_diag_final<<<1, BLOCK, 0, st>>>((int)nblocks_of(n), part, out);
     return hipGetLastError();
 }
 
-hipError_t launch_diagnostics_arrays(hipStream_t st, int dim, const int n[3], int fp32, const Phys& P,
+// the instantiation with or without wall bits
+template <typename T, int DIM, typename... A>
+static hipError_t diag_impl_w(hipStream_t st, const int n[3], int walls, A... a) {
+    return walls ? diag_impl<T, DIM, true>(st, n, walls, a...) : diag_impl<T, DIM, false>(st, n, walls, a...);
+}
+
+hipError_t launch_diagnostics_arrays(hipStream_t st, int dim, const int n[3], int walls, int fp32, const Phys& P,
                                      const void* phi, const void* const u[3], const double* p, double* part,
                                      double* out) {
     if (fp32)
-        return dim == 2 ? diag_impl<float, 2>(st, n, P, phi, u, p, part, out)
-                        : diag_impl<float, 3>(st, n, P, phi, u, p, part, out);
-    return dim == 2 ? diag_impl<double, 2>(st, n, P, phi, u, p, part, out)
-                    : diag_impl<double, 3>(st, n, P, phi, u, p, part, out);
+        return dim == 2 ? diag_impl_w<float, 2>(st, n, walls, P, phi, u, p, part, out)
+                        : diag_impl_w<float, 3>(st, n, walls, P, phi, u, p, part, out);
+    return dim == 2 ? diag_impl_w<double, 2>(st, n, walls, P, phi, u, p, part, out)
+                    : diag_impl_w<double, 3>(st, n, walls, P, phi, u, p, part, out);
 }
 
 hipError_t launch_diagnostics(tpf_ctx* c, const void* phi, const void* const u[3], const double* p) {
-    return launch_diagnostics_arrays(c->stream, c->dim, c->n, c->mixed, phys_of(c), phi, u, p, c->diag_part,
+    return launch_diagnostics_arrays(c->stream, c->dim, c->n, c->walls, c->mixed, phys_of(c), phi, u, p, c->diag_part,
                                      c->diag_out);
 }
 

@@ -151,6 +151,8 @@ def test_walls_validation(tpf):
     ok = tpf.batch_workspace_bytes([tpf.make_params((32, 32), walls=w) for w in range(4)])
     assert ok == tpf.batch_workspace_bytes([tpf.make_params((32, 32))] * 4)
     for n, w in (((32, 32), 1), ((16, 16, 16), 4)):
+        assert tpf.workspace_bytes(tpf.make_params(n, walls=w)) == tpf.workspace_bytes(tpf.make_params(n))
+        # the adjoint calls need a periodic box
         with pytest.raises(tpf.TpfError) as e:
-            tpf.workspace_bytes(tpf.make_params(n, walls=w))
-        assert e.value.status == tpf.TPF_EINVAL and "batched" in str(e.value)
+            tpf.workspace_bytes(tpf.make_params(n, walls=w, adjoint=1))
+        assert e.value.status == tpf.TPF_EINVAL and "periodic" in str(e.value)

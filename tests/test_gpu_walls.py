@@ -255,3 +255,144 @@ def test_batch_walls_equal_doubled_periodic_box(gpu, precision):
         say(f"  {c.name}: |dphi| {ephi:.2e} |du|/|u| {eu:.2e} mirror {esym:.2e}")
         bound = (1e-12, 1e-11) if precision == "fp64" else (1e-6, 2e-4)
         assert ephi < bound[0] and eu < bound[1] and esym < bound[1], c.name
+
+
+# ------------------------------------------------------------ single-case contexts
+
+
+def shut_walls3(u, walls):
+    """Copies of the 3D face velocities with 0 on the wall faces."""
+    u = [x.copy() for x in u]
+    for a in range(3):
+        if (walls >> a) & 1:
+            idx = [slice(None)] * 3
+            idx[2 - a] = 0
+            u[a][tuple(idx)] = 0.0
+    return u
+
+
+def single_cases():
+    """Walled single cases: 2D (FP64, the plain solver kernels) and 3D (the
+    z-marching fine level, stored-coefficient and fused coarse levels, the LDS
+    tail), every model, walls on one to three axes."""
+    C = workloads.Case
+    return [
+        (C("s2_cdi_eb", (48, 40), (0.3, 0.35), (0.25, 0.2), 10.0, 1.0, 0.02, 0.004, 1.0, 1.0, "CDI", "EB", "fp64"), 3),
+        (C("s2_sb_lcsf", (40, 48), (0.55, 0.3), (0.3, 0.25), 1.0, 0.01, 0.01, 1e-4, 1.0, 0.8, "SB", "LCSF", "fp64"), 2),
+        (C("s3_isodi_csf", (24, 20, 16), (0.35, 0.45, 0.3), (0.3, 0.25, 0.22), 10.0, 1.0, 0.02, 0.004, 1.2, 1.0,
+           "ISODI", "CSF", "fp64"), 5),
+        (C("s3_cdi_eb", (16, 16, 16), (0.4, 0.5, 0.35), (0.3, 0.25, 0.25), 10.0, 1.0, 0.02, 0.002, 1.0, 0.75,
+           "CDI", "EB", "fp64"), 7),
+    ]
+
+
+@pytest.mark.parametrize("k", range(4))
+def test_single_case_walls_match_oracle(gpu, ora, k):
+    """A single-case context with walls against the walled oracle, FP64,
+    3 steps from a seeded velocity that is 0 on the wall faces."""
+    c, w = single_cases()[k]
+    steps = 3
+    say(f"single-case walled parity {c.name} walls {w}")
+    P = oparams(ora, c, w)
+    phi0 = ora.init_droplet(P, c.center, c.semi_axes)
+    u0 = workloads.random_velocity(P.shape, 70 + k, 0.01)
+    u0 = shut_walls(u0, w) if c.dim == 2 else shut_walls3(u0, w)
+    dt = c.dt(umax0=max(np.abs(x).max() for x in u0))
+    s = gpu.solver_for_case(c, walls=w, poisson_rtol=1e-14, poisson_maxit=2000)
+    s.init_droplet(c.center, c.semi_axes)
+    phi_i, _, _ = s.get_state()
+    assert np.abs(phi_i - phi0).max() < 1e-14
+    s.set_state(phi0, u0)
+    s.step(dt, steps)
+    # a single-case context reports the projection pressure of its current
+    # state (a stage evaluation there), not the last stage's
+    got = s.get_state(with_pressure=True)
+    phi_o, u_o, p_last = ora.step(P, dt, steps, phi0, u0)
+    _, du_o, p_o = ora.stage(P, phi_o, u_o, p_last)
+    uref = max(max(np.abs(x).max() for x in u_o), dt * max(np.abs(x).max() for x in du_o))
+    ephi = np.abs(got[0] - phi_o).max()
+    eu = max(np.abs(got[1][a] - u_o[a]).max() for a in range(c.dim)) / uref
+    ep = np.abs(got[2] - p_o).max() / np.abs(p_o).max()
+    say(f"  |dphi| {ephi:.2e} |du|/Uref {eu:.2e} |dp|/|p| {ep:.2e}")
+    assert ephi < 1e-12 and eu < 1e-11 and ep < 1e-12
+    d = s.diagnostics()
+    do = ora.diagnostics(P, got[0], got[1], got[2])
+    for key in ("mass", "se", "ke", "umax", "div_max"):
+        assert abs(d[key] - do[key]) <= 1e-12 * max(abs(do[key]), 1e-300) + (1e-15 if key == "div_max" else 0.0), key
+
+
+def test_single_case_walls_mixed_error_statement(gpu, ora):
+    """FP32-mixed 3D walled case (24 x 20 x 16, walls on x and z) against the
+    FP64 oracle from the FP32-rounded state: the mixed-precision bounds."""
+    c, w = single_cases()[2]
+    c = dataclasses.replace(c, precision="fp32_mixed")
+    say(f"single-case walled FP32-mixed {c.name}")
+    P = oparams(ora, c, w)
+    phi0 = ora.init_droplet(P, c.center, c.semi_axes).astype(np.float32).astype(np.float64)
+    u0 = [x.astype(np.float32).astype(np.float64) for x in shut_walls3(workloads.random_velocity(P.shape, 77, 0.01), w)]
+    dt = c.dt(umax0=max(np.abs(x).max() for x in u0))
+    s = gpu.solver_for_case(c, walls=w)
+    s.set_state(phi0, u0)
+    s.step(dt, 4)
+    phi_g, u_g, _ = s.get_state()
+    phi_o, u_o, _ = ora.step(P, dt, 4, phi0, u0)
+    us = max(np.abs(x).max() for x in u_o)
+    ephi = np.abs(phi_g - phi_o).max()
+    eu = max(np.abs(u_g[a] - u_o[a]).max() for a in range(3)) / us
+    say(f"  |dphi| {ephi:.2e} |du|/|u| {eu:.2e}")
+    assert ephi < 1e-5 and eu < 1e-4
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+def test_single_case_walls_equal_doubled_periodic_box(gpu, precision):
+    """Beyond the oracle: a 64^3 box walled on all axes evolves like one octant
+    of the 128^3 periodic box holding its mirror images (both single-case
+    contexts on the GPU), 5 steps: the z-marching kernels, the coarse levels
+    and the tail with wall faces."""
+    C = workloads.Case
+    n = 64
+    c = C("box", (n, n, n), (0.4, 0.45, 0.55), (0.3, 0.25, 0.22), 10.0, 1.0, 0.02, 0.002, 1.0, 0.75, "CDI", "EB",
+          precision)
+    d = dataclasses.replace(c, n=(2 * n,) * 3, length=2.0)
+    say(f"single-case walled 64^3 vs doubled periodic 128^3, {precision}")
+    rtol = 1e-13 if precision == "fp64" else 1e-9
+    sw = gpu.solver_for_case(c, walls=7, poisson_rtol=rtol)
+    sw.init_droplet(c.center, c.semi_axes)
+    phi, _, _ = sw.get_state()
+    big = phi
+    for ax in range(3):
+        big = np.concatenate([big, np.flip(big, ax)], ax)
+    sp = gpu.solver_for_case(d, poisson_rtol=rtol)
+    sp.set_state(big, [np.zeros_like(big)] * 3)
+    dt = c.dt()
+    sw.step(dt, 5)
+    sp.step(dt, 5)
+    fw, uw, _ = sw.get_state()
+    fp, up, _ = sp.get_state()
+    us = max(np.abs(x).max() for x in up)
+    ephi = np.abs(fw - fp[:n, :n, :n]).max()
+    eu = max(np.abs(uw[a] - up[a][:n, :n, :n]).max() for a in range(3)) / us
+    say(f"  |dphi| {ephi:.2e} |du|/|u| {eu:.2e}")
+    bound = (1e-12, 1e-11) if precision == "fp64" else (2e-6, 3e-4)
+    assert ephi < bound[0] and eu < bound[1]
+
+
+def test_single_case_walls_match_batch(gpu):
+    """The same walled 2D case in a single-case context and in a batch
+    (different kernels and solvers), FP64, 4 steps."""
+    c, w = single_cases()[0]
+    say("single-case vs batch, walled")
+    s = gpu.solver_for_case(c, walls=w, poisson_rtol=1e-14)
+    s.init_droplet(c.center, c.semi_axes)
+    b = gpu.Batch([gpu.params_for_case(c, walls=w, poisson_rtol=1e-14)])
+    b.init_droplet(0, c.center, c.semi_axes)
+    dt = c.dt()
+    s.step(dt, 4)
+    b.step(np.array([dt]), 4)
+    fs, us_, _ = s.get_state()
+    fb, ub, _ = b.get_state(0)
+    um = max(np.abs(x).max() for x in us_)
+    ephi = np.abs(fs - fb).max()
+    eu = max(np.abs(us_[a] - ub[a]).max() for a in range(2)) / um
+    say(f"  |dphi| {ephi:.2e} |du|/|u| {eu:.2e}")
+    assert ephi < 1e-12 and eu < 1e-10
