@@ -179,22 +179,31 @@ __global__ __launch_bounds__(BLOCK) void k_cell_face_lds(
 
 // The same pass with the neighbourhoods staged in LDS (3D).  A block owns a
 // BX x BY column piece of kz planes.  It keeps a ring of three z planes
-// (k - 1, k, k + 1) of every field it reads neighbours of (phi, u, m, mu or
-// kappa, and r for CDI), each plane its BX x BY tile plus a one-cell halo, and
-// copies one new plane per step from HBM with coalesced loads; every stencil
-// point, diagonals included, is then read from LDS.  One global load per
-// field and cell (plus halo and the two extra planes of the ring) instead of
-// one per stencil point.
+// (k - 1, k, k + 1) of the fields it reads z neighbours and z diagonals of
+// (phi, u, m), each plane its BX x BY tile plus a one-cell halo, and a
+// single-plane tile of the fields it reads only in-plane (mu or kappa, and r_x,
+// r_y for CDI).  What else a cell reads is its own column: mu or kappa one
+// plane below, r_z (CDI) or kappa (the other models with the energy-based
+// force) at the cell, r_z one plane above, and the RK state and accumulator.
+// Every global load is issued one plane ahead, while the block computes the
+// plane before it: the ring and the single tile through coalesced loads of one
+// new plane per step, the column values into registers.  The compute phase
+// reads only LDS and registers.
 template <typename T>
 using Tile = T[BY + 2][BX + 2];
 
-template <typename T, unsigned RMASK, unsigned OMASK>
+// ZF: single-plane field whose value one plane below the cell comes from a
+// register (zm); CF: field read at the cell from a register (zc), and one
+// plane above it (zp) when CP; -1: none
+template <typename T, unsigned RMASK, unsigned OMASK, int ZF, int CF, bool CP>
 struct LAcc {
     const Cell& C;
     const T* p[F_NF];
     const Tile<T>* t[3];   // ring fields (RMASK), planes k - 1, k, k + 1: t[z][slot(f)]
     const Tile<T>* t1;     // single-plane fields (OMASK), plane k: t1[slot1(f)]
     int lx, ly;            // this cell in the tile (halo offset 1)
+    T zm, zc, zp;          // column values, see above
+    T yv[2];               // the cell's RK state y_n and accumulator
     static constexpr bool ring(int f) { return (RMASK >> f) & 1u; }
     static constexpr bool one(int f) { return (OMASK >> f) & 1u; }
     static constexpr int slot(int f) { return __builtin_popcount(RMASK & ((1u << f) - 1u)); }
@@ -202,11 +211,14 @@ struct LAcc {
     __device__ __forceinline__ T c(int f) const {
         if (ring(f)) return t[1][slot(f)][ly][lx];
         if (one(f)) return t1[slot1(f)][ly][lx];
+        if (f == CF) return zc;
         return ld(p[f], C.id);
     }
     __device__ __forceinline__ T nb(int f, int a, int s) const {
         if (ring(f)) return t[1 + (a == 2 ? s : 0)][slot(f)][ly + (a == 1 ? s : 0)][lx + (a == 0 ? s : 0)];
         if (one(f) && a != 2) return t1[slot1(f)][ly + (a == 1 ? s : 0)][lx + (a == 0 ? s : 0)];
+        if (f == ZF && a == 2 && s < 0) return zm;
+        if (CP && f == CF && a == 2 && s > 0) return zp;
         return ld(p[f], C.off(a, s));
     }
     __device__ __forceinline__ T nb2(int f, int a, int s, int b, int u) const {
@@ -217,6 +229,7 @@ struct LAcc {
             return t1[slot1(f)][ly + (a == 1 ? s : 0) + (b == 1 ? u : 0)][lx + (a == 0 ? s : 0) + (b == 0 ? u : 0)];
         return ld(p[f], C.off2(a, s, b, u));
     }
+    __device__ __forceinline__ T own(const T* __restrict__, int w) const { return yv[w]; }
 };
 
 template <typename T, bool CDI, bool EB>
@@ -228,13 +241,13 @@ __global__ __launch_bounds__(BLOCK) void k_phase_momentum_lds(
     const T* __restrict__ m0, const T* __restrict__ m1, const T* __restrict__ m2,
     const T* __restrict__ mu, T* __restrict__ f0, T* __restrict__ f1, T* __restrict__ f2,
     T* __restrict__ F0, T* __restrict__ F1, T* __restrict__ F2) {
-    // three-plane ring: the fields read at z neighbours and z diagonals;
-    // one plane: the fields read only in-plane (their c - e_z or c + e_z
-    // values come from memory)
     constexpr unsigned RMASK = (1u << F_PHI) | (7u << F_U0) | (7u << F_M0);
     constexpr unsigned OMASK = (EB ? (1u << F_MU) : (1u << F_KAP)) | (CDI ? ((1u << F_R0) | (1u << F_R1)) : 0u);
+    constexpr int ZF = EB ? F_MU : F_KAP;
+    constexpr int CF = CDI ? F_R2 : (EB ? F_KAP : -1);
+    constexpr bool CP = CDI;
     constexpr int NS = __builtin_popcount(RMASK), NS1 = __builtin_popcount(OMASK);
-    using A_t = LAcc<T, RMASK, OMASK>;
+    using A_t = LAcc<T, RMASK, OMASK, ZF, CF, CP>;
     __shared__ Tile<T> ring[3][NS];
     __shared__ Tile<T> tile1[NS1];
     int bx, by, bz;
@@ -262,7 +275,13 @@ __global__ __launch_bounds__(BLOCK) void k_phase_momentum_lds(
     }
     const bool second = tid + BLOCK < TP;
     const unsigned plane = (unsigned)(d.nx * d.ny);
+    // the thread's own column (cell 0 of the plane for threads outside the
+    // grid, whose values are never used)
+    const unsigned col = valid ? (unsigned)(j * d.nx + i) : 0u;
+    auto at = [&](int q) { return (unsigned)((q + d.nz) % d.nz) * plane + col; };
+    const bool rd_y = !rk.eval_only, rd_acc = !rk.eval_only && rk.stage != 0;
     T pre[2][NS], pre1[2][NS1 > 0 ? NS1 : 1];
+    T ny[2] = {T(0), T(0)}, nc = T(0);
     // ring fields of plane q and single-plane fields of plane q1 (periodic in
     // z) into registers; stored to ring slot r and the single tile
     auto load = [&](int q, int q1) {
@@ -275,6 +294,13 @@ __global__ __launch_bounds__(BLOCK) void k_phase_momentum_lds(
                 if ((RMASK >> f) & 1u) pre[h][A_t::slot(f)] = ld(p[f], base + pos[h]);
                 if ((OMASK >> f) & 1u) pre1[h][A_t::slot1(f)] = ld(p[f], base1 + pos[h]);
             }
+    };
+    // column values of plane q1: y_n, the accumulator, and CF at q1 (at
+    // q1 + 1 when CP: its value at q1 was loaded one plane earlier)
+    auto load_col = [&](int q1) {
+        if (rd_y) ny[0] = ld(yn, at(q1));
+        if (rd_acc) ny[1] = ld(acc, at(q1));
+        if (CF >= 0) nc = ld(p[CF >= 0 ? CF : 0], at(CP ? q1 + 1 : q1));
     };
     auto store = [&](int r, bool with1) {
 #pragma unroll
@@ -289,26 +315,41 @@ __global__ __launch_bounds__(BLOCK) void k_phase_momentum_lds(
             }
         }
     };
+    T zm = ld(p[ZF], at(k0 - 1)), zc = T(0), zp = T(0);
+    if (CP) zp = ld(p[CF >= 0 ? CF : 0], at(k0));
     load(k0 - 1, k0);
     store(0, false);
     load(k0, k0);
     store(1, true);
     load(k0 + 1, k0 + 1);
+    load_col(k0);
     for (int k = k0; k < k1; ++k) {
         const int rm = (k - k0) % 3, rc = (k - k0 + 1) % 3, rp = (k - k0 + 2) % 3;
+        // the column values of plane k, loaded one step earlier
+        const T yv0 = ny[0], yv1 = ny[1];
+        if (CP) {
+            zc = zp;
+            zp = nc;
+        } else {
+            zc = nc;
+        }
         // ring plane k + 1 into the slot plane k - 2 used, and (after the
         // first plane, whose single tile the prologue stored) the
         // single-plane fields of plane k, both loaded one step earlier
         store(rp, k > k0);
         __syncthreads();
-        if (k + 1 < k1) load(k + 2, k + 1);   // in flight while plane k is computed
+        if (k + 1 < k1) {                       // in flight while plane k is computed
+            load(k + 2, k + 1);
+            load_col(k + 1);
+        }
         if (valid) {
             const Cell C = make_cell(d, i, j, k);
             const A_t A{C, {phi, u0, u1, u2, m0, m1, m2, mu, kappa, r0, r1, r2}, {ring[rm], ring[rc], ring[rp]},
-                        tile1, (int)threadIdx.x + 1, (int)threadIdx.y + 1};
+                        tile1, (int)threadIdx.x + 1, (int)threadIdx.y + 1, zm, zc, zp, {yv0, yv1}};
             op_phase_g<T, 3>(P, rk, C, A, yn, acc, ynext, flags);
             op_momentum_g<T, 3>(P, C, A, f0, f1, f2, F0, F1, F2);
         }
+        zm = tile1[A_t::slot1(ZF)][threadIdx.y + 1][threadIdx.x + 1];   // ZF of plane k, for plane k + 1
         __syncthreads();           // plane k - 1's ring slot and the single tile are free
     }
 }

@@ -165,6 +165,9 @@ struct GAcc {
         const T v = ld(p[f], C.off2(a, s, b, t));
         return shut(f, (a == n ? s : 0) + (b == n ? t : 0)) ? T(0) : v;
     }
+    // the cell's own value of a field outside the table (the RK state y_n
+    // and accumulator of the phase update)
+    __device__ __forceinline__ T own(const T* __restrict__ q, int) const { return ld(q, C.id); }
 };
 
 // ------------------------------------------------------------------ phase field
@@ -202,8 +205,8 @@ __device__ __forceinline__ void op_phase_g(const Phys& P, const RKArgs& rk, cons
         stn(ynext, c, k);
         return;
     }
-    const T y0 = ld(yn, c);
-    const T a_new = (rk.stage == 0 ? y0 : ld(acc, c)) + T(rk.wacc) * k;
+    const T y0 = G.own(yn, 0);
+    const T a_new = (rk.stage == 0 ? y0 : G.own(acc, 1)) + T(rk.wacc) * k;
     stn(acc, c, a_new);
     if (rk.stage < 3) stn(ynext, c, y0 + T(rk.wnext) * k);
     else if (!isfinite(a_new)) flags[0] = 1;
