@@ -81,6 +81,14 @@ __device__ __forceinline__ void stn(T* base, unsigned idx, T v) {
 __device__ __forceinline__ float med3(float a, float lo, float hi) { return __builtin_amdgcn_fmed3f(a, lo, hi); }
 __device__ __forceinline__ double med3(double a, double lo, double hi) { return fmin(fmax(a, lo), hi); }
 
+// a / b and 1 / sqrt(s): in FP32 the hardware reciprocal and reciprocal
+// square root (1 ulp) instead of the correctly rounded sequences, which take
+// about ten instructions each; FP64 keeps the correctly rounded forms
+__device__ __forceinline__ float quot(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double quot(double a, double b) { return a / b; }
+__device__ __forceinline__ float rsqrt_of(float s) { return __builtin_amdgcn_rsqf(s); }
+__device__ __forceinline__ double rsqrt_of(double s) { return 1.0 / sqrt(s); }
+
 __device__ __forceinline__ int block_linear() {
     return (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
 }

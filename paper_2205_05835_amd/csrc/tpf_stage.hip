@@ -120,7 +120,7 @@ __global__ __launch_bounds__(BLOCK) void k_cell_face_lds(
             T gg = T(0);
 #pragma unroll
             for (int a = 0; a < 3; ++a) gg += g[a] * g[a];
-            const T inv = T(1) / sqrt(gg + T(P.delta2));
+            const T inv = rsqrt_of(gg + T(P.delta2));
 #pragma unroll
             for (int a = 0; a < 3; ++a) nr[sl][a][ny_][nx_] = g[a] * inv;
         }
@@ -346,8 +346,8 @@ __global__ __launch_bounds__(BLOCK) void k_phase_momentum_lds(
             const Cell C = make_cell(d, i, j, k);
             const A_t A{C, {phi, u0, u1, u2, m0, m1, m2, mu, kappa, r0, r1, r2}, {ring[rm], ring[rc], ring[rp]},
                         tile1, (int)threadIdx.x + 1, (int)threadIdx.y + 1, zm, zc, zp, {yv0, yv1}};
-            op_phase_g<T, 3>(P, rk, C, A, yn, acc, ynext, flags);
-            op_momentum_g<T, 3>(P, C, A, f0, f1, f2, F0, F1, F2);
+            op_phase_g<T, 3, A_t, CDI ? MODEL_CDI : -1>(P, rk, C, A, yn, acc, ynext, flags);
+            op_momentum_g<T, 3, A_t, EB ? FORCE_EB : -1>(P, C, A, f0, f1, f2, F0, F1, F2);
         }
         zm = tile1[A_t::slot1(ZF)][threadIdx.y + 1][threadIdx.x + 1];   // ZF of plane k, for plane k + 1
         __syncthreads();           // plane k - 1's ring slot and the single tile are free

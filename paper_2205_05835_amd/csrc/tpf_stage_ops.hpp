@@ -36,7 +36,7 @@ __device__ __forceinline__ T grad_inv(const Phys& P, const Cell& Q, const T* __r
         g[a] = (ld(phi, Q.off(a, 1)) - ld(phi, Q.off(a, -1))) * ih2;
         gg += g[a] * g[a];
     }
-    return T(1) / sqrt(gg + T(P.delta2));
+    return rsqrt_of(gg + T(P.delta2));
 }
 
 // L phi at cell C (5- or 7-point)
@@ -172,10 +172,13 @@ struct GAcc {
 
 // ------------------------------------------------------------------ phase field
 // dphi/dt = -D(u A phi) + g   (Eq. 1), g of Table 1; then the RK4 update.
-template <typename T, int DIM, typename Acc>
+// KM, KF: the model and force when the caller knows them at compile time
+// (-1: read from P)
+template <typename T, int DIM, typename Acc, int KM = -1>
 __device__ __forceinline__ void op_phase_g(const Phys& P, const RKArgs& rk, const Cell& C, const Acc& G,
                                            const T* __restrict__ yn, T* __restrict__ acc,
                                            T* __restrict__ ynext, int* __restrict__ flags) {
+    const int model = KM >= 0 ? KM : P.model;
     const unsigned c = C.id;
     const T f = G.c(F_PHI);
     const T ih = T(P.inv_h);
@@ -186,7 +189,7 @@ __device__ __forceinline__ void op_phase_g(const Phys& P, const RKArgs& rk, cons
         const T jhi = G.nb(F_U0 + a, a, 1) * (T(0.5) * (f + fp));
         const T jlo = G.c(F_U0 + a) * (T(0.5) * (fm + f));
         adv += (jhi - jlo) * ih;
-        if (P.model == MODEL_CDI) {
+        if (model == MODEL_CDI) {
             g += (G.nb(F_R0 + a, a, 1) - G.c(F_R0 + a)) * ih;
         } else {
             lap += ((fp - f) * ih - (f - fm) * ih) * ih;
@@ -194,9 +197,9 @@ __device__ __forceinline__ void op_phase_g(const Phys& P, const RKArgs& rk, cons
             gg += ga * ga;
         }
     }
-    if (P.model != MODEL_CDI) {
+    if (model != MODEL_CDI) {
         const T base = T(P.eps) * lap - dpsi(f) / T(P.eps);
-        const T curv = (P.model == MODEL_SB) ? T(P.eps) * sqrt(gg) * G.c(F_KAP)
+        const T curv = (model == MODEL_SB) ? T(P.eps) * sqrt(gg) * G.c(F_KAP)
                                              : f * (T(1) - f) * G.c(F_KAP);
         g = T(P.gamma) * (base + curv);
     }
@@ -234,10 +237,11 @@ __device__ __forceinline__ void op_phase(const Phys& P, const RKArgs& rk, const 
 //   F_a: surface tension -- EB: A_a(mu) G_a phi (Eq. 4, + sign on the RHS);
 //        CSF: sigma A_a(kappa) G_a phi;  LCSF: sigma_hat A_a(kappa)
 //        A_a(phi(1-phi)) G_a phi (Eq. 11)
-template <typename T, int DIM, typename Acc>
+template <typename T, int DIM, typename Acc, int KF = -1>
 __device__ __forceinline__ void op_momentum_g(const Phys& P, const Cell& C, const Acc& G, T* __restrict__ f0,
                                               T* __restrict__ f1, T* __restrict__ f2, T* __restrict__ F0,
                                               T* __restrict__ F1, T* __restrict__ F2) {
+    const int force = KF >= 0 ? KF : P.force;
     T* fs[3] = {f0, f1, f2};
     T* Fo[3] = {F0, F1, F2};
     const unsigned c = C.id;
@@ -280,9 +284,9 @@ __device__ __forceinline__ void op_momentum_g(const Phys& P, const Cell& C, cons
         // ---- surface tension (x 1/h)
         const T gh = f - fm;
         T fh;
-        if (P.force == FORCE_EB) {
+        if (force == FORCE_EB) {
             fh = T(0.5) * (G.nb(F_MU, a, -1) + G.c(F_MU)) * gh;
-        } else if (P.force == FORCE_CSF) {
+        } else if (force == FORCE_CSF) {
             fh = T(0.5 * P.sigma) * (G.nb(F_KAP, a, -1) + G.c(F_KAP)) * gh;
         } else {
             fh = T(0.25 * P.sigma_hat) * (G.nb(F_KAP, a, -1) + G.c(F_KAP)) *
@@ -291,7 +295,7 @@ __device__ __forceinline__ void op_momentum_g(const Phys& P, const Cell& C, cons
         const bool shut = C.wall(a, -1);   // face on a wall: f* = 0
         if (Fo[0]) stn(Fo[a], c, shut ? T(0) : fh * ih);
         const T rho_f = T(P.rho2) + T(0.5 * (P.rho1 - P.rho2)) * (clm + clc);
-        stn(fs[a], c, shut ? T(0) : ((fh - nh) * ih + vh2 * (ih * ih)) / rho_f);
+        stn(fs[a], c, shut ? T(0) : quot((fh - nh) * ih + vh2 * (ih * ih), rho_f));
     }
 }
 
