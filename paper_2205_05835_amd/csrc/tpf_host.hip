@@ -297,6 +297,8 @@ static void init_geometry(tpf_ctx* c, const tpf_params* P) {
     // the wall rules; the LDS tiles are filled periodically)
     c->walls = P->walls;
     if (c->walls) c->stage_lds = 0;
+    const char* pg = std::getenv("TPF_PCG_GRAPH");
+    c->pcg_graph = (pg && pg[0] == '1') ? 1 : 0;
     const char* slk = std::getenv("TPF_STAGE_LDS_KZ");
     c->stage_lds_kz = slk ? std::atoi(slk) : 32;
     c->stage_lds_kz = std::min(std::max(c->stage_lds_kz, 1), 256);
@@ -398,6 +400,8 @@ tpf_status tpf_destroy(tpf_ctx* c) {
     (void)hipStreamSynchronize(c->stream);
     prof_free(c);
     if (c->pub) (void)hipHostFree(c->pub);
+    for (int g = 0; g < c->n_pcg_graphs; ++g) (void)hipGraphExecDestroy(c->pcg_graphs[g].exec);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     delete c;
     return TPF_OK;
 }

@@ -147,6 +147,18 @@ struct tpf_ctx {
     long long stat_solves, stat_outer, stat_inner;   // pressure solves since the last reset
     int stat_recent[4];                              // PCG iterations of the last four solves
 
+    // pairs of PCG iterations replayed from HIP graphs (TPF_PCG_GRAPH=1, a
+    // measurement knob; off while profiling): captured on cap_stream, keyed
+    // by the correction array and the direction buffer the pair starts from
+    int pcg_graph;
+    hipStream_t cap_stream;
+    struct PcgGraph {
+        const void* key[2];
+        hipGraphExec_t exec;
+    };
+    PcgGraph pcg_graphs[4];
+    int n_pcg_graphs;
+
     // profiling: HIP event pairs around the launches of the selected classes
     unsigned prof_mask;
     int ev_cap;

@@ -1979,6 +1979,61 @@ struct Solver {
     // every 2 iterations.
     // Iterations launched after convergence exit at once; the profiler books
     // them as no-work launches.
+    // one PCG iteration after the first: new direction and its operator
+    // application, the x and r update with the first sweep, the rest of the
+    // V-cycle, and the flexible-CG scalars
+    template <typename X>
+    void iteration(const void* phi, int first, X* x) {
+        if (dim == 2) apply_update<2, X>(phi, first, x);
+        else apply_update<3, X>(phi, first, x);
+        vcycle(phi, true);
+        (void)finalize3(c, (int)nb0(), (int)nb0(), (int)nb0(), FIN_BETA, 0.0);
+    }
+
+    // Two iterations (not the first of a solve) captured as one HIP graph on
+    // a private stream and kept per (x, direction buffer): the pair swaps the
+    // direction buffers twice, so it leaves them as it found them and its
+    // launches are the same every time.  *out = nullptr: no graph (the cache
+    // is full), the caller launches directly.
+    template <typename X>
+    hipError_t pair_graph(const void* phi, X* x, hipGraphExec_t* out) {
+        *out = nullptr;
+        const void* key[2] = {static_cast<const void*>(x), c->pv};
+        for (int g = 0; g < c->n_pcg_graphs; ++g)
+            if (c->pcg_graphs[g].key[0] == key[0] && c->pcg_graphs[g].key[1] == key[1]) {
+                *out = c->pcg_graphs[g].exec;
+                return hipSuccess;
+            }
+        if (c->n_pcg_graphs == (int)(sizeof(c->pcg_graphs) / sizeof(c->pcg_graphs[0]))) return hipSuccess;
+        if (!c->cap_stream) {
+            hipError_t ec = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
+            if (ec != hipSuccess) {
+                c->cap_stream = nullptr;
+                return ec;
+            }
+        }
+        hipStream_t user = c->stream;
+        c->stream = c->cap_stream;
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            iteration(phi, 0, x);
+            iteration(phi, 0, x);
+            e = hipStreamEndCapture(c->stream, &g);
+        }
+        c->stream = user;
+        hipGraphExec_t ex = nullptr;
+        if (e == hipSuccess) e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return e;
+        c->pcg_graphs[c->n_pcg_graphs].key[0] = key[0];
+        c->pcg_graphs[c->n_pcg_graphs].key[1] = key[1];
+        c->pcg_graphs[c->n_pcg_graphs].exec = ex;
+        ++c->n_pcg_graphs;
+        *out = ex;
+        return hipSuccess;
+    }
+
     template <typename X>
     hipError_t pcg(const void* phi, X* x, int maxit, int slot, SolverScalars* last, bool* have_last) {
         vcycle(phi, false);                                       // z = M r, <r,z>
@@ -1990,13 +2045,26 @@ struct Solver {
         snap_.resize((size_t)maxit + 1);
         SolverScalars s{};
         while (it < maxit) {
-            for (int k = 0; k < window && it < maxit; ++k, ++it) {
+            for (int k = 0; k < window && it < maxit;) {
+                if (!first && c->pcg_graph && !c->prof_mask && k + 1 < window && it + 1 < maxit) {
+                    hipGraphExec_t ex = nullptr;
+                    hipError_t e = pair_graph(phi, x, &ex);
+                    if (e != hipSuccess) return e;
+                    if (ex) {
+                        snapshot(snap_[it]);
+                        snapshot(snap_[it + 1]);
+                        e = hipGraphLaunch(ex, c->stream);
+                        if (e != hipSuccess) return e;
+                        k += 2;
+                        it += 2;
+                        continue;
+                    }
+                }
                 snapshot(snap_[it]);
-                if (dim == 2) apply_update<2, X>(phi, first ? 1 : 0, x);
-                else apply_update<3, X>(phi, first ? 1 : 0, x);
+                iteration(phi, first ? 1 : 0, x);
                 first = false;
-                vcycle(phi, true);
-                (void)finalize3(c, (int)nb0(), (int)nb0(), (int)nb0(), FIN_BETA, 0.0);
+                ++k;
+                ++it;
             }
             window = 2;
             hipError_t e = hipGetLastError();

@@ -162,3 +162,25 @@ def test_fixed_iteration_mode(gpu, precision, fixed, outer, inner):
     assert np.abs(a - b).max() < 1e-6
     umax = max(np.abs(x).max() for x in ub)
     assert max(np.abs(x - y).max() for x, y in zip(ua, ub)) < 0.05 * umax
+
+
+@pytest.mark.parametrize("precision,n", [("fp32_mixed", 64), ("fp64", 32)])
+def test_pcg_graph_replay_is_bitwise(gpu, precision, n):
+    """TPF_PCG_GRAPH=1 (pairs of PCG iterations replayed from captured HIP
+    graphs) steps bit for bit like the direct launches."""
+    import os
+    case = workloads.oscillating_drop_3d(n, precision)
+    dt = case.dt()
+    say(f"PCG graph replay {precision} {n}^3")
+    out = []
+    for g in ("0", "1"):
+        os.environ["TPF_PCG_GRAPH"] = g
+        try:
+            s = gpu.solver_for_case(case)
+        finally:
+            del os.environ["TPF_PCG_GRAPH"]
+        s.init_droplet(case.center, case.semi_axes)
+        s.step(dt, 3)
+        phi, u, p = s.get_state(with_pressure=True)
+        out.append([phi] + u + [p])
+    assert all(np.array_equal(a, b) for a, b in zip(out[0], out[1]))
