@@ -623,20 +623,56 @@ __global__ __launch_bounds__(1024) void k_tail(TailDesc D, S w1, S w2, S omega_c
         const int l = D.nlev - 1;
         const int N = ncell(l);
         S* r = L + D.off[l];
-        S* src = r + 2 * N;   // zt
-        S* dst = r + N;       // z
-        for (int q = t; q < N; q += T) src[q] = S(0);
-        __syncthreads();
-        for (int s = 0; s < sweeps; ++s) {
-            const S* in = src;
-            sweep(l, omega_c, [&](const Cell& C, int a, int s2) { return in[s2 == 0 ? C.id : C.nb(a, s2)]; }, dst);
-            S* tmp = src;
-            src = dst;
-            dst = tmp;
-        }
-        if (src != r + 2 * N) {
-            for (int q = t; q < N; q += T) r[2 * N + q] = src[q];
+        if (N <= 64) {
+            // one cell per lane of the first wave: the sweeps read the
+            // neighbours' values by lane shuffles and need no block barrier
+            // (the same arithmetic as the block-wide sweeps below)
+            if (t < 64) {
+                const int q = t < N ? t : 0;
+                const Cell C = cell(l, q);
+                const CoefStored<S> cf = coef(l);
+                const S ih2 = S(D.ih2[l]);
+                S bl[3], bh[3];
+                cf.template faces<DIM>(C, bl, bh);
+                int lm[3] = {0, 0, 0}, lp[3] = {0, 0, 0};
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) {
+                    lm[a] = (int)C.nb(a, -1);
+                    lp[a] = (int)C.nb(a, 1);
+                }
+                const S rq = r[q];
+                S x = S(0);
+                for (int s = 0; s < sweeps; ++s) {
+                    S xm[3], xp[3];
+#pragma unroll
+                    for (int a = 0; a < DIM; ++a) {
+                        xm[a] = __shfl(x, lm[a], 64);
+                        xp[a] = __shfl(x, lp[a], 64);
+                    }
+                    auto X = [&](int a, int s2) { return s2 < 0 ? xm[a] : xp[a]; };
+                    S dg;
+                    const S az = apply_at<S, DIM>(bl, bh, X, x, ih2, dg);
+                    x = x + omega_c * (rq - az) / dg;
+                }
+                if (t < N) r[2 * N + t] = x;
+            }
             __syncthreads();
+        } else {
+            S* src = r + 2 * N;   // zt
+            S* dst = r + N;       // z
+            for (int q = t; q < N; q += T) src[q] = S(0);
+            __syncthreads();
+            for (int s = 0; s < sweeps; ++s) {
+                const S* in = src;
+                sweep(l, omega_c, [&](const Cell& C, int a, int s2) { return in[s2 == 0 ? C.id : C.nb(a, s2)]; }, dst);
+                S* tmp = src;
+                src = dst;
+                dst = tmp;
+            }
+            if (src != r + 2 * N) {
+                for (int q = t; q < N; q += T) r[2 * N + q] = src[q];
+                __syncthreads();
+            }
         }
     }
     // ---- up
