@@ -490,8 +490,8 @@ tpf_status tpf_init_droplet(tpf_ctx* c, const double center[3], const double sem
 // One stage evaluation at (phi_s, u_s): fields, phase RHS (+RK update),
 // momentum RHS, pressure solve, projection (+RK update).
 static tpf_status stage_eval(tpf_ctx* c, const void* phi_s, const void* const u_s[3], const RKArgs& rk,
-                             void* phi_out, void* const u_out[3], int want_force) {
-    hipError_t e = launch_stage_fields(c, phi_s, u_s);
+                             void* phi_out, void* const u_out[3], int want_force, bool normals) {
+    hipError_t e = launch_stage_fields(c, phi_s, u_s, normals);
     if (e == hipSuccess) e = launch_phase_momentum(c, phi_s, u_s, rk, phi_out, want_force);
     if (e == hipSuccess) e = launch_divergence(c);
     if (e != hipSuccess) return hip_fail(e, "stage kernels");
@@ -563,7 +563,7 @@ tpf_status advance(tpf_ctx* c, double dt, int nsteps, char* tape, size_t stage_b
             RKArgs rk{s, 0, wacc[s], wnext[s]};
             const void* us[3] = {u_s[0], u_s[1], u_s[2]};
             c->rk_stage = s;
-            tpf_status st = stage_eval(c, phi_s, us, rk, phi_o, u_o, 0);
+            tpf_status st = stage_eval(c, phi_s, us, rk, phi_o, u_o, 0, false);
             c->rk_stage = 0;
             if (st == TPF_OK && s == 0) st = copy_async(c, c->p_hist1, c->p, (size_t)Nn * 8);
             if (st == TPF_OK && s == 1) st = copy_async(c, c->p_hist2, c->p, (size_t)Nn * 8);
@@ -619,7 +619,7 @@ tpf_status tpf::eval_current(tpf_ctx* c, int want_force) {
     state_ptrs(c, c->s_y1, &phi_o, u_o);
     RKArgs rk{0, 1, 0.0, 0.0};
     const void* us[3] = {u_s[0], u_s[1], u_s[2]};
-    tpf_status st = stage_eval(c, phi_s, us, rk, phi_o, u_o, want_force);
+    tpf_status st = stage_eval(c, phi_s, us, rk, phi_o, u_o, want_force, true);
     if (st == TPF_OK) st = gauge_pressure(c);
     if (st == TPF_OK) c->p_valid = 1;
     return st;

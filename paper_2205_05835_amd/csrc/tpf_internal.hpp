@@ -221,7 +221,9 @@ void prof_begin(tpf_ctx* c, int cls, double bytes);
 void prof_end(tpf_ctx* c);
 
 // stage kernels (tpf_stage.hip)
-hipError_t launch_stage_fields(tpf_ctx* c, const void* phi_s, const void* const u_s[3]);
+// normals: also store n (the step skips it where nothing reads it: the LDS
+// pass with CDI and the energy-based force, which needs no kappa)
+hipError_t launch_stage_fields(tpf_ctx* c, const void* phi_s, const void* const u_s[3], bool normals = true);
 hipError_t launch_momentum(tpf_ctx* c, const void* phi_s, const void* const u_s[3], int want_force);
 // phase update and momentum right-hand side fused (one pass over phi and u)
 hipError_t launch_phase_momentum(tpf_ctx* c, const void* phi_s, const void* const u_s[3], const RKArgs& rk,

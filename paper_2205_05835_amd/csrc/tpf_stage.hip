@@ -145,8 +145,10 @@ __global__ __launch_bounds__(BLOCK) void k_cell_face_lds(
             const int qx = tx + 1, qy = ty + 1;         // n tile
             const unsigned c = (unsigned)k * plane + (unsigned)(j * d.nx + i);
             const T f = fc[cy][cx];
+            if (nout[0]) {
 #pragma unroll
-            for (int a = 0; a < 3; ++a) st(nout[a], c, nr[sc][a][qy][qx]);
+                for (int a = 0; a < 3; ++a) st(nout[a], c, nr[sc][a][qy][qx]);
+            }
             if (MU) {
                 const T fxp = fc[cy][cx + 1], fxm = fc[cy][cx - 1], fyp = fc[cy + 1][cx], fym = fc[cy - 1][cx];
                 const T fzp = fp[cy][cx], fzm = fm[cy][cx];
@@ -499,18 +501,20 @@ static hipError_t face_impl_w(tpf_ctx* c, A... a) {
 
 // the LDS form of k_cell + k_face, then k_kappa where kappa is needed (3D)
 template <typename T>
-static hipError_t cell_face_lds_impl(tpf_ctx* c, const void* phi_s, const void* const u_s[3]) {
+static hipError_t cell_face_lds_impl(tpf_ctx* c, const void* phi_s, const void* const u_s[3], bool normals) {
     const Phys P = phys_of(c);
     const Dims d = dims_of(c->n, c->walls);
     const int lkz = c->stage_lds_kz;
     const dim3 lg = zchunk_grid(c->n, lkz), b(BX, BY);
     const bool cdi = c->P.model == MODEL_CDI, need_mu = c->P.force == FORCE_EB;
     const bool need_kappa = !cdi || !need_mu;
-    prof_begin(c, PC_FACE, (double)c->N * c->tsz * (1 + 3 + 3 + (need_mu ? 1 : 0) + 3 * (cdi ? 2 : 1)));
+    // n is read only by the kappa pass (and by the callers that ask for it)
+    const bool store_n = normals || need_kappa;
+    prof_begin(c, PC_FACE, (double)c->N * c->tsz * (1 + 3 + (store_n ? 3 : 0) + (need_mu ? 1 : 0) + 3 * (cdi ? 2 : 1)));
     auto kern = cdi ? (need_mu ? k_cell_face_lds<T, true, true> : k_cell_face_lds<T, true, false>)
                     : (need_mu ? k_cell_face_lds<T, false, true> : k_cell_face_lds<T, false, false>);
     kern<<<lg, b, 0, c->stream>>>(d, lkz, P, ctp<T>(phi_s), ctp<T>(u_s[0]), ctp<T>(u_s[1]), ctp<T>(u_s[2]),
-                                  tp<T>(c->nrm[0]), tp<T>(c->nrm[1]), tp<T>(c->nrm[2]), tp<T>(c->mu),
+                                  store_n ? tp<T>(c->nrm[0]) : nullptr, tp<T>(c->nrm[1]), tp<T>(c->nrm[2]), tp<T>(c->mu),
                                   tp<T>(c->rflux[0]), tp<T>(c->rflux[1]), tp<T>(c->rflux[2]), tp<T>(c->mflux[0]),
                                   tp<T>(c->mflux[1]), tp<T>(c->mflux[2]));
     prof_end(c);
@@ -525,10 +529,11 @@ static hipError_t cell_face_lds_impl(tpf_ctx* c, const void* phi_s, const void* 
     return hipGetLastError();
 }
 
-hipError_t launch_stage_fields(tpf_ctx* c, const void* phi_s, const void* const u_s[3]) {
+hipError_t launch_stage_fields(tpf_ctx* c, const void* phi_s, const void* const u_s[3], bool normals) {
     hipError_t e;
     if (c->dim == 3 && c->stage_lds)
-        return c->mixed ? cell_face_lds_impl<float>(c, phi_s, u_s) : cell_face_lds_impl<double>(c, phi_s, u_s);
+        return c->mixed ? cell_face_lds_impl<float>(c, phi_s, u_s, normals)
+                        : cell_face_lds_impl<double>(c, phi_s, u_s, normals);
     if (c->mixed) {
         e = c->dim == 2 ? stage_fields_impl_w<float, 2>(c, phi_s) : stage_fields_impl_w<float, 3>(c, phi_s);
         if (e != hipSuccess) return e;
