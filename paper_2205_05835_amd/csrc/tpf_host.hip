@@ -555,7 +555,6 @@ tpf_status advance(tpf_ctx* c, double dt, int nsteps, char* tape, size_t stage_b
             // the stage-2 pressure the stage-3 minus stage-2 difference of the
             // previous step; stage 4 (t + dt) extrapolates from t and t + dt/2
             hipError_t ew = hipSuccess;
-            const long Nn = c->N;
             if (s == 1 && c->hist2_valid) ew = launch_lincomb(c, c->p, 2.0, c->p, -1.0, c->p_hist2);
             if (s == 2 && c->hist2_valid) ew = launch_lincomb(c, c->p, 1.0, c->p, 1.0, c->p_hist3);
             if (s == 3) ew = launch_lincomb(c, c->p, 2.0, c->p, -1.0, c->p_hist1);
@@ -563,14 +562,15 @@ tpf_status advance(tpf_ctx* c, double dt, int nsteps, char* tape, size_t stage_b
             RKArgs rk{s, 0, wacc[s], wnext[s]};
             const void* us[3] = {u_s[0], u_s[1], u_s[2]};
             c->rk_stage = s;
+            // the projection of stages 1-3 keeps the history: p_hist1 = p(t),
+            // p_hist2 = p(t + dt/2) of stage 2, p_hist3 = stage 3 minus stage 2
+            double* const hist[4] = {c->p_hist1, c->p_hist2, c->p_hist3, nullptr};
+            c->proj_hist = hist[s];
+            c->proj_hsub = s == 2 ? c->p_hist2 : nullptr;
             tpf_status st = stage_eval(c, phi_s, us, rk, phi_o, u_o, 0, false);
             c->rk_stage = 0;
-            if (st == TPF_OK && s == 0) st = copy_async(c, c->p_hist1, c->p, (size_t)Nn * 8);
-            if (st == TPF_OK && s == 1) st = copy_async(c, c->p_hist2, c->p, (size_t)Nn * 8);
-            if (st == TPF_OK && s == 2) {
-                ew = launch_lincomb(c, c->p_hist3, 1.0, c->p, -1.0, c->p_hist2);
-                if (ew != hipSuccess) st = hip_fail(ew, "pressure history");
-            }
+            c->proj_hist = nullptr;
+            c->proj_hsub = nullptr;
             if (st == TPF_OK && rec) st = copy_async(c, rec + (1 + c->dim) * fT, c->p, (size_t)c->N * 8);
             if (st != TPF_OK) {
                 c->p_valid = 0;

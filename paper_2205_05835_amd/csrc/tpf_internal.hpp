@@ -142,6 +142,10 @@ struct tpf_ctx {
     double* p_hist2;
     double* p_hist3;
     int hist2_valid;
+    // set by the step for one stage: the projection also writes the stage's
+    // pressure into proj_hist (minus proj_hsub when that is set)
+    double* proj_hist;
+    const double* proj_hsub;
     double last_relres;
     int last_outer, last_inner;
     long long stat_solves, stat_outer, stat_inner;   // pressure solves since the last reset
