@@ -152,8 +152,16 @@ struct CoefRho {
 // h = rho(phi) / 2 for the fine level, once per solve
 template <typename T, typename S, bool W>
 __global__ __launch_bounds__(BLOCK) void k_half_rho(long N, CoefPhi<T, S, W> cf, S* __restrict__ h) {
-    for (long c = (long)blockIdx.x * BLOCK + threadIdx.x; c < N; c += (long)gridDim.x * BLOCK)
-        h[c] = cf.hr((unsigned)c);
+    // four consecutive cells per thread and pass, their loads issued together
+    const long n4 = N / 4, t0 = (long)blockIdx.x * BLOCK + threadIdx.x, stride = (long)gridDim.x * BLOCK;
+    for (long q = t0; q < n4; q += stride) {
+        S v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = cf.hr((unsigned)(4 * q + u));
+#pragma unroll
+        for (int u = 0; u < 4; ++u) h[4 * q + u] = v[u];
+    }
+    for (long c = 4 * n4 + t0; c < N; c += stride) h[c] = cf.hr((unsigned)c);
 }
 
 template <typename S>
