@@ -358,13 +358,12 @@ __global__ __launch_bounds__(BLOCK) void k_phase_momentum_lds(
 
 // b = D f* in FP64, plus the block sums of b (for the mean)
 template <typename T, int DIM, bool W = false>
-__global__ __launch_bounds__(BLOCK) void k_div(Dims d, Phys P, const T* __restrict__ f0,
+__global__ __launch_bounds__(BLOCK) void k_div(Dims d, int kz, Phys P, const T* __restrict__ f0,
                                                const T* __restrict__ f1,
                                                const T* __restrict__ f2, double* __restrict__ b,
                                                double* __restrict__ partials) {
-    Cell C;
     double v[1] = {0.0};
-    if (cell_of_thread<W>(d, C)) v[0] = op_div<T, DIM>(P, C, f0, f1, f2, b);
+    for_cells_zchunk<W>(d, kz, [&](const Cell& C) { v[0] += op_div<T, DIM>(P, C, f0, f1, f2, b); });
     block_partials<1>(v, partials);
 }
 
@@ -631,9 +630,10 @@ hipError_t launch_phase_momentum(tpf_ctx* c, const void* phi_s, const void* cons
 template <typename T, int DIM, bool W>
 static hipError_t div_impl(tpf_ctx* c) {
     const Phys P = phys_of(c);
-    const dim3 g = grid_of(c->n), b(BX, BY);
+    const int kz = c->stage_kz;
+    const dim3 g = zchunk_grid(c->n, kz), b(BX, BY);
     prof_begin(c, PC_DIV, (double)c->N * (c->tsz * DIM + 8));
-    k_div<T, DIM, W><<<g, b, 0, c->stream>>>(dims_of(c->n, c->walls), P, ctp<T>(c->fs[0]), ctp<T>(c->fs[1]),
+    k_div<T, DIM, W><<<g, b, 0, c->stream>>>(dims_of(c->n, c->walls), kz, P, ctp<T>(c->fs[0]), ctp<T>(c->fs[1]),
                                           ctp<T>(c->fs[2]), c->b, c->partials);
     prof_end(c);
     return hipGetLastError();
@@ -650,7 +650,7 @@ hipError_t launch_divergence(tpf_ctx* c) {
     if (c->mixed) e = c->dim == 2 ? div_impl_w<float, 2>(c) : div_impl_w<float, 3>(c);
     else e = c->dim == 2 ? div_impl_w<double, 2>(c) : div_impl_w<double, 3>(c);
     if (e != hipSuccess) return e;
-    return launch_finalize(c, (int)nblocks_of(c->n), 1, FIN_MEAN);
+    return launch_finalize(c, (int)zchunk_grid(c->n, c->stage_kz).x, 1, FIN_MEAN);
 }
 
 template <typename T, int DIM, bool W>
