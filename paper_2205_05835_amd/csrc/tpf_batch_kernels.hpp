@@ -338,7 +338,8 @@ struct BatchBlock {
     // z = M r on level 0 (r in lev(0).r); the result ends in lev(0).zt.
     // Returns <r, zt> of level 0 (summed by the last sweep, per thread in cell
     // order, then over the workgroup).
-    __device__ __forceinline__ double vcycle(S omega) {
+    // z_ready: z = omega r / d of level 0 was formed by the PCG update pass
+    __device__ __forceinline__ double vcycle(S omega, bool z_ready = false) {
         const int nl = K.nlev;
         if (nl == 1) {
             const BLev<S> L = lev(0);
@@ -360,6 +361,7 @@ struct BatchBlock {
         }
         for (int l = 0; l + 1 < nl; ++l) {
             const BLev<S> L = lev(l);
+            if (!(z_ready && l == 0)) {
             cells_g(L.d, [&](const Cell* C, const bool* on) {      // z = omega r / d
                 S b0l[UG], b0h[UG], b1l[UG], b1h[UG], r[UG];
 #pragma unroll
@@ -380,6 +382,7 @@ struct BatchBlock {
                     }
             });
             __syncthreads();
+            }
             jacobi(L, L.z, L.zt, omega);                            // zt = z + omega (r - A z) / d
             __syncthreads();
             const BLev<S> Lc = lev(l + 1);
@@ -462,8 +465,10 @@ struct BatchBlock {
     // Solve A x = r0 (initial residual already in lev(0).r, |f|^2 = ff) to
     // |r|^2 <= tol2 ff.  x in precision X.  Returns iterations (>= 0), or -1
     // when maxit was reached, -2 on breakdown with a non-finite value.
+    // x_zero: x starts at 0 and is not read (the first update writes it);
+    // the x of a solve that returns 0 is then not written at all.
     template <typename X>
-    __device__ int pcg(X* x, double ff, double rr, double tol2, S omega) {
+    __device__ int pcg(X* x, double ff, double rr, double tol2, S omega, bool x_zero = false) {
         if (ff == 0.0 || rr <= tol2 * ff) return 0;
         const BLev<S> L = lev(0);
         S* p = static_cast<S*>(K.pv);      // direction of the last iteration
@@ -473,7 +478,7 @@ struct BatchBlock {
         const S* pold = L.zt;              // first direction: zt + 0 zt = zt
         for (int it = 0; it < K.maxit; ++it) {
             // preconditioned residual (one call site: the V-cycle is inlined once)
-            const double rzn = vcycle(omega);
+            const double rzn = vcycle(omega, it > 0);
             if (it > 0) {
                 beta = rzn / rz;
                 S* cur = pn;               // the last iteration's direction is this one's p
@@ -518,17 +523,24 @@ struct BatchBlock {
             if (!(pq > 0.0)) return isfinite(pq) ? it : -2;
             const double alpha = rz / pq;
             double r2 = 0.0;
+            // x, r update, and the first pre-smoothing sweep of the next
+            // V-cycle (z = omega r / d, pointwise) from the new r
+            const bool xz = x_zero && it == 0;
             cells_g(L.d, [&](const Cell* C, const bool* on) {
                 X xv[UG];
-                S pv[UG], rv[UG], qv[UG];
+                S pv[UG], rv[UG], qv[UG], b0l[UG], b0h[UG], b1l[UG], b1h[UG];
 #pragma unroll
                 for (int u = 0; u < UG; ++u)
                     if (on[u]) {
                         const unsigned c = C[u].id;
-                        xv[u] = x[c];
+                        xv[u] = xz ? X(0) : x[c];
                         pv[u] = pn[c];
                         rv[u] = L.r[c];
                         qv[u] = q[c];
+                        b0l[u] = L.b0[c];
+                        b0h[u] = L.b0[C[u].nb(0, 1)];
+                        b1l[u] = L.b1[c];
+                        b1h[u] = L.b1[C[u].nb(1, 1)];
                     }
 #pragma unroll
                 for (int u = 0; u < UG; ++u)
@@ -538,6 +550,8 @@ struct BatchBlock {
                         const S rn = rv[u] - S(alpha) * qv[u];
                         L.r[c] = rn;
                         r2 += (double)rn * (double)rn;
+                        const S dg = (b0l[u] + b0h[u] + b1l[u] + b1h[u]) * L.ih2;
+                        L.z[c] = omega * rn / dg;
                     }
             });
             r2 = bsum<NT>(r2, red);
@@ -622,18 +636,12 @@ struct BatchBlock {
 
     // Pressure solve for the current b (FP64, mean removed here): returns
     // TPF_OK / TPF_ENOCONV / TPF_ENONFINITE; K.p holds the zero-mean solution.
-    __device__ int poisson(const T* phi) {
+    // mean: the mean of b (summed by the divergence pass); gauge: remove the
+    // mean of the solution (the last stage of a step and a single stage
+    // evaluation; inside a step only G p is used, which a constant does not
+    // change, and the warm starts combine pressures with weights summing to 1)
+    __device__ int poisson(const T* phi, double mean, bool gauge) {
         const S omega = S(0.8);
-        double mean = 0.0;
-        cells_g(dims(0), [&](const Cell* C, const bool* on) {
-            double v[UG];
-#pragma unroll
-            for (int u = 0; u < UG; ++u) v[u] = on[u] ? K.b[C[u].id] : 0.0;
-#pragma unroll
-            for (int u = 0; u < UG; ++u)
-                if (on[u]) mean += v[u];
-        });
-        mean = bsum<NT>(mean, red) / (double)ncell(0);
         build_betas(phi);
         int total = 0, outer = 0, status = TPF_OK;
         double ff = 0.0, rr = 0.0, aa = 0.0;
@@ -657,14 +665,15 @@ struct BatchBlock {
                 if (!isfinite(ff) || !isfinite(rr)) { status = TPF_ENONFINITE; break; }
                 if (ff == 0.0 || rr <= K.rtol * K.rtol * ff || rr <= fl2 * aa) { status = TPF_OK; outer = o; break; }
                 S* e = static_cast<S*>(K.ev);
-                cells(dims(0), [&](const Cell& C) { e[C.id] = S(0); });
-                __syncthreads();
                 // aim at the outer tolerance, not below rtol_inner (FP32 depth);
-                // an inner solve stopped by maxit still improves the iterate
+                // an inner solve stopped by maxit still improves the iterate.
+                // e starts at 0 (written by the first update, untouched when
+                // the solve returns at once)
                 const double tin = fmin(0.1, fmax(K.rtol_inner, 0.5 * K.rtol * sqrt(ff / rr)));
-                const int it = pcg<S>(e, rr, rr, tin * tin, omega);
+                const int it = pcg<S>(e, rr, rr, tin * tin, omega, true);
                 if (it == -2) { status = TPF_ENONFINITE; break; }
                 total += it < 0 ? K.maxit : it;
+                if (it == 0) continue;
                 cells_g(dims(0), [&](const Cell* C, const bool* on) {
                     double pv[UG];
                     S ev[UG];
@@ -682,25 +691,27 @@ struct BatchBlock {
             }
         }
         // zero-mean gauge
-        double sx = 0.0;
-        cells_g(dims(0), [&](const Cell* C, const bool* on) {
-            double v[UG];
+        if (gauge) {
+            double sx = 0.0;
+            cells_g(dims(0), [&](const Cell* C, const bool* on) {
+                double v[UG];
 #pragma unroll
-            for (int u = 0; u < UG; ++u) v[u] = on[u] ? K.p[C[u].id] : 0.0;
+                for (int u = 0; u < UG; ++u) v[u] = on[u] ? K.p[C[u].id] : 0.0;
 #pragma unroll
-            for (int u = 0; u < UG; ++u)
-                if (on[u]) sx += v[u];
-        });
-        sx = bsum<NT>(sx, red) / (double)ncell(0);
-        cells_g(dims(0), [&](const Cell* C, const bool* on) {
-            double v[UG];
+                for (int u = 0; u < UG; ++u)
+                    if (on[u]) sx += v[u];
+            });
+            sx = bsum<NT>(sx, red) / (double)ncell(0);
+            cells_g(dims(0), [&](const Cell* C, const bool* on) {
+                double v[UG];
 #pragma unroll
-            for (int u = 0; u < UG; ++u)
-                if (on[u]) v[u] = K.p[C[u].id];
+                for (int u = 0; u < UG; ++u)
+                    if (on[u]) v[u] = K.p[C[u].id];
 #pragma unroll
-            for (int u = 0; u < UG; ++u)
-                if (on[u]) K.p[C[u].id] = v[u] - sx;
-        });
+                for (int u = 0; u < UG; ++u)
+                    if (on[u]) K.p[C[u].id] = v[u] - sx;
+            });
+        }
         __syncthreads();
         if (threadIdx.x == 0) {
             st->iters = total;
@@ -733,16 +744,13 @@ struct BatchBlock {
         });
         __syncthreads();
     }
-    __device__ void record_pressure(int s) {
+    // the history the warm starts of later stages read (stored by the
+    // projection pass of stages 1-3)
+    __device__ __forceinline__ void record_pressure(int s, unsigned c) const {
         const double* p = K.p;
-        if (s == 3) return;
-        cells(dims(0), [&](const Cell& C) {
-            const unsigned c = C.id;
-            if (s == 0) K.ph[0][c] = p[c];
-            else if (s == 1) K.ph[1][c] = p[c];
-            else K.ph[2][c] = p[c] - K.ph[1][c];
-        });
-        __syncthreads();
+        if (s == 0) K.ph[0][c] = p[c];
+        else if (s == 1) K.ph[1][c] = p[c];
+        else if (s == 2) K.ph[2][c] = p[c] - K.ph[1][c];
     }
 
     // ---------------------------------------------------------- one stage
@@ -783,17 +791,20 @@ struct BatchBlock {
                               nullptr, nullptr, nullptr);
         });
         __syncthreads();
-        cells(d, [&](const Cell& C) { (void)op_div<T, 2>(P, C, f0, f1, nullptr, K.b); });
-        __syncthreads();
+        // b = D f*, and the sum of b for the solve's mean
+        double bs = 0.0;
+        cells(d, [&](const Cell& C) { bs += op_div<T, 2>(P, C, f0, f1, nullptr, K.b); });
+        const double mean = bsum<NT>(bs, red) / (double)ncell(0);
         if (!rk.eval_only) warm_start(rk.stage, st->hist_valid != 0);
-        const int status = poisson(phi);
+        const int status = poisson(phi, mean, rk.eval_only || rk.stage == 3);
         if (status != TPF_OK) return status;
-        if (!rk.eval_only) record_pressure(rk.stage);
+        const bool rec = !rk.eval_only && rk.stage < 3;
         cells(d, [&](const Cell& C) {
             op_project<T, 2>(P, rk, C, phi, K.p, f0, f1, nullptr, static_cast<const T*>(K.y[yn][1]),
                              static_cast<const T*>(K.y[yn][2]), nullptr, static_cast<T*>(K.y[acc][1]),
                              static_cast<T*>(K.y[acc][2]), nullptr, static_cast<T*>(K.y[out][1]),
                              static_cast<T*>(K.y[out][2]), nullptr, flag);
+            if (rec) record_pressure(rk.stage, C.id);
         });
         __syncthreads();
         return TPF_OK;
