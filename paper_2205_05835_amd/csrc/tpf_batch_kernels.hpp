@@ -773,15 +773,40 @@ struct BatchBlock {
         T* f0 = static_cast<T*>(K.fs[0]);
         T* f1 = static_cast<T*>(K.fs[1]);
         int* flag = &st->nonfinite;
-        cells(d, [&](const Cell& C) { op_cell<T, 2>(P, C, phi, n0, n1, nullptr, K.need_mu ? mu : nullptr); });
-        __syncthreads();
-        if (K.need_kappa) {
-            cells(d, [&](const Cell& C) { op_kappa<T, 2>(P, C, n0, n1, nullptr, kap); });
+        // FP32 cases without kappa take the fused pass below (in FP64 its
+        // recomputed normals cost the walled kernel variant its registers)
+        if (sizeof(T) == 8 || K.need_kappa) {
+            cells(d, [&](const Cell& C) { op_cell<T, 2>(P, C, phi, n0, n1, nullptr, K.need_mu ? mu : nullptr); });
             __syncthreads();
+            if (K.need_kappa) {
+                cells(d, [&](const Cell& C) { op_kappa<T, 2>(P, C, n0, n1, nullptr, kap); });
+                __syncthreads();
+            }
+            cells(d, [&](const Cell& C) {
+                op_face<T, 2>(P, C, phi, n0, n1, nullptr, u0, u1, nullptr, r0, r1, nullptr, m0, m1, nullptr);
+            });
+        } else if constexpr (sizeof(T) == 4) {
+            // no kappa (CDI with the energy-based force): the fluxes recompute
+            // the normals of c - e_a instead of reading them back, one pass
+            // instead of two with the same values
+            cells(d, [&](const Cell& C) {
+                T g[3] = {T(0), T(0), T(0)};
+                const T inv = grad_inv<T, 2>(P, C, phi, g);
+                const T f = ld(phi, C.id);
+                if (K.need_mu)
+                    tpf::st(mu, C.id, T(P.sigma_hat / P.eps) * dpsi(f) - T(P.sigma_hat * P.eps) * lap_at<T, 2>(P, C, phi, f));
+                auto nrm = [&](int a, bool lower) -> T {
+                    if (!lower) return g[a] * inv;
+                    // the cell c - e_a (itself across a wall: the mirror image)
+                    const int i = (a == 0 && !C.wall(0, -1)) ? (C.i == 0 ? d.nx - 1 : C.i - 1) : C.i;
+                    const int j = (a == 1 && !C.wall(1, -1)) ? (C.j == 0 ? d.ny - 1 : C.j - 1) : C.j;
+                    T gm[3] = {T(0), T(0), T(0)};
+                    const T im = grad_inv<T, 2>(P, make_cell_w(d, i, j, 0), phi, gm);
+                    return gm[a] * im;
+                };
+                op_face_n<T, 2>(P, C, phi, nrm, u0, u1, nullptr, r0, r1, nullptr, m0, m1, nullptr);
+            });
         }
-        cells(d, [&](const Cell& C) {
-            op_face<T, 2>(P, C, phi, n0, n1, nullptr, u0, u1, nullptr, r0, r1, nullptr, m0, m1, nullptr);
-        });
         __syncthreads();
         T* ph_out = static_cast<T*>(K.y[out][0]);
         cells(d, [&](const Cell& C) {

@@ -88,15 +88,14 @@ __device__ __forceinline__ void op_kappa(const Phys& P, const Cell& C, const T* 
 // ------------------------------------------------------------------ face fluxes
 // CDI flux r_a = gamma [eps G_a phi - A_a(phi (1 - phi) n_a)]  (Table 1)
 // mass flux m_a = rho_a u_a - (rho1 - rho2) r_a  (CDI; r = 0 otherwise)
-template <typename T, int DIM>
-__device__ __forceinline__ void op_face(const Phys& P, const Cell& C, const T* __restrict__ phi,
-                                                const T* __restrict__ n0, const T* __restrict__ n1,
-                                                const T* __restrict__ n2, const T* __restrict__ u0,
-                                                const T* __restrict__ u1, const T* __restrict__ u2,
-                                                T* __restrict__ r0, T* __restrict__ r1,
-                                                T* __restrict__ r2, T* __restrict__ m0,
-                                                T* __restrict__ m1, T* __restrict__ m2) {
-    const T* n[3] = {n0, n1, n2};
+// nrm(a, lower): component a of the normal at c (lower = false) or at the
+// cell c - e_a reads (lower = true)
+template <typename T, int DIM, typename N>
+__device__ __forceinline__ void op_face_n(const Phys& P, const Cell& C, const T* __restrict__ phi, N nrm,
+                                          const T* __restrict__ u0, const T* __restrict__ u1,
+                                          const T* __restrict__ u2, T* __restrict__ r0, T* __restrict__ r1,
+                                          T* __restrict__ r2, T* __restrict__ m0, T* __restrict__ m1,
+                                          T* __restrict__ m2) {
     const T* u[3] = {u0, u1, u2};
     T* r[3] = {r0, r1, r2};
     T* m[3] = {m0, m1, m2};
@@ -112,13 +111,27 @@ __device__ __forceinline__ void op_face(const Phys& P, const Cell& C, const T* _
         const bool shut = C.wall(a, -1);   // face on a wall: no flux
         T ra = T(0);
         if (cdi) {
-            const T wm = fm * (T(1) - fm) * ld(n[a], cm);
-            const T wc = f * (T(1) - f) * ld(n[a], c);
+            const T wm = fm * (T(1) - fm) * nrm(a, true);
+            const T wc = f * (T(1) - f) * nrm(a, false);
             ra = shut ? T(0) : T(P.gamma) * (T(P.eps) * ((f - fm) * T(P.inv_h)) - T(0.5) * (wm + wc));
             st(r[a], c, ra);
         }
         st(m[a], c, shut ? T(0) : rho_f * ld(u[a], c) - drho * ra);
     }
+}
+
+// the same with the normals read from the stored n_a
+template <typename T, int DIM>
+__device__ __forceinline__ void op_face(const Phys& P, const Cell& C, const T* __restrict__ phi,
+                                                const T* __restrict__ n0, const T* __restrict__ n1,
+                                                const T* __restrict__ n2, const T* __restrict__ u0,
+                                                const T* __restrict__ u1, const T* __restrict__ u2,
+                                                T* __restrict__ r0, T* __restrict__ r1,
+                                                T* __restrict__ r2, T* __restrict__ m0,
+                                                T* __restrict__ m1, T* __restrict__ m2) {
+    const T* n[3] = {n0, n1, n2};
+    auto nrm = [&](int a, bool lower) { return ld(n[a], lower ? C.off(a, -1) : C.id); };
+    op_face_n<T, DIM>(P, C, phi, nrm, u0, u1, u2, r0, r1, r2, m0, m1, m2);
 }
 
 // ------------------------------------------------------------------ field access
