@@ -669,7 +669,7 @@ struct BatchBlock {
                 // an inner solve stopped by maxit still improves the iterate.
                 // e starts at 0 (written by the first update, untouched when
                 // the solve returns at once)
-                const double tin = fmin(0.1, fmax(K.rtol_inner, 0.5 * K.rtol * sqrt(ff / rr)));
+                const double tin = fmin(0.1, fmax(K.rtol_inner, INNER_MARGIN * K.rtol * sqrt(ff / rr)));
                 const int it = pcg<S>(e, rr, rr, tin * tin, omega, true);
                 if (it == -2) { status = TPF_ENONFINITE; break; }
                 total += it < 0 ? K.maxit : it;

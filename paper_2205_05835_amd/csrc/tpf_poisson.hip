@@ -1142,7 +1142,7 @@ __global__ void k_inner_setup(SolverScalars* sc, double tol2) {
 
 // The first inner solve's set-up without a host round trip: the inner
 // tolerance from the outer residual just finalized, by the rule of the mixed
-// solve (half the reduction the outer tolerance needs, clamped to [rin, 0.1];
+// solve (0.9 of the reduction the outer tolerance needs, INNER_MARGIN, clamped to [rin, 0.1];
 // 0 in the fixed-iteration mode).  An outer residual that already meets the
 // tolerance, or is not finite, leaves the inner solve done before it starts,
 // with iters = -1 and the outer ||f||^2, ||r||^2 kept for the host.
@@ -1154,7 +1154,7 @@ __global__ void k_inner_setup_first(SolverScalars* sc, double rtol, double rin, 
         sc->iters = -1;
         return;
     }
-    const double tin = fixed ? 0.0 : fmin(0.1, fmax(rin, 0.5 * rtol * sqrt(ff / rr)));
+    const double tin = fixed ? 0.0 : fmin(0.1, fmax(rin, INNER_MARGIN * rtol * sqrt(ff / rr)));
     sc->ff = rr;
     sc->tol2 = tin * tin;
     sc->done = rr > 0.0 ? 0 : 1;
@@ -2269,7 +2269,7 @@ static tpf_status poisson_solve_t(tpf_ctx* c, const void* phi, int* iters, doubl
     for (int o = 0; o < max_outer; ++o) {
         s64.template residual<float>(s64.coef_phi(phi), tp<float>(c->lv[0].r));   // FP64 residual, FP64 beta
         (void)finalize3(c, (int)s64.nb0(), (int)s64.nb0(), (int)s64.nb0(), FIN_INIT, fixed ? 0.0 : rtol * rtol);
-        // the inner solve aims straight at the outer tolerance (half of the
+        // the inner solve aims straight at the outer tolerance (INNER_MARGIN of the
         // reduction it needs), but never below rin, the depth an FP32 PCG
         // reaches reliably; a further outer pass picks up the rest.  The
         // first pass (a converged start is rare) sets this up on the device
@@ -2294,7 +2294,7 @@ static tpf_status poisson_solve_t(tpf_ctx* c, const void* phi, int* iters, doubl
             std::snprintf(buf, sizeof(buf), " %.2e (floor %.1e)", s.ff > 0 ? std::sqrt(s.rr / s.ff) : 0.0,
                           s.ff > 0 ? std::sqrt(s.floor2 / s.ff) : 0.0);
             trail += buf;
-            const double need = 0.5 * rtol * std::sqrt(s.ff / s.rr);
+            const double need = INNER_MARGIN * rtol * std::sqrt(s.ff / s.rr);
             const double tin = fixed ? 0.0 : std::min(0.1, std::max(rin, need));
             k_inner_setup<<<1, 64, 0, c->stream>>>(c->scal, tin * tin);
         }
