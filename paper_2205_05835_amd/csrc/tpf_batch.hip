@@ -684,6 +684,22 @@ tpf_status tpf_batch_tune(tpf_batch* b, const double* dt, const char* cache_path
     }
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return hip_fail(e, "saving pressures for tuning");
+    // the saved pressures, history and bookkeeping back on the device
+    // (stream-ordered), so that every timed window computes the same step
+    // from the same warm starts
+    auto restore = [&]() {
+        hipError_t er = hipSuccess;
+        for (int q = 0; q < b->ncases && er == hipSuccess; ++q) {
+            const BCase& K = b->h_cases[q];
+            const size_t N = (size_t)K.nx * K.ny;
+            double* dst[4] = {K.p, K.ph[0], K.ph[1], K.ph[2]};
+            for (int f = 0; f < 4 && er == hipSuccess; ++f)
+                er = hipMemcpyAsync(dst[f], saved[(size_t)q].data() + f * N, N * 8, hipMemcpyHostToDevice, b->stream);
+        }
+        if (er == hipSuccess)
+            er = hipMemcpyAsync(b->d_states, before.data(), sizeof(BState) * b->ncases, hipMemcpyHostToDevice, b->stream);
+        return er;
+    };
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
         set_error("hipEventCreate failed");
@@ -695,6 +711,8 @@ tpf_status tpf_batch_tune(tpf_batch* b, const double* dt, const char* cache_path
     for (int cfg = 0; cfg < NCONFIG; ++cfg) {
         st = tpf_batch_set_config(b, cfg);
         if (st != TPF_OK) break;
+        e = restore();
+        if (e != hipSuccess) break;
         e = launch_step(b, 0, 0);                       // warm-up
         if (e != hipSuccess) {                          // shape not launchable here: skip it
             (void)hipGetLastError();
@@ -702,10 +720,12 @@ tpf_status tpf_batch_tune(tpf_batch* b, const double* dt, const char* cache_path
             continue;
         }
         // the best of three single-step windows (one window is noisy at the
-        // few-percent level that separates the configurations)
+        // few-percent level that separates the configurations), each from
+        // the saved state
         float ms = 0.f;
         for (int w = 0; w < 3 && e == hipSuccess; ++w) {
-            e = hipEventRecord(e0, b->stream);
+            e = restore();
+            if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
             e = e == hipSuccess ? launch_step(b, 0, 0) : e;
             if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -723,19 +743,11 @@ tpf_status tpf_batch_tune(tpf_batch* b, const double* dt, const char* cache_path
     (void)hipEventDestroy(e1);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return hip_fail(e, "timing batch launch configurations");
-    // a case whose pressure solve failed in a timed step is reported; every
-    // case gets its pressures and bookkeeping back
+    // a case whose pressure solve failed in the last timed step is reported;
+    // every case gets its pressures and bookkeeping back
     st = read_states(b, after);
     if (st != TPF_OK) return st;
-    for (int q = 0; q < b->ncases && e == hipSuccess; ++q) {
-        const BCase& K = b->h_cases[q];
-        const size_t N = (size_t)K.nx * K.ny;
-        double* dst[4] = {K.p, K.ph[0], K.ph[1], K.ph[2]};
-        for (int f = 0; f < 4 && e == hipSuccess; ++f)
-            e = hipMemcpyAsync(dst[f], saved[(size_t)q].data() + f * N, N * 8, hipMemcpyHostToDevice, b->stream);
-    }
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(b->d_states, before.data(), sizeof(BState) * b->ncases, hipMemcpyHostToDevice, b->stream);
+    e = restore();
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return hip_fail(e, "restoring the batch after tuning");
     if (st != TPF_OK) return st;
