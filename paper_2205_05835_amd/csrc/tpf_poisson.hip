@@ -1712,10 +1712,15 @@ struct Solver {
     // level 0 in 3D runs the z-marching kernels: kz planes per block
     bool march0() const { return dim == 3 && c->march && kz() > 0; }
     // planes per block of the z-marching kernels: 8 or 16 (the march is
-    // unrolled for these); 0 when nz admits neither (plain kernels then)
+    // unrolled for these); 0 when nz admits neither (plain kernels then).
+    // 16 where the grid still gives at least 4096 blocks (at 256^3: 13.94 ->
+    // 13.86 ms per step, one prologue per 16 planes), else 8.
     int kz() const {
-        const int nz = c->lv[0].n[2];
+        const int* n = c->lv[0].n;
+        const int nz = n[2];
         if ((c->kz_override == 8 || c->kz_override == 16) && nz % c->kz_override == 0) return c->kz_override;
+        const long blocks16 = (long)((n[0] + BX - 1) / BX) * ((n[1] + BY - 1) / BY) * (nz / 16);
+        if (nz % 16 == 0 && blocks16 >= 4096) return 16;
         if (nz % 8 == 0) return 8;
         return 0;
     }
