@@ -111,8 +111,10 @@ struct CoefPhi {
     const T* __restrict__ phi;
     S h2, dh;          // rho2 / 2, (rho1 - rho2) / 2
     S lo, hi;          // clamp bounds of phi: [0, 1], or +-inf when not clamping
+    // the clamp in the storage precision T: the bounds (0, 1 or infinities)
+    // and the conversion to S are exact, so this equals clamping in S
     __device__ __forceinline__ S hr(unsigned c) const {
-        return h2 + dh * med3(S(ld(phi, c)), lo, hi);
+        return h2 + dh * S(med3(ld(phi, c), T(lo), T(hi)));
     }
     template <int DIM>
     __device__ __forceinline__ void faces(const Cell& C, S* bl, S* bh) const {
@@ -248,8 +250,9 @@ __global__ __launch_bounds__(BLOCK) void k_beta_coarsen(Dims fd, Dims cd, CoefSt
 
 // ---------------------------------------------------------------- residuals
 // r = -(b - mean) - A x in precision S (x and b FP64), stored as R;
-// partials: |f|^2 -> region 0, |r|^2 -> region 1
-template <typename Coef, typename S, typename R, int DIM>
+// partials: |f|^2 -> region 0, |r|^2 -> region 1, and with FL the sum of
+// squares of |A||x| (the rounding floor of the residual) -> region 2
+template <typename Coef, typename S, typename R, int DIM, bool FL = true>
 __global__ __launch_bounds__(BLOCK) void k_resid(Dims d, S ih2, Coef cf,
                                                  const double* __restrict__ b,
                                                  const double* __restrict__ x,
@@ -269,8 +272,10 @@ __global__ __launch_bounds__(BLOCK) void k_resid(Dims d, S ih2, Coef cf,
         st(r, c, R(rc));
         v[0] = f * f;
         v[1] = rc * rc;
-        const double ax = abs_flux_sum<S, DIM>(bl, bh, X, xc, ih2);
-        v[2] = ax * ax;
+        if (FL) {
+            const double ax = abs_flux_sum<S, DIM>(bl, bh, X, xc, ih2);
+            v[2] = ax * ax;
+        }
     }
     block_partials_3r(v, partials, stride);
 }
@@ -499,7 +504,7 @@ __global__ __launch_bounds__(1024) void k_coarse(Dims d, S ih2, S omega, int swe
             const S* xs = src;
             auto X = [&](int a, int t) { return xs[C.nb(a, t)]; };
             const S az = apply_at<S, DIM>(bl, bh, X, src[q], ih2, dg);
-            dst[q] = src[q] + omega * (r[q] - az) / dg;
+            dst[q] = src[q] + omega * (r[q] - az) * recip(dg);
         }
         __syncthreads();
         S* t = src;
@@ -543,43 +548,51 @@ __global__ __launch_bounds__(1024) void k_tail(TailDesc D, S w1, S w2, S omega_c
     const int t = threadIdx.x, T = blockDim.x;
     auto dims = [&](int l) { return Dims{D.n[l][0], D.n[l][1], D.n[l][2], 0, 0}; };
     auto ncell = [&](int l) { return D.n[l][0] * D.n[l][1] * D.n[l][2]; };
-    // (i, j, k) of cell q of level l: shifts and masks when nx and ny are
-    // powers of two (D.lg[l] >= 0, the usual case), else divisions
-    auto ijk = [&](int l, int q, int& i, int& j, int& k) {
-        const Dims d = dims(l);
-        if (D.lg[l][0] >= 0) {
-            i = q & (d.nx - 1);
-            j = (q >> D.lg[l][0]) & (d.ny - 1);
-            k = q >> D.lg[l][1];
+    // a level's sizes and index shifts, read from the descriptor once per pass
+    // (indexed by the level, the descriptor lives in kernel-argument memory)
+    struct Lev {
+        Dims d;
+        int lx, lxy;
+    };
+    auto lev = [&](int l) { return Lev{dims(l), D.lg[l][0], D.lg[l][1]}; };
+    // (i, j, k) of cell q: shifts and masks when nx and ny are powers of two
+    // (lx >= 0, the usual case), else divisions
+    auto ijk = [&](const Lev& V, int q, int& i, int& j, int& k) {
+        if (V.lx >= 0) {
+            i = q & (V.d.nx - 1);
+            j = (q >> V.lx) & (V.d.ny - 1);
+            k = q >> V.lxy;
         } else {
-            i = q % d.nx;
-            j = (q / d.nx) % d.ny;
-            k = q / (d.nx * d.ny);
+            i = q % V.d.nx;
+            j = (q / V.d.nx) % V.d.ny;
+            k = q / (V.d.nx * V.d.ny);
         }
     };
-    auto cell = [&](int l, int q) {
+    auto cell = [&](const Lev& V, int q) {
         int i, j, k;
-        ijk(l, q, i, j, k);
-        return make_cell(dims(l), i, j, k);
+        ijk(V, q, i, j, k);
+        return make_cell(V.d, i, j, k);
     };
     auto coef = [&](int l) {
         return CoefStored<S>{static_cast<const S*>(D.beta[l][0]), static_cast<const S*>(D.beta[l][1]),
                              static_cast<const S*>(D.beta[l][2])};
     };
     // one damped Jacobi sweep out = X + w (r - A X) / d, X(a, s) from get
+    // (1 / d by the reciprocal of the separate sweep kernels)
     auto sweep = [&](int l, S w, auto get, S* out) {
+        const Lev V = lev(l);
         const int N = ncell(l);
         const S* r = L + D.off[l];
         const S ih2 = S(D.ih2[l]);
         const CoefStored<S> cf = coef(l);
         for (int q = t; q < N; q += T) {
-            const Cell C = cell(l, q);
+            const Cell C = cell(V, q);
             S bl[3], bh[3], dg;
             cf.template faces<DIM>(C, bl, bh);
             auto X = [&](int a, int s) { return get(C, a, s); };
             const S xc = get(C, 0, 0);
             const S az = apply_at<S, DIM>(bl, bh, X, xc, ih2, dg);
-            out[q] = xc + w * (r[q] - az) / dg;
+            out[q] = xc + w * (r[q] - az) * recip(dg);
         }
         __syncthreads();
     };
@@ -596,22 +609,24 @@ __global__ __launch_bounds__(1024) void k_tail(TailDesc D, S w1, S w2, S omega_c
         S* zt = z + N;
         const S ih2 = S(D.ih2[l]);
         const CoefStored<S> cf = coef(l);
+        const Lev V = lev(l);
         for (int q = t; q < N; q += T) {            // z = omega r / d
-            const Cell C = cell(l, q);
+            const Cell C = cell(V, q);
             S bl[3], bh[3], dg = S(0);
             cf.template faces<DIM>(C, bl, bh);
             for (int a = 0; a < DIM; ++a) dg += bl[a] + bh[a];
-            z[q] = w1 * r[q] / (dg * ih2);
+            z[q] = w1 * r[q] * recip(dg * ih2);
         }
         __syncthreads();
         sweep(l, w2, [&](const Cell& C, int a, int s) { return z[s == 0 ? C.id : C.nb(a, s)]; }, zt);
         // restriction of r - A zt into the next level's r
         const int Nc = ncell(l + 1);
         S* rc = L + D.off[l + 1];
-        const Dims df = dims(l);
+        const Dims df = V.d;
+        const Lev VC = lev(l + 1);
         for (int Q = t; Q < Nc; Q += T) {
             int I, J, K;
-            ijk(l + 1, Q, I, J, K);
+            ijk(VC, Q, I, J, K);
             S s = S(0);
             for (int dk = 0; dk < (DIM == 3 ? 2 : 1); ++dk)
                 for (int dj = 0; dj < 2; ++dj)
@@ -637,7 +652,7 @@ __global__ __launch_bounds__(1024) void k_tail(TailDesc D, S w1, S w2, S omega_c
             // (the same arithmetic as the block-wide sweeps below)
             if (t < 64) {
                 const int q = t < N ? t : 0;
-                const Cell C = cell(l, q);
+                const Cell C = cell(lev(l), q);
                 const CoefStored<S> cf = coef(l);
                 const S ih2 = S(D.ih2[l]);
                 S bl[3], bh[3];
@@ -660,7 +675,7 @@ __global__ __launch_bounds__(1024) void k_tail(TailDesc D, S w1, S w2, S omega_c
                     auto X = [&](int a, int s2) { return s2 < 0 ? xm[a] : xp[a]; };
                     S dg;
                     const S az = apply_at<S, DIM>(bl, bh, X, x, ih2, dg);
-                    x = x + omega_c * (rq - az) / dg;
+                    x = x + omega_c * (rq - az) * recip(dg);
                 }
                 if (t < N) r[2 * N + t] = x;
             }
@@ -691,10 +706,12 @@ __global__ __launch_bounds__(1024) void k_tail(TailDesc D, S w1, S w2, S omega_c
         S* zt = z + N;
         const Dims dc = dims(l + 1);
         const S* zc = L + D.off[l + 1] + 2 * ncell(l + 1);
+        const Lev V = lev(l);
         // zt += P zc, then two sweeps zt -> z -> zt
         for (int q = t; q < N; q += T) {
-            const Cell C = cell(l, q);
-            zt[q] += prolong_at<S, DIM>(dc, zc, C.i, C.j, C.k);
+            int i, j, k;
+            ijk(V, q, i, j, k);
+            zt[q] += prolong_at<S, DIM>(dc, zc, i, j, k);
         }
         __syncthreads();
         sweep(l, w2, [&](const Cell& C, int a, int s) { return zt[s == 0 ? C.id : C.nb(a, s)]; }, z);
@@ -1626,8 +1643,8 @@ __global__ __launch_bounds__(BLOCK) void k_fz_restrict(Dims d, Dims cd, int kz, 
 }
 
 // r = -(b - mean) - A x (x FP64 read in precision S), stored as R;
-// |f|^2 -> region 0, |r|^2 -> region 1
-template <typename Coef, typename S, typename R>
+// |f|^2 -> region 0, |r|^2 -> region 1, with FL | |A||x| |^2 -> region 2
+template <typename Coef, typename S, typename R, bool FL = true>
 __global__ __launch_bounds__(BLOCK) void k_fz_resid(Dims d, int kz, S ih2, Coef cf,
                                                     const double* __restrict__ b,
                                                     const double* __restrict__ x,
@@ -1651,11 +1668,13 @@ __global__ __launch_bounds__(BLOCK) void k_fz_resid(Dims d, int kz, S ih2, Coef 
             st(r, c, R(rr));
             v[0] += f * f;
             v[1] += rr * rr;
+            if (FL) {
             const double aa = (fabs((double)bl[0] * (double)(X.c - X.xm)) + fabs((double)bh[0] * (double)(X.xp - X.c)) +
                                fabs((double)bl[1] * (double)(X.c - X.ym)) + fabs((double)bh[1] * (double)(X.yp - X.c)) +
                                fabs((double)bl[2] * (double)(X.c - X.zm)) + fabs((double)bh[2] * (double)(X.zp - X.c))) *
                               (double)ih2;
             v[2] += aa * aa;
+            }
         }
     });
     block_partials_3r(v, partials, stride);
@@ -2152,18 +2171,20 @@ struct Solver {
 
     // r = f - A x with the coefficient policy cf (FP64 path: the fine-level
     // half densities; mixed path: FP64 coefficients straight from phi)
-    template <typename R, typename Coef>
+    // FL: also the rounding floor |A||x| (without it the floor is 0, so the
+    // convergence test is the tolerance alone)
+    template <typename R, bool FL = true, typename Coef>
     void residual(Coef cf, R* r) {
         prof_begin(c, PC_RESID, (double)c->N * (8 + 8 + sizeof(T) + sizeof(R)));
         if (march0())
-            k_fz_resid<Coef, S, R><<<mgrid(), dim3(BX, BY), 0, c->stream>>>(dims(0), kz(), ih2(0), cf, c->b, c->p, r,
-                                                                           c->scal, c->partials, c->max_blocks);
+            k_fz_resid<Coef, S, R, FL><<<mgrid(), dim3(BX, BY), 0, c->stream>>>(
+                dims(0), kz(), ih2(0), cf, c->b, c->p, r, c->scal, c->partials, c->max_blocks);
         else if (dim == 3)
-            k_resid<Coef, S, R, 3><<<grid(0), dim3(BX, BY), 0, c->stream>>>(dims(0), ih2(0), cf, c->b, c->p, r,
-                                                                           c->scal, c->partials, c->max_blocks);
+            k_resid<Coef, S, R, 3, FL><<<grid(0), dim3(BX, BY), 0, c->stream>>>(
+                dims(0), ih2(0), cf, c->b, c->p, r, c->scal, c->partials, c->max_blocks);
         else
-            k_resid<Coef, S, R, 2><<<grid(0), dim3(BX, BY), 0, c->stream>>>(dims(0), ih2(0), cf, c->b, c->p, r,
-                                                                           c->scal, c->partials, c->max_blocks);
+            k_resid<Coef, S, R, 2, FL><<<grid(0), dim3(BX, BY), 0, c->stream>>>(
+                dims(0), ih2(0), cf, c->b, c->p, r, c->scal, c->partials, c->max_blocks);
         prof_end(c);
     }
 };
@@ -2272,7 +2293,13 @@ static tpf_status poisson_solve_t(tpf_ctx* c, const void* phi, int* iters, doubl
     const int max_outer = fixed ? c->fixed_outer + 1 : 12;
     std::string trail;      // relative outer residual after each pass, for the failure message
     for (int o = 0; o < max_outer; ++o) {
-        s64.template residual<float>(s64.coef_phi(phi), tp<float>(c->lv[0].r));   // FP64 residual, FP64 beta
+        // FP64 residual, FP64 beta.  The first pass leaves out the rounding
+        // floor: a start already at the floor costs one inner solve, after
+        // which the next pass (with the floor) stops.
+        if (o == 0)
+            s64.template residual<float, false>(s64.coef_phi(phi), tp<float>(c->lv[0].r));
+        else
+            s64.template residual<float, true>(s64.coef_phi(phi), tp<float>(c->lv[0].r));
         (void)finalize3(c, (int)s64.nb0(), (int)s64.nb0(), (int)s64.nb0(), FIN_INIT, fixed ? 0.0 : rtol * rtol);
         // the inner solve aims straight at the outer tolerance (INNER_MARGIN of the
         // reduction it needs), but never below rin, the depth an FP32 PCG
