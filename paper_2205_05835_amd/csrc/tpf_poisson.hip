@@ -299,7 +299,8 @@ __global__ __launch_bounds__(BLOCK) void k_jac_first(Dims d, S ih2, S omega, Coe
 
 // PCG update fused with the first smoothing sweep of the V-cycle:
 //   x += alpha p, r -= alpha q, <r,r> (region 0), z = omega r / d
-template <typename Coef, typename S, typename X, int DIM>
+// (XZ: x is zero before this update and not read)
+template <typename Coef, typename S, typename X, int DIM, bool XZ = false>
 __global__ __launch_bounds__(BLOCK) void k_jac_first_update(Dims d, S ih2, S omega, Coef cf,
                                                             X* __restrict__ x, S* __restrict__ r,
                                                             const S* __restrict__ p,
@@ -313,7 +314,7 @@ __global__ __launch_bounds__(BLOCK) void k_jac_first_update(Dims d, S ih2, S ome
     if (cell_of_thread<Coef::kWalls>(d, C)) {
         const unsigned c = C.id;
         const double alpha = sc->alpha;
-        st(x, c, X((double)ld(x, c) + alpha * (double)ld(p, c)));
+        st(x, c, X((double)(XZ ? X(0) : ld(x, c)) + alpha * (double)ld(p, c)));
         const S rn = S((double)ld(r, c) - alpha * (double)ld(q, c));
         st(r, c, rn);
         v[0] = (double)rn * (double)rn;
@@ -1065,12 +1066,6 @@ __global__ __launch_bounds__(BLOCK) void k_sub_mean(long N, double* __restrict__
         x[c] -= m;
 }
 
-template <typename S>
-__global__ __launch_bounds__(BLOCK) void k_fill_s(long N, S* __restrict__ x, S v) {
-    for (long c = (long)blockIdx.x * BLOCK + threadIdx.x; c < N; c += (long)gridDim.x * BLOCK)
-        x[c] = v;
-}
-
 // ---------------------------------------------------------------- finalize
 // One 1024-thread block sums region 0 (nb0 partials) and region 1 (nb1
 // partials at partials + stride) in a fixed order and applies op.
@@ -1515,7 +1510,8 @@ __global__ __launch_bounds__(BLOCK) void k_fz_jac(Dims d, int kz, S ih2, S omega
 }
 
 // first sweep from zero: z = omega r / d; UPD: first the PCG update
-// x += alpha p, r -= alpha q with <r, r> to the partials
+// x += alpha p, r -= alpha q with <r, r> to the partials (UPD 2: x is zero
+// before this update, the first of a solve from a zero guess, and not read)
 template <typename S, typename X>
 struct FirstPre {
     S r, q, p;
@@ -1540,7 +1536,7 @@ __global__ __launch_bounds__(BLOCK) void k_fz_first(Dims d, int kz, S ih2, S ome
         if (UPD) {
             e.q = ld(qv, c);
             e.p = ld(p, c);
-            e.x = ld(x, c);
+            e.x = UPD == 2 ? X(0) : ld(x, c);
         } else {
             e.q = e.p = S(0);
             e.x = X(0);
@@ -2006,8 +2002,9 @@ struct Solver {
 
     // p = z + beta p, q = A p (-> alpha), then x, r update fused with the
     // first pre-smoothing sweep
+    // xz: x is zero before this update (the first of a solve from zero)
     template <int DIM, typename X>
-    void apply_update(const void* phi, int first, X* x) {
+    void apply_update(const void* phi, int first, X* x, bool xz) {
         const auto cf = coef_fine();
         const dim3 b(BX, BY);
         S* pold = tp<S>(c->pv);
@@ -2018,10 +2015,15 @@ struct Solver {
                                                           pold, pnew, tp<S>(c->qv), c->scal, c->partials);
             prof_end(c);
             (void)finalize2(c, (int)nb0(), 0, FIN_ALPHA, 0.0);
-            prof_begin(c, PC_F_FIRST, fb(0, 5 + cfields(0)) + 2.0 * c->N * sizeof(X));
-            k_fz_first<CoefRho<S, W>, S, X, 1><<<mgrid(), b, 0, c->stream>>>(dims(0), kz(), ih2(0), w1, cf, x,
-                                                               tp<S>(c->lv[0].r), pnew, tp<S>(c->qv),
-                                                               tp<S>(c->lv[0].z), c->scal, c->partials);
+            prof_begin(c, PC_F_FIRST, fb(0, 5 + cfields(0)) + (xz ? 1.0 : 2.0) * c->N * sizeof(X));
+            if (xz)
+                k_fz_first<CoefRho<S, W>, S, X, 2><<<mgrid(), b, 0, c->stream>>>(dims(0), kz(), ih2(0), w1, cf, x,
+                                                                   tp<S>(c->lv[0].r), pnew, tp<S>(c->qv),
+                                                                   tp<S>(c->lv[0].z), c->scal, c->partials);
+            else
+                k_fz_first<CoefRho<S, W>, S, X, 1><<<mgrid(), b, 0, c->stream>>>(dims(0), kz(), ih2(0), w1, cf, x,
+                                                                   tp<S>(c->lv[0].r), pnew, tp<S>(c->qv),
+                                                                   tp<S>(c->lv[0].z), c->scal, c->partials);
             prof_end(c);
             std::swap(c->pv, c->pv2);
             return;
@@ -2031,10 +2033,15 @@ struct Solver {
             dims(0), ih2(0), cf, first, tp<S>(c->lv[0].zt), pold, pnew, tp<S>(c->qv), c->scal, c->partials);
         prof_end(c);
         (void)finalize2(c, (int)nbl(0), 0, FIN_ALPHA, 0.0);
-        prof_begin(c, PC_F_FIRST, fb(0, 5 + cfields(0)) + 2.0 * c->N * sizeof(X));
-        k_jac_first_update<CoefRho<S, W>, S, X, DIM><<<grid(0), b, 0, c->stream>>>(
-            dims(0), ih2(0), w1, cf, x, tp<S>(c->lv[0].r), pnew, tp<S>(c->qv), tp<S>(c->lv[0].z),
-            c->scal, c->partials);
+        prof_begin(c, PC_F_FIRST, fb(0, 5 + cfields(0)) + (xz ? 1.0 : 2.0) * c->N * sizeof(X));
+        if (xz)
+            k_jac_first_update<CoefRho<S, W>, S, X, DIM, true><<<grid(0), b, 0, c->stream>>>(
+                dims(0), ih2(0), w1, cf, x, tp<S>(c->lv[0].r), pnew, tp<S>(c->qv), tp<S>(c->lv[0].z),
+                c->scal, c->partials);
+        else
+            k_jac_first_update<CoefRho<S, W>, S, X, DIM, false><<<grid(0), b, 0, c->stream>>>(
+                dims(0), ih2(0), w1, cf, x, tp<S>(c->lv[0].r), pnew, tp<S>(c->qv), tp<S>(c->lv[0].z),
+                c->scal, c->partials);
         prof_end(c);
         std::swap(c->pv, c->pv2);
     }
@@ -2051,9 +2058,9 @@ struct Solver {
     // application, the x and r update with the first sweep, the rest of the
     // V-cycle, and the flexible-CG scalars
     template <typename X>
-    void iteration(const void* phi, int first, X* x) {
-        if (dim == 2) apply_update<2, X>(phi, first, x);
-        else apply_update<3, X>(phi, first, x);
+    void iteration(const void* phi, int first, X* x, bool xz = false) {
+        if (dim == 2) apply_update<2, X>(phi, first, x, xz);
+        else apply_update<3, X>(phi, first, x, xz);
         vcycle(phi, true);
         (void)finalize3(c, (int)nb0(), (int)nb0(), (int)nb0(), FIN_BETA, 0.0);
     }
@@ -2102,8 +2109,11 @@ struct Solver {
         return hipSuccess;
     }
 
+    // x_zero: x starts at zero and is not read before the first update writes
+    // it (nothing is written when the solve stops before that update)
     template <typename X>
-    hipError_t pcg(const void* phi, X* x, int maxit, int slot, SolverScalars* last, bool* have_last) {
+    hipError_t pcg(const void* phi, X* x, int maxit, int slot, SolverScalars* last, bool* have_last,
+                   bool x_zero = false) {
         vcycle(phi, false);                                       // z = M r, <r,z>
         (void)finalize2(c, 0, (int)nb0(), FIN_RZ0, 0.0);
         int it = 0;
@@ -2129,7 +2139,7 @@ struct Solver {
                     }
                 }
                 snapshot(snap_[it]);
-                iteration(phi, first ? 1 : 0, x);
+                iteration(phi, first ? 1 : 0, x, first && x_zero);
                 first = false;
                 ++k;
                 ++it;
@@ -2330,9 +2340,10 @@ static tpf_status poisson_solve_t(tpf_ctx* c, const void* phi, int* iters, doubl
             const double tin = fixed ? 0.0 : std::min(0.1, std::max(rin, need));
             k_inner_setup<<<1, 64, 0, c->stream>>>(c->scal, tin * tin);
         }
-        k_fill_s<float><<<vgrid(c->N), BLOCK, 0, c->stream>>>(c->N, tp<float>(c->ev), 0.0f);
+        // the correction starts at zero through its first update (x_zero)
         bool have = false;
-        e = sv.template pcg<float>(phi, tp<float>(c->ev), fixed ? c->fixed_inner : maxit, 1 + std::min(o, 2), &s, &have);
+        e = sv.template pcg<float>(phi, tp<float>(c->ev), fixed ? c->fixed_inner : maxit, 1 + std::min(o, 2), &s, &have,
+                                   true);
         if (e != hipSuccess) return hip_fail(e, "FP32 inner PCG");
         if (!have) {
             tpf_status st = read_scalars(c, &s);
@@ -2355,9 +2366,13 @@ static tpf_status poisson_solve_t(tpf_ctx* c, const void* phi, int* iters, doubl
             set_error("non-finite inner pressure residual");
             return TPF_ENONFINITE;
         }
-        prof_begin(c, PC_VECTOR, (double)c->N * (8 + 4 + 8));
-        k_correct<<<vgrid(c->N), BLOCK, 0, c->stream>>>(c->N, c->p, tp<float>(c->ev));
-        prof_end(c);
+        // no update, no correction: the solve stopped before its first
+        // update wrote the correction
+        if (s.iters > 0) {
+            prof_begin(c, PC_VECTOR, (double)c->N * (8 + 4 + 8));
+            k_correct<<<vgrid(c->N), BLOCK, 0, c->stream>>>(c->N, c->p, tp<float>(c->ev));
+            prof_end(c);
+        }
     }
     set_error("pressure defect correction did not converge (relative residual after each pass:" + trail + ")");
     return TPF_ENOCONV;
