@@ -156,10 +156,11 @@ tpf_status tpf_step(tpf_ctx* ctx, double dt, int32_t nsteps);
  * for phi and u of a TPF_FP32_MIXED context, TPF_DTYPE_F64 otherwise; p is
  * always TPF_DTYPE_F64).  The array has N = nx*ny*nz elements in the layout
  * above, contiguous.  Offsets are multiples of 256.  The state alternates
- * between two slots of the workspace each RK4 step, so the offsets of phi and
- * u hold until the next tpf_step or tpf_step_adjoint (ask again after
- * either; tpf_load_checkpoint and tpf_implicit_phase_step write the current
- * slot in place).  p holds the zero-mean
+ * between two slots of the workspace each RK4 step, and the pressure between
+ * two arrays (the projection of a stage writes the next stage's starting
+ * guess beside it), so the offsets of phi, u and p hold until the next
+ * tpf_step or tpf_step_adjoint (ask again after either; tpf_load_checkpoint
+ * and tpf_implicit_phase_step write the current slot in place).  p holds the zero-mean
  * projection pressure of the current state once tpf_get_state (with p),
  * tpf_diagnostics or tpf_eval_field has run since the state last changed;
  * otherwise it holds the last solve's iterate.  Returns TPF_EINVAL for an

@@ -177,7 +177,7 @@ static size_t carve(tpf_ctx* c, char* base) {
     c->p_hist1 = (double*)cv.take(N8);
     c->p_hist2 = (double*)cv.take(N8);
     c->p_hist3 = (double*)cv.take(N8);
-    c->r64 = c->mixed ? (double*)cv.take(N8) : nullptr;
+    c->p_alt = (double*)cv.take(N8);
     c->pv = cv.take((size_t)c->N * ssz);
     c->pv2 = cv.take((size_t)c->N * ssz);
     c->qv = cv.take((size_t)c->N * ssz);
@@ -548,17 +548,6 @@ tpf_status advance(tpf_ctx* c, double dt, int nsteps, char* tape, size_t stage_b
                     st = copy_async(c, rec + (1 + a) * fT, u_s[a], NT);
                 if (st != TPF_OK) return st;
             }
-            // warm start of the pressure solve, from the pressures of the
-            // previous stages: stage 1 (time t) takes the last pressure
-            // (stage 4 of the previous step); stage 2 (t + dt/2) extrapolates
-            // linearly from t - dt/2 and t; stage 3 (t + dt/2 again) adds to
-            // the stage-2 pressure the stage-3 minus stage-2 difference of the
-            // previous step; stage 4 (t + dt) extrapolates from t and t + dt/2
-            hipError_t ew = hipSuccess;
-            if (s == 1 && c->hist2_valid) ew = launch_lincomb(c, c->p, 2.0, c->p, -1.0, c->p_hist2);
-            if (s == 2 && c->hist2_valid) ew = launch_lincomb(c, c->p, 1.0, c->p, 1.0, c->p_hist3);
-            if (s == 3) ew = launch_lincomb(c, c->p, 2.0, c->p, -1.0, c->p_hist1);
-            if (ew != hipSuccess) return hip_fail(ew, "pressure extrapolation");
             RKArgs rk{s, 0, wacc[s], wnext[s]};
             const void* us[3] = {u_s[0], u_s[1], u_s[2]};
             c->rk_stage = s;
@@ -567,16 +556,31 @@ tpf_status advance(tpf_ctx* c, double dt, int nsteps, char* tape, size_t stage_b
             double* const hist[4] = {c->p_hist1, c->p_hist2, c->p_hist3, nullptr};
             c->proj_hist = hist[s];
             c->proj_hsub = s == 2 ? c->p_hist2 : nullptr;
+            // and writes the starting guess of the next stage's pressure solve
+            // (stage 1, at time t, starts from the last pressure, stage 4 of
+            // the previous step): stage 2 (t + dt/2) extrapolates linearly
+            // from t - dt/2 and t, 2 p(t) - p_hist2 of the previous step;
+            // stage 3 (t + dt/2 again) adds to the stage-2 pressure the
+            // stage-3 minus stage-2 difference of the previous step, p_hist3;
+            // stage 4 (t + dt) extrapolates from t and t + dt/2, 2 p - p_hist1
+            const bool guess = (s < 2 && c->hist2_valid) || s == 2;
+            c->proj_guess = guess ? c->p_alt : nullptr;
+            c->proj_gsrc = s == 0 ? c->p_hist2 : s == 1 ? c->p_hist3 : c->p_hist1;
+            c->proj_ga = s == 1 ? 1.0 : 2.0;
+            c->proj_gb = s == 1 ? 1.0 : -1.0;
             tpf_status st = stage_eval(c, phi_s, us, rk, phi_o, u_o, 0, false);
             c->rk_stage = 0;
             c->proj_hist = nullptr;
             c->proj_hsub = nullptr;
+            c->proj_guess = nullptr;
+            c->proj_gsrc = nullptr;
             if (st == TPF_OK && rec) st = copy_async(c, rec + (1 + c->dim) * fT, c->p, (size_t)c->N * 8);
             if (st != TPF_OK) {
                 c->p_valid = 0;
                 c->hist2_valid = 0;
                 return st;
             }
+            if (guess) std::swap(c->p, c->p_alt);
         }
         int flag = 0;
         e = fetch_flag(c, &flag);

@@ -119,7 +119,8 @@ struct tpf_ctx {
     // pressure (FP64)
     double* b;           // D f* (Poisson right-hand side)
     double* p;           // pressure = solver x (warm start)
-    double* r64;         // mixed: outer residual
+    double* p_alt;       // the next stage's starting guess, written by the
+                         // projection; the step then swaps it with p
     // PCG vectors at level 0 (solver precision S)
     void* pv;            // search direction
     void* pv2;           // search direction, ping-pong partner
@@ -152,9 +153,13 @@ struct tpf_ctx {
     double* p_hist3;
     int hist2_valid;
     // set by the step for one stage: the projection also writes the stage's
-    // pressure into proj_hist (minus proj_hsub when that is set)
+    // pressure into proj_hist (minus proj_hsub when that is set), and, when
+    // proj_guess is set, proj_ga p + proj_gb proj_gsrc into proj_guess
     double* proj_hist;
     const double* proj_hsub;
+    double* proj_guess;
+    const double* proj_gsrc;
+    double proj_ga, proj_gb;
     double last_relres;
     int last_outer, last_inner;
     long long stat_solves, stat_outer, stat_inner;   // pressure solves since the last reset
@@ -270,7 +275,6 @@ inline int adj_fields(int dim) { return 4 * (1 + dim) + 4 * dim + 7; }
 size_t align256(size_t x);
 hipError_t launch_finalize(tpf_ctx* c, int nblocks, int nv, int op);
 hipError_t launch_rhs_mean(tpf_ctx* c);
-hipError_t launch_lincomb(tpf_ctx* c, double* out, double a, const double* x, double b, const double* y);
 // the step's non-finite flag as it stands after the work queued so far
 // (through the pinned buffer when there is one)
 hipError_t fetch_flag(tpf_ctx* c, int* flag);

@@ -1038,13 +1038,7 @@ __global__ __launch_bounds__(BLOCK) void k_apply(Dims d, S ih2, Coef cf, int fir
 // ---------------------------------------------------------------- small vector kernels
 constexpr int VBLOCKS = 1024;   // grid-stride vector kernels
 
-// out = a x + b y (out may alias x): pressure warm starts from the history
-__global__ __launch_bounds__(BLOCK) void k_lincomb(long N, double* out, double a, const double* x, double b,
-                                                   const double* y) {
-    for (long c = (long)blockIdx.x * BLOCK + threadIdx.x; c < N; c += (long)gridDim.x * BLOCK)
-        out[c] = a * x[c] + b * y[c];
-}
-
+// x += e (the FP32 correction of a defect-correction pass)
 __global__ __launch_bounds__(BLOCK) void k_correct(long N, double* __restrict__ x,
                                                    const float* __restrict__ e) {
     for (long c = (long)blockIdx.x * BLOCK + threadIdx.x; c < N; c += (long)gridDim.x * BLOCK)
@@ -2198,14 +2192,6 @@ struct Solver {
         prof_end(c);
     }
 };
-
-
-hipError_t launch_lincomb(tpf_ctx* c, double* out, double a, const double* x, double b, const double* y) {
-    prof_begin(c, PC_VECTOR, (double)c->N * 24);
-    k_lincomb<<<vgrid(c->N), BLOCK, 0, c->stream>>>(c->N, out, a, x, b, y);
-    prof_end(c);
-    return hipGetLastError();
-}
 
 hipError_t launch_rhs_mean(tpf_ctx* c) {
     const unsigned nb = vgrid(c->N);

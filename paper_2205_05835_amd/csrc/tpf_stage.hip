@@ -376,11 +376,18 @@ __global__ __launch_bounds__(BLOCK) void k_project(Dims d, int kz, Phys P, RKArg
                                                    const T* yn1, const T* yn2, T* acc0, T* acc1,
                                                    T* acc2, T* nx0, T* nx1, T* nx2,
                                                    int* __restrict__ flags, double* __restrict__ hist,
-                                                   const double* __restrict__ hsub) {
+                                                   const double* __restrict__ hsub, double* __restrict__ guess,
+                                                   const double* __restrict__ gsrc, double ga, double gb) {
     for_cells_zchunk<W>(d, kz, [&](const Cell& C) {
         op_project<T, DIM>(P, rk, C, phi, p, f0, f1, f2, yn0, yn1, yn2, acc0, acc1, acc2, nx0, nx1, nx2, flags);
-        // the pressure history of the warm starts (hist = p, or p - hsub)
-        if (hist) stn(hist, C.id, hsub ? ld(p, C.id) - ld(hsub, C.id) : ld(p, C.id));
+        // the pressure history of the warm starts (hist = p, or p - hsub),
+        // and the next stage's starting guess (ga p + gb gsrc; both weights
+        // are 1 or 2 in magnitude, so the products are exact)
+        if (hist || guess) {
+            const double pc = ld(p, C.id);
+            if (hist) stn(hist, C.id, hsub ? pc - ld(hsub, C.id) : pc);
+            if (guess) stn(guess, C.id, ga * pc + gb * ld(gsrc, C.id));
+        }
     });
 }
 
@@ -660,12 +667,14 @@ static hipError_t proj_impl(tpf_ctx* c, const void* phi_s, const RKArgs& rk, voi
     const dim3 g = zchunk_grid(c->n, kz), b(BX, BY);
     const int yn = c->s_yn, ac = c->s_acc;
     prof_begin(c, PC_PROJ, (double)c->N * (c->tsz * (1 + DIM + (rk.eval_only ? DIM : DIM * (3 + (rk.stage < 3)))) + 8 +
-                                           (c->proj_hist ? 8 : 0) + (c->proj_hsub ? 8 : 0)));
+                                           (c->proj_hist ? 8 : 0) + (c->proj_hsub ? 8 : 0) +
+                                           (c->proj_guess ? 16 : 0)));
     k_project<T, DIM, W><<<g, b, 0, c->stream>>>(
         dims_of(c->n, c->walls), kz, P, rk, ctp<T>(phi_s), c->p, ctp<T>(c->fs[0]), ctp<T>(c->fs[1]),
         ctp<T>(c->fs[2]), ctp<T>(c->u[0][yn]), ctp<T>(c->u[1][yn]), ctp<T>(c->u[2][yn]),
         tp<T>(c->u[0][ac]), tp<T>(c->u[1][ac]), tp<T>(c->u[2][ac]), tp<T>(out[0]), tp<T>(out[1]),
-        tp<T>(out[2]), c->flags, c->proj_hist, c->proj_hist ? c->proj_hsub : nullptr);
+        tp<T>(out[2]), c->flags, c->proj_hist, c->proj_hist ? c->proj_hsub : nullptr, c->proj_guess,
+        c->proj_guess ? c->proj_gsrc : nullptr, c->proj_ga, c->proj_gb);
     prof_end(c);
     return hipGetLastError();
 }

@@ -270,7 +270,7 @@ class Solver:
     def state_views(self):
         """Zero-copy tensors over the current state inside the workspace:
         (phi, [u_a], p), in the state's own precision (p always float64).
-        phi and u move to the other state slot at every step: take new views
+        phi, u and p move to another array at every step: take new views
         after step()/step_adjoint().  After writing phi or u through them,
         call state_changed()."""
         phi = self._view(TPF_STATE_PHI)
