@@ -564,7 +564,7 @@ tpf_status advance(tpf_ctx* c, double dt, int nsteps, char* tape, size_t stage_b
             // stage-3 minus stage-2 difference of the previous step, p_hist3;
             // stage 4 (t + dt) extrapolates from t and t + dt/2, 2 p - p_hist1
             const bool guess = (s < 2 && c->hist2_valid) || s == 2;
-            c->proj_guess = guess ? c->p_alt : nullptr;
+            c->proj_guess = guess ? 1 : 0;
             c->proj_gsrc = s == 0 ? c->p_hist2 : s == 1 ? c->p_hist3 : c->p_hist1;
             c->proj_ga = s == 1 ? 1.0 : 2.0;
             c->proj_gb = s == 1 ? 1.0 : -1.0;
@@ -572,7 +572,7 @@ tpf_status advance(tpf_ctx* c, double dt, int nsteps, char* tape, size_t stage_b
             c->rk_stage = 0;
             c->proj_hist = nullptr;
             c->proj_hsub = nullptr;
-            c->proj_guess = nullptr;
+            c->proj_guess = 0;
             c->proj_gsrc = nullptr;
             if (st == TPF_OK && rec) st = copy_async(c, rec + (1 + c->dim) * fT, c->p, (size_t)c->N * 8);
             if (st != TPF_OK) {

@@ -154,10 +154,11 @@ struct tpf_ctx {
     int hist2_valid;
     // set by the step for one stage: the projection also writes the stage's
     // pressure into proj_hist (minus proj_hsub when that is set), and, when
-    // proj_guess is set, proj_ga p + proj_gb proj_gsrc into proj_guess
+    // proj_guess is set, proj_ga p + proj_gb proj_gsrc into p_alt (the array
+    // beside p; the step swaps the two after the stage)
     double* proj_hist;
     const double* proj_hsub;
-    double* proj_guess;
+    int proj_guess;
     const double* proj_gsrc;
     double proj_ga, proj_gb;
     double last_relres;

@@ -673,8 +673,8 @@ static hipError_t proj_impl(tpf_ctx* c, const void* phi_s, const RKArgs& rk, voi
         dims_of(c->n, c->walls), kz, P, rk, ctp<T>(phi_s), c->p, ctp<T>(c->fs[0]), ctp<T>(c->fs[1]),
         ctp<T>(c->fs[2]), ctp<T>(c->u[0][yn]), ctp<T>(c->u[1][yn]), ctp<T>(c->u[2][yn]),
         tp<T>(c->u[0][ac]), tp<T>(c->u[1][ac]), tp<T>(c->u[2][ac]), tp<T>(out[0]), tp<T>(out[1]),
-        tp<T>(out[2]), c->flags, c->proj_hist, c->proj_hist ? c->proj_hsub : nullptr, c->proj_guess,
-        c->proj_guess ? c->proj_gsrc : nullptr, c->proj_ga, c->proj_gb);
+        tp<T>(out[2]), c->flags, c->proj_hist, c->proj_hist ? c->proj_hsub : nullptr,
+        c->proj_guess ? c->p_alt : nullptr, c->proj_guess ? c->proj_gsrc : nullptr, c->proj_ga, c->proj_gb);
     prof_end(c);
     return hipGetLastError();
 }
