@@ -189,6 +189,7 @@ static size_t carve(tpf_ctx* c, char* base) {
         L.z = cv.take((size_t)L.N * ssz);
         L.zt = cv.take((size_t)L.N * ssz);
         L.r = cv.take((size_t)L.N * ssz);
+        L.dinv = l > 0 ? cv.take((size_t)L.N * ssz) : nullptr;
     }
     c->max_blocks = std::max(nblocks_of(c->n), (long)((c->N + BLOCK - 1) / BLOCK));
     c->partials = (double*)cv.take((size_t)c->max_blocks * 3 * 8);

@@ -71,6 +71,7 @@ struct Level {
     void* z;        // correction / PCG preconditioned residual at level 0
     void* zt;       // Jacobi ping-pong partner of z
     void* r;        // right-hand side (level 0: the PCG residual)
+    void* dinv;     // coarse levels: 1 / diagonal, for the fused first two sweeps
 };
 
 // Kernel classes for the optional per-launch timing.  Each fine-level (level

@@ -363,6 +363,45 @@ __global__ __launch_bounds__(BLOCK) void k_jac(Dims d, S ih2, S omega, Coef cf,
     if (DOT) block_partials_2r(v, partials, stride);
 }
 
+// 1 / d of a stored-coefficient level (d = ih2 times the sum of the face
+// coefficients, summed as in k_jac_first), once per solve
+template <typename S, int DIM>
+__global__ __launch_bounds__(BLOCK) void k_dinv(Dims d, S ih2, CoefStored<S> cf, S* __restrict__ dinv) {
+    Cell C;
+    if (!cell_of_thread<false>(d, C)) return;
+    S bl[3], bh[3], dg = S(0);
+    cf.template faces<DIM>(C, bl, bh);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) dg += bl[a] + bh[a];
+    st(dinv, C.id, recip(dg * ih2));
+}
+
+// The first two pre-smoothing sweeps of a stored-coefficient level in one
+// pass: the first sweep from zero is pointwise, z1 = w1 r / d, so the second,
+// zt = z1 + w2 (r - A z1) / d, forms z1 at its stencil points from r and the
+// stored 1 / d.  The same arithmetic as k_jac_first then k_jac (bitwise: z1
+// is rounded as when it is stored, its products are not contracted into the
+// stencil's differences), and z1 never goes to memory.
+template <typename S, int DIM>
+__global__ __launch_bounds__(BLOCK) void k_jac2_first(Dims d, S ih2, S w1, S w2, CoefStored<S> cf,
+                                                      const S* __restrict__ r, const S* __restrict__ dinv,
+                                                      S* __restrict__ zt, const SolverScalars* __restrict__ sc) {
+    if (sc->done) return;
+    Cell C;
+    if (!cell_of_thread<false>(d, C)) return;
+    auto z1 = [&](unsigned n) {
+#pragma clang fp contract(off)
+        return w1 * ld(r, n) * ld(dinv, n);
+    };
+    S bl[3], bh[3], dg;
+    cf.template faces<DIM>(C, bl, bh);
+    const unsigned c = C.id;
+    const S zc = z1(c);
+    auto Z = [&](int a, int s) -> S { return z1(C.nb(a, s)); };
+    const S az = apply_at<S, DIM>(bl, bh, Z, zc, ih2, dg);
+    st(zt, c, zc + w2 * (ld(r, c) - az) * recip(dg));
+}
+
 // Cell-centred multilinear interpolation of a coarse field at fine cell
 // (i, j, k): along each axis the fine cell 2I + s takes 3/4 of coarse cell I
 // and 1/4 of the coarse neighbour on its own side (I - 1 for s = 0, I + 1 for
@@ -1756,6 +1795,18 @@ struct Solver {
             k_beta_coarsen<S, DIM><<<grid(l), b, 0, c->stream>>>(
                 dims(l - 1), dims(l), coef(l - 1), tp<S>(c->lv[l].beta[0]),
                 tp<S>(c->lv[l].beta[1]), tp<S>(c->lv[l].beta[2]));
+        for (int l = 1; l < c->nlev; ++l)
+            if (separate_level<DIM>(l))
+                k_dinv<S, DIM><<<grid(l), b, 0, c->stream>>>(dims(l), ih2(l), coef(l), tp<S>(c->lv[l].dinv));
+    }
+    // a coarse level that runs the separate down/up kernels (level_down,
+    // level_up): not the tail, not the coarsest grid, not a fused level
+    template <int DIM>
+    bool separate_level(int l) const {
+        if (l < 1 || l == c->nlev - 1) return false;
+        const int tf = tail_first();
+        if (tf >= 1 && l >= tf) return false;
+        return !(DIM == 3 && c->coarse_fused && c->lv[l].N <= CFUSE_MAX_CELLS);
     }
     void build_betas(const void* phi) {
         if (dim == 2) build_betas_t<2>(phi); else build_betas_t<3>(phi);
@@ -1798,15 +1849,27 @@ struct Solver {
                 return;
             }
         }
+        if constexpr (std::is_same<Coef, CoefStored<S>>::value) {
+            if (!first_done) {     // a stored level: both sweeps in one pass (1 / d stored per solve)
+                prof_begin(c, PC_COARSE_LEVELS, fb(l, 3 + cfl));
+                k_jac2_first<S, DIM><<<grid(l), b, 0, c->stream>>>(dims(l), ih2(l), w1, w2, cf, r,
+                                                                   tp<S>(L.dinv), zt, c->scal);
+                prof_end(c);
+                first_done = true;
+                z = nullptr;
+            }
+        }
         if (!first_done) {
             prof_begin(c, fine ? PC_F_FIRST0 : PC_COARSE_LEVELS, fb(l, 2 + cfl));
             k_jac_first<Coef, S, DIM><<<grid(l), b, 0, c->stream>>>(dims(l), ih2(l), w1, cf, r, z, c->scal);
             prof_end(c);
         }
-        prof_begin(c, fine ? PC_F_SWEEP : PC_COARSE_LEVELS, fb(l, 3 + cfl));
-        k_jac<Coef, S, DIM, 0><<<grid(l), b, 0, c->stream>>>(dims(l), ih2(l), w2, cf, r, z, zt, nullptr,
-                                                              c->scal, nullptr, 0);
-        prof_end(c);
+        if (z) {
+            prof_begin(c, fine ? PC_F_SWEEP : PC_COARSE_LEVELS, fb(l, 3 + cfl));
+            k_jac<Coef, S, DIM, 0><<<grid(l), b, 0, c->stream>>>(dims(l), ih2(l), w2, cf, r, z, zt, nullptr,
+                                                                  c->scal, nullptr, 0);
+            prof_end(c);
+        }
         Level& Lc = c->lv[l + 1];
         prof_begin(c, fine ? PC_F_RESTRICT : PC_COARSE_LEVELS, fb(l, 2 + cfl) + (double)Lc.N * sizeof(S));
         k_restrict<Coef, S, DIM><<<restrict_grid(l), restrict_block(), 0, c->stream>>>(
