@@ -361,7 +361,9 @@ struct BatchBlock {
         }
         for (int l = 0; l + 1 < nl; ++l) {
             const BLev<S> L = lev(l);
-            if (!(z_ready && l == 0)) {
+            // the first sweep from zero: on level 0 here (unless the PCG update
+            // pass formed it), on the coarser levels in the restriction above
+            if (l == 0 && !z_ready) {
             cells_g(L.d, [&](const Cell* C, const bool* on) {      // z = omega r / d
                 S b0l[UG], b0h[UG], b1l[UG], b1h[UG], r[UG];
 #pragma unroll
@@ -386,6 +388,7 @@ struct BatchBlock {
             jacobi(L, L.z, L.zt, omega);                            // zt = z + omega (r - A z) / d
             __syncthreads();
             const BLev<S> Lc = lev(l + 1);
+            const bool zc_first = l + 2 < nl;     // the coarse level is not the coarsest
             cells(Lc.d, [&](const Cell& Cc) {          // rc = mean of children of (r - A zt)
                 S s = S(0);
                 for (int dj = 0; dj < 2; ++dj)
@@ -394,7 +397,13 @@ struct BatchBlock {
                         S dg;
                         s += L.r[C.id] - bapply(L, C, L.zt, dg);
                     }
-                Lc.r[Cc.id] = s * S(0.25);
+                const S rc = s * S(0.25);
+                Lc.r[Cc.id] = rc;
+                if (zc_first) {                        // and the coarse z = omega rc / d (pointwise)
+                    const unsigned c = Cc.id;
+                    const S dg = (Lc.b0[c] + Lc.b0[Cc.nb(0, 1)] + Lc.b1[c] + Lc.b1[Cc.nb(1, 1)]) * Lc.ih2;
+                    Lc.z[c] = omega * rc / dg;
+                }
             });
             __syncthreads();
         }
