@@ -111,6 +111,14 @@ __device__ __forceinline__ void bsum2(double& x, double& y, double* red) {
 }
 
 // ------------------------------------------------------------------ levels
+// two-element vector of S (an aligned pair of x neighbours)
+template <typename S>
+struct BVec2;
+template <>
+struct BVec2<float> { using type = float2; };
+template <>
+struct BVec2<double> { using type = double2; };
+
 template <typename S>
 struct BLev {
     Dims d;
@@ -284,12 +292,14 @@ struct BatchBlock {
     }
 
     // dst = src + omega (r - A src) / d on level L (one damped Jacobi sweep)
-    // (dot: also sum <r, dst> over the thread's cells into *dot)
+    // (dot: also sum <r, dst> over the thread's cells into *dot; up: also add
+    // each new value to the four children in up->zt, the piecewise-constant
+    // prolongation into the finer level, whose sizes are twice L's)
     __device__ __forceinline__ void jacobi(const BLev<S>& L, const S* src, S* dst, S omega,
-                                           double* dot = nullptr) const {
+                                           double* dot = nullptr, const BLev<S>* up = nullptr) const {
         cells_g(L.d, [&](const Cell* C, const bool* on) {
             Stencil<S> v[UG];
-            S r[UG];
+            S r[UG], zn[UG];
 #pragma unroll
             for (int u = 0; u < UG; ++u)
                 if (on[u]) {
@@ -301,11 +311,35 @@ struct BatchBlock {
                 if (on[u]) {
                     S dg;
                     const S az = v[u].apply(L.ih2, dg);
-                    const S zn = v[u].xc + omega * (r[u] - az) / dg;
-                    dst[C[u].id] = zn;
-                    if (dot) *dot += (double)r[u] * (double)zn;
+                    zn[u] = v[u].xc + omega * (r[u] - az) / dg;
+                    dst[C[u].id] = zn[u];
+                    if (dot) *dot += (double)r[u] * (double)zn[u];
                 }
+            if (up) prolong_children(*up, C, on, zn);
         });
+    }
+
+    // up->zt += the coarse value zn of each of the group's cells, at its
+    // four children (disjoint between coarse cells; coarsening keeps every
+    // level's sizes even, so all four exist and each pair of x children is
+    // one aligned two-element vector)
+    __device__ __forceinline__ void prolong_children(const BLev<S>& F, const Cell* C, const bool* on,
+                                                     const S* zn) const {
+        using V2 = typename BVec2<S>::type;
+        const int fx = F.d.nx;
+#pragma unroll
+        for (int u = 0; u < UG; ++u)
+            if (on[u]) {
+                V2* lo = reinterpret_cast<V2*>(F.zt + (2 * C[u].j) * fx + 2 * C[u].i);
+                V2* hi = reinterpret_cast<V2*>(F.zt + (2 * C[u].j + 1) * fx + 2 * C[u].i);
+                V2 a = *lo, b = *hi;
+                a.x = a.x + zn[u];
+                a.y = a.y + zn[u];
+                b.x = b.x + zn[u];
+                b.y = b.y + zn[u];
+                *lo = a;
+                *hi = b;
+            }
     }
 
     // ---------------------------------------------------------- coarsest grid
@@ -314,7 +348,9 @@ struct BatchBlock {
     // per lane, and each sweep reads the four neighbours' values from their
     // lanes (cross-lane permutes), so the sweeps need no workgroup barrier.
     // Lanes past the grid mirror cell 0 and write nothing.  Result in zt.
-    __device__ __forceinline__ void coarsest_in_wave(const BLev<S>& L, int N, int sweeps, S wc) const {
+    // up: also add the result to its four children in up->zt (as jacobi does)
+    __device__ __forceinline__ void coarsest_in_wave(const BLev<S>& L, int N, int sweeps, S wc,
+                                                     const BLev<S>* up = nullptr) const {
         if (threadIdx.x >= 64) return;
         const int lane = threadIdx.x;
         const int q = lane < N ? lane : 0;
@@ -331,7 +367,17 @@ struct BatchBlock {
             const S az = (bl0 * (z - zw) - bh0 * (ze - z) + bl1 * (z - zs) - bh1 * (zn - z)) * L.ih2;
             z = z + wc * (r - az) / dg;
         }
-        if (lane < N) L.zt[q] = z;
+        if (lane < N) {
+            L.zt[q] = z;
+            if (up) {
+                const int fx = up->d.nx;
+                const unsigned f = (unsigned)((2 * C.j) * fx + 2 * C.i);
+                up->zt[f] = up->zt[f] + z;
+                up->zt[f + 1] = up->zt[f + 1] + z;
+                up->zt[f + fx] = up->zt[f + fx] + z;
+                up->zt[f + fx + 1] = up->zt[f + fx + 1] + z;
+            }
+        }
     }
 
     // ---------------------------------------------------------- V-cycle
@@ -407,13 +453,16 @@ struct BatchBlock {
             });
             __syncthreads();
         }
+        bool pro_done = false;  // the prolongation into the next finer level is done
         {   // coarsest: fixed damped Jacobi sweeps from zero, result in zt
             const BLev<S> L = lev(nl - 1);
             const int N = ncell(nl - 1);
             const int sweeps = 8 * max(L.d.nx, L.d.ny);
             const S wc = S(0.8);
             if (N <= 64) {
-                coarsest_in_wave(L, N, sweeps, wc);
+                const BLev<S> Lf = lev(nl - 2);
+                coarsest_in_wave(L, N, sweeps, wc, &Lf);    // with the prolongation into nl - 2
+                pro_done = true;
                 __syncthreads();
             } else {
             for (int q = threadIdx.x; q < N; q += NT) L.zt[q] = S(0);
@@ -441,10 +490,14 @@ struct BatchBlock {
             const BLev<S> L = lev(l);
             const BLev<S> Lc = lev(l + 1);
             // zt += P zc (piecewise constant), then z = zt + omega (r - A zt) / d and
-            // zt = z + omega (r - A z) / d.  Two passes instead of one that forms
-            // zt + P zc at all five stencil points: a workgroup owns the case, and
-            // the fused pass held 15 loads per cell in registers, which cost more
-            // latency than the extra barrier.
+            // zt = z + omega (r - A z) / d.  The prolongation is pointwise from the
+            // coarse side, so the coarse level's last pass adds its values to the
+            // children as it writes them (pro_done); a pass of its own only after
+            // a coarsest grid solved by the block-wide loop.  Not fused into the
+            // first sweep (zt + P zc at all five stencil points): a workgroup owns
+            // the case, and that pass held 15 loads per cell in registers, which
+            // cost more latency than the extra barrier.
+            if (!pro_done) {
             cells_g(L.d, [&](const Cell* C, const bool* on) {
                 S zf[UG], zc[UG];
 #pragma unroll
@@ -458,10 +511,13 @@ struct BatchBlock {
                     if (on[u]) L.zt[C[u].id] = zf[u] + zc[u];
             });
             __syncthreads();
+            }
             jacobi(L, L.zt, L.z, omega);
             __syncthreads();
             if (l > 0) {
-                jacobi(L, L.z, L.zt, omega);
+                const BLev<S> Lf = lev(l - 1);
+                jacobi(L, L.z, L.zt, omega, nullptr, &Lf);  // with the prolongation into l - 1
+                pro_done = true;
                 __syncthreads();
             }
         }
