@@ -777,13 +777,24 @@ __global__ __launch_bounds__(1024) void k_tail(TailDesc D, S w1, S w2, S omega_c
 // both), so the results are bitwise those of the separate kernels.  Only
 // small levels take this path (at 256^3: 64^3 and 32^3), where the separate
 // kernels are bound by launch latency, not bandwidth.
-constexpr int CT = 8;              // tile edge (even: restriction pairs stay in the tile)
-constexpr int CH2 = CT + 4;        // tile plus two cells on each side
-constexpr int CH1 = CT + 2;        // tile plus one
-constexpr int CB = CT + 5;         // coefficient region: the faces of the CH2 cells
-constexpr int CC = CT / 2 + 4;     // coarse region of k_cup: the coarse cells the CH2 cells interpolate from
-constexpr int CNB = CB * CB * CB, CN2 = CH2 * CH2 * CH2, CN1 = CH1 * CH1 * CH1, CNT = CT * CT * CT;
-constexpr int CNC = CC * CC * CC;
+// The tile edge TE is 8, or 4 on a level whose 8^3 tiles would not give
+// every compute unit a block (at 256^3: 32^3, 64 tiles of 8^3).
+template <int TE>
+struct CTile {
+    static_assert(TE % 2 == 0, "restriction pairs stay in the tile");
+    static constexpr int CT = TE;              // tile edge
+    static constexpr int CH2 = CT + 4;         // tile plus two cells on each side
+    static constexpr int CH1 = CT + 2;         // tile plus one
+    static constexpr int CB = CT + 5;          // coefficient region: the faces of the CH2 cells
+    static constexpr int CC = CT / 2 + 4;      // coarse region of k_cup: the coarse cells the CH2 cells interpolate from
+    static constexpr int CNB = CB * CB * CB, CN2 = CH2 * CH2 * CH2, CN1 = CH1 * CH1 * CH1, CNT = CT * CT * CT;
+    static constexpr int CNC = CC * CC * CC;
+};
+#define TPF_CTILE(TE)                                                                            \
+    constexpr int CT = CTile<TE>::CT, CH2 = CTile<TE>::CH2, CH1 = CTile<TE>::CH1, CB = CTile<TE>::CB; \
+    constexpr int CC = CTile<TE>::CC, CNB = CTile<TE>::CNB, CN2 = CTile<TE>::CN2, CN1 = CTile<TE>::CN1; \
+    constexpr int CNT = CTile<TE>::CNT, CNC = CTile<TE>::CNC;                                     \
+    (void)CT; (void)CH2; (void)CH1; (void)CB; (void)CC; (void)CNB; (void)CN2; (void)CN1; (void)CNT; (void)CNC
 // Levels up to this size take the fused kernels.  Measured per V-cycle at
 // 256^3: 64^3 18 us fused against 28 us in six launches, 32^3 15 against
 // 28 us; at 128^3 (4096 tiles, each recomputing a halo of 3.4 times its
@@ -813,8 +824,9 @@ __device__ __forceinline__ void coarse_offsets(const Dims& d, int o0, int o1, in
 }
 
 // face coefficients of the cell at position b of the coefficient region
-template <typename S>
+template <int TE, typename S>
 __device__ __forceinline__ void cfaces(const S* sb, int b, S* bl, S* bh) {
+    TPF_CTILE(TE);
     bl[0] = sb[b];
     bh[0] = sb[b + 1];
     bl[1] = sb[CNB + b];
@@ -823,10 +835,11 @@ __device__ __forceinline__ void cfaces(const S* sb, int b, S* bl, S* bh) {
     bh[2] = sb[2 * CNB + b + CB * CB];
 }
 
-template <typename S>
+template <typename S, int TE>
 __global__ __launch_bounds__(BLOCK) void k_cdown(Dims d, Dims cd, S ih2, S w1, S w2, S rw, CoefStored<S> cf,
                                                  const S* __restrict__ r, S* __restrict__ zt,
                                                  S* __restrict__ rc, const SolverScalars* __restrict__ sc) {
+    TPF_CTILE(TE);
     if (sc->done) return;
     // sb: the three coefficient arrays on the CB^3 region, then r on the CH2^3
     // region (both with origin tile - 2); sz: z on CH2^3, later the residual
@@ -873,7 +886,7 @@ __global__ __launch_bounds__(BLOCK) void k_cdown(Dims d, Dims cd, S ih2, S w1, S
         int x, y, z;
         cdec<CH2>(e, x, y, z);
         S bl[3], bh[3], dg = S(0);
-        cfaces(sb, (z * CB + y) * CB + x, bl, bh);
+        cfaces<TE>(sb, (z * CB + y) * CB + x, bl, bh);
 #pragma unroll
         for (int a = 0; a < 3; ++a) dg += bl[a] + bh[a];
         sz[e] = w1 * sr[e] * recip(dg * ih2);
@@ -885,7 +898,7 @@ __global__ __launch_bounds__(BLOCK) void k_cdown(Dims d, Dims cd, S ih2, S w1, S
         cdec<CH1>(e, x, y, z);
         const int p = ((z + 1) * CH2 + y + 1) * CH2 + x + 1;
         S bl[3], bh[3], dg;
-        cfaces(sb, ((z + 1) * CB + y + 1) * CB + x + 1, bl, bh);
+        cfaces<TE>(sb, ((z + 1) * CB + y + 1) * CB + x + 1, bl, bh);
         auto Z = [&](int a, int s) {
             const int o = a == 0 ? 1 : a == 1 ? CH2 : CH2 * CH2;
             return sz[s > 0 ? p + o : p - o];
@@ -902,7 +915,7 @@ __global__ __launch_bounds__(BLOCK) void k_cdown(Dims d, Dims cd, S ih2, S w1, S
         cdec<CT>(e, x, y, z);
         const int q = ((z + 1) * CH1 + y + 1) * CH1 + x + 1;
         S bl[3], bh[3], dg;
-        cfaces(sb, ((z + 2) * CB + y + 2) * CB + x + 2, bl, bh);
+        cfaces<TE>(sb, ((z + 2) * CB + y + 2) * CB + x + 2, bl, bh);
         auto X = [&](int a, int s) {
             const int o = a == 0 ? 1 : a == 1 ? CH1 : CH1 * CH1;
             return szt[s > 0 ? q + o : q - o];
@@ -932,9 +945,10 @@ __global__ __launch_bounds__(BLOCK) void k_cdown(Dims d, Dims cd, S ih2, S w1, S
 
 // the prolongation step of k_prolong for fine position (x, y, z) of the CH2
 // region from the CC^3 coarse region; contraction off, as there
-template <typename S>
+template <int TE, typename S>
 __device__ __forceinline__ S cprolong(const S* szc, int x, int y, int z) {
 #pragma clang fp contract(off)
+    TPF_CTILE(TE);
     const int I = 1 + (x >> 1), J = 1 + (y >> 1), K = 1 + (z >> 1);
     const int I2 = I + ((x & 1) ? 1 : -1), J2 = J + ((y & 1) ? 1 : -1), K2 = K + ((z & 1) ? 1 : -1);
     auto at = [&](int a, int b, int e) { return szc[(e * CC + b) * CC + a]; };
@@ -944,11 +958,12 @@ __device__ __forceinline__ S cprolong(const S* szc, int x, int y, int z) {
     return w1 * yz(K) + w2 * yz(K2);
 }
 
-template <typename S>
+template <typename S, int TE>
 __global__ __launch_bounds__(BLOCK) void k_cup(Dims d, Dims cd, S ih2, S w1, S w2, CoefStored<S> cf,
                                                const S* __restrict__ r, const S* __restrict__ zc,
                                                const S* __restrict__ zt, S* __restrict__ zout,
                                                const SolverScalars* __restrict__ sc) {
+    TPF_CTILE(TE);
     if (sc->done) return;
     // sb: coefficients on CB^3, then zt on CH2^3 (origin tile - 2), r on CH1^3
     // (origin tile - 1) and the coarse correction on CC^3 (origin tile/2 - 2)
@@ -1006,7 +1021,7 @@ __global__ __launch_bounds__(BLOCK) void k_cup(Dims d, Dims cd, S ih2, S w1, S w
     for (int e = t; e < CN2; e += BLOCK) {
         int x, y, z;
         cdec<CH2>(e, x, y, z);
-        szt[e] = szt[e] + cprolong(szc, x, y, z);
+        szt[e] = szt[e] + cprolong<TE>(szc, x, y, z);
     }
     __syncthreads();
     // first post-sweep on the tile plus one: z = zt + w2 (r - A zt) / d
@@ -1015,7 +1030,7 @@ __global__ __launch_bounds__(BLOCK) void k_cup(Dims d, Dims cd, S ih2, S w1, S w
         cdec<CH1>(e, x, y, z);
         const int p = ((z + 1) * CH2 + y + 1) * CH2 + x + 1;
         S bl[3], bh[3], dg;
-        cfaces(sb, ((z + 1) * CB + y + 1) * CB + x + 1, bl, bh);
+        cfaces<TE>(sb, ((z + 1) * CB + y + 1) * CB + x + 1, bl, bh);
         auto X = [&](int a, int s) {
             const int o = a == 0 ? 1 : a == 1 ? CH2 : CH2 * CH2;
             return szt[s > 0 ? p + o : p - o];
@@ -1032,7 +1047,7 @@ __global__ __launch_bounds__(BLOCK) void k_cup(Dims d, Dims cd, S ih2, S w1, S w
         cdec<CT>(e, x, y, z);
         const int q = ((z + 1) * CH1 + y + 1) * CH1 + x + 1;
         S bl[3], bh[3], dg;
-        cfaces(sb, ((z + 2) * CB + y + 2) * CB + x + 2, bl, bh);
+        cfaces<TE>(sb, ((z + 2) * CB + y + 2) * CB + x + 2, bl, bh);
         auto X = [&](int a, int s) {
             const int o = a == 0 ? 1 : a == 1 ? CH1 : CH1 * CH1;
             return sz[s > 0 ? q + o : q - o];
@@ -1974,6 +1989,27 @@ struct Solver {
     }
 
     // V-cycle from level l >= 1 (stored coefficients); the correction ends in zt
+    // k_cdown, the levels below, k_cup on stored-coefficient level l (3D)
+    // with TE^3 tiles; the correction ends in z
+    template <int TE>
+    const S* fused_level(int l) {
+        Level& L = c->lv[l];
+        const Level& Lc = c->lv[l + 1];
+        const CoefStored<S> cf = coef(l);
+        const dim3 g = tile_grid((L.n[0] + TE - 1) / TE, (L.n[1] + TE - 1) / TE, (L.n[2] + TE - 1) / TE);
+        const double cb = (double)Lc.N * sizeof(S);
+        prof_begin(c, PC_COARSE_LEVELS, fb(l, 2 + 3) + cb);      // r, 3 coefficients -> zt, coarse r
+        k_cdown<S, TE><<<g, BLOCK, 0, c->stream>>>(dims(l), dims(l + 1), ih2(l), w1, w2, rw(), cf, tp<S>(L.r),
+                                                   tp<S>(L.zt), tp<S>(Lc.r), c->scal);
+        prof_end(c);
+        const S* zc = vcycle_coarse<3>(l + 1);
+        prof_begin(c, PC_COARSE_LEVELS, fb(l, 3 + 3) + cb);      // zt, r, 3 coefficients, zc -> z
+        k_cup<S, TE><<<g, BLOCK, 0, c->stream>>>(dims(l), dims(l + 1), ih2(l), w1, w2, cf, tp<S>(L.r), zc,
+                                                 tp<S>(L.zt), tp<S>(L.z), c->scal);
+        prof_end(c);
+        return tp<S>(L.z);
+    }
+
     template <int DIM>
     const S* vcycle_coarse(int l) {
         Level& L = c->lv[l];
@@ -1988,21 +2024,13 @@ struct Solver {
         }
         if (DIM == 3 && c->coarse_fused && L.N <= CFUSE_MAX_CELLS) {
             // one launch down, one up (k_cdown, k_cup); the correction ends in
-            // z, since k_cup reads zt on its halo while other blocks write
-            const Level& Lc = c->lv[l + 1];
-            const CoefStored<S> cf = coef(l);
-            const dim3 g = tile_grid((L.n[0] + CT - 1) / CT, (L.n[1] + CT - 1) / CT, (L.n[2] + CT - 1) / CT);
-            const double cb = (double)Lc.N * sizeof(S);
-            prof_begin(c, PC_COARSE_LEVELS, fb(l, 2 + 3) + cb);      // r, 3 coefficients -> zt, coarse r
-            k_cdown<S><<<g, BLOCK, 0, c->stream>>>(dims(l), dims(l + 1), ih2(l), w1, w2, rw(), cf, tp<S>(L.r),
-                                                   tp<S>(L.zt), tp<S>(Lc.r), c->scal);
-            prof_end(c);
-            const S* zc = vcycle_coarse<DIM>(l + 1);
-            prof_begin(c, PC_COARSE_LEVELS, fb(l, 3 + 3) + cb);      // zt, r, 3 coefficients, zc -> z
-            k_cup<S><<<g, BLOCK, 0, c->stream>>>(dims(l), dims(l + 1), ih2(l), w1, w2, cf, tp<S>(L.r), zc,
-                                                 tp<S>(L.zt), tp<S>(L.z), c->scal);
-            prof_end(c);
-            return tp<S>(L.z);
+            // z, since k_cup reads zt on its halo while other blocks write.
+            // 8^3 tiles, or 4^3 where 8^3 tiles would leave compute units idle
+            const auto ntiles = [&](int e) {
+                return (long)((L.n[0] + e - 1) / e) * ((L.n[1] + e - 1) / e) * ((L.n[2] + e - 1) / e);
+            };
+            if (ntiles(8) < 256) return fused_level<4>(l);
+            return fused_level<8>(l);
         }
         level_down<DIM>(l, coef(l), false, false);
         const S* zc = vcycle_coarse<DIM>(l + 1);
